@@ -1,0 +1,93 @@
+"""2x2 subspace step, restart ratio, safe step and the PNCG loop (FP64).
+
+Test infrastructure (see the package docstring).
+
+* Subspace step (Section 4.2; supplement Section 2): p(mu, nu) = -mu z + nu p_k
+  minimises Q = g^T p + 1/2 p^T H~ p.  The oracle forms the three entries
+  z^T H~ z, z^T H~ p_k, p_k^T H~ p_k with explicit products by the assembled
+  H~ and solves the 2x2 system of supplement Eq. (10) by Gaussian elimination
+  with partial pivoting.  Near-singular systems (supplement Section 2.4.3:
+  |Delta| < eps_sing max(A11 A22, eps_abs)) fall back to mu = 1, nu = 0.
+* Restart iteration (Algorithm 1): mu = g^T z / z^T H~ z, nu = 0.  The
+  supplement's alternative (mu = 1 on the very first iteration) is not used;
+  mu = 1, nu = 0 is also taken when z^T H~ z <= 0.
+* Restart ratio (Section 4.3): r_k = |g_{k+1}^T z_k| / (g_{k+1}^T z_{k+1}).
+* Safe step: the paper's per-subdomain conservative CCD is not part of this
+  path; for affine stencils each candidate c gets
+  a_c = min(1, 0.9 d_c / sum_j max(0, -grad_{c,j} . p_j)), which keeps d_c
+  positive for any per-vertex steps in [0, a_c]; a subdomain takes the
+  minimum over the candidates touching it (Algorithm 1, per-subdomain
+  steps).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def solve2(A, b):
+    """2x2 Gaussian elimination with partial pivoting."""
+    A = np.array(A, np.float64)
+    b = np.array(b, np.float64)
+    if abs(A[1, 0]) > abs(A[0, 0]):
+        A = A[::-1].copy()
+        b = b[::-1].copy()
+    l = A[1, 0] / A[0, 0]
+    a22 = A[1, 1] - l * A[0, 1]
+    b2 = b[1] - l * b[0]
+    y = b2 / a22
+    x = (b[0] - A[0, 1] * y) / A[0, 0]
+    return np.array([x, y])
+
+
+def subspace_step(g, z, p, Hmul, restart, eps_sing=1e-12, eps_abs=1e-300):
+    """Returns (mu, nu, p_next, fallback, A11, A12, A22)."""
+    Hz = Hmul(z)
+    A11 = float(z @ Hz)
+    gz = float(g @ z)
+    if restart:
+        if A11 > 0:
+            mu, nu, fb = gz / A11, 0.0, False
+        else:
+            mu, nu, fb = 1.0, 0.0, True
+        return mu, nu, -mu * z, fb, A11, 0.0, 0.0
+    Hp = Hmul(p)
+    A12 = float(z @ Hp)
+    A22 = float(p @ Hp)
+    gp = float(g @ p)
+    det = A11 * A22 - A12 * A12
+    if abs(det) < eps_sing * max(A11 * A22, eps_abs):
+        return 1.0, 0.0, -z, True, A11, A12, A22
+    mu, nu = solve2([[A11, -A12], [-A12, A22]], [gz, -gp])
+    return float(mu), float(nu), -mu * z + nu * p, False, A11, A12, A22
+
+
+def restart_ratio(g_new, z_prev, z_new):
+    return abs(float(g_new @ z_prev)) / float(g_new @ z_new)
+
+
+def safe_alpha(hier, idx, grad, d, p):
+    """Per-subdomain step sizes (D,) for affine candidate stencils."""
+    P = np.asarray(p).reshape(-1, 3)
+    D = hier.num_subdomains(0)
+    alpha = np.ones(D)
+    for c in range(idx.shape[0]):
+        s = 0.0
+        for j in range(4):
+            v = idx[c, j]
+            if v >= 0:
+                s += max(0.0, -float(grad[c, 3 * j:3 * j + 3] @ P[v]))
+        if s <= 0.0:
+            continue
+        a = min(1.0, 0.9 * d[c] / s)
+        for j in range(4):
+            v = idx[c, j]
+            if v >= 0:
+                sd = hier.subdomain_of_vertex(v)
+                alpha[sd] = min(alpha[sd], a)
+    return alpha
+
+
+def step_positions(hier, x, p, alpha):
+    """x + S_d^T alpha_d S_d p for every subdomain (Algorithm 1)."""
+    a = alpha[hier.rank // 32]
+    return (np.asarray(x).reshape(-1, 3) + a[:, None] * np.asarray(p).reshape(-1, 3)).reshape(-1)

@@ -1,0 +1,155 @@
+"""Pins of the oracle's subspace step, restart ratio and safe step.
+
+Anchors: numpy.linalg.solve for the 2x2 system, stationarity of the
+quadratic model checked by finite differences in (mu, nu), the descent
+property g^T p < 0, the degenerate direction p = c z, the textbook
+equivalence with preconditioned CG on an SPD quadratic, and the safety
+property of the affine step bound.
+"""
+import numpy as np
+import pytest
+
+from oracle import mas, pncg
+from paper_2604_19892_amd import synth
+
+
+def spd(rng, n, cond=1e3):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return Q @ np.diag(np.geomspace(1, cond, n)) @ Q.T
+
+
+def test_two_by_two_matches_lapack_and_is_stationary():
+    rng = np.random.default_rng(0)
+    n = 30
+    A = spd(rng, n)
+    g, z, p = rng.standard_normal((3, n))
+    mu, nu, pn, fb, A11, A12, A22 = pncg.subspace_step(g, z, p, lambda v: A @ v, restart=False)
+    assert not fb
+    ref = np.linalg.solve([[z @ A @ z, -(z @ A @ p)], [-(p @ A @ z), p @ A @ p]], [g @ z, -(g @ p)])
+    np.testing.assert_allclose([mu, nu], ref, rtol=1e-12)
+
+    def Q(m_, n_):
+        q = -m_ * z + n_ * p
+        return g @ q + 0.5 * q @ A @ q
+
+    h = 1e-5 * max(1.0, abs(mu), abs(nu))
+    dQm = (Q(mu + h, nu) - Q(mu - h, nu)) / (2 * h)
+    dQn = (Q(mu, nu + h) - Q(mu, nu - h)) / (2 * h)
+    scale = abs(g @ z) + abs(g @ p)
+    assert abs(dQm) < 1e-7 * scale and abs(dQn) < 1e-7 * scale
+    # the optimum is a descent direction: g^T p = -[mu nu] A_sub [mu nu]^T < 0
+    Asub = np.array([[A11, -A12], [-A12, A22]])
+    sol = np.array([mu, nu])
+    assert g @ pn == pytest.approx(-sol @ Asub @ sol, rel=1e-10)
+    assert g @ pn < 0
+
+
+def test_pivoting_path_matches_lapack():
+    A = np.array([[1e-14, 2.0], [3.0, 1.0]])
+    b = np.array([1.0, 2.0])
+    np.testing.assert_allclose(pncg.solve2(A, b), np.linalg.solve(A, b), rtol=1e-14)
+
+
+def test_fallback_on_parallel_directions():
+    rng = np.random.default_rng(1)
+    A = spd(rng, 10)
+    g, z = rng.standard_normal((2, 10))
+    mu, nu, pn, fb, *_ = pncg.subspace_step(g, z, -2.5 * z, lambda v: A @ v, restart=False)
+    assert fb and mu == 1.0 and nu == 0.0
+    np.testing.assert_array_equal(pn, -z)
+
+
+def test_restart_iteration_is_exact_line_search():
+    rng = np.random.default_rng(2)
+    A = spd(rng, 12)
+    g, z = rng.standard_normal((2, 12))
+    mu, nu, pn, fb, *_ = pncg.subspace_step(g, z, np.zeros(12), lambda v: A @ v, restart=True)
+    assert nu == 0 and not fb
+    # minimiser of g^T(-mu z) + 1/2 mu^2 z^T A z
+    assert mu == pytest.approx((g @ z) / (z @ A @ z), rel=1e-14)
+
+
+def test_subspace_pncg_equals_pcg_on_spd_quadratic():
+    """With H~ = A exact, a fixed SPD preconditioner and unit steps, the
+    2D-subspace iteration reproduces preconditioned CG and terminates in at
+    most n steps."""
+    rng = np.random.default_rng(3)
+    n = 12
+    A = spd(rng, n, cond=10.0)
+    Pm = np.linalg.inv(np.diag(np.diag(A)) + 0.1 * spd(rng, n, cond=10))
+    Pm = 0.5 * (Pm + Pm.T)
+    b = rng.standard_normal(n)
+    # textbook PCG
+    x = np.zeros(n)
+    r = b - A @ x
+    zc = Pm @ r
+    d = zc.copy()
+    xs_pcg = []
+    for _ in range(n):
+        a = (r @ zc) / (d @ A @ d)
+        x = x + a * d
+        r_new = r - a * (A @ d)
+        z_new = Pm @ r_new
+        beta = (r_new @ z_new) / (r @ zc)
+        d = z_new + beta * d
+        r, zc = r_new, z_new
+        xs_pcg.append(x.copy())
+    # 2D subspace with alpha = 1
+    x = np.zeros(n)
+    p = np.zeros(n)
+    xs = []
+    for k in range(n):
+        g = A @ x - b
+        z = Pm @ g
+        mu, nu, p, fb, *_ = pncg.subspace_step(g, z, p, lambda v: A @ v, restart=(k == 0))
+        x = x + p
+        xs.append(x.copy())
+    xe = np.linalg.solve(A, b)
+    for k in range(n):
+        assert np.linalg.norm(xs[k] - xs_pcg[k]) < 1e-10 * np.linalg.norm(xe)
+    # finite termination (exact arithmetic: n steps), up to rounding
+    assert np.linalg.norm(xs[-1] - xe) < 1e-10 * np.linalg.norm(xe)
+    assert np.linalg.norm(xs[n // 2] - xe) > 1e-6 * np.linalg.norm(xe)
+
+
+def test_restart_ratio_definition_cases():
+    g = np.array([1.0, 2.0])
+    assert pncg.restart_ratio(g, np.array([1.0, 0.0]), np.array([0.0, 1.0])) == pytest.approx(0.5)
+    assert pncg.restart_ratio(g, np.array([-3.0, 0.0]), np.array([1.0, 1.0])) == pytest.approx(1.0)
+
+
+def test_safe_step_keeps_every_stencil_apart():
+    sc = synth.two_boxes_scene(n_contacts=3000, nxy=12, nz=6, active_frac=0.7)
+    hier = mas.Hierarchy(sc.X, 2)
+    pool = sc.pool
+    rng = np.random.default_rng(4)
+    x = sc.x.reshape(-1)
+    p = 0.05 * rng.standard_normal(x.size)
+
+    def dist(xx):
+        xs = np.where(pool['idx'][..., None] >= 0, xx.reshape(-1, 3)[np.maximum(pool['idx'], 0)], 0)
+        return (pool['grad'] * xs.reshape(-1, 12)).sum(1) - pool['off']
+
+    d0 = dist(x)
+    alpha = pncg.safe_alpha(hier, pool['idx'], pool['grad'], d0, p)
+    assert np.all((alpha > 0) & (alpha <= 1))
+    assert np.any(alpha < 1)
+    # any per-subdomain fraction of the step keeps d >= 0.1 d0
+    for frac in (1.0, 0.5, 0.0):
+        a = alpha * (frac + (1 - frac) * rng.uniform(size=alpha.size))
+        d1 = dist(pncg.step_positions(hier, x, p, a))
+        assert np.all(d1 >= 0.1 * d0 - 1e-15)
+
+
+def test_safe_step_single_contact_closed_form():
+    X = np.random.default_rng(5).uniform(size=(40, 3))
+    hier = mas.Hierarchy(X, 1)
+    idx = np.array([[3, -1, -1, -1]], np.int32)
+    grad = np.zeros((1, 12))
+    grad[0, :3] = [0, 0, 1.0]
+    p = np.zeros(120)
+    p[3 * 3 + 2] = -2e-3          # moving toward the plane at 2e-3 per unit step
+    alpha = pncg.safe_alpha(hier, idx, grad, np.array([1e-3]), p)
+    d = hier.subdomain_of_vertex(3)
+    assert alpha[d] == pytest.approx(0.9 * 1e-3 / 2e-3)
+    assert np.all(np.delete(alpha, d) == 1.0)
