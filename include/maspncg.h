@@ -1,0 +1,226 @@
+/*
+ * maspncg.h - C ABI of the MAS-PNCG hot path for AMD MI355X (gfx950).
+ *
+ * The library computes the data-parallel core of one iteration of the
+ * multilevel-preconditioned nonlinear conjugate gradient method for
+ * Incremental Potential Contact (MAS-PNCG):
+ *
+ *   mas_build            RebuildMAS of Algorithm 1: Hessian snapshot and all
+ *                        MAS levels (Section 3.3, supplement Section 1)
+ *   mas_woodbury_update  contact classification, localized Top-K and the
+ *                        per-subdomain capacitance factors (Section 4.1)
+ *   mas_apply            z = P g with Woodbury-updated level 0 and frozen
+ *                        coarse levels (Section 4.1.2, assembly of z_{k+1})
+ *   hess_vec             y = H_base v (+ U U^T v) (Eq. for H~ in Section 4.1;
+ *                        supplement Eqs. (11)-(15))
+ *   pncg_subspace_step   2x2 subspace minimisation, fallback and restart
+ *                        ratio (Sections 4.2-4.3; supplement Section 2)
+ *
+ * plus the supporting calls an iteration needs (energy and gradient of the
+ * incremental potential, Section 3.1; per-subdomain safe step of Algorithm 1
+ * for affine contact stencils).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Vertex numbering.  mas_create sorts the vertices by a 63-bit Morton code of
+ * their rest positions (21 bits per axis, normalised to the bounding box,
+ * ties kept in input order) and returns perm[new] = old.  Every vector and
+ * every contact vertex index passed afterwards uses that library order.
+ * Level-0 subdomain d holds vertices [32 d, 32 d + 32); a level-l node is a
+ * run of 32^l consecutive vertices; a level-l subdomain is 32 consecutive
+ * level-l nodes.  Blocks are 96 x 96 (3 DOFs per vertex or node).
+ *
+ * Vectors.  Device float64 arrays of length 3N, xyz interleaved per vertex.
+ *
+ * Contacts.  An affine distance stencil over up to four vertices:
+ * key (identity, uint64), idx[4] (library vertex ids, -1 padded), d (current
+ * distance) and grad[12] = dd/dx.  Contacts with d >= dhat carry zero
+ * stiffness.  All contact arrays are device pointers.
+ *
+ * Memory ownership.  The caller owns every pointer it passes.  The library
+ * copies what it keeps (mesh at mas_create, the base contact set at
+ * mas_build, the update columns at mas_woodbury_update) and frees its own
+ * memory in mas_destroy.  Calls never free caller memory.
+ *
+ * Streams.  Every call is enqueued on the stream given to mas_create and
+ * returns without synchronising, except where stated.  Scalar outputs are
+ * written to device memory.
+ *
+ * Errors.  Invalid arguments and call-order mistakes return immediately
+ * (MAS_ERR_INVALID_ARG, MAS_ERR_STATE).  Conditions detected by kernels
+ * (non-positive pivot, non-finite input, rank overflow) set a sticky device
+ * error word that mas_sync_status reports.  No call aborts the process.
+ * A context is bound to one stream and is not thread-safe.
+ */
+#ifndef MASPNCG_H
+#define MASPNCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MAS_OK = 0,
+  MAS_ERR_INVALID_ARG = 1,
+  MAS_ERR_STATE = 2,
+  MAS_ERR_OOM = 3,
+  MAS_ERR_HIP = 4,
+  MAS_ERR_NOT_SPD = 5,
+  MAS_ERR_NONFINITE = 6,
+  MAS_ERR_RANK = 7
+} mas_status;
+
+/* Storage precision of the level-0 inverse blocks (block_prec) and of the
+ * element Hessian snapshot (hess_prec: MAS_F64 or MAS_F32).  Blocks are
+ * always assembled and inverted in float64 (supplement Section 1.1); BF16
+ * and FP16 blocks are stored with a per-row symmetric scaling s_i =
+ * B_ii^-1/2 and applied with float32 accumulation. */
+typedef enum { MAS_F64 = 0, MAS_F32 = 1, MAS_BF16 = 2, MAS_F16 = 3 } mas_prec;
+
+typedef struct {
+  int32_t num_levels;   /* MAS levels including level 0, 1..6 (supplement 1.2) */
+  int32_t max_rank;     /* Top-K per subdomain, 0..32 (Section 4.1.1, K = 8) */
+  double cos_rot;       /* cosine of the rotation threshold (25 degrees) */
+  double restart_delta; /* restart threshold delta (Section 4.3, 0.3) */
+  double eps_sing;      /* relative singularity tolerance (supplement 2.4.3) */
+  double eps_abs;       /* absolute floor of the singularity test */
+  double kappa;         /* barrier stiffness: B = kappa sum_c b(d_c) */
+  double dhat;          /* barrier activation distance */
+  double h;             /* time step */
+  double gravity[3];    /* external acceleration used for x~ */
+  int32_t block_prec;   /* mas_prec of level-0 blocks */
+  int32_t coarse_prec;  /* MAS_F64 or MAS_F32 for levels >= 1 */
+  int32_t hess_prec;    /* MAS_F64 or MAS_F32 element Hessian snapshot */
+  int32_t reserved;
+} mas_config;
+
+/* Tetrahedral mesh, host pointers, original vertex numbering.  tets must
+ * have positive orientation at rest. */
+typedef struct {
+  int64_t num_vertices;
+  int64_t num_tets;
+  const double* rest_x;   /* 3N */
+  const int32_t* tets;    /* 4T */
+  const double* density;  /* T */
+  const double* youngs;   /* T */
+  const double* poisson;  /* T */
+} mas_mesh;
+
+/* Contact stencils, device pointers, library vertex numbering. */
+typedef struct {
+  int64_t m;
+  const uint64_t* key;    /* m */
+  const int32_t* idx;     /* 4m, -1 padded */
+  const double* d;        /* m */
+  const double* grad;     /* 12m */
+} mas_contacts;
+
+/* Scalars written by pncg_subspace_step (device memory). */
+typedef struct {
+  double mu, nu;          /* p_{k+1} = -mu z + nu p_k */
+  double r;               /* restart ratio |g^T z_prev| / (g^T z) */
+  double gz, gp, gzp;     /* g^T z, g^T p_k, g^T z_prev */
+  double A11, A12, A22;   /* entries of the 2x2 system (supplement Eq. (19)) */
+  double gnorm2, znorm2;  /* squared norms of g and z */
+  int32_t fallback;       /* 1 if mu = 1, nu = 0 was taken */
+  int32_t restart_next;   /* r > restart_delta */
+  int32_t restart_used;   /* the restart form (nu = 0) was used */
+  int32_t reserved;
+} mas_step_out;
+
+/* Fills cfg with the paper's stated defaults (K = 8, 25 degrees, delta = 0.3,
+ * eps_sing = 1e-12) and float64 storage. */
+void mas_default_config(mas_config* cfg);
+
+/* Creates a context: Morton order, element rest quantities (Dm^-1, volume,
+ * Lame parameters from Young's modulus and Poisson's ratio, lumped masses),
+ * subdomain tables.  perm_out (host, N) receives perm[new] = old.
+ * Allocates all fixed-size device memory.  stream may be NULL (default). */
+mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_stream,
+                      void** ctx_out, int32_t* perm_out);
+
+mas_status mas_destroy(void* ctx);
+
+/* RebuildMAS (Algorithm 1; supplement Section 1).  At x_base (device, 3N):
+ * per-tet SNH Hessians with eigenvalues of d2Psi/dF2 clamped at zero, the
+ * base contact set (copied; k = kappa b''(d), n = grad), level-0 blocks
+ * S_d H_base S_d^T and Galerkin coarse blocks of every level, all inverted in
+ * float64 and stored at the configured precision.  Clears the Woodbury
+ * update.  A non-positive pivot sets MAS_ERR_NOT_SPD. */
+mas_status mas_build(void* ctx, const double* x_base, const mas_contacts* base);
+
+/* Sparse-Input Woodbury update (Section 4.1).  Classifies every current
+ * contact against the base set by key (new, rotated: cos < cos_rot, stiffening,
+ * softening), keeps the untruncated update columns u = sqrt(dS) n for
+ * hess_vec and the subspace step, selects per level-0 subdomain the max_rank
+ * candidates of largest dS (ties: smaller key first), and factors the
+ * capacitance I + U_d^T B_d U_d in float64.  rank_hist (device, max_rank+1
+ * int32, nullable) receives the histogram of per-subdomain ranks. */
+mas_status mas_woodbury_update(void* ctx, const mas_contacts* curr, int32_t* rank_hist);
+
+/* z = P g (device vectors, 3N, must not alias): level-0 blocks with the
+ * Woodbury correction z_d = B_d g_d - W_d C_d^-1 U_d^T B_d g_d, plus
+ * C_(l)^T M_(l)^-1 C_(l) g for every coarse level. */
+mas_status mas_apply(void* ctx, const double* g, double* z);
+
+/* y = H_base v, plus U U^T v when with_update != 0 (device, 3N, no alias).
+ * H_base = M + sum_e S_e^T H_e S_e + sum_{c in base} k_c n_c n_c^T frozen at
+ * the last mas_build. */
+mas_status hess_vec(void* ctx, const double* v, double* y, int32_t with_update);
+
+/* 2x2 subspace step (Section 4.2; supplement Section 2.4).  Inputs g, z,
+ * z_prev, v_z = H_base z; in/out p (p_k -> p_{k+1}) and v_p (H_base p_k ->
+ * H_base p_{k+1}, updated by linearity).  restart != 0 takes mu = g^T z /
+ * z^T H~ z, nu = 0 (Algorithm 1).  z_prev may be NULL (r = 0).  out is a
+ * device pointer.  Singular systems fall back to mu = 1, nu = 0. */
+mas_status pncg_subspace_step(void* ctx, const double* g, const double* z, const double* z_prev,
+                              const double* v_z, double* p, double* v_p, int32_t restart,
+                              mas_step_out* out);
+
+/* Incremental potential (Section 3.1) at x: E (device scalar) and, if g is
+ * not NULL, its gradient (device, 3N).  Contacts with d <= 0 make E = +inf. */
+mas_status mas_energy_grad(void* ctx, const double* x, const double* x_tilde,
+                           const mas_contacts* c, double* E, double* g);
+
+/* x~ = x^t + h v^t + h^2 gravity (device vectors). */
+mas_status mas_inertial_target(void* ctx, const double* x_t, const double* v_t, double* x_tilde);
+
+/* Distances of affine stencils d = grad . x[idx] - off (device arrays). */
+mas_status mas_stencil_distance(void* ctx, const double* x, int64_t m, const int32_t* idx,
+                                const double* grad, const double* off, double* d_out);
+
+/* Per-subdomain safe steps for affine stencils (cand): alpha_c = min(1,
+ * 0.9 d_c / sum_j max(0, -grad_cj . p_j)), alpha_d = min(1, min over stencils
+ * touching subdomain d).  Writes x_out = x + scale * alpha_{sub(v)} p_v
+ * (device, 3N).  cand == NULL reuses the step sizes of the previous call
+ * (line-search halving only changes scale).  alpha (device, D_0, nullable)
+ * receives the step sizes. */
+mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_contacts* cand,
+                         double scale, double* alpha, double* x_out);
+
+/* Synchronises the stream and returns the sticky device error (and clears
+ * it); msg (nullable) receives a description. */
+mas_status mas_sync_status(void* ctx, char* msg, int32_t msg_len);
+
+/* Sizes: N, T, number of levels, D_l for l < 6. */
+mas_status mas_query(void* ctx, int64_t* N, int64_t* T, int32_t* levels, int64_t* nsub /*6*/);
+
+/* Copies block d of level l, dequantised to float64, as a dense 96x96
+ * row-major host array (for verification). */
+mas_status mas_get_block(void* ctx, int32_t level, int64_t d, double* out_host);
+
+/* Copies the Top-K selection: per level-0 subdomain its rank (host int32 D_0)
+ * and the selected current-contact indices (host int32 D_0 x max_rank, -1 when
+ * unused), in ranking order. */
+mas_status mas_get_selection(void* ctx, int32_t* rank_host, int32_t* sel_host);
+
+/* Returns a static string naming a status code. */
+const char* mas_status_string(mas_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MASPNCG_H */

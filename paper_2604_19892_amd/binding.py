@@ -1,0 +1,213 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+PyTorch provides device memory and the stream; every computation runs in
+the HIP library.  Vectors live in the library's Morton vertex order; the
+helpers ``to_lib`` / ``from_lib`` move host arrays in and out of it.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import MasConfig, MasContacts, MasMesh, MasStepOut, check
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=None,
+                hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12):
+    cfg = MasConfig()
+    _abi.lib().mas_default_config(ctypes.byref(cfg))
+    if scene is not None:
+        cfg.kappa = float(scene.kappa)
+        cfg.dhat = float(scene.dhat)
+        cfg.h = float(scene.h)
+        for a in range(3):
+            cfg.gravity[a] = float(scene.gravity[a])
+        cfg.num_levels = int(levels if levels is not None else scene.levels)
+        cfg.max_rank = int(K if K is not None else scene.K)
+    else:
+        if levels is not None:
+            cfg.num_levels = int(levels)
+        if K is not None:
+            cfg.max_rank = int(K)
+    cfg.block_prec = _abi.PREC[block_prec]
+    cp = coarse_prec or ("f64" if block_prec == "f64" else "f32")
+    hp = hess_prec or ("f64" if block_prec == "f64" else "f32")
+    cfg.coarse_prec = _abi.PREC[cp]
+    cfg.hess_prec = _abi.PREC[hp]
+    cfg.restart_delta = float(delta)
+    cfg.eps_sing = float(eps_sing)
+    if cos_rot is not None:
+        cfg.cos_rot = float(cos_rot)
+    return cfg
+
+
+class DeviceContacts:
+    """Contact stencils on the device in library vertex numbering."""
+
+    def __init__(self, key, idx, grad, d=None, off=None, device="cuda"):
+        self.key = torch.as_tensor(np.ascontiguousarray(key).view(np.int64), device=device)
+        self.idx = torch.as_tensor(np.ascontiguousarray(idx, np.int32), device=device)
+        self.grad = torch.as_tensor(np.ascontiguousarray(grad, np.float64), device=device)
+        m = self.key.shape[0]
+        self.d = (torch.as_tensor(np.ascontiguousarray(d, np.float64), device=device) if d is not None
+                  else torch.zeros(m, dtype=torch.float64, device=device))
+        self.off = (torch.as_tensor(np.ascontiguousarray(off, np.float64), device=device)
+                    if off is not None else None)
+
+    @property
+    def m(self):
+        return int(self.key.shape[0])
+
+    def struct(self):
+        c = MasContacts()
+        c.m = self.m
+        c.key = self.key.data_ptr() if self.m else None
+        c.idx = self.idx.data_ptr() if self.m else None
+        c.d = self.d.data_ptr() if self.m else None
+        c.grad = self.grad.data_ptr() if self.m else None
+        return c
+
+
+class MasContext:
+    """One library context for one mesh (``mas_create`` .. ``mas_destroy``)."""
+
+    def __init__(self, scene, cfg, device="cuda"):
+        L = _abi.lib()
+        self.device = device
+        self.scene = scene
+        X = np.ascontiguousarray(scene.X, np.float64)
+        tets = np.ascontiguousarray(scene.tets, np.int32)
+        self._host = [X, tets, np.ascontiguousarray(scene.density, np.float64),
+                      np.ascontiguousarray(scene.youngs, np.float64),
+                      np.ascontiguousarray(scene.poisson, np.float64)]
+        mesh = MasMesh()
+        mesh.num_vertices = X.shape[0]
+        mesh.num_tets = tets.shape[0]
+        mesh.rest_x = X.ctypes.data
+        mesh.tets = tets.ctypes.data
+        mesh.density = self._host[2].ctypes.data
+        mesh.youngs = self._host[3].ctypes.data
+        mesh.poisson = self._host[4].ctypes.data
+        self.N = X.shape[0]
+        self.perm = np.zeros(self.N, np.int32)
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream().cuda_stream
+        check("mas_create", L.mas_create(ctypes.byref(cfg), ctypes.byref(mesh), ctypes.c_void_p(stream),
+                                         ctypes.byref(h), self.perm.ctypes.data))
+        self.h = h
+        self.cfg = cfg
+        self.rank = np.empty(self.N, np.int64)
+        self.rank[self.perm] = np.arange(self.N)
+        nsub = np.zeros(6, np.int64)
+        levels = ctypes.c_int32()
+        check("mas_query", L.mas_query(h, None, None, ctypes.byref(levels), nsub.ctypes.data))
+        self.levels = levels.value
+        self.nsub = nsub[:self.levels].copy()
+        self.out = torch.zeros(ctypes.sizeof(MasStepOut) // 8, dtype=torch.float64, device=device)
+
+    def close(self):
+        if self.h:
+            _abi.lib().mas_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- marshalling
+    def to_lib(self, v):
+        """(N,3) or (3N,) host array in original order -> (3N,) device tensor."""
+        a = np.asarray(v, np.float64).reshape(-1, 3)[self.perm].reshape(-1)
+        return torch.as_tensor(np.ascontiguousarray(a), device=self.device)
+
+    def from_lib(self, t):
+        a = t.detach().cpu().numpy().reshape(-1, 3)
+        out = np.empty_like(a)
+        out[self.perm] = a
+        return out.reshape(-1)
+
+    def contacts(self, cset):
+        """Host contact set (original vertex ids) -> DeviceContacts."""
+        idx = np.where(cset['idx'] >= 0, self.rank[np.maximum(cset['idx'], 0)], -1).astype(np.int32)
+        return DeviceContacts(cset['key'], idx, cset['grad'], d=cset.get('d'), off=cset.get('off'),
+                              device=self.device)
+
+    def vec(self):
+        return torch.zeros(3 * self.N, dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------- calls
+    def build(self, x, base):
+        c = base.struct() if base is not None else None
+        check("mas_build", _abi.lib().mas_build(self.h, _ptr(x), ctypes.byref(c) if c else None))
+
+    def woodbury_update(self, curr, rank_hist=None):
+        c = curr.struct()
+        check("mas_woodbury_update", _abi.lib().mas_woodbury_update(self.h, ctypes.byref(c), _ptr(rank_hist)))
+
+    def apply(self, g, z=None):
+        z = self.vec() if z is None else z
+        check("mas_apply", _abi.lib().mas_apply(self.h, _ptr(g), _ptr(z)))
+        return z
+
+    def hess_vec(self, v, with_update=True, y=None):
+        y = self.vec() if y is None else y
+        check("hess_vec", _abi.lib().hess_vec(self.h, _ptr(v), _ptr(y), int(with_update)))
+        return y
+
+    def subspace_step(self, g, z, z_prev, vz, p, vp, restart):
+        check("pncg_subspace_step", _abi.lib().pncg_subspace_step(
+            self.h, _ptr(g), _ptr(z), _ptr(z_prev), _ptr(vz), _ptr(p), _ptr(vp), int(restart),
+            _ptr(self.out)))
+        return self.out
+
+    def step_out(self):
+        raw = self.out.cpu().numpy().view(np.uint8)
+        s = MasStepOut.from_buffer_copy(raw.tobytes())
+        return {f: getattr(s, f) for f in _abi.STEP_FIELDS}
+
+    def energy_grad(self, x, x_tilde, contacts, E, g=None):
+        c = contacts.struct() if contacts is not None else None
+        check("mas_energy_grad", _abi.lib().mas_energy_grad(self.h, _ptr(x), _ptr(x_tilde),
+                                                           ctypes.byref(c) if c else None, _ptr(E), _ptr(g)))
+
+    def inertial_target(self, x_t, v_t, out=None):
+        out = self.vec() if out is None else out
+        check("mas_inertial_target", _abi.lib().mas_inertial_target(self.h, _ptr(x_t), _ptr(v_t), _ptr(out)))
+        return out
+
+    def stencil_distance(self, x, contacts):
+        check("mas_stencil_distance", _abi.lib().mas_stencil_distance(
+            self.h, _ptr(x), contacts.m, _ptr(contacts.idx), _ptr(contacts.grad), _ptr(contacts.off),
+            _ptr(contacts.d)))
+
+    def safe_step(self, x, p, cand, scale, x_out, alpha=None):
+        c = cand.struct() if cand is not None else None
+        check("mas_safe_step", _abi.lib().mas_safe_step(self.h, _ptr(x), _ptr(p), ctypes.byref(c) if c else None,
+                                                       float(scale), _ptr(alpha), _ptr(x_out)))
+
+    def sync(self):
+        buf = ctypes.create_string_buffer(256)
+        code = _abi.lib().mas_sync_status(self.h, buf, 256)
+        return code, buf.value.decode()
+
+    def get_block(self, level, d):
+        out = np.zeros((96, 96))
+        check("mas_get_block", _abi.lib().mas_get_block(self.h, int(level), int(d), out.ctypes.data))
+        return out
+
+    def get_selection(self):
+        D0 = int(self.nsub[0])
+        K = max(int(self.cfg.max_rank), 0)
+        rank = np.zeros(D0, np.int32)
+        sel = np.full(D0 * max(K, 1), -1, np.int32)
+        check("mas_get_selection", _abi.lib().mas_get_selection(self.h, rank.ctypes.data, sel.ctypes.data))
+        return rank, sel[:D0 * K].reshape(D0, K)

@@ -1,0 +1,456 @@
+// C ABI entry points: argument checks, context lifetime, call order.
+#include <algorithm>
+#include <cstdio>
+#include <numeric>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace mas;
+
+namespace {
+
+Ctx* as_ctx(void* p) { return reinterpret_cast<Ctx*>(p); }
+
+template <typename T>
+mas_status dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)) != hipSuccess) return MAS_ERR_OOM;
+  return MAS_OK;
+}
+
+mas_status dalloc_bytes(void** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(p, n) != hipSuccess) return MAS_ERR_OOM;
+  return MAS_OK;
+}
+
+// 63-bit Morton code of positions normalised to the bounding box, 21 bits
+// per axis; x bits at positions 3b, y at 3b+1, z at 3b+2.
+void morton_order(const double* X, int64_t N, std::vector<int32_t>& perm) {
+  double lo[3], hi[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = X[a];
+    hi[a] = X[a];
+  }
+  for (int64_t i = 0; i < N; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], X[3 * i + a]);
+      hi[a] = std::max(hi[a], X[3 * i + a]);
+    }
+  for (int a = 0; a < 3; ++a) {
+    ext[a] = hi[a] - lo[a];
+    if (!(ext[a] > 0)) ext[a] = 1.0;
+  }
+  std::vector<uint64_t> code(N);
+  for (int64_t i = 0; i < N; ++i) {
+    uint64_t c = 0;
+    for (int a = 0; a < 3; ++a) {
+      double t = (X[3 * i + a] - lo[a]) / ext[a] * 2097151.0;
+      double f = std::floor(t);
+      if (f < 0) f = 0;
+      if (f > 2097151.0) f = 2097151.0;
+      uint64_t q = uint64_t(f);
+      for (int b = 0; b < 21; ++b) c |= ((q >> b) & 1ull) << (3 * b + a);
+    }
+    code[i] = c;
+  }
+  perm.resize(N);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t p, int32_t q) { return code[p] < code[q]; });
+}
+
+mas_status valid_contacts(const mas_contacts* c) {
+  if (!c) return MAS_OK;
+  if (c->m < 0) return MAS_ERR_INVALID_ARG;
+  if (c->m > 0 && (!c->key || !c->idx || !c->d || !c->grad)) return MAS_ERR_INVALID_ARG;
+  if (c->m > INT32_MAX / 4) return MAS_ERR_INVALID_ARG;
+  return MAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mas_default_config(mas_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->num_levels = 2;
+  cfg->max_rank = 8;
+  cfg->cos_rot = std::cos(25.0 * M_PI / 180.0);
+  cfg->restart_delta = 0.3;
+  cfg->eps_sing = 1e-12;
+  cfg->eps_abs = 1e-300;
+  cfg->kappa = 1.0;
+  cfg->dhat = 1e-3;
+  cfg->h = 0.01;
+  cfg->gravity[2] = -9.81;
+  cfg->block_prec = MAS_F64;
+  cfg->coarse_prec = MAS_F64;
+  cfg->hess_prec = MAS_F64;
+}
+
+const char* mas_status_string(mas_status s) {
+  switch (s) {
+    case MAS_OK: return "ok";
+    case MAS_ERR_INVALID_ARG: return "invalid argument";
+    case MAS_ERR_STATE: return "call out of order";
+    case MAS_ERR_OOM: return "device allocation failed";
+    case MAS_ERR_HIP: return "HIP runtime error";
+    case MAS_ERR_NOT_SPD: return "non-positive pivot (matrix not SPD)";
+    case MAS_ERR_NONFINITE: return "non-finite input";
+    case MAS_ERR_RANK: return "rank overflow";
+  }
+  return "unknown status";
+}
+
+mas_status mas_destroy(void* p) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx* c = as_ctx(p);
+  hipStreamSynchronize(c->s);
+  void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->tet_list, c->hf64, c->hf32, c->bkey,
+                  c->bkey_sorted, c->biota, c->bperm, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
+                  c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
+                  c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
+                  c->alpha, c->err, c->cub_tmp};
+  for (void* q : ptrs)
+    if (q) hipFree(q);
+  for (int l = 0; l < MAXL; ++l) {
+    Level& L = c->lv[l];
+    void* lp[] = {L.blk, L.scale, L.acc, L.r, L.c};
+    for (void* q : lp)
+      if (q) hipFree(q);
+  }
+  delete c;
+  return MAS_OK;
+}
+
+mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_stream, void** ctx_out,
+                      int32_t* perm_out) {
+  if (!cfg || !mesh || !ctx_out) return MAS_ERR_INVALID_ARG;
+  *ctx_out = nullptr;
+  const int64_t N = mesh->num_vertices, T = mesh->num_tets;
+  if (N <= 0 || T < 0 || N > (int64_t(1) << 30) || T > (int64_t(1) << 29)) return MAS_ERR_INVALID_ARG;
+  if (!mesh->rest_x || (T > 0 && (!mesh->tets || !mesh->density || !mesh->youngs || !mesh->poisson)))
+    return MAS_ERR_INVALID_ARG;
+  if (cfg->num_levels < 1 || cfg->num_levels > MAXL) return MAS_ERR_INVALID_ARG;
+  if (cfg->max_rank < 0 || cfg->max_rank > MAXK) return MAS_ERR_INVALID_ARG;
+  if (cfg->block_prec < MAS_F64 || cfg->block_prec > MAS_F16) return MAS_ERR_INVALID_ARG;
+  if (cfg->coarse_prec != MAS_F64 && cfg->coarse_prec != MAS_F32) return MAS_ERR_INVALID_ARG;
+  if (cfg->hess_prec != MAS_F64 && cfg->hess_prec != MAS_F32) return MAS_ERR_INVALID_ARG;
+  if (!(cfg->dhat > 0) || !(cfg->h > 0) || !(cfg->kappa >= 0)) return MAS_ERR_INVALID_ARG;
+  for (int64_t t = 0; t < 4 * T; ++t)
+    if (mesh->tets[t] < 0 || mesh->tets[t] >= N) return MAS_ERR_INVALID_ARG;
+
+  Ctx* c = new (std::nothrow) Ctx();
+  if (!c) return MAS_ERR_OOM;
+  c->s = reinterpret_cast<hipStream_t>(hip_stream);
+  c->cfg = *cfg;
+  c->N = N;
+  c->T = T;
+  c->Tpad = (T + TILE - 1) / TILE * TILE;
+  if (c->Tpad == 0) c->Tpad = TILE;
+  c->L = cfg->num_levels;
+  c->K = cfg->max_rank;
+  mas_status st = MAS_OK;
+#define TRY(x)                 \
+  do {                         \
+    st = (x);                  \
+    if (st != MAS_OK) {        \
+      mas_destroy(c);          \
+      return st;               \
+    }                          \
+  } while (0)
+
+  // Morton order and renumbered, locality-sorted tets
+  std::vector<int32_t> perm;
+  morton_order(mesh->rest_x, N, perm);
+  std::vector<int32_t> rank(N);
+  for (int64_t i = 0; i < N; ++i) rank[perm[i]] = int32_t(i);
+  std::vector<int32_t> torder(T);
+  std::vector<int32_t> tmin(T);
+  for (int64_t t = 0; t < T; ++t) {
+    int32_t m = INT32_MAX;
+    for (int j = 0; j < 4; ++j) m = std::min(m, rank[mesh->tets[4 * t + j]]);
+    tmin[t] = m;
+  }
+  std::iota(torder.begin(), torder.end(), 0);
+  std::stable_sort(torder.begin(), torder.end(), [&](int32_t a, int32_t b) { return tmin[a] < tmin[b]; });
+  std::vector<int32_t> tets(4 * T);
+  std::vector<double> rho(T), E(T), nu(T);
+  for (int64_t i = 0; i < T; ++i) {
+    int64_t t = torder[i];
+    for (int j = 0; j < 4; ++j) tets[4 * i + j] = rank[mesh->tets[4 * t + j]];
+    rho[i] = mesh->density[t];
+    E[i] = mesh->youngs[t];
+    nu[i] = mesh->poisson[t];
+  }
+  std::vector<double> Xl(3 * N);
+  for (int64_t i = 0; i < N; ++i)
+    for (int a = 0; a < 3; ++a) Xl[3 * i + a] = mesh->rest_x[3 * int64_t(perm[i]) + a];
+
+  // levels
+  int64_t nodes = N;
+  for (int l = 0; l < c->L; ++l) {
+    c->lv[l].nodes = nodes;
+    c->lv[l].nsub = (nodes + SUB - 1) / SUB;
+    c->lv[l].prec = (l == 0) ? cfg->block_prec : cfg->coarse_prec;
+    nodes = c->lv[l].nsub;
+  }
+  const int64_t D0 = c->lv[0].nsub;
+
+  // level-0 subdomain -> touching tets
+  std::vector<int32_t> toff(D0 + 1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    int ds[4], n = 0;
+    for (int j = 0; j < 4; ++j) {
+      int d = tets[4 * t + j] >> 5;
+      bool dup = false;
+      for (int q = 0; q < n; ++q) dup |= ds[q] == d;
+      if (!dup) ds[n++] = d;
+    }
+    for (int q = 0; q < n; ++q) toff[ds[q] + 1]++;
+  }
+  for (int64_t d = 0; d < D0; ++d) toff[d + 1] += toff[d];
+  std::vector<int32_t> tlist(std::max<int32_t>(toff[D0], 1));
+  {
+    std::vector<int32_t> cur(toff.begin(), toff.end() - 1);
+    for (int64_t t = 0; t < T; ++t) {
+      int ds[4], n = 0;
+      for (int j = 0; j < 4; ++j) {
+        int d = tets[4 * t + j] >> 5;
+        bool dup = false;
+        for (int q = 0; q < n; ++q) dup |= ds[q] == d;
+        if (!dup) ds[n++] = d;
+      }
+      for (int q = 0; q < n; ++q) tlist[cur[ds[q]]++] = int32_t(t);
+    }
+  }
+
+  // device memory
+  TRY(dalloc(&c->tets, 4 * T));
+  TRY(dalloc(&c->geo, 12 * T));
+  TRY(dalloc(&c->mass, N));
+  TRY(dalloc(&c->tet_off, D0 + 1));
+  TRY(dalloc(&c->tet_list, tlist.size()));
+  TRY(dalloc(&c->hf64, EH * c->Tpad));
+  if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hf32, EH * c->Tpad));
+  for (int l = 0; l < c->L; ++l) {
+    Level& L = c->lv[l];
+    TRY(dalloc_bytes(&L.blk, L.nsub * blk_elems(L.prec) * prec_size(L.prec)));
+    if (L.prec == MAS_BF16 || L.prec == MAS_F16) TRY(dalloc(&L.scale, L.nsub * BD));
+    if (l > 0) {
+      TRY(dalloc(&L.acc, L.nsub * PK));
+      TRY(dalloc(&L.r, 3 * L.nodes));
+      TRY(dalloc(&L.c, 3 * L.nodes));
+    }
+  }
+  TRY(dalloc(&c->bc_cnt, D0 + 1));
+  TRY(dalloc(&c->bc_off, D0 + 1));
+  TRY(dalloc(&c->cand_cnt, D0 + 1));
+  TRY(dalloc(&c->cand_off, D0 + 1));
+  int Kk = std::max(c->K, 1);
+  TRY(dalloc(&c->rank, D0));
+  TRY(dalloc(&c->sel, D0 * Kk));
+  TRY(dalloc(&c->slots, D0 * Kk));
+  TRY(dalloc_bytes(&c->W, size_t(D0) * Kk * BD * (cfg->block_prec == MAS_F64 ? 8 : 4)));
+  TRY(dalloc(&c->Lcap, D0 * (Kk * (Kk + 1) / 2)));
+  TRY(dalloc(&c->partials, 16 * c->n_partial_blocks));
+  TRY(dalloc(&c->scal, 64));
+  TRY(dalloc(&c->alpha, D0));
+  TRY(dalloc(&c->err, 1));
+  HIPCHK(hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->s));
+  HIPCHK(hipMemsetAsync(c->rank, 0, sizeof(int32_t) * D0, c->s));
+  HIPCHK(hipMemsetAsync(c->alpha, 0, sizeof(double) * D0, c->s));
+
+  HIPCHK(hipMemcpyAsync(c->tets, tets.data(), 4 * T * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->tet_off, toff.data(), (D0 + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->tet_list, tlist.data(), tlist.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  double *dX = nullptr, *drho = nullptr, *dE = nullptr, *dnu = nullptr;
+  TRY(dalloc(&dX, 3 * N));
+  TRY(dalloc(&drho, T));
+  TRY(dalloc(&dE, T));
+  TRY(dalloc(&dnu, T));
+  HIPCHK(hipMemcpyAsync(dX, Xl.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(drho, rho.data(), T * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(dE, E.data(), T * sizeof(double), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(dnu, nu.data(), T * sizeof(double), hipMemcpyHostToDevice, c->s));
+  st = launch_rest(*c, dX, drho, dE, dnu);
+  hipStreamSynchronize(c->s);
+  hipFree(dX);
+  hipFree(drho);
+  hipFree(dE);
+  hipFree(dnu);
+  if (st != MAS_OK) {
+    mas_destroy(c);
+    return st;
+  }
+  // scan temporaries for the subdomain buckets, sized once
+  TRY(bucket_by_subdomain(*c, 0, nullptr, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (perm_out) std::memcpy(perm_out, perm.data(), N * sizeof(int32_t));
+  *ctx_out = c;
+#undef TRY
+  return MAS_OK;
+}
+
+mas_status mas_build(void* p, const double* x_base, const mas_contacts* base) {
+  if (!p || !x_base) return MAS_ERR_INVALID_ARG;
+  mas_status st = valid_contacts(base);
+  if (st != MAS_OK) return st;
+  Ctx& c = *as_ctx(p);
+  if ((st = launch_elem_hessians(c, x_base)) != MAS_OK) return st;
+  if ((st = launch_base_contacts(c, base)) != MAS_OK) return st;
+  if ((st = launch_level0_build(c)) != MAS_OK) return st;
+  if ((st = launch_coarse_build(c)) != MAS_OK) return st;
+  c.built = true;
+  c.have_update = false;
+  c.mc = 0;
+  return MAS_OK;
+}
+
+mas_status mas_woodbury_update(void* p, const mas_contacts* cur, int32_t* rank_hist) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  mas_status st = valid_contacts(cur);
+  if (st != MAS_OK) return st;
+  Ctx& c = *as_ctx(p);
+  if (!c.built) return MAS_ERR_STATE;
+  if ((st = launch_woodbury(c, cur, rank_hist)) != MAS_OK) return st;
+  c.have_update = true;
+  return MAS_OK;
+}
+
+mas_status mas_apply(void* p, const double* g, double* z) {
+  if (!p || !g || !z || g == z) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.built) return MAS_ERR_STATE;
+  return launch_apply(c, g, z);
+}
+
+mas_status hess_vec(void* p, const double* v, double* y, int32_t with_update) {
+  if (!p || !v || !y || v == y) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.built) return MAS_ERR_STATE;
+  return launch_hessvec(c, v, y, with_update);
+}
+
+mas_status pncg_subspace_step(void* p, const double* g, const double* z, const double* z_prev,
+                              const double* v_z, double* pk_, double* v_p, int32_t restart,
+                              mas_step_out* out) {
+  if (!p || !g || !z || !v_z || !pk_ || !v_p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.built) return MAS_ERR_STATE;
+  return launch_subspace(c, g, z, z_prev, v_z, pk_, v_p, restart, out);
+}
+
+mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, const mas_contacts* ct,
+                           double* E, double* g) {
+  if (!p || !x || !x_tilde || !E) return MAS_ERR_INVALID_ARG;
+  mas_status st = valid_contacts(ct);
+  if (st != MAS_OK) return st;
+  return launch_energy_grad(*as_ctx(p), x, x_tilde, ct, E, g);
+}
+
+mas_status mas_inertial_target(void* p, const double* x_t, const double* v_t, double* x_tilde) {
+  if (!p || !x_t || !v_t || !x_tilde) return MAS_ERR_INVALID_ARG;
+  return launch_inertial(*as_ctx(p), x_t, v_t, x_tilde);
+}
+
+mas_status mas_stencil_distance(void* p, const double* x, int64_t m, const int32_t* idx,
+                                const double* grad, const double* off, double* d_out) {
+  if (!p || !x || m < 0 || (m > 0 && (!idx || !grad || !off || !d_out))) return MAS_ERR_INVALID_ARG;
+  return launch_stencil_distance(*as_ctx(p), x, m, idx, grad, off, d_out);
+}
+
+mas_status mas_safe_step(void* p, const double* x, const double* pv, const mas_contacts* cand,
+                         double scale, double* alpha, double* x_out) {
+  if (!p || !x || !pv || !x_out) return MAS_ERR_INVALID_ARG;
+  mas_status st = valid_contacts(cand);
+  if (st != MAS_OK) return st;
+  return launch_safe_step(*as_ctx(p), x, pv, cand, scale, alpha, x_out);
+}
+
+mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  hipError_t e = hipStreamSynchronize(c.s);
+  mas_status st = MAS_OK;
+  if (e != hipSuccess) {
+    st = MAS_ERR_HIP;
+  } else {
+    uint32_t bits = 0;
+    if (hipMemcpy(&bits, c.err, sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) st = MAS_ERR_HIP;
+    hipMemset(c.err, 0, sizeof(uint32_t));
+    if (bits & ERRB_NOT_SPD) st = MAS_ERR_NOT_SPD;
+    else if (bits & ERRB_NONFINITE) st = MAS_ERR_NONFINITE;
+    else if (bits & ERRB_RANK) st = MAS_ERR_RANK;
+  }
+  if (msg && msg_len > 0) {
+    if (st == MAS_ERR_HIP)
+      std::snprintf(msg, msg_len, "%s: %s", mas_status_string(st), hipGetErrorString(e));
+    else
+      std::snprintf(msg, msg_len, "%s", mas_status_string(st));
+  }
+  return st;
+}
+
+mas_status mas_query(void* p, int64_t* N, int64_t* T, int32_t* levels, int64_t* nsub) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (N) *N = c.N;
+  if (T) *T = c.T;
+  if (levels) *levels = c.L;
+  if (nsub)
+    for (int l = 0; l < MAXL; ++l) nsub[l] = l < c.L ? c.lv[l].nsub : 0;
+  return MAS_OK;
+}
+
+mas_status mas_get_block(void* p, int32_t level, int64_t d, double* out) {
+  if (!p || !out) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (level < 0 || level >= c.L || d < 0 || d >= c.lv[level].nsub) return MAS_ERR_INVALID_ARG;
+  if (!c.built) return MAS_ERR_STATE;
+  Level& L = c.lv[level];
+  size_t es = prec_size(L.prec), ne = blk_elems(L.prec);
+  std::vector<unsigned char> raw(ne * es);
+  std::vector<float> sig(BD, 1.0f);
+  HIPCHK(hipStreamSynchronize(c.s));
+  HIPCHK(hipMemcpy(raw.data(), reinterpret_cast<unsigned char*>(L.blk) + d * ne * es, ne * es,
+                   hipMemcpyDeviceToHost));
+  if (L.scale) HIPCHK(hipMemcpy(sig.data(), L.scale + d * BD, BD * sizeof(float), hipMemcpyDeviceToHost));
+  for (int i = 0; i < BD; ++i)
+    for (int j = 0; j <= i; ++j) {
+      int e = pk(i, j);
+      double v;
+      if (L.prec == MAS_F64) v = reinterpret_cast<double*>(raw.data())[e];
+      else if (L.prec == MAS_F32) v = reinterpret_cast<float*>(raw.data())[e];
+      else {
+        uint16_t h = reinterpret_cast<uint16_t*>(raw.data())[e];
+        float f = L.prec == MAS_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
+        v = double(f) * sig[i] * sig[j];
+      }
+      out[i * BD + j] = v;
+      out[j * BD + i] = v;
+    }
+  return MAS_OK;
+}
+
+mas_status mas_get_selection(void* p, int32_t* rank_host, int32_t* sel_host) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  const int64_t D0 = c.lv[0].nsub;
+  HIPCHK(hipStreamSynchronize(c.s));
+  if (!c.have_update || c.K == 0) {
+    if (rank_host) std::memset(rank_host, 0, D0 * sizeof(int32_t));
+    if (sel_host) std::fill(sel_host, sel_host + D0 * c.K, -1);
+    return MAS_OK;
+  }
+  if (rank_host) HIPCHK(hipMemcpy(rank_host, c.rank, D0 * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (sel_host) HIPCHK(hipMemcpy(sel_host, c.sel, D0 * c.K * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return MAS_OK;
+}
+
+}  // extern "C"

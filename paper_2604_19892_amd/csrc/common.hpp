@@ -1,0 +1,158 @@
+// Shared types of the MAS-PNCG HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <cstring>
+#include <cmath>
+
+#include "maspncg.h"
+
+namespace mas {
+
+constexpr int SUB = 32;                 // vertices (nodes) per subdomain
+constexpr int BD = 96;                  // block dimension (3 DOFs x 32)
+constexpr int PK = BD * (BD + 1) / 2;   // packed lower-triangular entries (4656)
+constexpr int MAXL = 6;                 // maximum MAS levels
+constexpr int MAXK = 32;                // maximum Woodbury rank per subdomain
+constexpr int EH = 54;                  // per-tet snapshot: 45 (9x9 packed) + 9 (Dm^-1)
+constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
+
+// sticky device error bits
+constexpr uint32_t ERRB_NOT_SPD = 1u;
+constexpr uint32_t ERRB_NONFINITE = 2u;
+constexpr uint32_t ERRB_RANK = 4u;
+
+// packed lower-triangular index, i >= j
+__host__ __device__ inline int pk(int i, int j) { return i * (i + 1) / 2 + j; }
+__host__ __device__ inline int pks(int i, int j) { return i >= j ? pk(i, j) : pk(j, i); }
+
+// symmetric 9x9 packed index (upper storage is the same as lower by symmetry)
+__host__ __device__ inline constexpr int p9(int i, int j) {
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+__host__ __device__ inline constexpr size_t prec_size(int p) {
+  return p == MAS_F64 ? 8 : (p == MAS_F32 ? 4 : 2);
+}
+// elements per stored block: packed size rounded up to a 256-byte multiple
+__host__ __device__ inline constexpr size_t blk_elems(int p) {
+  return (PK + 256 / prec_size(p) - 1) / (256 / prec_size(p)) * (256 / prec_size(p));
+}
+
+// ------------------------------------------------------------ 16-bit floats
+// bfloat16: upper half of an IEEE binary32; rounding to nearest even.
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  uint32_t u = uint32_t(h) << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t(u >> 16);  // inf / nan
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return uint16_t(u >> 16);
+}
+__host__ __device__ inline float f16_to_f32(uint16_t h) {
+  _Float16 v;
+  memcpy(&v, &h, 2);
+  return float(v);
+}
+__host__ __device__ inline uint16_t f32_to_f16(float f) {
+  _Float16 v = _Float16(f);
+  uint16_t h;
+  memcpy(&h, &v, 2);
+  return h;
+}
+
+// positive doubles order like their bit patterns: atomic min through uint64
+__device__ inline void atomic_min_pos(double* a, double v) {
+  atomicMin(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
+}
+
+struct SlotCol {        // one column of U_d restricted to its subdomain
+  int32_t lv[4];        // local vertex (0..31) of each stencil vertex, -1 if outside
+  double u[12];
+};
+
+struct Level {
+  int64_t nodes = 0;    // level-l nodes (level 0: vertices)
+  int64_t nsub = 0;     // D_l
+  int prec = MAS_F64;
+  void* blk = nullptr;  // nsub * blk_elems(prec) entries
+  float* scale = nullptr;  // nsub * 96 row scales (16-bit storage)
+  double* acc = nullptr;   // packed FP64 accumulation (levels >= 1)
+  double* r = nullptr;     // restricted residual 3*nodes (levels >= 1)
+  double* c = nullptr;     // coarse correction 3*nodes (levels >= 1)
+};
+
+struct Ctx {
+  hipStream_t s = nullptr;
+  mas_config cfg{};
+  int64_t N = 0, T = 0, Tpad = 0;
+  int L = 1, K = 8;
+  Level lv[MAXL];
+
+  // mesh, library order
+  int32_t* tets = nullptr;     // 4T
+  double* geo = nullptr;       // 12T: Dm^-1 (9, row-major), vol, mu, lam
+  double* mass = nullptr;      // N
+  int32_t* tet_off = nullptr;  // D0+1, level-0 subdomain -> touching tets
+  int32_t* tet_list = nullptr;
+
+  // Hessian snapshot (AoSoA tiles of 64 tets: [Tpad/64][54][64])
+  double* hf64 = nullptr;
+  float* hf32 = nullptr;
+  bool built = false;
+
+  // base contact set
+  int64_t mb = 0, mb_cap = 0;
+  uint64_t* bkey = nullptr;        // mb, input order
+  uint64_t* bkey_sorted = nullptr; // mb
+  int32_t* biota = nullptr;        // mb
+  int32_t* bperm = nullptr;        // mb: sorted position -> input index
+  double* bk = nullptr;            // mb stiffness
+  double* bgrad = nullptr;         // 12 mb
+  int32_t* bidx = nullptr;         // 4 mb
+  double* bu = nullptr;            // 12 mb, sqrt(k) n
+  int32_t* bc_cnt = nullptr;       // D0
+  int32_t* bc_off = nullptr;       // D0+1
+  int32_t* bc_list = nullptr;      // 4 mb
+
+  // current update (untruncated U) and the localized Woodbury data
+  int64_t mc = 0, mc_cap = 0;
+  double* U = nullptr;             // 12 mc
+  int32_t* Uidx = nullptr;         // 4 mc
+  double* dS = nullptr;            // mc
+  uint64_t* ckey = nullptr;        // mc
+  int32_t* cand_cnt = nullptr;     // D0
+  int32_t* cand_off = nullptr;     // D0+1
+  int32_t* cand_list = nullptr;    // 4 mc
+  int32_t* rank = nullptr;         // D0
+  int32_t* sel = nullptr;          // D0*K
+  SlotCol* slots = nullptr;        // D0*K
+  void* W = nullptr;               // D0*96*K (FP64 if block_prec==F64 else FP32)
+  double* Lcap = nullptr;          // D0*K*(K+1)/2
+  bool have_update = false;
+
+  // scratch
+  double* partials = nullptr;      // reductions
+  int n_partial_blocks = 1024;
+  double* scal = nullptr;          // small device scalars (mu, nu, ...)
+  double* alpha = nullptr;         // D0
+  uint32_t* err = nullptr;         // sticky error bits
+  void* cub_tmp = nullptr;
+  size_t cub_bytes = 0;
+};
+
+}  // namespace mas
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return MAS_ERR_HIP;         \
+  } while (0)

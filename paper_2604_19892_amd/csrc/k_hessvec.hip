@@ -1,0 +1,87 @@
+// Matrix-free product with the frozen Hessian snapshot:
+//   y = M v + sum_e S_e^T H_e S_e v + sum_{c in base} k_c n_c (n_c^T v)
+//       [+ sum_c u_c (u_c^T v) for the current update columns].
+// H_e is never formed: each tet stores its projected 9x9 tangent (45) and
+// Dm^-1 (9) and applies B^T Hf B v on the fly, which moves 54 values per tet
+// instead of the 78 of a packed 12x12.
+#include "kernels.hpp"
+#include "elem.hpp"
+
+namespace mas {
+
+__global__ void k_mass_mul(int64_t n3, const double* mass, const double* v, double* y) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  y[i] = mass[i / 3] * v[i];
+}
+
+template <typename TH>
+__global__ __launch_bounds__(256) void k_hv_tets(int64_t T, const int32_t* tets, const TH* hf,
+                                                 const double* v, double* y) {
+  int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= T) return;
+  const int64_t base = (t / TILE) * (EH * TILE) + (t % TILE);
+  TH H[45], Dmi[9];
+#pragma unroll
+  for (int q = 0; q < 45; ++q) H[q] = hf[base + q * TILE];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Dmi[q] = hf[base + (45 + q) * TILE];
+  int vi[4];
+  double ve[12];
+  const int4 tv = reinterpret_cast<const int4*>(tets)[t];
+  vi[0] = tv.x; vi[1] = tv.y; vi[2] = tv.z; vi[3] = tv.w;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ve[3 * j + a] = v[3 * vi[j] + a];
+  double f[12];
+  elem_hv<TH>(H, Dmi, ve, f);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) atomicAdd(&y[3 * vi[j] + a], f[3 * j + a]);
+}
+
+// rank-one stencil columns: y += u (u^T v)
+__global__ void k_hv_cols(int64_t m, const int32_t* idx, const double* u, const double* v, double* y) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= m) return;
+  const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+  int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+  double uu[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) uu[q] = u[12 * i + q];
+  double w = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (vi[j] < 0) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w += uu[3 * j + a] * v[3 * vi[j] + a];
+  }
+  if (w == 0.0) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (vi[j] < 0) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) atomicAdd(&y[3 * vi[j] + a], w * uu[3 * j + a]);
+  }
+}
+
+mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update) {
+  int64_t n3 = 3 * c.N;
+  k_mass_mul<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, c.mass, v, y);
+  if (c.T > 0) {
+    if (c.hf32)
+      k_hv_tets<float><<<dim3((c.T + 255) / 256), dim3(256), 0, c.s>>>(c.T, c.tets, c.hf32, v, y);
+    else
+      k_hv_tets<double><<<dim3((c.T + 255) / 256), dim3(256), 0, c.s>>>(c.T, c.tets, c.hf64, v, y);
+  }
+  if (c.mb > 0)
+    k_hv_cols<<<dim3((c.mb + 255) / 256), dim3(256), 0, c.s>>>(c.mb, c.bidx, c.bu, v, y);
+  if (with_update && c.have_update && c.mc > 0)
+    k_hv_cols<<<dim3((c.mc + 255) / 256), dim3(256), 0, c.s>>>(c.mc, c.Uidx, c.U, v, y);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+}  // namespace mas

@@ -1,0 +1,338 @@
+// Per-iteration kernels around the preconditioner: energy and gradient of
+// the incremental potential, the 2x2 subspace step with its fallback and the
+// restart ratio, and the per-subdomain safe step.
+#include "kernels.hpp"
+#include "elem.hpp"
+
+namespace mas {
+
+constexpr int RB = 256;  // reduction block size
+
+// sums NV values across the block; thread 0 writes out[v * nblk + blockIdx.x]
+template <int NV>
+__device__ inline void block_reduce_store(double (&v)[NV], double* out, int nblk) {
+  __shared__ double sh[NV][RB / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double x = v[q];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) sh[q][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0;
+      for (int i = 0; i < RB / 64; ++i) s += sh[q][i];
+      out[q * nblk + blockIdx.x] = s;
+    }
+  }
+}
+
+// ----------------------------------------------------------- energy / grad
+// g = M (x - x~) and the inertia energy
+__global__ __launch_bounds__(RB) void k_eg_vertices(int64_t N, const double* mass, const double* x,
+                                                    const double* xt, double* g, double* part, int nblk) {
+  double e[1] = {0.0};
+  for (int64_t v = blockIdx.x * int64_t(RB) + threadIdx.x; v < N; v += int64_t(nblk) * RB) {
+    double m = mass[v];
+    for (int a = 0; a < 3; ++a) {
+      double dx = x[3 * v + a] - xt[3 * v + a];
+      if (g) g[3 * v + a] = m * dx;
+      e[0] += 0.5 * m * dx * dx;
+    }
+  }
+  block_reduce_store<1>(e, part, nblk);
+}
+
+// h^2 V Psi(F) and its gradient h^2 V P Dm^-T scattered to the vertices
+__global__ __launch_bounds__(RB) void k_eg_tets(int64_t T, const int32_t* tets, const double* geo,
+                                                const double* x, double h2, double* g, double* part,
+                                                int nblk) {
+  double e[1] = {0.0};
+  for (int64_t t = blockIdx.x * int64_t(RB) + threadIdx.x; t < T; t += int64_t(nblk) * RB) {
+    const int4 tv = reinterpret_cast<const int4*>(tets)[t];
+    int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+    double xe[12];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
+    const double* gm = geo + 12 * t;
+    double Dmi[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Dmi[q] = gm[q];
+    double F[3][3];
+    def_grad(xe, Dmi, F);
+    const double s = h2 * gm[9];
+    e[0] += s * snh_energy(F, gm[10], gm[11]);
+    if (g) {
+      double P[3][3];
+      snh_stress(F, gm[10], gm[11], P);
+      double f0[3] = {0, 0, 0};
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          double acc = 0;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) acc += P[a][b] * Dmi[3 * cc + b];
+          acc *= s;
+          f0[a] -= acc;
+          atomicAdd(&g[3 * vi[cc + 1] + a], acc);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) atomicAdd(&g[3 * vi[0] + a], f0[a]);
+    }
+  }
+  block_reduce_store<1>(e, part, nblk);
+}
+
+// kappa b(d) and kappa b'(d) grad d; a non-positive distance flags +inf
+__global__ __launch_bounds__(RB) void k_eg_contacts(int64_t m, const int32_t* idx, const double* d,
+                                                    const double* grad, double kappa, double dhat,
+                                                    double* g, double* part, int nblk) {
+  double e[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * int64_t(RB) + threadIdx.x; i < m; i += int64_t(nblk) * RB) {
+    double di = d[i];
+    if (!(di > 0.0)) {
+      e[1] += 1.0;
+      continue;
+    }
+    if (di >= dhat) continue;
+    double b, b1, b2;
+    barrier3(di, dhat, &b, &b1, &b2);
+    e[0] += kappa * b;
+    if (g) {
+      double s = kappa * b1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int v = idx[4 * i + j];
+        if (v < 0) continue;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) atomicAdd(&g[3 * v + a], s * grad[12 * i + 3 * j + a]);
+      }
+    }
+  }
+  block_reduce_store<2>(e, part, nblk);
+}
+
+__global__ void k_eg_finalize(const double* part, int nblk, double* E) {
+  if (threadIdx.x != 0) return;
+  double s = 0, bad = 0;
+  for (int q = 0; q < 3; ++q)
+    for (int i = 0; i < nblk; ++i) s += part[q * nblk + i];
+  for (int i = 0; i < nblk; ++i) bad += part[3 * nblk + i];
+  *E = bad > 0 ? INFINITY : s;
+}
+
+mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const mas_contacts* ct,
+                              double* E, double* g) {
+  const int nb = c.n_partial_blocks;
+  double* part = c.partials;  // [0]: inertia [1]: elastic [2]: barrier [3]: infeasible count
+  k_eg_vertices<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, c.mass, x, xt, g, part, nb);
+  k_eg_tets<<<dim3(nb), dim3(RB), 0, c.s>>>(c.T, c.tets, c.geo, x, c.cfg.h * c.cfg.h, g, part + nb, nb);
+  int64_t m = ct ? ct->m : 0;
+  if (m > 0) {
+    // writes part[2*nb..] (energy) and part[3*nb..] (infeasible count)
+    k_eg_contacts<<<dim3(nb), dim3(RB), 0, c.s>>>(m, ct->idx, ct->d, ct->grad, c.cfg.kappa, c.cfg.dhat, g,
+                                                   part + 2 * nb, nb);
+  } else {
+    HIPCHK(hipMemsetAsync(part + 2 * nb, 0, sizeof(double) * 2 * nb, c.s));
+  }
+  k_eg_finalize<<<dim3(1), dim3(64), 0, c.s>>>(part, nb, E);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+// ------------------------------------------------------------ subspace step
+// per block: g.z, g.p, g.zp, z.vz, z.vp, p.vp, g.g, z.z and over the update
+// columns (u.z)^2, (u.z)(u.p), (u.p)^2
+constexpr int NS = 11;
+
+__global__ __launch_bounds__(RB) void k_ss_reduce(int64_t n3, const double* g, const double* z,
+                                                  const double* zp, const double* p, const double* vz,
+                                                  const double* vp, int use_p, int64_t m,
+                                                  const int32_t* Uidx, const double* U, double* part,
+                                                  int nblk) {
+  double s[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) s[q] = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(RB) + threadIdx.x; i < n3; i += int64_t(nblk) * RB) {
+    double gi = g[i], zi = z[i], vzi = vz[i];
+    s[0] += gi * zi;
+    if (zp) s[2] += gi * zp[i];
+    s[3] += zi * vzi;
+    s[6] += gi * gi;
+    s[7] += zi * zi;
+    if (use_p) {
+      double pi = p[i], vpi = vp[i];
+      s[1] += gi * pi;
+      s[4] += zi * vpi;
+      s[5] += pi * vpi;
+    }
+  }
+  for (int64_t c = blockIdx.x * int64_t(RB) + threadIdx.x; c < m; c += int64_t(nblk) * RB) {
+    const int4 iv = reinterpret_cast<const int4*>(Uidx)[c];
+    int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+    double xz = 0, xp = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (vi[j] < 0) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double u = U[12 * c + 3 * j + a];
+        xz += u * z[3 * vi[j] + a];
+        if (use_p) xp += u * p[3 * vi[j] + a];
+      }
+    }
+    s[8] += xz * xz;
+    s[9] += xz * xp;
+    s[10] += xp * xp;
+  }
+  block_reduce_store<NS>(s, part, nblk);
+}
+
+__global__ void k_ss_finalize(const double* part, int nblk, int restart, int has_zp, double eps_sing,
+                              double eps_abs, double delta, mas_step_out* out, double* scal) {
+  if (threadIdx.x != 0) return;
+  double s[NS];
+  for (int q = 0; q < NS; ++q) {
+    double acc = 0;
+    for (int i = 0; i < nblk; ++i) acc += part[q * nblk + i];
+    s[q] = acc;
+  }
+  double gz = s[0], gp = s[1], gzp = s[2];
+  double A11 = s[3] + s[8], A12 = s[4] + s[9], A22 = s[5] + s[10];
+  double mu, nu;
+  int fb = 0;
+  if (restart) {
+    if (A11 > 0) {
+      mu = gz / A11;
+      nu = 0.0;
+    } else {
+      mu = 1.0;
+      nu = 0.0;
+      fb = 1;
+    }
+  } else {
+    double det = A11 * A22 - A12 * A12;
+    if (fabs(det) < eps_sing * fmax(A11 * A22, eps_abs)) {
+      mu = 1.0;
+      nu = 0.0;
+      fb = 1;
+    } else {
+      mu = (gz * A22 - A12 * gp) / det;
+      nu = (A12 * gz - A11 * gp) / det;
+    }
+  }
+  double r = has_zp ? fabs(gzp) / gz : 0.0;
+  mas_step_out o;
+  o.mu = mu;
+  o.nu = nu;
+  o.r = r;
+  o.gz = gz;
+  o.gp = gp;
+  o.gzp = gzp;
+  o.A11 = A11;
+  o.A12 = A12;
+  o.A22 = A22;
+  o.gnorm2 = s[6];
+  o.znorm2 = s[7];
+  o.fallback = fb;
+  o.restart_next = (r > delta) ? 1 : 0;
+  o.restart_used = restart ? 1 : 0;
+  o.reserved = 0;
+  if (out) *out = o;
+  scal[0] = mu;
+  scal[1] = nu;
+}
+
+// p <- -mu z + nu p;  v_p <- -mu v_z + nu v_p  (H_base is linear)
+__global__ void k_ss_update(int64_t n3, const double* z, const double* vz, double* p, double* vp,
+                            const double* scal) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  const double mu = scal[0], nu = scal[1];
+  if (nu == 0.0) {
+    p[i] = -mu * z[i];
+    vp[i] = -mu * vz[i];
+  } else {
+    p[i] = -mu * z[i] + nu * p[i];
+    vp[i] = -mu * vz[i] + nu * vp[i];
+  }
+}
+
+mas_status launch_subspace(Ctx& c, const double* g, const double* z, const double* zp,
+                           const double* vz, double* p, double* vp, int restart, mas_step_out* out) {
+  const int nb = c.n_partial_blocks;
+  int64_t n3 = 3 * c.N;
+  int64_t m = (c.have_update) ? c.mc : 0;
+  k_ss_reduce<<<dim3(nb), dim3(RB), 0, c.s>>>(n3, g, z, zp, p, vz, vp, restart ? 0 : 1, m, c.Uidx, c.U,
+                                              c.partials, nb);
+  k_ss_finalize<<<dim3(1), dim3(64), 0, c.s>>>(c.partials, nb, restart, zp != nullptr, c.cfg.eps_sing,
+                                               c.cfg.eps_abs, c.cfg.restart_delta, out, c.scal);
+  k_ss_update<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, z, vz, p, vp, c.scal);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+// ------------------------------------------------------------- safe step
+__global__ void k_alpha_init(int64_t D, double* alpha) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < D) alpha[i] = 1.0;
+}
+
+// alpha_c = min(1, 0.9 d / sum_j max(0, -grad_j . p_j)) to every subdomain
+// the stencil touches
+__global__ void k_alpha_stencils(int64_t m, const int32_t* idx, const double* grad, const double* d,
+                                 const double* p, double* alpha) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= m) return;
+  const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+  int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+  double s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (vi[j] < 0) continue;
+    double dot = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dot += grad[12 * i + 3 * j + a] * p[3 * vi[j] + a];
+    s += fmax(0.0, -dot);
+  }
+  if (!(s > 0.0)) return;
+  double a = fmin(1.0, 0.9 * d[i] / s);
+  a = fmax(a, 0.0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (vi[j] < 0) continue;
+    atomic_min_pos(&alpha[vi[j] >> 5], a);
+  }
+}
+
+__global__ void k_step(int64_t n3, const double* x, const double* p, const double* alpha, double scale,
+                       double* xo) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  xo[i] = x[i] + scale * alpha[(i / 3) >> 5] * p[i];
+}
+
+mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
+                            double scale, double* alpha, double* x_out) {
+  const int64_t D = c.lv[0].nsub;
+  if (cand) {
+    k_alpha_init<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, c.alpha);
+    if (cand->m > 0)
+      k_alpha_stencils<<<dim3((cand->m + 255) / 256), dim3(256), 0, c.s>>>(cand->m, cand->idx, cand->grad,
+                                                                            cand->d, p, c.alpha);
+  }
+  int64_t n3 = 3 * c.N;
+  k_step<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);
+  if (alpha) HIPCHK(hipMemcpyAsync(alpha, c.alpha, sizeof(double) * D, hipMemcpyDeviceToDevice, c.s));
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+}  // namespace mas

@@ -1,0 +1,114 @@
+// Bucketing of contact stencils into per-subdomain lists and key sorting.
+#include <hipcub/hipcub.hpp>
+
+#include "kernels.hpp"
+
+namespace mas {
+
+// distinct level-0 subdomains of stencil i that carry a nonzero part of the
+// 12-vector vec (only when w[i] > 0); returns count, writes them to out[4]
+__device__ inline int stencil_buckets(int64_t i, const int32_t* idx, const double* w,
+                                      const double* vec12, int out[4]) {
+  int n = 0;
+  if (!(w[i] > 0.0)) return 0;
+  for (int j = 0; j < 4; ++j) {
+    int v = idx[4 * i + j];
+    if (v < 0) continue;
+    const double* u = vec12 + 12 * i + 3 * j;
+    if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
+    int d = v >> 5;
+    bool dup = false;
+    for (int q = 0; q < n; ++q) dup |= (out[q] == d);
+    if (!dup) out[n++] = d;
+  }
+  return n;
+}
+
+__global__ void k_bucket_count(int64_t m, const int32_t* idx, const double* w, const double* vec12,
+                               int32_t* cnt) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= m) return;
+  int b[4];
+  int n = stencil_buckets(i, idx, w, vec12, b);
+  for (int q = 0; q < n; ++q) atomicAdd(&cnt[b[q]], 1);
+}
+
+__global__ void k_bucket_fill(int64_t m, const int32_t* idx, const double* w, const double* vec12,
+                              int32_t* cursor, int32_t* list) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= m) return;
+  int b[4];
+  int n = stencil_buckets(i, idx, w, vec12, b);
+  for (int q = 0; q < n; ++q) {
+    int pos = atomicAdd(&cursor[b[q]], 1);
+    list[pos] = int32_t(i);
+  }
+}
+
+// list order inside a bucket depends on atomics; sort each bucket by item id
+// so that every later sum over a bucket has a fixed order
+__global__ void k_bucket_sort(int64_t D, const int32_t* off, int32_t* list) {
+  int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (d >= D) return;
+  int b = off[d], e = off[d + 1];
+  for (int i = b + 1; i < e; ++i) {  // insertion sort: buckets are short
+    int v = list[i];
+    int j = i - 1;
+    while (j >= b && list[j] > v) {
+      list[j + 1] = list[j];
+      --j;
+    }
+    list[j + 1] = v;
+  }
+}
+
+mas_status ensure_cub(Ctx& c, size_t bytes) {
+  if (bytes <= c.cub_bytes) return MAS_OK;
+  if (c.cub_tmp) HIPCHK(hipFree(c.cub_tmp));
+  c.cub_tmp = nullptr;
+  c.cub_bytes = 0;
+  if (hipMalloc(&c.cub_tmp, bytes) != hipSuccess) return MAS_ERR_OOM;
+  c.cub_bytes = bytes;
+  return MAS_OK;
+}
+
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w,
+                               const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
+  const int64_t D = c.lv[0].nsub;
+  HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (D + 1), c.s));
+  if (m > 0) {
+    int bs = 256;
+    int64_t gs = (m + bs - 1) / bs;
+    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt);
+  }
+  size_t bytes = 0;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, cnt, off, int(D + 1), c.s));
+  mas_status st = ensure_cub(c, bytes);
+  if (st != MAS_OK) return st;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(c.cub_tmp, bytes, cnt, off, int(D + 1), c.s));
+  if (m > 0) {
+    // reuse cnt as the fill cursor
+    HIPCHK(hipMemcpyAsync(cnt, off, sizeof(int32_t) * D, hipMemcpyDeviceToDevice, c.s));
+    int bs = 256;
+    int64_t gs = (m + bs - 1) / bs;
+    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt, list);
+    k_bucket_sort<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, off, list);
+  }
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
+                     const int32_t* vals_in, int32_t* vals_out) {
+  if (m == 0) return MAS_OK;
+  size_t bytes = 0;
+  HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, keys_in, keys_out, vals_in, vals_out,
+                                            int(m), 0, 64, c.s));
+  mas_status st = ensure_cub(c, bytes);
+  if (st != MAS_OK) return st;
+  HIPCHK(hipcub::DeviceRadixSort::SortPairs(c.cub_tmp, bytes, keys_in, keys_out, vals_in, vals_out,
+                                            int(m), 0, 64, c.s));
+  return MAS_OK;
+}
+
+}  // namespace mas

@@ -1,0 +1,275 @@
+// Sparse-Input Woodbury update of the level-0 blocks: classification of the
+// current contacts against the base set, localized Top-K per subdomain and
+// the capacitance factors I + U_d^T B_d U_d.
+#include "kernels.hpp"
+#include "elem.hpp"
+
+namespace mas {
+
+// Each current contact: k = kappa b''(d); looked up by key in the base set.
+//   not found            -> dS = k
+//   found, cos < cos_rot -> dS = k          (rotated normal, treated as new)
+//   found, k > k_base    -> dS = k - k_base (stiffening)
+//   otherwise            -> dS = 0          (softening)
+// The column u = sqrt(dS) n enters the untruncated U.
+__global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, const double* d,
+                           const double* grad, double kappa, double dhat, double cos_rot, int64_t mb,
+                           const uint64_t* bkey_sorted, const int32_t* bperm, const double* bk,
+                           const double* bgrad, double* U, int32_t* Uidx, double* dS, uint64_t* ckey,
+                           uint32_t* err) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= m) return;
+  double b, b1, b2;
+  double di = d[i];
+  if (!isfinite(di)) atomicOr(err, ERRB_NONFINITE);
+  barrier3(di, dhat, &b, &b1, &b2);
+  double k = kappa * b2;
+  uint64_t kk = key[i];
+  double n[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) n[q] = grad[12 * i + q];
+  // lower_bound in the sorted base keys
+  int64_t lo = 0, hi = mb;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (bkey_sorted[mid] < kk) lo = mid + 1;
+    else hi = mid;
+  }
+  double s = k;
+  if (lo < mb && bkey_sorted[lo] == kk) {
+    int64_t bi = bperm[lo];
+    double dot = 0, nn = 0, bb = 0;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      double nb = bgrad[12 * bi + q];
+      dot += n[q] * nb;
+      nn += n[q] * n[q];
+      bb += nb * nb;
+    }
+    double cosang = dot / (sqrt(nn) * sqrt(bb));
+    if (cosang < cos_rot) s = k;
+    else if (k > bk[bi]) s = k - bk[bi];
+    else s = 0.0;
+  }
+  if (!(s > 0.0)) s = 0.0;
+  dS[i] = s;
+  ckey[i] = kk;
+  double sq = sqrt(s);
+#pragma unroll
+  for (int q = 0; q < 12; ++q) U[12 * i + q] = sq * n[q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Uidx[4 * i + q] = idx[4 * i + q];
+}
+
+// ranking order: larger dS first, then smaller key
+__device__ inline bool ranks_before(double s1, uint64_t k1, double s2, uint64_t k2) {
+  return s1 > s2 || (s1 == s2 && k1 < k2);
+}
+
+// One wavefront per subdomain: K rounds of a wave-wide arg-best over the
+// candidates ranked after the previous pick.
+__global__ __launch_bounds__(64) void k_topk(int K, const int32_t* off, const int32_t* list,
+                                             const double* dS, const uint64_t* key, const int32_t* Uidx,
+                                             const double* U, int32_t* rank, int32_t* sel,
+                                             SlotCol* slots, int32_t* hist) {
+  const int64_t d = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int b = off[d], e = off[d + 1];
+  double ps = 0.0;
+  uint64_t pkey = 0;
+  bool first = true;
+  int r = 0;
+  for (; r < K; ++r) {
+    double bs = 0.0;
+    unsigned long long bkey = 0;
+    int bc = -1;
+    for (int q = b + lane; q < e; q += 64) {
+      int c = list[q];
+      double s = dS[c];
+      uint64_t kk = key[c];
+      if (!first && !ranks_before(ps, pkey, s, kk)) continue;
+      if (bc < 0 || ranks_before(s, kk, bs, bkey)) {
+        bs = s;
+        bkey = kk;
+        bc = c;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double os = __shfl_xor(bs, o);
+      unsigned long long ok = __shfl_xor(bkey, o);
+      int oc = __shfl_xor(bc, o);
+      if (oc >= 0 && (bc < 0 || ranks_before(os, ok, bs, bkey))) {
+        bs = os;
+        bkey = ok;
+        bc = oc;
+      }
+    }
+    if (bc < 0) break;
+    SlotCol* sc = slots + d * K + r;
+    if (lane == 0) sel[d * K + r] = bc;
+    if (lane < 12) sc->u[lane] = U[12 * int64_t(bc) + lane];
+    if (lane < 4) {
+      int v = Uidx[4 * int64_t(bc) + lane];
+      sc->lv[lane] = (v >= 0 && (v >> 5) == d) ? (v & 31) : -1;
+    }
+    ps = bs;
+    pkey = bkey;
+    first = false;
+  }
+  if (lane == 0) {
+    rank[d] = r;
+    for (int q = r; q < K; ++q) sel[d * K + q] = -1;
+    if (hist) atomicAdd(&hist[r], 1);
+  }
+}
+
+template <int P>
+__device__ inline double block_entry(const void* A, const float* sig, int i, int j) {
+  int e = pks(i, j);
+  if (P == MAS_F64) return reinterpret_cast<const double*>(A)[e];
+  if (P == MAS_F32) return double(reinterpret_cast<const float*>(A)[e]);
+  uint16_t h = reinterpret_cast<const uint16_t*>(A)[e];
+  float v = (P == MAS_BF16) ? bf16_to_f32(h) : f16_to_f32(h);
+  return double(v) * double(sig[i]) * double(sig[j]);
+}
+
+// One workgroup per subdomain with rank r > 0: W = B_d U_d (96 x r, a gather
+// of at most 12 columns of B_d per column of U_d), C = I + U_d^T W, and the
+// float64 Cholesky factor of C.
+template <int P>
+__global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, const float* scale,
+                                                     const int32_t* rank, const SlotCol* slots, void* W,
+                                                     double* Lcap, uint32_t* err) {
+  constexpr size_t E = blk_elems(P);
+  constexpr size_t ES = prec_size(P);
+  __shared__ __align__(16) unsigned char As[E * ES];
+  __shared__ float sig[BD];
+  __shared__ double Ws[MAXK][BD];
+  __shared__ double Cm[MAXK * MAXK];
+  __shared__ SlotCol sl[MAXK];
+  const int64_t d = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int r = rank[d];
+  if (r == 0) return;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(blk) + d * E * ES);
+    uint4* dst = reinterpret_cast<uint4*>(As);
+    for (int q = tid; q < int(E * ES / 16); q += blockDim.x) dst[q] = src[q];
+  }
+  if (P == MAS_BF16 || P == MAS_F16) {
+    if (tid < BD) sig[tid] = scale[d * BD + tid];
+  }
+  for (int q = tid; q < r; q += blockDim.x) sl[q] = slots[d * K + q];
+  __syncthreads();
+  for (int q = tid; q < r * BD; q += blockDim.x) {
+    int j = q / BD, i = q % BD;
+    double acc = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int lv = sl[j].lv[s];
+      if (lv < 0) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc += block_entry<P>(As, sig, i, 3 * lv + a) * sl[j].u[3 * s + a];
+    }
+    Ws[j][i] = acc;
+  }
+  __syncthreads();
+  for (int q = tid; q < r * r; q += blockDim.x) {
+    int j = q / r, k = q % r;
+    double acc = (j == k) ? 1.0 : 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int lv = sl[j].lv[s];
+      if (lv < 0) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc += sl[j].u[3 * s + a] * Ws[k][3 * lv + a];
+    }
+    Cm[j * r + k] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // Cholesky C = L L^T (lower), in place, float64
+    bool bad = false;
+    for (int j = 0; j < r; ++j) {
+      double dj = Cm[j * r + j];
+      for (int k = 0; k < j; ++k) dj -= Cm[j * r + k] * Cm[j * r + k];
+      if (!(dj > 0.0)) {
+        bad = true;
+        dj = 1.0;
+      }
+      double ljj = sqrt(dj);
+      Cm[j * r + j] = ljj;
+      for (int i = j + 1; i < r; ++i) {
+        double v = Cm[i * r + j];
+        for (int k = 0; k < j; ++k) v -= Cm[i * r + k] * Cm[j * r + k];
+        Cm[i * r + j] = v / ljj;
+      }
+    }
+    if (bad) atomicOr(err, ERRB_NOT_SPD);
+    double* L = Lcap + d * (K * (K + 1) / 2);
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j <= i; ++j) L[pk(i, j)] = Cm[i * r + j];
+  }
+  for (int q = tid; q < r * BD; q += blockDim.x) {
+    int j = q / BD, i = q % BD;
+    if (P == MAS_F64) reinterpret_cast<double*>(W)[(d * K + j) * BD + i] = Ws[j][i];
+    else reinterpret_cast<float*>(W)[(d * K + j) * BD + i] = float(Ws[j][i]);
+  }
+}
+
+static mas_status grow_current(Ctx& c, int64_t m) {
+  if (m <= c.mc_cap) return MAS_OK;
+  int64_t cap = m + m / 4 + 1024;
+  hipFree(c.U); hipFree(c.Uidx); hipFree(c.dS); hipFree(c.ckey); hipFree(c.cand_list);
+  bool ok = hipMalloc(&c.U, 96 * cap) == hipSuccess && hipMalloc(&c.Uidx, 16 * cap) == hipSuccess &&
+            hipMalloc(&c.dS, 8 * cap) == hipSuccess && hipMalloc(&c.ckey, 8 * cap) == hipSuccess &&
+            hipMalloc(&c.cand_list, 16 * cap) == hipSuccess;
+  if (!ok) return MAS_ERR_OOM;
+  c.mc_cap = cap;
+  return MAS_OK;
+}
+
+mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) {
+  int64_t m = cur ? cur->m : 0;
+  mas_status st = grow_current(c, m > 0 ? m : 1);
+  if (st != MAS_OK) return st;
+  c.mc = m;
+  if (m > 0) {
+    k_classify<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(
+        m, cur->key, cur->idx, cur->d, cur->grad, c.cfg.kappa, c.cfg.dhat, c.cfg.cos_rot, c.mb,
+        c.bkey_sorted, c.bperm, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
+    HIPCHK(hipGetLastError());
+  }
+  st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
+  if (st != MAS_OK) return st;
+  const int64_t D = c.lv[0].nsub;
+  if (rank_hist) HIPCHK(hipMemsetAsync(rank_hist, 0, sizeof(int32_t) * (c.K + 1), c.s));
+  if (c.K == 0) {
+    HIPCHK(hipMemsetAsync(c.rank, 0, sizeof(int32_t) * D, c.s));
+    return MAS_OK;
+  }
+  k_topk<<<dim3(D), dim3(64), 0, c.s>>>(c.K, c.cand_off, c.cand_list, c.dS, c.ckey, c.Uidx, c.U, c.rank,
+                                        c.sel, c.slots, rank_hist);
+  Level& L0 = c.lv[0];
+  switch (L0.prec) {
+    case MAS_F64:
+      k_capacitance<MAS_F64><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
+                                                             c.Lcap, c.err);
+      break;
+    case MAS_F32:
+      k_capacitance<MAS_F32><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
+                                                             c.Lcap, c.err);
+      break;
+    case MAS_BF16:
+      k_capacitance<MAS_BF16><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
+                                                              c.Lcap, c.err);
+      break;
+    default:
+      k_capacitance<MAS_F16><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
+                                                             c.Lcap, c.err);
+  }
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+}  // namespace mas

@@ -1,0 +1,49 @@
+// Host-side launchers of the library kernels (one definition per .hip file).
+#pragma once
+
+#include "common.hpp"
+
+namespace mas {
+
+// k_util.hip -----------------------------------------------------------
+// Buckets items into per-subdomain lists: item i belongs to the distinct
+// level-0 subdomains (v >> 5) of its stencil vertices for which keep(i, j)
+// holds; mode 0: every vertex with idx >= 0 and weight > 0 (weights w[m]
+// nonzero); the kernel filters with w[i] > 0 and a nonzero 3-vector in vec.
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w,
+                               const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
+mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
+                     const int32_t* vals_in, int32_t* vals_out);
+mas_status ensure_cub(Ctx& c, size_t bytes);
+
+// k_setup.hip ----------------------------------------------------------
+mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E,
+                       const double* nu);
+mas_status launch_inertial(Ctx& c, const double* xt, const double* vt, double* xtil);
+mas_status launch_stencil_distance(Ctx& c, const double* x, int64_t m, const int32_t* idx,
+                                   const double* grad, const double* off, double* d);
+
+// k_build.hip ----------------------------------------------------------
+mas_status launch_elem_hessians(Ctx& c, const double* x_base);
+mas_status launch_base_contacts(Ctx& c, const mas_contacts* b);
+mas_status launch_level0_build(Ctx& c);
+mas_status launch_coarse_build(Ctx& c);
+
+// k_woodbury.hip -------------------------------------------------------
+mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist);
+
+// k_apply.hip ----------------------------------------------------------
+mas_status launch_apply(Ctx& c, const double* g, double* z);
+
+// k_hessvec.hip --------------------------------------------------------
+mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update);
+
+// k_pncg.hip -----------------------------------------------------------
+mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const mas_contacts* ct,
+                              double* E, double* g);
+mas_status launch_subspace(Ctx& c, const double* g, const double* z, const double* zp,
+                           const double* vz, double* p, double* vp, int restart, mas_step_out* out);
+mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
+                            double scale, double* alpha, double* x_out);
+
+}  // namespace mas

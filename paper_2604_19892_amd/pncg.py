@@ -1,0 +1,105 @@
+"""Device-resident MAS-PNCG iteration (Algorithm 1) driven through the C ABI.
+
+Per iteration: contact distances of the affine stencil pool, RebuildMAS or
+the Woodbury update, z = P g, v_z = H_base z, the 2x2 subspace step (which
+also advances H_base p by linearity), per-subdomain safe steps, the trial
+energy and gradient, and the restart decision.  The only host reads per
+iteration are the trial energy (descent check) and the step scalars.
+
+The descent check halves every subdomain's step until the energy does not
+increase (at most ``max_halvings`` times); the paper does not describe its
+line search.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from .binding import DeviceContacts, MasContext, make_config
+
+
+class PNCG:
+    def __init__(self, scene, block_prec="f32", levels=None, K=None, delta=0.3, hess_prec=None,
+                 max_halvings=8, device="cuda"):
+        cfg = make_config(scene, levels=levels, K=K, block_prec=block_prec, hess_prec=hess_prec,
+                          delta=delta)
+        self.ctx = ctx = MasContext(scene, cfg, device=device)
+        self.scene = scene
+        self.max_halvings = max_halvings
+        self.pool = ctx.contacts(scene.pool)
+        # a second view of the pool with its own distance array for trial points
+        self.pool_t = DeviceContacts.__new__(DeviceContacts)
+        self.pool_t.__dict__.update(self.pool.__dict__)
+        self.pool_t.d = torch.zeros_like(self.pool.d)
+        self.x = ctx.to_lib(scene.x)
+        self.xt = ctx.inertial_target(self.x, ctx.to_lib(scene.v))
+        v = ctx.vec
+        self.x_trial, self.g, self.g_trial = v(), v(), v()
+        self.z, self.z_prev, self.vz, self.p, self.vp = v(), v(), v(), v(), v()
+        self.E = torch.zeros(1, dtype=torch.float64, device=device)
+        self.E_trial = torch.zeros(1, dtype=torch.float64, device=device)
+        self.rank_hist = torch.zeros(max(cfg.max_rank, 0) + 1, dtype=torch.int32, device=device)
+        ctx.stencil_distance(self.x, self.pool)
+        ctx.energy_grad(self.x, self.xt, self.pool, self.E, self.g)
+        self.E_host = float(self.E.item())
+        self.restart = True
+        self.k = 0
+        self.n_restarts = 0
+        self.n_halvings = 0
+        self.log = []
+        self.g0norm = None
+
+    def iterate(self):
+        ctx = self.ctx
+        if self.restart:
+            ctx.build(self.x, self.pool)
+            self.n_restarts += 1
+        else:
+            ctx.woodbury_update(self.pool, self.rank_hist)
+        ctx.apply(self.g, self.z)
+        ctx.hess_vec(self.z, with_update=False, y=self.vz)
+        ctx.subspace_step(self.g, self.z, self.z_prev if self.k > 0 else None, self.vz, self.p, self.vp,
+                          self.restart)
+        ctx.safe_step(self.x, self.p, self.pool, 1.0, self.x_trial)
+        scale = 1.0
+        for h in range(self.max_halvings + 1):
+            ctx.stencil_distance(self.x_trial, self.pool_t)
+            ctx.energy_grad(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
+            Et = float(self.E_trial.item())
+            if Et <= self.E_host or h == self.max_halvings:
+                break
+            scale *= 0.5
+            self.n_halvings += 1
+            ctx.safe_step(self.x, self.p, None, scale, self.x_trial)
+        st = ctx.step_out()
+        if self.g0norm is None:
+            self.g0norm = np.sqrt(st["gnorm2"])
+        self.log.append(dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), znorm=float(np.sqrt(st["znorm2"])),
+                             mu=st["mu"], nu=st["nu"], r=st["r"], restart=bool(self.restart),
+                             fallback=bool(st["fallback"]), E=Et, scale=scale))
+        # accept the trial point
+        self.x, self.x_trial = self.x_trial, self.x
+        self.g, self.g_trial = self.g_trial, self.g
+        self.pool.d, self.pool_t.d = self.pool_t.d, self.pool.d
+        self.z, self.z_prev = self.z_prev, self.z
+        self.E_host = Et
+        self.restart = bool(st["restart_next"])
+        self.k += 1
+        return st
+
+    def gnorm(self):
+        return float(torch.linalg.vector_norm(self.g).item())
+
+    def solve(self, rel_tol=1e-6, max_iter=1000):
+        """Iterates until ||grad E|| <= rel_tol ||grad E_0||; returns (iters, seconds)."""
+        g0 = self.gnorm()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it = 0
+        while it < max_iter and self.gnorm() > rel_tol * g0:
+            self.iterate()
+            it += 1
+        torch.cuda.synchronize()
+        return it, time.perf_counter() - t

@@ -1,0 +1,253 @@
+"""GPU parity: every C ABI call against the FP64 oracle on the same inputs.
+
+Cases: the 8x8x8 grid scene (512 vertices, 16 subdomains, two levels,
+scripted update touching every classification branch) and the two stacked
+boxes (64,000 vertices, 2,000 subdomains, three levels, 30% scripted churn).
+Tolerances: relative 1e-10 (float64 storage), 1e-5 (float32 blocks), 2e-2
+(bfloat16 / float16 blocks); integer results (Morton order, Top-K
+selection) are compared exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, mas, pncg, woodbury
+from paper_2604_19892_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+class Case:
+    """Oracle results and a GPU context for one scene and update."""
+
+    def __init__(self, scene, base, curr, levels, K, block_prec="f64"):
+        import torch
+        from paper_2604_19892_amd.binding import MasContext, make_config
+        self.scene, self.base, self.curr = scene, base, curr
+        prob = fem.Problem(scene)
+        hier = mas.Hierarchy(scene.X, levels)
+        self.prob, self.hier = prob, hier
+        self.H = prob.assemble(scene.x, base)
+        self.M = mas.MAS(hier, self.H)
+        self.dS, self.u, self.case = woodbury.classify(prob, base, curr)
+        self.sel = woodbury.topk(hier, curr, self.dS, self.u, K)
+        self.blocks = woodbury.updated_blocks(hier, self.H, curr, self.u, self.sel)
+        self.U = woodbury.global_U(prob, curr, self.u, self.dS)
+        self.ctx = MasContext(scene, make_config(scene, levels=levels, K=K, block_prec=block_prec))
+        self.x = self.ctx.to_lib(scene.x)
+        self.dbase = self.ctx.contacts(base)
+        self.dcurr = self.ctx.contacts(curr)
+        self.ctx.build(self.x, self.dbase)
+        self.ctx.woodbury_update(self.dcurr)
+        code, msg = self.ctx.sync()
+        assert code == 0, msg
+        self.torch = torch
+
+
+def grid_case(block_prec="f64"):
+    sc = synth.grid_scene()
+    base, curr = synth.grid_update_sets(sc)
+    return Case(sc, base, curr, levels=2, K=8, block_prec=block_prec)
+
+
+def boxes_case():
+    sc = synth.two_boxes_scene()
+    rng = np.random.default_rng(5)
+    d = synth.pool_distance(sc.pool, sc.x)
+    base = synth.contact_set(sc.pool['key'], sc.pool['idx'], sc.pool['grad'], d)
+    curr = synth.churn_set(rng, sc, base, 0.3)
+    return Case(sc, base, curr, levels=3, K=8)
+
+
+@pytest.fixture(scope="module", params=["grid", "boxes"])
+def case(request):
+    print("\n[parity case] %s" % request.param, flush=True)
+    c = grid_case() if request.param == "grid" else boxes_case()
+    yield c
+    c.ctx.close()
+
+
+def test_morton_order_matches_oracle(case):
+    np.testing.assert_array_equal(case.ctx.perm, case.hier.perm)
+
+
+def test_level0_blocks(case):
+    D = case.hier.num_subdomains(0)
+    ds = range(D) if D <= 64 else np.random.default_rng(0).choice(D, 64, replace=False)
+    worst = 0.0
+    for d in ds:
+        Bo = case.M.fine[d]
+        n = Bo.shape[0]
+        # build state is still in effect for the blocks (the update does not change them)
+        Bg = case.ctx.get_block(0, d)[:n, :n]
+        worst = max(worst, rel(Bg, Bo))
+    assert worst < 1e-10, worst
+
+
+def test_coarse_blocks(case):
+    for l in range(1, case.hier.L):
+        _, _, invs = case.M.coarse[l - 1]
+        for d, (dofs, Minv) in enumerate(invs):
+            n = Minv.shape[0]
+            Bg = case.ctx.get_block(l, d)[:n, :n]
+            assert rel(Bg, Minv) < 1e-10, (l, d, rel(Bg, Minv))
+
+
+def test_topk_selection_exact(case):
+    rank, sel = case.ctx.get_selection()
+    D = case.hier.num_subdomains(0)
+    for d in range(D):
+        want = case.sel.get(d, [])
+        assert rank[d] == len(want), d
+        assert list(sel[d, :rank[d]]) == list(want), d
+    # every classification branch is exercised
+    assert {woodbury.NEW, woodbury.ROTATED, woodbury.STIFFEN, woodbury.SOFTEN} <= set(case.case.tolist())
+
+
+def test_apply_with_woodbury_update(case):
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(3 * case.scene.N)
+    zo = case.M.apply(g, case.blocks)
+    zg = case.ctx.from_lib(case.ctx.apply(case.ctx.to_lib(g)))
+    assert rel(zg, zo) < 1e-10, rel(zg, zo)
+
+
+def test_apply_symmetric_positive(case):
+    rng = np.random.default_rng(2)
+    a, b = rng.standard_normal((2, 3 * case.scene.N))
+    ctx = case.ctx
+    Pa = ctx.from_lib(ctx.apply(ctx.to_lib(a)))
+    Pb = ctx.from_lib(ctx.apply(ctx.to_lib(b)))
+    assert abs(a @ Pb - b @ Pa) < 1e-11 * abs(a @ Pa)
+    assert a @ Pa > 0 and b @ Pb > 0
+
+
+def test_hess_vec(case):
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(3 * case.scene.N)
+    yo = case.H @ v
+    yo_u = yo + case.U @ (case.U.T @ v)
+    ctx = case.ctx
+    y0 = ctx.from_lib(ctx.hess_vec(ctx.to_lib(v), with_update=False))
+    y1 = ctx.from_lib(ctx.hess_vec(ctx.to_lib(v), with_update=True))
+    assert rel(y0, yo) < 1e-10, rel(y0, yo)
+    assert rel(y1, yo_u) < 1e-10, rel(y1, yo_u)
+
+
+def test_subspace_step(case):
+    rng = np.random.default_rng(4)
+    n = 3 * case.scene.N
+    xt = fem.inertial_target(case.scene.x, case.scene.v, case.scene.h, case.scene.gravity).reshape(-1)
+    g = case.prob.gradient(case.scene.x, xt, case.curr)
+    z = case.M.apply(g, case.blocks)
+    z_prev = z + 0.3 * rng.standard_normal(n) * np.abs(z).max()
+    p = -0.7 * z_prev + 0.1 * rng.standard_normal(n) * np.abs(z).max()
+
+    def Ht(v):
+        return case.H @ v + case.U @ (case.U.T @ v)
+
+    mu, nu, pn, fb, A11, A12, A22 = pncg.subspace_step(g, z, p, Ht, restart=False)
+    r = pncg.restart_ratio(g, z_prev, z)
+    ctx = case.ctx
+    dp = ctx.to_lib(p)
+    dvp = ctx.to_lib(case.H @ p)
+    out = ctx.subspace_step(ctx.to_lib(g), ctx.to_lib(z), ctx.to_lib(z_prev), ctx.to_lib(case.H @ z), dp, dvp,
+                            restart=False)
+    s = ctx.step_out()
+    assert s['fallback'] == int(fb)
+    assert s['mu'] == pytest.approx(mu, rel=1e-10)
+    assert s['nu'] == pytest.approx(nu, rel=1e-10, abs=1e-12 * abs(mu))
+    assert s['A11'] == pytest.approx(A11, rel=1e-10)
+    assert s['A12'] == pytest.approx(A12, rel=1e-10, abs=1e-12 * A11)
+    assert s['A22'] == pytest.approx(A22, rel=1e-10)
+    assert s['r'] == pytest.approx(r, rel=1e-10)
+    assert s['restart_next'] == int(r > 0.3)
+    assert rel(ctx.from_lib(dp), pn) < 1e-10
+    assert rel(ctx.from_lib(dvp), case.H @ pn) < 1e-10
+    # restart form: mu = g.z / z^T H~ z, nu = 0
+    mu0, nu0, pn0, fb0, *_ = pncg.subspace_step(g, z, p, Ht, restart=True)
+    dp = ctx.to_lib(p)
+    dvp = ctx.to_lib(case.H @ p)
+    ctx.subspace_step(ctx.to_lib(g), ctx.to_lib(z), None, ctx.to_lib(case.H @ z), dp, dvp, restart=True)
+    s = ctx.step_out()
+    assert s['mu'] == pytest.approx(mu0, rel=1e-10) and s['nu'] == 0.0 and s['restart_used'] == 1
+    assert rel(ctx.from_lib(dp), pn0) < 1e-10
+
+
+def test_energy_gradient(case):
+    sc = case.scene
+    xt = fem.inertial_target(sc.x, sc.v, sc.h, sc.gravity).reshape(-1)
+    Eo = case.prob.energy(sc.x, xt, case.curr)
+    go = case.prob.gradient(sc.x, xt, case.curr)
+    ctx = case.ctx
+    dxt = ctx.inertial_target(ctx.to_lib(sc.x), ctx.to_lib(sc.v))
+    assert rel(ctx.from_lib(dxt), xt) < 1e-15
+    E = case.torch.zeros(1, dtype=case.torch.float64, device="cuda")
+    g = ctx.vec()
+    ctx.energy_grad(case.x, dxt, case.dcurr, E, g)
+    assert float(E.item()) == pytest.approx(Eo, rel=1e-10)
+    assert rel(ctx.from_lib(g), go) < 1e-10
+
+
+def test_stencil_distance_and_safe_step(case):
+    sc = case.scene
+    ctx = case.ctx
+    pool = ctx.contacts(sc.pool)
+    ctx.stencil_distance(case.x, pool)
+    do = synth.pool_distance(sc.pool, sc.x)
+    # d = n . x - off cancels: compare against the size of the summed terms
+    scale = np.abs(sc.pool['grad']).sum(1) * np.abs(sc.x).max() + np.abs(sc.pool['off'])
+    assert np.all(np.abs(pool.d.cpu().numpy() - do) <= 1e-15 * scale)
+    # the step rule itself is compared on identical distances
+    pool.d.copy_(case.torch.as_tensor(do, device="cuda"))
+    rng = np.random.default_rng(6)
+    p = 0.05 * rng.standard_normal(3 * sc.N) * (sc.X.max() - sc.X.min()) / 8
+    ao = pncg.safe_alpha(case.hier, sc.pool['idx'], sc.pool['grad'], do, p)
+    alpha = case.torch.zeros(case.hier.num_subdomains(0), dtype=case.torch.float64, device="cuda")
+    xo = ctx.vec()
+    ctx.safe_step(case.x, ctx.to_lib(p), pool, 1.0, xo, alpha)
+    assert np.any(ao < 1)
+    np.testing.assert_allclose(alpha.cpu().numpy(), ao, rtol=1e-12)
+    xn = pncg.step_positions(case.hier, sc.x.reshape(-1), p, ao)
+    assert rel(ctx.from_lib(xo), xn) < 1e-14
+    # halved step reuses the step sizes
+    ctx.safe_step(case.x, ctx.to_lib(p), None, 0.5, xo)
+    assert rel(ctx.from_lib(xo), pncg.step_positions(case.hier, sc.x.reshape(-1), p, 0.5 * ao)) < 1e-14
+
+
+def test_apply_after_rebuild_without_update(case):
+    ctx = case.ctx
+    ctx.build(case.x, case.dbase)
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal(3 * case.scene.N)
+    zg = ctx.from_lib(ctx.apply(ctx.to_lib(g)))
+    assert rel(zg, case.M.apply(g)) < 1e-10
+    rank, _ = ctx.get_selection()
+    assert np.all(rank == 0)
+    ctx.woodbury_update(case.dcurr)      # restore the updated state
+    code, msg = ctx.sync()
+    assert code == 0, msg
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16", 2e-2), ("f16", 2e-2)])
+def test_low_precision_blocks(prec, tol):
+    print("\n[parity case] grid %s" % prec, flush=True)
+    c = grid_case(prec)
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal(3 * c.scene.N)
+    zo = c.M.apply(g, c.blocks)
+    zg = c.ctx.from_lib(c.ctx.apply(c.ctx.to_lib(g)))
+    err = rel(zg, zo)
+    print("apply rel err %s: %.3e" % (prec, err))
+    assert err < tol
+    # Hessian snapshot in float32 for the mixed forms
+    v = rng.standard_normal(3 * c.scene.N)
+    yo = c.H @ v + c.U @ (c.U.T @ v)
+    y = c.ctx.from_lib(c.ctx.hess_vec(c.ctx.to_lib(v), with_update=True))
+    assert rel(y, yo) < 1e-5
+    c.ctx.close()
