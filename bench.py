@@ -1,0 +1,208 @@
+#!/usr/bin/env python
+"""MAS-PNCG iterations per second on one MI355X.
+
+Workload: eight spiky soft balls (the Puffer Balls shape: 1.14M vertices,
+2.71M tets, 1.25M affine contact stencils of which ~1M start active, four
+MAS levels, Top-K 8), float32 level-0 blocks and element Hessians, float64
+vectors, barrier sums, capacitance factors and 2x2 solve.  One step is one
+full PNCG iteration of Algorithm 1 (contact distances, RebuildMAS or the
+Woodbury update, z = P g, H_base z, the subspace step, safe steps, trial
+energy/gradient with the descent check, restart test); restarts happen
+when the restart test asks for them, inside the timed region.
+
+Prints one JSON line.  The roofline object covers the level-0 kernel of
+mas_apply, timed with HIP events recorded by the library on its own stream
+during the timed steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PNCG iters/s + mas_apply HBM GB/s at 1.1M verts; mixed vs FP64 at same ‖∇E‖ tol"
+HBM_PEAK_GBS = 8000.0
+PK = 96 * 97 // 2
+
+
+def apply_l0_bytes(ctx, prec, hists, K):
+    """Algorithmic bytes of one level-0 apply launch per rank histogram."""
+    N = ctx.N
+    D0 = int(ctx.nsub[0])
+    sB = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[prec]
+    sW = 8 if prec == "f64" else 4
+    base = D0 * PK * sB + (D0 * 96 * 4 if sB == 2 else 0)      # blocks (+ row scales)
+    base += 2 * 8 * 3 * N                                        # g read, z write
+    nodes = N
+    for _ in range(1, ctx.levels):                               # coarse corrections read
+        nodes = -(-nodes // 32)
+        base += 8 * 3 * nodes
+    base += 4 * D0                                               # ranks
+    out = []
+    for h in hists:
+        wb = 0
+        for r, cnt in enumerate(h):
+            if r:
+                wb += cnt * (96 * r * sW + r * 112 + 8 * r * (r + 1) // 2)
+        out.append(base + wb)
+    return out
+
+
+def hv_tets_bytes(ctx, hess_prec):
+    sH = 8 if hess_prec == "f64" else 4
+    return ctx.scene.T * (54 * sH + 16) + 2 * 8 * 3 * ctx.N
+
+
+def traffic_record(kernel_src):
+    """Measured HBM bytes per launch from rocprofv3 counters, if they were
+    taken on the current source of the kernel."""
+    path = os.path.join(ROOT, "profiles", "apply_l0_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec
+
+
+def cpu_baseline(full_N, iters=3):
+    """The FP64 oracle (Algorithm 1 with full-rebuild semantics) on a
+    bounded sample of the same workload family, scaled linearly in vertex
+    count to the full scene."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle.solver import OraclePNCG
+    from paper_2604_19892_amd import synth
+    sc = synth.puffer_scene(core=(12, 12, 13), n_spikes=130, spike_len=7, pool_size=46000)
+    s = OraclePNCG(sc)
+    t = time.perf_counter()
+    for _ in range(iters):
+        s.iterate()
+    dt = time.perf_counter() - t
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": iters / dt * sc.N / full_N, "unit": "iters/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d oracle iterations (first one a restart) on an 8-ball puffer scene with %d vertices, "
+                      "%d tets, %d stencils; %.1f s; iters/s scaled by %d/%d vertices"
+                      % (iters, sc.N, sc.T, sc.pool['key'].size, dt, sc.N, full_N)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--small", action="store_true", help="two-boxes scene instead (quick check)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2604_19892_amd import synth
+    from paper_2604_19892_amd.pncg import PNCG
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    if args.small:
+        sc = synth.two_boxes_scene(active_frac=0.8)
+        workload = "two_boxes"
+    else:
+        sc = synth.puffer_scene()
+        workload = "puffer_balls"
+    print("[bench] scene %s: %d verts %d tets %d stencils (%.1fs)"
+          % (workload, sc.N, sc.T, sc.pool['key'].size, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    hess_prec = "f64" if args.prec == "f64" else "f32"
+    solver = PNCG(sc, block_prec=args.prec, hess_prec=hess_prec)
+    ctx = solver.ctx
+    print("[bench] context ready (%.1fs)" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        solver.iterate()
+    torch.cuda.synchronize()
+    print("[bench] warmup done (%d iters)" % args.warmup, file=sys.stderr, flush=True)
+
+    ctx.profile(True)
+    hists = []
+    r0 = solver.n_restarts
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        restart = solver.restart
+        solver.iterate()
+        hists.append([0] if restart else solver.rank_hist.cpu().numpy().tolist())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    restarts = solver.n_restarts - r0
+    timers = {k: ctx.profile_read(k) for k in ("apply_l0", "apply", "hv_tets", "hess_vec", "update",
+                                               "capacitance", "build", "energy", "subspace")}
+    ctx.profile(False)
+    print("[bench] timed %d iters in %.3fs" % (args.steps, dt), file=sys.stderr, flush=True)
+
+    ms_l0, n_l0 = timers["apply_l0"]
+    bytes_l0 = apply_l0_bytes(ctx, args.prec, hists, solver.ctx.cfg.max_rank)
+    achieved = sum(bytes_l0) / (ms_l0 * 1e-3) / 1e9 if n_l0 else 0.0
+    ms_hv, n_hv = timers["hv_tets"]
+    hv_b = hv_tets_bytes(ctx, hess_prec)
+    hv_achieved = n_hv * hv_b / (ms_hv * 1e-3) / 1e9 if n_hv else 0.0
+    tr = traffic_record(os.path.join(ROOT, "paper_2604_19892_amd", "csrc", "k_apply.hip"))
+    traffic = None
+    if tr and tr.get("prec") == args.prec and tr.get("workload") == workload:
+        traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": workload,
+            "vertices": int(sc.N), "tets": int(sc.T), "stencils": int(sc.pool['key'].size),
+            "levels": int(ctx.levels), "K": int(ctx.cfg.max_rank),
+            "block_storage": args.prec, "hessian_storage": hess_prec,
+            "restarts_in_timed_steps": int(restarts),
+        },
+        "mas_apply_GBps": achieved,
+        "roofline": {
+            "kernel": "k_apply_l0 (level-0 blocks + Woodbury correction of mas_apply)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": float(np.mean(bytes_l0)) if bytes_l0 else 0.0,
+            "launches": int(n_l0), "avg_us": 1e3 * ms_l0 / max(n_l0, 1),
+        },
+        "roofline_hess_vec": {
+            "kernel": "k_hv_tets", "bound": "hbm", "achieved": hv_achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": hv_achieved / HBM_PEAK_GBS, "bytes_per_launch": hv_b,
+            "launches": int(n_hv), "avg_us": 1e3 * ms_hv / max(n_hv, 1),
+        },
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in timers.items()},
+        "gnorm_rel": solver.gnorm() / solver.g0norm if solver.g0norm else None,
+    }
+    code, msg = ctx.sync()
+    if code != 0:
+        print("[bench] library error: %s" % msg, file=sys.stderr)
+        sys.exit(1)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc.N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

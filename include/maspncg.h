@@ -76,7 +76,7 @@ typedef enum {
  * element Hessian snapshot (hess_prec: MAS_F64 or MAS_F32).  Blocks are
  * always assembled and inverted in float64 (supplement Section 1.1); BF16
  * and FP16 blocks are stored with a per-row symmetric scaling s_i =
- * B_ii^-1/2 and applied with float32 accumulation. */
+ * B_ii^-1/2.  Products with stored blocks accumulate in float64. */
 typedef enum { MAS_F64 = 0, MAS_F32 = 1, MAS_BF16 = 2, MAS_F16 = 3 } mas_prec;
 
 typedef struct {
@@ -215,6 +215,29 @@ mas_status mas_get_block(void* ctx, int32_t level, int64_t d, double* out_host);
  * and the selected current-contact indices (host int32 D_0 x max_rank, -1 when
  * unused), in ranking order. */
 mas_status mas_get_selection(void* ctx, int32_t* rank_host, int32_t* sel_host);
+
+/* Kernel timers.  While enabled, the library records a HIP event pair on its
+ * stream around the named kernel (or call) every time it runs, so that
+ * durations are measured on the stream the kernels are launched on. */
+typedef enum {
+  MAS_T_APPLY_L0 = 0,     /* level-0 block apply kernel of mas_apply */
+  MAS_T_APPLY = 1,        /* the whole mas_apply call */
+  MAS_T_HV_TETS = 2,      /* element kernel of hess_vec */
+  MAS_T_HESSVEC = 3,      /* the whole hess_vec call */
+  MAS_T_UPDATE = 4,       /* the whole mas_woodbury_update call */
+  MAS_T_CAPACITANCE = 5,  /* capacitance kernel of mas_woodbury_update */
+  MAS_T_BUILD = 6,        /* the whole mas_build call */
+  MAS_T_ENERGY = 7,       /* the whole mas_energy_grad call */
+  MAS_T_SUBSPACE = 8,     /* the whole pncg_subspace_step call */
+  MAS_T_COUNT = 9
+} mas_timer;
+
+/* Enables (1) or disables (0) the kernel timers; enabling clears them. */
+mas_status mas_profile_enable(void* ctx, int32_t enable);
+
+/* Synchronises the stream and returns the summed duration (ms) and number of
+ * timed launches of one timer since the last read, then clears it. */
+mas_status mas_profile_read(void* ctx, int32_t timer, double* total_ms, int64_t* count);
 
 /* Returns a static string naming a status code. */
 const char* mas_status_string(mas_status s);

@@ -71,6 +71,9 @@ class MasStepOut(ctypes.Structure):
 
 STEP_FIELDS = [f for f, _ in MasStepOut._fields_]
 
+TIMERS = {"apply_l0": 0, "apply": 1, "hv_tets": 2, "hess_vec": 3, "update": 4, "capacitance": 5,
+          "build": 6, "energy": 7, "subspace": 8}
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
@@ -94,6 +97,8 @@ SIGNATURES = {
     "mas_get_block": (_I32, [_P, _I32, _I64, _P]),
     "mas_get_selection": (_I32, [_P, _P, _P]),
     "mas_status_string": (ctypes.c_char_p, [_I32]),
+    "mas_profile_enable": (_I32, [_P, _I32]),
+    "mas_profile_read": (_I32, [_P, _I32, _P, _P]),
 }
 
 _lib = None

@@ -204,6 +204,16 @@ class MasContext:
         check("mas_get_block", _abi.lib().mas_get_block(self.h, int(level), int(d), out.ctypes.data))
         return out
 
+    def profile(self, enable=True):
+        check("mas_profile_enable", _abi.lib().mas_profile_enable(self.h, int(enable)))
+
+    def profile_read(self, timer):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check("mas_profile_read", _abi.lib().mas_profile_read(self.h, _abi.TIMERS[timer], ctypes.byref(ms),
+                                                             ctypes.byref(n)))
+        return ms.value, n.value
+
     def get_selection(self):
         D0 = int(self.nsub[0])
         K = max(int(self.cfg.max_rank), 0)

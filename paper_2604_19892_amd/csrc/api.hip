@@ -7,6 +7,45 @@
 
 #include "kernels.hpp"
 
+namespace mas {
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> done[MAS_T_COUNT];
+  hipEvent_t open[MAS_T_COUNT] = {};
+};
+
+static hipEvent_t prof_take(Prof& p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(Ctx& c, int t) {
+  if (!c.prof || !c.prof->on || t < 0 || t >= MAS_T_COUNT) return;
+  hipEvent_t e = prof_take(*c.prof);
+  if (!e) return;
+  hipEventRecord(e, c.s);
+  c.prof->open[t] = e;
+}
+
+void prof_end(Ctx& c, int t) {
+  if (!c.prof || !c.prof->on || t < 0 || t >= MAS_T_COUNT || !c.prof->open[t]) return;
+  hipEvent_t e = prof_take(*c.prof);
+  if (!e) return;
+  hipEventRecord(e, c.s);
+  c.prof->done[t].push_back({c.prof->open[t], e});
+  c.prof->open[t] = nullptr;
+}
+
+}  // namespace mas
+
 using namespace mas;
 
 namespace {
@@ -115,7 +154,7 @@ mas_status mas_destroy(void* p) {
                   c->bkey_sorted, c->biota, c->bperm, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
-                  c->alpha, c->err, c->cub_tmp};
+                  c->alpha, c->err, c->diag, c->acc_ptrs, c->cub_tmp};
   for (void* q : ptrs)
     if (q) hipFree(q);
   for (int l = 0; l < MAXL; ++l) {
@@ -123,6 +162,15 @@ mas_status mas_destroy(void* p) {
     void* lp[] = {L.blk, L.scale, L.acc, L.r, L.c};
     for (void* q : lp)
       if (q) hipFree(q);
+  }
+  if (c->prof) {
+    for (int t = 0; t < MAS_T_COUNT; ++t)
+      for (auto& pr : c->prof->done[t]) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+      }
+    for (hipEvent_t e : c->prof->pool) hipEventDestroy(e);
+    delete c->prof;
   }
   delete c;
   return MAS_OK;
@@ -242,8 +290,8 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     Level& L = c->lv[l];
     TRY(dalloc_bytes(&L.blk, L.nsub * blk_elems(L.prec) * prec_size(L.prec)));
     if (L.prec == MAS_BF16 || L.prec == MAS_F16) TRY(dalloc(&L.scale, L.nsub * BD));
+    TRY(dalloc(&L.acc, L.nsub * PK));
     if (l > 0) {
-      TRY(dalloc(&L.acc, L.nsub * PK));
       TRY(dalloc(&L.r, 3 * L.nodes));
       TRY(dalloc(&L.c, 3 * L.nodes));
     }
@@ -262,7 +310,15 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->scal, 64));
   TRY(dalloc(&c->alpha, D0));
   TRY(dalloc(&c->err, 1));
+  TRY(dalloc(&c->diag, 1));
+  {
+    double* ptrs[MAXL] = {};
+    for (int l = 0; l < c->L; ++l) ptrs[l] = c->lv[l].acc;
+    TRY(dalloc(&c->acc_ptrs, MAXL));
+    HIPCHK(hipMemcpy(c->acc_ptrs, ptrs, sizeof(ptrs), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->s));
+  HIPCHK(hipMemsetAsync(c->diag, 0, sizeof(DiagRec), c->s));
   HIPCHK(hipMemsetAsync(c->rank, 0, sizeof(int32_t) * D0, c->s));
   HIPCHK(hipMemsetAsync(c->alpha, 0, sizeof(double) * D0, c->s));
 
@@ -302,6 +358,7 @@ mas_status mas_build(void* p, const double* x_base, const mas_contacts* base) {
   mas_status st = valid_contacts(base);
   if (st != MAS_OK) return st;
   Ctx& c = *as_ctx(p);
+  ProfScope ps(c, MAS_T_BUILD);
   if ((st = launch_elem_hessians(c, x_base)) != MAS_OK) return st;
   if ((st = launch_base_contacts(c, base)) != MAS_OK) return st;
   if ((st = launch_level0_build(c)) != MAS_OK) return st;
@@ -378,19 +435,27 @@ mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
   Ctx& c = *as_ctx(p);
   hipError_t e = hipStreamSynchronize(c.s);
   mas_status st = MAS_OK;
+  DiagRec dg{};
   if (e != hipSuccess) {
     st = MAS_ERR_HIP;
   } else {
     uint32_t bits = 0;
     if (hipMemcpy(&bits, c.err, sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) st = MAS_ERR_HIP;
+    if (hipMemcpy(&dg, c.diag, sizeof(dg), hipMemcpyDeviceToHost) != hipSuccess) st = MAS_ERR_HIP;
     hipMemset(c.err, 0, sizeof(uint32_t));
+    hipMemset(c.diag, 0, sizeof(DiagRec));
     if (bits & ERRB_NOT_SPD) st = MAS_ERR_NOT_SPD;
     else if (bits & ERRB_NONFINITE) st = MAS_ERR_NONFINITE;
     else if (bits & ERRB_RANK) st = MAS_ERR_RANK;
   }
   if (msg && msg_len > 0) {
+    static const char* src[] = {"?", "level-0 block", "coarse block", "capacitance"};
     if (st == MAS_ERR_HIP)
       std::snprintf(msg, msg_len, "%s: %s", mas_status_string(st), hipGetErrorString(e));
+    else if (dg.flag)
+      std::snprintf(msg, msg_len, "%s: %s (level %d, subdomain %lld, step %d, pivot %.6g)",
+                    mas_status_string(st), src[dg.source >= 1 && dg.source <= 3 ? dg.source : 0], dg.level,
+                    (long long)dg.index, dg.step, dg.value);
     else
       std::snprintf(msg, msg_len, "%s", mas_status_string(st));
   }
@@ -435,6 +500,46 @@ mas_status mas_get_block(void* p, int32_t level, int64_t d, double* out) {
       out[i * BD + j] = v;
       out[j * BD + i] = v;
     }
+  return MAS_OK;
+}
+
+mas_status mas_profile_enable(void* p, int32_t enable) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.prof) c.prof = new (std::nothrow) Prof();
+  if (!c.prof) return MAS_ERR_OOM;
+  HIPCHK(hipStreamSynchronize(c.s));
+  for (int t = 0; t < MAS_T_COUNT; ++t) {
+    for (auto& pr : c.prof->done[t]) {
+      c.prof->pool.push_back(pr.first);
+      c.prof->pool.push_back(pr.second);
+    }
+    c.prof->done[t].clear();
+    c.prof->open[t] = nullptr;
+  }
+  c.prof->on = enable != 0;
+  return MAS_OK;
+}
+
+mas_status mas_profile_read(void* p, int32_t timer, double* total_ms, int64_t* count) {
+  if (!p || timer < 0 || timer >= MAS_T_COUNT) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  double tot = 0;
+  int64_t n = 0;
+  if (c.prof) {
+    HIPCHK(hipStreamSynchronize(c.s));
+    for (auto& pr : c.prof->done[timer]) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      tot += ms;
+      ++n;
+      c.prof->pool.push_back(pr.first);
+      c.prof->pool.push_back(pr.second);
+    }
+    c.prof->done[timer].clear();
+  }
+  if (total_ms) *total_ms = tot;
+  if (count) *count = n;
   return MAS_OK;
 }
 

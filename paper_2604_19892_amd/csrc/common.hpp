@@ -74,6 +74,29 @@ __device__ inline void atomic_min_pos(double* a, double v) {
   atomicMin(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
 }
 
+// first device-side failure, written once (source: 1 level-0 build,
+// 2 coarse build, 3 capacitance)
+struct DiagRec {
+  uint32_t flag;
+  int32_t source;
+  int32_t level;
+  int32_t step;
+  int64_t index;
+  double value;
+};
+
+__device__ inline void diag_report(DiagRec* dg, int source, int level, int64_t index, int step,
+                                   double value) {
+  if (!dg) return;
+  if (atomicCAS(&dg->flag, 0u, 1u) == 0u) {
+    dg->source = source;
+    dg->level = level;
+    dg->index = index;
+    dg->step = step;
+    dg->value = value;
+  }
+}
+
 struct SlotCol {        // one column of U_d restricted to its subdomain
   int32_t lv[4];        // local vertex (0..31) of each stencil vertex, -1 if outside
   double u[12];
@@ -85,13 +108,16 @@ struct Level {
   int prec = MAS_F64;
   void* blk = nullptr;  // nsub * blk_elems(prec) entries
   float* scale = nullptr;  // nsub * 96 row scales (16-bit storage)
-  double* acc = nullptr;   // packed FP64 accumulation (levels >= 1)
+  double* acc = nullptr;   // packed FP64 assembly of every block of the level
   double* r = nullptr;     // restricted residual 3*nodes (levels >= 1)
   double* c = nullptr;     // coarse correction 3*nodes (levels >= 1)
 };
 
+struct Prof;  // host-side kernel timers (api.hip)
+
 struct Ctx {
   hipStream_t s = nullptr;
+  Prof* prof = nullptr;
   mas_config cfg{};
   int64_t N = 0, T = 0, Tpad = 0;
   int L = 1, K = 8;
@@ -145,8 +171,20 @@ struct Ctx {
   double* scal = nullptr;          // small device scalars (mu, nu, ...)
   double* alpha = nullptr;         // D0
   uint32_t* err = nullptr;         // sticky error bits
+  DiagRec* diag = nullptr;         // first failure record
+  double** acc_ptrs = nullptr;     // device copy of lv[l].acc
   void* cub_tmp = nullptr;
   size_t cub_bytes = 0;
+};
+
+// Records a HIP event pair around its scope when timers are enabled.
+void prof_begin(Ctx& c, int timer);
+void prof_end(Ctx& c, int timer);
+struct ProfScope {
+  Ctx& c;
+  int t;
+  ProfScope(Ctx& c_, int t_) : c(c_), t(t_) { prof_begin(c, t); }
+  ~ProfScope() { prof_end(c, t); }
 };
 
 }  // namespace mas

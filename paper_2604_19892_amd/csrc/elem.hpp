@@ -128,7 +128,7 @@ __device__ inline void psd_project9(double A[45]) {
   for (int i = 0; i < 9; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j) fro += (i == j ? 1.0 : 2.0) * A[p9(i, j)] * A[p9(i, j)];
-  const double tol = 1e-32 * fro;
+  const double tol = 1e-30 * fro;
   for (int sweep = 0; sweep < 20; ++sweep) {
     double off = 0;
 #pragma unroll

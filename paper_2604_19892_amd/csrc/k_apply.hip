@@ -160,16 +160,15 @@ __global__ __launch_bounds__(256) void k_apply_l0(FineArgs fa) {
     }
     __syncthreads();
     if (tid == 0) {
-      // (L L^T) lambda = r
+      // (L L^T) lambda = r: forward substitution in place in rr, then backward
       const double* Lm = fa.Lcap + d * (fa.K * (fa.K + 1) / 2);
-      double y[MAXK];
       for (int i = 0; i < r; ++i) {
         double v = rr[i];
-        for (int k = 0; k < i; ++k) v -= Lm[pk(i, k)] * y[k];
-        y[i] = v / Lm[pk(i, i)];
+        for (int k = 0; k < i; ++k) v -= Lm[pk(i, k)] * rr[k];
+        rr[i] = v / Lm[pk(i, i)];
       }
       for (int i = r - 1; i >= 0; --i) {
-        double v = y[i];
+        double v = rr[i];
         for (int k = i + 1; k < r; ++k) v -= Lm[pk(k, i)] * lam[k];
         lam[i] = v / Lm[pk(i, i)];
       }
@@ -199,6 +198,7 @@ __global__ __launch_bounds__(256) void k_apply_l0(FineArgs fa) {
 }
 
 mas_status launch_apply(Ctx& c, const double* g, double* z) {
+  ProfScope ps(c, MAS_T_APPLY);
   if (c.L > 1) {
     RestrictArgs ra{};
     ra.L = c.L;
@@ -234,12 +234,14 @@ mas_status launch_apply(Ctx& c, const double* g, double* z) {
   fa.L = c.L;
   for (int l = 1; l < c.L; ++l) fa.c[l] = c.lv[l].c;
   dim3 gr(c.lv[0].nsub), bl(256);
+  prof_begin(c, MAS_T_APPLY_L0);
   switch (c.lv[0].prec) {
     case MAS_F64: k_apply_l0<MAS_F64><<<gr, bl, 0, c.s>>>(fa); break;
     case MAS_F32: k_apply_l0<MAS_F32><<<gr, bl, 0, c.s>>>(fa); break;
     case MAS_BF16: k_apply_l0<MAS_BF16><<<gr, bl, 0, c.s>>>(fa); break;
     default: k_apply_l0<MAS_F16><<<gr, bl, 0, c.s>>>(fa);
   }
+  prof_end(c, MAS_T_APPLY_L0);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

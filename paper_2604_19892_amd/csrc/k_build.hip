@@ -131,7 +131,8 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
 // -A^-1.  The matrix lives in registers during the sweeps: thread t < 136
 // owns the 6x6 tile (ti, tj), ti >= tj, of a 16x16 tile grid; per pivot only
 // the pivot column passes through LDS (double-buffered, one barrier a step).
-__device__ void spd_invert_lds(double* A, double (*colbuf)[BD], uint32_t* err) {
+__device__ __forceinline__ void spd_invert_lds(double* A, double (*colbuf)[BD], uint32_t* err, DiagRec* dg,
+                                               int source, int level, int64_t index) {
   const int tid = threadIdx.x;
   const bool act = tid < 136;
   int ti = 0, tj = 0;
@@ -148,25 +149,42 @@ __device__ void spd_invert_lds(double* A, double (*colbuf)[BD], uint32_t* err) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) R[r][q] = A[pks(6 * ti + r, 6 * tj + q)];
   }
-  bool bad = false;
+  int bad_k = -1;
+  double bad_v = 0.0;
   for (int k = 0; k < BD; ++k) {
     double* col = colbuf[k & 1];
+    // kb, kr are the same in every lane: the switches below are scalar branches
     const int kb = k / 6, kr = k % 6;
     if (act) {
-      if (tj == kb) {
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          if (6 * ti + r >= k) col[6 * ti + r] = R[r][kr];
+      if (tj == kb) {  // column kr of the tile holds A(i, k), i >= 6 kb
+        switch (kr) {
+#define MAS_COLK(KR)                                                       \
+  case KR:                                                                 \
+    _Pragma("unroll") for (int r = 0; r < 6; ++r) if (6 * ti + r >= k)     \
+        col[6 * ti + r] = R[r][KR];                                        \
+    break;
+          MAS_COLK(0) MAS_COLK(1) MAS_COLK(2) MAS_COLK(3) MAS_COLK(4) MAS_COLK(5)
+#undef MAS_COLK
+        }
       }
-      if (ti == kb) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-          if (6 * tj + q < k) col[6 * tj + q] = R[kr][q];
+      if (ti == kb) {  // row kr of the tile holds A(k, j), j < k
+        switch (kr) {
+#define MAS_ROWK(KR)                                                       \
+  case KR:                                                                 \
+    _Pragma("unroll") for (int q = 0; q < 6; ++q) if (6 * tj + q < k)      \
+        col[6 * tj + q] = R[KR][q];                                        \
+    break;
+          MAS_ROWK(0) MAS_ROWK(1) MAS_ROWK(2) MAS_ROWK(3) MAS_ROWK(4) MAS_ROWK(5)
+#undef MAS_ROWK
+        }
       }
     }
     __syncthreads();
     const double dk = col[k];
-    bad |= !(dk > 0.0) || !isfinite(dk);
+    if (bad_k < 0 && (!(dk > 0.0) || !isfinite(dk))) {
+      bad_k = k;
+      bad_v = dk;
+    }
     const double inv = 1.0 / dk;
     if (act) {
       double ci[6], cj[6];
@@ -174,26 +192,38 @@ __device__ void spd_invert_lds(double* A, double (*colbuf)[BD], uint32_t* err) {
       for (int r = 0; r < 6; ++r) ci[r] = col[6 * ti + r];
 #pragma unroll
       for (int q = 0; q < 6; ++q) cj[q] = col[6 * tj + q] * inv;
-      if (ti != kb && tj != kb) {
+      // sweep: a_ij -= a_ik a_kj / a_kk everywhere, then row and column k
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
+      for (int r = 0; r < 6; ++r)
 #pragma unroll
-          for (int q = 0; q < 6; ++q) R[r][q] -= ci[r] * cj[q];
-      } else {
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int q = 0; q < 6; ++q) {
-            const int i = 6 * ti + r, j = 6 * tj + q;
-            if (i == k && j == k) R[r][q] = -inv;
-            else if (i == k) R[r][q] = cj[q];
-            else if (j == k) R[r][q] = ci[r] * inv;
-            else R[r][q] -= ci[r] * cj[q];
-          }
+        for (int q = 0; q < 6; ++q) R[r][q] -= ci[r] * cj[q];
+      if (tj == kb) {  // a_ik <- a_ik / a_kk
+        switch (kr) {
+#define MAS_FIXC(KR)                                                       \
+  case KR:                                                                 \
+    _Pragma("unroll") for (int r = 0; r < 6; ++r) R[r][KR] = ci[r] * inv;  \
+    break;
+          MAS_FIXC(0) MAS_FIXC(1) MAS_FIXC(2) MAS_FIXC(3) MAS_FIXC(4) MAS_FIXC(5)
+#undef MAS_FIXC
+        }
+      }
+      if (ti == kb) {  // a_kj <- a_kj / a_kk, a_kk <- -1 / a_kk
+        switch (kr) {
+#define MAS_FIXR(KR)                                                       \
+  case KR:                                                                 \
+    _Pragma("unroll") for (int q = 0; q < 6; ++q) R[KR][q] = cj[q];        \
+    if (tj == kb) R[KR][KR] = -inv;                                        \
+    break;
+          MAS_FIXR(0) MAS_FIXR(1) MAS_FIXR(2) MAS_FIXR(3) MAS_FIXR(4) MAS_FIXR(5)
+#undef MAS_FIXR
+        }
       }
     }
   }
-  if (bad && tid == 0) atomicOr(err, ERRB_NOT_SPD);
+  if (bad_k >= 0 && tid == 0) {
+    atomicOr(err, ERRB_NOT_SPD);
+    diag_report(dg, source, level, index, bad_k, bad_v);
+  }
   __syncthreads();
   if (act) {
 #pragma unroll
@@ -210,7 +240,7 @@ __device__ void spd_invert_lds(double* A, double (*colbuf)[BD], uint32_t* err) {
 // Store an inverted block (LDS, packed f64) at the requested precision.
 // 16-bit storage keeps A_ij / (sigma_i sigma_j) with sigma_i = sqrt(A_ii).
 template <int P>
-__device__ void store_block(const double* A, void* out, float* scale_out, int64_t d, float* sig) {
+__device__ __forceinline__ void store_block(const double* A, void* out, float* scale_out, int64_t d, float* sig) {
   const int tid = threadIdx.x;
   const size_t stride = blk_elems(P);
   if (P == MAS_F64) {
@@ -278,19 +308,20 @@ __device__ inline void add_block_global(double* A, int li, int lj, bool diag, co
 }
 
 // ---------------------------------------------------------------------------
-// Level 0: one workgroup per subdomain d assembles S_d H_base S_d^T in LDS
-// (mass, every tet touching d, every base contact touching d), inverts it and
-// stores it.  Rows of vertices beyond N are identity.
-template <int P>
-__global__ __launch_bounds__(256) void k_build_l0(int64_t N, const int32_t* tets, const double* mass,
-                                                  const double* hf64, const int32_t* tet_off,
-                                                  const int32_t* tet_list, const double* bk,
-                                                  const double* bgrad, const int32_t* bidx,
-                                                  const int32_t* bc_off, const int32_t* bc_list,
-                                                  void* blk, float* scale, uint32_t* err) {
+// Level 0: one workgroup per subdomain d accumulates S_d H_base S_d^T in LDS
+// (mass, every tet touching d, every base contact touching d) and writes it
+// packed in float64 to the assembly buffer; k_invert_blocks inverts it.
+// Each work item is one (tet, vertex pair) so few values stay live.
+__constant__ int8_t c_pair_i[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+__constant__ int8_t c_pair_j[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
+
+__global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* tets, const double* mass,
+                                                     const double* hf64, const int32_t* tet_off,
+                                                     const int32_t* tet_list, const double* bk,
+                                                     const double* bgrad, const int32_t* bidx,
+                                                     const int32_t* bc_off, const int32_t* bc_list,
+                                                     double* acc) {
   __shared__ double A[PK];
-  __shared__ double colbuf[2][BD];
-  __shared__ float sig[BD];
   const int64_t d = blockIdx.x;
   const int tid = threadIdx.x;
   for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
@@ -300,69 +331,101 @@ __global__ __launch_bounds__(256) void k_build_l0(int64_t N, const int32_t* tets
     A[pk(tid, tid)] = (v < N) ? mass[v] : 1.0;
   }
   __syncthreads();
-  for (int e = tet_off[d] + tid; e < tet_off[d + 1]; e += blockDim.x) {
-    int64_t t = tet_list[e];
-    int v[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = tets[4 * t + j];
+  const int t0 = tet_off[d], nt = tet_off[d + 1] - t0;
+  for (int w = tid; w < 10 * nt; w += blockDim.x) {
+    const int64_t t = tet_list[t0 + w / 10];
+    const int pr = w % 10;
+    const int i = c_pair_i[pr], j = c_pair_j[pr];
+    const int vi = tets[4 * t + i], vj = tets[4 * t + j];
+    if ((vi >> 5) != d || (vj >> 5) != d) continue;
     double H[45], Dmi[9], coef[4][3];
     load_snapshot(hf64, t, H, Dmi);
     dfdx_coef(Dmi, coef);
+    double ci[3], cj[3];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int b = 0; b < 3; ++b) {
+      ci[b] = (i == 0) ? coef[0][b] : (i == 1) ? coef[1][b] : (i == 2) ? coef[2][b] : coef[3][b];
+      cj[b] = (j == 0) ? coef[0][b] : (j == 1) ? coef[1][b] : (j == 2) ? coef[2][b] : coef[3][b];
+    }
+    double blk[3][3];
 #pragma unroll
-      for (int j = 0; j <= i; ++j) {
-        if ((v[i] >> 5) != d || (v[j] >> 5) != d) continue;
-        double b[3][3];
-        elem_block(H, coef, i, j, b);
-        add_block_lds(A, v[i] & 31, v[j] & 31, i == j, b);
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int ap = 0; ap < 3; ++ap) {
+        double s = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int bp = 0; bp < 3; ++bp) s += ci[b] * H[p9(3 * b + a, 3 * bp + ap)] * cj[bp];
+        blk[a][ap] = s;
       }
+    add_block_lds(A, vi & 31, vj & 31, i == j, blk);
   }
-  for (int e = bc_off[d] + tid; e < bc_off[d + 1]; e += blockDim.x) {
-    int64_t ci = bc_list[e];
-    double k = bk[ci];
+  const int c0 = bc_off[d], nc = bc_off[d + 1] - c0;
+  for (int w = tid; w < 10 * nc; w += blockDim.x) {
+    const int64_t ci = bc_list[c0 + w / 10];
+    const int pr = w % 10;
+    const int i = c_pair_i[pr], j = c_pair_j[pr];
+    const int vi = bidx[4 * ci + i], vj = bidx[4 * ci + j];
+    if (vi < 0 || vj < 0 || (vi >> 5) != d || (vj >> 5) != d) continue;
+    const double k = bk[ci];
     const double* n = bgrad + 12 * ci;
-    int v[4];
+    double blk[3][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = bidx[4 * ci + j];
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j <= i; ++j) {
-        if (v[i] < 0 || v[j] < 0 || (v[i] >> 5) != d || (v[j] >> 5) != d) continue;
-        double b[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int q = 0; q < 3; ++q) b[a][q] = k * n[3 * i + a] * n[3 * j + q];
-        add_block_lds(A, v[i] & 31, v[j] & 31, i == j, b);
-      }
+      for (int q = 0; q < 3; ++q) blk[a][q] = k * n[3 * i + a] * n[3 * j + q];
+    add_block_lds(A, vi & 31, vj & 31, i == j, blk);
   }
   __syncthreads();
-  spd_invert_lds(A, colbuf, err);
+  double* out = acc + d * PK;
+  for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
+}
+
+// Inverts the packed float64 blocks of one level (rows of nodes beyond the
+// node count are identity) and stores them at precision P.
+template <int P>
+__global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const double* acc, void* blk, float* scale,
+                                                       uint32_t* err, DiagRec* dg, int level) {
+  __shared__ double A[PK];
+  __shared__ double colbuf[2][BD];
+  __shared__ float sig[BD];
+  const int64_t d = blockIdx.x;
+  const double* src = acc + d * PK;
+  for (int e = threadIdx.x; e < PK; e += blockDim.x) A[e] = src[e];
+  __syncthreads();
+  if (threadIdx.x < BD) {
+    int64_t a = SUB * d + threadIdx.x / 3;
+    if (a >= nodes) A[pk(threadIdx.x, threadIdx.x)] = 1.0;
+  }
+  __syncthreads();
+  spd_invert_lds(A, colbuf, err, dg, level == 0 ? 1 : 2, level, d);
   store_block<P>(A, blk, scale, d, sig);
+}
+
+static void launch_invert(Ctx& c, int l) {
+  Level& Lv = c.lv[l];
+  dim3 g(Lv.nsub), b(256);
+  switch (Lv.prec) {
+    case MAS_F64:
+      k_invert_blocks<MAS_F64><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
+      break;
+    case MAS_F32:
+      k_invert_blocks<MAS_F32><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
+      break;
+    case MAS_BF16:
+      k_invert_blocks<MAS_BF16><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
+      break;
+    default:
+      k_invert_blocks<MAS_F16><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
+  }
 }
 
 mas_status launch_level0_build(Ctx& c) {
   Level& L0 = c.lv[0];
-  dim3 g(L0.nsub), b(256);
-  switch (L0.prec) {
-    case MAS_F64:
-      k_build_l0<MAS_F64><<<g, b, 0, c.s>>>(c.N, c.tets, c.mass, c.hf64, c.tet_off, c.tet_list, c.bk,
-                                            c.bgrad, c.bidx, c.bc_off, c.bc_list, L0.blk, L0.scale, c.err);
-      break;
-    case MAS_F32:
-      k_build_l0<MAS_F32><<<g, b, 0, c.s>>>(c.N, c.tets, c.mass, c.hf64, c.tet_off, c.tet_list, c.bk,
-                                            c.bgrad, c.bidx, c.bc_off, c.bc_list, L0.blk, L0.scale, c.err);
-      break;
-    case MAS_BF16:
-      k_build_l0<MAS_BF16><<<g, b, 0, c.s>>>(c.N, c.tets, c.mass, c.hf64, c.tet_off, c.tet_list, c.bk,
-                                             c.bgrad, c.bidx, c.bc_off, c.bc_list, L0.blk, L0.scale, c.err);
-      break;
-    default:
-      k_build_l0<MAS_F16><<<g, b, 0, c.s>>>(c.N, c.tets, c.mass, c.hf64, c.tet_off, c.tet_list, c.bk,
-                                            c.bgrad, c.bidx, c.bc_off, c.bc_list, L0.blk, L0.scale, c.err);
-  }
+  k_assemble_l0<<<dim3(L0.nsub), dim3(256), 0, c.s>>>(c.N, c.tets, c.mass, c.hf64, c.tet_off, c.tet_list, c.bk,
+                                                      c.bgrad, c.bidx, c.bc_off, c.bc_list, L0.acc);
+  launch_invert(c, 0);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }
@@ -377,27 +440,27 @@ mas_status launch_level0_build(Ctx& c) {
 
 struct CoarseArgs {
   int L;                    // number of levels
-  double* acc[MAXL];        // packed f64 accumulation per level (index 1..L-1)
+  double* const* acc;       // device array: packed f64 assembly per level
 };
 
-__global__ void k_coarse_tets(int64_t T, const int32_t* tets, const double* hf64, CoarseArgs ca) {
+__global__ __launch_bounds__(256) void k_coarse_tets(int64_t T, const int32_t* tets, const double* hf64, CoarseArgs ca) {
   int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (t >= T) return;
   int v[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[j] = tets[4 * t + j];
-  bool loaded = false;
+  // vertices sharing a level-1 node share every coarser node as well
+  if ((v[0] >> 5) == (v[1] >> 5) && (v[0] >> 5) == (v[2] >> 5) && (v[0] >> 5) == (v[3] >> 5)) return;
   double H[45], Dmi[9], coef[4][3];
-  for (int l = 1; l < ca.L; ++l) {
+  load_snapshot(hf64, t, H, Dmi);
+  dfdx_coef(Dmi, coef);
+#pragma unroll
+  for (int l = 1; l < MAXL; ++l) {
+    if (l >= ca.L) break;
     int nd[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) nd[j] = v[j] >> (5 * l);
-    if (nd[0] == nd[1] && nd[0] == nd[2] && nd[0] == nd[3]) continue;
-    if (!loaded) {
-      load_snapshot(hf64, t, H, Dmi);
-      dfdx_coef(Dmi, coef);
-      loaded = true;
-    }
+    if (nd[0] == nd[1] && nd[0] == nd[2] && nd[0] == nd[3]) break;
     int lead[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -442,7 +505,7 @@ __global__ void k_coarse_tets(int64_t T, const int32_t* tets, const double* hf64
   }
 }
 
-__global__ void k_coarse_contacts(int64_t m, const double* bk, const double* bgrad, const int32_t* bidx,
+__global__ __launch_bounds__(256) void k_coarse_contacts(int64_t m, const double* bk, const double* bgrad, const int32_t* bidx,
                                   CoarseArgs ca) {
   int64_t ci = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (ci >= m) return;
@@ -452,7 +515,29 @@ __global__ void k_coarse_contacts(int64_t m, const double* bk, const double* bgr
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[j] = bidx[4 * ci + j];
   const double* n = bgrad + 12 * ci;
-  for (int l = 1; l < ca.L; ++l) {
+  // A stencil whose vertices share one level-1 node contributes k nhat nhat^T
+  // with nhat = sum_j n_j; for translation-invariant stencils (point-triangle,
+  // edge-edge) nhat vanishes up to rounding, so the term is skipped.
+  {
+    int n1 = -1;
+    bool same = true;
+    double nh[3] = {0, 0, 0}, nn = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (v[j] < 0) continue;
+      if (n1 < 0) n1 = v[j] >> 5;
+      same &= (v[j] >> 5) == n1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        nh[a] += n[3 * j + a];
+        nn += n[3 * j + a] * n[3 * j + a];
+      }
+    }
+    if (same && nh[0] * nh[0] + nh[1] * nh[1] + nh[2] * nh[2] <= 1e-24 * nn) return;
+  }
+#pragma unroll
+  for (int l = 1; l < MAXL; ++l) {
+    if (l >= ca.L) break;
     int nd[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) nd[j] = v[j] >= 0 ? (v[j] >> (5 * l)) : -1 - j;
@@ -508,33 +593,13 @@ __global__ void k_coarse_mass(int64_t nodes, int64_t child_n, const double* chil
   for (int c3 = 0; c3 < 3; ++c3) A[pk(3 * la + c3, 3 * la + c3)] += s;
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_coarse_invert(int64_t nodes, const double* acc, void* blk,
-                                                       uint32_t* err) {
-  __shared__ double A[PK];
-  __shared__ double colbuf[2][BD];
-  __shared__ float sig[BD];
-  const int64_t d = blockIdx.x;
-  const double* src = acc + d * PK;
-  for (int e = threadIdx.x; e < PK; e += blockDim.x) A[e] = src[e];
-  __syncthreads();
-  if (threadIdx.x < BD) {
-    int64_t a = SUB * d + threadIdx.x / 3;
-    if (a >= nodes) A[pk(threadIdx.x, threadIdx.x)] = 1.0;
-  }
-  __syncthreads();
-  spd_invert_lds(A, colbuf, err);
-  store_block<P>(A, blk, nullptr, d, sig);
-}
-
 mas_status launch_coarse_build(Ctx& c) {
   if (c.L < 2) return MAS_OK;
   CoarseArgs ca{};
   ca.L = c.L;
-  for (int l = 1; l < c.L; ++l) {
-    ca.acc[l] = c.lv[l].acc;
+  ca.acc = c.acc_ptrs;
+  for (int l = 1; l < c.L; ++l)
     HIPCHK(hipMemsetAsync(c.lv[l].acc, 0, sizeof(double) * PK * c.lv[l].nsub, c.s));
-  }
   // masses: level-1 nodes from vertices, then upward; r buffers hold node masses
   const double* child = c.mass;
   int64_t child_n = c.N;
@@ -548,13 +613,7 @@ mas_status launch_coarse_build(Ctx& c) {
   k_coarse_tets<<<dim3((c.T + 255) / 256), dim3(256), 0, c.s>>>(c.T, c.tets, c.hf64, ca);
   if (c.mb > 0)
     k_coarse_contacts<<<dim3((c.mb + 255) / 256), dim3(256), 0, c.s>>>(c.mb, c.bk, c.bgrad, c.bidx, ca);
-  for (int l = 1; l < c.L; ++l) {
-    Level& Lv = c.lv[l];
-    if (Lv.prec == MAS_F64)
-      k_coarse_invert<MAS_F64><<<dim3(Lv.nsub), dim3(256), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, c.err);
-    else
-      k_coarse_invert<MAS_F32><<<dim3(Lv.nsub), dim3(256), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, c.err);
-  }
+  for (int l = 1; l < c.L; ++l) launch_invert(c, l);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

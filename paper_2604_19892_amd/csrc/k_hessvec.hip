@@ -68,9 +68,11 @@ __global__ void k_hv_cols(int64_t m, const int32_t* idx, const double* u, const 
 }
 
 mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update) {
+  ProfScope ps(c, MAS_T_HESSVEC);
   int64_t n3 = 3 * c.N;
   k_mass_mul<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, c.mass, v, y);
   if (c.T > 0) {
+    ProfScope pt(c, MAS_T_HV_TETS);
     if (c.hf32)
       k_hv_tets<float><<<dim3((c.T + 255) / 256), dim3(256), 0, c.s>>>(c.T, c.tets, c.hf32, v, y);
     else

@@ -119,17 +119,38 @@ __global__ __launch_bounds__(RB) void k_eg_contacts(int64_t m, const int32_t* id
   block_reduce_store<2>(e, part, nblk);
 }
 
-__global__ void k_eg_finalize(const double* part, int nblk, double* E) {
-  if (threadIdx.x != 0) return;
-  double s = 0, bad = 0;
-  for (int q = 0; q < 3; ++q)
-    for (int i = 0; i < nblk; ++i) s += part[q * nblk + i];
-  for (int i = 0; i < nblk; ++i) bad += part[3 * nblk + i];
-  *E = bad > 0 ? INFINITY : s;
+// sums NV rows of nblk partials with one block of RB threads in a fixed order;
+// the totals land in tot[0..NV) (LDS)
+template <int NV>
+__device__ inline void sum_partials(const double* part, int nblk, double* tot) {
+  __shared__ double red[NV][RB];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nblk; i += RB) s += part[q * nblk + i];
+    red[q][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = RB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NV) tot[threadIdx.x] = red[threadIdx.x][0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(RB) void k_eg_finalize(const double* part, int nblk, double* E) {
+  __shared__ double tot[4];
+  sum_partials<4>(part, nblk, tot);
+  if (threadIdx.x == 0) *E = tot[3] > 0 ? INFINITY : (tot[0] + tot[1]) + tot[2];
 }
 
 mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const mas_contacts* ct,
                               double* E, double* g) {
+  ProfScope ps(c, MAS_T_ENERGY);
   const int nb = c.n_partial_blocks;
   double* part = c.partials;  // [0]: inertia [1]: elastic [2]: barrier [3]: infeasible count
   k_eg_vertices<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, c.mass, x, xt, g, part, nb);
@@ -142,7 +163,7 @@ mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const m
   } else {
     HIPCHK(hipMemsetAsync(part + 2 * nb, 0, sizeof(double) * 2 * nb, c.s));
   }
-  k_eg_finalize<<<dim3(1), dim3(64), 0, c.s>>>(part, nb, E);
+  k_eg_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(part, nb, E);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }
@@ -195,15 +216,12 @@ __global__ __launch_bounds__(RB) void k_ss_reduce(int64_t n3, const double* g, c
   block_reduce_store<NS>(s, part, nblk);
 }
 
-__global__ void k_ss_finalize(const double* part, int nblk, int restart, int has_zp, double eps_sing,
-                              double eps_abs, double delta, mas_step_out* out, double* scal) {
+__global__ __launch_bounds__(RB) void k_ss_finalize(const double* part, int nblk, int restart, int has_zp,
+                                                    double eps_sing, double eps_abs, double delta,
+                                                    mas_step_out* out, double* scal) {
+  __shared__ double s[NS];
+  sum_partials<NS>(part, nblk, s);
   if (threadIdx.x != 0) return;
-  double s[NS];
-  for (int q = 0; q < NS; ++q) {
-    double acc = 0;
-    for (int i = 0; i < nblk; ++i) acc += part[q * nblk + i];
-    s[q] = acc;
-  }
   double gz = s[0], gp = s[1], gzp = s[2];
   double A11 = s[3] + s[8], A12 = s[4] + s[9], A22 = s[5] + s[10];
   double mu, nu;
@@ -267,12 +285,13 @@ __global__ void k_ss_update(int64_t n3, const double* z, const double* vz, doubl
 
 mas_status launch_subspace(Ctx& c, const double* g, const double* z, const double* zp,
                            const double* vz, double* p, double* vp, int restart, mas_step_out* out) {
+  ProfScope ps(c, MAS_T_SUBSPACE);
   const int nb = c.n_partial_blocks;
   int64_t n3 = 3 * c.N;
   int64_t m = (c.have_update) ? c.mc : 0;
   k_ss_reduce<<<dim3(nb), dim3(RB), 0, c.s>>>(n3, g, z, zp, p, vz, vp, restart ? 0 : 1, m, c.Uidx, c.U,
                                               c.partials, nb);
-  k_ss_finalize<<<dim3(1), dim3(64), 0, c.s>>>(c.partials, nb, restart, zp != nullptr, c.cfg.eps_sing,
+  k_ss_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(c.partials, nb, restart, zp != nullptr, c.cfg.eps_sing,
                                                c.cfg.eps_abs, c.cfg.restart_delta, out, c.scal);
   k_ss_update<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, z, vz, p, vp, c.scal);
   HIPCHK(hipGetLastError());

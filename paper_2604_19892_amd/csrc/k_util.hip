@@ -45,22 +45,9 @@ __global__ void k_bucket_fill(int64_t m, const int32_t* idx, const double* w, co
   }
 }
 
-// list order inside a bucket depends on atomics; sort each bucket by item id
-// so that every later sum over a bucket has a fixed order
-__global__ void k_bucket_sort(int64_t D, const int32_t* off, int32_t* list) {
-  int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (d >= D) return;
-  int b = off[d], e = off[d + 1];
-  for (int i = b + 1; i < e; ++i) {  // insertion sort: buckets are short
-    int v = list[i];
-    int j = i - 1;
-    while (j >= b && list[j] > v) {
-      list[j + 1] = list[j];
-      --j;
-    }
-    list[j + 1] = v;
-  }
-}
+// The order of items inside a bucket follows the atomics of the fill pass;
+// every consumer is order independent (Top-K ranks by a total order, block
+// assembly adds with atomics).
 
 mas_status ensure_cub(Ctx& c, size_t bytes) {
   if (bytes <= c.cub_bytes) return MAS_OK;
@@ -92,7 +79,6 @@ mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const doub
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
     k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt, list);
-    k_bucket_sort<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, off, list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;

@@ -139,7 +139,7 @@ __device__ inline double block_entry(const void* A, const float* sig, int i, int
 template <int P>
 __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, const float* scale,
                                                      const int32_t* rank, const SlotCol* slots, void* W,
-                                                     double* Lcap, uint32_t* err) {
+                                                     double* Lcap, uint32_t* err, DiagRec* dg) {
   constexpr size_t E = blk_elems(P);
   constexpr size_t ES = prec_size(P);
   __shared__ __align__(16) unsigned char As[E * ES];
@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
       double dj = Cm[j * r + j];
       for (int k = 0; k < j; ++k) dj -= Cm[j * r + k] * Cm[j * r + k];
       if (!(dj > 0.0)) {
+        if (!bad) diag_report(dg, 3, 0, d, j, dj);
         bad = true;
         dj = 1.0;
       }
@@ -230,6 +231,7 @@ static mas_status grow_current(Ctx& c, int64_t m) {
 }
 
 mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) {
+  ProfScope ps(c, MAS_T_UPDATE);
   int64_t m = cur ? cur->m : 0;
   mas_status st = grow_current(c, m > 0 ? m : 1);
   if (st != MAS_OK) return st;
@@ -251,22 +253,23 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
   k_topk<<<dim3(D), dim3(64), 0, c.s>>>(c.K, c.cand_off, c.cand_list, c.dS, c.ckey, c.Uidx, c.U, c.rank,
                                         c.sel, c.slots, rank_hist);
   Level& L0 = c.lv[0];
+  ProfScope pc(c, MAS_T_CAPACITANCE);
   switch (L0.prec) {
     case MAS_F64:
       k_capacitance<MAS_F64><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                             c.Lcap, c.err);
+                                                             c.Lcap, c.err, c.diag);
       break;
     case MAS_F32:
       k_capacitance<MAS_F32><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                             c.Lcap, c.err);
+                                                             c.Lcap, c.err, c.diag);
       break;
     case MAS_BF16:
       k_capacitance<MAS_BF16><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                              c.Lcap, c.err);
+                                                              c.Lcap, c.err, c.diag);
       break;
     default:
       k_capacitance<MAS_F16><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                             c.Lcap, c.err);
+                                                             c.Lcap, c.err, c.diag);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;
