@@ -29,27 +29,25 @@ HBM_PEAK_GBS = 8000.0
 PK = 96 * 97 // 2
 
 
-def apply_l0_bytes(ctx, prec, hists, K):
-    """Algorithmic bytes of one level-0 apply launch per rank histogram."""
+def apply_l0_bytes(ctx, counts, hist):
+    """Algorithmic bytes of one level-0 apply launch: every block in its
+    stored precision (+ row scales for 16-bit), g read, z written, coarse
+    corrections read, ranks, and per updated subdomain its float64 W, slot
+    columns and capacitance factor."""
     N = ctx.N
     D0 = int(ctx.nsub[0])
-    sB = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[prec]
-    sW = 8 if prec == "f64" else 4
-    base = D0 * PK * sB + (D0 * 96 * 4 if sB == 2 else 0)      # blocks (+ row scales)
-    base += 2 * 8 * 3 * N                                        # g read, z write
+    size = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+    b = sum(n * (PK * size[p] + (96 * 4 if size[p] == 2 else 0)) for p, n in counts.items())
+    b += 2 * 8 * 3 * N
     nodes = N
-    for _ in range(1, ctx.levels):                               # coarse corrections read
+    for _ in range(1, ctx.levels):
         nodes = -(-nodes // 32)
-        base += 8 * 3 * nodes
-    base += 4 * D0                                               # ranks
-    out = []
-    for h in hists:
-        wb = 0
-        for r, cnt in enumerate(h):
-            if r:
-                wb += cnt * (96 * r * sW + r * 112 + 8 * r * (r + 1) // 2)
-        out.append(base + wb)
-    return out
+        b += 8 * 3 * nodes
+    b += 4 * D0
+    for r, cnt in enumerate(hist):
+        if r:
+            b += cnt * (96 * r * 8 + r * 112 + 8 * r * (r + 1) // 2)
+    return b
 
 
 def hv_tets_bytes(ctx, hess_prec):
@@ -130,15 +128,19 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done (%d iters)" % args.warmup, file=sys.stderr, flush=True)
 
+    solver.track_precisions = True
+    if solver.precision_counts is None:
+        solver.precision_counts = ctx.block_precisions(0)
     ctx.profile(True)
-    hists = []
+    l0_bytes = []
     r0 = solver.n_restarts
     torch.cuda.synchronize()
     t = time.perf_counter()
     for i in range(args.steps):
         restart = solver.restart
         solver.iterate()
-        hists.append([0] if restart else solver.rank_hist.cpu().numpy().tolist())
+        hist = [0] if restart else solver.rank_hist.cpu().numpy().tolist()
+        l0_bytes.append(apply_l0_bytes(ctx, solver.precision_counts, hist))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     restarts = solver.n_restarts - r0
@@ -148,7 +150,7 @@ def main():
     print("[bench] timed %d iters in %.3fs" % (args.steps, dt), file=sys.stderr, flush=True)
 
     ms_l0, n_l0 = timers["apply_l0"]
-    bytes_l0 = apply_l0_bytes(ctx, args.prec, hists, solver.ctx.cfg.max_rank)
+    bytes_l0 = l0_bytes
     achieved = sum(bytes_l0) / (ms_l0 * 1e-3) / 1e9 if n_l0 else 0.0
     ms_hv, n_hv = timers["hv_tets"]
     hv_b = hv_tets_bytes(ctx, hess_prec)
@@ -177,6 +179,7 @@ def main():
             "levels": int(ctx.levels), "K": int(ctx.cfg.max_rank),
             "block_storage": args.prec, "hessian_storage": hess_prec,
             "restarts_in_timed_steps": int(restarts),
+            "stored_block_precisions": solver.precision_counts,
         },
         "mas_apply_GBps": achieved,
         "roofline": {

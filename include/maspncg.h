@@ -74,9 +74,14 @@ typedef enum {
 
 /* Storage precision of the level-0 inverse blocks (block_prec) and of the
  * element Hessian snapshot (hess_prec: MAS_F64 or MAS_F32).  Blocks are
- * always assembled and inverted in float64 (supplement Section 1.1); BF16
- * and FP16 blocks are stored with a per-row symmetric scaling s_i =
- * B_ii^-1/2.  Products with stored blocks accumulate in float64. */
+ * always assembled and inverted in float64 (supplement Section 1.1) and then
+ * stored in the requested form when that form can hold them: with
+ * kappa_d = max_i (M_d)_ii (B_d)_ii (a lower bound on the condition number of
+ * the Jacobi-scaled block), a block is kept in a format of unit roundoff eps
+ * only if kappa_d <= prec_guard / (20 eps); otherwise it is promoted
+ * (BF16/FP16 -> FP32 -> FP64), so no stored block loses definiteness.  BF16
+ * and FP16 blocks carry a per-row symmetric scaling sigma_i = B_ii^1/2.
+ * Products with stored blocks accumulate in float64. */
 typedef enum { MAS_F64 = 0, MAS_F32 = 1, MAS_BF16 = 2, MAS_F16 = 3 } mas_prec;
 
 typedef struct {
@@ -90,10 +95,11 @@ typedef struct {
   double dhat;          /* barrier activation distance */
   double h;             /* time step */
   double gravity[3];    /* external acceleration used for x~ */
-  int32_t block_prec;   /* mas_prec of level-0 blocks */
-  int32_t coarse_prec;  /* MAS_F64 or MAS_F32 for levels >= 1 */
+  int32_t block_prec;   /* requested mas_prec of level-0 blocks */
+  int32_t coarse_prec;  /* requested mas_prec of levels >= 1 */
   int32_t hess_prec;    /* MAS_F64 or MAS_F32 element Hessian snapshot */
   int32_t reserved;
+  double prec_guard;    /* promotion threshold factor (default 0.5; 0: never promote) */
 } mas_config;
 
 /* Tetrahedral mesh, host pointers, original vertex numbering.  tets must
@@ -159,6 +165,8 @@ mas_status mas_build(void* ctx, const double* x_base, const mas_contacts* base);
  * capacitance I + U_d^T B_d U_d in float64.  rank_hist (device, max_rank+1
  * int32, nullable) receives the histogram of per-subdomain ranks. */
 mas_status mas_woodbury_update(void* ctx, const mas_contacts* curr, int32_t* rank_hist);
+/* (W_d = B_d U_d is kept in float64: its product with C_d^-1 cancels against
+ * B_d along stiff contact directions.) */
 
 /* z = P g (device vectors, 3N, must not alias): level-0 blocks with the
  * Woodbury correction z_d = B_d g_d - W_d C_d^-1 U_d^T B_d g_d, plus
@@ -206,6 +214,10 @@ mas_status mas_sync_status(void* ctx, char* msg, int32_t msg_len);
 
 /* Sizes: N, T, number of levels, D_l for l < 6. */
 mas_status mas_query(void* ctx, int64_t* N, int64_t* T, int32_t* levels, int64_t* nsub /*6*/);
+
+/* Number of blocks of level l stored in each precision by the last
+ * mas_build (counts[4] indexed by mas_prec, host). */
+mas_status mas_block_precisions(void* ctx, int32_t level, int64_t* counts);
 
 /* Copies block d of level l, dequantised to float64, as a dense 96x96
  * row-major host array (for verification). */

@@ -33,6 +33,7 @@ class MasConfig(ctypes.Structure):
         ("coarse_prec", ctypes.c_int32),
         ("hess_prec", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("prec_guard", ctypes.c_double),
     ]
 
 
@@ -95,6 +96,7 @@ SIGNATURES = {
     "mas_sync_status": (_I32, [_P, ctypes.c_char_p, _I32]),
     "mas_query": (_I32, [_P, _P, _P, _P, _P]),
     "mas_get_block": (_I32, [_P, _I32, _I64, _P]),
+    "mas_block_precisions": (_I32, [_P, _I32, _P]),
     "mas_get_selection": (_I32, [_P, _P, _P]),
     "mas_status_string": (ctypes.c_char_p, [_I32]),
     "mas_profile_enable": (_I32, [_P, _I32]),

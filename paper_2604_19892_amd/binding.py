@@ -20,7 +20,7 @@ def _ptr(t):
 
 
 def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=None,
-                hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12):
+                hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12, prec_guard=None):
     cfg = MasConfig()
     _abi.lib().mas_default_config(ctypes.byref(cfg))
     if scene is not None:
@@ -37,7 +37,7 @@ def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=N
         if K is not None:
             cfg.max_rank = int(K)
     cfg.block_prec = _abi.PREC[block_prec]
-    cp = coarse_prec or ("f64" if block_prec == "f64" else "f32")
+    cp = coarse_prec or "f64"
     hp = hess_prec or ("f64" if block_prec == "f64" else "f32")
     cfg.coarse_prec = _abi.PREC[cp]
     cfg.hess_prec = _abi.PREC[hp]
@@ -45,6 +45,8 @@ def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=N
     cfg.eps_sing = float(eps_sing)
     if cos_rot is not None:
         cfg.cos_rot = float(cos_rot)
+    if prec_guard is not None:
+        cfg.prec_guard = float(prec_guard)
     return cfg
 
 
@@ -135,11 +137,18 @@ class MasContext:
         out[self.perm] = a
         return out.reshape(-1)
 
-    def contacts(self, cset):
-        """Host contact set (original vertex ids) -> DeviceContacts."""
+    def contacts(self, cset, sort=False):
+        """Host contact set (original vertex ids) -> DeviceContacts in library
+        numbering; ``sort`` orders the stencils by their smallest library
+        vertex, which keeps the library's scatter kernels local."""
         idx = np.where(cset['idx'] >= 0, self.rank[np.maximum(cset['idx'], 0)], -1).astype(np.int32)
-        return DeviceContacts(cset['key'], idx, cset['grad'], d=cset.get('d'), off=cset.get('off'),
-                              device=self.device)
+        order = slice(None)
+        if sort:
+            vmin = np.where(idx >= 0, idx, np.iinfo(np.int32).max).min(axis=1)
+            order = np.argsort(vmin, kind='stable')
+        pick = (lambda a: None if a is None else np.ascontiguousarray(a[order]))
+        return DeviceContacts(cset['key'][order], idx[order], cset['grad'][order], d=pick(cset.get('d')),
+                              off=pick(cset.get('off')), device=self.device)
 
     def vec(self):
         return torch.zeros(3 * self.N, dtype=torch.float64, device=self.device)
@@ -213,6 +222,12 @@ class MasContext:
         check("mas_profile_read", _abi.lib().mas_profile_read(self.h, _abi.TIMERS[timer], ctypes.byref(ms),
                                                              ctypes.byref(n)))
         return ms.value, n.value
+
+    def block_precisions(self, level=0):
+        """Blocks of a level stored as {f64, f32, bf16, f16} by the last build."""
+        counts = np.zeros(4, np.int64)
+        check("mas_block_precisions", _abi.lib().mas_block_precisions(self.h, int(level), counts.ctypes.data))
+        return dict(zip(("f64", "f32", "bf16", "f16"), counts.tolist()))
 
     def get_selection(self):
         D0 = int(self.nsub[0])

@@ -130,6 +130,7 @@ void mas_default_config(mas_config* cfg) {
   cfg->block_prec = MAS_F64;
   cfg->coarse_prec = MAS_F64;
   cfg->hess_prec = MAS_F64;
+  cfg->prec_guard = 0.5;
 }
 
 const char* mas_status_string(mas_status s) {
@@ -159,7 +160,7 @@ mas_status mas_destroy(void* p) {
     if (q) hipFree(q);
   for (int l = 0; l < MAXL; ++l) {
     Level& L = c->lv[l];
-    void* lp[] = {L.blk, L.scale, L.acc, L.r, L.c};
+    void* lp[] = {L.blk, L.bprec, L.scale, L.acc, L.r, L.c};
     for (void* q : lp)
       if (q) hipFree(q);
   }
@@ -187,7 +188,8 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (cfg->num_levels < 1 || cfg->num_levels > MAXL) return MAS_ERR_INVALID_ARG;
   if (cfg->max_rank < 0 || cfg->max_rank > MAXK) return MAS_ERR_INVALID_ARG;
   if (cfg->block_prec < MAS_F64 || cfg->block_prec > MAS_F16) return MAS_ERR_INVALID_ARG;
-  if (cfg->coarse_prec != MAS_F64 && cfg->coarse_prec != MAS_F32) return MAS_ERR_INVALID_ARG;
+  if (cfg->coarse_prec < MAS_F64 || cfg->coarse_prec > MAS_F16) return MAS_ERR_INVALID_ARG;
+  if (!(cfg->prec_guard >= 0)) return MAS_ERR_INVALID_ARG;
   if (cfg->hess_prec != MAS_F64 && cfg->hess_prec != MAS_F32) return MAS_ERR_INVALID_ARG;
   if (!(cfg->dhat > 0) || !(cfg->h > 0) || !(cfg->kappa >= 0)) return MAS_ERR_INVALID_ARG;
   for (int64_t t = 0; t < 4 * T; ++t)
@@ -203,6 +205,13 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (c->Tpad == 0) c->Tpad = TILE;
   c->L = cfg->num_levels;
   c->K = cfg->max_rank;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        prop.multiProcessorCount > 0)
+      c->n_cu = prop.multiProcessorCount;
+  }
   mas_status st = MAS_OK;
 #define TRY(x)                 \
   do {                         \
@@ -288,8 +297,9 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hf32, EH * c->Tpad));
   for (int l = 0; l < c->L; ++l) {
     Level& L = c->lv[l];
-    TRY(dalloc_bytes(&L.blk, L.nsub * blk_elems(L.prec) * prec_size(L.prec)));
-    if (L.prec == MAS_BF16 || L.prec == MAS_F16) TRY(dalloc(&L.scale, L.nsub * BD));
+    TRY(dalloc_bytes(&L.blk, L.nsub * BLK_STRIDE));
+    TRY(dalloc(&L.bprec, L.nsub));
+    TRY(dalloc(&L.scale, L.nsub * BD));
     TRY(dalloc(&L.acc, L.nsub * PK));
     if (l > 0) {
       TRY(dalloc(&L.r, 3 * L.nodes));
@@ -304,7 +314,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->rank, D0));
   TRY(dalloc(&c->sel, D0 * Kk));
   TRY(dalloc(&c->slots, D0 * Kk));
-  TRY(dalloc_bytes(&c->W, size_t(D0) * Kk * BD * (cfg->block_prec == MAS_F64 ? 8 : 4)));
+  TRY(dalloc(&c->W, size_t(D0) * Kk * BD));
   TRY(dalloc(&c->Lcap, D0 * (Kk * (Kk + 1) / 2)));
   TRY(dalloc(&c->partials, 16 * c->n_partial_blocks));
   TRY(dalloc(&c->scal, 64));
@@ -479,27 +489,43 @@ mas_status mas_get_block(void* p, int32_t level, int64_t d, double* out) {
   if (level < 0 || level >= c.L || d < 0 || d >= c.lv[level].nsub) return MAS_ERR_INVALID_ARG;
   if (!c.built) return MAS_ERR_STATE;
   Level& L = c.lv[level];
-  size_t es = prec_size(L.prec), ne = blk_elems(L.prec);
-  std::vector<unsigned char> raw(ne * es);
-  std::vector<float> sig(BD, 1.0f);
+  uint8_t p8 = 0;
   HIPCHK(hipStreamSynchronize(c.s));
-  HIPCHK(hipMemcpy(raw.data(), reinterpret_cast<unsigned char*>(L.blk) + d * ne * es, ne * es,
+  HIPCHK(hipMemcpy(&p8, L.bprec + d, 1, hipMemcpyDeviceToHost));
+  const int P = p8;
+  std::vector<unsigned char> raw(BLK_STRIDE);
+  std::vector<float> sig(BD, 1.0f);
+  HIPCHK(hipMemcpy(raw.data(), reinterpret_cast<unsigned char*>(L.blk) + d * BLK_STRIDE, BLK_STRIDE,
                    hipMemcpyDeviceToHost));
-  if (L.scale) HIPCHK(hipMemcpy(sig.data(), L.scale + d * BD, BD * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(sig.data(), L.scale + d * BD, BD * sizeof(float), hipMemcpyDeviceToHost));
   for (int i = 0; i < BD; ++i)
     for (int j = 0; j <= i; ++j) {
       int e = pk(i, j);
       double v;
-      if (L.prec == MAS_F64) v = reinterpret_cast<double*>(raw.data())[e];
-      else if (L.prec == MAS_F32) v = reinterpret_cast<float*>(raw.data())[e];
+      if (P == MAS_F64) v = reinterpret_cast<double*>(raw.data())[e];
+      else if (P == MAS_F32) v = reinterpret_cast<float*>(raw.data())[e];
       else {
         uint16_t h = reinterpret_cast<uint16_t*>(raw.data())[e];
-        float f = L.prec == MAS_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
+        float f = P == MAS_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
         v = double(f) * sig[i] * sig[j];
       }
       out[i * BD + j] = v;
       out[j * BD + i] = v;
     }
+  return MAS_OK;
+}
+
+mas_status mas_block_precisions(void* p, int32_t level, int64_t* counts) {
+  if (!p || !counts) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (level < 0 || level >= c.L) return MAS_ERR_INVALID_ARG;
+  if (!c.built) return MAS_ERR_STATE;
+  Level& L = c.lv[level];
+  std::vector<uint8_t> pr(L.nsub);
+  HIPCHK(hipStreamSynchronize(c.s));
+  HIPCHK(hipMemcpy(pr.data(), L.bprec, L.nsub, hipMemcpyDeviceToHost));
+  for (int q = 0; q < 4; ++q) counts[q] = 0;
+  for (uint8_t v : pr) counts[v & 3]++;
   return MAS_OK;
 }
 

@@ -41,6 +41,16 @@ __host__ __device__ inline constexpr size_t blk_elems(int p) {
   return (PK + 256 / prec_size(p) - 1) / (256 / prec_size(p)) * (256 / prec_size(p));
 }
 
+// every block occupies a slot of the float64 size; its stored precision is
+// recorded per block
+constexpr size_t BLK_STRIDE = blk_elems(MAS_F64) * 8;
+
+// unit roundoff of each storage format
+__host__ __device__ inline constexpr double prec_eps(int p) {
+  return p == MAS_F64 ? 1.1102230246251565e-16
+                      : (p == MAS_F32 ? 5.9604644775390625e-08 : (p == MAS_F16 ? 4.8828125e-04 : 3.90625e-03));
+}
+
 // ------------------------------------------------------------ 16-bit floats
 // bfloat16: upper half of an IEEE binary32; rounding to nearest even.
 __host__ __device__ inline float bf16_to_f32(uint16_t h) {
@@ -105,8 +115,9 @@ struct SlotCol {        // one column of U_d restricted to its subdomain
 struct Level {
   int64_t nodes = 0;    // level-l nodes (level 0: vertices)
   int64_t nsub = 0;     // D_l
-  int prec = MAS_F64;
-  void* blk = nullptr;  // nsub * blk_elems(prec) entries
+  int prec = MAS_F64;      // requested storage precision
+  void* blk = nullptr;     // nsub slots of BLK_STRIDE bytes
+  uint8_t* bprec = nullptr;  // stored precision of each block
   float* scale = nullptr;  // nsub * 96 row scales (16-bit storage)
   double* acc = nullptr;   // packed FP64 assembly of every block of the level
   double* r = nullptr;     // restricted residual 3*nodes (levels >= 1)
@@ -120,6 +131,7 @@ struct Ctx {
   Prof* prof = nullptr;
   mas_config cfg{};
   int64_t N = 0, T = 0, Tpad = 0;
+  int n_cu = 256;                  // compute units of the device
   int L = 1, K = 8;
   Level lv[MAXL];
 
@@ -161,7 +173,7 @@ struct Ctx {
   int32_t* rank = nullptr;         // D0
   int32_t* sel = nullptr;          // D0*K
   SlotCol* slots = nullptr;        // D0*K
-  void* W = nullptr;               // D0*96*K (FP64 if block_prec==F64 else FP32)
+  double* W = nullptr;             // D0*K*96, float64
   double* Lcap = nullptr;          // D0*K*(K+1)/2
   bool have_update = false;
 
@@ -176,6 +188,57 @@ struct Ctx {
   void* cub_tmp = nullptr;
   size_t cub_bytes = 0;
 };
+
+// Scatter through an LDS window.  A workgroup handles a chunk of items
+// sorted by their smallest vertex; vertices in [vbase, vbase + SW_WIN) are
+// accumulated in LDS, the others (and finally the window) are added to the
+// global vector with atomics, which cuts global atomics several-fold.
+constexpr int SW_WIN = 1024;
+constexpr int SW_CHUNK = 1024;
+
+__device__ __forceinline__ void sw_add(double* win, double* y, int vbase, int v, int a, double val) {
+  const int lv = v - vbase;
+  if (lv >= 0 && lv < SW_WIN) atomicAdd(&win[3 * lv + a], val);
+  else atomicAdd(&y[3 * int64_t(v) + a], val);
+}
+
+__device__ __forceinline__ void sw_flush(const double* win, double* y, int vbase, int64_t N) {
+  for (int e = threadIdx.x; e < 3 * SW_WIN; e += blockDim.x) {
+    const double val = win[e];
+    if (val != 0.0 && int64_t(vbase) + e / 3 < N) atomicAdd(&y[3 * int64_t(vbase) + e], val);
+  }
+}
+
+// Wavefront aggregation of atomics: lanes whose key matches the lowest
+// pending lane's key combine their values (one shuffle reduction per
+// distinct key) and only that lane issues the atomic.  Every lane of the
+// wavefront must call these together (uniform control flow); key < 0 marks
+// a lane with nothing to add.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+
+// atomic min of a positive double per key (address addr of the leader)
+__device__ __forceinline__ void wave_min_pos(long long key, double* addr, double val) {
+  const int lane = threadIdx.x & 63;
+  bool pending = key >= 0;
+  while (true) {
+    const unsigned long long act = __ballot(pending);
+    if (act == 0) break;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const long long lk = __shfl(key, leader);
+    const bool mine = pending && key == lk;
+    const double m = wave_min(mine ? val : INFINITY);
+    if (lane == leader) atomic_min_pos(addr, m);
+    if (mine) pending = false;
+  }
+}
 
 // Records a HIP event pair around its scope when timers are enabled.
 void prof_begin(Ctx& c, int timer);

@@ -237,17 +237,17 @@ __device__ __forceinline__ void spd_invert_lds(double* A, double (*colbuf)[BD], 
   __syncthreads();
 }
 
-// Store an inverted block (LDS, packed f64) at the requested precision.
+// Store an inverted block (LDS, packed f64) at precision P in slot d.
 // 16-bit storage keeps A_ij / (sigma_i sigma_j) with sigma_i = sqrt(A_ii).
 template <int P>
 __device__ __forceinline__ void store_block(const double* A, void* out, float* scale_out, int64_t d, float* sig) {
   const int tid = threadIdx.x;
-  const size_t stride = blk_elems(P);
+  unsigned char* slot = reinterpret_cast<unsigned char*>(out) + d * BLK_STRIDE;
   if (P == MAS_F64) {
-    double* o = reinterpret_cast<double*>(out) + d * stride;
+    double* o = reinterpret_cast<double*>(slot);
     for (int e = tid; e < PK; e += blockDim.x) o[e] = A[e];
   } else if (P == MAS_F32) {
-    float* o = reinterpret_cast<float*>(out) + d * stride;
+    float* o = reinterpret_cast<float*>(slot);
     for (int e = tid; e < PK; e += blockDim.x) o[e] = float(A[e]);
   } else {
     for (int i = tid; i < BD; i += blockDim.x) {
@@ -256,7 +256,7 @@ __device__ __forceinline__ void store_block(const double* A, void* out, float* s
       scale_out[d * BD + i] = s;
     }
     __syncthreads();
-    uint16_t* o = reinterpret_cast<uint16_t*>(out) + d * stride;
+    uint16_t* o = reinterpret_cast<uint16_t*>(slot);
     for (int e = tid; e < PK; e += blockDim.x) {
       int i = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
       while ((i + 1) * (i + 2) / 2 <= e) ++i;
@@ -304,6 +304,28 @@ __device__ inline void add_block_global(double* A, int li, int lj, bool diag, co
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * lj + q, 3 * li + a)], b[a][q]);
+  }
+}
+
+// add a 3x3 block to a packed-lower global matrix after summing it over the
+// lanes of the wavefront with the same key (see wave_min_pos)
+__device__ __forceinline__ void wave_add_block(long long key, double* A, int li, int lj, bool diag,
+                                               const double (&b)[3][3]) {
+  const int lane = threadIdx.x & 63;
+  bool pending = key >= 0;
+  while (true) {
+    const unsigned long long act = __ballot(pending);
+    if (act == 0) break;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const long long lk = __shfl(key, leader);
+    const bool mine = pending && key == lk;
+    double t[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) t[a][q] = wave_sum(mine ? b[a][q] : 0.0);
+    if (lane == leader) add_block_global(A, li, lj, diag, t);
+    if (mine) pending = false;
   }
 }
 
@@ -383,13 +405,18 @@ __global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* t
 }
 
 // Inverts the packed float64 blocks of one level (rows of nodes beyond the
-// node count are identity) and stores them at precision P.
-template <int P>
+// node count are identity) and stores each in the requested precision, or a
+// wider one when kappa = max_i M_ii B_ii exceeds guard / (20 eps): the spectral
+// norm of the rounding error of a unit-diagonal 96x96 matrix is about 20 eps,
+// and 1/kappa bounds its smallest eigenvalue from above.
 __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const double* acc, void* blk, float* scale,
-                                                       uint32_t* err, DiagRec* dg, int level) {
+                                                       uint8_t* bprec, int req, double guard, uint32_t* err,
+                                                       DiagRec* dg, int level) {
   __shared__ double A[PK];
   __shared__ double colbuf[2][BD];
+  __shared__ double mdiag[BD];
   __shared__ float sig[BD];
+  __shared__ int chosen;
   const int64_t d = blockIdx.x;
   const double* src = acc + d * PK;
   for (int e = threadIdx.x; e < PK; e += blockDim.x) A[e] = src[e];
@@ -397,28 +424,38 @@ __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const doub
   if (threadIdx.x < BD) {
     int64_t a = SUB * d + threadIdx.x / 3;
     if (a >= nodes) A[pk(threadIdx.x, threadIdx.x)] = 1.0;
+    mdiag[threadIdx.x] = A[pk(threadIdx.x, threadIdx.x)];
   }
   __syncthreads();
   spd_invert_lds(A, colbuf, err, dg, level == 0 ? 1 : 2, level, d);
-  store_block<P>(A, blk, scale, d, sig);
+  if (threadIdx.x < 64) {
+    double k1 = mdiag[threadIdx.x] * A[pk(threadIdx.x, threadIdx.x)];
+    if (threadIdx.x < BD - 64) {
+      int i2 = threadIdx.x + 64;
+      k1 = fmax(k1, mdiag[i2] * A[pk(i2, i2)]);
+    }
+    for (int o = 32; o > 0; o >>= 1) k1 = fmax(k1, __shfl_xor(k1, o));
+    if (threadIdx.x == 0) {
+      int p = req;
+      while (guard > 0.0 && p != MAS_F64 && !(k1 <= guard / (20.0 * prec_eps(p))))
+        p = (p == MAS_F32) ? MAS_F64 : MAS_F32;
+      chosen = p;
+      bprec[d] = uint8_t(p);
+    }
+  }
+  __syncthreads();
+  switch (chosen) {
+    case MAS_F64: store_block<MAS_F64>(A, blk, scale, d, sig); break;
+    case MAS_F32: store_block<MAS_F32>(A, blk, scale, d, sig); break;
+    case MAS_BF16: store_block<MAS_BF16>(A, blk, scale, d, sig); break;
+    default: store_block<MAS_F16>(A, blk, scale, d, sig);
+  }
 }
 
 static void launch_invert(Ctx& c, int l) {
   Level& Lv = c.lv[l];
-  dim3 g(Lv.nsub), b(256);
-  switch (Lv.prec) {
-    case MAS_F64:
-      k_invert_blocks<MAS_F64><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
-      break;
-    case MAS_F32:
-      k_invert_blocks<MAS_F32><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
-      break;
-    case MAS_BF16:
-      k_invert_blocks<MAS_BF16><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
-      break;
-    default:
-      k_invert_blocks<MAS_F16><<<g, b, 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, c.err, c.diag, l);
-  }
+  k_invert_blocks<<<dim3(Lv.nsub), dim3(256), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, Lv.bprec, Lv.prec,
+                                                         c.cfg.prec_guard, c.err, c.diag, l);
 }
 
 mas_status launch_level0_build(Ctx& c) {
@@ -444,23 +481,34 @@ struct CoarseArgs {
 };
 
 __global__ __launch_bounds__(256) void k_coarse_tets(int64_t T, const int32_t* tets, const double* hf64, CoarseArgs ca) {
-  int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (t >= T) return;
-  int v[4];
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  int v[4] = {0, 0, 0, 0};
+  if (t < T) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = tets[4 * t + j];
+    for (int j = 0; j < 4; ++j) v[j] = tets[4 * t + j];
+  }
   // vertices sharing a level-1 node share every coarser node as well
-  if ((v[0] >> 5) == (v[1] >> 5) && (v[0] >> 5) == (v[2] >> 5) && (v[0] >> 5) == (v[3] >> 5)) return;
+  const bool live = t < T && !((v[0] >> 5) == (v[1] >> 5) && (v[0] >> 5) == (v[2] >> 5) &&
+                               (v[0] >> 5) == (v[3] >> 5));
+  if (__ballot(live) == 0) return;  // uniform: the whole wavefront is done
   double H[45], Dmi[9], coef[4][3];
-  load_snapshot(hf64, t, H, Dmi);
+  if (live) {
+    load_snapshot(hf64, t, H, Dmi);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 45; ++q) H[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Dmi[q] = 0.0;
+  }
   dfdx_coef(Dmi, coef);
 #pragma unroll
   for (int l = 1; l < MAXL; ++l) {
-    if (l >= ca.L) break;
+    if (l >= ca.L) break;  // uniform
     int nd[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) nd[j] = v[j] >> (5 * l);
-    if (nd[0] == nd[1] && nd[0] == nd[2] && nd[0] == nd[3]) break;
+    const bool lv_live = live && !(nd[0] == nd[1] && nd[0] == nd[2] && nd[0] == nd[3]);
+    if (__ballot(lv_live) == 0) break;  // uniform
     int lead[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -484,9 +532,8 @@ __global__ __launch_bounds__(256) void k_coarse_tets(int64_t T, const int32_t* t
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int u = 0; u <= s; ++u) {
-        if (lead[s] != s || lead[u] != u) continue;
-        int a_s = nd[s], a_u = nd[u];
-        if ((a_s >> 5) != (a_u >> 5)) continue;
+        const int a_s = nd[s], a_u = nd[u];
+        const bool ok = lv_live && lead[s] == s && lead[u] == u && (a_s >> 5) == (a_u >> 5);
         double b[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -499,25 +546,31 @@ __global__ __launch_bounds__(256) void k_coarse_tets(int64_t T, const int32_t* t
               for (int bp = 0; bp < 3; ++bp) acc += ch[s][bb] * H[p9(3 * bb + a, 3 * bp + ap)] * ch[u][bp];
             b[a][ap] = acc;
           }
-        double* A = ca.acc[l] + int64_t(a_s >> 5) * PK;
-        add_block_global(A, a_s & 31, a_u & 31, s == u, b);
+        const long long key = ok ? ((long long)(a_s >> 5) << 10 | (a_s & 31) << 5 | (a_u & 31)) : -1ll;
+        wave_add_block(key, ca.acc[l] + int64_t(a_s >> 5) * PK, a_s & 31, a_u & 31, s == u, b);
       }
   }
 }
 
-__global__ __launch_bounds__(256) void k_coarse_contacts(int64_t m, const double* bk, const double* bgrad, const int32_t* bidx,
-                                  CoarseArgs ca) {
-  int64_t ci = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (ci >= m) return;
-  double k = bk[ci];
-  if (!(k > 0.0)) return;
-  int v[4];
+__global__ __launch_bounds__(256) void k_coarse_contacts(int64_t m, const double* bk, const double* bgrad,
+                                                         const int32_t* bidx, CoarseArgs ca) {
+  const int64_t ci = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  double k = 0.0;
+  int v[4] = {-1, -1, -1, -1};
+  double n[12];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = bidx[4 * ci + j];
-  const double* n = bgrad + 12 * ci;
+  for (int q = 0; q < 12; ++q) n[q] = 0.0;
+  if (ci < m) {
+    k = bk[ci];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = bidx[4 * ci + j];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) n[q] = bgrad[12 * ci + q];
+  }
   // A stencil whose vertices share one level-1 node contributes k nhat nhat^T
   // with nhat = sum_j n_j; for translation-invariant stencils (point-triangle,
   // edge-edge) nhat vanishes up to rounding, so the term is skipped.
+  bool live = ci < m && k > 0.0;
   {
     int n1 = -1;
     bool same = true;
@@ -533,11 +586,12 @@ __global__ __launch_bounds__(256) void k_coarse_contacts(int64_t m, const double
         nn += n[3 * j + a] * n[3 * j + a];
       }
     }
-    if (same && nh[0] * nh[0] + nh[1] * nh[1] + nh[2] * nh[2] <= 1e-24 * nn) return;
+    if (same && nh[0] * nh[0] + nh[1] * nh[1] + nh[2] * nh[2] <= 1e-24 * nn) live = false;
   }
+  if (__ballot(live) == 0) return;  // uniform
 #pragma unroll
   for (int l = 1; l < MAXL; ++l) {
-    if (l >= ca.L) break;
+    if (l >= ca.L) break;  // uniform
     int nd[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) nd[j] = v[j] >= 0 ? (v[j] >> (5 * l)) : -1 - j;
@@ -564,16 +618,16 @@ __global__ __launch_bounds__(256) void k_coarse_contacts(int64_t m, const double
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int u = 0; u <= s; ++u) {
-        if (lead[s] != s || lead[u] != u || v[s] < 0 || v[u] < 0) continue;
-        int a_s = nd[s], a_u = nd[u];
-        if ((a_s >> 5) != (a_u >> 5)) continue;
+        const int a_s = nd[s], a_u = nd[u];
+        const bool ok = live && lead[s] == s && lead[u] == u && v[s] >= 0 && v[u] >= 0 &&
+                        (a_s >> 5) == (a_u >> 5);
         double b[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int q = 0; q < 3; ++q) b[a][q] = k * nh[s][a] * nh[u][q];
-        double* A = ca.acc[l] + int64_t(a_s >> 5) * PK;
-        add_block_global(A, a_s & 31, a_u & 31, s == u, b);
+        const long long key = ok ? ((long long)(a_s >> 5) << 10 | (a_s & 31) << 5 | (a_u & 31)) : -1ll;
+        wave_add_block(key, ca.acc[l] + int64_t(ok ? (a_s >> 5) : 0) * PK, a_s & 31, a_u & 31, s == u, b);
       }
   }
 }

@@ -46,74 +46,122 @@ __global__ __launch_bounds__(RB) void k_eg_vertices(int64_t N, const double* mas
   block_reduce_store<1>(e, part, nblk);
 }
 
-// h^2 V Psi(F) and its gradient h^2 V P Dm^-T scattered to the vertices
-__global__ __launch_bounds__(RB) void k_eg_tets(int64_t T, const int32_t* tets, const double* geo,
-                                                const double* x, double h2, double* g, double* part,
-                                                int nblk) {
+// h^2 V Psi(F) and its gradient h^2 V P Dm^-T scattered to the vertices:
+// each workgroup takes SW_CHUNK consecutive tets and scatters through an LDS
+// window; the energy is reduced per workgroup in a fixed order
+__global__ __launch_bounds__(RB) void k_eg_tets(int64_t N, int64_t T, const int32_t* tets, const double* geo,
+                                                const double* x, double h2, double* g, double* part, int nblk) {
+  __shared__ double win[3 * SW_WIN];
   double e[1] = {0.0};
-  for (int64_t t = blockIdx.x * int64_t(RB) + threadIdx.x; t < T; t += int64_t(nblk) * RB) {
-    const int4 tv = reinterpret_cast<const int4*>(tets)[t];
-    int vi[4] = {tv.x, tv.y, tv.z, tv.w};
-    double xe[12];
+  const bool grad = g != nullptr;
+  for (int64_t chunk = blockIdx.x; chunk * SW_CHUNK < T; chunk += nblk) {
+    const int64_t t0 = chunk * SW_CHUNK;
+    const int4 f4 = reinterpret_cast<const int4*>(tets)[t0];
+    const int vbase = min(min(f4.x, f4.y), min(f4.z, f4.w));
+    if (grad) {
+      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0;
+      __syncthreads();
+    }
+    for (int k = 0; k < SW_CHUNK; k += RB) {
+      const int64_t t = t0 + k + threadIdx.x;
+      if (t >= T) break;
+      const int4 tv = reinterpret_cast<const int4*>(tets)[t];
+      const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+      double xe[12];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
-    const double* gm = geo + 12 * t;
-    double Dmi[9];
+        for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
+      const double* gm = geo + 12 * t;
+      double Dmi[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) Dmi[q] = gm[q];
-    double F[3][3];
-    def_grad(xe, Dmi, F);
-    const double s = h2 * gm[9];
-    e[0] += s * snh_energy(F, gm[10], gm[11]);
-    if (g) {
-      double P[3][3];
-      snh_stress(F, gm[10], gm[11], P);
-      double f0[3] = {0, 0, 0};
+      for (int q = 0; q < 9; ++q) Dmi[q] = gm[q];
+      double F[3][3];
+      def_grad(xe, Dmi, F);
+      const double s = h2 * gm[9];
+      e[0] += s * snh_energy(F, gm[10], gm[11]);
+      if (grad) {
+        double P[3][3];
+        snh_stress(F, gm[10], gm[11], P);
+        double f0[3] = {0, 0, 0};
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
+        for (int cc = 0; cc < 3; ++cc) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          double acc = 0;
+          for (int a = 0; a < 3; ++a) {
+            double acc = 0;
 #pragma unroll
-          for (int b = 0; b < 3; ++b) acc += P[a][b] * Dmi[3 * cc + b];
-          acc *= s;
-          f0[a] -= acc;
-          atomicAdd(&g[3 * vi[cc + 1] + a], acc);
+            for (int b = 0; b < 3; ++b) acc += P[a][b] * Dmi[3 * cc + b];
+            acc *= s;
+            f0[a] -= acc;
+            sw_add(win, g, vbase, vi[cc + 1], a, acc);
+          }
         }
-      }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) atomicAdd(&g[3 * vi[0] + a], f0[a]);
+        for (int a = 0; a < 3; ++a) sw_add(win, g, vbase, vi[0], a, f0[a]);
+      }
+    }
+    if (grad) {
+      __syncthreads();
+      sw_flush(win, g, vbase, N);
+      __syncthreads();
     }
   }
   block_reduce_store<1>(e, part, nblk);
 }
 
-// kappa b(d) and kappa b'(d) grad d; a non-positive distance flags +inf
-__global__ __launch_bounds__(RB) void k_eg_contacts(int64_t m, const int32_t* idx, const double* d,
-                                                    const double* grad, double kappa, double dhat,
-                                                    double* g, double* part, int nblk) {
+// kappa b(d) and kappa b'(d) grad d; a non-positive distance flags +inf.
+// Chunks of SW_CHUNK stencils scatter through an LDS window (stencils sorted
+// by smallest vertex stay local).
+__global__ __launch_bounds__(RB) void k_eg_contacts(int64_t N, int64_t m, const int32_t* idx, const double* d,
+                                                    const double* grad, double kappa, double dhat, double* g,
+                                                    double* part, int nblk) {
+  __shared__ double win[3 * SW_WIN];
   double e[2] = {0.0, 0.0};
-  for (int64_t i = blockIdx.x * int64_t(RB) + threadIdx.x; i < m; i += int64_t(nblk) * RB) {
-    double di = d[i];
-    if (!(di > 0.0)) {
-      e[1] += 1.0;
-      continue;
+  const bool gr = g != nullptr;
+  for (int64_t chunk = blockIdx.x; chunk * SW_CHUNK < m; chunk += nblk) {
+    const int64_t c0 = chunk * SW_CHUNK;
+    int vbase;
+    {
+      const int4 f4 = reinterpret_cast<const int4*>(idx)[c0];
+      int mn = INT32_MAX;
+      if (f4.x >= 0) mn = min(mn, f4.x);
+      if (f4.y >= 0) mn = min(mn, f4.y);
+      if (f4.z >= 0) mn = min(mn, f4.z);
+      if (f4.w >= 0) mn = min(mn, f4.w);
+      vbase = (mn == INT32_MAX) ? 0 : mn;
     }
-    if (di >= dhat) continue;
-    double b, b1, b2;
-    barrier3(di, dhat, &b, &b1, &b2);
-    e[0] += kappa * b;
-    if (g) {
-      double s = kappa * b1;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int v = idx[4 * i + j];
-        if (v < 0) continue;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) atomicAdd(&g[3 * v + a], s * grad[12 * i + 3 * j + a]);
+    if (gr) {
+      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0;
+      __syncthreads();
+    }
+    for (int k = 0; k < SW_CHUNK; k += RB) {
+      const int64_t i = c0 + k + threadIdx.x;
+      if (i >= m) break;
+      const double di = d[i];
+      if (!(di > 0.0)) {
+        e[1] += 1.0;
+        continue;
       }
+      if (di >= dhat) continue;
+      double b, b1, b2;
+      barrier3(di, dhat, &b, &b1, &b2);
+      e[0] += kappa * b;
+      if (gr) {
+        const double s = kappa * b1;
+        const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+        const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (vi[j] < 0) continue;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) sw_add(win, g, vbase, vi[j], a, s * grad[12 * i + 3 * j + a]);
+        }
+      }
+    }
+    if (gr) {
+      __syncthreads();
+      sw_flush(win, g, vbase, N);
+      __syncthreads();
     }
   }
   block_reduce_store<2>(e, part, nblk);
@@ -154,12 +202,12 @@ mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const m
   const int nb = c.n_partial_blocks;
   double* part = c.partials;  // [0]: inertia [1]: elastic [2]: barrier [3]: infeasible count
   k_eg_vertices<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, c.mass, x, xt, g, part, nb);
-  k_eg_tets<<<dim3(nb), dim3(RB), 0, c.s>>>(c.T, c.tets, c.geo, x, c.cfg.h * c.cfg.h, g, part + nb, nb);
+  k_eg_tets<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, c.T, c.tets, c.geo, x, c.cfg.h * c.cfg.h, g, part + nb, nb);
   int64_t m = ct ? ct->m : 0;
   if (m > 0) {
     // writes part[2*nb..] (energy) and part[3*nb..] (infeasible count)
-    k_eg_contacts<<<dim3(nb), dim3(RB), 0, c.s>>>(m, ct->idx, ct->d, ct->grad, c.cfg.kappa, c.cfg.dhat, g,
-                                                   part + 2 * nb, nb);
+    k_eg_contacts<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, m, ct->idx, ct->d, ct->grad, c.cfg.kappa, c.cfg.dhat,
+                                                   g, part + 2 * nb, nb);
   } else {
     HIPCHK(hipMemsetAsync(part + 2 * nb, 0, sizeof(double) * 2 * nb, c.s));
   }
@@ -306,28 +354,32 @@ __global__ void k_alpha_init(int64_t D, double* alpha) {
 
 // alpha_c = min(1, 0.9 d / sum_j max(0, -grad_j . p_j)) to every subdomain
 // the stencil touches
-__global__ void k_alpha_stencils(int64_t m, const int32_t* idx, const double* grad, const double* d,
-                                 const double* p, double* alpha) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= m) return;
-  const int4 iv = reinterpret_cast<const int4*>(idx)[i];
-  int vi[4] = {iv.x, iv.y, iv.z, iv.w};
-  double s = 0;
+__global__ __launch_bounds__(256) void k_alpha_stencils(int64_t m, const int32_t* idx, const double* grad,
+                                                        const double* d, const double* p, double* alpha) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  int vi[4] = {-1, -1, -1, -1};
+  double a = INFINITY;
+  if (i < m) {
+    const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+    vi[0] = iv.x; vi[1] = iv.y; vi[2] = iv.z; vi[3] = iv.w;
+    double s = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (vi[j] < 0) continue;
-    double dot = 0;
+    for (int j = 0; j < 4; ++j) {
+      if (vi[j] < 0) continue;
+      double dot = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dot += grad[12 * i + 3 * j + a] * p[3 * vi[j] + a];
-    s += fmax(0.0, -dot);
+      for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
+      s += fmax(0.0, -dot);
+    }
+    if (s > 0.0) a = fmax(fmin(1.0, 0.9 * d[i] / s), 0.0);
   }
-  if (!(s > 0.0)) return;
-  double a = fmin(1.0, 0.9 * d[i] / s);
-  a = fmax(a, 0.0);
+  const bool has = a < 1.0;
+  if (__ballot(has) == 0) return;  // uniform
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (vi[j] < 0) continue;
-    atomic_min_pos(&alpha[vi[j] >> 5], a);
+    const int sd = vi[j] >> 5;
+    const long long key = (has && vi[j] >= 0) ? (long long)sd : -1ll;
+    wave_min_pos(key, alpha + (key >= 0 ? sd : 0), a);
   }
 }
 

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64) void k_topk(int K, const int32_t* off, const in
 }
 
 template <int P>
-__device__ inline double block_entry(const void* A, const float* sig, int i, int j) {
+__device__ __forceinline__ double block_entry(const unsigned char* A, const float* sig, int i, int j) {
   int e = pks(i, j);
   if (P == MAS_F64) return reinterpret_cast<const double*>(A)[e];
   if (P == MAS_F32) return double(reinterpret_cast<const float*>(A)[e]);
@@ -133,35 +133,11 @@ __device__ inline double block_entry(const void* A, const float* sig, int i, int
   return double(v) * double(sig[i]) * double(sig[j]);
 }
 
-// One workgroup per subdomain with rank r > 0: W = B_d U_d (96 x r, a gather
-// of at most 12 columns of B_d per column of U_d), C = I + U_d^T W, and the
-// float64 Cholesky factor of C.
+// W[:, j] = B_d u_j: a gather of at most 12 columns of B_d
 template <int P>
-__global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, const float* scale,
-                                                     const int32_t* rank, const SlotCol* slots, void* W,
-                                                     double* Lcap, uint32_t* err, DiagRec* dg) {
-  constexpr size_t E = blk_elems(P);
-  constexpr size_t ES = prec_size(P);
-  __shared__ __align__(16) unsigned char As[E * ES];
-  __shared__ float sig[BD];
-  __shared__ double Ws[MAXK][BD];
-  __shared__ double Cm[MAXK * MAXK];
-  __shared__ SlotCol sl[MAXK];
-  const int64_t d = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int r = rank[d];
-  if (r == 0) return;
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(blk) + d * E * ES);
-    uint4* dst = reinterpret_cast<uint4*>(As);
-    for (int q = tid; q < int(E * ES / 16); q += blockDim.x) dst[q] = src[q];
-  }
-  if (P == MAS_BF16 || P == MAS_F16) {
-    if (tid < BD) sig[tid] = scale[d * BD + tid];
-  }
-  for (int q = tid; q < r; q += blockDim.x) sl[q] = slots[d * K + q];
-  __syncthreads();
-  for (int q = tid; q < r * BD; q += blockDim.x) {
+__device__ __forceinline__ void gather_w(const unsigned char* As, const float* sig, const SlotCol* sl, int r,
+                                         double (*Ws)[BD]) {
+  for (int q = threadIdx.x; q < r * BD; q += blockDim.x) {
     int j = q / BD, i = q % BD;
     double acc = 0;
 #pragma unroll
@@ -172,6 +148,40 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
       for (int a = 0; a < 3; ++a) acc += block_entry<P>(As, sig, i, 3 * lv + a) * sl[j].u[3 * s + a];
     }
     Ws[j][i] = acc;
+  }
+}
+
+// One workgroup per subdomain with rank r > 0: W = B_d U_d (96 x r), the
+// capacitance C = I + U_d^T W and its float64 Cholesky factor.
+__global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, const uint8_t* bprec,
+                                                     const float* scale, const int32_t* rank, const SlotCol* slots,
+                                                     double* W, double* Lcap, uint32_t* err, DiagRec* dg) {
+  __shared__ __align__(16) unsigned char As[BLK_STRIDE];
+  __shared__ float sig[BD];
+  __shared__ double Ws[MAXK][BD];
+  __shared__ double Cm[MAXK * MAXK];
+  __shared__ SlotCol sl[MAXK];
+  const int64_t d = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int r = rank[d];
+  if (r == 0) return;
+  const int P = bprec[d];
+  {
+    const int nbytes = int(blk_elems(P) * prec_size(P));
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(blk) + d * BLK_STRIDE);
+    uint4* dst = reinterpret_cast<uint4*>(As);
+    for (int q = tid; q < nbytes / 16; q += blockDim.x) dst[q] = src[q];
+  }
+  if (P == MAS_BF16 || P == MAS_F16) {
+    if (tid < BD) sig[tid] = scale[d * BD + tid];
+  }
+  for (int q = tid; q < r; q += blockDim.x) sl[q] = slots[d * K + q];
+  __syncthreads();
+  switch (P) {
+    case MAS_F64: gather_w<MAS_F64>(As, sig, sl, r, Ws); break;
+    case MAS_F32: gather_w<MAS_F32>(As, sig, sl, r, Ws); break;
+    case MAS_BF16: gather_w<MAS_BF16>(As, sig, sl, r, Ws); break;
+    default: gather_w<MAS_F16>(As, sig, sl, r, Ws);
   }
   __syncthreads();
   for (int q = tid; q < r * r; q += blockDim.x) {
@@ -213,8 +223,7 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
   }
   for (int q = tid; q < r * BD; q += blockDim.x) {
     int j = q / BD, i = q % BD;
-    if (P == MAS_F64) reinterpret_cast<double*>(W)[(d * K + j) * BD + i] = Ws[j][i];
-    else reinterpret_cast<float*>(W)[(d * K + j) * BD + i] = float(Ws[j][i]);
+    W[(d * K + j) * BD + i] = Ws[j][i];
   }
 }
 
@@ -254,23 +263,8 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
                                         c.sel, c.slots, rank_hist);
   Level& L0 = c.lv[0];
   ProfScope pc(c, MAS_T_CAPACITANCE);
-  switch (L0.prec) {
-    case MAS_F64:
-      k_capacitance<MAS_F64><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                             c.Lcap, c.err, c.diag);
-      break;
-    case MAS_F32:
-      k_capacitance<MAS_F32><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                             c.Lcap, c.err, c.diag);
-      break;
-    case MAS_BF16:
-      k_capacitance<MAS_BF16><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                              c.Lcap, c.err, c.diag);
-      break;
-    default:
-      k_capacitance<MAS_F16><<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.scale, c.rank, c.slots, c.W,
-                                                             c.Lcap, c.err, c.diag);
-  }
+  k_capacitance<<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.bprec, L0.scale, c.rank, c.slots, c.W, c.Lcap,
+                                                c.err, c.diag);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -28,7 +28,7 @@ class PNCG:
         self.ctx = ctx = MasContext(scene, cfg, device=device)
         self.scene = scene
         self.max_halvings = max_halvings
-        self.pool = ctx.contacts(scene.pool)
+        self.pool = ctx.contacts(scene.pool, sort=True)
         # a second view of the pool with its own distance array for trial points
         self.pool_t = DeviceContacts.__new__(DeviceContacts)
         self.pool_t.__dict__.update(self.pool.__dict__)
@@ -50,12 +50,16 @@ class PNCG:
         self.n_halvings = 0
         self.log = []
         self.g0norm = None
+        self.track_precisions = False
+        self.precision_counts = None
 
     def iterate(self):
         ctx = self.ctx
         if self.restart:
             ctx.build(self.x, self.pool)
             self.n_restarts += 1
+            if self.track_precisions:
+                self.precision_counts = ctx.block_precisions(0)
         else:
             ctx.woodbury_update(self.pool, self.rank_hist)
         ctx.apply(self.g, self.z)

@@ -238,6 +238,9 @@ def test_apply_after_rebuild_without_update(case):
 def test_low_precision_blocks(prec, tol):
     print("\n[parity case] grid %s" % prec, flush=True)
     c = grid_case(prec)
+    counts = c.ctx.block_precisions(0)
+    print("stored block precisions", counts)
+    assert sum(counts.values()) == c.hier.num_subdomains(0)
     rng = np.random.default_rng(8)
     g = rng.standard_normal(3 * c.scene.N)
     zo = c.M.apply(g, c.blocks)
@@ -250,4 +253,57 @@ def test_low_precision_blocks(prec, tol):
     yo = c.H @ v + c.U @ (c.U.T @ v)
     y = c.ctx.from_lib(c.ctx.hess_vec(c.ctx.to_lib(v), with_update=True))
     assert rel(y, yo) < 1e-5
+    c.ctx.close()
+
+
+def stiff_case(prec, guard):
+    """Grid scene whose contacts sit at d ~ 1e-9 (barrier stiffness ~1e9 x
+    the vertex mass): inverse blocks far beyond float32 resolution."""
+    import torch
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    sc = synth.grid_scene()
+    base, curr = synth.grid_update_sets(sc)
+    base = dict(base)
+    curr = dict(curr)
+    # stiff contacts only on vertices of the first eight Morton subdomains
+    rank = np.empty(sc.N, np.int64)
+    rank[mas.morton_perm(sc.X)] = np.arange(sc.N)
+    low_b = rank[base['idx'][:, 0]] < 256
+    low_c = rank[curr['idx'][:, 0]] < 256
+    base['d'] = np.where(low_b, 2e-9, base['d'])
+    curr['d'] = np.where(low_c & (curr['d'] < 5e-4), 1e-9, curr['d'])
+    case = Case.__new__(Case)
+    case.scene, case.base, case.curr = sc, base, curr
+    prob = fem.Problem(sc)
+    hier = mas.Hierarchy(sc.X, 2)
+    case.prob, case.hier = prob, hier
+    case.H = prob.assemble(sc.x, base)
+    case.M = mas.MAS(hier, case.H)
+    case.dS, case.u, case.case = woodbury.classify(prob, base, curr)
+    case.sel = woodbury.topk(hier, curr, case.dS, case.u, 8)
+    case.blocks = woodbury.updated_blocks(hier, case.H, curr, case.u, case.sel)
+    case.ctx = MasContext(sc, make_config(sc, levels=2, K=8, block_prec=prec, prec_guard=guard))
+    case.x = case.ctx.to_lib(sc.x)
+    case.ctx.build(case.x, case.ctx.contacts(base))
+    case.ctx.woodbury_update(case.ctx.contacts(curr))
+    case.torch = torch
+    return case
+
+
+def test_stiff_blocks_are_promoted_and_stay_definite():
+    print("\n[parity case] grid stiff f32 guarded", flush=True)
+    c = stiff_case("f32", 0.5)
+    code, msg = c.ctx.sync()
+    assert code == 0, msg
+    counts = c.ctx.block_precisions(0)
+    print("stored block precisions", counts)
+    assert counts["f64"] > 0 and counts["f32"] > 0
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(3 * c.scene.N)
+    zo = c.M.apply(g, c.blocks)
+    zg = c.ctx.from_lib(c.ctx.apply(c.ctx.to_lib(g)))
+    assert rel(zg, zo) < 1e-5, rel(zg, zo)
+    a = rng.standard_normal(3 * c.scene.N)
+    Pa = c.ctx.from_lib(c.ctx.apply(c.ctx.to_lib(a)))
+    assert a @ Pa > 0
     c.ctx.close()
