@@ -98,6 +98,11 @@ static mas_status grow_base(Ctx& c, int64_t m) {
   int64_t cap = m + m / 4 + 1024;
   hipFree(c.bkey); hipFree(c.bkey_sorted); hipFree(c.biota); hipFree(c.bperm);
   hipFree(c.bk); hipFree(c.bgrad); hipFree(c.bidx); hipFree(c.bu); hipFree(c.bc_list);
+  for (int l = 1; l < c.L; ++l) {
+    hipFree(c.lv[l].xc_list);
+    c.lv[l].xc_list = nullptr;
+    if (hipMalloc(&c.lv[l].xc_list, 16 * cap) != hipSuccess) return MAS_ERR_OOM;
+  }
   bool ok = hipMalloc(&c.bkey, 8 * cap) == hipSuccess && hipMalloc(&c.bkey_sorted, 8 * cap) == hipSuccess &&
             hipMalloc(&c.biota, 4 * cap) == hipSuccess && hipMalloc(&c.bperm, 4 * cap) == hipSuccess &&
             hipMalloc(&c.bk, 8 * cap) == hipSuccess && hipMalloc(&c.bgrad, 96 * cap) == hipSuccess &&
@@ -122,7 +127,14 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
     st = sort_keys(c, m, c.bkey, c.bkey_sorted, c.biota, c.bperm);
     if (st != MAS_OK) return st;
   }
-  return bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
+  st = bucket_by_subdomain(c, 0, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
+  if (st != MAS_OK) return st;
+  for (int l = 1; l < c.L; ++l) {
+    Level& Lv = c.lv[l];
+    st = bucket_by_subdomain(c, l, m, c.bidx, c.bk, c.bgrad, Lv.xc_cnt, Lv.xc_off, Lv.xc_list);
+    if (st != MAS_OK) return st;
+  }
+  return MAS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -288,54 +300,47 @@ __device__ inline void add_block_lds(double* A, int li, int lj, bool diag, const
   }
 }
 
-__device__ inline void add_block_global(double* A, int li, int lj, bool diag, const double b[3][3]) {
-  if (diag) {
+// Sum of the 3x3 blocks of a packed symmetric block (rows of nodes >= valid
+// excluded): the diagonal block of the level-(l+1) node the subdomain forms,
+// since C_(l+1) = C_hat C_(l) sums node blocks (supplement Eq. (3)).
+__device__ __forceinline__ void block_node_sum(const double* A, int valid, double* out9) {
+  __shared__ double red[9][4];
+  double s9[9];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+  for (int q = 0; q < 9; ++q) s9[q] = 0.0;
+  for (int e = threadIdx.x; e < PK; e += blockDim.x) {
+    int i = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    while (i * (i + 1) / 2 > e) --i;
+    const int j = e - i * (i + 1) / 2;
+    if (i / 3 >= valid || j / 3 >= valid) continue;
+    const double v = A[e];
+    const int a = i % 3, b = j % 3;
 #pragma unroll
-      for (int q = 0; q <= a; ++q) atomicAdd(&A[pk(3 * li + a, 3 * li + q)], b[a][q]);
-  } else if (li > lj) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * li + a, 3 * lj + q)], b[a][q]);
-  } else {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * lj + q, 3 * li + a)], b[a][q]);
+    for (int q = 0; q < 9; ++q) {
+      if (q == 3 * a + b) s9[q] += v;
+      if (i != j && q == 3 * b + a) s9[q] += v;
+    }
   }
-}
-
-// add a 3x3 block to a packed-lower global matrix after summing it over the
-// lanes of the wavefront with the same key (see wave_min_pos)
-__device__ __forceinline__ void wave_add_block(long long key, double* A, int li, int lj, bool diag,
-                                               const double (&b)[3][3]) {
-  const int lane = threadIdx.x & 63;
-  bool pending = key >= 0;
-  while (true) {
-    const unsigned long long act = __ballot(pending);
-    if (act == 0) break;
-    const int leader = __ffsll((unsigned long long)act) - 1;
-    const long long lk = __shfl(key, leader);
-    const bool mine = pending && key == lk;
-    double t[3][3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) t[a][q] = wave_sum(mine ? b[a][q] : 0.0);
-    if (lane == leader) add_block_global(A, li, lj, diag, t);
-    if (mine) pending = false;
+  for (int q = 0; q < 9; ++q) {
+    const double t = wave_sum(s9[q]);
+    if (lane == 0) red[q][w] = t;
   }
+  __syncthreads();
+  if (threadIdx.x < 9) out9[threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
+                                           red[threadIdx.x][3];
 }
 
 // ---------------------------------------------------------------------------
 // Level 0: one workgroup per subdomain d accumulates S_d H_base S_d^T in LDS
 // (mass, every tet touching d, every base contact touching d) and writes it
-// packed in float64 to the assembly buffer; k_invert_blocks inverts it.
-// Each work item is one (tet, vertex pair) so few values stay live.
+// packed in float64 to the assembly buffer.  Tets are staged through LDS in
+// batches; each work item is then one (tet, vertex pair).
 __constant__ int8_t c_pair_i[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
 __constant__ int8_t c_pair_j[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
+constexpr int TB = 24;  // tets staged per batch
 
 __global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* tets, const double* mass,
                                                      const double* hf64, const int32_t* tet_off,
@@ -344,6 +349,8 @@ __global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* t
                                                      const int32_t* bc_off, const int32_t* bc_list,
                                                      double* acc) {
   __shared__ double A[PK];
+  __shared__ double snap[TB][EH];
+  __shared__ int32_t tv[TB][4];
   const int64_t d = blockIdx.x;
   const int tid = threadIdx.x;
   for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
@@ -352,36 +359,49 @@ __global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* t
     int64_t v = SUB * d + tid / 3;
     A[pk(tid, tid)] = (v < N) ? mass[v] : 1.0;
   }
-  __syncthreads();
   const int t0 = tet_off[d], nt = tet_off[d + 1] - t0;
-  for (int w = tid; w < 10 * nt; w += blockDim.x) {
-    const int64_t t = tet_list[t0 + w / 10];
-    const int pr = w % 10;
-    const int i = c_pair_i[pr], j = c_pair_j[pr];
-    const int vi = tets[4 * t + i], vj = tets[4 * t + j];
-    if ((vi >> 5) != d || (vj >> 5) != d) continue;
-    double H[45], Dmi[9], coef[4][3];
-    load_snapshot(hf64, t, H, Dmi);
-    dfdx_coef(Dmi, coef);
-    double ci[3], cj[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      ci[b] = (i == 0) ? coef[0][b] : (i == 1) ? coef[1][b] : (i == 2) ? coef[2][b] : coef[3][b];
-      cj[b] = (j == 0) ? coef[0][b] : (j == 1) ? coef[1][b] : (j == 2) ? coef[2][b] : coef[3][b];
+  for (int b0 = 0; b0 < nt; b0 += TB) {
+    const int nb = min(TB, nt - b0);
+    __syncthreads();
+    for (int q = tid; q < nb * EH; q += blockDim.x) {
+      const int k = q / EH, c = q % EH;
+      const int64_t t = tet_list[t0 + b0 + k];
+      snap[k][c] = hf64[(t / TILE) * (EH * TILE) + c * TILE + (t % TILE)];
     }
-    double blk[3][3];
+    if (tid < 4 * nb) {
+      const int k = tid / 4;
+      tv[k][tid % 4] = tets[4 * int64_t(tet_list[t0 + b0 + k]) + tid % 4];
+    }
+    __syncthreads();
+    for (int w = tid; w < 10 * nb; w += blockDim.x) {
+      const int k = w / 10, pr = w % 10;
+      const int i = c_pair_i[pr], j = c_pair_j[pr];
+      const int vi = tv[k][i], vj = tv[k][j];
+      if ((vi >> 5) != d || (vj >> 5) != d) continue;
+      const double* H = snap[k];
+      const double* Dmi = snap[k] + 45;
+      double coef[4][3];
+      dfdx_coef(Dmi, coef);
+      double ci[3], cj[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int ap = 0; ap < 3; ++ap) {
-        double s = 0;
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-          for (int bp = 0; bp < 3; ++bp) s += ci[b] * H[p9(3 * b + a, 3 * bp + ap)] * cj[bp];
-        blk[a][ap] = s;
+      for (int b = 0; b < 3; ++b) {
+        ci[b] = (i == 0) ? coef[0][b] : (i == 1) ? coef[1][b] : (i == 2) ? coef[2][b] : coef[3][b];
+        cj[b] = (j == 0) ? coef[0][b] : (j == 1) ? coef[1][b] : (j == 2) ? coef[2][b] : coef[3][b];
       }
-    add_block_lds(A, vi & 31, vj & 31, i == j, blk);
+      double blk[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int ap = 0; ap < 3; ++ap) {
+          double sum = 0;
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int bp = 0; bp < 3; ++bp) sum += ci[b] * H[p9(3 * b + a, 3 * bp + ap)] * cj[bp];
+          blk[a][ap] = sum;
+        }
+      add_block_lds(A, vi & 31, vj & 31, i == j, blk);
+    }
   }
   const int c0 = bc_off[d], nc = bc_off[d + 1] - c0;
   for (int w = tid; w < 10 * nc; w += blockDim.x) {
@@ -411,7 +431,7 @@ __global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* t
 // and 1/kappa bounds its smallest eigenvalue from above.
 __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const double* acc, void* blk, float* scale,
                                                        uint8_t* bprec, int req, double guard, uint32_t* err,
-                                                       DiagRec* dg, int level) {
+                                                       DiagRec* dg, int level, double* ndiag_next) {
   __shared__ double A[PK];
   __shared__ double colbuf[2][BD];
   __shared__ double mdiag[BD];
@@ -427,6 +447,7 @@ __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const doub
     mdiag[threadIdx.x] = A[pk(threadIdx.x, threadIdx.x)];
   }
   __syncthreads();
+  if (ndiag_next) block_node_sum(A, int(min<int64_t>(SUB, nodes - SUB * d)), ndiag_next + 9 * d);
   spd_invert_lds(A, colbuf, err, dg, level == 0 ? 1 : 2, level, d);
   if (threadIdx.x < 64) {
     double k1 = mdiag[threadIdx.x] * A[pk(threadIdx.x, threadIdx.x)];
@@ -455,7 +476,8 @@ __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const doub
 static void launch_invert(Ctx& c, int l) {
   Level& Lv = c.lv[l];
   k_invert_blocks<<<dim3(Lv.nsub), dim3(256), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, Lv.bprec, Lv.prec,
-                                                         c.cfg.prec_guard, c.err, c.diag, l);
+                                                         c.cfg.prec_guard, c.err, c.diag, l,
+                                                         l + 1 < c.L ? c.lv[l + 1].ndiag : nullptr);
 }
 
 mas_status launch_level0_build(Ctx& c) {
@@ -468,206 +490,202 @@ mas_status launch_level0_build(Ctx& c) {
 }
 
 // ---------------------------------------------------------------------------
-// Coarse levels.  A_(l) = C_(l) H_base C_(l)^T: a term S_e^T H_e S_e restricted
-// to level-l nodes sums the coefficients of vertices that share a node, so
-// the element contributes  chat_s^T Hf chat_t  per node pair (s, t), where
-// chat_s = sum of dF/dx coefficients of its vertices in node s.  Elements whose
-// vertices all share one node contribute nothing (translations are in the
-// kernel of H_e); the same holds for contacts through nhat_s = sum of n_j.
+// Coarse level l: A_(l) = C_(l) H_base C_(l)^T on the 32 nodes of each
+// level-l subdomain S.  The diagonal node blocks come from the level below
+// (block sums taken while inverting it).  The rest are pairs of different
+// nodes of S, which only tets and base contacts with at least two nodes in S
+// produce: a tet contributes chat_s^T Hf chat_u, where chat_s sums the dF/dx
+// coefficients of its vertices in node s; a contact k nhat_s nhat_u^T with
+// nhat_s the sum of its n_j in node s.  The items of S are split over
+// `splits` workgroups that accumulate in LDS (one LDS atomic per distinct
+// node pair and wavefront) and add their nonzero entries to the block.
 
-struct CoarseArgs {
-  int L;                    // number of levels
-  double* const* acc;       // device array: packed f64 assembly per level
-};
-
-__global__ __launch_bounds__(256) void k_coarse_tets(int64_t T, const int32_t* tets, const double* hf64, CoarseArgs ca) {
-  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  int v[4] = {0, 0, 0, 0};
-  if (t < T) {
+// adds b (node pair ls > lu) to A, summed over the lanes of the wavefront with
+// the same pair first; key < 0: nothing to add.  Uniform control flow.
+__device__ __forceinline__ void wave_add_pair(double* A, int key, const double (&b)[3][3]) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const unsigned long long act = __ballot(key >= 0);
+    if (act == 0) break;
+    const int leader = __ffsll(act) - 1;
+    const int lk = __shfl(key, leader);
+    const bool mine = key == lk;
+    double t[3][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = tets[4 * t + j];
-  }
-  // vertices sharing a level-1 node share every coarser node as well
-  const bool live = t < T && !((v[0] >> 5) == (v[1] >> 5) && (v[0] >> 5) == (v[2] >> 5) &&
-                               (v[0] >> 5) == (v[3] >> 5));
-  if (__ballot(live) == 0) return;  // uniform: the whole wavefront is done
-  double H[45], Dmi[9], coef[4][3];
-  if (live) {
-    load_snapshot(hf64, t, H, Dmi);
-  } else {
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int q = 0; q < 45; ++q) H[q] = 0.0;
+      for (int q = 0; q < 3; ++q) t[a][q] = wave_sum(mine ? b[a][q] : 0.0);
+    if (lane == leader) {
+      const int ls = lk >> 5, lu = lk & 31;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) Dmi[q] = 0.0;
-  }
-  dfdx_coef(Dmi, coef);
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-  for (int l = 1; l < MAXL; ++l) {
-    if (l >= ca.L) break;  // uniform
-    int nd[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) nd[j] = v[j] >> (5 * l);
-    const bool lv_live = live && !(nd[0] == nd[1] && nd[0] == nd[2] && nd[0] == nd[3]);
-    if (__ballot(lv_live) == 0) break;  // uniform
-    int lead[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      lead[j] = j;
-#pragma unroll
-      for (int i = 3; i >= 0; --i)
-        if (i < j && nd[i] == nd[j]) lead[j] = i;
+        for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * ls + a, 3 * lu + q)], t[a][q]);
     }
-    double ch[4][3];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        double acc = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (lead[j] == s) acc += coef[j][b];
-        ch[s][b] = acc;
-      }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int u = 0; u <= s; ++u) {
-        const int a_s = nd[s], a_u = nd[u];
-        const bool ok = lv_live && lead[s] == s && lead[u] == u && (a_s >> 5) == (a_u >> 5);
-        double b[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int ap = 0; ap < 3; ++ap) {
-            double acc = 0;
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-              for (int bp = 0; bp < 3; ++bp) acc += ch[s][bb] * H[p9(3 * bb + a, 3 * bp + ap)] * ch[u][bp];
-            b[a][ap] = acc;
-          }
-        const long long key = ok ? ((long long)(a_s >> 5) << 10 | (a_s & 31) << 5 | (a_u & 31)) : -1ll;
-        wave_add_block(key, ca.acc[l] + int64_t(a_s >> 5) * PK, a_s & 31, a_u & 31, s == u, b);
-      }
+    if (mine) key = -1;
   }
 }
 
-__global__ __launch_bounds__(256) void k_coarse_contacts(int64_t m, const double* bk, const double* bgrad,
-                                                         const int32_t* bidx, CoarseArgs ca) {
-  const int64_t ci = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  double k = 0.0;
-  int v[4] = {-1, -1, -1, -1};
-  double n[12];
+// the first index j' <= j of a stencil vertex in the same node as j
+__device__ __forceinline__ void node_leaders(const int (&nd)[4], int (&lead)[4]) {
 #pragma unroll
-  for (int q = 0; q < 12; ++q) n[q] = 0.0;
-  if (ci < m) {
-    k = bk[ci];
+  for (int j = 0; j < 4; ++j) {
+    lead[j] = j;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = bidx[4 * ci + j];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) n[q] = bgrad[12 * ci + q];
+    for (int i = 3; i >= 0; --i)
+      if (i < j && nd[i] == nd[j]) lead[j] = i;
   }
-  // A stencil whose vertices share one level-1 node contributes k nhat nhat^T
-  // with nhat = sum_j n_j; for translation-invariant stencils (point-triangle,
-  // edge-edge) nhat vanishes up to rounding, so the term is skipped.
-  bool live = ci < m && k > 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_assemble_coarse(int l, int64_t nodes, int splits, const double* ndiag,
+                                                         const int32_t* tets, const double* hf64,
+                                                         const int32_t* xt_off, const int32_t* xt_list,
+                                                         const double* bk, const double* bgrad, const int32_t* bidx,
+                                                         const int32_t* xc_off, const int32_t* xc_list,
+                                                         double* acc) {
+  __shared__ double A[PK];
+  const int64_t S = blockIdx.x;
+  const int part = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int ns = 5 * l;
+  for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
+  __syncthreads();
+  if (part == 0 && tid < SUB) {
+    const int64_t a = SUB * S + tid;
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int y = 0; y <= x; ++y)
+        A[pk(3 * tid + x, 3 * tid + y)] = (a < nodes) ? ndiag[9 * a + 3 * x + y] : (x == y ? 1.0 : 0.0);
+  }
+  __syncthreads();
   {
-    int n1 = -1;
-    bool same = true;
-    double nh[3] = {0, 0, 0}, nn = 0;
+    const int o = xt_off[S], n = xt_off[S + 1] - o;
+    const int lo = o + int(int64_t(n) * part / splits), hi = o + int(int64_t(n) * (part + 1) / splits);
+    for (int w0 = lo; w0 < hi; w0 += blockDim.x) {
+      const int w = w0 + tid;
+      const bool ok = w < hi;
+      const int64_t t = ok ? xt_list[w] : 0;
+      int nd[4], lead[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (v[j] < 0) continue;
-      if (n1 < 0) n1 = v[j] >> 5;
-      same &= (v[j] >> 5) == n1;
+      for (int j = 0; j < 4; ++j) nd[j] = ok ? (tets[4 * t + j] >> ns) : -1;
+      node_leaders(nd, lead);
+      double H[45], Dmi[9], coef[4][3];
+      load_snapshot(hf64, t, H, Dmi);
+      dfdx_coef(Dmi, coef);
+      double ch[4][3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        nh[a] += n[3 * j + a];
-        nn += n[3 * j + a] * n[3 * j + a];
-      }
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          double sum = 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (lead[j] == s) sum += coef[j][b];
+          ch[s][b] = sum;
+        }
+#pragma unroll
+      for (int s = 1; s < 4; ++s)
+#pragma unroll
+        for (int u = 0; u < s; ++u) {
+          const bool act = ok && lead[s] == s && lead[u] == u && (nd[s] >> 5) == S && (nd[u] >> 5) == S;
+          const int ls = nd[s] & 31, lu = nd[u] & 31;
+          const bool sw = ls < lu;  // store the pair with the larger local node first
+          double b[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int ap = 0; ap < 3; ++ap) {
+              double sum = 0;
+#pragma unroll
+              for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int bp = 0; bp < 3; ++bp) sum += ch[s][bb] * H[p9(3 * bb + a, 3 * bp + ap)] * ch[u][bp];
+              b[a][ap] = sum;
+            }
+          if (sw) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int q = 0; q < a; ++q) {
+                const double x = b[a][q];
+                b[a][q] = b[q][a];
+                b[q][a] = x;
+              }
+          }
+          wave_add_pair(A, act ? (sw ? (lu << 5) | ls : (ls << 5) | lu) : -1, b);
+        }
     }
-    if (same && nh[0] * nh[0] + nh[1] * nh[1] + nh[2] * nh[2] <= 1e-24 * nn) live = false;
   }
-  if (__ballot(live) == 0) return;  // uniform
+  {
+    const int o = xc_off[S], n = xc_off[S + 1] - o;
+    const int lo = o + int(int64_t(n) * part / splits), hi = o + int(int64_t(n) * (part + 1) / splits);
+    for (int w0 = lo; w0 < hi; w0 += blockDim.x) {
+      const int w = w0 + tid;
+      const bool ok = w < hi;
+      const int64_t ci = ok ? xc_list[w] : 0;
+      const double k = ok ? bk[ci] : 0.0;
+      const double* n = bgrad + 12 * ci;
+      int v[4], nd[4], lead[4];
 #pragma unroll
-  for (int l = 1; l < MAXL; ++l) {
-    if (l >= ca.L) break;  // uniform
-    int nd[4];
+      for (int j = 0; j < 4; ++j) {
+        v[j] = ok ? bidx[4 * ci + j] : -1;
+        nd[j] = v[j] >= 0 ? (v[j] >> ns) : -1 - j;
+      }
+      node_leaders(nd, lead);
+      double nh[4][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) nd[j] = v[j] >= 0 ? (v[j] >> (5 * l)) : -1 - j;
-    int lead[4];
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      lead[j] = j;
+        for (int a = 0; a < 3; ++a) {
+          double sum = 0;
 #pragma unroll
-      for (int i = 3; i >= 0; --i)
-        if (i < j && nd[i] == nd[j]) lead[j] = i;
+          for (int j = 0; j < 4; ++j)
+            if (lead[j] == s && v[j] >= 0) sum += n[3 * j + a];
+          nh[s][a] = sum;
+        }
+#pragma unroll
+      for (int s = 1; s < 4; ++s)
+#pragma unroll
+        for (int u = 0; u < s; ++u) {
+          const bool act = lead[s] == s && lead[u] == u && v[s] >= 0 && v[u] >= 0 && (nd[s] >> 5) == S &&
+                           (nd[u] >> 5) == S;
+          const int ls = nd[s] & 31, lu = nd[u] & 31;
+          const bool sw = ls < lu;
+          double b[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) b[a][q] = sw ? k * nh[u][a] * nh[s][q] : k * nh[s][a] * nh[u][q];
+          wave_add_pair(A, act ? (sw ? (lu << 5) | ls : (ls << 5) | lu) : -1, b);
+        }
     }
-    double nh[4][3];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double acc = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (lead[j] == s && v[j] >= 0) acc += n[3 * j + a];
-        nh[s][a] = acc;
-      }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int u = 0; u <= s; ++u) {
-        const int a_s = nd[s], a_u = nd[u];
-        const bool ok = live && lead[s] == s && lead[u] == u && v[s] >= 0 && v[u] >= 0 &&
-                        (a_s >> 5) == (a_u >> 5);
-        double b[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int q = 0; q < 3; ++q) b[a][q] = k * nh[s][a] * nh[u][q];
-        const long long key = ok ? ((long long)(a_s >> 5) << 10 | (a_s & 31) << 5 | (a_u & 31)) : -1ll;
-        wave_add_block(key, ca.acc[l] + int64_t(ok ? (a_s >> 5) : 0) * PK, a_s & 31, a_u & 31, s == u, b);
-      }
+  }
+  __syncthreads();
+  double* out = acc + S * PK;
+  if (splits == 1) {
+    for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
+  } else {
+    for (int e = tid; e < PK; e += blockDim.x)
+      if (A[e] != 0.0) unsafeAtomicAdd(&out[e], A[e]);
   }
 }
 
-// node masses of level l from level l-1 (or vertex) masses; adds them to the
-// diagonal of the level-l accumulation
-__global__ void k_coarse_mass(int64_t nodes, int64_t child_n, const double* child_mass,
-                              double* node_mass, double* acc) {
-  int64_t a = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (a >= nodes) return;
-  double s = 0;
-  for (int64_t q = SUB * a; q < SUB * a + SUB && q < child_n; ++q) s += child_mass[q];
-  node_mass[a] = s;
-  double* A = acc + (a >> 5) * PK;
-  int la = int(a & 31);
-#pragma unroll
-  for (int c3 = 0; c3 < 3; ++c3) A[pk(3 * la + c3, 3 * la + c3)] += s;
+__global__ void k_zero(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
 }
 
 mas_status launch_coarse_build(Ctx& c) {
-  if (c.L < 2) return MAS_OK;
-  CoarseArgs ca{};
-  ca.L = c.L;
-  ca.acc = c.acc_ptrs;
-  for (int l = 1; l < c.L; ++l)
-    HIPCHK(hipMemsetAsync(c.lv[l].acc, 0, sizeof(double) * PK * c.lv[l].nsub, c.s));
-  // masses: level-1 nodes from vertices, then upward; r buffers hold node masses
-  const double* child = c.mass;
-  int64_t child_n = c.N;
   for (int l = 1; l < c.L; ++l) {
-    int64_t nodes = c.lv[l].nodes;
-    k_coarse_mass<<<dim3((nodes + 255) / 256), dim3(256), 0, c.s>>>(nodes, child_n, child, c.lv[l].r,
-                                                                   c.lv[l].acc);
-    child = c.lv[l].r;
-    child_n = nodes;
+    Level& Lv = c.lv[l];
+    const int sp = Lv.splits;
+    if (sp > 1) k_zero<<<dim3(1024), dim3(256), 0, c.s>>>(Lv.acc, Lv.nsub * PK);
+    k_assemble_coarse<<<dim3(Lv.nsub, sp), dim3(256), 0, c.s>>>(l, Lv.nodes, sp, Lv.ndiag, c.tets, c.hf64,
+                                                                Lv.xt_off, Lv.xt_list, c.bk, c.bgrad, c.bidx,
+                                                                Lv.xc_off, Lv.xc_list, Lv.acc);
+    launch_invert(c, l);
   }
-  k_coarse_tets<<<dim3((c.T + 255) / 256), dim3(256), 0, c.s>>>(c.T, c.tets, c.hf64, ca);
-  if (c.mb > 0)
-    k_coarse_contacts<<<dim3((c.mb + 255) / 256), dim3(256), 0, c.s>>>(c.mb, c.bk, c.bgrad, c.bidx, ca);
-  for (int l = 1; l < c.L; ++l) launch_invert(c, l);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -5,43 +5,95 @@
 
 namespace mas {
 
-// distinct level-0 subdomains of stencil i that carry a nonzero part of the
-// 12-vector vec (only when w[i] > 0); returns count, writes them to out[4]
-__device__ inline int stencil_buckets(int64_t i, const int32_t* idx, const double* w,
+// subdomains of stencil i at a level (see bucket_by_subdomain); returns the
+// count and writes them to out[4]
+__device__ inline int stencil_buckets(int level, int64_t i, const int32_t* idx, const double* w,
                                       const double* vec12, int out[4]) {
   int n = 0;
   if (!(w[i] > 0.0)) return 0;
+  int v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = idx[4 * i + j];
+  if (level == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (v[j] < 0) continue;
+      const double* u = vec12 + 12 * i + 3 * j;
+      if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
+      int d = v[j] >> 5;
+      bool dup = false;
+      for (int q = 0; q < n; ++q) dup |= (out[q] == d);
+      if (!dup) out[n++] = d;
+    }
+    return n;
+  }
+  const int ns = 5 * level, ss = 5 * (level + 1);
+#pragma unroll
   for (int j = 0; j < 4; ++j) {
-    int v = idx[4 * i + j];
-    if (v < 0) continue;
-    const double* u = vec12 + 12 * i + 3 * j;
-    if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
-    int d = v >> 5;
+    if (v[j] < 0) continue;
+    const int S = v[j] >> ss;
     bool dup = false;
-    for (int q = 0; q < n; ++q) dup |= (out[q] == d);
-    if (!dup) out[n++] = d;
+    for (int q = 0; q < n; ++q) dup |= (out[q] == S);
+    if (dup) continue;
+    // a second, different node of the stencil inside S?
+    bool two = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (v[k] >= 0 && (v[k] >> ss) == S && (v[k] >> ns) != (v[j] >> ns)) two = true;
+    if (two) out[n++] = S;
   }
   return n;
 }
 
-__global__ void k_bucket_count(int64_t m, const int32_t* idx, const double* w, const double* vec12,
-                               int32_t* cnt) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= m) return;
+// Counting and filling aggregate over the wavefront: lanes with the same
+// bucket share one atomic (stencils arrive sorted by their smallest vertex,
+// so neighbouring lanes mostly share buckets, which at coarse levels are
+// few).  Every lane runs the loops, including those past the end.
+__global__ __launch_bounds__(256) void k_bucket_count(int level, int64_t m, const int32_t* idx, const double* w,
+                                                      const double* vec12, int32_t* cnt) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   int b[4];
-  int n = stencil_buckets(i, idx, w, vec12, b);
-  for (int q = 0; q < n; ++q) atomicAdd(&cnt[b[q]], 1);
+  const int n = (i < m) ? stencil_buckets(level, i, idx, w, vec12, b) : 0;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int key = q < n ? b[q] : -1;
+    while (true) {
+      const unsigned long long act = __ballot(key >= 0);
+      if (act == 0) break;
+      const int leader = __ffsll(act) - 1;
+      const int lk = __shfl(key, leader);
+      const unsigned long long match = __ballot(key == lk);
+      if (lane == leader) atomicAdd(&cnt[lk], __popcll(match));
+      if (key == lk) key = -1;
+    }
+  }
 }
 
-__global__ void k_bucket_fill(int64_t m, const int32_t* idx, const double* w, const double* vec12,
-                              int32_t* cursor, int32_t* list) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= m) return;
+__global__ __launch_bounds__(256) void k_bucket_fill(int level, int64_t m, const int32_t* idx, const double* w,
+                                                     const double* vec12, int32_t* cursor, int32_t* list) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   int b[4];
-  int n = stencil_buckets(i, idx, w, vec12, b);
-  for (int q = 0; q < n; ++q) {
-    int pos = atomicAdd(&cursor[b[q]], 1);
-    list[pos] = int32_t(i);
+  const int n = (i < m) ? stencil_buckets(level, i, idx, w, vec12, b) : 0;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int key = q < n ? b[q] : -1;
+    while (true) {
+      const unsigned long long act = __ballot(key >= 0);
+      if (act == 0) break;
+      const int leader = __ffsll(act) - 1;
+      const int lk = __shfl(key, leader);
+      const unsigned long long match = __ballot(key == lk);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&cursor[lk], __popcll(match));
+      base = __shfl(base, leader);
+      if (key == lk) {
+        list[base + __popcll(match & below)] = int32_t(i);
+        key = -1;
+      }
+    }
   }
 }
 
@@ -59,14 +111,14 @@ mas_status ensure_cub(Ctx& c, size_t bytes) {
   return MAS_OK;
 }
 
-mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w,
+mas_status bucket_by_subdomain(Ctx& c, int level, int64_t m, const int32_t* idx, const double* w,
                                const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
-  const int64_t D = c.lv[0].nsub;
+  const int64_t D = c.lv[level].nsub;
   HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (D + 1), c.s));
   if (m > 0) {
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
-    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt);
+    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(level, m, idx, w, vec12, cnt);
   }
   size_t bytes = 0;
   HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, cnt, off, int(D + 1), c.s));
@@ -78,7 +130,7 @@ mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const doub
     HIPCHK(hipMemcpyAsync(cnt, off, sizeof(int32_t) * D, hipMemcpyDeviceToDevice, c.s));
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
-    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt, list);
+    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(level, m, idx, w, vec12, cnt, list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;

@@ -6,11 +6,11 @@
 namespace mas {
 
 // k_util.hip -----------------------------------------------------------
-// Buckets items into per-subdomain lists: item i belongs to the distinct
-// level-0 subdomains (v >> 5) of its stencil vertices for which keep(i, j)
-// holds; mode 0: every vertex with idx >= 0 and weight > 0 (weights w[m]
-// nonzero); the kernel filters with w[i] > 0 and a nonzero 3-vector in vec.
-mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w,
+// Buckets stencils (w[i] > 0) into per-subdomain lists of one level.  Level
+// 0: the distinct subdomains (v >> 5) of its vertices whose part of vec12 is
+// nonzero.  Level l >= 1: the distinct level-l subdomains (v >> 5(l+1))
+// holding at least two distinct level-l nodes (v >> 5l) of the stencil.
+mas_status bucket_by_subdomain(Ctx& c, int level, int64_t m, const int32_t* idx, const double* w,
                                const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
 mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
                      const int32_t* vals_in, int32_t* vals_out);
