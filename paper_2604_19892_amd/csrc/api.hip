@@ -554,7 +554,7 @@ mas_status mas_get_block(void* p, int32_t level, int64_t d, double* out) {
   HIPCHK(hipMemcpy(sig.data(), L.scale + d * BD, BD * sizeof(float), hipMemcpyDeviceToHost));
   for (int i = 0; i < BD; ++i)
     for (int j = 0; j <= i; ++j) {
-      int e = pk(i, j);
+      const int e = blk_pos(P, i, j);
       double v;
       if (P == MAS_F64) v = reinterpret_cast<double*>(raw.data())[e];
       else if (P == MAS_F32) v = reinterpret_cast<float*>(raw.data())[e];

@@ -45,6 +45,90 @@ __host__ __device__ inline constexpr size_t blk_elems(int p) {
 // recorded per block
 constexpr size_t BLK_STRIDE = blk_elems(MAS_F64) * 8;
 
+// Stored block layout.  A symmetric 96x96 block is cut into 6x6 tiles: the
+// 120 tiles (bi, bj), bi > bj, numbered t = bi (bi - 1) / 2 + bj with their 36
+// entries row-major, and the 16 diagonal tiles in pairs (2m, 2m + 1) with 21
+// packed-lower entries each, numbered t = 120 + m.  A block product runs 128
+// threads, thread t on tile t.  Each tile's entries are cut into 8-byte
+// units; unit k of the 64 tiles of a wavefront are stored next to each other,
+// so every unit is one contiguous 512-byte access.  The diagonal pairs (lanes
+// 56..63 of the second wavefront) have a few more units, stored last.
+constexpr int NTILE = 128;
+__host__ __device__ inline constexpr int tile_epu(int P) { return 8 / int(prec_size(P)); }
+__host__ __device__ inline constexpr int tile_uo(int P) { return 36 / tile_epu(P); }
+__host__ __device__ inline constexpr int tile_ud(int P) { return (42 + tile_epu(P) - 1) / tile_epu(P); }
+__host__ __device__ inline constexpr int blk_positions(int P) {
+  return (128 * tile_uo(P) + 8 * (tile_ud(P) - tile_uo(P))) * tile_epu(P);
+}
+// index of unit k of tile t
+__host__ __device__ inline int tile_unit(int P, int t, int k) {
+  const int uo = tile_uo(P);
+  if (t < 64) return k * 64 + t;
+  if (k < uo) return 64 * uo + k * 64 + (t - 64);
+  return 128 * uo + (k - uo) * 8 + (t - 120);
+}
+// row/column tile of off-diagonal tile t < 120
+__host__ __device__ inline void tile_rc(int t, int& bi, int& bj) {
+  bi = 1;
+  while ((bi + 1) * bi / 2 <= t) ++bi;
+  bj = t - bi * (bi - 1) / 2;
+}
+// storage position (in entries) of A(i, j)
+__host__ __device__ inline int blk_pos(int P, int i, int j) {
+  if (i < j) {
+    const int x = i;
+    i = j;
+    j = x;
+  }
+  const int bi = i / 6, bj = j / 6, r = i % 6, q = j % 6;
+  int t, e;
+  if (bi > bj) {
+    t = bi * (bi - 1) / 2 + bj;
+    e = 6 * r + q;
+  } else {
+    t = 120 + bi / 2;
+    e = 21 * (bi & 1) + r * (r + 1) / 2 + q;
+  }
+  const int epu = tile_epu(P);
+  return tile_unit(P, t, e / epu) * epu + e % epu;
+}
+// the entry (i >= j) held at storage position pos; false for padding
+__host__ __device__ inline bool blk_entry_of(int P, int pos, int& i, int& j) {
+  const int epu = tile_epu(P), uo = tile_uo(P);
+  const int u = pos / epu, sub = pos % epu;
+  int t, k;
+  if (u < 64 * uo) {
+    t = u % 64;
+    k = u / 64;
+  } else if (u < 128 * uo) {
+    t = 64 + (u - 64 * uo) % 64;
+    k = (u - 64 * uo) / 64;
+  } else {
+    t = 120 + (u - 128 * uo) % 8;
+    k = uo + (u - 128 * uo) / 8;
+  }
+  int e = k * epu + sub;
+  if (t < 120) {
+    int bi, bj;
+    tile_rc(t, bi, bj);
+    i = 6 * bi + e / 6;
+    j = 6 * bj + e % 6;
+    return true;
+  }
+  if (e >= 42) return false;
+  const int b = 2 * (t - 120) + (e >= 21 ? 1 : 0);
+  if (e >= 21) e -= 21;
+  int r = 0;
+  while ((r + 1) * (r + 2) / 2 <= e) ++r;
+  i = 6 * b + r;
+  j = 6 * b + e - r * (r + 1) / 2;
+  return true;
+}
+
+static_assert(blk_positions(MAS_F64) <= int(blk_elems(MAS_F64)) && blk_positions(MAS_F32) <= int(blk_elems(MAS_F32)) &&
+                  blk_positions(MAS_BF16) <= int(blk_elems(MAS_BF16)),
+              "tiled blocks fit their slots");
+
 // unit roundoff of each storage format
 __host__ __device__ inline constexpr double prec_eps(int p) {
   return p == MAS_F64 ? 1.1102230246251565e-16

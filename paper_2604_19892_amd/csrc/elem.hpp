@@ -114,70 +114,181 @@ __device__ inline void snh_tangent(const double F[3][3], double mu, double lam, 
   add_skew(2, 1, f[0], 1.0);
 }
 
-// Clamp the eigenvalues of a symmetric 9x9 matrix (packed) at zero, in
-// place.  Cyclic Jacobi rotations (Golub & Van Loan, Sec. 8.5) accumulate the
-// eigenvectors; the projection V max(Lambda, 0) V^T is rebuilt from them.
-__device__ inline void psd_project9(double A[45]) {
-  double V[9][9];
+// One Jacobi rotation of a symmetric 3x3 A zeroing A[P][Q]; V accumulates
+// the rotations (columns are eigenvectors).
+template <int P, int Q>
+__device__ __forceinline__ void jacobi3_rot(double (&A)[3][3], double (&V)[3][3]) {
+  constexpr int R = 3 - P - Q;
+  const double apq = A[P][Q];
+  if (apq == 0.0) return;
+  const double theta = (A[Q][Q] - A[P][P]) / (2.0 * apq);
+  const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  const double c = 1.0 / sqrt(t * t + 1.0);
+  const double sn = t * c;
+  A[P][P] -= t * apq;
+  A[Q][Q] += t * apq;
+  A[P][Q] = A[Q][P] = 0.0;
+  const double arp = A[R][P], arq = A[R][Q];
+  A[R][P] = A[P][R] = c * arp - sn * arq;
+  A[R][Q] = A[Q][R] = sn * arp + c * arq;
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+  for (int k = 0; k < 3; ++k) {
+    const double vkp = V[k][P], vkq = V[k][Q];
+    V[k][P] = c * vkp - sn * vkq;
+    V[k][Q] = sn * vkp + c * vkq;
+  }
+}
+
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi: on return the diagonal
+// of A holds the eigenvalues and V the eigenvectors (columns).
+__device__ inline void jacobi3(double (&A)[3][3], double (&V)[3][3]) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
-  double fro = 0;
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (!(off > 1e-36 * dia)) break;
+    jacobi3_rot<0, 1>(A, V);
+    jacobi3_rot<0, 2>(A, V);
+    jacobi3_rot<1, 2>(A, V);
+  }
+}
+
+// Givens rotation on rows P, Q of B zeroing B[Q][C] (B[P][C] >= 0 after);
+// U accumulates the transposed rotations so that U B stays invariant.
+template <int P, int Q, int C>
+__device__ __forceinline__ void givens3(double (&B)[3][3], double (&U)[3][3]) {
+  const double a = B[P][C], b = B[Q][C];
+  const double r = sqrt(a * a + b * b);
+  const double c = (r > 0.0) ? a / r : 1.0, sn = (r > 0.0) ? b / r : 0.0;
 #pragma unroll
-    for (int j = 0; j <= i; ++j) fro += (i == j ? 1.0 : 2.0) * A[p9(i, j)] * A[p9(i, j)];
-  const double tol = 1e-30 * fro;
-  for (int sweep = 0; sweep < 20; ++sweep) {
-    double off = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double bp = B[P][k], bq = B[Q][k];
+    B[P][k] = c * bp + sn * bq;
+    B[Q][k] = -sn * bp + c * bq;
+    const double up = U[k][P], uq = U[k][Q];
+    U[k][P] = c * up + sn * uq;
+    U[k][Q] = -sn * up + c * uq;
+  }
+}
+
+// Rotation-variant SVD F = U diag(sig) V^T with U, V proper rotations and
+// sig[0] >= sig[1] >= |sig[2]|, sig[2] < 0 for inverted F: V from the
+// eigenvectors of F^T F, then U and sig from a Givens QR of F V (the diagonal
+// of R; it carries the sign of det F), following McAdams et al. (2011).
+__device__ inline void svd3_rv(const double (&F)[3][3], double (&U)[3][3], double (&sig)[3], double (&V)[3][3]) {
+  double S[3][3];
 #pragma unroll
-    for (int i = 1; i < 9; ++i)
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < i; ++j) off += A[p9(i, j)] * A[p9(i, j)];
-    if (off <= tol) break;
+    for (int j = 0; j < 3; ++j) S[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
+  jacobi3(S, V);
+  double ev[3] = {S[0][0], S[1][1], S[2][2]};
+  auto cswap = [&](int i, int j) {
+    if (ev[i] < ev[j]) {
+      const double e = ev[i];
+      ev[i] = ev[j];
+      ev[j] = e;
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < 9; ++q) {
-        double apq = A[p9(p, q)];
-        if (apq != 0.0) {
-          double theta = (A[p9(q, q)] - A[p9(p, p)]) / (2.0 * apq);
-          double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          double c = 1.0 / sqrt(t * t + 1.0);
-          double s = t * c;
-          A[p9(p, p)] -= t * apq;
-          A[p9(q, q)] += t * apq;
-          A[p9(p, q)] = 0.0;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            if (k == p || k == q) continue;
-            double akp = A[p9(k, p)], akq = A[p9(k, q)];
-            A[p9(k, p)] = c * akp - s * akq;
-            A[p9(k, q)] = s * akp + c * akq;
-          }
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            double vkp = V[k][p], vkq = V[k][q];
-            V[k][p] = c * vkp - s * vkq;
-            V[k][q] = s * vkp + c * vkq;
-          }
-        }
+      for (int k = 0; k < 3; ++k) {
+        const double v = V[k][i];
+        V[k][i] = V[k][j];
+        V[k][j] = v;
       }
     }
-  }
-  double lam[9];
+  };
+  cswap(0, 1);
+  cswap(0, 2);
+  cswap(1, 2);
+  const double dv = V[0][0] * (V[1][1] * V[2][2] - V[1][2] * V[2][1]) -
+                    V[0][1] * (V[1][0] * V[2][2] - V[1][2] * V[2][0]) +
+                    V[0][2] * (V[1][0] * V[2][1] - V[1][1] * V[2][0]);
+  if (dv < 0.0) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) lam[i] = fmax(A[p9(i, i)], 0.0);
+    for (int k = 0; k < 3; ++k) V[k][2] = -V[k][2];
+  }
+  double B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[i][j] = F[i][0] * V[0][j] + F[i][1] * V[1][j] + F[i][2] * V[2][j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) U[i][j] = (i == j) ? 1.0 : 0.0;
+  givens3<0, 1, 0>(B, U);
+  givens3<0, 2, 0>(B, U);
+  givens3<1, 2, 1>(B, U);
+  sig[0] = B[0][0];
+  sig[1] = B[1][1];
+  sig[2] = B[2][2];
+}
+
+// H -= lam q q^T (packed 9x9)
+__device__ __forceinline__ void sub_rank1_9(double (&H)[45], double lam, const double (&q)[9]) {
 #pragma unroll
   for (int i = 0; i < 9; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      double acc = 0;
+    for (int j = 0; j <= i; ++j) H[p9(i, j)] -= lam * q[i] * q[j];
+}
+
+// The SNH tangent with its negative eigenvalues clamped to zero.  Its
+// eigenvectors are known in closed form from the rotation-variant SVD of F
+// (Smith, de Goes and Kim 2019): for each axis k a twist and a flip mode
+// (u_i v_j^T -/+ u_j v_i^T)/sqrt2 with eigenvalues mu + s sig_k and
+// mu - s sig_k, s = lam (J - 1) - mu, and three scaling modes
+// sum_i w_i u_i v_i^T from the 3x3 matrix mu I + lam d d^T + s d2J/dsig2.
+// The clamped tangent is the full tangent minus its negative modes.
+__device__ inline void snh_tangent_psd(const double F[3][3], double mu, double lam, double (&H)[45]) {
+  snh_tangent(F, mu, lam, H);
+  const double (&Fr)[3][3] = *reinterpret_cast<const double(*)[3][3]>(F);
+  double U[3][3], V[3][3], sg[3];
+  svd3_rv(Fr, U, sg, V);
+  const double s = lam * (det3(F) - 1.0) - mu;
+  const double r2 = 0.70710678118654752440;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc += V[i][k] * lam[k] * V[j][k];
-      A[p9(i, j)] = acc;
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const double et = mu + s * sg[k], ef = mu - s * sg[k];
+    if (et < 0.0) {
+      double q[9];
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[3 * b + a] = r2 * (U[a][i] * V[b][j] - U[a][j] * V[b][i]);
+      sub_rank1_9(H, et, q);
     }
+    if (ef < 0.0) {
+      double q[9];
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[3 * b + a] = r2 * (U[a][i] * V[b][j] + U[a][j] * V[b][i]);
+      sub_rank1_9(H, ef, q);
+    }
+  }
+  const double d[3] = {sg[1] * sg[2], sg[0] * sg[2], sg[0] * sg[1]};
+  double A3[3][3], W[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A3[i][j] = lam * d[i] * d[j] + (i == j ? mu : s * sg[3 - i - j]);
+  jacobi3(A3, W);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double e = A3[m][m];
+    if (e < 0.0) {
+      double q[9];
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          q[3 * b + a] = W[0][m] * U[a][0] * V[b][0] + W[1][m] * U[a][1] * V[b][1] + W[2][m] * U[a][2] * V[b][2];
+      sub_rank1_9(H, e, q);
+    }
+  }
 }
 
 // f = B^T Hf B v for one tet.  Hf: 45 packed entries (already scaled by

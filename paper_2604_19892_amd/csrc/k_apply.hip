@@ -1,7 +1,7 @@
-// Preconditioner apply z = P g: restriction to every coarse level, coarse
-// block solves, then one workgroup per level-0 subdomain streams its inverse
-// block through LDS, applies the Woodbury correction and adds the coarse
-// corrections of the subdomain's vertices.
+// Preconditioner apply z = P g (supplement Eq. (4)): restriction to every
+// coarse level, coarse block products, then one workgroup per level-0
+// subdomain applies its inverse block, the Woodbury correction (Section 4.1)
+// and adds the coarse corrections of the subdomain's vertices.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -28,52 +28,114 @@ __global__ void k_restrict(int64_t N, int64_t nodes1, const double* g, RestrictA
   for (int l = 2; l < ra.L; ++l) atomicAdd(&ra.r[l][3 * (a >> (5 * (l - 1))) + c], s);
 }
 
-template <int P>
-__device__ __forceinline__ double lds_entry(const unsigned char* As, int e) {
-  if (P == MAS_F64) return reinterpret_cast<const double*>(As)[e];
-  if (P == MAS_F32) return double(reinterpret_cast<const float*>(As)[e]);
-  uint16_t h = reinterpret_cast<const uint16_t*>(As)[e];
-  return double((P == MAS_BF16) ? bf16_to_f32(h) : f16_to_f32(h));
-}
+// ---------------------------------------------------------------------------
+// y = B x for one stored block, 128 threads, thread t on tile t of the tiled
+// layout.  The tile's units are loaded straight into registers (every
+// wavefront access is one contiguous 512-byte piece); x goes through LDS;
+// each tile produces a row-side and a column-side partial of six sums
+// (diagonal pairs only row sides), collected in LDS as part[b][s] for row
+// tile b and partner tile s, 16 per row tile, and summed by threads 0..95.
+// 16-bit blocks hold B_ij / (sig_i sig_j): x is scaled by sig before and y
+// after.  Arithmetic in float64.
+constexpr int PB = 102;  // doubles per row tile in part[] (16 x 6, padded against bank conflicts)
 
-// y_row = sum_j A(row, j) x_j for a packed-lower symmetric block in LDS; the
-// 192 threads split each row into two halves of 48 columns.
 template <int P>
-__device__ __forceinline__ double row_half(const unsigned char* As, const double* x, int row, int half) {
-  double acc = 0;
-  const int j0 = 48 * half;
-  const int br = row * (row + 1) / 2;
-#pragma unroll 8
-  for (int jj = 0; jj < 48; ++jj) {
-    const int j = j0 + jj;
-    const int e = (j <= row) ? br + j : j * (j + 1) / 2 + row;
-    acc += lds_entry<P>(As, e) * x[j];
+__device__ __forceinline__ double unit_entry(const uint2 (&u)[tile_ud(P)], int e) {
+  const uint2 w = u[e / tile_epu(P)];
+  if constexpr (P == MAS_F64) {
+    return __hiloint2double(int(w.y), int(w.x));
+  } else if constexpr (P == MAS_F32) {
+    return double(__uint_as_float((e & 1) ? w.y : w.x));
+  } else {
+    const uint32_t h2 = (e & 2) ? w.y : w.x;
+    const uint16_t h = uint16_t((e & 1) ? (h2 >> 16) : (h2 & 0xffffu));
+    return double((P == MAS_BF16) ? bf16_to_f32(h) : f16_to_f32(h));
   }
-  return acc;
 }
 
-__device__ __forceinline__ int slot_bytes(int P) { return int(blk_elems(P) * prec_size(P)); }
+template <int P>
+__device__ __forceinline__ double block_apply(const unsigned char* slot, const float* scale_d, double xv, int bi,
+                                              int bj, double* xs, double* part) {
+  constexpr int EPU = tile_epu(P), UO = tile_uo(P), UD = tile_ud(P);
+  constexpr bool q16 = (P == MAS_BF16 || P == MAS_F16);
+  const int t = threadIdx.x;
+  const bool diag = t >= 120;
+  uint2 u[UD];
+  const uint2* s2 = reinterpret_cast<const uint2*>(slot);
+#pragma unroll
+  for (int k = 0; k < UD; ++k) {
+    u[k] = make_uint2(0u, 0u);
+    if (k < UO || diag) u[k] = s2[tile_unit(P, t, k)];
+  }
+  float sg = 1.0f;
+  if (t < BD) {
+    if (q16) sg = scale_d[t];
+    xs[t] = q16 ? xv * double(sg) : xv;
+  }
+  __syncthreads();
+  if (!diag) {
+    double xi[6], xj[6], y[6], w[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      xi[q] = xs[6 * bi + q];
+      xj[q] = xs[6 * bj + q];
+      w[q] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double a = unit_entry<P>(u, 6 * r + q);
+        acc += a * xj[q];
+        w[q] += a * xi[r];
+      }
+      y[r] = acc;
+    }
+    double* pr = part + bi * PB + 6 * bj;
+    double* pc = part + bj * PB + 6 * bi;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      pr[q] = y[q];
+      pc[q] = w[q];
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = 2 * (t - 120) + h;
+      double xb[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) xb[q] = xs[6 * b + q];
+      double* pd = part + b * PB + 6 * b;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          acc += unit_entry<P>(u, 21 * h + (r >= q ? r * (r + 1) / 2 + q : q * (q + 1) / 2 + r)) * xb[q];
+        pd[r] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  double z = 0.0;
+  if (t < BD) {
+    const double* pz = part + (t / 6) * PB + t % 6;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) z += pz[6 * s];
+    if (q16) z *= double(sg);
+  }
+  return z;
+}
 
-// the 192 row-halves of a block product, in the block's stored precision
-__device__ __forceinline__ void block_rows(int P, const unsigned char* As, const double* x, double (*part)[BD]) {
-  const int tid = threadIdx.x;
-  if (tid >= 2 * BD) return;
-  const int row = tid % BD, half = tid / BD;
-  double v;
+__device__ __forceinline__ double block_apply_any(int P, const unsigned char* slot, const float* scale_d, double xv,
+                                                  int bi, int bj, double* xs, double* part) {
   switch (P) {
-    case MAS_F64: v = row_half<MAS_F64>(As, x, row, half); break;
-    case MAS_F32: v = row_half<MAS_F32>(As, x, row, half); break;
-    case MAS_BF16: v = row_half<MAS_BF16>(As, x, row, half); break;
-    default: v = row_half<MAS_F16>(As, x, row, half);
+    case MAS_F64: return block_apply<MAS_F64>(slot, scale_d, xv, bi, bj, xs, part);
+    case MAS_F32: return block_apply<MAS_F32>(slot, scale_d, xv, bi, bj, xs, part);
+    case MAS_BF16: return block_apply<MAS_BF16>(slot, scale_d, xv, bi, bj, xs, part);
+    default: return block_apply<MAS_F16>(slot, scale_d, xv, bi, bj, xs, part);
   }
-  part[half][row] = v;
-}
-
-__device__ __forceinline__ void load_slot(const void* blk, int64_t d, int P, unsigned char* As) {
-  const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(blk) + d * BLK_STRIDE);
-  uint4* dst = reinterpret_cast<uint4*>(As);
-  const int n = slot_bytes(P) / 16;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) dst[q] = src[q];
 }
 
 struct CoarseBlocks {
@@ -87,42 +149,25 @@ struct CoarseBlocks {
   double* c[MAXL];
 };
 
-__global__ __launch_bounds__(256) void k_apply_coarse(CoarseBlocks cb) {
-  __shared__ __align__(16) unsigned char As[BLK_STRIDE];
-  __shared__ double x[BD];
-  __shared__ double part[2][BD];
-  __shared__ float sig[BD];
-  int64_t gb = blockIdx.x;
+__global__ __launch_bounds__(NTILE) void k_apply_coarse(CoarseBlocks cb) {
+  __shared__ double xs[BD];
+  __shared__ __align__(16) double part[16 * PB];
+  const int64_t gb = blockIdx.x;
   int l = 1;
   while (l + 1 < cb.L && gb >= cb.first[l + 1]) ++l;
   const int64_t d = gb - cb.first[l];
-  const int tid = threadIdx.x;
-  const int P = cb.bprec[l][d];
-  const bool q16 = (P == MAS_BF16 || P == MAS_F16);
-  load_slot(cb.blk[l], d, P, As);
-  if (tid < BD) {
-    int64_t a = SUB * d + tid / 3;
-    double xv = a < cb.nodes[l] ? cb.r[l][BD * d + tid] : 0.0;
-    if (q16) {
-      sig[tid] = cb.scale[l][BD * d + tid];
-      xv *= double(sig[tid]);
-    }
-    x[tid] = xv;
-  }
-  __syncthreads();
-  block_rows(P, As, x, part);
-  __syncthreads();
-  if (tid < BD) {
-    int64_t a = SUB * d + tid / 3;
-    double v = part[0][tid] + part[1][tid];
-    if (q16) v *= double(sig[tid]);
-    if (a < cb.nodes[l]) cb.c[l][BD * d + tid] = v;
-  }
+  const int t = threadIdx.x;
+  int bi = 0, bj = 0;
+  if (t < 120) tile_rc(t, bi, bj);
+  const int64_t a = SUB * d + t / 3;
+  const double xv = (t < BD && a < cb.nodes[l]) ? cb.r[l][BD * d + t] : 0.0;
+  const unsigned char* slot = reinterpret_cast<const unsigned char*>(cb.blk[l]) + d * BLK_STRIDE;
+  const double v = block_apply_any(cb.bprec[l][d], slot, cb.scale[l] + BD * d, xv, bi, bj, xs, part);
+  if (t < BD && a < cb.nodes[l]) cb.c[l][BD * d + t] = v;
 }
 
 struct FineArgs {
   int64_t N;
-  int64_t D;
   const void* blk;
   const uint8_t* bprec;
   const float* scale;
@@ -137,137 +182,76 @@ struct FineArgs {
   const double* c[MAXL];
 };
 
-constexpr int PF = (BLK_STRIDE / 16 + 255) / 256;  // 16-byte prefetch registers per thread
-
-// Persistent workgroups stream the level-0 blocks.  While block d is applied
-// from LDS, everything block d + grid needs from memory (the block, its
-// slice of g, the coarse corrections of its vertices and its rank) is
-// already loading into registers, so the HBM latency overlaps the LDS work.
-// Updated subdomains fetch their Woodbury data (slot columns, capacitance
-// factor, W) in one batch.
-__global__ __launch_bounds__(256) void k_apply_l0(FineArgs fa) {
-  __shared__ __align__(16) unsigned char As[BLK_STRIDE];
-  __shared__ double x[BD];
-  __shared__ double part[2][BD];
+// One workgroup per level-0 subdomain d: z_d = B_d g_d, minus the Woodbury
+// correction W_d C_d^-1 U_d^T B_d g_d where the subdomain was updated, plus
+// the coarse corrections of its vertices.
+__global__ __launch_bounds__(NTILE) void k_apply_l0(FineArgs fa) {
+  __shared__ double xs[BD];
+  __shared__ __align__(16) double part[16 * PB];
   __shared__ double zb[BD];
   __shared__ double rr[MAXK];
   __shared__ double lam[MAXK];
   __shared__ double Lf[MAXK * (MAXK + 1) / 2];
   __shared__ SlotCol sl[MAXK];
-  __shared__ float sig[BD];
-  const int tid = threadIdx.x;
+  const int64_t d = blockIdx.x;
+  const int t = threadIdx.x;
   const int K = fa.K;
-  int P = 0, Pn = 0, rn = 0;
-  double gn = 0.0, cn[MAXL - 1];
-  float sn = 1.0f;
-#pragma unroll
-  for (int l = 0; l < MAXL - 1; ++l) cn[l] = 0.0;
-  int64_t d = blockIdx.x;
-  static_assert(PF == 10, "prefetch registers are spelled out for 10 chunks");
-  uint4 p0, p1, p2, p3, p4, p5, p6, p7, p8, p9;
-#define MAS_PF1(R, Q) \
-  if (tid + 256 * (Q) < n_) R = src_[tid + 256 * (Q)];
-#define MAS_PREFETCH(dd)                                                                                   \
-  do {                                                                                                     \
-    Pn = fa.bprec[dd];                                                                                     \
-    rn = fa.rank ? fa.rank[dd] : 0;                                                                        \
-    const int n_ = slot_bytes(Pn) / 16;                                                                    \
-    const uint4* src_ =                                                                                    \
-        reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(fa.blk) + (dd) * BLK_STRIDE); \
-    MAS_PF1(p0, 0) MAS_PF1(p1, 1) MAS_PF1(p2, 2) MAS_PF1(p3, 3) MAS_PF1(p4, 4)                              \
-    MAS_PF1(p5, 5) MAS_PF1(p6, 6) MAS_PF1(p7, 7) MAS_PF1(p8, 8) MAS_PF1(p9, 9)                              \
-    if (tid < BD) {                                                                                        \
-      const int64_t v_ = SUB * (dd) + tid / 3;                                                             \
-      gn = v_ < fa.N ? fa.g[BD * (dd) + tid] : 0.0;                                                        \
-      sn = fa.scale[BD * (dd) + tid];                                                                      \
-      if (v_ < fa.N) {                                                                                     \
-        _Pragma("unroll") for (int l_ = 1; l_ < MAXL; ++l_) if (l_ < fa.L) cn[l_ - 1] =                    \
-            fa.c[l_][3 * (v_ >> (5 * l_)) + tid % 3];                                                      \
-      }                                                                                                    \
-    }                                                                                                      \
-  } while (0)
-#define MAS_ST1(R, Q) \
-  if (tid + 256 * (Q) < n) dst[tid + 256 * (Q)] = R;
-  if (d < fa.D) MAS_PREFETCH(d);
-  for (; d < fa.D; d += gridDim.x) {
-    P = Pn;
-    const int r = rn;
-    const bool q16 = (P == MAS_BF16 || P == MAS_F16);
-    double corr = 0.0;
-#pragma unroll
-    for (int l = 0; l < MAXL - 1; ++l) corr += cn[l];
-    {
-      const int n = slot_bytes(P) / 16;
-      uint4* dst = reinterpret_cast<uint4*>(As);
-      MAS_ST1(p0, 0) MAS_ST1(p1, 1) MAS_ST1(p2, 2) MAS_ST1(p3, 3) MAS_ST1(p4, 4)
-      MAS_ST1(p5, 5) MAS_ST1(p6, 6) MAS_ST1(p7, 7) MAS_ST1(p8, 8) MAS_ST1(p9, 9)
-    }
-    if (tid < BD) {
-      if (q16) sig[tid] = sn;
-      x[tid] = q16 ? gn * double(sn) : gn;
-    }
-    if (r > 0) {
-      // Woodbury data of this subdomain, all loads in flight together
-      const int nl = r * (r + 1) / 2;
-      const double* Lm = fa.Lcap + d * (K * (K + 1) / 2);
-      for (int q = tid; q < nl; q += blockDim.x) Lf[q] = Lm[q];
-      if (tid < r) sl[tid] = fa.slots[d * K + tid];
-    }
-    __syncthreads();
-    if (d + gridDim.x < fa.D) MAS_PREFETCH(d + gridDim.x);
-    block_rows(P, As, x, part);
-    __syncthreads();
-    double zv = 0.0;
-    if (tid < BD) {
-      zv = part[0][tid] + part[1][tid];
-      if (q16) zv *= double(sig[tid]);
-      zb[tid] = zv;
-    }
-    if (r > 0) {
-      __syncthreads();
-      // r_j = u_j^T z_base over the stencil vertices inside the subdomain
-      if (tid < r) {
-        double acc = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          int lv = sl[tid].lv[s];
-          if (lv < 0) continue;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) acc += sl[tid].u[3 * s + a] * zb[3 * lv + a];
-        }
-        rr[tid] = acc;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        // (L L^T) lambda = r: forward substitution in place in rr, then backward
-        for (int i = 0; i < r; ++i) {
-          double v = rr[i];
-          for (int k = 0; k < i; ++k) v -= Lf[pk(i, k)] * rr[k];
-          rr[i] = v / Lf[pk(i, i)];
-        }
-        for (int i = r - 1; i >= 0; --i) {
-          double v = rr[i];
-          for (int k = i + 1; k < r; ++k) v -= Lf[pk(k, i)] * lam[k];
-          lam[i] = v / Lf[pk(i, i)];
-        }
-      }
-      __syncthreads();
-      if (tid < BD) {
-        const double* Wd = fa.W + d * K * BD;
-        double acc = 0;
-        for (int j = 0; j < r; ++j) acc += Wd[j * BD + tid] * lam[j];
-        zv -= acc;
-      }
-    }
-    if (tid < BD) {
-      const int64_t v = SUB * d + tid / 3;
-      if (v < fa.N) fa.z[BD * d + tid] = zv + corr;
-    }
-    __syncthreads();
+  const int r = fa.rank ? fa.rank[d] : 0;
+  if (r > 0) {
+    const double* Lm = fa.Lcap + d * (K * (K + 1) / 2);
+    for (int q = t; q < r * (r + 1) / 2; q += blockDim.x) Lf[q] = Lm[q];
+    if (t < r) sl[t] = fa.slots[d * K + t];
   }
-#undef MAS_PREFETCH
-#undef MAS_PF1
-#undef MAS_ST1
+  int bi = 0, bj = 0;
+  if (t < 120) tile_rc(t, bi, bj);
+  const int64_t v = SUB * d + t / 3;
+  double xv = 0.0, corr = 0.0;
+  if (t < BD && v < fa.N) {
+    xv = fa.g[BD * d + t];
+#pragma unroll
+    for (int l = 1; l < MAXL; ++l)
+      if (l < fa.L) corr += fa.c[l][3 * (v >> (5 * l)) + t % 3];
+  }
+  const unsigned char* slot = reinterpret_cast<const unsigned char*>(fa.blk) + d * BLK_STRIDE;
+  double zv = block_apply_any(fa.bprec[d], slot, fa.scale + BD * d, xv, bi, bj, xs, part);
+  if (r > 0) {
+    if (t < BD) zb[t] = zv;
+    __syncthreads();
+    // r_j = u_j^T z_base over the stencil vertices inside the subdomain
+    if (t < r) {
+      double acc = 0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int lv = sl[t].lv[s];
+        if (lv < 0) continue;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc += sl[t].u[3 * s + a] * zb[3 * lv + a];
+      }
+      rr[t] = acc;
+    }
+    __syncthreads();
+    if (t == 0) {
+      // (L L^T) lambda = r: forward substitution in place in rr, then backward
+      for (int i = 0; i < r; ++i) {
+        double y = rr[i];
+        for (int k = 0; k < i; ++k) y -= Lf[pk(i, k)] * rr[k];
+        rr[i] = y / Lf[pk(i, i)];
+      }
+      for (int i = r - 1; i >= 0; --i) {
+        double y = rr[i];
+        for (int k = i + 1; k < r; ++k) y -= Lf[pk(k, i)] * lam[k];
+        lam[i] = y / Lf[pk(i, i)];
+      }
+    }
+    __syncthreads();
+    if (t < BD) {
+      const double* Wd = fa.W + d * K * BD;
+      double acc = 0;
+      for (int j = 0; j < r; ++j) acc += Wd[j * BD + t] * lam[j];
+      zv -= acc;
+    }
+  }
+  if (t < BD && v < fa.N) fa.z[BD * d + t] = zv + corr;
 }
 
 mas_status launch_apply(Ctx& c, const double* g, double* z) {
@@ -292,11 +276,10 @@ mas_status launch_apply(Ctx& c, const double* g, double* z) {
       cb.c[l] = c.lv[l].c;
     }
     int64_t total = cb.first[c.L];
-    k_apply_coarse<<<dim3(total), dim3(256), 0, c.s>>>(cb);
+    k_apply_coarse<<<dim3(total), dim3(NTILE), 0, c.s>>>(cb);
   }
   FineArgs fa{};
   fa.N = c.N;
-  fa.D = c.lv[0].nsub;
   fa.blk = c.lv[0].blk;
   fa.bprec = c.lv[0].bprec;
   fa.scale = c.lv[0].scale;
@@ -310,8 +293,7 @@ mas_status launch_apply(Ctx& c, const double* g, double* z) {
   fa.L = c.L;
   for (int l = 1; l < c.L; ++l) fa.c[l] = c.lv[l].c;
   prof_begin(c, MAS_T_APPLY_L0);
-  const int64_t grid = std::min<int64_t>(c.lv[0].nsub, int64_t(c.n_cu) * 3);
-  k_apply_l0<<<dim3(grid), dim3(256), 0, c.s>>>(fa);
+  k_apply_l0<<<dim3(c.lv[0].nsub), dim3(NTILE), 0, c.s>>>(fa);
   prof_end(c, MAS_T_APPLY_L0);
   HIPCHK(hipGetLastError());
   return MAS_OK;

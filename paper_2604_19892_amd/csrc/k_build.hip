@@ -29,8 +29,7 @@ __global__ __launch_bounds__(64) void k_elem_hess(int64_t T, int64_t Tpad, const
     for (int q = 0; q < 9; ++q) Dmi[q] = g[q];
     double F[3][3];
     def_grad(xe, Dmi, F);
-    snh_tangent(F, g[10], g[11], H);
-    psd_project9(H);
+    snh_tangent_psd(F, g[10], g[11], H);
     double s = h * h * g[9];
 #pragma unroll
     for (int q = 0; q < 45; ++q) H[q] *= s;
@@ -138,13 +137,65 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
 }
 
 // ---------------------------------------------------------------------------
-// In-place inverse of an SPD 96x96 matrix held packed-lower in LDS, using the
-// symmetric sweep operator (Goodnight 1979): sweeping every pivot k maps A to
-// -A^-1.  The matrix lives in registers during the sweeps: thread t < 136
-// owns the 6x6 tile (ti, tj), ti >= tj, of a 16x16 tile grid; per pivot only
-// the pivot column passes through LDS (double-buffered, one barrier a step).
-__device__ __forceinline__ void spd_invert_lds(double* A, double (*colbuf)[BD], uint32_t* err, DiagRec* dg,
-                                               int source, int level, int64_t index) {
+// 1/x: hardware reciprocal refined by two Newton steps (x positive, normal)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Inverse of a small SPD block (W = 1, 2, 3) by cofactors.  pivot receives
+// the first non-positive leading minor (or the last one if all are positive).
+template <int W>
+__device__ __forceinline__ bool small_spd_inv(const double (&a)[W][W], double (&m)[W][W], double& pivot) {
+  if constexpr (W == 1) {
+    pivot = a[0][0];
+    m[0][0] = rcp_nr(a[0][0]);
+    return a[0][0] > 0.0 && isfinite(a[0][0]);
+  } else if constexpr (W == 2) {
+    const double det = a[0][0] * a[1][1] - a[1][0] * a[1][0];
+    pivot = a[0][0] > 0.0 ? det : a[0][0];
+    const double id = rcp_nr(det);
+    m[0][0] = a[1][1] * id;
+    m[1][1] = a[0][0] * id;
+    m[0][1] = m[1][0] = -a[1][0] * id;
+    return a[0][0] > 0.0 && det > 0.0 && isfinite(det);
+  } else {
+    const double c00 = a[1][1] * a[2][2] - a[2][1] * a[2][1];
+    const double c10 = a[2][1] * a[2][0] - a[1][0] * a[2][2];
+    const double c20 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+    const double det = a[0][0] * c00 + a[1][0] * c10 + a[2][0] * c20;
+    const double m2 = a[0][0] * a[1][1] - a[1][0] * a[1][0];
+    pivot = !(a[0][0] > 0.0) ? a[0][0] : (!(m2 > 0.0) ? m2 : det);
+    const double id = rcp_nr(det);
+    m[0][0] = c00 * id;
+    m[1][0] = m[0][1] = c10 * id;
+    m[2][0] = m[0][2] = c20 * id;
+    m[1][1] = (a[0][0] * a[2][2] - a[2][0] * a[2][0]) * id;
+    m[2][1] = m[1][2] = (a[2][0] * a[1][0] - a[0][0] * a[2][1]) * id;
+    m[2][2] = m2 * id;
+    return a[0][0] > 0.0 && m2 > 0.0 && det > 0.0 && isfinite(det);
+  }
+}
+
+// In-place inverse of an SPD 96x96 matrix held packed-lower in LDS with the
+// symmetric sweep operator (Goodnight 1979), which maps A to -A^-1 once every
+// pivot has been swept; sweeping a set K of pivots at once is
+//   A_ij -= A_iK A_KK^-1 A_Kj,  A_iK <- A_iK A_KK^-1,  A_KK <- -A_KK^-1.
+// The matrix is first scaled to unit diagonal (sc = diag^-1/2).  Thread
+// t < 136 keeps the 6x6 tile (ti, tj), ti >= tj, of a 16x16 tile grid in
+// registers; per panel of W pivots the W pivot columns pass through LDS (a
+// double buffer that reuses A's storage, one barrier per panel).  All three
+// updates are one rank-W product R -= P Q^T with P the panel, its KK part
+// lowered by I, and Q = P A_KK^-1; it leaves the diagonal of A_KK too large by
+// exactly 2, and no later panel reads those entries, so 2 is taken off at the
+// end.  With unit diagonal, the diagonal of -A^-1 is at most -1 and the shift
+// costs no accuracy.
+template <int W>
+__device__ __forceinline__ void spd_invert_lds(double* A, double* sc, uint32_t* err, DiagRec* dg, int source,
+                                               int level, int64_t index) {
   const int tid = threadIdx.x;
   const bool act = tid < 136;
   int ti = 0, tj = 0;
@@ -154,81 +205,73 @@ __device__ __forceinline__ void spd_invert_lds(double* A, double (*colbuf)[BD], 
     while (ti * (ti + 1) / 2 > tid) --ti;
     tj = tid - ti * (ti + 1) / 2;
   }
+  if (tid < BD) sc[tid] = 1.0 / sqrt(A[pk(tid, tid)]);
+  __syncthreads();
   double R[6][6];
   if (act) {
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
-      for (int q = 0; q < 6; ++q) R[r][q] = A[pks(6 * ti + r, 6 * tj + q)];
+      for (int q = 0; q < 6; ++q) R[r][q] = A[pks(6 * ti + r, 6 * tj + q)] * sc[6 * ti + r] * sc[6 * tj + q];
   }
+  __syncthreads();
   int bad_k = -1;
   double bad_v = 0.0;
-  for (int k = 0; k < BD; ++k) {
-    double* col = colbuf[k & 1];
-    // kb, kr are the same in every lane: the switches below are scalar branches
-    const int kb = k / 6, kr = k % 6;
-    if (act) {
-      if (tj == kb) {  // column kr of the tile holds A(i, k), i >= 6 kb
-        switch (kr) {
-#define MAS_COLK(KR)                                                       \
-  case KR:                                                                 \
-    _Pragma("unroll") for (int r = 0; r < 6; ++r) if (6 * ti + r >= k)     \
-        col[6 * ti + r] = R[r][KR];                                        \
-    break;
-          MAS_COLK(0) MAS_COLK(1) MAS_COLK(2) MAS_COLK(3) MAS_COLK(4) MAS_COLK(5)
-#undef MAS_COLK
+  for (int kb = 0; kb < BD / 6; ++kb) {
+#pragma unroll
+    for (int sub = 0; sub < 6 / W; ++sub) {
+      const int co = sub * W;
+      double* P = A + ((kb * (6 / W) + sub) & 1) * (W * BD);
+      if (act) {
+        if (tj == kb) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c < W; ++c)
+              P[c * BD + 6 * ti + r] = (ti == kb && r == co + c) ? R[r][co + c] - 1.0 : R[r][co + c];
+        } else if (ti == kb) {
+#pragma unroll
+          for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int c = 0; c < W; ++c) P[c * BD + 6 * tj + q] = R[co + c][q];
         }
       }
-      if (ti == kb) {  // row kr of the tile holds A(k, j), j < k
-        switch (kr) {
-#define MAS_ROWK(KR)                                                       \
-  case KR:                                                                 \
-    _Pragma("unroll") for (int q = 0; q < 6; ++q) if (6 * tj + q < k)      \
-        col[6 * tj + q] = R[KR][q];                                        \
-    break;
-          MAS_ROWK(0) MAS_ROWK(1) MAS_ROWK(2) MAS_ROWK(3) MAS_ROWK(4) MAS_ROWK(5)
-#undef MAS_ROWK
-        }
+      __syncthreads();
+      const int k0 = 6 * kb + co;
+      double a[W][W], M[W][W], pivot;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int c2 = 0; c2 < W; ++c2) a[c][c2] = P[c2 * BD + k0 + c] + (c == c2 ? 1.0 : 0.0);
+      if (!small_spd_inv<W>(a, M, pivot) && bad_k < 0) {
+        bad_k = k0;
+        bad_v = pivot;
       }
-    }
-    __syncthreads();
-    const double dk = col[k];
-    if (bad_k < 0 && (!(dk > 0.0) || !isfinite(dk))) {
-      bad_k = k;
-      bad_v = dk;
-    }
-    const double inv = 1.0 / dk;
-    if (act) {
-      double ci[6], cj[6];
+      if (act) {
+        double ci[6][W], Q[6][W];
 #pragma unroll
-      for (int r = 0; r < 6; ++r) ci[r] = col[6 * ti + r];
+        for (int r = 0; r < 6; ++r)
 #pragma unroll
-      for (int q = 0; q < 6; ++q) cj[q] = col[6 * tj + q] * inv;
-      // sweep: a_ij -= a_ik a_kj / a_kk everywhere, then row and column k
+          for (int c = 0; c < W; ++c) ci[r][c] = P[c * BD + 6 * ti + r];
 #pragma unroll
-      for (int r = 0; r < 6; ++r)
+        for (int q = 0; q < 6; ++q) {
+          double pj[W];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) R[r][q] -= ci[r] * cj[q];
-      if (tj == kb) {  // a_ik <- a_ik / a_kk
-        switch (kr) {
-#define MAS_FIXC(KR)                                                       \
-  case KR:                                                                 \
-    _Pragma("unroll") for (int r = 0; r < 6; ++r) R[r][KR] = ci[r] * inv;  \
-    break;
-          MAS_FIXC(0) MAS_FIXC(1) MAS_FIXC(2) MAS_FIXC(3) MAS_FIXC(4) MAS_FIXC(5)
-#undef MAS_FIXC
+          for (int c = 0; c < W; ++c) pj[c] = P[c * BD + 6 * tj + q];
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int c2 = 0; c2 < W; ++c2) t += pj[c2] * M[c2][c];
+            Q[q][c] = t;
+          }
         }
-      }
-      if (ti == kb) {  // a_kj <- a_kj / a_kk, a_kk <- -1 / a_kk
-        switch (kr) {
-#define MAS_FIXR(KR)                                                       \
-  case KR:                                                                 \
-    _Pragma("unroll") for (int q = 0; q < 6; ++q) R[KR][q] = cj[q];        \
-    if (tj == kb) R[KR][KR] = -inv;                                        \
-    break;
-          MAS_FIXR(0) MAS_FIXR(1) MAS_FIXR(2) MAS_FIXR(3) MAS_FIXR(4) MAS_FIXR(5)
-#undef MAS_FIXR
-        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int c = 0; c < W; ++c) R[r][q] -= ci[r][c] * Q[q][c];
       }
     }
   }
@@ -243,39 +286,38 @@ __device__ __forceinline__ void spd_invert_lds(double* A, double (*colbuf)[BD], 
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         const int i = 6 * ti + r, j = 6 * tj + q;
-        if (i >= j) A[pk(i, j)] = -R[r][q];
+        if (i >= j) A[pk(i, j)] = ((i == j) ? 2.0 - R[r][q] : -R[r][q]) * sc[i] * sc[j];
       }
   }
   __syncthreads();
 }
 
-// Store an inverted block (LDS, packed f64) at precision P in slot d.
+// Store an inverted block (LDS, packed f64) at precision P in slot d, in the
+// tiled layout of the block products (writes in storage order).
 // 16-bit storage keeps A_ij / (sigma_i sigma_j) with sigma_i = sqrt(A_ii).
 template <int P>
 __device__ __forceinline__ void store_block(const double* A, void* out, float* scale_out, int64_t d, float* sig) {
   const int tid = threadIdx.x;
   unsigned char* slot = reinterpret_cast<unsigned char*>(out) + d * BLK_STRIDE;
-  if (P == MAS_F64) {
-    double* o = reinterpret_cast<double*>(slot);
-    for (int e = tid; e < PK; e += blockDim.x) o[e] = A[e];
-  } else if (P == MAS_F32) {
-    float* o = reinterpret_cast<float*>(slot);
-    for (int e = tid; e < PK; e += blockDim.x) o[e] = float(A[e]);
-  } else {
+  constexpr bool q16 = (P == MAS_BF16 || P == MAS_F16);
+  if (q16) {
     for (int i = tid; i < BD; i += blockDim.x) {
       float s = float(sqrt(A[pk(i, i)]));
       sig[i] = s;
       scale_out[d * BD + i] = s;
     }
     __syncthreads();
-    uint16_t* o = reinterpret_cast<uint16_t*>(slot);
-    for (int e = tid; e < PK; e += blockDim.x) {
-      int i = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      while (i * (i + 1) / 2 > e) --i;
-      int j = e - i * (i + 1) / 2;
-      float v = float(A[e] / (double(sig[i]) * double(sig[j])));
-      o[e] = (P == MAS_BF16) ? f32_to_bf16(v) : f32_to_f16(v);
+  }
+  for (int pos = tid; pos < blk_positions(P); pos += blockDim.x) {
+    int i = 0, j = 0;
+    const double v = blk_entry_of(P, pos, i, j) ? A[pk(i, j)] : 0.0;
+    if (P == MAS_F64) {
+      reinterpret_cast<double*>(slot)[pos] = v;
+    } else if (P == MAS_F32) {
+      reinterpret_cast<float*>(slot)[pos] = float(v);
+    } else {
+      const float f = float(v / (double(sig[i]) * double(sig[j])));
+      reinterpret_cast<uint16_t*>(slot)[pos] = (P == MAS_BF16) ? f32_to_bf16(f) : f32_to_f16(f);
     }
   }
 }
@@ -424,6 +466,8 @@ __global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* t
   for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
 }
 
+constexpr int INV_W = 1;  // pivots per panel of the block sweep
+
 // Inverts the packed float64 blocks of one level (rows of nodes beyond the
 // node count are identity) and stores each in the requested precision, or a
 // wider one when kappa = max_i M_ii B_ii exceeds guard / (20 eps): the spectral
@@ -433,7 +477,7 @@ __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const doub
                                                        uint8_t* bprec, int req, double guard, uint32_t* err,
                                                        DiagRec* dg, int level, double* ndiag_next) {
   __shared__ double A[PK];
-  __shared__ double colbuf[2][BD];
+  __shared__ double sc[BD];
   __shared__ double mdiag[BD];
   __shared__ float sig[BD];
   __shared__ int chosen;
@@ -448,7 +492,7 @@ __global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const doub
   }
   __syncthreads();
   if (ndiag_next) block_node_sum(A, int(min<int64_t>(SUB, nodes - SUB * d)), ndiag_next + 9 * d);
-  spd_invert_lds(A, colbuf, err, dg, level == 0 ? 1 : 2, level, d);
+  spd_invert_lds<INV_W>(A, sc, err, dg, level == 0 ? 1 : 2, level, d);
   if (threadIdx.x < 64) {
     double k1 = mdiag[threadIdx.x] * A[pk(threadIdx.x, threadIdx.x)];
     if (threadIdx.x < BD - 64) {
@@ -500,8 +544,9 @@ mas_status launch_level0_build(Ctx& c) {
 // `splits` workgroups that accumulate in LDS (one LDS atomic per distinct
 // node pair and wavefront) and add their nonzero entries to the block.
 
-// adds b (node pair ls > lu) to A, summed over the lanes of the wavefront with
-// the same pair first; key < 0: nothing to add.  Uniform control flow.
+// adds b (node pair ls > lu) to A, summed first over the lanes of the
+// wavefront with the same pair while such groups are large; key < 0: nothing
+// to add.  Uniform control flow.
 __device__ __forceinline__ void wave_add_pair(double* A, int key, const double (&b)[3][3]) {
   const int lane = threadIdx.x & 63;
   while (true) {
@@ -510,6 +555,16 @@ __device__ __forceinline__ void wave_add_pair(double* A, int key, const double (
     const int leader = __ffsll(act) - 1;
     const int lk = __shfl(key, leader);
     const bool mine = key == lk;
+    if (__popcll(__ballot(mine)) < 4) {  // mostly distinct pairs: add directly
+      if (key >= 0) {
+        const int ls = key >> 5, lu = key & 31;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * ls + a, 3 * lu + q)], b[a][q]);
+      }
+      break;
+    }
     double t[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)

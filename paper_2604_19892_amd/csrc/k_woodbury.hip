@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64) void k_topk(int K, const int32_t* off, const in
 
 template <int P>
 __device__ __forceinline__ double block_entry(const unsigned char* A, const float* sig, int i, int j) {
-  int e = pks(i, j);
+  const int e = blk_pos(P, i, j);
   if (P == MAS_F64) return reinterpret_cast<const double*>(A)[e];
   if (P == MAS_F32) return double(reinterpret_cast<const float*>(A)[e]);
   uint16_t h = reinterpret_cast<const uint16_t*>(A)[e];

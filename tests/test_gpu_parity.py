@@ -307,3 +307,22 @@ def test_stiff_blocks_are_promoted_and_stay_definite():
     Pa = c.ctx.from_lib(c.ctx.apply(c.ctx.to_lib(a)))
     assert a @ Pa > 0
     c.ctx.close()
+
+
+def test_indefinite_block_is_reported():
+    """Negative vertex masses make the level-0 blocks indefinite: the build
+    must flag MAS_ERR_NOT_SPD with the failing block named, not fault."""
+    import dataclasses
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    print("\n[parity case] grid with negative density", flush=True)
+    sc = synth.grid_scene()
+    sc = dataclasses.replace(sc, density=-1e3 * np.asarray(sc.density))
+    base, _ = synth.grid_update_sets(sc)
+    ctx = MasContext(sc, make_config(sc, levels=2, K=8))
+    ctx.build(ctx.to_lib(sc.x), ctx.contacts(base))
+    code, msg = ctx.sync()
+    assert code == 5, (code, msg)
+    assert "level-0 block" in msg, msg
+    # the sticky error is cleared by the read
+    assert ctx.sync()[0] == 0
+    ctx.close()
