@@ -1,6 +1,5 @@
 // C ABI entry points: argument checks, context lifetime, call order.
 #include <algorithm>
-#include <array>
 #include <cstdio>
 #include <numeric>
 #include <new>
@@ -161,7 +160,7 @@ mas_status mas_destroy(void* p) {
     if (q) hipFree(q);
   for (int l = 0; l < MAXL; ++l) {
     Level& L = c->lv[l];
-    void* lp[] = {L.blk, L.bprec, L.scale, L.acc, L.r, L.c, L.ndiag, L.xt_off, L.xt_list, L.xc_cnt, L.xc_off, L.xc_list};
+    void* lp[] = {L.blk, L.bprec, L.scale, L.acc, L.r, L.c};
     for (void* q : lp)
       if (q) hipFree(q);
   }
@@ -288,54 +287,6 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     }
   }
 
-  // level l >= 1 subdomain -> tets with two or more distinct level-l nodes in
-  // it (the only tets with off-diagonal node pairs there)
-  std::vector<int32_t> xoff[MAXL], xlist[MAXL];
-  for (int l = 1; l < c->L; ++l) {
-    const int ns = 5 * l, ss = 5 * (l + 1);
-    const int64_t Dl = c->lv[l].nsub;
-    auto subs = [&](int64_t t, int* out) {
-      int n = 0;
-      for (int j = 0; j < 4; ++j) {
-        const int v = tets[4 * t + j], S = v >> ss;
-        bool dup = false, two = false;
-        for (int q = 0; q < n; ++q) dup |= out[q] == S;
-        for (int k = 0; k < 4; ++k) two |= (tets[4 * t + k] >> ss) == S && (tets[4 * t + k] >> ns) != (v >> ns);
-        if (!dup && two) out[n++] = S;
-      }
-      return n;
-    };
-    xoff[l].assign(Dl + 1, 0);
-    for (int64_t t = 0; t < T; ++t) {
-      int ds[4];
-      const int n = subs(t, ds);
-      for (int q = 0; q < n; ++q) xoff[l][ds[q] + 1]++;
-    }
-    for (int64_t d = 0; d < Dl; ++d) xoff[l][d + 1] += xoff[l][d];
-    xlist[l].assign(std::max<int32_t>(xoff[l][Dl], 1), 0);
-    std::vector<int32_t> cur(xoff[l].begin(), xoff[l].end() - 1);
-    for (int64_t t = 0; t < T; ++t) {
-      int ds[4];
-      const int n = subs(t, ds);
-      for (int q = 0; q < n; ++q) xlist[l][cur[ds[q]]++] = int32_t(t);
-    }
-    // within a subdomain, tets with the same nodes next to each other (the
-    // assembly sums equal node pairs over a wavefront before adding them)
-    int32_t most = 0;
-    for (int64_t d = 0; d < Dl; ++d) {
-      auto sig = [&](int32_t t) {
-        std::array<int, 4> nd;
-        for (int j = 0; j < 4; ++j) nd[j] = tets[4 * int64_t(t) + j] >> ns;
-        std::sort(nd.begin(), nd.end());
-        return nd;
-      };
-      std::stable_sort(xlist[l].begin() + xoff[l][d], xlist[l].begin() + xoff[l][d + 1],
-                       [&](int32_t a, int32_t b) { return sig(a) < sig(b); });
-      most = std::max(most, xoff[l][d + 1] - xoff[l][d]);
-    }
-    c->lv[l].splits = std::max(1, std::min(1024, (most + 2047) / 2048));
-  }
-
   // device memory
   TRY(dalloc(&c->tets, 4 * T));
   TRY(dalloc(&c->geo, 12 * T));
@@ -353,15 +304,6 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     if (l > 0) {
       TRY(dalloc(&L.r, 3 * L.nodes));
       TRY(dalloc(&L.c, 3 * L.nodes));
-      TRY(dalloc(&L.ndiag, 9 * L.nodes));
-      TRY(dalloc(&L.xt_off, L.nsub + 1));
-      TRY(dalloc(&L.xt_list, xlist[l].size()));
-      TRY(dalloc(&L.xc_cnt, L.nsub + 1));
-      TRY(dalloc(&L.xc_off, L.nsub + 1));
-      HIPCHK(hipMemcpyAsync(L.xt_off, xoff[l].data(), xoff[l].size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                            c->s));
-      HIPCHK(hipMemcpyAsync(L.xt_list, xlist[l].data(), xlist[l].size() * sizeof(int32_t),
-                            hipMemcpyHostToDevice, c->s));
     }
   }
   TRY(dalloc(&c->bc_cnt, D0 + 1));
@@ -407,9 +349,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     return st;
   }
   // scan temporaries for the subdomain buckets, sized once
-  TRY(bucket_by_subdomain(*c, 0, 0, nullptr, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
-  for (int l = 1; l < c->L; ++l)
-    TRY(bucket_by_subdomain(*c, l, 0, nullptr, nullptr, nullptr, c->lv[l].xc_cnt, c->lv[l].xc_off, nullptr));
+  TRY(bucket_by_subdomain(*c, 0, nullptr, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
   HIPCHK(hipStreamSynchronize(c->s));
   if (perm_out) std::memcpy(perm_out, perm.data(), N * sizeof(int32_t));
   *ctx_out = c;

@@ -204,13 +204,6 @@ struct Level {
   uint8_t* bprec = nullptr;  // stored precision of each block
   float* scale = nullptr;  // nsub * 96 row scales (16-bit storage)
   double* acc = nullptr;   // packed FP64 assembly of every block of the level
-  double* ndiag = nullptr;   // levels >= 1: 3x3 diagonal block of every node (9 per node)
-  int32_t* xt_off = nullptr;   // levels >= 1: subdomain -> tets with >= 2 of its nodes
-  int32_t* xt_list = nullptr;
-  int splits = 1;              // levels >= 1: workgroups per subdomain in the assembly
-  int32_t* xc_cnt = nullptr;   // levels >= 1: subdomain -> base contacts with >= 2 of its nodes
-  int32_t* xc_off = nullptr;
-  int32_t* xc_list = nullptr;
   double* r = nullptr;     // restricted residual 3*nodes (levels >= 1)
   double* c = nullptr;     // coarse correction 3*nodes (levels >= 1)
 };

@@ -1,6 +1,8 @@
 // RebuildMAS: the frozen element Hessians, the base contact set, level-0
 // subdomain blocks (assembled and inverted inside one workgroup) and the
 // Galerkin coarse blocks of every level.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "elem.hpp"
 
@@ -69,27 +71,40 @@ __device__ inline void load_snapshot(const double* hf64, int64_t t, double* H, d
 
 // ---------------------------------------------------------------------------
 // Base contact set: copy, stiffness k = kappa b''(d) and columns sqrt(k) n.
-__global__ void k_base_copy(int64_t m, const uint64_t* key, const int32_t* idx, const double* d,
-                            const double* grad, double kappa, double dhat, uint64_t* bkey,
-                            int32_t* biota, double* bk, double* bgrad, int32_t* bidx, double* bu,
-                            uint32_t* err) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= m) return;
-  double b, b1, b2;
-  double di = d[i];
-  if (!isfinite(di)) atomicOr(err, ERRB_NONFINITE);
-  barrier3(di, dhat, &b, &b1, &b2);
-  double k = kappa * b2;
-  bk[i] = k;
-  bkey[i] = key[i];
-  biota[i] = int32_t(i);
-  double sk = sqrt(k);
-  for (int q = 0; q < 12; ++q) {
-    double n = grad[12 * i + q];
-    bgrad[12 * i + q] = n;
-    bu[12 * i + q] = sk * n;
+// Each wavefront takes 64 stencils; the 12-wide rows are copied by the whole
+// wavefront in 64-element strides so that every store is contiguous.
+__global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* key, const int32_t* idx,
+                                                   const double* d, const double* grad, double kappa, double dhat,
+                                                   uint64_t* bkey, int32_t* biota, double* bk, double* bgrad,
+                                                   int32_t* bidx, double* bu, uint32_t* err) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = i - lane;  // first stencil of this wavefront
+  double sk = 0.0;
+  if (i < m) {
+    double b, b1, b2;
+    const double di = d[i];
+    if (!isfinite(di)) atomicOr(err, ERRB_NONFINITE);
+    barrier3(di, dhat, &b, &b1, &b2);
+    const double k = kappa * b2;
+    bk[i] = k;
+    bkey[i] = key[i];
+    biota[i] = int32_t(i);
+    sk = sqrt(k);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bidx[4 * i + q] = idx[4 * i + q];
   }
-  for (int q = 0; q < 4; ++q) bidx[4 * i + q] = idx[4 * i + q];
+  const int64_t n12 = 12 * (min<int64_t>(m, w0 + 64) - w0);
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int e = q * 64 + lane;
+    const double s = __shfl(sk, e / 12);
+    if (e < n12) {
+      const double n = grad[12 * w0 + e];
+      bgrad[12 * w0 + e] = n;
+      bu[12 * w0 + e] = s * n;
+    }
+  }
 }
 
 static mas_status grow_base(Ctx& c, int64_t m) {
@@ -97,11 +112,6 @@ static mas_status grow_base(Ctx& c, int64_t m) {
   int64_t cap = m + m / 4 + 1024;
   hipFree(c.bkey); hipFree(c.bkey_sorted); hipFree(c.biota); hipFree(c.bperm);
   hipFree(c.bk); hipFree(c.bgrad); hipFree(c.bidx); hipFree(c.bu); hipFree(c.bc_list);
-  for (int l = 1; l < c.L; ++l) {
-    hipFree(c.lv[l].xc_list);
-    c.lv[l].xc_list = nullptr;
-    if (hipMalloc(&c.lv[l].xc_list, 16 * cap) != hipSuccess) return MAS_ERR_OOM;
-  }
   bool ok = hipMalloc(&c.bkey, 8 * cap) == hipSuccess && hipMalloc(&c.bkey_sorted, 8 * cap) == hipSuccess &&
             hipMalloc(&c.biota, 4 * cap) == hipSuccess && hipMalloc(&c.bperm, 4 * cap) == hipSuccess &&
             hipMalloc(&c.bk, 8 * cap) == hipSuccess && hipMalloc(&c.bgrad, 96 * cap) == hipSuccess &&
@@ -126,14 +136,7 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
     st = sort_keys(c, m, c.bkey, c.bkey_sorted, c.biota, c.bperm);
     if (st != MAS_OK) return st;
   }
-  st = bucket_by_subdomain(c, 0, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
-  if (st != MAS_OK) return st;
-  for (int l = 1; l < c.L; ++l) {
-    Level& Lv = c.lv[l];
-    st = bucket_by_subdomain(c, l, m, c.bidx, c.bk, c.bgrad, Lv.xc_cnt, Lv.xc_off, Lv.xc_list);
-    if (st != MAS_OK) return st;
-  }
-  return MAS_OK;
+  return bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,182 +147,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
-}
-
-// Inverse of a small SPD block (W = 1, 2, 3) by cofactors.  pivot receives
-// the first non-positive leading minor (or the last one if all are positive).
-template <int W>
-__device__ __forceinline__ bool small_spd_inv(const double (&a)[W][W], double (&m)[W][W], double& pivot) {
-  if constexpr (W == 1) {
-    pivot = a[0][0];
-    m[0][0] = rcp_nr(a[0][0]);
-    return a[0][0] > 0.0 && isfinite(a[0][0]);
-  } else if constexpr (W == 2) {
-    const double det = a[0][0] * a[1][1] - a[1][0] * a[1][0];
-    pivot = a[0][0] > 0.0 ? det : a[0][0];
-    const double id = rcp_nr(det);
-    m[0][0] = a[1][1] * id;
-    m[1][1] = a[0][0] * id;
-    m[0][1] = m[1][0] = -a[1][0] * id;
-    return a[0][0] > 0.0 && det > 0.0 && isfinite(det);
-  } else {
-    const double c00 = a[1][1] * a[2][2] - a[2][1] * a[2][1];
-    const double c10 = a[2][1] * a[2][0] - a[1][0] * a[2][2];
-    const double c20 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
-    const double det = a[0][0] * c00 + a[1][0] * c10 + a[2][0] * c20;
-    const double m2 = a[0][0] * a[1][1] - a[1][0] * a[1][0];
-    pivot = !(a[0][0] > 0.0) ? a[0][0] : (!(m2 > 0.0) ? m2 : det);
-    const double id = rcp_nr(det);
-    m[0][0] = c00 * id;
-    m[1][0] = m[0][1] = c10 * id;
-    m[2][0] = m[0][2] = c20 * id;
-    m[1][1] = (a[0][0] * a[2][2] - a[2][0] * a[2][0]) * id;
-    m[2][1] = m[1][2] = (a[2][0] * a[1][0] - a[0][0] * a[2][1]) * id;
-    m[2][2] = m2 * id;
-    return a[0][0] > 0.0 && m2 > 0.0 && det > 0.0 && isfinite(det);
-  }
-}
-
-// In-place inverse of an SPD 96x96 matrix held packed-lower in LDS with the
-// symmetric sweep operator (Goodnight 1979), which maps A to -A^-1 once every
-// pivot has been swept; sweeping a set K of pivots at once is
-//   A_ij -= A_iK A_KK^-1 A_Kj,  A_iK <- A_iK A_KK^-1,  A_KK <- -A_KK^-1.
-// The matrix is first scaled to unit diagonal (sc = diag^-1/2).  Thread
-// t < 136 keeps the 6x6 tile (ti, tj), ti >= tj, of a 16x16 tile grid in
-// registers; per panel of W pivots the W pivot columns pass through LDS (a
-// double buffer that reuses A's storage, one barrier per panel).  All three
-// updates are one rank-W product R -= P Q^T with P the panel, its KK part
-// lowered by I, and Q = P A_KK^-1; it leaves the diagonal of A_KK too large by
-// exactly 2, and no later panel reads those entries, so 2 is taken off at the
-// end.  With unit diagonal, the diagonal of -A^-1 is at most -1 and the shift
-// costs no accuracy.
-template <int W>
-__device__ __forceinline__ void spd_invert_lds(double* A, double* sc, uint32_t* err, DiagRec* dg, int source,
-                                               int level, int64_t index) {
-  const int tid = threadIdx.x;
-  const bool act = tid < 136;
-  int ti = 0, tj = 0;
-  if (act) {
-    ti = int((sqrt(8.0 * tid + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= tid) ++ti;
-    while (ti * (ti + 1) / 2 > tid) --ti;
-    tj = tid - ti * (ti + 1) / 2;
-  }
-  if (tid < BD) sc[tid] = 1.0 / sqrt(A[pk(tid, tid)]);
-  __syncthreads();
-  double R[6][6];
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int q = 0; q < 6; ++q) R[r][q] = A[pks(6 * ti + r, 6 * tj + q)] * sc[6 * ti + r] * sc[6 * tj + q];
-  }
-  __syncthreads();
-  int bad_k = -1;
-  double bad_v = 0.0;
-  for (int kb = 0; kb < BD / 6; ++kb) {
-#pragma unroll
-    for (int sub = 0; sub < 6 / W; ++sub) {
-      const int co = sub * W;
-      double* P = A + ((kb * (6 / W) + sub) & 1) * (W * BD);
-      if (act) {
-        if (tj == kb) {
-#pragma unroll
-          for (int r = 0; r < 6; ++r)
-#pragma unroll
-            for (int c = 0; c < W; ++c)
-              P[c * BD + 6 * ti + r] = (ti == kb && r == co + c) ? R[r][co + c] - 1.0 : R[r][co + c];
-        } else if (ti == kb) {
-#pragma unroll
-          for (int q = 0; q < 6; ++q)
-#pragma unroll
-            for (int c = 0; c < W; ++c) P[c * BD + 6 * tj + q] = R[co + c][q];
-        }
-      }
-      __syncthreads();
-      const int k0 = 6 * kb + co;
-      double a[W][W], M[W][W], pivot;
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-#pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) a[c][c2] = P[c2 * BD + k0 + c] + (c == c2 ? 1.0 : 0.0);
-      if (!small_spd_inv<W>(a, M, pivot) && bad_k < 0) {
-        bad_k = k0;
-        bad_v = pivot;
-      }
-      if (act) {
-        double ci[6][W], Q[6][W];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int c = 0; c < W; ++c) ci[r][c] = P[c * BD + 6 * ti + r];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          double pj[W];
-#pragma unroll
-          for (int c = 0; c < W; ++c) pj[c] = P[c * BD + 6 * tj + q];
-#pragma unroll
-          for (int c = 0; c < W; ++c) {
-            double t = 0.0;
-#pragma unroll
-            for (int c2 = 0; c2 < W; ++c2) t += pj[c2] * M[c2][c];
-            Q[q][c] = t;
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int q = 0; q < 6; ++q)
-#pragma unroll
-            for (int c = 0; c < W; ++c) R[r][q] -= ci[r][c] * Q[q][c];
-      }
-    }
-  }
-  if (bad_k >= 0 && tid == 0) {
-    atomicOr(err, ERRB_NOT_SPD);
-    diag_report(dg, source, level, index, bad_k, bad_v);
-  }
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const int i = 6 * ti + r, j = 6 * tj + q;
-        if (i >= j) A[pk(i, j)] = ((i == j) ? 2.0 - R[r][q] : -R[r][q]) * sc[i] * sc[j];
-      }
-  }
-  __syncthreads();
-}
-
-// Store an inverted block (LDS, packed f64) at precision P in slot d, in the
-// tiled layout of the block products (writes in storage order).
-// 16-bit storage keeps A_ij / (sigma_i sigma_j) with sigma_i = sqrt(A_ii).
-template <int P>
-__device__ __forceinline__ void store_block(const double* A, void* out, float* scale_out, int64_t d, float* sig) {
-  const int tid = threadIdx.x;
-  unsigned char* slot = reinterpret_cast<unsigned char*>(out) + d * BLK_STRIDE;
-  constexpr bool q16 = (P == MAS_BF16 || P == MAS_F16);
-  if (q16) {
-    for (int i = tid; i < BD; i += blockDim.x) {
-      float s = float(sqrt(A[pk(i, i)]));
-      sig[i] = s;
-      scale_out[d * BD + i] = s;
-    }
-    __syncthreads();
-  }
-  for (int pos = tid; pos < blk_positions(P); pos += blockDim.x) {
-    int i = 0, j = 0;
-    const double v = blk_entry_of(P, pos, i, j) ? A[pk(i, j)] : 0.0;
-    if (P == MAS_F64) {
-      reinterpret_cast<double*>(slot)[pos] = v;
-    } else if (P == MAS_F32) {
-      reinterpret_cast<float*>(slot)[pos] = float(v);
-    } else {
-      const float f = float(v / (double(sig[i]) * double(sig[j])));
-      reinterpret_cast<uint16_t*>(slot)[pos] = (P == MAS_BF16) ? f32_to_bf16(f) : f32_to_f16(f);
-    }
-  }
 }
 
 // place a 3x3 block (pair of local nodes li, lj) into the packed lower matrix
@@ -342,388 +169,429 @@ __device__ inline void add_block_lds(double* A, int li, int lj, bool diag, const
   }
 }
 
-// Sum of the 3x3 blocks of a packed symmetric block (rows of nodes >= valid
-// excluded): the diagonal block of the level-(l+1) node the subdomain forms,
-// since C_(l+1) = C_hat C_(l) sums node blocks (supplement Eq. (3)).
-__device__ __forceinline__ void block_node_sum(const double* A, int valid, double* out9) {
-  __shared__ double red[9][4];
-  double s9[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) s9[q] = 0.0;
-  for (int e = threadIdx.x; e < PK; e += blockDim.x) {
-    int i = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    while (i * (i + 1) / 2 > e) --i;
-    const int j = e - i * (i + 1) / 2;
-    if (i / 3 >= valid || j / 3 >= valid) continue;
-    const double v = A[e];
-    const int a = i % 3, b = j % 3;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      if (q == 3 * a + b) s9[q] += v;
-      if (i != j && q == 3 * b + a) s9[q] += v;
+// ---------------------------------------------------------------------------
+// Level 0 and the coupling blocks of the coarse levels.  One workgroup per
+// level-0 subdomain d accumulates S_d H_base S_d^T in LDS (mass, every tet
+// and base contact touching d) and writes it packed in float64 to the level-0
+// assembly buffer.  The same pass yields the off-diagonal node blocks of
+// every coarse level A_(l) = C_(l) H C_(l)^T (supplement Eq. (3)): a vertex
+// pair (a in d, b outside d) adds H_ab to exactly one of them, at the level l
+// where a and b first share a subdomain, node pair (a >> 5l, b >> 5l); the
+// workgroup of the larger node takes it (the lower block).  Level 1's node is
+// d itself, so its row of blocks is complete here and written directly;
+// deeper levels are summed per workgroup in LDS and added with atomics.  The
+// diagonal node blocks come later, from the block sums taken while the level
+// below is inverted.  One thread per tet (or contact): it forms
+// G_j = Hf (c_j x I) once per vertex j and the 3x3 blocks c_i^T G_j of the
+// pairs it has to deliver.
+struct L0Args {
+  int64_t N;
+  int L;
+  const int32_t* tets;
+  const double* mass;
+  const double* hf64;
+  const int32_t* tet_off;
+  const int32_t* tet_list;
+  const double* bk;
+  const double* bgrad;
+  const int32_t* bidx;
+  const int32_t* bc_off;
+  const int32_t* bc_list;
+  double* acc[MAXL];
+};
+
+// Where the pair (vi, vj) of a stencil touching subdomain d goes: 0 = level 0
+// block, l >= 1 = coupling table of level l (node of the outside vertex in
+// *nb, *flip if vj is the vertex in d), -1 = nowhere.
+__device__ __forceinline__ int route_pair(int64_t d, int L, int vi, int vj, int* nb, bool* flip) {
+  const bool in_i = (vi >> 5) == d, in_j = (vj >> 5) == d;
+  if (in_i && in_j) return 0;
+  if (in_i == in_j) return -1;
+  const int a = in_i ? vi : vj, b = in_i ? vj : vi;
+  *flip = !in_i;
+  for (int l = 1; l < L; ++l) {
+    if ((a >> (5 * (l + 1))) == (b >> (5 * (l + 1)))) {
+      if ((a >> (5 * l)) < (b >> (5 * l))) return -1;
+      *nb = (b >> (5 * l)) & 31;
+      return l;
     }
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const double t = wave_sum(s9[q]);
-    if (lane == 0) red[q][w] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < 9) out9[threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
-                                           red[threadIdx.x][3];
+  return -1;
 }
 
-// ---------------------------------------------------------------------------
-// Level 0: one workgroup per subdomain d accumulates S_d H_base S_d^T in LDS
-// (mass, every tet touching d, every base contact touching d) and writes it
-// packed in float64 to the assembly buffer.  Tets are staged through LDS in
-// batches; each work item is then one (tet, vertex pair).
-__constant__ int8_t c_pair_i[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
-__constant__ int8_t c_pair_j[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
-constexpr int TB = 24;  // tets staged per batch
+__device__ __forceinline__ void add_coupling(double* T, int l, int nb, bool flip, const double (&b)[3][3]) {
+  double* e = T + ((l - 1) * SUB + nb) * 9;
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int y = 0; y < 3; ++y) atomicAdd(&e[3 * x + y], flip ? b[y][x] : b[x][y]);
+}
 
-__global__ __launch_bounds__(256) void k_assemble_l0(int64_t N, const int32_t* tets, const double* mass,
-                                                     const double* hf64, const int32_t* tet_off,
-                                                     const int32_t* tet_list, const double* bk,
-                                                     const double* bgrad, const int32_t* bidx,
-                                                     const int32_t* bc_off, const int32_t* bc_list,
-                                                     double* acc) {
+constexpr int L0_THREADS = 128;
+
+__global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   __shared__ double A[PK];
-  __shared__ double snap[TB][EH];
-  __shared__ int32_t tv[TB][4];
+  extern __shared__ double T[];  // (L - 1) x 32 node blocks of 9
   const int64_t d = blockIdx.x;
   const int tid = threadIdx.x;
+  const int nT = (a.L - 1) * SUB * 9;
   for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
+  for (int e = tid; e < nT; e += blockDim.x) T[e] = 0.0;
   __syncthreads();
   if (tid < BD) {
     int64_t v = SUB * d + tid / 3;
-    A[pk(tid, tid)] = (v < N) ? mass[v] : 1.0;
+    A[pk(tid, tid)] = (v < a.N) ? a.mass[v] : 1.0;
   }
-  const int t0 = tet_off[d], nt = tet_off[d + 1] - t0;
-  for (int b0 = 0; b0 < nt; b0 += TB) {
-    const int nb = min(TB, nt - b0);
-    __syncthreads();
-    for (int q = tid; q < nb * EH; q += blockDim.x) {
-      const int k = q / EH, c = q % EH;
-      const int64_t t = tet_list[t0 + b0 + k];
-      snap[k][c] = hf64[(t / TILE) * (EH * TILE) + c * TILE + (t % TILE)];
-    }
-    if (tid < 4 * nb) {
-      const int k = tid / 4;
-      tv[k][tid % 4] = tets[4 * int64_t(tet_list[t0 + b0 + k]) + tid % 4];
-    }
-    __syncthreads();
-    for (int w = tid; w < 10 * nb; w += blockDim.x) {
-      const int k = w / 10, pr = w % 10;
-      const int i = c_pair_i[pr], j = c_pair_j[pr];
-      const int vi = tv[k][i], vj = tv[k][j];
-      if ((vi >> 5) != d || (vj >> 5) != d) continue;
-      const double* H = snap[k];
-      const double* Dmi = snap[k] + 45;
-      double coef[4][3];
-      dfdx_coef(Dmi, coef);
-      double ci[3], cj[3];
+  const int t0 = a.tet_off[d], t1 = a.tet_off[d + 1];
+  for (int w = t0 + tid; w < t1; w += blockDim.x) {
+    const int64_t t = a.tet_list[w];
+    const int4 tv = reinterpret_cast<const int4*>(a.tets)[t];
+    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+    int dest[4][4], nbr[4][4];
+    bool flip[4][4], need[4];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        ci[b] = (i == 0) ? coef[0][b] : (i == 1) ? coef[1][b] : (i == 2) ? coef[2][b] : coef[3][b];
-        cj[b] = (j == 0) ? coef[0][b] : (j == 1) ? coef[1][b] : (j == 2) ? coef[2][b] : coef[3][b];
+    for (int j = 0; j < 4; ++j) {
+      need[j] = false;
+#pragma unroll
+      for (int i = j; i < 4; ++i) {
+        nbr[i][j] = 0;
+        flip[i][j] = false;
+        dest[i][j] = route_pair(d, a.L, v[i], v[j], &nbr[i][j], &flip[i][j]);
+        need[j] |= dest[i][j] >= 0;
       }
-      double blk[3][3];
+    }
+    if (!(need[0] || need[1] || need[2] || need[3])) continue;
+    const int64_t base = (t / TILE) * (EH * TILE) + (t % TILE);
+    double H[45], Dmi[9];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+    for (int q = 0; q < 45; ++q) H[q] = a.hf64[base + q * TILE];
 #pragma unroll
-        for (int ap = 0; ap < 3; ++ap) {
-          double sum = 0;
+    for (int q = 0; q < 9; ++q) Dmi[q] = a.hf64[base + (45 + q) * TILE];
+    double coef[4][3];
+    dfdx_coef(Dmi, coef);
 #pragma unroll
-          for (int b = 0; b < 3; ++b)
+    for (int j = 0; j < 4; ++j) {
+      if (!need[j]) continue;
+      double G[9][3];  // G[3b + x][y] = sum_b' Hf(3b + x, 3b' + y) c_j[b']
 #pragma unroll
-            for (int bp = 0; bp < 3; ++bp) sum += ci[b] * H[p9(3 * b + a, 3 * bp + ap)] * cj[bp];
-          blk[a][ap] = sum;
-        }
-      add_block_lds(A, vi & 31, vj & 31, i == j, blk);
+      for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+          G[r][y] = H[p9(r, y)] * coef[j][0] + H[p9(r, 3 + y)] * coef[j][1] + H[p9(r, 6 + y)] * coef[j][2];
+#pragma unroll
+      for (int i = j; i < 4; ++i) {
+        if (dest[i][j] < 0) continue;
+        double blk[3][3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y)
+            blk[x][y] = coef[i][0] * G[x][y] + coef[i][1] * G[3 + x][y] + coef[i][2] * G[6 + x][y];
+        if (dest[i][j] == 0) add_block_lds(A, v[i] & 31, v[j] & 31, i == j, blk);
+        else add_coupling(T, dest[i][j], nbr[i][j], flip[i][j], blk);
+      }
     }
   }
-  const int c0 = bc_off[d], nc = bc_off[d + 1] - c0;
-  for (int w = tid; w < 10 * nc; w += blockDim.x) {
-    const int64_t ci = bc_list[c0 + w / 10];
-    const int pr = w % 10;
-    const int i = c_pair_i[pr], j = c_pair_j[pr];
-    const int vi = bidx[4 * ci + i], vj = bidx[4 * ci + j];
-    if (vi < 0 || vj < 0 || (vi >> 5) != d || (vj >> 5) != d) continue;
-    const double k = bk[ci];
-    const double* n = bgrad + 12 * ci;
-    double blk[3][3];
+  const int c0 = a.bc_off[d], c1 = a.bc_off[d + 1];
+  for (int w = c0 + tid; w < c1; w += blockDim.x) {
+    const int64_t ci = a.bc_list[w];
+    int v[4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int j = 0; j < 4; ++j) v[j] = a.bidx[4 * ci + j];
+    const double k = a.bk[ci];
+    const double* n = a.bgrad + 12 * ci;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) blk[a][q] = k * n[3 * i + a] * n[3 * j + q];
-    add_block_lds(A, vi & 31, vj & 31, i == j, blk);
+    for (int j = 0; j < 4; ++j) {
+      if (v[j] < 0) continue;
+#pragma unroll
+      for (int i = j; i < 4; ++i) {
+        if (v[i] < 0) continue;
+        int nbr = 0;
+        bool flip = false;
+        const int dest = route_pair(d, a.L, v[i], v[j], &nbr, &flip);
+        if (dest < 0) continue;
+        double blk[3][3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y) blk[x][y] = k * n[3 * i + x] * n[3 * j + y];
+        if (dest == 0) add_block_lds(A, v[i] & 31, v[j] & 31, i == j, blk);
+        else add_coupling(T, dest, nbr, flip, blk);
+      }
+    }
   }
   __syncthreads();
-  double* out = acc + d * PK;
+  double* out = a.acc[0] + d * PK;
   for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
+  if (a.L > 1) {
+    // level 1: the blocks (d, u), u < d, of row d of subdomain d >> 5
+    const int ld = int(d & 31);
+    double* o1 = a.acc[1] + (d >> 5) * PK;
+    for (int q = tid; q < 9 * ld; q += blockDim.x) {
+      const int u = q / 9, x = (q % 9) / 3, y = q % 3;
+      o1[pk(3 * ld + x, 3 * u + y)] = T[u * 9 + 3 * x + y];
+    }
+    // deeper levels: only the tables this subdomain touched
+    for (int q = SUB * 9 + tid; q < nT; q += blockDim.x) {
+      const double val = T[q];
+      if (val == 0.0) continue;
+      const int l = q / (SUB * 9) + 1, u = (q / 9) % SUB, x = (q % 9) / 3, y = q % 3;
+      const int na = int((d >> (5 * (l - 1))) & 31);
+      unsafeAtomicAdd(&a.acc[l][(d >> (5 * l)) * PK + pk(3 * na + x, 3 * u + y)], val);
+    }
+  }
 }
 
-constexpr int INV_W = 1;  // pivots per panel of the block sweep
+// ---------------------------------------------------------------------------
+// Block inversion.  One workgroup per block; thread t < 136 keeps the 6x6
+// tile (ti, tj), ti >= tj, of the 16x16 tile grid in registers from load to
+// store (t = ti (ti + 1) / 2 + tj).
+//
+// The inverse comes from the symmetric sweep operator (Goodnight 1979):
+// sweeping pivot k maps a_kk to -1/a_kk, a_ik and a_kj to a_ik/a_kk and
+// a_kj/a_kk, and every other a_ij to a_ij - a_ik a_kj / a_kk; after all
+// pivots the matrix is -A^-1.  The block is first scaled to unit diagonal
+// (sc_i = a_ii^-1/2).  The three updates of a step are one rank-1 product
+// R -= u w^T with u the pivot column, its pivot entry lowered by 1, and
+// w = u / a_kk: that leaves a_kk larger by exactly 2, an entry no later step
+// reads, so 2 is taken off at the end (the diagonal of the scaled inverse is
+// at least 1, so this costs no accuracy).  The pivot column passes through
+// LDS, double-buffered, one barrier per pivot.
+constexpr int INV_THREADS = 192;
 
-// Inverts the packed float64 blocks of one level (rows of nodes beyond the
-// node count are identity) and stores each in the requested precision, or a
-// wider one when kappa = max_i M_ii B_ii exceeds guard / (20 eps): the spectral
-// norm of the rounding error of a unit-diagonal 96x96 matrix is about 20 eps,
-// and 1/kappa bounds its smallest eigenvalue from above.
-__global__ __launch_bounds__(256) void k_invert_blocks(int64_t nodes, const double* acc, void* blk, float* scale,
-                                                       uint8_t* bprec, int req, double guard, uint32_t* err,
-                                                       DiagRec* dg, int level, double* ndiag_next) {
-  __shared__ double A[PK];
-  __shared__ double sc[BD];
-  __shared__ double mdiag[BD];
+__device__ __forceinline__ void tri_tile(int t, int& ti, int& tj) {
+  ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  tj = t - ti * (ti + 1) / 2;
+}
+
+// Store the final tile F (values of A^-1, 16-bit: divided by sig_i sig_j) in
+// the tiled layout of the block products.  Off-diagonal tiles own whole
+// 8-byte units; diagonal tiles share units with their pair partner and store
+// entry by entry.
+template <int P>
+__device__ __forceinline__ void store_tile(unsigned char* slot, int ti, int tj, const double (&F)[6][6]) {
+  constexpr int EPU = tile_epu(P);
+  if (ti > tj) {
+    const int o = ti * (ti - 1) / 2 + tj;
+    uint2* s2 = reinterpret_cast<uint2*>(slot);
+#pragma unroll
+    for (int k = 0; k < tile_uo(P); ++k) {
+      uint2 u;
+      if constexpr (P == MAS_F64) {
+        const double v = F[k / 6][k % 6];
+        u.x = uint32_t(__double2loint(v));
+        u.y = uint32_t(__double2hiint(v));
+      } else if constexpr (P == MAS_F32) {
+        u.x = __float_as_uint(float(F[(2 * k) / 6][(2 * k) % 6]));
+        u.y = __float_as_uint(float(F[(2 * k + 1) / 6][(2 * k + 1) % 6]));
+      } else {
+        uint32_t h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float f = float(F[(4 * k + q) / 6][(4 * k + q) % 6]);
+          h[q] = (P == MAS_BF16) ? f32_to_bf16(f) : f32_to_f16(f);
+        }
+        u.x = h[0] | (h[1] << 16);
+        u.y = h[2] | (h[3] << 16);
+      }
+      s2[tile_unit(P, o, k)] = u;
+    }
+  } else {
+    const int m = ti / 2, h = ti & 1;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) {
+        const int e = 21 * h + r * (r + 1) / 2 + q;
+        const int pos = tile_unit(P, 120 + m, e / EPU) * EPU + e % EPU;
+        if constexpr (P == MAS_F64) reinterpret_cast<double*>(slot)[pos] = F[r][q];
+        else if constexpr (P == MAS_F32) reinterpret_cast<float*>(slot)[pos] = float(F[r][q]);
+        else
+          reinterpret_cast<uint16_t*>(slot)[pos] =
+              (P == MAS_BF16) ? f32_to_bf16(float(F[r][q])) : f32_to_f16(float(F[r][q]));
+      }
+  }
+}
+
+// Inverts the packed float64 blocks of one level (rows and columns of nodes
+// beyond the node count are identity) and stores each in the requested
+// precision, or a wider one when kappa = max_i M_ii B_ii exceeds
+// guard / (20 eps): the spectral norm of the rounding error of a
+// unit-diagonal 96x96 matrix is about 20 eps, and 1/kappa bounds its smallest
+// eigenvalue from above.  With acc_next, the sum of all 3x3 blocks of the
+// block (before inversion) becomes the diagonal block of node d at the next
+// level (C_(l+1) sums the nodes of d).
+__global__ __launch_bounds__(INV_THREADS) void k_invert_blocks(int64_t nodes, const double* acc, void* blk,
+                                                               float* scale, uint8_t* bprec, int req, double guard,
+                                                               uint32_t* err, DiagRec* dg, int level,
+                                                               double* acc_next) {
+  __shared__ __align__(16) double col[2][BD];
+  __shared__ double pv[2];
+  __shared__ __align__(16) double sc[BD];
   __shared__ float sig[BD];
+  __shared__ double red[9][4];
   __shared__ int chosen;
   const int64_t d = blockIdx.x;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const bool act = t < 136;
+  int ti = 0, tj = 0;
+  if (act) tri_tile(t, ti, tj);
+  const bool dtile = act && ti == tj;
   const double* src = acc + d * PK;
-  for (int e = threadIdx.x; e < PK; e += blockDim.x) A[e] = src[e];
-  __syncthreads();
-  if (threadIdx.x < BD) {
-    int64_t a = SUB * d + threadIdx.x / 3;
-    if (a >= nodes) A[pk(threadIdx.x, threadIdx.x)] = 1.0;
-    mdiag[threadIdx.x] = A[pk(threadIdx.x, threadIdx.x)];
+  const int valid = int(min<int64_t>(SUB, nodes - SUB * d));
+  double R[6][6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int i = 6 * ti + r, j = 6 * tj + q;
+      const bool pad = i / 3 >= valid || j / 3 >= valid;
+      R[r][q] = 0.0;
+      if (act) R[r][q] = pad ? (i == j ? 1.0 : 0.0) : src[i >= j ? pk(i, j) : pk(j, i)];
+    }
+  if (acc_next) {
+    double s9[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s9[q] = 0.0;
+#pragma unroll
+    for (int nr = 0; nr < 2; ++nr)
+#pragma unroll
+      for (int nq = 0; nq < 2; ++nq) {
+        if (!act || 2 * ti + nr >= valid || 2 * tj + nq >= valid) continue;
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y) {
+            const double v = R[3 * nr + x][3 * nq + y];
+            s9[3 * x + y] += v;
+            if (!dtile) s9[3 * y + x] += v;
+          }
+      }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const double v = wave_sum(s9[q]);
+      if (lane == 0) red[q][wv] = v;
+    }
+  }
+  if (dtile) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) sc[6 * ti + r] = 1.0 / sqrt(R[r][r]);
   }
   __syncthreads();
-  if (ndiag_next) block_node_sum(A, int(min<int64_t>(SUB, nodes - SUB * d)), ndiag_next + 9 * d);
-  spd_invert_lds<INV_W>(A, sc, err, dg, level == 0 ? 1 : 2, level, d);
-  if (threadIdx.x < 64) {
-    double k1 = mdiag[threadIdx.x] * A[pk(threadIdx.x, threadIdx.x)];
-    if (threadIdx.x < BD - 64) {
-      int i2 = threadIdx.x + 64;
-      k1 = fmax(k1, mdiag[i2] * A[pk(i2, i2)]);
-    }
-    for (int o = 32; o > 0; o >>= 1) k1 = fmax(k1, __shfl_xor(k1, o));
-    if (threadIdx.x == 0) {
-      int p = req;
-      while (guard > 0.0 && p != MAS_F64 && !(k1 <= guard / (20.0 * prec_eps(p))))
-        p = (p == MAS_F32) ? MAS_F64 : MAS_F32;
-      chosen = p;
-      bprec[d] = uint8_t(p);
+  if (acc_next && t < 9 && (t / 3) >= (t % 3)) {
+    const int ln = int(d & 31);
+    acc_next[(d >> 5) * PK + pk(3 * ln + t / 3, 3 * ln + t % 3)] = red[t][0] + red[t][1] + red[t][2];
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) R[r][q] *= sc[6 * ti + r] * sc[6 * tj + q];
+  }
+  int bad_k = -1;
+  double bad_v = 0.0;
+  for (int kb = 0; kb < BD / 6; ++kb) {
+#pragma unroll
+    for (int kr = 0; kr < 6; ++kr) {
+      const int k = 6 * kb + kr;
+      double* cb = col[kr & 1];
+      if (act) {
+        if (tj == kb) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r) cb[6 * ti + r] = (ti == kb && r == kr) ? R[r][kr] - 1.0 : R[r][kr];
+          if (ti == kb) pv[kr & 1] = R[kr][kr];
+        } else if (ti == kb) {
+#pragma unroll
+          for (int q = 0; q < 6; ++q) cb[6 * tj + q] = R[kr][q];
+        }
+      }
+      __syncthreads();
+      const double p = pv[kr & 1];
+      if (bad_k < 0 && !(p > 0.0 && isfinite(p))) {
+        bad_k = k;
+        bad_v = p;
+      }
+      const double inv = rcp_nr(p);
+      if (act) {
+        double ci[6], cj[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) ci[r] = cb[6 * ti + r];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) cj[q] = cb[6 * tj + q] * inv;
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int q = 0; q < 6; ++q) R[r][q] -= ci[r] * cj[q];
+      }
     }
   }
+  if (bad_k >= 0 && t == 0) {
+    atomicOr(err, ERRB_NOT_SPD);
+    diag_report(dg, level == 0 ? 1 : 2, level, d, bad_k, bad_v);
+  }
+  // kappa = max_i M_ii B_ii = max_i of the scaled inverse's diagonal
+  double kap = 0.0;
+  if (dtile) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) kap = fmax(kap, 2.0 - R[r][r]);
+  }
+  for (int o = 32; o > 0; o >>= 1) kap = fmax(kap, __shfl_xor(kap, o));
+  if (lane == 0) red[0][wv] = kap;
+  // final values of A^-1 in R
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        R[r][q] = (dtile && r == q ? 2.0 - R[r][q] : -R[r][q]) * sc[6 * ti + r] * sc[6 * tj + q];
+  }
   __syncthreads();
-  switch (chosen) {
-    case MAS_F64: store_block<MAS_F64>(A, blk, scale, d, sig); break;
-    case MAS_F32: store_block<MAS_F32>(A, blk, scale, d, sig); break;
-    case MAS_BF16: store_block<MAS_BF16>(A, blk, scale, d, sig); break;
-    default: store_block<MAS_F16>(A, blk, scale, d, sig);
+  if (t == 0) {
+    const double k1 = fmax(fmax(red[0][0], red[0][1]), red[0][2]);
+    int pr = req;
+    while (guard > 0.0 && pr != MAS_F64 && !(k1 <= guard / (20.0 * prec_eps(pr))))
+      pr = (pr == MAS_F32) ? MAS_F64 : MAS_F32;
+    chosen = pr;
+    bprec[d] = uint8_t(pr);
+  }
+  __syncthreads();
+  const int P = chosen;
+  unsigned char* slot = reinterpret_cast<unsigned char*>(blk) + d * BLK_STRIDE;
+  if (P == MAS_BF16 || P == MAS_F16) {
+    // 16-bit storage keeps B_ij / (sig_i sig_j), sig_i = sqrt(B_ii)
+    if (dtile) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const float sgv = float(sqrt(R[r][r]));
+        sig[6 * ti + r] = sgv;
+        scale[d * BD + 6 * ti + r] = sgv;
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) R[r][q] /= double(sig[6 * ti + r]) * double(sig[6 * tj + q]);
+    }
+  }
+  if (!act) return;
+  switch (P) {
+    case MAS_F64: store_tile<MAS_F64>(slot, ti, tj, R); break;
+    case MAS_F32: store_tile<MAS_F32>(slot, ti, tj, R); break;
+    case MAS_BF16: store_tile<MAS_BF16>(slot, ti, tj, R); break;
+    default: store_tile<MAS_F16>(slot, ti, tj, R);
   }
 }
 
 static void launch_invert(Ctx& c, int l) {
   Level& Lv = c.lv[l];
-  k_invert_blocks<<<dim3(Lv.nsub), dim3(256), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, Lv.bprec, Lv.prec,
+  k_invert_blocks<<<dim3(Lv.nsub), dim3(INV_THREADS), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, Lv.bprec,
+                                                                 Lv.prec,
                                                          c.cfg.prec_guard, c.err, c.diag, l,
-                                                         l + 1 < c.L ? c.lv[l + 1].ndiag : nullptr);
-}
-
-mas_status launch_level0_build(Ctx& c) {
-  Level& L0 = c.lv[0];
-  k_assemble_l0<<<dim3(L0.nsub), dim3(256), 0, c.s>>>(c.N, c.tets, c.mass, c.hf64, c.tet_off, c.tet_list, c.bk,
-                                                      c.bgrad, c.bidx, c.bc_off, c.bc_list, L0.acc);
-  launch_invert(c, 0);
-  HIPCHK(hipGetLastError());
-  return MAS_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Coarse level l: A_(l) = C_(l) H_base C_(l)^T on the 32 nodes of each
-// level-l subdomain S.  The diagonal node blocks come from the level below
-// (block sums taken while inverting it).  The rest are pairs of different
-// nodes of S, which only tets and base contacts with at least two nodes in S
-// produce: a tet contributes chat_s^T Hf chat_u, where chat_s sums the dF/dx
-// coefficients of its vertices in node s; a contact k nhat_s nhat_u^T with
-// nhat_s the sum of its n_j in node s.  The items of S are split over
-// `splits` workgroups that accumulate in LDS (one LDS atomic per distinct
-// node pair and wavefront) and add their nonzero entries to the block.
-
-// adds b (node pair ls > lu) to A, summed first over the lanes of the
-// wavefront with the same pair while such groups are large; key < 0: nothing
-// to add.  Uniform control flow.
-__device__ __forceinline__ void wave_add_pair(double* A, int key, const double (&b)[3][3]) {
-  const int lane = threadIdx.x & 63;
-  while (true) {
-    const unsigned long long act = __ballot(key >= 0);
-    if (act == 0) break;
-    const int leader = __ffsll(act) - 1;
-    const int lk = __shfl(key, leader);
-    const bool mine = key == lk;
-    if (__popcll(__ballot(mine)) < 4) {  // mostly distinct pairs: add directly
-      if (key >= 0) {
-        const int ls = key >> 5, lu = key & 31;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * ls + a, 3 * lu + q)], b[a][q]);
-      }
-      break;
-    }
-    double t[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) t[a][q] = wave_sum(mine ? b[a][q] : 0.0);
-    if (lane == leader) {
-      const int ls = lk >> 5, lu = lk & 31;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * ls + a, 3 * lu + q)], t[a][q]);
-    }
-    if (mine) key = -1;
-  }
-}
-
-// the first index j' <= j of a stencil vertex in the same node as j
-__device__ __forceinline__ void node_leaders(const int (&nd)[4], int (&lead)[4]) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    lead[j] = j;
-#pragma unroll
-    for (int i = 3; i >= 0; --i)
-      if (i < j && nd[i] == nd[j]) lead[j] = i;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_assemble_coarse(int l, int64_t nodes, int splits, const double* ndiag,
-                                                         const int32_t* tets, const double* hf64,
-                                                         const int32_t* xt_off, const int32_t* xt_list,
-                                                         const double* bk, const double* bgrad, const int32_t* bidx,
-                                                         const int32_t* xc_off, const int32_t* xc_list,
-                                                         double* acc) {
-  __shared__ double A[PK];
-  const int64_t S = blockIdx.x;
-  const int part = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int ns = 5 * l;
-  for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
-  __syncthreads();
-  if (part == 0 && tid < SUB) {
-    const int64_t a = SUB * S + tid;
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-      for (int y = 0; y <= x; ++y)
-        A[pk(3 * tid + x, 3 * tid + y)] = (a < nodes) ? ndiag[9 * a + 3 * x + y] : (x == y ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  {
-    const int o = xt_off[S], n = xt_off[S + 1] - o;
-    const int lo = o + int(int64_t(n) * part / splits), hi = o + int(int64_t(n) * (part + 1) / splits);
-    for (int w0 = lo; w0 < hi; w0 += blockDim.x) {
-      const int w = w0 + tid;
-      const bool ok = w < hi;
-      const int64_t t = ok ? xt_list[w] : 0;
-      int nd[4], lead[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) nd[j] = ok ? (tets[4 * t + j] >> ns) : -1;
-      node_leaders(nd, lead);
-      double H[45], Dmi[9], coef[4][3];
-      load_snapshot(hf64, t, H, Dmi);
-      dfdx_coef(Dmi, coef);
-      double ch[4][3];
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          double sum = 0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (lead[j] == s) sum += coef[j][b];
-          ch[s][b] = sum;
-        }
-#pragma unroll
-      for (int s = 1; s < 4; ++s)
-#pragma unroll
-        for (int u = 0; u < s; ++u) {
-          const bool act = ok && lead[s] == s && lead[u] == u && (nd[s] >> 5) == S && (nd[u] >> 5) == S;
-          const int ls = nd[s] & 31, lu = nd[u] & 31;
-          const bool sw = ls < lu;  // store the pair with the larger local node first
-          double b[3][3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int ap = 0; ap < 3; ++ap) {
-              double sum = 0;
-#pragma unroll
-              for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-                for (int bp = 0; bp < 3; ++bp) sum += ch[s][bb] * H[p9(3 * bb + a, 3 * bp + ap)] * ch[u][bp];
-              b[a][ap] = sum;
-            }
-          if (sw) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-              for (int q = 0; q < a; ++q) {
-                const double x = b[a][q];
-                b[a][q] = b[q][a];
-                b[q][a] = x;
-              }
-          }
-          wave_add_pair(A, act ? (sw ? (lu << 5) | ls : (ls << 5) | lu) : -1, b);
-        }
-    }
-  }
-  {
-    const int o = xc_off[S], n = xc_off[S + 1] - o;
-    const int lo = o + int(int64_t(n) * part / splits), hi = o + int(int64_t(n) * (part + 1) / splits);
-    for (int w0 = lo; w0 < hi; w0 += blockDim.x) {
-      const int w = w0 + tid;
-      const bool ok = w < hi;
-      const int64_t ci = ok ? xc_list[w] : 0;
-      const double k = ok ? bk[ci] : 0.0;
-      const double* n = bgrad + 12 * ci;
-      int v[4], nd[4], lead[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[j] = ok ? bidx[4 * ci + j] : -1;
-        nd[j] = v[j] >= 0 ? (v[j] >> ns) : -1 - j;
-      }
-      node_leaders(nd, lead);
-      double nh[4][3];
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          double sum = 0;
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (lead[j] == s && v[j] >= 0) sum += n[3 * j + a];
-          nh[s][a] = sum;
-        }
-#pragma unroll
-      for (int s = 1; s < 4; ++s)
-#pragma unroll
-        for (int u = 0; u < s; ++u) {
-          const bool act = lead[s] == s && lead[u] == u && v[s] >= 0 && v[u] >= 0 && (nd[s] >> 5) == S &&
-                           (nd[u] >> 5) == S;
-          const int ls = nd[s] & 31, lu = nd[u] & 31;
-          const bool sw = ls < lu;
-          double b[3][3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) b[a][q] = sw ? k * nh[u][a] * nh[s][q] : k * nh[s][a] * nh[u][q];
-          wave_add_pair(A, act ? (sw ? (lu << 5) | ls : (ls << 5) | lu) : -1, b);
-        }
-    }
-  }
-  __syncthreads();
-  double* out = acc + S * PK;
-  if (splits == 1) {
-    for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
-  } else {
-    for (int e = tid; e < PK; e += blockDim.x)
-      if (A[e] != 0.0) unsafeAtomicAdd(&out[e], A[e]);
-  }
+                                                         l + 1 < c.L ? c.lv[l + 1].acc : nullptr);
 }
 
 __global__ void k_zero(double* p, int64_t n) {
@@ -731,16 +599,34 @@ __global__ void k_zero(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
+mas_status launch_level0_build(Ctx& c) {
+  Level& L0 = c.lv[0];
+  for (int l = 2; l < c.L; ++l) k_zero<<<dim3(256), dim3(256), 0, c.s>>>(c.lv[l].acc, c.lv[l].nsub * PK);
+  L0Args a{};
+  a.N = c.N;
+  a.L = c.L;
+  a.tets = c.tets;
+  a.mass = c.mass;
+  a.hf64 = c.hf64;
+  a.tet_off = c.tet_off;
+  a.tet_list = c.tet_list;
+  a.bk = c.bk;
+  a.bgrad = c.bgrad;
+  a.bidx = c.bidx;
+  a.bc_off = c.bc_off;
+  a.bc_list = c.bc_list;
+  for (int l = 0; l < c.L; ++l) a.acc[l] = c.lv[l].acc;
+  const size_t lds = sizeof(double) * size_t(std::max(c.L - 1, 1)) * SUB * 9;
+  k_assemble_l0<<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+  launch_invert(c, 0);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+// the coarse levels, in order: inverting level l completes the diagonal node
+// blocks of level l + 1
 mas_status launch_coarse_build(Ctx& c) {
-  for (int l = 1; l < c.L; ++l) {
-    Level& Lv = c.lv[l];
-    const int sp = Lv.splits;
-    if (sp > 1) k_zero<<<dim3(1024), dim3(256), 0, c.s>>>(Lv.acc, Lv.nsub * PK);
-    k_assemble_coarse<<<dim3(Lv.nsub, sp), dim3(256), 0, c.s>>>(l, Lv.nodes, sp, Lv.ndiag, c.tets, c.hf64,
-                                                                Lv.xt_off, Lv.xt_list, c.bk, c.bgrad, c.bidx,
-                                                                Lv.xc_off, Lv.xc_list, Lv.acc);
-    launch_invert(c, l);
-  }
+  for (int l = 1; l < c.L; ++l) launch_invert(c, l);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -5,42 +5,22 @@
 
 namespace mas {
 
-// subdomains of stencil i at a level (see bucket_by_subdomain); returns the
-// count and writes them to out[4]
-__device__ inline int stencil_buckets(int level, int64_t i, const int32_t* idx, const double* w,
-                                      const double* vec12, int out[4]) {
+// subdomains (v >> 5) of the vertices of stencil i (w[i] > 0) whose part of
+// vec12 is nonzero; returns the count and writes them to out[4]
+__device__ inline int stencil_buckets(int64_t i, const int32_t* idx, const double* w, const double* vec12,
+                                      int out[4]) {
   int n = 0;
   if (!(w[i] > 0.0)) return 0;
-  int v[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = idx[4 * i + j];
-  if (level == 0) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (v[j] < 0) continue;
-      const double* u = vec12 + 12 * i + 3 * j;
-      if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
-      int d = v[j] >> 5;
-      bool dup = false;
-      for (int q = 0; q < n; ++q) dup |= (out[q] == d);
-      if (!dup) out[n++] = d;
-    }
-    return n;
-  }
-  const int ns = 5 * level, ss = 5 * (level + 1);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (v[j] < 0) continue;
-    const int S = v[j] >> ss;
+    const int v = idx[4 * i + j];
+    if (v < 0) continue;
+    const double* u = vec12 + 12 * i + 3 * j;
+    if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
+    const int d = v >> 5;
     bool dup = false;
-    for (int q = 0; q < n; ++q) dup |= (out[q] == S);
-    if (dup) continue;
-    // a second, different node of the stencil inside S?
-    bool two = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (v[k] >= 0 && (v[k] >> ss) == S && (v[k] >> ns) != (v[j] >> ns)) two = true;
-    if (two) out[n++] = S;
+    for (int q = 0; q < n; ++q) dup |= (out[q] == d);
+    if (!dup) out[n++] = d;
   }
   return n;
 }
@@ -49,11 +29,11 @@ __device__ inline int stencil_buckets(int level, int64_t i, const int32_t* idx, 
 // bucket share one atomic (stencils arrive sorted by their smallest vertex,
 // so neighbouring lanes mostly share buckets, which at coarse levels are
 // few).  Every lane runs the loops, including those past the end.
-__global__ __launch_bounds__(256) void k_bucket_count(int level, int64_t m, const int32_t* idx, const double* w,
+__global__ __launch_bounds__(256) void k_bucket_count(int64_t m, const int32_t* idx, const double* w,
                                                       const double* vec12, int32_t* cnt) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   int b[4];
-  const int n = (i < m) ? stencil_buckets(level, i, idx, w, vec12, b) : 0;
+  const int n = (i < m) ? stencil_buckets(i, idx, w, vec12, b) : 0;
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -70,11 +50,11 @@ __global__ __launch_bounds__(256) void k_bucket_count(int level, int64_t m, cons
   }
 }
 
-__global__ __launch_bounds__(256) void k_bucket_fill(int level, int64_t m, const int32_t* idx, const double* w,
+__global__ __launch_bounds__(256) void k_bucket_fill(int64_t m, const int32_t* idx, const double* w,
                                                      const double* vec12, int32_t* cursor, int32_t* list) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   int b[4];
-  const int n = (i < m) ? stencil_buckets(level, i, idx, w, vec12, b) : 0;
+  const int n = (i < m) ? stencil_buckets(i, idx, w, vec12, b) : 0;
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
@@ -98,8 +78,8 @@ __global__ __launch_bounds__(256) void k_bucket_fill(int level, int64_t m, const
 }
 
 // The order of items inside a bucket follows the atomics of the fill pass;
-// every consumer is order independent (Top-K ranks by a total order, block
-// assembly adds with atomics).
+// every consumer is order independent up to the rounding order of sums (Top-K
+// ranks by a total order, block assembly adds with atomics).
 
 mas_status ensure_cub(Ctx& c, size_t bytes) {
   if (bytes <= c.cub_bytes) return MAS_OK;
@@ -111,14 +91,14 @@ mas_status ensure_cub(Ctx& c, size_t bytes) {
   return MAS_OK;
 }
 
-mas_status bucket_by_subdomain(Ctx& c, int level, int64_t m, const int32_t* idx, const double* w,
-                               const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
-  const int64_t D = c.lv[level].nsub;
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
+                               int32_t* cnt, int32_t* off, int32_t* list) {
+  const int64_t D = c.lv[0].nsub;
   HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (D + 1), c.s));
   if (m > 0) {
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
-    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(level, m, idx, w, vec12, cnt);
+    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt);
   }
   size_t bytes = 0;
   HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, cnt, off, int(D + 1), c.s));
@@ -130,7 +110,7 @@ mas_status bucket_by_subdomain(Ctx& c, int level, int64_t m, const int32_t* idx,
     HIPCHK(hipMemcpyAsync(cnt, off, sizeof(int32_t) * D, hipMemcpyDeviceToDevice, c.s));
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
-    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(level, m, idx, w, vec12, cnt, list);
+    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt, list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;

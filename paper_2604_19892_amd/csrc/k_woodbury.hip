@@ -251,7 +251,7 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
         c.bkey_sorted, c.bperm, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
     HIPCHK(hipGetLastError());
   }
-  st = bucket_by_subdomain(c, 0, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
+  st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
   if (st != MAS_OK) return st;
   const int64_t D = c.lv[0].nsub;
   if (rank_hist) HIPCHK(hipMemsetAsync(rank_hist, 0, sizeof(int32_t) * (c.K + 1), c.s));

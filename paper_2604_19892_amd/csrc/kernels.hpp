@@ -6,12 +6,10 @@
 namespace mas {
 
 // k_util.hip -----------------------------------------------------------
-// Buckets stencils (w[i] > 0) into per-subdomain lists of one level.  Level
-// 0: the distinct subdomains (v >> 5) of its vertices whose part of vec12 is
-// nonzero.  Level l >= 1: the distinct level-l subdomains (v >> 5(l+1))
-// holding at least two distinct level-l nodes (v >> 5l) of the stencil.
-mas_status bucket_by_subdomain(Ctx& c, int level, int64_t m, const int32_t* idx, const double* w,
-                               const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
+// Buckets stencils (w[i] > 0) into per-level-0-subdomain lists: the distinct
+// subdomains (v >> 5) of its vertices whose part of vec12 is nonzero.
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
+                               int32_t* cnt, int32_t* off, int32_t* list);
 mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
                      const int32_t* vals_in, int32_t* vals_out);
 mas_status ensure_cub(Ctx& c, size_t bytes);
