@@ -289,12 +289,12 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
 
   // device memory
   TRY(dalloc(&c->tets, 4 * T));
-  TRY(dalloc(&c->geo, 12 * T));
+  TRY(dalloc(&c->geo, 12 * c->Tpad));
   TRY(dalloc(&c->mass, N));
   TRY(dalloc(&c->tet_off, D0 + 1));
   TRY(dalloc(&c->tet_list, tlist.size()));
   TRY(dalloc(&c->hf64, EH * c->Tpad));
-  if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hf32, EH * c->Tpad));
+  if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hf32, 4 * SNAP_NC32 * c->Tpad));
   for (int l = 0; l < c->L; ++l) {
     Level& L = c->lv[l];
     TRY(dalloc_bytes(&L.blk, L.nsub * BLK_STRIDE));

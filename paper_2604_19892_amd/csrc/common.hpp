@@ -18,6 +18,8 @@ constexpr int MAXL = 6;                 // maximum MAS levels
 constexpr int MAXK = 32;                // maximum Woodbury rank per subdomain
 constexpr int EH = 54;                  // per-tet snapshot: 45 (9x9 packed) + 9 (Dm^-1)
 constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
+constexpr int SNAP_NC64 = EH / 2;       // 16-byte chunks per float64 snapshot (27)
+constexpr int SNAP_NC32 = (EH + 3) / 4; // 16-byte chunks per float32 snapshot (14, 2 entries padding)
 
 // sticky device error bits
 constexpr uint32_t ERRB_NOT_SPD = 1u;
@@ -44,6 +46,49 @@ __host__ __device__ inline constexpr size_t blk_elems(int p) {
 // every block occupies a slot of the float64 size; its stored precision is
 // recorded per block
 constexpr size_t BLK_STRIDE = blk_elems(MAS_F64) * 8;
+
+// Element snapshot layout (45 packed tangent entries, then Dm^-1): per tile
+// of 64 tets, 16-byte chunk c of every tet of the tile lies contiguously
+// (chunk-major, then tet), so a wavefront reads one chunk of 64 tets as one
+// 1 KiB access.
+__device__ __forceinline__ void snap_load(const double* hf, int64_t t, double (&e)[EH]) {
+  const double2* p = reinterpret_cast<const double2*>(hf) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
+#pragma unroll
+  for (int c = 0; c < SNAP_NC64; ++c) {
+    const double2 v = p[c * TILE];
+    e[2 * c] = v.x;
+    e[2 * c + 1] = v.y;
+  }
+}
+__device__ __forceinline__ void snap_load(const float* hf, int64_t t, float (&e)[4 * SNAP_NC32]) {
+  const float4* p = reinterpret_cast<const float4*>(hf) + (t / TILE) * (SNAP_NC32 * TILE) + (t % TILE);
+#pragma unroll
+  for (int c = 0; c < SNAP_NC32; ++c) {
+    const float4 v = p[c * TILE];
+    e[4 * c] = v.x;
+    e[4 * c + 1] = v.y;
+    e[4 * c + 2] = v.z;
+    e[4 * c + 3] = v.w;
+  }
+}
+
+// Per-tet rest data (Dm^-1 row-major, V, mu, lam): 12 doubles in the same
+// chunked tile layout (6 chunks of 2).
+constexpr int GEO_NC = 6;
+__device__ __forceinline__ void geo_load(const double* geo, int64_t t, double (&g)[12]) {
+  const double2* p = reinterpret_cast<const double2*>(geo) + (t / TILE) * (GEO_NC * TILE) + (t % TILE);
+#pragma unroll
+  for (int c = 0; c < GEO_NC; ++c) {
+    const double2 v = p[c * TILE];
+    g[2 * c] = v.x;
+    g[2 * c + 1] = v.y;
+  }
+}
+__device__ __forceinline__ void geo_store(double* geo, int64_t t, const double (&g)[12]) {
+  double2* p = reinterpret_cast<double2*>(geo) + (t / TILE) * (GEO_NC * TILE) + (t % TILE);
+#pragma unroll
+  for (int c = 0; c < GEO_NC; ++c) p[c * TILE] = make_double2(g[2 * c], g[2 * c + 1]);
+}
 
 // Stored block layout.  A symmetric 96x96 block is cut into 6x6 tiles: the
 // 120 tiles (bi, bj), bi > bj, numbered t = bi (bi - 1) / 2 + bj with their 36
@@ -279,10 +324,14 @@ struct Ctx {
 constexpr int SW_WIN = 1024;
 constexpr int SW_CHUNK = 1024;
 
+// (the two branches use different atomic scopes so that they stay an LDS
+// atomic and a global atomic rather than being merged into one generic one)
 __device__ __forceinline__ void sw_add(double* win, double* y, int vbase, int v, int a, double val) {
   const int lv = v - vbase;
-  if (lv >= 0 && lv < SW_WIN) atomicAdd(&win[3 * lv + a], val);
-  else atomicAdd(&y[3 * int64_t(v) + a], val);
+  if (lv >= 0 && lv < SW_WIN)
+    __hip_atomic_fetch_add(&win[3 * lv + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_fetch_add(&y[3 * int64_t(v) + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void sw_flush(const double* win, double* y, int vbase, int64_t N) {

@@ -8,24 +8,18 @@
 
 namespace mas {
 
-// r_1[3a+c] = sum of g over the 32 vertices of level-1 node a; levels >= 2
-// accumulate those sums into their nodes (zeroed beforehand).
-struct RestrictArgs {
-  int L;
-  double* r[MAXL];
-};
-
-__global__ void k_restrict(int64_t N, int64_t nodes1, const double* g, RestrictArgs ra) {
-  int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (q >= 3 * nodes1) return;
-  int64_t a = q / 3;
-  int c = int(q % 3);
+// Restriction C_(l) g (supplement Section 1.3), level by level: the value
+// of node a at level l (component c) is the sum over its 32 children at
+// level l - 1 (level 0: the vertices).
+__global__ void k_restrict(int64_t n_child, int64_t nodes, const double* child, double* out) {
+  const int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (q >= 3 * nodes) return;
+  const int64_t a = q / 3;
+  const int c = int(q % 3);
+  const int64_t v0 = SUB * a, v1 = min<int64_t>(v0 + SUB, n_child);
   double s = 0;
-  int64_t v0 = SUB * a;
-  int64_t v1 = v0 + SUB < N ? v0 + SUB : N;
-  for (int64_t v = v0; v < v1; ++v) s += g[3 * v + c];
-  ra.r[1][q] = s;
-  for (int l = 2; l < ra.L; ++l) atomicAdd(&ra.r[l][3 * (a >> (5 * (l - 1))) + c], s);
+  for (int64_t v = v0; v < v1; ++v) s += child[3 * v + c];
+  out[q] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -257,12 +251,11 @@ __global__ __launch_bounds__(NTILE) void k_apply_l0(FineArgs fa) {
 mas_status launch_apply(Ctx& c, const double* g, double* z) {
   ProfScope ps(c, MAS_T_APPLY);
   if (c.L > 1) {
-    RestrictArgs ra{};
-    ra.L = c.L;
-    for (int l = 1; l < c.L; ++l) ra.r[l] = c.lv[l].r;
-    for (int l = 2; l < c.L; ++l) HIPCHK(hipMemsetAsync(c.lv[l].r, 0, sizeof(double) * 3 * c.lv[l].nodes, c.s));
-    int64_t n1 = c.lv[1].nodes;
-    k_restrict<<<dim3((3 * n1 + 255) / 256), dim3(256), 0, c.s>>>(c.N, n1, g, ra);
+    for (int l = 1; l < c.L; ++l) {
+      const int64_t n = c.lv[l].nodes;
+      k_restrict<<<dim3((3 * n + 255) / 256), dim3(256), 0, c.s>>>(c.lv[l - 1].nodes, n,
+                                                                   l == 1 ? g : c.lv[l - 1].r, c.lv[l].r);
+    }
     CoarseBlocks cb{};
     cb.L = c.L;
     cb.first[1] = 0;

@@ -10,9 +10,8 @@ namespace mas {
 
 // ---------------------------------------------------------------------------
 // Element snapshot: per tet the 9x9 tangent of h^2 V Psi with its negative
-// eigenvalues clamped, packed (45), followed by Dm^-1 (9).  AoSoA layout:
-// tile t/64, component, lane t%64 - one wavefront reads a component with one
-// coalesced 512-byte (f64) access.
+// eigenvalues clamped, packed (45), followed by Dm^-1 (9), in the chunked
+// tile layout of snap_load.
 __global__ __launch_bounds__(64) void k_elem_hess(int64_t T, int64_t Tpad, const int32_t* tets,
                                                   const double* geo, const double* x, double h,
                                                   double* hf64, float* hf32) {
@@ -26,7 +25,8 @@ __global__ __launch_bounds__(64) void k_elem_hess(int64_t T, int64_t Tpad, const
       int v = tets[4 * t + j];
       for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * v + a];
     }
-    const double* g = geo + 12 * t;
+    double g[12];
+    geo_load(geo, t, g);
 #pragma unroll
     for (int q = 0; q < 9; ++q) Dmi[q] = g[q];
     double F[3][3];
@@ -41,16 +41,24 @@ __global__ __launch_bounds__(64) void k_elem_hess(int64_t T, int64_t Tpad, const
 #pragma unroll
     for (int q = 0; q < 9; ++q) Dmi[q] = 0.0;
   }
-  int64_t base = (t / TILE) * (EH * TILE) + (t % TILE);
+  double2* p64 = reinterpret_cast<double2*>(hf64) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
 #pragma unroll
-  for (int q = 0; q < 45; ++q) hf64[base + q * TILE] = H[q];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) hf64[base + (45 + q) * TILE] = Dmi[q];
+  for (int c = 0; c < SNAP_NC64; ++c) {
+    const int q0 = 2 * c, q1 = 2 * c + 1;
+    p64[c * TILE] = make_double2(q0 < 45 ? H[q0] : Dmi[q0 - 45], q1 < 45 ? H[q1] : Dmi[q1 - 45]);
+  }
   if (hf32) {
+    float4* p32 = reinterpret_cast<float4*>(hf32) + (t / TILE) * (SNAP_NC32 * TILE) + (t % TILE);
 #pragma unroll
-    for (int q = 0; q < 45; ++q) hf32[base + q * TILE] = float(H[q]);
+    for (int c = 0; c < SNAP_NC32; ++c) {
+      float v[4];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) hf32[base + (45 + q) * TILE] = float(Dmi[q]);
+      for (int k = 0; k < 4; ++k) {
+        const int q = 4 * c + k;
+        v[k] = q < 45 ? float(H[q]) : (q < EH ? float(Dmi[q - 45]) : 0.0f);
+      }
+      p32[c * TILE] = make_float4(v[0], v[1], v[2], v[3]);
+    }
   }
 }
 
@@ -61,13 +69,6 @@ mas_status launch_elem_hessians(Ctx& c, const double* x_base) {
   return MAS_OK;
 }
 
-__device__ inline void load_snapshot(const double* hf64, int64_t t, double* H, double* Dmi) {
-  int64_t base = (t / TILE) * (EH * TILE) + (t % TILE);
-#pragma unroll
-  for (int q = 0; q < 45; ++q) H[q] = hf64[base + q * TILE];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) Dmi[q] = hf64[base + (45 + q) * TILE];
-}
 
 // ---------------------------------------------------------------------------
 // Base contact set: copy, stiffness k = kappa b''(d) and columns sqrt(k) n.
@@ -261,14 +262,10 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
       }
     }
     if (!(need[0] || need[1] || need[2] || need[3])) continue;
-    const int64_t base = (t / TILE) * (EH * TILE) + (t % TILE);
-    double H[45], Dmi[9];
-#pragma unroll
-    for (int q = 0; q < 45; ++q) H[q] = a.hf64[base + q * TILE];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Dmi[q] = a.hf64[base + (45 + q) * TILE];
+    double H[EH];
+    snap_load(a.hf64, t, H);
     double coef[4][3];
-    dfdx_coef(Dmi, coef);
+    dfdx_coef(H + 45, coef);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (!need[j]) continue;

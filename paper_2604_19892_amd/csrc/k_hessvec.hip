@@ -30,12 +30,8 @@ __global__ __launch_bounds__(256) void k_hv_tets(int64_t N, int64_t T, const int
   for (int k = 0; k < SW_CHUNK; k += 256) {
     const int64_t t = t0 + k + threadIdx.x;
     if (t >= T) break;
-    const int64_t base = (t / TILE) * (EH * TILE) + (t % TILE);
-    TH H[45], Dmi[9];
-#pragma unroll
-    for (int q = 0; q < 45; ++q) H[q] = hf[base + q * TILE];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Dmi[q] = hf[base + (45 + q) * TILE];
+    TH H[sizeof(TH) == 8 ? EH : 4 * SNAP_NC32];
+    snap_load(hf, t, H);
     const int4 tv = reinterpret_cast<const int4*>(tets)[t];
     const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
     double ve[12];
@@ -44,7 +40,7 @@ __global__ __launch_bounds__(256) void k_hv_tets(int64_t N, int64_t T, const int
 #pragma unroll
       for (int a = 0; a < 3; ++a) ve[3 * j + a] = v[3 * vi[j] + a];
     double f[12];
-    elem_hv<TH>(H, Dmi, ve, f);
+    elem_hv<TH>(H, H + 45, ve, f);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll

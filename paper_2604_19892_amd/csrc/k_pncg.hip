@@ -72,7 +72,8 @@ __global__ __launch_bounds__(RB) void k_eg_tets(int64_t N, int64_t T, const int3
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
-      const double* gm = geo + 12 * t;
+      double gm[12];
+      geo_load(geo, t, gm);
       double Dmi[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) Dmi[q] = gm[q];

@@ -29,7 +29,7 @@ __global__ void k_rest(int64_t T, const int32_t* tets, const double* X, const do
   cross3(e3, e1, c31);
   cross3(e1, e2, c12);
   double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
-  double* g = geo + 12 * t;
+  double g[12];
   double id = 1.0 / det;
   for (int a = 0; a < 3; ++a) {
     g[0 * 3 + a] = c23[a] * id;
@@ -41,6 +41,7 @@ __global__ void k_rest(int64_t T, const int32_t* tets, const double* X, const do
   g[9] = vol;
   g[10] = Ev / (2.0 * (1.0 + nv));
   g[11] = Ev * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
+  geo_store(geo, t, g);
   double mq = rho[t] * vol * 0.25;
   for (int j = 0; j < 4; ++j) atomicAdd(&mass[v[j]], mq);
 }
