@@ -151,7 +151,8 @@ mas_status mas_destroy(void* p) {
   if (!p) return MAS_ERR_INVALID_ARG;
   Ctx* c = as_ctx(p);
   hipStreamSynchronize(c->s);
-  void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->tet_list, c->hf64, c->hf32, c->bkey,
+  void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->tet_list, c->rt_off, c->rbeg, c->vrange, c->ctr, c->rl_t, c->rl_tv,
+                  c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->hf64, c->bkey,
                   c->bkey_sorted, c->biota, c->bperm, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
@@ -259,31 +260,92 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   }
   const int64_t D0 = c->lv[0].nsub;
 
-  // level-0 subdomain -> touching tets
-  std::vector<int32_t> toff(D0 + 1, 0);
-  for (int64_t t = 0; t < T; ++t) {
-    int ds[4], n = 0;
-    for (int j = 0; j < 4; ++j) {
-      int d = tets[4 * t + j] >> 5;
-      bool dup = false;
-      for (int q = 0; q < n; ++q) dup |= ds[q] == d;
-      if (!dup) ds[n++] = d;
-    }
-    for (int q = 0; q < n; ++q) toff[ds[q] + 1]++;
-  }
-  for (int64_t d = 0; d < D0; ++d) toff[d + 1] += toff[d];
-  std::vector<int32_t> tlist(std::max<int32_t>(toff[D0], 1));
-  {
-    std::vector<int32_t> cur(toff.begin(), toff.end() - 1);
-    for (int64_t t = 0; t < T; ++t) {
-      int ds[4], n = 0;
+  // bucket (v / div) -> tets touching it, ascending tet order
+  auto tet_buckets = [&](int div, int64_t nb, std::vector<int32_t>& off, std::vector<int32_t>& list) {
+    auto buckets = [&](int64_t t, int* ds) {
+      int n = 0;
       for (int j = 0; j < 4; ++j) {
-        int d = tets[4 * t + j] >> 5;
+        const int d = tets[4 * t + j] / div;
         bool dup = false;
         for (int q = 0; q < n; ++q) dup |= ds[q] == d;
         if (!dup) ds[n++] = d;
       }
-      for (int q = 0; q < n; ++q) tlist[cur[ds[q]]++] = int32_t(t);
+      return n;
+    };
+    off.assign(nb + 1, 0);
+    int ds[4];
+    for (int64_t t = 0; t < T; ++t) {
+      const int n = buckets(t, ds);
+      for (int q = 0; q < n; ++q) off[ds[q] + 1]++;
+    }
+    for (int64_t d = 0; d < nb; ++d) off[d + 1] += off[d];
+    list.assign(std::max<int32_t>(off[nb], 1), 0);
+    std::vector<int32_t> cur(off.begin(), off.end() - 1);
+    for (int64_t t = 0; t < T; ++t) {
+      const int n = buckets(t, ds);
+      for (int q = 0; q < n; ++q) list[cur[ds[q]]++] = int32_t(t);
+    }
+  };
+  std::vector<int32_t> toff, tlist, roff, rlist;
+  tet_buckets(SUB, D0, toff, tlist);
+  // vertex ranges: cut greedily in vertex order so that each range is
+  // touched by about RANGE_TETS tets and spans at most RANGE_MAX vertices
+  std::vector<int32_t> rbeg, vrange(N);
+  {
+    std::vector<int32_t> voff(N + 1, 0), vt(4 * T);
+    for (int64_t q = 0; q < 4 * T; ++q) voff[tets[q] + 1]++;
+    for (int64_t v = 0; v < N; ++v) voff[v + 1] += voff[v];
+    std::vector<int32_t> cur(voff.begin(), voff.end() - 1);
+    for (int64_t t = 0; t < T; ++t)
+      for (int j = 0; j < 4; ++j) vt[cur[tets[4 * t + j]]++] = int32_t(t);
+    const int64_t target = RANGE_TETS;
+    std::vector<int32_t> mark(T, -1);
+    int64_t cnt = 0;
+    int32_t r = 0, start = 0;
+    rbeg.push_back(0);
+    for (int64_t v = 0; v < N; ++v) {
+      int64_t add = 0;
+      for (int32_t q = voff[v]; q < voff[v + 1]; ++q) add += mark[vt[q]] != r;
+      if (v > start && (cnt + add > target || v - start >= RANGE_MAX)) {
+        ++r;
+        start = int32_t(v);
+        rbeg.push_back(start);
+        cnt = 0;
+        add = voff[v + 1] - voff[v];
+      }
+      for (int32_t q = voff[v]; q < voff[v + 1]; ++q) mark[vt[q]] = r;
+      cnt += add;
+      vrange[v] = r;
+    }
+    rbeg.push_back(int32_t(N));
+    c->nrange = int64_t(rbeg.size()) - 1;
+    c->rmax = 0;
+    for (int64_t q = 0; q < c->nrange; ++q) c->rmax = std::max(c->rmax, rbeg[q + 1] - rbeg[q]);
+  }
+  {
+    // range -> touching tets, ascending tet order
+    roff.assign(c->nrange + 1, 0);
+    auto ranges = [&](int64_t t, int* ds) {
+      int n = 0;
+      for (int j = 0; j < 4; ++j) {
+        const int d = vrange[tets[4 * t + j]];
+        bool dup = false;
+        for (int q = 0; q < n; ++q) dup |= ds[q] == d;
+        if (!dup) ds[n++] = d;
+      }
+      return n;
+    };
+    int ds[4];
+    for (int64_t t = 0; t < T; ++t) {
+      const int n = ranges(t, ds);
+      for (int q = 0; q < n; ++q) roff[ds[q] + 1]++;
+    }
+    for (int64_t d = 0; d < c->nrange; ++d) roff[d + 1] += roff[d];
+    rlist.assign(std::max<int32_t>(roff[c->nrange], 1), 0);
+    std::vector<int32_t> cur(roff.begin(), roff.end() - 1);
+    for (int64_t t = 0; t < T; ++t) {
+      const int n = ranges(t, ds);
+      for (int q = 0; q < n; ++q) rlist[cur[ds[q]]++] = int32_t(t);
     }
   }
 
@@ -293,8 +355,22 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->mass, N));
   TRY(dalloc(&c->tet_off, D0 + 1));
   TRY(dalloc(&c->tet_list, tlist.size()));
+  TRY(dalloc(&c->rt_off, c->nrange + 1));
+  TRY(dalloc(&c->rbeg, c->nrange + 1));
+  TRY(dalloc(&c->vrange, N));
+  TRY(dalloc(&c->ctr, 4));
+  HIPCHK(hipMemcpy(c->rbeg, rbeg.data(), rbeg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->vrange, vrange.data(), vrange.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  c->nent = int64_t(roff[c->nrange]);
+  c->nent_pad = std::max<int64_t>((c->nent + TILE - 1) / TILE * TILE, TILE);
+  TRY(dalloc(&c->rl_t, c->nent_pad));
+  TRY(dalloc(&c->rl_tv, 4 * c->nent_pad));
+  TRY(dalloc(&c->rl_geo, 12 * c->nent_pad));
+  TRY(dalloc(&c->rc_cnt, c->nrange + 1));
+  TRY(dalloc(&c->rc_off, c->nrange + 1));
   TRY(dalloc(&c->hf64, EH * c->Tpad));
-  if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hf32, 4 * SNAP_NC32 * c->Tpad));
+  if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hr32, 4 * SNAP_NC32 * c->nent_pad));
+  else TRY(dalloc(&c->hr64, EH * c->nent_pad));
   for (int l = 0; l < c->L; ++l) {
     Level& L = c->lv[l];
     TRY(dalloc_bytes(&L.blk, L.nsub * BLK_STRIDE));
@@ -316,6 +392,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->slots, D0 * Kk));
   TRY(dalloc(&c->W, size_t(D0) * Kk * BD));
   TRY(dalloc(&c->Lcap, D0 * (Kk * (Kk + 1) / 2)));
+  c->n_partial_blocks = int(std::max<int64_t>(1024, c->nrange));
   TRY(dalloc(&c->partials, 16 * c->n_partial_blocks));
   TRY(dalloc(&c->scal, 64));
   TRY(dalloc(&c->alpha, D0));
@@ -329,6 +406,23 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   HIPCHK(hipMemcpyAsync(c->tets, tets.data(), 4 * T * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->tet_off, toff.data(), (D0 + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->tet_list, tlist.data(), tlist.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->rt_off, roff.data(), roff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  {
+    // entries: tet id (home flag in bit 31) and its vertices
+    std::vector<int32_t> et(c->nent_pad, 0), etv(4 * c->nent_pad, 0);
+    for (int64_t r = 0; r < c->nrange; ++r)
+      for (int32_t w = roff[r]; w < roff[r + 1]; ++w) {
+        const int64_t t = rlist[w];
+        int vmin = tets[4 * t];
+        for (int j = 0; j < 4; ++j) {
+          etv[4 * w + j] = tets[4 * t + j];
+          vmin = std::min(vmin, tets[4 * t + j]);
+        }
+        et[w] = int32_t(t) | ((vrange[vmin] == r) ? int32_t(0x80000000u) : 0);
+      }
+    HIPCHK(hipMemcpy(c->rl_t, et.data(), et.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->rl_tv, etv.data(), etv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   double *dX = nullptr, *drho = nullptr, *dE = nullptr, *dnu = nullptr;
   TRY(dalloc(&dX, 3 * N));
   TRY(dalloc(&drho, T));
@@ -350,6 +444,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   }
   // scan temporaries for the subdomain buckets, sized once
   TRY(bucket_by_subdomain(*c, 0, nullptr, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
+  TRY(bucket_stencils(*c, 1, c->vrange, c->nrange, 0, nullptr, nullptr, nullptr, c->rc_cnt, c->rc_off, nullptr));
   HIPCHK(hipStreamSynchronize(c->s));
   if (perm_out) std::memcpy(perm_out, perm.data(), N * sizeof(int32_t));
   *ctx_out = c;

@@ -18,6 +18,13 @@ constexpr int MAXL = 6;                 // maximum MAS levels
 constexpr int MAXK = 32;                // maximum Woodbury rank per subdomain
 constexpr int EH = 54;                  // per-tet snapshot: 45 (9x9 packed) + 9 (Dm^-1)
 constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
+// Vertex ranges of the owner-computes products: range r owns the vertices
+// [rbeg[r], rbeg[r+1]) (at most RANGE_MAX of them) and writes their outputs
+// without atomics.  Ranges are cut so that each is touched by about
+// RANGE_TETS tets; resident workgroups take ranges from a counter until all
+// are done.
+constexpr int RANGE_MAX = 1024;
+constexpr int RANGE_TETS = 1024;
 constexpr int SNAP_NC64 = EH / 2;       // 16-byte chunks per float64 snapshot (27)
 constexpr int SNAP_NC32 = (EH + 3) / 4; // 16-byte chunks per float32 snapshot (14, 2 entries padding)
 
@@ -270,10 +277,21 @@ struct Ctx {
   double* mass = nullptr;      // N
   int32_t* tet_off = nullptr;  // D0+1, level-0 subdomain -> touching tets
   int32_t* tet_list = nullptr;
+  int rmax = 0;                // largest range (vertices)
+  int64_t nrange = 0;          // vertex ranges
+  int32_t* rbeg = nullptr;     // nrange+1 range starts
+  int32_t* vrange = nullptr;   // N: range of each vertex
+  uint32_t* ctr = nullptr;     // work counters of the range kernels (4)
+  int32_t* rt_off = nullptr;   // nrange+1, range -> its entries [rt_off[r], rt_off[r+1])
+  int64_t nent = 0, nent_pad = 0;  // entries: (range, tet touching it), range-major
+  int32_t* rl_t = nullptr;     // tet of each entry, bit 31 set on the entry of its smallest vertex's range
+  int32_t* rl_tv = nullptr;    // 4 vertices of the entry's tet
+  double* rl_geo = nullptr;    // rest data per entry (chunked tile layout over entries)
+  double* hr64 = nullptr;      // element snapshot per entry, float64 Hessian storage
+  float* hr32 = nullptr;       // element snapshot per entry, float32 Hessian storage
 
   // Hessian snapshot (AoSoA tiles of 64 tets: [Tpad/64][54][64])
-  double* hf64 = nullptr;
-  float* hf32 = nullptr;
+  double* hf64 = nullptr;      // element snapshot per tet (float64), for the block assembly
   bool built = false;
 
   // base contact set
@@ -289,6 +307,9 @@ struct Ctx {
   int32_t* bc_cnt = nullptr;       // D0
   int32_t* bc_off = nullptr;       // D0+1
   int32_t* bc_list = nullptr;      // 4 mb
+  int32_t* rc_cnt = nullptr;       // nrange+1: range -> base stencils touching it
+  int32_t* rc_off = nullptr;
+  int32_t* rc_list = nullptr;      // 4 mb
 
   // current update (untruncated U) and the localized Woodbury data
   int64_t mc = 0, mc_cap = 0;
@@ -322,6 +343,7 @@ struct Ctx {
 // accumulated in LDS, the others (and finally the window) are added to the
 // global vector with atomics, which cuts global atomics several-fold.
 constexpr int SW_WIN = 1024;
+
 constexpr int SW_CHUNK = 1024;
 
 // (the two branches use different atomic scopes so that they stay an LDS

@@ -9,66 +9,70 @@
 namespace mas {
 
 // ---------------------------------------------------------------------------
-// Element snapshot: per tet the 9x9 tangent of h^2 V Psi with its negative
+// Element snapshots: per tet the 9x9 tangent of h^2 V Psi with its negative
 // eigenvalues clamped, packed (45), followed by Dm^-1 (9), in the chunked
-// tile layout of snap_load.
-__global__ __launch_bounds__(64) void k_elem_hess(int64_t T, int64_t Tpad, const int32_t* tets,
-                                                  const double* geo, const double* x, double h,
-                                                  double* hf64, float* hf32) {
-  int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (t >= Tpad) return;
-  double H[45];
-  double Dmi[9];
-  if (t < T) {
+// tile layout of snap_load.  One thread per range entry: it writes the
+// entry's copy for the Hessian-vector product (float32 or float64) and, on
+// the tet's home entry, the tet-indexed float64 copy used by the block
+// assembly.
+__global__ __launch_bounds__(64) void k_elem_hess(int64_t nent, int64_t nent_pad, const int32_t* rl_t,
+                                                  const int32_t* rl_tv, const double* rl_geo, const double* x,
+                                                  double h, double* hf64, double* hr64, float* hr32) {
+  const int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (w >= nent_pad) return;
+  double e[EH];
+#pragma unroll
+  for (int q = 0; q < EH; ++q) e[q] = 0.0;
+  int32_t tcode = 0;
+  if (w < nent) {
+    tcode = rl_t[w];
+    const int4 tv = reinterpret_cast<const int4*>(rl_tv)[w];
+    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
     double xe[12];
-    for (int j = 0; j < 4; ++j) {
-      int v = tets[4 * t + j];
-      for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * v + a];
-    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * v[j] + a];
     double g[12];
-    geo_load(geo, t, g);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Dmi[q] = g[q];
+    geo_load(rl_geo, w, g);
     double F[3][3];
-    def_grad(xe, Dmi, F);
+    def_grad(xe, g, F);
+    double H[45];
     snh_tangent_psd(F, g[10], g[11], H);
-    double s = h * h * g[9];
+    const double s = h * h * g[9];
 #pragma unroll
-    for (int q = 0; q < 45; ++q) H[q] *= s;
-  } else {
+    for (int q = 0; q < 45; ++q) e[q] = H[q] * s;
 #pragma unroll
-    for (int q = 0; q < 45; ++q) H[q] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Dmi[q] = 0.0;
+    for (int q = 0; q < 9; ++q) e[45 + q] = g[q];
   }
-  double2* p64 = reinterpret_cast<double2*>(hf64) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
-#pragma unroll
-  for (int c = 0; c < SNAP_NC64; ++c) {
-    const int q0 = 2 * c, q1 = 2 * c + 1;
-    p64[c * TILE] = make_double2(q0 < 45 ? H[q0] : Dmi[q0 - 45], q1 < 45 ? H[q1] : Dmi[q1 - 45]);
-  }
-  if (hf32) {
-    float4* p32 = reinterpret_cast<float4*>(hf32) + (t / TILE) * (SNAP_NC32 * TILE) + (t % TILE);
+  if (hr32) {
+    float4* p32 = reinterpret_cast<float4*>(hr32) + (w / TILE) * (SNAP_NC32 * TILE) + (w % TILE);
 #pragma unroll
     for (int c = 0; c < SNAP_NC32; ++c) {
-      float v[4];
+      float vv[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int q = 4 * c + k;
-        v[k] = q < 45 ? float(H[q]) : (q < EH ? float(Dmi[q - 45]) : 0.0f);
-      }
-      p32[c * TILE] = make_float4(v[0], v[1], v[2], v[3]);
+      for (int k = 0; k < 4; ++k) vv[k] = (4 * c + k < EH) ? float(e[4 * c + k]) : 0.0f;
+      p32[c * TILE] = make_float4(vv[0], vv[1], vv[2], vv[3]);
     }
+  } else {
+    double2* p64 = reinterpret_cast<double2*>(hr64) + (w / TILE) * (SNAP_NC64 * TILE) + (w % TILE);
+#pragma unroll
+    for (int c = 0; c < SNAP_NC64; ++c) p64[c * TILE] = make_double2(e[2 * c], e[2 * c + 1]);
+  }
+  if (tcode < 0) {
+    const int64_t t = tcode & 0x7fffffff;
+    double2* p64 = reinterpret_cast<double2*>(hf64) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
+#pragma unroll
+    for (int c = 0; c < SNAP_NC64; ++c) p64[c * TILE] = make_double2(e[2 * c], e[2 * c + 1]);
   }
 }
 
 mas_status launch_elem_hessians(Ctx& c, const double* x_base) {
-  k_elem_hess<<<dim3(c.Tpad / TILE), dim3(TILE), 0, c.s>>>(c.T, c.Tpad, c.tets, c.geo, x_base,
-                                                            c.cfg.h, c.hf64, c.hf32);
+  k_elem_hess<<<dim3(c.nent_pad / TILE), dim3(TILE), 0, c.s>>>(c.nent, c.nent_pad, c.rl_t, c.rl_tv, c.rl_geo,
+                                                               x_base, c.cfg.h, c.hf64, c.hr64, c.hr32);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }
-
 
 // ---------------------------------------------------------------------------
 // Base contact set: copy, stiffness k = kappa b''(d) and columns sqrt(k) n.
@@ -112,12 +116,12 @@ static mas_status grow_base(Ctx& c, int64_t m) {
   if (m <= c.mb_cap) return MAS_OK;
   int64_t cap = m + m / 4 + 1024;
   hipFree(c.bkey); hipFree(c.bkey_sorted); hipFree(c.biota); hipFree(c.bperm);
-  hipFree(c.bk); hipFree(c.bgrad); hipFree(c.bidx); hipFree(c.bu); hipFree(c.bc_list);
+  hipFree(c.bk); hipFree(c.bgrad); hipFree(c.bidx); hipFree(c.bu); hipFree(c.bc_list); hipFree(c.rc_list);
   bool ok = hipMalloc(&c.bkey, 8 * cap) == hipSuccess && hipMalloc(&c.bkey_sorted, 8 * cap) == hipSuccess &&
             hipMalloc(&c.biota, 4 * cap) == hipSuccess && hipMalloc(&c.bperm, 4 * cap) == hipSuccess &&
             hipMalloc(&c.bk, 8 * cap) == hipSuccess && hipMalloc(&c.bgrad, 96 * cap) == hipSuccess &&
             hipMalloc(&c.bidx, 16 * cap) == hipSuccess && hipMalloc(&c.bu, 96 * cap) == hipSuccess &&
-            hipMalloc(&c.bc_list, 16 * cap) == hipSuccess;
+            hipMalloc(&c.bc_list, 16 * cap) == hipSuccess && hipMalloc(&c.rc_list, 16 * cap) == hipSuccess;
   if (!ok) return MAS_ERR_OOM;
   c.mb_cap = cap;
   return MAS_OK;
@@ -137,7 +141,9 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
     st = sort_keys(c, m, c.bkey, c.bkey_sorted, c.biota, c.bperm);
     if (st != MAS_OK) return st;
   }
-  return bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
+  st = bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
+  if (st != MAS_OK) return st;
+  return bucket_stencils(c, 1, c.vrange, c.nrange, m, c.bidx, c.bk, c.bgrad, c.rc_cnt, c.rc_off, c.rc_list);
 }
 
 // ---------------------------------------------------------------------------

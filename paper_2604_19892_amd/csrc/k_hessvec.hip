@@ -1,53 +1,93 @@
-// Matrix-free product with the frozen Hessian snapshot:
+// Matrix-free product with the frozen Hessian snapshot (H~ of Section 4.1):
 //   y = M v + sum_e S_e^T H_e S_e v + sum_{c in base} k_c n_c (n_c^T v)
 //       [+ sum_c u_c (u_c^T v) for the current update columns].
 // H_e is never formed: each tet stores its projected 9x9 tangent (45) and
 // Dm^-1 (9) and applies B^T Hf B v on the fly, which moves 54 values per tet
 // instead of the 78 of a packed 12x12.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "elem.hpp"
 
 namespace mas {
 
-__global__ void k_mass_mul(int64_t n3, const double* mass, const double* v, double* y) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= n3) return;
-  y[i] = mass[i / 3] * v[i];
-}
-
-// Each workgroup applies SW_CHUNK consecutive tets (sorted by smallest
-// vertex) and scatters through an LDS window starting at the chunk's first
-// smallest vertex.
+// Owner-computes product over the vertex ranges: the workgroup of range r
+// applies every tet and every base stencil touching r, keeps only the rows of
+// its own vertices (LDS accumulation) and writes y for them together with
+// the mass term, so no output is ever written by two workgroups.  A tet
+// touching k ranges has k entries (about 1.4 on the test scenes), each with
+// its own copy of the snapshot, so a workgroup streams contiguous data.
+// Resident workgroups take ranges from a counter (dynamic balance); each
+// exits once the counter has passed the last range.
 template <typename TH>
-__global__ __launch_bounds__(256) void k_hv_tets(int64_t N, int64_t T, const int32_t* tets, const TH* hf,
-                                                 const double* v, double* y) {
-  __shared__ double win[3 * SW_WIN];
-  const int64_t t0 = int64_t(blockIdx.x) * SW_CHUNK;
-  const int4 f4 = reinterpret_cast<const int4*>(tets)[t0];
-  const int vbase = min(min(f4.x, f4.y), min(f4.z, f4.w));
-  for (int e = threadIdx.x; e < 3 * SW_WIN; e += blockDim.x) win[e] = 0.0;
-  __syncthreads();
-  for (int k = 0; k < SW_CHUNK; k += 256) {
-    const int64_t t = t0 + k + threadIdx.x;
-    if (t >= T) break;
-    TH H[sizeof(TH) == 8 ? EH : 4 * SNAP_NC32];
-    snap_load(hf, t, H);
-    const int4 tv = reinterpret_cast<const int4*>(tets)[t];
-    const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
-    double ve[12];
+__global__ __launch_bounds__(256, 4) void k_hv_range(int64_t nrange, const int32_t* rbeg, const int32_t* rt_off,
+                                                     const int32_t* rl_tv, const TH* hr, const int32_t* bidx,
+                                                     const double* bu, const int32_t* rc_off, const int32_t* rc_list,
+                                                     const double* mass, const double* v, double* y, uint32_t* ctr) {
+  __shared__ double win[3 * RANGE_MAX];
+  __shared__ int64_t cur;
+  constexpr int NH = sizeof(TH) == 8 ? EH : 4 * SNAP_NC32;
+  while (true) {
+    if (threadIdx.x == 0) cur = atomicAdd(ctr, 1u);
+    __syncthreads();
+    const int64_t r = cur;
+    if (r >= nrange) break;  // every workgroup ends here once the counter passes nrange
+    const int v0 = rbeg[r], nv = rbeg[r + 1] - v0;
+    for (int e = threadIdx.x; e < 3 * nv; e += blockDim.x) win[e] = 0.0;
+    __syncthreads();
+    const int t0 = rt_off[r], t1 = rt_off[r + 1];
+    for (int w = t0 + threadIdx.x; w < t1; w += blockDim.x) {
+      const int4 tv = reinterpret_cast<const int4*>(rl_tv)[w];
+      const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+      TH H[NH];
+      snap_load(hr, w, H);
+      double ve[12];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) ve[3 * j + a] = v[3 * vi[j] + a];
-    double f[12];
-    elem_hv<TH>(H, H + 45, ve, f);
+        for (int a = 0; a < 3; ++a) ve[3 * j + a] = v[3 * vi[j] + a];
+      double f[12];
+      elem_hv<TH>(H, H + 45, ve, f);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
+        const int lv = vi[j] - v0;
+        if (lv >= 0 && lv < nv) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) sw_add(win, y, vbase, vi[j], a, f[3 * j + a]);
+          for (int a = 0; a < 3; ++a) atomicAdd(&win[3 * lv + a], f[3 * j + a]);
+        }
+      }
+    }
+    const int c0 = rc_off[r], c1 = rc_off[r + 1];
+    for (int w = c0 + threadIdx.x; w < c1; w += blockDim.x) {
+      const int64_t i = rc_list[w];
+      const int4 iv = reinterpret_cast<const int4*>(bidx)[i];
+      const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+      double uu[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) uu[q] = bu[12 * i + q];
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (vi[j] < 0) continue;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s += uu[3 * j + a] * v[3 * vi[j] + a];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int lv = vi[j] - v0;
+        if (vi[j] >= 0 && lv >= 0 && lv < nv) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) atomicAdd(&win[3 * lv + a], s * uu[3 * j + a]);
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * nv; e += blockDim.x) {
+      const int64_t q = 3 * int64_t(v0) + e;
+      y[q] = mass[q / 3] * v[q] + win[e];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  sw_flush(win, y, vbase, N);
 }
 
 // rank-one stencil columns: y += u (u^T v), scattered through an LDS window
@@ -97,18 +137,17 @@ __global__ __launch_bounds__(256) void k_hv_cols(int64_t N, int64_t m, const int
 
 mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update) {
   ProfScope ps(c, MAS_T_HESSVEC);
-  int64_t n3 = 3 * c.N;
-  k_mass_mul<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, c.mass, v, y);
-  if (c.T > 0) {
+  {
     ProfScope pt(c, MAS_T_HV_TETS);
-    dim3 g((c.T + SW_CHUNK - 1) / SW_CHUNK), b(256);
-    if (c.hf32)
-      k_hv_tets<float><<<g, b, 0, c.s>>>(c.N, c.T, c.tets, c.hf32, v, y);
+    const int64_t grid = std::min<int64_t>(c.nrange, int64_t(c.n_cu) * 4);
+    k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr, 0u);
+    if (c.hr32)
+      k_hv_range<float><<<dim3(grid), dim3(256), 0, c.s>>>(c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr32, c.bidx, c.bu,
+                                                           c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
     else
-      k_hv_tets<double><<<g, b, 0, c.s>>>(c.N, c.T, c.tets, c.hf64, v, y);
+      k_hv_range<double><<<dim3(grid), dim3(256), 0, c.s>>>(c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr64, c.bidx,
+                                                            c.bu, c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
   }
-  if (c.mb > 0)
-    k_hv_cols<<<dim3((c.mb + SW_CHUNK - 1) / SW_CHUNK), dim3(256), 0, c.s>>>(c.N, c.mb, c.bidx, c.bu, v, y);
   if (with_update && c.have_update && c.mc > 0)
     k_hv_cols<<<dim3((c.mc + SW_CHUNK - 1) / SW_CHUNK), dim3(256), 0, c.s>>>(c.N, c.mc, c.Uidx, c.U, v, y);
   HIPCHK(hipGetLastError());

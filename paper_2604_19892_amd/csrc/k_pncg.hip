@@ -1,6 +1,8 @@
 // Per-iteration kernels around the preconditioner: energy and gradient of
 // the incremental potential, the 2x2 subspace step with its fallback and the
 // restart ratio, and the per-subdomain safe step.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "elem.hpp"
 
@@ -31,57 +33,64 @@ __device__ inline void block_reduce_store(double (&v)[NV], double* out, int nblk
 }
 
 // ----------------------------------------------------------- energy / grad
-// g = M (x - x~) and the inertia energy
-__global__ __launch_bounds__(RB) void k_eg_vertices(int64_t N, const double* mass, const double* x,
-                                                    const double* xt, double* g, double* part, int nblk) {
-  double e[1] = {0.0};
-  for (int64_t v = blockIdx.x * int64_t(RB) + threadIdx.x; v < N; v += int64_t(nblk) * RB) {
-    double m = mass[v];
-    for (int a = 0; a < 3; ++a) {
-      double dx = x[3 * v + a] - xt[3 * v + a];
-      if (g) g[3 * v + a] = m * dx;
-      e[0] += 0.5 * m * dx * dx;
-    }
-  }
-  block_reduce_store<1>(e, part, nblk);
-}
-
-// h^2 V Psi(F) and its gradient h^2 V P Dm^-T scattered to the vertices:
-// each workgroup takes SW_CHUNK consecutive tets and scatters through an LDS
-// window; the energy is reduced per workgroup in a fixed order
-__global__ __launch_bounds__(RB) void k_eg_tets(int64_t N, int64_t T, const int32_t* tets, const double* geo,
-                                                const double* x, double h2, double* g, double* part, int nblk) {
-  __shared__ double win[3 * SW_WIN];
-  double e[1] = {0.0};
+// Inertia and elasticity, owner-computes over the vertex ranges: workgroup r
+// takes its vertices' inertia term M (x - x~) and every tet touching r (its
+// range-major entries), accumulates the elastic gradient h^2 V P Dm^-T of its
+// own vertices in LDS and writes g for them (no atomics).  A tet's energy
+// h^2 V Psi(F) is counted by its home entry (the range of its smallest
+// vertex).  Energies are reduced per
+// range in a fixed order (part rows 0 and 1, one slot per range).
+__global__ __launch_bounds__(RB) void k_eg_range(int64_t nrange, const int32_t* rbeg, const int32_t* rl_t,
+                                                 const int32_t* rl_tv, const double* rl_geo, const int32_t* rt_off,
+                                                 const double* mass, const double* x, const double* xt, double h2,
+                                                 double* g, double* part, int nblk, uint32_t* ctr) {
+  __shared__ double win[3 * RANGE_MAX];
+  __shared__ double red[2][RB / 64];
+  __shared__ int64_t cur;
   const bool grad = g != nullptr;
-  for (int64_t chunk = blockIdx.x; chunk * SW_CHUNK < T; chunk += nblk) {
-    const int64_t t0 = chunk * SW_CHUNK;
-    const int4 f4 = reinterpret_cast<const int4*>(tets)[t0];
-    const int vbase = min(min(f4.x, f4.y), min(f4.z, f4.w));
-    if (grad) {
-      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0;
-      __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // partial slots past the last range stay zero
+  for (int64_t q = nrange + blockIdx.x * int64_t(RB) + threadIdx.x; q < nblk; q += int64_t(gridDim.x) * RB) {
+    part[q] = 0.0;
+    part[nblk + q] = 0.0;
+  }
+  while (true) {
+    if (threadIdx.x == 0) cur = atomicAdd(ctr, 1u);
+    __syncthreads();
+    const int64_t r = cur;
+    if (r >= nrange) break;  // every workgroup ends here once the counter passes nrange
+    double e[2] = {0.0, 0.0};
+    const int v0 = rbeg[r], nv = rbeg[r + 1] - v0;
+    for (int q = threadIdx.x; q < 3 * nv; q += RB) win[q] = 0.0;
+    for (int lv = threadIdx.x; lv < nv; lv += RB) {
+      const double m = mass[v0 + lv];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double dx = x[3 * int64_t(v0 + lv) + a] - xt[3 * int64_t(v0 + lv) + a];
+        e[0] += 0.5 * m * dx * dx;
+      }
     }
-    for (int k = 0; k < SW_CHUNK; k += RB) {
-      const int64_t t = t0 + k + threadIdx.x;
-      if (t >= T) break;
-      const int4 tv = reinterpret_cast<const int4*>(tets)[t];
+    __syncthreads();
+    const int t0 = rt_off[r], t1 = rt_off[r + 1];
+    for (int w = t0 + threadIdx.x; w < t1; w += RB) {
+      const int4 tv = reinterpret_cast<const int4*>(rl_tv)[w];
       const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
+      const bool own_e = rl_t[w] < 0;  // home entry of the tet
+      bool touch[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) touch[j] = grad && vi[j] >= v0 && vi[j] < v0 + nv;
       double xe[12];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
       double gm[12];
-      geo_load(geo, t, gm);
-      double Dmi[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) Dmi[q] = gm[q];
+      geo_load(rl_geo, w, gm);
       double F[3][3];
-      def_grad(xe, Dmi, F);
+      def_grad(xe, gm, F);
       const double s = h2 * gm[9];
-      e[0] += s * snh_energy(F, gm[10], gm[11]);
-      if (grad) {
+      if (own_e) e[1] += s * snh_energy(F, gm[10], gm[11]);
+      if (touch[0] || touch[1] || touch[2] || touch[3]) {
         double P[3][3];
         snh_stress(F, gm[10], gm[11], P);
         double f0[3] = {0, 0, 0};
@@ -91,23 +100,37 @@ __global__ __launch_bounds__(RB) void k_eg_tets(int64_t N, int64_t T, const int3
           for (int a = 0; a < 3; ++a) {
             double acc = 0;
 #pragma unroll
-            for (int b = 0; b < 3; ++b) acc += P[a][b] * Dmi[3 * cc + b];
+            for (int b = 0; b < 3; ++b) acc += P[a][b] * gm[3 * cc + b];
             acc *= s;
             f0[a] -= acc;
-            sw_add(win, g, vbase, vi[cc + 1], a, acc);
+            if (touch[cc + 1]) atomicAdd(&win[3 * (vi[cc + 1] - v0) + a], acc);
           }
         }
+        if (touch[0]) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) sw_add(win, g, vbase, vi[0], a, f0[a]);
+          for (int a = 0; a < 3; ++a) atomicAdd(&win[3 * (vi[0] - v0) + a], f0[a]);
+        }
       }
     }
-    if (grad) {
-      __syncthreads();
-      sw_flush(win, g, vbase, N);
-      __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double t = wave_sum(e[q]);
+      if (lane == 0) red[q][wv] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      double t = 0.0;
+      for (int i = 0; i < RB / 64; ++i) t += red[threadIdx.x][i];
+      part[threadIdx.x * int64_t(nblk) + r] = t;
+    }
+    if (grad) {
+      for (int q = threadIdx.x; q < 3 * nv; q += RB) {
+        const int64_t gq = 3 * int64_t(v0) + q;
+        g[gq] = mass[gq / 3] * (x[gq] - xt[gq]) + win[q];
+      }
+    }
+    __syncthreads();
   }
-  block_reduce_store<1>(e, part, nblk);
 }
 
 // kappa b(d) and kappa b'(d) grad d; a non-positive distance flags +inf.
@@ -202,8 +225,9 @@ mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const m
   ProfScope ps(c, MAS_T_ENERGY);
   const int nb = c.n_partial_blocks;
   double* part = c.partials;  // [0]: inertia [1]: elastic [2]: barrier [3]: infeasible count
-  k_eg_vertices<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, c.mass, x, xt, g, part, nb);
-  k_eg_tets<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, c.T, c.tets, c.geo, x, c.cfg.h * c.cfg.h, g, part + nb, nb);
+  k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr + 1, 0u);
+  k_eg_range<<<dim3(std::min<int64_t>(c.nrange, int64_t(c.n_cu) * 4)), dim3(RB), 0, c.s>>>(
+      c.nrange, c.rbeg, c.rl_t, c.rl_tv, c.rl_geo, c.rt_off, c.mass, x, xt, c.cfg.h * c.cfg.h, g, part, nb, c.ctr + 1);
   int64_t m = ct ? ct->m : 0;
   if (m > 0) {
     // writes part[2*nb..] (energy) and part[3*nb..] (infeasible count)

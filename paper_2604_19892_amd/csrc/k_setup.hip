@@ -46,11 +46,25 @@ __global__ void k_rest(int64_t T, const int32_t* tets, const double* X, const do
   for (int j = 0; j < 4; ++j) atomicAdd(&mass[v[j]], mq);
 }
 
+// rest data copied to the range-major entries (padding entries zero)
+__global__ void k_geo_entries(int64_t nent, int64_t nent_pad, const int32_t* rl_t, const double* geo,
+                              double* rl_geo) {
+  const int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (w >= nent_pad) return;
+  double g[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) g[q] = 0.0;
+  if (w < nent) geo_load(geo, rl_t[w] & 0x7fffffff, g);
+  geo_store(rl_geo, w, g);
+}
+
 mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E,
                        const double* nu) {
   HIPCHK(hipMemsetAsync(c.mass, 0, sizeof(double) * c.N, c.s));
   int bs = 256;
   k_rest<<<dim3((c.T + bs - 1) / bs), dim3(bs), 0, c.s>>>(c.T, c.tets, X, rho, E, nu, c.geo, c.mass);
+  k_geo_entries<<<dim3((c.nent_pad + bs - 1) / bs), dim3(bs), 0, c.s>>>(c.nent, c.nent_pad, c.rl_t, c.geo,
+                                                                        c.rl_geo);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

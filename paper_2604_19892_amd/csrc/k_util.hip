@@ -5,10 +5,10 @@
 
 namespace mas {
 
-// subdomains (v >> 5) of the vertices of stencil i (w[i] > 0) whose part of
-// vec12 is nonzero; returns the count and writes them to out[4]
-__device__ inline int stencil_buckets(int64_t i, const int32_t* idx, const double* w, const double* vec12,
-                                      int out[4]) {
+// buckets (map ? map[v] : v / div) of the vertices of stencil i (w[i] > 0)
+// whose part of vec12 is nonzero; returns the count and writes them to out[4]
+__device__ inline int stencil_buckets(int div, const int32_t* map, int64_t i, const int32_t* idx, const double* w,
+                                      const double* vec12, int out[4]) {
   int n = 0;
   if (!(w[i] > 0.0)) return 0;
 #pragma unroll
@@ -17,7 +17,7 @@ __device__ inline int stencil_buckets(int64_t i, const int32_t* idx, const doubl
     if (v < 0) continue;
     const double* u = vec12 + 12 * i + 3 * j;
     if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
-    const int d = v >> 5;
+    const int d = map ? map[v] : v / div;
     bool dup = false;
     for (int q = 0; q < n; ++q) dup |= (out[q] == d);
     if (!dup) out[n++] = d;
@@ -29,11 +29,11 @@ __device__ inline int stencil_buckets(int64_t i, const int32_t* idx, const doubl
 // bucket share one atomic (stencils arrive sorted by their smallest vertex,
 // so neighbouring lanes mostly share buckets, which at coarse levels are
 // few).  Every lane runs the loops, including those past the end.
-__global__ __launch_bounds__(256) void k_bucket_count(int64_t m, const int32_t* idx, const double* w,
+__global__ __launch_bounds__(256) void k_bucket_count(int div, const int32_t* map, int64_t m, const int32_t* idx, const double* w,
                                                       const double* vec12, int32_t* cnt) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   int b[4];
-  const int n = (i < m) ? stencil_buckets(i, idx, w, vec12, b) : 0;
+  const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -50,11 +50,11 @@ __global__ __launch_bounds__(256) void k_bucket_count(int64_t m, const int32_t* 
   }
 }
 
-__global__ __launch_bounds__(256) void k_bucket_fill(int64_t m, const int32_t* idx, const double* w,
+__global__ __launch_bounds__(256) void k_bucket_fill(int div, const int32_t* map, int64_t m, const int32_t* idx, const double* w,
                                                      const double* vec12, int32_t* cursor, int32_t* list) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   int b[4];
-  const int n = (i < m) ? stencil_buckets(i, idx, w, vec12, b) : 0;
+  const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
@@ -81,6 +81,8 @@ __global__ __launch_bounds__(256) void k_bucket_fill(int64_t m, const int32_t* i
 // every consumer is order independent up to the rounding order of sums (Top-K
 // ranks by a total order, block assembly adds with atomics).
 
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
 mas_status ensure_cub(Ctx& c, size_t bytes) {
   if (bytes <= c.cub_bytes) return MAS_OK;
   if (c.cub_tmp) HIPCHK(hipFree(c.cub_tmp));
@@ -91,14 +93,13 @@ mas_status ensure_cub(Ctx& c, size_t bytes) {
   return MAS_OK;
 }
 
-mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
-                               int32_t* cnt, int32_t* off, int32_t* list) {
-  const int64_t D = c.lv[0].nsub;
+mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
+                           const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
   HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (D + 1), c.s));
   if (m > 0) {
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
-    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt);
+    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(div, map, m, idx, w, vec12, cnt);
   }
   size_t bytes = 0;
   HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, cnt, off, int(D + 1), c.s));
@@ -110,10 +111,15 @@ mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const doub
     HIPCHK(hipMemcpyAsync(cnt, off, sizeof(int32_t) * D, hipMemcpyDeviceToDevice, c.s));
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
-    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(m, idx, w, vec12, cnt, list);
+    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(div, map, m, idx, w, vec12, cnt, list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;
+}
+
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
+                               int32_t* cnt, int32_t* off, int32_t* list) {
+  return bucket_stencils(c, SUB, nullptr, c.lv[0].nsub, m, idx, w, vec12, cnt, off, list);
 }
 
 mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
