@@ -50,22 +50,72 @@ def apply_l0_bytes(ctx, counts, hist):
     return b
 
 
-def hv_tets_bytes(ctx, hess_prec):
+def hv_bytes(ctx, hess_prec, n_active):
+    """Algorithmic bytes of one Hessian-vector launch: every tet's snapshot
+    (45 tangent + 9 Dm^-1 entries in the Hessian storage precision) and its
+    four vertex indices once, every active base stencil's column (12 doubles)
+    and indices once, the lumped masses, v read and y written."""
     sH = 8 if hess_prec == "f64" else 4
-    return ctx.scene.T * (54 * sH + 16) + 2 * 8 * 3 * ctx.N
+    N = ctx.N
+    return ctx.scene.T * (54 * sH + 16) + n_active * (12 * 8 + 16) + 8 * N + 2 * 8 * 3 * N
 
 
-def traffic_record(kernel_src):
-    """Measured HBM bytes per launch from rocprofv3 counters, if they were
-    taken on the current source of the kernel."""
-    path = os.path.join(ROOT, "profiles", "apply_l0_traffic.json")
-    if not os.path.exists(path):
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = {"k_apply_l0": "k_apply.hip", "k_hv_range": "k_hessvec.hip"}
+
+
+def _src_hash(kernel):
+    path = os.path.join(ROOT, "paper_2604_19892_amd", "csrc", KERNEL_SRC[kernel])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def traffic_record(kernel, prec, workload):
+    """Measured HBM bytes per launch of a kernel from rocprofv3 counters, if
+    they were taken on the kernel's current source and this workload."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    rec = json.load(open(path))
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != h:
+    rec = json.load(open(TRAFFIC_JSON)).get(kernel)
+    if not rec or rec.get("source_sha256") != _src_hash(kernel):
         return None
-    return rec
+    if rec.get("prec") != prec or rec.get("workload") != workload:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def traffic_from_counters(fetch_dir, write_dir, prec, workload):
+    """Writes profiles/traffic.json from two rocprofv3 --pmc runs of
+    `bench.py --copy-probe` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
+    Each counter is scaled by what it reads for the 1 GiB device copy of the
+    probe (known size) and averaged over the kernel's dispatches."""
+    import csv
+    import glob
+    import numpy as np
+
+    def per_kernel(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = per_kernel(d, counter)
+        copy = max(v for k, vs in vals.items() if "copyBuffer" in k for v in vs)
+        scale = (1 << 30) / (copy * 1024.0)
+        for kern in KERNEL_SRC:
+            vs = [v for k, v_ in vals.items() if kern in k for v in v_]
+            if vs:
+                e = out.setdefault(kern, {"prec": prec, "workload": workload, "source_sha256": _src_hash(kern)})
+                e[counter.lower() + "_bytes"] = float(np.mean(vs)) * 1024.0 * scale
+                e[counter.lower() + "_scale"] = scale
+                e["dispatches"] = len(vs)
+    for e in out.values():
+        e["bytes_per_launch"] = e.get("fetch_size_bytes", 0.0) + e.get("write_size_bytes", 0.0)
+    json.dump(out, open(TRAFFIC_JSON, "w"), indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(full_N, iters=3):
@@ -98,7 +148,15 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="two-boxes scene instead (quick check)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (reference size for rocprofv3 byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc output folders and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.prec,
+                              "two_boxes" if args.small else "puffer_balls")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
               file=sys.stderr)
@@ -153,12 +211,16 @@ def main():
     bytes_l0 = l0_bytes
     achieved = sum(bytes_l0) / (ms_l0 * 1e-3) / 1e9 if n_l0 else 0.0
     ms_hv, n_hv = timers["hv_tets"]
-    hv_b = hv_tets_bytes(ctx, hess_prec)
+    n_active = int(((solver.pool.d > 0) & (solver.pool.d < sc.dhat)).sum().item())
+    hv_b = hv_bytes(ctx, hess_prec, n_active)
     hv_achieved = n_hv * hv_b / (ms_hv * 1e-3) / 1e9 if n_hv else 0.0
-    tr = traffic_record(os.path.join(ROOT, "paper_2604_19892_amd", "csrc", "k_apply.hip"))
-    traffic = None
-    if tr and tr.get("prec") == args.prec and tr.get("workload") == workload:
-        traffic = tr.get("bytes_per_launch")
+    traffic = traffic_record("k_apply_l0", args.prec, workload)
+    traffic_hv = traffic_record("k_hv_range", args.prec, workload)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
 
     out = {
         "metric": METRIC,
@@ -190,8 +252,9 @@ def main():
             "launches": int(n_l0), "avg_us": 1e3 * ms_l0 / max(n_l0, 1),
         },
         "roofline_hess_vec": {
-            "kernel": "k_hv_tets", "bound": "hbm", "achieved": hv_achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": hv_achieved / HBM_PEAK_GBS, "bytes_per_launch": hv_b,
+            "kernel": "k_hv_range (tets, base stencils and mass of hess_vec)", "bound": "hbm",
+            "achieved": hv_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv_achieved / HBM_PEAK_GBS,
+            "traffic": traffic_hv, "bytes_per_launch": hv_b, "active_base_stencils": n_active,
             "launches": int(n_hv), "avg_us": 1e3 * ms_hv / max(n_hv, 1),
         },
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in timers.items()},

@@ -182,14 +182,16 @@ struct FineArgs {
 __global__ __launch_bounds__(NTILE) void k_apply_l0(FineArgs fa) {
   __shared__ double xs[BD];
   __shared__ __align__(16) double part[16 * PB];
-  __shared__ double zb[BD];
-  __shared__ double rr[MAXK];
-  __shared__ double lam[MAXK];
-  __shared__ double Lf[MAXK * (MAXK + 1) / 2];
-  __shared__ SlotCol sl[MAXK];
+  // Woodbury scratch sized by K: factor, r, lambda, slot columns
+  extern __shared__ __align__(16) double wdyn[];
+  const int K = fa.K;
+  double* Lf = wdyn;
+  double* rr = Lf + K * (K + 1) / 2;
+  double* lam = rr + K;
+  SlotCol* sl = reinterpret_cast<SlotCol*>(lam + K + ((K * (K + 1) / 2 + 2 * K) & 1));
+  double* zb = part;  // the base product, after the partials are consumed
   const int64_t d = blockIdx.x;
   const int t = threadIdx.x;
-  const int K = fa.K;
   const int r = fa.rank ? fa.rank[d] : 0;
   if (r > 0) {
     const double* Lm = fa.Lcap + d * (K * (K + 1) / 2);
@@ -209,6 +211,7 @@ __global__ __launch_bounds__(NTILE) void k_apply_l0(FineArgs fa) {
   const unsigned char* slot = reinterpret_cast<const unsigned char*>(fa.blk) + d * BLK_STRIDE;
   double zv = block_apply_any(fa.bprec[d], slot, fa.scale + BD * d, xv, bi, bj, xs, part);
   if (r > 0) {
+    __syncthreads();
     if (t < BD) zb[t] = zv;
     __syncthreads();
     // r_j = u_j^T z_base over the stencil vertices inside the subdomain
@@ -286,7 +289,9 @@ mas_status launch_apply(Ctx& c, const double* g, double* z) {
   fa.L = c.L;
   for (int l = 1; l < c.L; ++l) fa.c[l] = c.lv[l].c;
   prof_begin(c, MAS_T_APPLY_L0);
-  k_apply_l0<<<dim3(c.lv[0].nsub), dim3(NTILE), 0, c.s>>>(fa);
+  const int K = std::max(c.K, 1);
+  const size_t wlds = sizeof(double) * size_t(K * (K + 1) / 2 + 2 * K + 1) + sizeof(SlotCol) * size_t(K);
+  k_apply_l0<<<dim3(c.lv[0].nsub), dim3(NTILE), wlds, c.s>>>(fa);
   prof_end(c, MAS_T_APPLY_L0);
   HIPCHK(hipGetLastError());
   return MAS_OK;

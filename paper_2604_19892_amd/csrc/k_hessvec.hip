@@ -137,10 +137,10 @@ __global__ __launch_bounds__(256) void k_hv_cols(int64_t N, int64_t m, const int
 
 mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update) {
   ProfScope ps(c, MAS_T_HESSVEC);
+  k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr, 0u);
   {
     ProfScope pt(c, MAS_T_HV_TETS);
     const int64_t grid = std::min<int64_t>(c.nrange, int64_t(c.n_cu) * 4);
-    k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr, 0u);
     if (c.hr32)
       k_hv_range<float><<<dim3(grid), dim3(256), 0, c.s>>>(c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr32, c.bidx, c.bu,
                                                            c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
