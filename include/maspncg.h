@@ -199,12 +199,16 @@ mas_status mas_inertial_target(void* ctx, const double* x_t, const double* v_t, 
 mas_status mas_stencil_distance(void* ctx, const double* x, int64_t m, const int32_t* idx,
                                 const double* grad, const double* off, double* d_out);
 
-/* Per-subdomain safe steps for affine stencils (cand): alpha_c = min(1,
- * 0.9 d_c / sum_j max(0, -grad_cj . p_j)), alpha_d = min(1, min over stencils
+/* Per-subdomain safe steps for affine stencils (cand; Section 4.4 and
+ * supplement Section 3, relative displacement of the stencil's vertices):
+ * a stencil closing at the rate s_c = -sum_j grad_cj . p_j > 0 allows
+ * alpha_c = max(0, min(1, 0.9 d_c / s_c)); alpha_d = min(1, min over stencils
  * touching subdomain d).  Writes x_out = x + scale * alpha_{sub(v)} p_v
- * (device, 3N).  cand == NULL reuses the step sizes of the previous call
- * (line-search halving only changes scale).  alpha (device, D_0, nullable)
- * receives the step sizes. */
+ * (device, 3N).  Vertices of one stencil in different subdomains may move
+ * with different steps; the caller's energy check (E = +inf at d <= 0)
+ * rejects trial points that close a stencil.  cand == NULL reuses the step
+ * sizes of the previous call (line-search halving only changes scale).
+ * alpha (device, D_0, nullable) receives the step sizes. */
 mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_contacts* cand,
                          double scale, double* alpha, double* x_out);
 

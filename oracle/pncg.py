@@ -12,12 +12,16 @@ Test infrastructure (see the package docstring).
   supplement's alternative (mu = 1 on the very first iteration) is not used;
   mu = 1, nu = 0 is also taken when z^T H~ z <= 0.
 * Restart ratio (Section 4.3): r_k = |g_{k+1}^T z_k| / (g_{k+1}^T z_{k+1}).
-* Safe step: the paper's per-subdomain conservative CCD is not part of this
-  path; for affine stencils each candidate c gets
-  a_c = min(1, 0.9 d_c / sum_j max(0, -grad_{c,j} . p_j)), which keeps d_c
-  positive for any per-vertex steps in [0, a_c]; a subdomain takes the
-  minimum over the candidates touching it (Algorithm 1, per-subdomain
-  steps).
+* Safe step (Section 4.4, supplement Section 3): the cubic CCD of the paper
+  reduces to a linear time of contact for affine stencils.  Candidate c
+  closes at the rate s_c = -sum_j grad_{c,j} . p_j (the relative
+  displacement of its vertices, so a common translation does not count) and
+  gets a_c = max(0, min(1, 0.9 d_c / s_c)) when s_c > 0; a subdomain takes
+  the minimum over the candidates touching it (Algorithm 1, per-subdomain
+  steps).  A common step keeps every d_c >= 0.1 d_c; where the subdomains of
+  one stencil move with different steps and the combined motion would bring
+  it below 0.05 d_c, the steps of those subdomains are halved, repeatedly
+  (at most 40 rounds), so that only the critical subdomains are damped.
 """
 from __future__ import annotations
 
@@ -65,25 +69,54 @@ def restart_ratio(g_new, z_prev, z_new):
     return abs(float(g_new @ z_prev)) / float(g_new @ z_new)
 
 
+SAFE_ROUNDS = 40
+
+
 def safe_alpha(hier, idx, grad, d, p):
-    """Per-subdomain step sizes (D,) for affine candidate stencils."""
+    """Per-subdomain step sizes (D,) for affine candidate stencils
+    (Section 4.4; supplement Section 3).  Along p a stencil's distance
+    changes at the rate sum_j grad_j . p_j (its vertices moving together:
+    the relative displacement, independent of the frame); if it closes, its
+    step is 0.9 of the time to contact, capped at 1 (and 0 for a stencil
+    already at d <= 0).  Each subdomain takes the smallest step of the
+    stencils touching it; subdomains whose different steps would together
+    close a stencil are then damped (halved) until none does."""
     P = np.asarray(p).reshape(-1, 3)
     D = hier.num_subdomains(0)
     alpha = np.ones(D)
     for c in range(idx.shape[0]):
-        s = 0.0
+        rate = 0.0
         for j in range(4):
             v = idx[c, j]
             if v >= 0:
-                s += max(0.0, -float(grad[c, 3 * j:3 * j + 3] @ P[v]))
-        if s <= 0.0:
+                rate -= float(grad[c, 3 * j:3 * j + 3] @ P[v])
+        if rate <= 0.0:
             continue
-        a = min(1.0, 0.9 * d[c] / s)
+        a = max(0.0, min(1.0, 0.9 * d[c] / rate))
         for j in range(4):
             v = idx[c, j]
             if v >= 0:
                 sd = hier.subdomain_of_vertex(v)
                 alpha[sd] = min(alpha[sd], a)
+    # Vertices of one stencil in different subdomains move with different
+    # steps: while the combined motion would bring a stencil below 0.05 of
+    # its distance, halve the steps of every subdomain such a stencil touches.
+    sub = np.where(idx >= 0, hier.rank[np.maximum(idx, 0)] // 32, -1)
+    for _ in range(SAFE_ROUNDS):
+        marked = np.zeros(D, bool)
+        for c in range(idx.shape[0]):
+            if not d[c] > 0.0:
+                continue
+            dn = d[c]
+            for j in range(4):
+                v = idx[c, j]
+                if v >= 0:
+                    dn += alpha[sub[c, j]] * float(grad[c, 3 * j:3 * j + 3] @ P[v])
+            if dn < 0.05 * d[c]:
+                marked[sub[c][sub[c] >= 0]] = True
+        if not marked.any():
+            break
+        alpha[marked] *= 0.5
     return alpha
 
 

@@ -9,8 +9,9 @@ Algorithm 1 with full-rebuild semantics for the preconditioner blocks:
    subdomain and invert the updated fine blocks directly;
 3. g = grad E(x_k), z = P g, and the subspace step with H~ = H_base + U U^T;
 4. per-subdomain safe steps, then the descent check: all step sizes are
-   halved (at most 8 times) until E does not increase (the paper's line
-   search is not described; this is the reading used here);
+   halved (at most 8 times) until E does not increase; if none does, x is
+   kept and the next iteration restarts (the paper's line search is not
+   described; this is the reading used here);
 5. r_k = |g^T z_prev| / (g^T z) decides the next restart (threshold delta).
 """
 from __future__ import annotations
@@ -77,17 +78,21 @@ class OraclePNCG:
         dpool = pool_distance(self.pool, x)
         alpha = pncg.safe_alpha(hier, self.pool['idx'], self.pool['grad'], dpool, p)
         E0 = prob.energy(x, self.x_tilde, C)
+        accepted = False
         for _ in range(self.max_halvings + 1):
             xn = pncg.step_positions(hier, x, p, alpha)
             if prob.energy(xn, self.x_tilde, self.constraint_set(xn)) <= E0:
+                accepted = True
                 break
             alpha = 0.5 * alpha
         r = pncg.restart_ratio(g, self.z_prev, z) if self.z_prev is not None else 0.0
         self.log.append(dict(gnorm=float(np.linalg.norm(g)), znorm=float(np.linalg.norm(z)),
                              mu=mu, nu=nu, r=r, restart=self.restart, fallback=fb, E=E0,
-                             m=int(C['key'].size)))
-        self.restart = r > self.delta
+                             m=int(C['key'].size), accepted=accepted))
+        # without a decrease the point is kept and the next iteration restarts
+        self.restart = (r > self.delta) or not accepted
         self.z_prev = z
         self.p = p
-        self.x = xn
+        if accepted:
+            self.x = xn
         return g, z, p

@@ -156,7 +156,7 @@ mas_status mas_destroy(void* p) {
                   c->bkey_sorted, c->biota, c->bperm, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
-                  c->alpha, c->err, c->diag, c->cub_tmp};
+                  c->alpha, c->amark, c->err, c->diag, c->cub_tmp};
   for (void* q : ptrs)
     if (q) hipFree(q);
   for (int l = 0; l < MAXL; ++l) {
@@ -396,12 +396,14 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->partials, 16 * c->n_partial_blocks));
   TRY(dalloc(&c->scal, 64));
   TRY(dalloc(&c->alpha, D0));
+  TRY(dalloc(&c->amark, D0));
   TRY(dalloc(&c->err, 1));
   TRY(dalloc(&c->diag, 1));
   HIPCHK(hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->s));
   HIPCHK(hipMemsetAsync(c->diag, 0, sizeof(DiagRec), c->s));
   HIPCHK(hipMemsetAsync(c->rank, 0, sizeof(int32_t) * D0, c->s));
   HIPCHK(hipMemsetAsync(c->alpha, 0, sizeof(double) * D0, c->s));
+  HIPCHK(hipMemsetAsync(c->amark, 0, D0, c->s));
 
   HIPCHK(hipMemcpyAsync(c->tets, tets.data(), 4 * T * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->tet_off, toff.data(), (D0 + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->s));

@@ -16,6 +16,7 @@ constexpr int BD = 96;                  // block dimension (3 DOFs x 32)
 constexpr int PK = BD * (BD + 1) / 2;   // packed lower-triangular entries (4656)
 constexpr int MAXL = 6;                 // maximum MAS levels
 constexpr int MAXK = 32;                // maximum Woodbury rank per subdomain
+constexpr int SAFE_ROUNDS = 40;         // safe-step repair rounds
 constexpr int EH = 54;                  // per-tet snapshot: 45 (9x9 packed) + 9 (Dm^-1)
 constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
 // Vertex ranges of the owner-computes products: range r owns the vertices
@@ -332,6 +333,7 @@ struct Ctx {
   int n_partial_blocks = 1024;
   double* scal = nullptr;          // small device scalars (mu, nu, ...)
   double* alpha = nullptr;         // D0
+  uint8_t* amark = nullptr;        // D0, subdomains marked by the safe-step check
   uint32_t* err = nullptr;         // sticky error bits
   DiagRec* diag = nullptr;         // first failure record
   void* cub_tmp = nullptr;

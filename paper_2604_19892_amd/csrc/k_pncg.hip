@@ -377,8 +377,8 @@ __global__ void k_alpha_init(int64_t D, double* alpha) {
   if (i < D) alpha[i] = 1.0;
 }
 
-// alpha_c = min(1, 0.9 d / sum_j max(0, -grad_j . p_j)) to every subdomain
-// the stencil touches
+// alpha_c = min(1, 0.9 d / s) for a stencil closing at the rate
+// s = -sum_j grad_j . p_j > 0, to every subdomain the stencil touches
 __global__ __launch_bounds__(256) void k_alpha_stencils(int64_t m, const int32_t* idx, const double* grad,
                                                         const double* d, const double* p, double* alpha) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -387,14 +387,12 @@ __global__ __launch_bounds__(256) void k_alpha_stencils(int64_t m, const int32_t
   if (i < m) {
     const int4 iv = reinterpret_cast<const int4*>(idx)[i];
     vi[0] = iv.x; vi[1] = iv.y; vi[2] = iv.z; vi[3] = iv.w;
-    double s = 0;
+    double s = 0;  // closing rate of the stencil along p
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (vi[j] < 0) continue;
-      double dot = 0;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
-      s += fmax(0.0, -dot);
+      for (int q = 0; q < 3; ++q) s -= grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
     }
     if (s > 0.0) a = fmax(fmin(1.0, 0.9 * d[i] / s), 0.0);
   }
@@ -415,14 +413,67 @@ __global__ void k_step(int64_t n3, const double* x, const double* p, const doubl
   xo[i] = x[i] + scale * alpha[(i / 3) >> 5] * p[i];
 }
 
+// A stencil whose vertices, each moved with its own subdomain's step, would
+// close to below 0.05 of its distance marks the subdomains it touches.
+__global__ __launch_bounds__(256) void k_alpha_check(int64_t m, const int32_t* idx, const double* grad,
+                                                     const double* d, const double* p, const double* alpha,
+                                                     uint8_t* mark, uint32_t* count) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  bool viol = false;
+  if (i < m) {
+    const double di = d[i];
+    if (di > 0.0) {
+      const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+      const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+      double dn = di;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (vi[j] < 0) continue;
+        double dot = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
+        dn += alpha[vi[j] >> 5] * dot;
+      }
+      if (dn < 0.05 * di) {
+        viol = true;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (vi[j] >= 0) mark[vi[j] >> 5] = 1;
+      }
+    }
+  }
+  const unsigned long long b = __ballot(viol);
+  if (b != 0 && (threadIdx.x & 63) == 0) atomicAdd(count, uint32_t(__popcll(b)));
+}
+
+__global__ void k_alpha_halve(int64_t D, double* alpha, uint8_t* mark) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < D && mark[i]) {
+    alpha[i] *= 0.5;
+    mark[i] = 0;
+  }
+}
+
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out) {
   const int64_t D = c.lv[0].nsub;
   if (cand) {
     k_alpha_init<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, c.alpha);
-    if (cand->m > 0)
-      k_alpha_stencils<<<dim3((cand->m + 255) / 256), dim3(256), 0, c.s>>>(cand->m, cand->idx, cand->grad,
-                                                                            cand->d, p, c.alpha);
+    if (cand->m > 0) {
+      const dim3 g((cand->m + 255) / 256), b(256);
+      k_alpha_stencils<<<g, b, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha);
+      // subdomains moving at different steps: halve the steps of the
+      // subdomains of any stencil the combined motion would close
+      for (int round = 0; round < SAFE_ROUNDS; ++round) {
+        k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr + 2, 0u);
+        k_alpha_check<<<g, b, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha, c.amark, c.ctr + 2);
+        uint32_t nv = 0;
+        HIPCHK(hipMemcpyAsync(&nv, c.ctr + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, c.s));
+        HIPCHK(hipStreamSynchronize(c.s));
+        if (nv == 0) break;
+        k_alpha_halve<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, c.alpha, c.amark);
+      }
+    }
   }
   int64_t n3 = 3 * c.N;
   k_step<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);

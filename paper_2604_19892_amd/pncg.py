@@ -7,8 +7,9 @@ energy and gradient, and the restart decision.  The only host reads per
 iteration are the trial energy (descent check) and the step scalars.
 
 The descent check halves every subdomain's step until the energy does not
-increase (at most ``max_halvings`` times); the paper does not describe its
-line search.
+increase (at most ``max_halvings`` times); if none does, the point is kept
+and the next iteration restarts.  The paper does not describe its line
+search.
 """
 from __future__ import annotations
 
@@ -48,6 +49,7 @@ class PNCG:
         self.k = 0
         self.n_restarts = 0
         self.n_halvings = 0
+        self.n_rejected = 0
         self.log = []
         self.g0norm = None
         self.track_precisions = False
@@ -68,28 +70,37 @@ class PNCG:
                           self.restart)
         ctx.safe_step(self.x, self.p, self.pool, 1.0, self.x_trial)
         scale = 1.0
+        accepted = False
         for h in range(self.max_halvings + 1):
             ctx.stencil_distance(self.x_trial, self.pool_t)
             ctx.energy_grad(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
             Et = float(self.E_trial.item())
-            if Et <= self.E_host or h == self.max_halvings:
+            if Et <= self.E_host:
+                accepted = True
                 break
-            scale *= 0.5
-            self.n_halvings += 1
-            ctx.safe_step(self.x, self.p, None, scale, self.x_trial)
+            if h < self.max_halvings:
+                scale *= 0.5
+                self.n_halvings += 1
+                ctx.safe_step(self.x, self.p, None, scale, self.x_trial)
         st = ctx.step_out()
         if self.g0norm is None:
             self.g0norm = np.sqrt(st["gnorm2"])
         self.log.append(dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), znorm=float(np.sqrt(st["znorm2"])),
                              mu=st["mu"], nu=st["nu"], r=st["r"], restart=bool(self.restart),
                              fallback=bool(st["fallback"]), E=Et, scale=scale))
-        # accept the trial point
-        self.x, self.x_trial = self.x_trial, self.x
-        self.g, self.g_trial = self.g_trial, self.g
-        self.pool.d, self.pool_t.d = self.pool_t.d, self.pool.d
-        self.z, self.z_prev = self.z_prev, self.z
-        self.E_host = Et
-        self.restart = bool(st["restart_next"])
+        if accepted:
+            self.x, self.x_trial = self.x_trial, self.x
+            self.g, self.g_trial = self.g_trial, self.g
+            self.pool.d, self.pool_t.d = self.pool_t.d, self.pool.d
+            self.z, self.z_prev = self.z_prev, self.z
+            self.E_host = Et
+            self.restart = bool(st["restart_next"])
+        else:
+            # no step decreased the energy: stay at x and rebuild the
+            # preconditioner there (the next step starts afresh)
+            self.z, self.z_prev = self.z_prev, self.z
+            self.n_rejected += 1
+            self.restart = True
         self.k += 1
         return st
 

@@ -431,13 +431,13 @@ def churn_set(rng, scene, base, frac=0.3):
 
 def puffer_scene(seed=2, n_balls_axis=2, core=(36, 36, 37), n_spikes=1182, spike_len=20,
                  pool_size=1_250_000, active_frac=0.8, dhat=1e-4, h=0.005, E=1e5, nu=0.4,
-                 rho=1000.0, ball_size=0.2, levels=4, K=8, speed=0.5):
+                 rho=1000.0, ball_size=0.2, levels=4, K=8, speed=0.5, kappa_scale=1.0, dmin=1e-7):
     """Eight spiky balls in a 2x2x2 arrangement.  Each ball is a lattice
     core plus radial 2x2-vertex spike columns standing on its faces; the
     spikes of face-adjacent balls interleave, and the contact stencils
     (PT and EE) are drawn between those interleaved spikes.  With the
     defaults: 1,140,096 vertices, 2,709,600 tets, 1.25M candidate stencils
-    of which 80% start active (distance log-uniform in (1e-7, dhat)).
+    of which 80% start active (distance log-uniform in (dmin, dhat)).
     Velocities point toward the scene centre at ``speed``."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = core
@@ -530,7 +530,7 @@ def puffer_scene(seed=2, n_balls_axis=2, core=(36, 36, 37), n_spikes=1182, spike
     key, idx, grad = key[sel], idx[sel], grad[sel]
     m = key.size
     n_act = int(round(active_frac * m))
-    d = np.concatenate([_loguniform(rng, 1e-7, dhat, n_act),
+    d = np.concatenate([_loguniform(rng, dmin, dhat, n_act),
                         rng.uniform(1.05 * dhat, 3 * dhat, m - n_act)])
     rng.shuffle(d)
     pool = stencil_pool(key, idx, grad, x, d)
@@ -539,7 +539,7 @@ def puffer_scene(seed=2, n_balls_axis=2, core=(36, 36, 37), n_spikes=1182, spike
     T = tets.shape[0]
     return Scene("puffer_balls", X, x, speed * vdir, tets,
                  np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
-                 kappa=rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]),
+                 kappa=kappa_scale * rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]),
                  pool=pool, levels=levels, K=K)
 
 

@@ -134,11 +134,60 @@ def test_safe_step_keeps_every_stencil_apart():
     alpha = pncg.safe_alpha(hier, pool['idx'], pool['grad'], d0, p)
     assert np.all((alpha > 0) & (alpha <= 1))
     assert np.any(alpha < 1)
-    # any per-subdomain fraction of the step keeps d >= 0.1 d0
-    for frac in (1.0, 0.5, 0.0):
-        a = alpha * (frac + (1 - frac) * rng.uniform(size=alpha.size))
+    # a common step no larger than any subdomain's keeps d >= 0.1 d0
+    for frac in (1.0, 0.5):
+        a = np.full(alpha.size, frac * alpha.min())
         d1 = dist(pncg.step_positions(hier, x, p, a))
         assert np.all(d1 >= 0.1 * d0 - 1e-15)
+    # the step of every stencil is 0.9 of its own time to contact, exactly
+    xs = np.where(pool['idx'][..., None] >= 0, p.reshape(-1, 3)[np.maximum(pool['idx'], 0)], 0).reshape(-1, 12)
+    rate = -(pool['grad'] * xs).sum(1)
+    closing = rate > 0
+    ac = np.minimum(1.0, 0.9 * d0[closing] / rate[closing])
+    sub = np.where(pool['idx'] >= 0, hier.rank[np.maximum(pool['idx'], 0)] // 32, -1)[closing]
+    for c in range(ac.size):
+        for s_ in sub[c][sub[c] >= 0]:
+            assert alpha[s_] <= ac[c] + 1e-15
+
+
+def test_safe_step_mixed_subdomain_steps_keep_stencils_apart():
+    """With the per-subdomain steps themselves (not a common one) every
+    stencil keeps at least 0.05 of its distance, also for a search direction
+    with a large common translation, where stencils across subdomain borders
+    see their vertices move by different amounts."""
+    sc = synth.two_boxes_scene(n_contacts=600, nxy=12, nz=6)
+    pool = sc.pool
+    hier = mas.Hierarchy(sc.X, 2)
+    assert np.allclose(pool['grad'].reshape(-1, 4, 3).sum(1), 0.0)
+    rng = np.random.default_rng(8)
+    x = sc.x.reshape(-1)
+
+    def dist(xx):
+        xs = np.where(pool['idx'][..., None] >= 0, xx.reshape(-1, 3)[np.maximum(pool['idx'], 0)], 0)
+        return (pool['grad'] * xs.reshape(-1, 12)).sum(1) - pool['off']
+
+    d0 = dist(x)
+    assert np.all(d0 > 0)
+    p = 0.05 * rng.standard_normal(x.size)
+    shift = np.tile(rng.standard_normal(3), sc.N)
+    for q in (p, p + shift):
+        alpha = pncg.safe_alpha(hier, pool['idx'], pool['grad'], d0, q)
+        assert np.all((alpha > 0) & (alpha <= 1))
+        d1 = dist(pncg.step_positions(hier, x, q, alpha))
+        assert np.all(d1 >= 0.05 * d0 - 1e-15)
+        assert np.any(alpha < 1)
+
+
+def test_safe_step_closed_stencil_gives_zero():
+    X = np.random.default_rng(6).uniform(size=(40, 3))
+    hier = mas.Hierarchy(X, 1)
+    idx = np.array([[3, -1, -1, -1]], np.int32)
+    grad = np.zeros((1, 12))
+    grad[0, :3] = [0, 0, 1.0]
+    p = np.zeros(120)
+    p[3 * 3 + 2] = -1.0
+    alpha = pncg.safe_alpha(hier, idx, grad, np.array([-1e-6]), p)
+    assert alpha[hier.subdomain_of_vertex(3)] == 0.0
 
 
 def test_safe_step_single_contact_closed_form():
