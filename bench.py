@@ -12,7 +12,10 @@ when the restart test asks for them, inside the timed region.
 
 Prints one JSON line.  The roofline object covers the level-0 kernel of
 mas_apply, timed with HIP events recorded by the library on its own stream
-during the timed steps.
+during the timed steps.  After the timed steps, ``tol_solve`` runs one solve
+per level-0 block storage (f64 with float64 element Hessians; f32, bf16 and
+f16 with float32 element Hessians) from the same start to
+||grad E|| <= 1e-6 ||grad E_0|| and reports iterations and wall-clock time.
 """
 import argparse
 import hashlib
@@ -140,6 +143,32 @@ def cpu_baseline(full_N, iters=3):
                       % (iters, sc.N, sc.T, sc.pool['key'].size, dt, sc.N, full_N)}
 
 
+def tolerance_solves(sc, precs, tol, max_iter):
+    """One PNCG solve per block storage precision from the same start to
+    ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds (each
+    context is created before its clock starts)."""
+    import torch
+    from paper_2604_19892_amd.pncg import PNCG
+    runs = {}
+    for prec in precs:
+        s = PNCG(sc, block_prec=prec, hess_prec="f64" if prec == "f64" else "f32")
+        it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
+        code, msg = s.ctx.sync()
+        runs[prec] = {"iters": it, "seconds": sec, "rel_gnorm": rel, "converged": bool(rel <= tol),
+                      "restarts": s.n_restarts, "rejected_steps": s.n_rejected,
+                      "hessian_storage": "f64" if prec == "f64" else "f32", "status": code}
+        print("[bench] solve %s: %d iters %.2fs rel %.2e" % (prec, it, sec, rel), file=sys.stderr, flush=True)
+        s.ctx.close()
+        del s
+        torch.cuda.empty_cache()
+    out = {"tol": tol, "max_iter": max_iter, "runs": runs}
+    ref = runs.get("f64")
+    if ref and ref["converged"]:
+        out["f64_seconds_over"] = {p: ref["seconds"] / r["seconds"] for p, r in runs.items()
+                                   if p != "f64" and r["converged"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +176,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the solves to the gradient tolerance (f64 vs mixed storage)")
+    ap.add_argument("--solve-tol", type=float, default=1e-6)
+    ap.add_argument("--solve-max-iter", type=int, default=1500)
     ap.add_argument("--small", action="store_true", help="two-boxes scene instead (quick check)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference size for rocprofv3 byte counters)")
@@ -258,12 +291,18 @@ def main():
             "launches": int(n_hv), "avg_us": 1e3 * ms_hv / max(n_hv, 1),
         },
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in timers.items()},
-        "gnorm_rel": solver.gnorm() / solver.g0norm if solver.g0norm else None,
+        "gnorm_rel": solver.log[-1]["gnorm"] / solver.g0norm if solver.g0norm else None,
     }
     code, msg = ctx.sync()
     if code != 0:
         print("[bench] library error: %s" % msg, file=sys.stderr)
         sys.exit(1)
+    if not args.no_solve:
+        solver.ctx.close()
+        del solver, ctx
+        torch.cuda.empty_cache()
+        out["tol_solve"] = tolerance_solves(sc, ("f64", "f32", "bf16", "f16"), args.solve_tol,
+                                            args.solve_max_iter)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc.N)

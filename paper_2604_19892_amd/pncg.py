@@ -108,13 +108,23 @@ class PNCG:
         return float(torch.linalg.vector_norm(self.g).item())
 
     def solve(self, rel_tol=1e-6, max_iter=1000):
-        """Iterates until ||grad E|| <= rel_tol ||grad E_0||; returns (iters, seconds)."""
-        g0 = self.gnorm()
+        """Iterates until the gradient an iteration starts from satisfies
+        ||grad E|| <= rel_tol ||grad E_0|| (norms from the subspace step
+        kernel; that last iteration is counted and timed).  Returns
+        (iterations, seconds, relative gradient norm)."""
         torch.cuda.synchronize()
         t = time.perf_counter()
+        g0 = None
+        rel = float("inf")
         it = 0
-        while it < max_iter and self.gnorm() > rel_tol * g0:
-            self.iterate()
+        while it < max_iter:
+            st = self.iterate()
             it += 1
+            gn = float(np.sqrt(st["gnorm2"]))
+            if g0 is None:
+                g0 = gn
+            rel = gn / g0 if g0 > 0 else 0.0
+            if rel <= rel_tol or not np.isfinite(rel):
+                break
         torch.cuda.synchronize()
-        return it, time.perf_counter() - t
+        return it, time.perf_counter() - t, rel

@@ -431,14 +431,23 @@ def churn_set(rng, scene, base, frac=0.3):
 
 def puffer_scene(seed=2, n_balls_axis=2, core=(36, 36, 37), n_spikes=1182, spike_len=20,
                  pool_size=1_250_000, active_frac=0.8, dhat=1e-4, h=0.005, E=1e5, nu=0.4,
-                 rho=1000.0, ball_size=0.2, levels=4, K=8, speed=0.5, kappa_scale=1.0, dmin=1e-7):
+                 rho=1000.0, ball_size=0.2, levels=4, K=8, speed=0.5, kappa_scale=1e3, dmin=1e-7):
     """Eight spiky balls in a 2x2x2 arrangement.  Each ball is a lattice
     core plus radial 2x2-vertex spike columns standing on its faces; the
     spikes of face-adjacent balls interleave, and the contact stencils
     (PT and EE) are drawn between those interleaved spikes.  With the
     defaults: 1,140,096 vertices, 2,709,600 tets, 1.25M candidate stencils
     of which 80% start active (distance log-uniform in (dmin, dhat)).
-    Velocities point toward the scene centre at ``speed``."""
+    Velocities point toward the scene centre at ``speed``.
+
+    The barrier stiffness is kappa_scale * rho * edge^3 (the paper leaves
+    kappa open).  With kappa_scale = 1e3 (kappa ~ 0.17) the barrier force of
+    a stencil balances the inertial push of a vertex (mass rho edge^3 moved
+    h * speed toward the centre) at a distance of about 1e-7, inside the
+    initial distance range; at kappa_scale = 1 that balance sits near
+    1e-10, stencils pushed by several vertices close to 1e-14 and below,
+    and the descent check then rejects every trial point (the barrier's
+    curvature changes by orders of magnitude within one step)."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = core
     edge = ball_size / (max(core) - 1)
