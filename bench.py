@@ -224,6 +224,7 @@ def main():
         solver.precision_counts = ctx.block_precisions(0)
     ctx.profile(True)
     l0_bytes = []
+    hist_sum = None
     r0 = solver.n_restarts
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -231,6 +232,8 @@ def main():
         restart = solver.restart
         solver.iterate()
         hist = [0] if restart else solver.rank_hist.cpu().numpy().tolist()
+        if not restart:
+            hist_sum = hist if hist_sum is None else [a + b for a, b in zip(hist_sum, hist)]
         l0_bytes.append(apply_l0_bytes(ctx, solver.precision_counts, hist))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
@@ -291,6 +294,7 @@ def main():
             "launches": int(n_hv), "avg_us": 1e3 * ms_hv / max(n_hv, 1),
         },
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in timers.items()},
+        "woodbury_rank_hist": hist_sum,
         "gnorm_rel": solver.log[-1]["gnorm"] / solver.g0norm if solver.g0norm else None,
     }
     code, msg = ctx.sync()

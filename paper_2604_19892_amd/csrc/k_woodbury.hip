@@ -1,6 +1,8 @@
 // Sparse-Input Woodbury update of the level-0 blocks: classification of the
 // current contacts against the base set, localized Top-K per subdomain and
 // the capacitance factors I + U_d^T B_d U_d.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "elem.hpp"
 
@@ -12,11 +14,15 @@ namespace mas {
 //   found, k > k_base    -> dS = k - k_base (stiffening)
 //   otherwise            -> dS = 0          (softening)
 // The column u = sqrt(dS) n enters the untruncated U.
+// A contact with k = 0 (d >= dhat) has dS = 0 whatever the base holds, so it
+// is not looked up.  The lookup first tries the same position in the base
+// set (contact sets that keep their order between build and update), then a
+// binary search of the sorted base keys.
 __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, const double* d,
                            const double* grad, double kappa, double dhat, double cos_rot, int64_t mb,
-                           const uint64_t* bkey_sorted, const int32_t* bperm, const double* bk,
-                           const double* bgrad, double* U, int32_t* Uidx, double* dS, uint64_t* ckey,
-                           uint32_t* err) {
+                           const uint64_t* bkey, const uint64_t* bkey_sorted, const int32_t* bperm,
+                           const double* bk, const double* bgrad, double* U, int32_t* Uidx, double* dS,
+                           uint64_t* ckey, uint32_t* err) {
   int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (i >= m) return;
   double b, b1, b2;
@@ -28,16 +34,23 @@ __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, c
   double n[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) n[q] = grad[12 * i + q];
-  // lower_bound in the sorted base keys
-  int64_t lo = 0, hi = mb;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (bkey_sorted[mid] < kk) lo = mid + 1;
-    else hi = mid;
-  }
   double s = k;
-  if (lo < mb && bkey_sorted[lo] == kk) {
-    int64_t bi = bperm[lo];
+  int64_t bi = -1;
+  if (k > 0.0) {
+    if (i < mb && bkey[i] == kk) {
+      bi = i;
+    } else {
+      // lower_bound in the sorted base keys
+      int64_t lo = 0, hi = mb;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (bkey_sorted[mid] < kk) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < mb && bkey_sorted[lo] == kk) bi = bperm[lo];
+    }
+  }
+  if (bi >= 0) {
     double dot = 0, nn = 0, bb = 0;
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
@@ -66,61 +79,124 @@ __device__ inline bool ranks_before(double s1, uint64_t k1, double s2, uint64_t 
   return s1 > s2 || (s1 == s2 && k1 < k2);
 }
 
-// One wavefront per subdomain: K rounds of a wave-wide arg-best over the
-// candidates ranked after the previous pick.
-__global__ __launch_bounds__(64) void k_topk(int K, const int32_t* off, const int32_t* list,
+// One wavefront per subdomain: K rounds of a wave-wide arg-best.  Lists of
+// up to 64 * TOPK_R candidates are held in registers (TOPK_R per lane) and a
+// pick is struck out by its holder; longer lists are rescanned from memory
+// each round for the best candidate ranked after the previous pick.
+constexpr int TOPK_R = 8;
+
+__device__ __forceinline__ void wave_best(double& bs, unsigned long long& bkey, int& bc) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double os = __shfl_xor(bs, o);
+    const unsigned long long ok = __shfl_xor(bkey, o);
+    const int oc = __shfl_xor(bc, o);
+    if (oc >= 0 && (bc < 0 || ranks_before(os, ok, bs, bkey))) {
+      bs = os;
+      bkey = ok;
+      bc = oc;
+    }
+  }
+}
+
+__device__ __forceinline__ void topk_emit(int64_t d, int K, int r, int bc, int lane, const int32_t* Uidx,
+                                          const double* U, int32_t* sel, SlotCol* slots) {
+  SlotCol* sc = slots + d * K + r;
+  if (lane == 0) sel[d * K + r] = bc;
+  if (lane < 12) sc->u[lane] = U[12 * int64_t(bc) + lane];
+  if (lane < 4) {
+    const int v = Uidx[4 * int64_t(bc) + lane];
+    sc->lv[lane] = (v >= 0 && (v >> 5) == d) ? (v & 31) : -1;
+  }
+}
+
+__global__ __launch_bounds__(64, 6) void k_topk(int K, const int32_t* off, const int32_t* list,
                                              const double* dS, const uint64_t* key, const int32_t* Uidx,
                                              const double* U, int32_t* rank, int32_t* sel,
-                                             SlotCol* slots, int32_t* hist) {
+                                             SlotCol* slots) {
   const int64_t d = blockIdx.x;
   const int lane = threadIdx.x;
   const int b = off[d], e = off[d + 1];
-  double ps = 0.0;
-  uint64_t pkey = 0;
-  bool first = true;
   int r = 0;
-  for (; r < K; ++r) {
-    double bs = 0.0;
-    unsigned long long bkey = 0;
-    int bc = -1;
-    for (int q = b + lane; q < e; q += 64) {
-      int c = list[q];
-      double s = dS[c];
-      uint64_t kk = key[c];
-      if (!first && !ranks_before(ps, pkey, s, kk)) continue;
-      if (bc < 0 || ranks_before(s, kk, bs, bkey)) {
-        bs = s;
-        bkey = kk;
-        bc = c;
+  if (e - b <= 64 * TOPK_R) {
+    double s[TOPK_R];
+    unsigned long long kk[TOPK_R];
+    int cc[TOPK_R];
+#pragma unroll
+    for (int q = 0; q < TOPK_R; ++q) {
+      const int w = b + lane + 64 * q;
+      cc[q] = -1;
+      s[q] = 0.0;
+      kk[q] = 0;
+      if (w < e) {
+        cc[q] = list[w];
+        s[q] = dS[cc[q]];
+        kk[q] = key[cc[q]];
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      double os = __shfl_xor(bs, o);
-      unsigned long long ok = __shfl_xor(bkey, o);
-      int oc = __shfl_xor(bc, o);
-      if (oc >= 0 && (bc < 0 || ranks_before(os, ok, bs, bkey))) {
-        bs = os;
-        bkey = ok;
-        bc = oc;
+    for (; r < K; ++r) {
+      double bs = 0.0;
+      unsigned long long bkey = 0;
+      int bc = -1;
+#pragma unroll
+      for (int q = 0; q < TOPK_R; ++q) {
+        if (cc[q] >= 0 && (bc < 0 || ranks_before(s[q], kk[q], bs, bkey))) {
+          bs = s[q];
+          bkey = kk[q];
+          bc = cc[q];
+        }
       }
+      wave_best(bs, bkey, bc);
+      if (bc < 0) break;
+#pragma unroll
+      for (int q = 0; q < TOPK_R; ++q)
+        if (cc[q] == bc) cc[q] = -1;
+      topk_emit(d, K, r, bc, lane, Uidx, U, sel, slots);
     }
-    if (bc < 0) break;
-    SlotCol* sc = slots + d * K + r;
-    if (lane == 0) sel[d * K + r] = bc;
-    if (lane < 12) sc->u[lane] = U[12 * int64_t(bc) + lane];
-    if (lane < 4) {
-      int v = Uidx[4 * int64_t(bc) + lane];
-      sc->lv[lane] = (v >= 0 && (v >> 5) == d) ? (v & 31) : -1;
+  } else {
+    double ps = 0.0;
+    uint64_t pkey = 0;
+    bool first = true;
+    for (; r < K; ++r) {
+      double bs = 0.0;
+      unsigned long long bkey = 0;
+      int bc = -1;
+      for (int q = b + lane; q < e; q += 64) {
+        const int c = list[q];
+        const double sv = dS[c];
+        const uint64_t kv = key[c];
+        if (!first && !ranks_before(ps, pkey, sv, kv)) continue;
+        if (bc < 0 || ranks_before(sv, kv, bs, bkey)) {
+          bs = sv;
+          bkey = kv;
+          bc = c;
+        }
+      }
+      wave_best(bs, bkey, bc);
+      if (bc < 0) break;
+      topk_emit(d, K, r, bc, lane, Uidx, U, sel, slots);
+      ps = bs;
+      pkey = bkey;
+      first = false;
     }
-    ps = bs;
-    pkey = bkey;
-    first = false;
   }
   if (lane == 0) {
     rank[d] = r;
     for (int q = r; q < K; ++q) sel[d * K + q] = -1;
-    if (hist) atomicAdd(&hist[r], 1);
   }
+}
+
+// Histogram of the per-subdomain ranks: LDS counts per workgroup, then one
+// global atomic per bin and workgroup (a global atomic per subdomain would
+// serialise on the K + 1 addresses).
+__global__ __launch_bounds__(256) void k_rank_hist(int64_t D, int K, const int32_t* rank, int32_t* hist) {
+  __shared__ int h[MAXK + 1];
+  for (int q = threadIdx.x; q <= K; q += blockDim.x) h[q] = 0;
+  __syncthreads();
+  for (int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; d < D; d += int64_t(gridDim.x) * blockDim.x)
+    atomicAdd(&h[rank[d]], 1);
+  __syncthreads();
+  for (int q = threadIdx.x; q <= K; q += blockDim.x)
+    if (h[q]) atomicAdd(&hist[q], h[q]);
 }
 
 template <int P>
@@ -152,33 +228,42 @@ __device__ __forceinline__ void gather_w(const unsigned char* As, const float* s
 }
 
 // One workgroup per subdomain with rank r > 0: W = B_d U_d (96 x r), the
-// capacitance C = I + U_d^T W and its float64 Cholesky factor.
+// capacitance C = I + U_d^T W and its float64 Cholesky factor (right-looking,
+// the rank-one updates of each column spread over the workgroup).  Blocks
+// stored in 32 or 16 bits are staged in LDS, float64 blocks are read in
+// place; W, C and the slot columns live in dynamic LDS sized by K.
+constexpr size_t CAP_STAGE = blk_elems(MAS_F32) * 4;
+
 __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, const uint8_t* bprec,
                                                      const float* scale, const int32_t* rank, const SlotCol* slots,
                                                      double* W, double* Lcap, uint32_t* err, DiagRec* dg) {
-  __shared__ __align__(16) unsigned char As[BLK_STRIDE];
+  __shared__ __align__(16) unsigned char As[CAP_STAGE];
   __shared__ float sig[BD];
-  __shared__ double Ws[MAXK][BD];
-  __shared__ double Cm[MAXK * MAXK];
-  __shared__ SlotCol sl[MAXK];
+  __shared__ int bad;
+  extern __shared__ __align__(16) double cdyn[];
+  double(*Ws)[BD] = reinterpret_cast<double(*)[BD]>(cdyn);
+  double* Cm = cdyn + K * BD;
+  SlotCol* sl = reinterpret_cast<SlotCol*>(Cm + K * K);
   const int64_t d = blockIdx.x;
   const int tid = threadIdx.x;
   const int r = rank[d];
   if (r == 0) return;
   const int P = bprec[d];
-  {
+  const unsigned char* src = reinterpret_cast<const unsigned char*>(blk) + d * BLK_STRIDE;
+  if (P != MAS_F64) {
     const int nbytes = int(blk_elems(P) * prec_size(P));
-    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(blk) + d * BLK_STRIDE);
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
     uint4* dst = reinterpret_cast<uint4*>(As);
-    for (int q = tid; q < nbytes / 16; q += blockDim.x) dst[q] = src[q];
+    for (int q = tid; q < nbytes / 16; q += blockDim.x) dst[q] = s4[q];
   }
   if (P == MAS_BF16 || P == MAS_F16) {
     if (tid < BD) sig[tid] = scale[d * BD + tid];
   }
   for (int q = tid; q < r; q += blockDim.x) sl[q] = slots[d * K + q];
+  if (tid == 0) bad = 0;
   __syncthreads();
   switch (P) {
-    case MAS_F64: gather_w<MAS_F64>(As, sig, sl, r, Ws); break;
+    case MAS_F64: gather_w<MAS_F64>(src, sig, sl, r, Ws); break;
     case MAS_F32: gather_w<MAS_F32>(As, sig, sl, r, Ws); break;
     case MAS_BF16: gather_w<MAS_BF16>(As, sig, sl, r, Ws); break;
     default: gather_w<MAS_F16>(As, sig, sl, r, Ws);
@@ -197,29 +282,33 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
     Cm[j * r + k] = acc;
   }
   __syncthreads();
-  if (tid == 0) {
-    // Cholesky C = L L^T (lower), in place, float64
-    bool bad = false;
-    for (int j = 0; j < r; ++j) {
-      double dj = Cm[j * r + j];
-      for (int k = 0; k < j; ++k) dj -= Cm[j * r + k] * Cm[j * r + k];
-      if (!(dj > 0.0)) {
-        if (!bad) diag_report(dg, 3, 0, d, j, dj);
-        bad = true;
-        dj = 1.0;
+  // C = L L^T in place (lower triangle), float64
+  for (int j = 0; j < r; ++j) {
+    if (tid == 0) {
+      double djj = Cm[j * r + j];
+      if (!(djj > 0.0)) {
+        if (!bad) diag_report(dg, 3, 0, d, j, djj);
+        bad = 1;
+        djj = 1.0;
       }
-      double ljj = sqrt(dj);
-      Cm[j * r + j] = ljj;
-      for (int i = j + 1; i < r; ++i) {
-        double v = Cm[i * r + j];
-        for (int k = 0; k < j; ++k) v -= Cm[i * r + k] * Cm[j * r + k];
-        Cm[i * r + j] = v / ljj;
-      }
+      Cm[j * r + j] = sqrt(djj);
     }
-    if (bad) atomicOr(err, ERRB_NOT_SPD);
-    double* L = Lcap + d * (K * (K + 1) / 2);
-    for (int i = 0; i < r; ++i)
-      for (int j = 0; j <= i; ++j) L[pk(i, j)] = Cm[i * r + j];
+    __syncthreads();
+    const double ljj = Cm[j * r + j];
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) Cm[i * r + j] /= ljj;
+    __syncthreads();
+    const int nr = r - j - 1;
+    for (int q = tid; q < nr * nr; q += blockDim.x) {
+      const int i = j + 1 + q / nr, k = j + 1 + q % nr;
+      if (k <= i) Cm[i * r + k] -= Cm[i * r + j] * Cm[k * r + j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && bad) atomicOr(err, ERRB_NOT_SPD);
+  double* L = Lcap + d * (K * (K + 1) / 2);
+  for (int q = tid; q < r * r; q += blockDim.x) {
+    const int i = q / r, j = q % r;
+    if (j <= i) L[pk(i, j)] = Cm[i * r + j];
   }
   for (int q = tid; q < r * BD; q += blockDim.x) {
     int j = q / BD, i = q % BD;
@@ -248,7 +337,7 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
   if (m > 0) {
     k_classify<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(
         m, cur->key, cur->idx, cur->d, cur->grad, c.cfg.kappa, c.cfg.dhat, c.cfg.cos_rot, c.mb,
-        c.bkey_sorted, c.bperm, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
+        c.bkey, c.bkey_sorted, c.bperm, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
     HIPCHK(hipGetLastError());
   }
   st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
@@ -260,11 +349,14 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
     return MAS_OK;
   }
   k_topk<<<dim3(D), dim3(64), 0, c.s>>>(c.K, c.cand_off, c.cand_list, c.dS, c.ckey, c.Uidx, c.U, c.rank,
-                                        c.sel, c.slots, rank_hist);
+                                        c.sel, c.slots);
+  if (rank_hist)
+    k_rank_hist<<<dim3(std::min<int64_t>(64, (D + 255) / 256)), dim3(256), 0, c.s>>>(D, c.K, c.rank, rank_hist);
   Level& L0 = c.lv[0];
   ProfScope pc(c, MAS_T_CAPACITANCE);
-  k_capacitance<<<dim3(D), dim3(256), 0, c.s>>>(c.K, L0.blk, L0.bprec, L0.scale, c.rank, c.slots, c.W, c.Lcap,
-                                                c.err, c.diag);
+  const size_t cap_lds = sizeof(double) * (size_t(c.K) * BD + size_t(c.K) * c.K) + sizeof(SlotCol) * c.K;
+  k_capacitance<<<dim3(D), dim3(256), cap_lds, c.s>>>(c.K, L0.blk, L0.bprec, L0.scale, c.rank, c.slots, c.W,
+                                                      c.Lcap, c.err, c.diag);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }
