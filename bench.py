@@ -12,10 +12,10 @@ when the restart test asks for them, inside the timed region.
 
 Prints one JSON line.  The roofline object covers the level-0 kernel of
 mas_apply, timed with HIP events recorded by the library on its own stream
-during the timed steps.  After the timed steps, ``tol_solve`` runs one solve
-per level-0 block storage (f64 with float64 element Hessians; f32, bf16 and
-f16 with float32 element Hessians) from the same start to
-||grad E|| <= 1e-6 ||grad E_0|| and reports iterations and wall-clock time.
+during the timed steps.  After the timed steps, ``tol_solve`` solves from
+the same start to ||grad E|| <= 1e-6 ||grad E_0|| three times per level-0
+block storage (f64 with float64 element Hessians; f32, bf16 and f16 with
+float32 element Hessians) and reports iterations and wall-clock times.
 """
 import argparse
 import hashlib
@@ -143,29 +143,39 @@ def cpu_baseline(full_N, iters=3):
                       % (iters, sc.N, sc.T, sc.pool['key'].size, dt, sc.N, full_N)}
 
 
-def tolerance_solves(sc, precs, tol, max_iter):
-    """One PNCG solve per block storage precision from the same start to
-    ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds (each
-    context is created before its clock starts)."""
+def tolerance_solves(sc, precs, tol, max_iter, repeats):
+    """PNCG solves per block storage precision from the same start to
+    ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds of each
+    (each context is created before its clock starts).  Trajectories differ
+    between runs (the order of atomic float64 sums differs, and a restart
+    decision near the threshold can flip), so each form is solved
+    ``repeats`` times, interleaved, and the means are compared."""
     import torch
     from paper_2604_19892_amd.pncg import PNCG
-    runs = {}
-    for prec in precs:
-        s = PNCG(sc, block_prec=prec, hess_prec="f64" if prec == "f64" else "f32")
-        it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
-        code, msg = s.ctx.sync()
-        runs[prec] = {"iters": it, "seconds": sec, "rel_gnorm": rel, "converged": bool(rel <= tol),
-                      "restarts": s.n_restarts, "rejected_steps": s.n_rejected,
-                      "hessian_storage": "f64" if prec == "f64" else "f32", "status": code}
-        print("[bench] solve %s: %d iters %.2fs rel %.2e" % (prec, it, sec, rel), file=sys.stderr, flush=True)
-        s.ctx.close()
-        del s
-        torch.cuda.empty_cache()
-    out = {"tol": tol, "max_iter": max_iter, "runs": runs}
-    ref = runs.get("f64")
-    if ref and ref["converged"]:
-        out["f64_seconds_over"] = {p: ref["seconds"] / r["seconds"] for p, r in runs.items()
-                                   if p != "f64" and r["converged"]}
+    runs = {p: [] for p in precs}
+    for _ in range(repeats):
+        for prec in precs:
+            s = PNCG(sc, block_prec=prec, hess_prec="f64" if prec == "f64" else "f32")
+            it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
+            code, msg = s.ctx.sync()
+            runs[prec].append({"iters": it, "seconds": sec, "rel_gnorm": rel, "converged": bool(rel <= tol),
+                               "restarts": s.n_restarts, "rejected_steps": s.n_rejected, "status": code})
+            print("[bench] solve %s: %d iters %.2fs rel %.2e" % (prec, it, sec, rel), file=sys.stderr, flush=True)
+            s.ctx.close()
+            del s
+            torch.cuda.empty_cache()
+    out = {"tol": tol, "max_iter": max_iter, "repeats": repeats, "runs": runs, "mean_seconds": {},
+           "mean_iters": {}, "mean_ms_per_iter": {}}
+    for p, rs in runs.items():
+        ok = [r for r in rs if r["converged"]]
+        if len(ok) == len(rs):
+            out["mean_seconds"][p] = sum(r["seconds"] for r in rs) / len(rs)
+            out["mean_iters"][p] = sum(r["iters"] for r in rs) / len(rs)
+            out["mean_ms_per_iter"][p] = 1e3 * out["mean_seconds"][p] / out["mean_iters"][p]
+    if "f64" in out["mean_seconds"]:
+        out["f64_seconds_over"] = {p: out["mean_seconds"]["f64"] / t for p, t in out["mean_seconds"].items()
+                                   if p != "f64"}
+    out["element_hessian_storage"] = {p: "f64" if p == "f64" else "f32" for p in precs}
     return out
 
 
@@ -180,6 +190,7 @@ def main():
                     help="skip the solves to the gradient tolerance (f64 vs mixed storage)")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=1500)
+    ap.add_argument("--solve-repeats", type=int, default=3)
     ap.add_argument("--small", action="store_true", help="two-boxes scene instead (quick check)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference size for rocprofv3 byte counters)")
@@ -306,7 +317,7 @@ def main():
         del solver, ctx
         torch.cuda.empty_cache()
         out["tol_solve"] = tolerance_solves(sc, ("f64", "f32", "bf16", "f16"), args.solve_tol,
-                                            args.solve_max_iter)
+                                            args.solve_max_iter, args.solve_repeats)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc.N)
