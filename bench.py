@@ -143,6 +143,32 @@ def cpu_baseline(full_N, iters=3):
                       % (iters, sc.N, sc.T, sc.pool['key'].size, dt, sc.N, full_N)}
 
 
+def hbm_probe(reps=5):
+    """Plain device copy and sum of 1 GiB with torch's own kernels, timed with
+    events on torch's stream: what simple streaming kernels reach on this
+    GPU, reported beside the nominal 8 TB/s."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    a.sum()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    for _ in range(reps):
+        a.sum()
+    e2.record()
+    torch.cuda.synchronize()
+    gib = float(1 << 30)
+    out = {"copy_GBps": reps * 2 * gib / (e0.elapsed_time(e1) * 1e-3) / 1e9,
+           "read_GBps": reps * gib / (e1.elapsed_time(e2) * 1e-3) / 1e9, "bytes": int(gib)}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def tolerance_solves(sc, precs, tol, max_iter, repeats):
     """PNCG solves per block storage precision from the same start to
     ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds of each
@@ -312,6 +338,7 @@ def main():
     if code != 0:
         print("[bench] library error: %s" % msg, file=sys.stderr)
         sys.exit(1)
+    out["hbm_probe"] = hbm_probe()
     if not args.no_solve:
         solver.ctx.close()
         del solver, ctx

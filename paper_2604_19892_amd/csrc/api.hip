@@ -152,7 +152,7 @@ mas_status mas_destroy(void* p) {
   Ctx* c = as_ctx(p);
   hipStreamSynchronize(c->s);
   void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->tet_list, c->rt_off, c->rbeg, c->vrange, c->ctr, c->rl_t, c->rl_tv,
-                  c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->hf64, c->bkey,
+                  c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->t_home, c->bkey,
                   c->bkey_sorted, c->biota, c->bperm, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
@@ -368,7 +368,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->rl_geo, 12 * c->nent_pad));
   TRY(dalloc(&c->rc_cnt, c->nrange + 1));
   TRY(dalloc(&c->rc_off, c->nrange + 1));
-  TRY(dalloc(&c->hf64, EH * c->Tpad));
+  TRY(dalloc(&c->t_home, c->Tpad));
   if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hr32, 4 * SNAP_NC32 * c->nent_pad));
   else TRY(dalloc(&c->hr64, EH * c->nent_pad));
   for (int l = 0; l < c->L; ++l) {
@@ -411,7 +411,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   HIPCHK(hipMemcpyAsync(c->rt_off, roff.data(), roff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   {
     // entries: tet id (home flag in bit 31) and its vertices
-    std::vector<int32_t> et(c->nent_pad, 0), etv(4 * c->nent_pad, 0);
+    std::vector<int32_t> et(c->nent_pad, 0), etv(4 * c->nent_pad, 0), th(c->Tpad, 0);
     for (int64_t r = 0; r < c->nrange; ++r)
       for (int32_t w = roff[r]; w < roff[r + 1]; ++w) {
         const int64_t t = rlist[w];
@@ -420,10 +420,13 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
           etv[4 * w + j] = tets[4 * t + j];
           vmin = std::min(vmin, tets[4 * t + j]);
         }
-        et[w] = int32_t(t) | ((vrange[vmin] == r) ? int32_t(0x80000000u) : 0);
+        const bool home = vrange[vmin] == r;
+        et[w] = int32_t(t) | (home ? int32_t(0x80000000u) : 0);
+        if (home) th[t] = w;
       }
     HIPCHK(hipMemcpy(c->rl_t, et.data(), et.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->rl_tv, etv.data(), etv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->t_home, th.data(), th.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   double *dX = nullptr, *drho = nullptr, *dE = nullptr, *dnu = nullptr;
   TRY(dalloc(&dX, 3 * N));

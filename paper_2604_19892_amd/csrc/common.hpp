@@ -292,7 +292,7 @@ struct Ctx {
   float* hr32 = nullptr;       // element snapshot per entry, float32 Hessian storage
 
   // Hessian snapshot (AoSoA tiles of 64 tets: [Tpad/64][54][64])
-  double* hf64 = nullptr;      // element snapshot per tet (float64), for the block assembly
+  int32_t* t_home = nullptr;   // T: range entry holding each tet's home copy (the block assembly reads it)
   bool built = false;
 
   // base contact set

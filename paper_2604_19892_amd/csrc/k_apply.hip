@@ -34,8 +34,7 @@ __global__ void k_restrict(int64_t n_child, int64_t nodes, const double* child, 
 constexpr int PB = 102;  // doubles per row tile in part[] (16 x 6, padded against bank conflicts)
 
 template <int P>
-__device__ __forceinline__ double unit_entry(const uint2 (&u)[tile_ud(P)], int e) {
-  const uint2 w = u[e / tile_epu(P)];
+__device__ __forceinline__ double decode_entry(uint2 w, int e) {
   if constexpr (P == MAS_F64) {
     return __hiloint2double(int(w.y), int(w.x));
   } else if constexpr (P == MAS_F32) {
@@ -47,19 +46,31 @@ __device__ __forceinline__ double unit_entry(const uint2 (&u)[tile_ud(P)], int e
   }
 }
 
-template <int P>
+// Entry e of this thread's tile: from the registers loaded up front, or
+// (STREAM) loaded from memory where it is used, which keeps the registers
+// of a rarely taken wide path from setting the occupancy of the kernel.
+template <int P, bool STREAM>
+__device__ __forceinline__ double tile_entry(const uint2 (&u)[STREAM ? 1 : tile_ud(P)], const uint2* s2, int t,
+                                             int e) {
+  if constexpr (STREAM) return decode_entry<P>(s2[tile_unit(P, t, e / tile_epu(P))], e);
+  else return decode_entry<P>(u[e / tile_epu(P)], e);
+}
+
+template <int P, bool STREAM = false>
 __device__ __forceinline__ double block_apply(const unsigned char* slot, const float* scale_d, double xv, int bi,
                                               int bj, double* xs, double* part) {
-  constexpr int EPU = tile_epu(P), UO = tile_uo(P), UD = tile_ud(P);
+  constexpr int UO = tile_uo(P), UD = tile_ud(P);
   constexpr bool q16 = (P == MAS_BF16 || P == MAS_F16);
   const int t = threadIdx.x;
   const bool diag = t >= 120;
-  uint2 u[UD];
+  uint2 u[STREAM ? 1 : UD];
   const uint2* s2 = reinterpret_cast<const uint2*>(slot);
+  if constexpr (!STREAM) {
 #pragma unroll
-  for (int k = 0; k < UD; ++k) {
-    u[k] = make_uint2(0u, 0u);
-    if (k < UO || diag) u[k] = s2[tile_unit(P, t, k)];
+    for (int k = 0; k < UD; ++k) {
+      u[k] = make_uint2(0u, 0u);
+      if (k < UO || diag) u[k] = s2[tile_unit(P, t, k)];
+    }
   }
   float sg = 1.0f;
   if (t < BD) {
@@ -80,7 +91,7 @@ __device__ __forceinline__ double block_apply(const unsigned char* slot, const f
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        const double a = unit_entry<P>(u, 6 * r + q);
+        const double a = tile_entry<P, STREAM>(u, s2, t, 6 * r + q);
         acc += a * xj[q];
         w[q] += a * xi[r];
       }
@@ -106,7 +117,8 @@ __device__ __forceinline__ double block_apply(const unsigned char* slot, const f
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-          acc += unit_entry<P>(u, 21 * h + (r >= q ? r * (r + 1) / 2 + q : q * (q + 1) / 2 + r)) * xb[q];
+          acc += tile_entry<P, STREAM>(u, s2, t, 21 * h + (r >= q ? r * (r + 1) / 2 + q : q * (q + 1) / 2 + r)) *
+                 xb[q];
         pd[r] = acc;
       }
     }
@@ -122,10 +134,13 @@ __device__ __forceinline__ double block_apply(const unsigned char* slot, const f
   return z;
 }
 
+// WIDE = false: float64 blocks (promoted ones when a narrower format was
+// requested) take the streamed path.
+template <bool WIDE = true>
 __device__ __forceinline__ double block_apply_any(int P, const unsigned char* slot, const float* scale_d, double xv,
                                                   int bi, int bj, double* xs, double* part) {
   switch (P) {
-    case MAS_F64: return block_apply<MAS_F64>(slot, scale_d, xv, bi, bj, xs, part);
+    case MAS_F64: return block_apply<MAS_F64, !WIDE>(slot, scale_d, xv, bi, bj, xs, part);
     case MAS_F32: return block_apply<MAS_F32>(slot, scale_d, xv, bi, bj, xs, part);
     case MAS_BF16: return block_apply<MAS_BF16>(slot, scale_d, xv, bi, bj, xs, part);
     default: return block_apply<MAS_F16>(slot, scale_d, xv, bi, bj, xs, part);
@@ -179,7 +194,8 @@ struct FineArgs {
 // One workgroup per level-0 subdomain d: z_d = B_d g_d, minus the Woodbury
 // correction W_d C_d^-1 U_d^T B_d g_d where the subdomain was updated, plus
 // the coarse corrections of its vertices.
-__global__ __launch_bounds__(NTILE) void k_apply_l0(FineArgs fa) {
+template <bool WIDE>
+__global__ __launch_bounds__(NTILE, WIDE ? 4 : 5) void k_apply_l0(FineArgs fa) {
   __shared__ double xs[BD];
   __shared__ __align__(16) double part[16 * PB];
   // Woodbury scratch sized by K: factor, r, lambda, slot columns
@@ -209,7 +225,7 @@ __global__ __launch_bounds__(NTILE) void k_apply_l0(FineArgs fa) {
       if (l < fa.L) corr += fa.c[l][3 * (v >> (5 * l)) + t % 3];
   }
   const unsigned char* slot = reinterpret_cast<const unsigned char*>(fa.blk) + d * BLK_STRIDE;
-  double zv = block_apply_any(fa.bprec[d], slot, fa.scale + BD * d, xv, bi, bj, xs, part);
+  double zv = block_apply_any<WIDE>(fa.bprec[d], slot, fa.scale + BD * d, xv, bi, bj, xs, part);
   if (r > 0) {
     __syncthreads();
     if (t < BD) zb[t] = zv;
@@ -291,7 +307,10 @@ mas_status launch_apply(Ctx& c, const double* g, double* z) {
   prof_begin(c, MAS_T_APPLY_L0);
   const int K = std::max(c.K, 1);
   const size_t wlds = sizeof(double) * size_t(K * (K + 1) / 2 + 2 * K + 1) + sizeof(SlotCol) * size_t(K);
-  k_apply_l0<<<dim3(c.lv[0].nsub), dim3(NTILE), wlds, c.s>>>(fa);
+  if (c.lv[0].prec == MAS_F64)
+    k_apply_l0<true><<<dim3(c.lv[0].nsub), dim3(NTILE), wlds, c.s>>>(fa);
+  else
+    k_apply_l0<false><<<dim3(c.lv[0].nsub), dim3(NTILE), wlds, c.s>>>(fa);
   prof_end(c, MAS_T_APPLY_L0);
   HIPCHK(hipGetLastError());
   return MAS_OK;

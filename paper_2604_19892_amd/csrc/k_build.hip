@@ -12,20 +12,17 @@ namespace mas {
 // Element snapshots: per tet the 9x9 tangent of h^2 V Psi with its negative
 // eigenvalues clamped, packed (45), followed by Dm^-1 (9), in the chunked
 // tile layout of snap_load.  One thread per range entry: it writes the
-// entry's copy for the Hessian-vector product (float32 or float64) and, on
-// the tet's home entry, the tet-indexed float64 copy used by the block
-// assembly.
+// entry's copy (float32 or float64), read by the Hessian-vector product and,
+// on the tet's home entry, by the block assembly.
 __global__ __launch_bounds__(64) void k_elem_hess(int64_t nent, int64_t nent_pad, const int32_t* rl_t,
                                                   const int32_t* rl_tv, const double* rl_geo, const double* x,
-                                                  double h, double* hf64, double* hr64, float* hr32) {
+                                                  double h, double* hr64, float* hr32) {
   const int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (w >= nent_pad) return;
   double e[EH];
 #pragma unroll
   for (int q = 0; q < EH; ++q) e[q] = 0.0;
-  int32_t tcode = 0;
   if (w < nent) {
-    tcode = rl_t[w];
     const int4 tv = reinterpret_cast<const int4*>(rl_tv)[w];
     const int v[4] = {tv.x, tv.y, tv.z, tv.w};
     double xe[12];
@@ -59,17 +56,11 @@ __global__ __launch_bounds__(64) void k_elem_hess(int64_t nent, int64_t nent_pad
 #pragma unroll
     for (int c = 0; c < SNAP_NC64; ++c) p64[c * TILE] = make_double2(e[2 * c], e[2 * c + 1]);
   }
-  if (tcode < 0) {
-    const int64_t t = tcode & 0x7fffffff;
-    double2* p64 = reinterpret_cast<double2*>(hf64) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
-#pragma unroll
-    for (int c = 0; c < SNAP_NC64; ++c) p64[c * TILE] = make_double2(e[2 * c], e[2 * c + 1]);
-  }
 }
 
 mas_status launch_elem_hessians(Ctx& c, const double* x_base) {
   k_elem_hess<<<dim3(c.nent_pad / TILE), dim3(TILE), 0, c.s>>>(c.nent, c.nent_pad, c.rl_t, c.rl_tv, c.rl_geo,
-                                                               x_base, c.cfg.h, c.hf64, c.hr64, c.hr32);
+                                                               x_base, c.cfg.h, c.hr64, c.hr32);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }
@@ -196,7 +187,9 @@ struct L0Args {
   int L;
   const int32_t* tets;
   const double* mass;
-  const double* hf64;
+  const int32_t* t_home;  // tet -> its home range entry
+  const float* h32;       // entry snapshots (one of the two is set)
+  const double* h64;
   const int32_t* tet_off;
   const int32_t* tet_list;
   const double* bk;
@@ -236,6 +229,7 @@ __device__ __forceinline__ void add_coupling(double* T, int l, int nb, bool flip
 
 constexpr int L0_THREADS = 128;
 
+template <typename TH>
 __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   __shared__ double A[PK];
   extern __shared__ double T[];  // (L - 1) x 32 node blocks of 9
@@ -268,10 +262,17 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
       }
     }
     if (!(need[0] || need[1] || need[2] || need[3])) continue;
-    double H[EH];
-    snap_load(a.hf64, t, H);
+    constexpr int NH = sizeof(TH) == 8 ? EH : 4 * SNAP_NC32;
+    TH H[NH];
+    if constexpr (sizeof(TH) == 8) snap_load(a.h64, a.t_home[t], H);
+    else snap_load(a.h32, a.t_home[t], H);
     double coef[4][3];
-    dfdx_coef(H + 45, coef);
+    {
+      double dm[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dm[q] = double(H[45 + q]);
+      dfdx_coef(dm, coef);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (!need[j]) continue;
@@ -280,7 +281,8 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
       for (int r = 0; r < 9; ++r)
 #pragma unroll
         for (int y = 0; y < 3; ++y)
-          G[r][y] = H[p9(r, y)] * coef[j][0] + H[p9(r, 3 + y)] * coef[j][1] + H[p9(r, 6 + y)] * coef[j][2];
+          G[r][y] = double(H[p9(r, y)]) * coef[j][0] + double(H[p9(r, 3 + y)]) * coef[j][1] +
+                    double(H[p9(r, 6 + y)]) * coef[j][2];
 #pragma unroll
       for (int i = j; i < 4; ++i) {
         if (dest[i][j] < 0) continue;
@@ -610,7 +612,9 @@ mas_status launch_level0_build(Ctx& c) {
   a.L = c.L;
   a.tets = c.tets;
   a.mass = c.mass;
-  a.hf64 = c.hf64;
+  a.t_home = c.t_home;
+  a.h32 = c.hr32;
+  a.h64 = c.hr64;
   a.tet_off = c.tet_off;
   a.tet_list = c.tet_list;
   a.bk = c.bk;
@@ -620,7 +624,10 @@ mas_status launch_level0_build(Ctx& c) {
   a.bc_list = c.bc_list;
   for (int l = 0; l < c.L; ++l) a.acc[l] = c.lv[l].acc;
   const size_t lds = sizeof(double) * size_t(std::max(c.L - 1, 1)) * SUB * 9;
-  k_assemble_l0<<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+  if (c.hr32)
+    k_assemble_l0<float><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+  else
+    k_assemble_l0<double><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
   launch_invert(c, 0);
   HIPCHK(hipGetLastError());
   return MAS_OK;
