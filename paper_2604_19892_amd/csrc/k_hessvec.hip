@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256, 4) void k_hv_range(int64_t nrange, const int32
 // rank-one stencil columns: y += u (u^T v), scattered through an LDS window
 // (columns in the order given; sorted by smallest vertex they stay local)
 __global__ __launch_bounds__(256) void k_hv_cols(int64_t N, int64_t m, const int32_t* idx, const double* u,
-                                                 const double* v, double* y) {
+                                                 const double* dS, const double* v, double* y) {
   __shared__ double win[3 * SW_WIN];
   const int64_t c0 = int64_t(blockIdx.x) * SW_CHUNK;
   int vbase;
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_hv_cols(int64_t N, int64_t m, const int
   for (int k = 0; k < SW_CHUNK; k += 256) {
     const int64_t i = c0 + k + threadIdx.x;
     if (i >= m) break;
+    if (!(dS[i] > 0.0)) continue;  // zero column (not stored)
     const int4 iv = reinterpret_cast<const int4*>(idx)[i];
     const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
     double uu[12];
@@ -149,7 +150,7 @@ mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update) {
                                                             c.bu, c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
   }
   if (with_update && c.have_update && c.mc > 0)
-    k_hv_cols<<<dim3((c.mc + SW_CHUNK - 1) / SW_CHUNK), dim3(256), 0, c.s>>>(c.N, c.mc, c.Uidx, c.U, v, y);
+    k_hv_cols<<<dim3((c.mc + SW_CHUNK - 1) / SW_CHUNK), dim3(256), 0, c.s>>>(c.N, c.mc, c.Uidx, c.U, c.dS, v, y);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -249,8 +249,8 @@ constexpr int NS = 11;
 __global__ __launch_bounds__(RB) void k_ss_reduce(int64_t n3, const double* g, const double* z,
                                                   const double* zp, const double* p, const double* vz,
                                                   const double* vp, int use_p, int64_t m,
-                                                  const int32_t* Uidx, const double* U, double* part,
-                                                  int nblk) {
+                                                  const int32_t* Uidx, const double* U, const double* dS,
+                                                  double* part, int nblk) {
   double s[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q) s[q] = 0.0;
@@ -269,6 +269,7 @@ __global__ __launch_bounds__(RB) void k_ss_reduce(int64_t n3, const double* g, c
     }
   }
   for (int64_t c = blockIdx.x * int64_t(RB) + threadIdx.x; c < m; c += int64_t(nblk) * RB) {
+    if (!(dS[c] > 0.0)) continue;  // zero column (not stored)
     const int4 iv = reinterpret_cast<const int4*>(Uidx)[c];
     int vi[4] = {iv.x, iv.y, iv.z, iv.w};
     double xz = 0, xp = 0;
@@ -363,7 +364,7 @@ mas_status launch_subspace(Ctx& c, const double* g, const double* z, const doubl
   int64_t n3 = 3 * c.N;
   int64_t m = (c.have_update) ? c.mc : 0;
   k_ss_reduce<<<dim3(nb), dim3(RB), 0, c.s>>>(n3, g, z, zp, p, vz, vp, restart ? 0 : 1, m, c.Uidx, c.U,
-                                              c.partials, nb);
+                                              c.dS, c.partials, nb);
   k_ss_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(c.partials, nb, restart, zp != nullptr, c.cfg.eps_sing,
                                                c.cfg.eps_abs, c.cfg.restart_delta, out, c.scal);
   k_ss_update<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, z, vz, p, vp, c.scal);

@@ -15,7 +15,8 @@ namespace mas {
 //   otherwise            -> dS = 0          (softening)
 // The column u = sqrt(dS) n enters the untruncated U.
 // A contact with k = 0 (d >= dhat) has dS = 0 whatever the base holds, so it
-// is not looked up.  The lookup first tries the same position in the base
+// is not looked up, and a column with dS = 0 is not stored (readers of U
+// test dS first).  The lookup first tries the same position in the base
 // set (contact sets that keep their order between build and update), then a
 // binary search of the sorted base keys.
 __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, const double* d,
@@ -31,12 +32,18 @@ __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, c
   barrier3(di, dhat, &b, &b1, &b2);
   double k = kappa * b2;
   uint64_t kk = key[i];
+  ckey[i] = kk;
+  reinterpret_cast<int4*>(Uidx)[i] = reinterpret_cast<const int4*>(idx)[i];
+  if (!(k > 0.0)) {
+    dS[i] = 0.0;  // the column is zero and is not stored: readers test dS first
+    return;
+  }
   double n[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) n[q] = grad[12 * i + q];
   double s = k;
   int64_t bi = -1;
-  if (k > 0.0) {
+  {
     if (i < mb && bkey[i] == kk) {
       bi = i;
     } else {
@@ -66,12 +73,11 @@ __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, c
   }
   if (!(s > 0.0)) s = 0.0;
   dS[i] = s;
-  ckey[i] = kk;
-  double sq = sqrt(s);
+  if (s > 0.0) {
+    const double sq = sqrt(s);
 #pragma unroll
-  for (int q = 0; q < 12; ++q) U[12 * i + q] = sq * n[q];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) Uidx[4 * i + q] = idx[4 * i + q];
+    for (int q = 0; q < 12; ++q) U[12 * i + q] = sq * n[q];
+  }
 }
 
 // ranking order: larger dS first, then smaller key

@@ -1,0 +1,116 @@
+"""GPU edge cases against the FP64 oracle: ragged sizes (vertex and node
+counts that are not multiples of 32), empty contact sets, a subdomain with
+more Top-K candidates than the register-resident selection holds (the
+rescanning path), and the largest Woodbury rank (K = 32).  Tolerance:
+relative 1e-10 (float64 storage); selections compared exactly."""
+import numpy as np
+import pytest
+
+from oracle import fem, mas, woodbury
+from paper_2604_19892_amd import synth
+
+from test_gpu_parity import Case, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def empty_set():
+    return synth.contact_set(np.zeros(0, np.uint64), np.zeros((0, 4), np.int32), np.zeros((0, 12)),
+                             np.zeros(0))
+
+
+def crowded_set(sc, n, seed, verts):
+    """n point-plane contacts on the given vertices (original ids), distinct
+    keys, random normals, distances uniform in (1e-5, dhat)."""
+    rng = np.random.default_rng(seed)
+    pts = rng.choice(verts, n)
+    nrm = rng.standard_normal((n, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    idx = np.full((n, 4), -1, np.int32)
+    idx[:, 0] = pts
+    grad = np.zeros((n, 12))
+    grad[:, :3] = nrm
+    key = (np.uint64(synth.KEY_PLANE) << np.uint64(60)) | (np.uint64(1 << 20) + np.arange(n, dtype=np.uint64))
+    return synth.contact_set(key, idx, grad, rng.uniform(1e-5, sc.dhat, n))
+
+
+def check_case(c, blocks=True):
+    D = c.hier.num_subdomains(0)
+    if blocks:
+        worst = max(rel(c.ctx.get_block(0, d)[:c.M.fine[d].shape[0], :c.M.fine[d].shape[0]], c.M.fine[d])
+                    for d in range(D))
+        assert worst < 1e-10, worst
+        for l in range(1, c.hier.L):
+            _, _, invs = c.M.coarse[l - 1]
+            for d, (dofs, Minv) in enumerate(invs):
+                n = Minv.shape[0]
+                assert rel(c.ctx.get_block(l, d)[:n, :n], Minv) < 1e-10, (l, d)
+    rank, sel = c.ctx.get_selection()
+    for d in range(D):
+        want = c.sel.get(d, [])
+        assert rank[d] == len(want), d
+        assert list(sel[d, :rank[d]]) == list(want), d
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(3 * c.scene.N)
+    zo = c.M.apply(g, c.blocks)
+    zg = c.ctx.from_lib(c.ctx.apply(c.ctx.to_lib(g)))
+    assert rel(zg, zo) < 1e-10, rel(zg, zo)
+    v = rng.standard_normal(3 * c.scene.N)
+    yo = c.H @ v + c.U @ (c.U.T @ v)
+    y = c.ctx.from_lib(c.ctx.hess_vec(c.ctx.to_lib(v), with_update=True))
+    assert rel(y, yo) < 1e-10, rel(y, yo)
+    code, msg = c.ctx.sync()
+    assert code == 0, msg
+    return rank
+
+
+@pytest.mark.parametrize("n,levels", [(9, 2), (9, 3), (7, 2)])
+def test_ragged_sizes(n, levels):
+    sc = synth.grid_scene(n=n, n_contacts=min(200, n ** 3 // 2))
+    print("\n[edge case] grid n=%d (%d vertices) levels=%d" % (n, sc.N, levels), flush=True)
+    assert sc.N % 32 != 0
+    base, curr = synth.grid_update_sets(sc)
+    c = Case(sc, base, curr, levels=levels, K=8)
+    try:
+        check_case(c)
+    finally:
+        c.ctx.close()
+
+
+def test_empty_contact_sets():
+    sc = synth.grid_scene()
+    print("\n[edge case] grid, empty base and current sets", flush=True)
+    c = Case(sc, empty_set(), empty_set(), levels=2, K=8)
+    try:
+        rank = check_case(c)
+        assert np.all(rank == 0)
+    finally:
+        c.ctx.close()
+
+
+def test_long_candidate_list_uses_rescanning_topk():
+    sc = synth.grid_scene()
+    hier = mas.Hierarchy(sc.X, 2)
+    first = hier.perm[:32]                      # original ids of subdomain 0
+    curr = crowded_set(sc, 700, 3, first)
+    print("\n[edge case] 700 candidates in subdomain 0", flush=True)
+    c = Case(sc, empty_set(), curr, levels=2, K=8)
+    try:
+        cnt = np.bincount(hier.rank[curr['idx'][:, 0]] // 32, minlength=hier.num_subdomains(0))
+        assert cnt[0] > 64 * 8
+        rank = check_case(c, blocks=False)
+        assert rank[0] == 8
+    finally:
+        c.ctx.close()
+
+
+def test_largest_rank_K32():
+    sc = synth.grid_scene()
+    curr = crowded_set(sc, 1200, 4, np.arange(sc.N))
+    print("\n[edge case] K = 32, 1200 new contacts", flush=True)
+    c = Case(sc, empty_set(), curr, levels=2, K=32)
+    try:
+        rank = check_case(c, blocks=False)
+        assert rank.max() == 32
+    finally:
+        c.ctx.close()

@@ -1,0 +1,166 @@
+"""Parity at the full size of the benchmark workload (puffer balls,
+1,140,096 vertices, 2,709,600 tets, 1.25M stencils; float32 blocks and
+element Hessians, four levels, K = 8: the configuration bench.py times).
+
+The oracle cannot assemble or invert the whole system at this size, so it
+checks sampled outputs it computes one by one (level-0 blocks and rows of
+H_base v assembled from only the tets and stencils touching a sampled
+subdomain; energy and gradient in full, vectorised) and properties that
+hold at any size (P and H_base symmetric positive definite).
+Tolerances: 1e-5 where float32 storage enters, 1e-10 for the float64
+energy and gradient."""
+import numpy as np
+import pytest
+
+from oracle import fem, mas
+from paper_2604_19892_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    print("\n[full-size case] puffer balls, f32 blocks and element Hessians", flush=True)
+    sc = synth.puffer_scene()
+    ctx = MasContext(sc, make_config(sc, block_prec="f32", hess_prec="f32"))
+    d0 = synth.pool_distance(sc.pool, sc.x)
+    # both sides take the same distances
+    pool = ctx.contacts(dict(key=sc.pool["key"], idx=sc.pool["idx"], grad=sc.pool["grad"], d=d0), sort=True)
+    x = ctx.to_lib(sc.x)
+    ctx.build(x, pool)
+    code, msg = ctx.sync()
+    assert code == 0, msg
+    prob = fem.Problem(sc)
+    hier = mas.Hierarchy(sc.X, sc.levels)
+    yield dict(sc=sc, ctx=ctx, pool=pool, x=x, prob=prob, hier=hier, d0=d0, torch=torch)
+    ctx.close()
+
+
+def local_system(f, d):
+    """S_d H_base S_d^T from the masses, tets and stencils touching d."""
+    sc, prob, hier = f["sc"], f["prob"], f["hier"]
+    verts = hier.perm[32 * d: 32 * (d + 1)]
+    loc = -np.ones(sc.N, np.int64)
+    loc[verts] = np.arange(verts.size)
+    n = 3 * verts.size
+    A = np.diag(np.repeat(prob.mass[verts], 3))
+    tmask = (loc[sc.tets] >= 0).any(1)
+    tets = prob.tets[tmask]
+    He = fem.elem_hessians(sc.x, tets, prob.Dm_inv[tmask], prob.vol[tmask], prob.mu[tmask],
+                           prob.lam[tmask], prob.h)
+    for e in range(tets.shape[0]):
+        for i in range(4):
+            li = loc[tets[e, i]]
+            if li < 0:
+                continue
+            for j in range(4):
+                lj = loc[tets[e, j]]
+                if lj >= 0:
+                    A[3 * li:3 * li + 3, 3 * lj:3 * lj + 3] += He[e, 3 * i:3 * i + 3, 3 * j:3 * j + 3]
+    idx = sc.pool["idx"]
+    cmask = ((idx >= 0) & (loc[np.maximum(idx, 0)] >= 0)).any(1)
+    k = prob.contact_stiffness(f["d0"][cmask])
+    for c_, kc in zip(np.nonzero(cmask)[0], k):
+        if kc == 0.0:
+            continue
+        n12 = sc.pool["grad"][c_]
+        for i in range(4):
+            vi = idx[c_, i]
+            if vi < 0 or loc[vi] < 0:
+                continue
+            for j in range(4):
+                vj = idx[c_, j]
+                if vj < 0 or loc[vj] < 0:
+                    continue
+                A[3 * loc[vi]:3 * loc[vi] + 3, 3 * loc[vj]:3 * loc[vj] + 3] += \
+                    kc * np.outer(n12[3 * i:3 * i + 3], n12[3 * j:3 * j + 3])
+    return verts, tets, He, cmask, A
+
+
+SAMPLE = (0, 7777, 17000, 35627)
+
+
+def test_morton_order_full(full):
+    np.testing.assert_array_equal(full["ctx"].perm, full["hier"].perm)
+
+
+def test_sampled_level0_blocks(full):
+    for d in SAMPLE:
+        _, _, _, _, A = local_system(full, d)
+        n = A.shape[0]
+        Bg = full["ctx"].get_block(0, d)[:n, :n]
+        err = rel(Bg, np.linalg.inv(A))
+        print("block %d: rel err %.2e" % (d, err))
+        assert err < 1e-5, (d, err)
+
+
+def test_sampled_hess_vec_rows(full):
+    sc, ctx, prob = full["sc"], full["ctx"], full["prob"]
+    rng = np.random.default_rng(21)
+    v = rng.standard_normal((sc.N, 3))
+    y = ctx.from_lib(ctx.hess_vec(ctx.to_lib(v), with_update=False)).reshape(-1, 3)
+    idx, grad = sc.pool["idx"], sc.pool["grad"]
+    for d in SAMPLE:
+        verts, tets, He, cmask, _ = local_system(full, d)
+        yo = np.zeros((sc.N, 3))
+        yo[verts] = prob.mass[verts, None] * v[verts]
+        ve = v[tets].reshape(-1, 12)
+        fe = np.einsum("tij,tj->ti", He, ve).reshape(-1, 4, 3)
+        for j in range(4):
+            np.add.at(yo, tets[:, j], fe[:, j])
+        k = prob.contact_stiffness(full["d0"][cmask])
+        vs = fem.stencil_gather(idx[cmask], v)
+        s = k * (grad[cmask] * vs).sum(1)
+        yo += fem.stencil_scatter(idx[cmask], s[:, None] * grad[cmask], sc.N)
+        err = rel(y[verts], yo[verts])
+        print("hess_vec rows of %d: rel err %.2e" % (d, err))
+        assert err < 1e-5, (d, err)
+
+
+def test_energy_gradient_full(full):
+    sc, ctx, prob, torch = full["sc"], full["ctx"], full["prob"], full["torch"]
+    xt_o = fem.inertial_target(sc.x, sc.v, sc.h, sc.gravity).reshape(-1)
+    cset = dict(idx=sc.pool["idx"], grad=sc.pool["grad"], d=full["d0"])
+    Eo = prob.energy(sc.x, xt_o, cset)
+    go = prob.gradient(sc.x, xt_o, cset)
+    xt = ctx.inertial_target(full["x"], ctx.to_lib(sc.v))
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = ctx.vec()
+    ctx.energy_grad(full["x"], xt, full["pool"], E, g)
+    assert float(E.item()) == pytest.approx(Eo, rel=1e-10)
+    assert rel(ctx.from_lib(g), go) < 1e-10
+
+
+def test_apply_and_hess_vec_spd_full(full):
+    sc, ctx = full["sc"], full["ctx"]
+    rng = np.random.default_rng(22)
+    # a Woodbury update: a fifth of the stencils close to between half and
+    # all of their distance (stiffening)
+    dc = full["d0"].copy()
+    pick = rng.random(dc.size) < 0.2
+    dc[pick] *= rng.uniform(0.5, 1.0, pick.sum())
+    cur = ctx.contacts(dict(key=sc.pool["key"], idx=sc.pool["idx"], grad=sc.pool["grad"], d=dc), sort=True)
+    hist = full["torch"].zeros(ctx.cfg.max_rank + 1, dtype=full["torch"].int32, device="cuda")
+    ctx.woodbury_update(cur, hist)
+    h = hist.cpu().numpy()
+    print("rank histogram", h.tolist())
+    assert h[1:].sum() > 0
+    a, b = rng.standard_normal((2, 3 * sc.N))
+    Pa = ctx.from_lib(ctx.apply(ctx.to_lib(a)))
+    Pb = ctx.from_lib(ctx.apply(ctx.to_lib(b)))
+    assert abs(a @ Pb - b @ Pa) < 1e-10 * abs(a @ Pa)
+    assert a @ Pa > 0 and b @ Pb > 0
+    Ha = ctx.from_lib(ctx.hess_vec(ctx.to_lib(a), with_update=True))
+    Hb = ctx.from_lib(ctx.hess_vec(ctx.to_lib(b), with_update=True))
+    assert abs(a @ Hb - b @ Ha) < 1e-10 * abs(a @ Ha)
+    assert a @ Ha > 0 and b @ Hb > 0
+    code, msg = ctx.sync()
+    assert code == 0, msg
