@@ -20,7 +20,7 @@ namespace mas {
 // Resident workgroups take ranges from a counter (dynamic balance); each
 // exits once the counter has passed the last range.
 template <typename TH>
-__global__ __launch_bounds__(256, 4) void k_hv_range(int64_t nrange, const int32_t* rbeg, const int32_t* rt_off,
+__global__ __launch_bounds__(256, 3) void k_hv_range(int64_t nrange, const int32_t* rbeg, const int32_t* rt_off,
                                                      const int32_t* rl_tv, const TH* hr, const int32_t* bidx,
                                                      const double* bu, const int32_t* rc_off, const int32_t* rc_list,
                                                      const double* mass, const double* v, double* y, uint32_t* ctr) {
