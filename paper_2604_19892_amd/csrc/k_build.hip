@@ -239,10 +239,12 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
   for (int e = tid; e < nT; e += blockDim.x) T[e] = 0.0;
   __syncthreads();
+  // the lumped mass goes in before any tet or stencil adds to the diagonal
   if (tid < BD) {
     int64_t v = SUB * d + tid / 3;
     A[pk(tid, tid)] = (v < a.N) ? a.mass[v] : 1.0;
   }
+  __syncthreads();
   const int t0 = a.tet_off[d], t1 = a.tet_off[d + 1];
   for (int w = t0 + tid; w < t1; w += blockDim.x) {
     const int64_t t = a.tet_list[w];
