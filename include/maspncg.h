@@ -33,9 +33,11 @@
  * Vectors.  Device float64 arrays of length 3N, xyz interleaved per vertex.
  *
  * Contacts.  An affine distance stencil over up to four vertices:
- * key (identity, uint64), idx[4] (library vertex ids, -1 padded), d (current
- * distance) and grad[12] = dd/dx.  Contacts with d >= dhat carry zero
- * stiffness.  All contact arrays are device pointers.
+ * key (identity, uint64; unique within a set and different from
+ * 0xffffffffffffffff, which marks free slots of the library's key table),
+ * idx[4] (library vertex ids, -1 padded), d (current distance) and
+ * grad[12] = dd/dx.  Contacts with d >= dhat carry zero stiffness.  All
+ * contact arrays are device pointers.
  *
  * Memory ownership.  The caller owns every pointer it passes.  The library
  * copies what it keeps (mesh at mas_create, the base contact set at

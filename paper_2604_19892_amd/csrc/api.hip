@@ -153,7 +153,7 @@ mas_status mas_destroy(void* p) {
   hipStreamSynchronize(c->s);
   void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->tet_list, c->rt_off, c->rbeg, c->vrange, c->ctr, c->rl_t, c->rl_tv,
                   c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->t_home, c->bkey,
-                  c->bkey_sorted, c->biota, c->bperm, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
+                  c->hkey, c->hval, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
                   c->alpha, c->amark, c->err, c->diag, c->cub_tmp};

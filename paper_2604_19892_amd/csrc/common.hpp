@@ -244,6 +244,17 @@ __device__ inline void diag_report(DiagRec* dg, int source, int level, int64_t i
   }
 }
 
+// Base-key table: linear probing from a SplitMix64-finalised hash (Steele,
+// Lea and Flood 2014; the finaliser constants as Vigna published them).
+constexpr uint64_t HKEY_EMPTY = ~uint64_t(0);
+__host__ __device__ inline uint64_t key_hash(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
 struct SlotCol {        // one column of U_d restricted to its subdomain
   int32_t lv[4];        // local vertex (0..31) of each stencil vertex, -1 if outside
   double u[12];
@@ -298,9 +309,9 @@ struct Ctx {
   // base contact set
   int64_t mb = 0, mb_cap = 0;
   uint64_t* bkey = nullptr;        // mb, input order
-  uint64_t* bkey_sorted = nullptr; // mb
-  int32_t* biota = nullptr;        // mb
-  int32_t* bperm = nullptr;        // mb: sorted position -> input index
+  uint64_t* hkey = nullptr;        // hcap: open-addressing table of the base keys (HKEY_EMPTY: free)
+  int32_t* hval = nullptr;         // hcap: base index of each stored key
+  int64_t hcap = 0;                // power of two, at least twice the base capacity
   double* bk = nullptr;            // mb stiffness
   double* bgrad = nullptr;         // 12 mb
   int32_t* bidx = nullptr;         // 4 mb

@@ -71,7 +71,7 @@ mas_status launch_elem_hessians(Ctx& c, const double* x_base) {
 // wavefront in 64-element strides so that every store is contiguous.
 __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* key, const int32_t* idx,
                                                    const double* d, const double* grad, double kappa, double dhat,
-                                                   uint64_t* bkey, int32_t* biota, double* bk, double* bgrad,
+                                                   uint64_t* bkey, double* bk, double* bgrad,
                                                    int32_t* bidx, double* bu, uint32_t* err) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -85,7 +85,6 @@ __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* ke
     const double k = kappa * b2;
     bk[i] = k;
     bkey[i] = key[i];
-    biota[i] = int32_t(i);
     sk = sqrt(k);
 #pragma unroll
     for (int q = 0; q < 4; ++q) bidx[4 * i + q] = idx[4 * i + q];
@@ -103,18 +102,49 @@ __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* ke
   }
 }
 
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// Inserts the keys of the base contacts with k > 0 into the table (it has at
+// least twice as many slots as keys, so every probe sequence meets a free
+// slot).  A base contact with k = 0 classifies a current one exactly as
+// absence does (dS = k either way), so it is left out.  A key already
+// present keeps its first entry.
+__global__ void k_hash_insert(int64_t m, const uint64_t* key, const double* bk, uint64_t* hkey, int32_t* hval,
+                              int64_t mask) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= m || !(bk[i] > 0.0)) return;
+  const uint64_t k = key[i];
+  int64_t h = int64_t(key_hash(k) & uint64_t(mask));
+  while (true) {
+    const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(hkey + h),
+                                              (unsigned long long)HKEY_EMPTY, (unsigned long long)k);
+    if (prev == HKEY_EMPTY) {
+      hval[h] = int32_t(i);
+      return;
+    }
+    if (prev == k) return;
+    h = (h + 1) & mask;
+  }
+}
+
 static mas_status grow_base(Ctx& c, int64_t m) {
   if (m <= c.mb_cap) return MAS_OK;
   int64_t cap = m + m / 4 + 1024;
-  hipFree(c.bkey); hipFree(c.bkey_sorted); hipFree(c.biota); hipFree(c.bperm);
+  hipFree(c.bkey); hipFree(c.hkey); hipFree(c.hval);
   hipFree(c.bk); hipFree(c.bgrad); hipFree(c.bidx); hipFree(c.bu); hipFree(c.bc_list); hipFree(c.rc_list);
-  bool ok = hipMalloc(&c.bkey, 8 * cap) == hipSuccess && hipMalloc(&c.bkey_sorted, 8 * cap) == hipSuccess &&
-            hipMalloc(&c.biota, 4 * cap) == hipSuccess && hipMalloc(&c.bperm, 4 * cap) == hipSuccess &&
+  int64_t hcap = 1024;
+  while (hcap < 2 * cap) hcap *= 2;
+  bool ok = hipMalloc(&c.bkey, 8 * cap) == hipSuccess && hipMalloc(&c.hkey, 8 * hcap) == hipSuccess &&
+            hipMalloc(&c.hval, 4 * hcap) == hipSuccess &&
             hipMalloc(&c.bk, 8 * cap) == hipSuccess && hipMalloc(&c.bgrad, 96 * cap) == hipSuccess &&
             hipMalloc(&c.bidx, 16 * cap) == hipSuccess && hipMalloc(&c.bu, 96 * cap) == hipSuccess &&
             hipMalloc(&c.bc_list, 16 * cap) == hipSuccess && hipMalloc(&c.rc_list, 16 * cap) == hipSuccess;
   if (!ok) return MAS_ERR_OOM;
   c.mb_cap = cap;
+  c.hcap = hcap;
   return MAS_OK;
 }
 
@@ -126,11 +156,12 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
   if (m > 0) {
     int bs = 256;
     k_base_copy<<<dim3((m + bs - 1) / bs), dim3(bs), 0, c.s>>>(
-        m, b->key, b->idx, b->d, b->grad, c.cfg.kappa, c.cfg.dhat, c.bkey, c.biota, c.bk, c.bgrad,
+        m, b->key, b->idx, b->d, b->grad, c.cfg.kappa, c.cfg.dhat, c.bkey, c.bk, c.bgrad,
         c.bidx, c.bu, c.err);
+    k_fill_u64<<<dim3(std::min<int64_t>(1024, (c.hcap + 255) / 256)), dim3(256), 0, c.s>>>(c.hkey, c.hcap,
+                                                                                            HKEY_EMPTY);
+    k_hash_insert<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(m, c.bkey, c.bk, c.hkey, c.hval, c.hcap - 1);
     HIPCHK(hipGetLastError());
-    st = sort_keys(c, m, c.bkey, c.bkey_sorted, c.biota, c.bperm);
-    if (st != MAS_OK) return st;
   }
   st = bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
   if (st != MAS_OK) return st;

@@ -1,4 +1,4 @@
-// Bucketing of contact stencils into per-subdomain lists and key sorting.
+// Bucketing of contact stencils into per-subdomain and per-range lists.
 #include <hipcub/hipcub.hpp>
 
 #include "kernels.hpp"
@@ -120,19 +120,6 @@ mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64
 mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
                                int32_t* cnt, int32_t* off, int32_t* list) {
   return bucket_stencils(c, SUB, nullptr, c.lv[0].nsub, m, idx, w, vec12, cnt, off, list);
-}
-
-mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
-                     const int32_t* vals_in, int32_t* vals_out) {
-  if (m == 0) return MAS_OK;
-  size_t bytes = 0;
-  HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, keys_in, keys_out, vals_in, vals_out,
-                                            int(m), 0, 64, c.s));
-  mas_status st = ensure_cub(c, bytes);
-  if (st != MAS_OK) return st;
-  HIPCHK(hipcub::DeviceRadixSort::SortPairs(c.cub_tmp, bytes, keys_in, keys_out, vals_in, vals_out,
-                                            int(m), 0, 64, c.s));
-  return MAS_OK;
 }
 
 }  // namespace mas

@@ -17,11 +17,11 @@ namespace mas {
 // A contact with k = 0 (d >= dhat) has dS = 0 whatever the base holds, so it
 // is not looked up, and a column with dS = 0 is not stored (readers of U
 // test dS first).  The lookup first tries the same position in the base
-// set (contact sets that keep their order between build and update), then a
-// binary search of the sorted base keys.
+// set (contact sets that keep their order between build and update), then
+// the base-key hash table.
 __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, const double* d,
                            const double* grad, double kappa, double dhat, double cos_rot, int64_t mb,
-                           const uint64_t* bkey, const uint64_t* bkey_sorted, const int32_t* bperm,
+                           const uint64_t* bkey, const uint64_t* hkey, const int32_t* hval, int64_t hmask,
                            const double* bk, const double* bgrad, double* U, int32_t* Uidx, double* dS,
                            uint64_t* ckey, uint32_t* err) {
   int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -46,15 +46,18 @@ __global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, c
   {
     if (i < mb && bkey[i] == kk) {
       bi = i;
-    } else {
-      // lower_bound in the sorted base keys
-      int64_t lo = 0, hi = mb;
-      while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (bkey_sorted[mid] < kk) lo = mid + 1;
-        else hi = mid;
+    } else if (mb > 0) {
+      // probe the base-key table until the key or a free slot
+      int64_t h = int64_t(key_hash(kk) & uint64_t(hmask));
+      while (true) {
+        const uint64_t hk = hkey[h];
+        if (hk == kk) {
+          bi = hval[h];
+          break;
+        }
+        if (hk == HKEY_EMPTY) break;
+        h = (h + 1) & hmask;
       }
-      if (lo < mb && bkey_sorted[lo] == kk) bi = bperm[lo];
     }
   }
   if (bi >= 0) {
@@ -343,7 +346,7 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
   if (m > 0) {
     k_classify<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(
         m, cur->key, cur->idx, cur->d, cur->grad, c.cfg.kappa, c.cfg.dhat, c.cfg.cos_rot, c.mb,
-        c.bkey, c.bkey_sorted, c.bperm, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
+        c.bkey, c.hkey, c.hval, c.hcap - 1, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
     HIPCHK(hipGetLastError());
   }
   st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);

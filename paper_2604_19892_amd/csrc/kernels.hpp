@@ -13,8 +13,7 @@ mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const doub
 // the same into D buckets map[v] (map non-null) or v / div
 mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
                            const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
-mas_status sort_keys(Ctx& c, int64_t m, const uint64_t* keys_in, uint64_t* keys_out,
-                     const int32_t* vals_in, int32_t* vals_out);
+
 mas_status ensure_cub(Ctx& c, size_t bytes);
 // one-thread store of a counter (graph-capturable, unlike a memset)
 __global__ void k_set_u32(uint32_t* p, uint32_t v);
