@@ -244,6 +244,18 @@ __device__ inline void diag_report(DiagRec* dg, int source, int level, int64_t i
   }
 }
 
+// Logical workgroup index for L2 locality: workgroups are dealt to the
+// eight XCDs (each with its own L2) in turn, so workgroup b runs on XCD
+// b mod 8.  This bijection of [0, G) gives every XCD a contiguous run of
+// logical indices, so neighbouring work that reads the same cache lines
+// (gathers of shared vertices, entries of one vertex range) meets in one L2
+// instead of fetching the lines once per XCD.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+  const int64_t q = G / NXCD, r = G % NXCD, x = b % NXCD, k = b / NXCD;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Base-key table: linear probing from a SplitMix64-finalised hash (Steele,
 // Lea and Flood 2014; the finaliser constants as Vigna published them).
 constexpr uint64_t HKEY_EMPTY = ~uint64_t(0);

@@ -17,7 +17,7 @@ namespace mas {
 __global__ __launch_bounds__(64) void k_elem_hess(int64_t nent, int64_t nent_pad, const int32_t* rl_t,
                                                   const int32_t* rl_tv, const double* rl_geo, const double* x,
                                                   double h, double* hr64, float* hr32) {
-  const int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (w >= nent_pad) return;
   double e[EH];
 #pragma unroll
@@ -264,7 +264,7 @@ template <typename TH>
 __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   __shared__ double A[PK];
   extern __shared__ double T[];  // (L - 1) x 32 node blocks of 9
-  const int64_t d = blockIdx.x;
+  const int64_t d = xcd_block(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int nT = (a.L - 1) * SUB * 9;
   for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;

@@ -382,7 +382,7 @@ __global__ void k_alpha_init(int64_t D, double* alpha) {
 // s = -sum_j grad_j . p_j > 0, to every subdomain the stencil touches
 __global__ __launch_bounds__(256) void k_alpha_stencils(int64_t m, const int32_t* idx, const double* grad,
                                                         const double* d, const double* p, double* alpha) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int vi[4] = {-1, -1, -1, -1};
   double a = INFINITY;
   if (i < m) {
@@ -419,7 +419,7 @@ __global__ void k_step(int64_t n3, const double* x, const double* p, const doubl
 __global__ __launch_bounds__(256) void k_alpha_check(int64_t m, const int32_t* idx, const double* grad,
                                                      const double* d, const double* p, const double* alpha,
                                                      uint8_t* mark, uint32_t* count) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   bool viol = false;
   if (i < m) {
     const double di = d[i];

@@ -89,7 +89,7 @@ mas_status launch_inertial(Ctx& c, const double* xt, const double* vt, double* x
 
 __global__ void k_stencil_distance(int64_t m, const double* x, const int32_t* idx,
                                    const double* grad, const double* off, double* d) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= m) return;
   double acc = 0;
   for (int j = 0; j < 4; ++j) {
