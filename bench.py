@@ -169,6 +169,31 @@ def hbm_probe(reps=5):
     return out
 
 
+def ccd_measure(ctx, solver, reps=10):
+    """Conservative CCD (supplement Section 3.4) of every point-triangle /
+    edge-edge stencil of the pool along the step to the inertial target
+    x~ - x (the time step's predicted motion), timed with the library's
+    events; the inputs are device tensors prepared before the clock."""
+    import torch
+    pool = solver.pool
+    m = int(pool.idx.shape[0])
+    step = solver.xt - solver.x
+    kind = ((pool.key >> 60) == 3).to(torch.uint8)          # key tag 3: edge-edge, 2: point-triangle
+    dist = pool.d.clamp_min(0.0)
+    ap = torch.empty(m, dtype=torch.float64, device=pool.idx.device)
+    alpha = torch.empty(int(ctx.nsub[0]), dtype=torch.float64, device=pool.idx.device)
+    ctx.ccd_steps(solver.x, step, pool.idx, kind, dist, ap, alpha)
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.ccd_steps(solver.x, step, pool.idx, kind, dist, ap, alpha)
+    ms, n = ctx.profile_read("ccd")
+    ctx.profile(False)
+    us = 1e3 * ms / max(n, 1)
+    return {"pairs": m, "us_per_call": us, "pairs_per_s": m / (us * 1e-6),
+            "pairs_with_step_below_1": float((ap < 1.0).double().mean().item()),
+            "subdomains_with_step_below_1": float((alpha < 1.0).double().mean().item())}
+
+
 def tolerance_solves(sc, precs, tol, max_iter, repeats):
     """PNCG solves per block storage precision from the same start to
     ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds of each
@@ -338,6 +363,7 @@ def main():
     if code != 0:
         print("[bench] library error: %s" % msg, file=sys.stderr)
         sys.exit(1)
+    out["ccd"] = ccd_measure(ctx, solver)
     out["hbm_probe"] = hbm_probe()
     if not args.no_solve:
         solver.ctx.close()

@@ -214,6 +214,26 @@ mas_status mas_stencil_distance(void* ctx, const double* x, int64_t m, const int
 mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_contacts* cand,
                          double scale, double* alpha, double* x_out);
 
+/* Conservative CCD of point-triangle and edge-edge pairs (supplement
+ * Section 3.4, Algorithms 1 and 2).  Per pair: the lower bound
+ * alpha_l = dist / l with l the largest relative displacement along p of a
+ * vertex of one primitive and a vertex of the other (supplement Eqs. (29),
+ * (31)); then the coplanarity cubic f(t), the signed volume of the four
+ * vertices at x + t p, is cut at its critical points into monotonic pieces
+ * on [max(0, alpha_l), 1] and the first piece whose ends differ in sign is
+ * bisected 16 times toward the safe side (a piece entered past alpha_l
+ * returns its start); 1 if no piece changes sign.
+ * x, p: device 3N.  pairs: device int32 4m, library vertex ids,
+ * point-triangle (P, T0, T1, T2) or edge-edge (E1a, E1b, E2a, E2b); kind:
+ * device uint8 m, 0 = point-triangle, 1 = edge-edge; dist: device float64 m,
+ * the pairs' current distances (a lower bound is safe).  alpha_pair
+ * (device float64 m, nullable) receives the pair steps; alpha (device
+ * float64 D_0, nullable) receives per level-0 subdomain the smallest step
+ * of the pairs with a vertex in it, 1 where there is none (Algorithm 1's
+ * per-subdomain alpha_d). */
+mas_status mas_ccd_steps(void* ctx, const double* x, const double* p, int64_t m, const int32_t* pairs,
+                         const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
+
 /* Synchronises the stream and returns the sticky device error (and clears
  * it); msg (nullable) receives a description. */
 mas_status mas_sync_status(void* ctx, char* msg, int32_t msg_len);
@@ -247,7 +267,8 @@ typedef enum {
   MAS_T_BUILD = 6,        /* the whole mas_build call */
   MAS_T_ENERGY = 7,       /* the whole mas_energy_grad call */
   MAS_T_SUBSPACE = 8,     /* the whole pncg_subspace_step call */
-  MAS_T_COUNT = 9
+  MAS_T_CCD = 9,          /* the whole mas_ccd_steps call */
+  MAS_T_COUNT = 10
 } mas_timer;
 
 /* Enables (1) or disables (0) the kernel timers; enabling clears them. */

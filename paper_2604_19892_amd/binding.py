@@ -198,6 +198,13 @@ class MasContext:
             self.h, _ptr(x), contacts.m, _ptr(contacts.idx), _ptr(contacts.grad), _ptr(contacts.off),
             _ptr(contacts.d)))
 
+    def ccd_steps(self, x, p, pairs, kind, dist, alpha_pair=None, alpha=None):
+        """Conservative CCD step of each point-triangle / edge-edge pair and
+        the per-subdomain minima (device tensors; pairs in library ids)."""
+        m = int(pairs.shape[0])
+        check("mas_ccd_steps", _abi.lib().mas_ccd_steps(self.h, _ptr(x), _ptr(p), m, _ptr(pairs), _ptr(kind),
+                                                       _ptr(dist), _ptr(alpha_pair), _ptr(alpha)))
+
     def safe_step(self, x, p, cand, scale, x_out, alpha=None):
         c = cand.struct() if cand is not None else None
         check("mas_safe_step", _abi.lib().mas_safe_step(self.h, _ptr(x), _ptr(p), ctypes.byref(c) if c else None,

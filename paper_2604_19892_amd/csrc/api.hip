@@ -534,6 +534,13 @@ mas_status mas_safe_step(void* p, const double* x, const double* pv, const mas_c
   return launch_safe_step(*as_ctx(p), x, pv, cand, scale, alpha, x_out);
 }
 
+mas_status mas_ccd_steps(void* p, const double* x, const double* pv, int64_t m, const int32_t* pairs,
+                         const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha) {
+  if (!p || !x || !pv || m < 0) return MAS_ERR_INVALID_ARG;
+  if (m > 0 && (!pairs || !kind || !dist)) return MAS_ERR_INVALID_ARG;
+  return launch_ccd(*as_ctx(p), x, pv, m, pairs, kind, dist, alpha_pair, alpha);
+}
+
 mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
   if (!p) return MAS_ERR_INVALID_ARG;
   Ctx& c = *as_ctx(p);

@@ -48,4 +48,8 @@ mas_status launch_subspace(Ctx& c, const double* g, const double* z, const doubl
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out);
 
+// k_ccd.hip ------------------------------------------------------------
+mas_status launch_ccd(Ctx& c, const double* x, const double* p, int64_t m, const int32_t* pairs,
+                      const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
+
 }  // namespace mas
