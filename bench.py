@@ -13,7 +13,7 @@ when the restart test asks for them, inside the timed region.
 Prints one JSON line.  The roofline object covers the level-0 kernel of
 mas_apply, timed with HIP events recorded by the library on its own stream
 during the timed steps.  After the timed steps, ``tol_solve`` solves from
-the same start to ||grad E|| <= 1e-6 ||grad E_0|| three times per level-0
+the same start to ||grad E|| <= 1e-6 ||grad E_0|| five times per level-0
 block storage (f64 with float64 element Hessians; f32, bf16 and f16 with
 float32 element Hessians) and reports iterations and wall-clock times.
 """
@@ -241,7 +241,7 @@ def main():
                     help="skip the solves to the gradient tolerance (f64 vs mixed storage)")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=1500)
-    ap.add_argument("--solve-repeats", type=int, default=3)
+    ap.add_argument("--solve-repeats", type=int, default=5)
     ap.add_argument("--small", action="store_true", help="two-boxes scene instead (quick check)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference size for rocprofv3 byte counters)")

@@ -24,8 +24,8 @@ constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
 // without atomics.  Ranges are cut so that each is touched by about
 // RANGE_TETS tets; resident workgroups take ranges from a counter until all
 // are done.
-constexpr int RANGE_MAX = 1024;
-constexpr int RANGE_TETS = 2048;
+constexpr int RANGE_MAX = 2048;
+constexpr int RANGE_TETS = 4096;
 constexpr int SNAP_NC64 = EH / 2;       // 16-byte chunks per float64 snapshot (27)
 constexpr int SNAP_NC32 = (EH + 3) / 4; // 16-byte chunks per float32 snapshot (14, 2 entries padding)
 
