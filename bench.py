@@ -68,8 +68,11 @@ KERNEL_SRC = {"k_apply_l0": "k_apply.hip", "k_hv_range": "k_hessvec.hip"}
 
 
 def _src_hash(kernel):
-    path = os.path.join(ROOT, "paper_2604_19892_amd", "csrc", KERNEL_SRC[kernel])
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    """Hash of the kernel's source file and of the shared layout header."""
+    h = hashlib.sha256()
+    for name in (KERNEL_SRC[kernel], "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2604_19892_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def traffic_record(kernel, prec, workload):
