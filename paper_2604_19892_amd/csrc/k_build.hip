@@ -465,7 +465,7 @@ __global__ __launch_bounds__(INV_THREADS) void k_invert_blocks(int64_t nodes, co
                                                                uint32_t* err, DiagRec* dg, int level,
                                                                double* acc_next) {
   __shared__ __align__(16) double col[2][BD];
-  __shared__ double pv[2];
+  __shared__ double pv[2], pinv[2];
   __shared__ __align__(16) double sc[BD];
   __shared__ float sig[BD];
   __shared__ double red[9][4];
@@ -539,7 +539,10 @@ __global__ __launch_bounds__(INV_THREADS) void k_invert_blocks(int64_t nodes, co
         if (tj == kb) {
 #pragma unroll
           for (int r = 0; r < 6; ++r) cb[6 * ti + r] = (ti == kb && r == kr) ? R[r][kr] - 1.0 : R[r][kr];
-          if (ti == kb) pv[kr & 1] = R[kr][kr];
+          if (ti == kb) {
+            pv[kr & 1] = R[kr][kr];
+            pinv[kr & 1] = rcp_nr(R[kr][kr]);  // once here instead of in every thread
+          }
         } else if (ti == kb) {
 #pragma unroll
           for (int q = 0; q < 6; ++q) cb[6 * tj + q] = R[kr][q];
@@ -551,7 +554,7 @@ __global__ __launch_bounds__(INV_THREADS) void k_invert_blocks(int64_t nodes, co
         bad_k = k;
         bad_v = p;
       }
-      const double inv = rcp_nr(p);
+      const double inv = pinv[kr & 1];
       if (act) {
         double ci[6], cj[6];
 #pragma unroll
