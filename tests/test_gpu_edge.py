@@ -44,7 +44,8 @@ def check_case(c, blocks=True):
             _, _, invs = c.M.coarse[l - 1]
             for d, (dofs, Minv) in enumerate(invs):
                 n = Minv.shape[0]
-                assert rel(c.ctx.get_block(l, d)[:n, :n], Minv) < 1e-10, (l, d)
+                err = rel(c.ctx.get_block(l, d)[:n, :n], Minv)
+                assert err < 1e-10, (l, d, err)
     rank, sel = c.ctx.get_selection()
     for d in range(D):
         want = c.sel.get(d, [])
