@@ -55,6 +55,35 @@ __host__ __device__ inline constexpr size_t blk_elems(int p) {
 // recorded per block
 constexpr size_t BLK_STRIDE = blk_elems(MAS_F64) * 8;
 
+// Data streamed once per pass in whole-wavefront pieces (stored blocks,
+// element snapshots, rest geometry) is loaded and stored with the non-temporal
+// hint, so the stream does not displace the vectors that are gathered
+// through the caches.
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 ld_once(const uint2* p) {
+  const nt_u2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p));
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_once(const float4* p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 ld_once(const double2* p) {
+  const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_once(uint2* p, uint2 v) {
+  __builtin_nontemporal_store(nt_u2{v.x, v.y}, reinterpret_cast<nt_u2*>(p));
+}
+__device__ __forceinline__ void st_once(float4* p, float4 v) {
+  __builtin_nontemporal_store(nt_f4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_f4*>(p));
+}
+__device__ __forceinline__ void st_once(double2* p, double2 v) {
+  __builtin_nontemporal_store(nt_d2{v.x, v.y}, reinterpret_cast<nt_d2*>(p));
+}
+
 // Element snapshot layout (45 packed tangent entries, then Dm^-1): per tile
 // of 64 tets, 16-byte chunk c of every tet of the tile lies contiguously
 // (chunk-major, then tet), so a wavefront reads one chunk of 64 tets as one
@@ -63,7 +92,7 @@ __device__ __forceinline__ void snap_load(const double* hf, int64_t t, double (&
   const double2* p = reinterpret_cast<const double2*>(hf) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
 #pragma unroll
   for (int c = 0; c < SNAP_NC64; ++c) {
-    const double2 v = p[c * TILE];
+    const double2 v = ld_once(p + c * TILE);
     e[2 * c] = v.x;
     e[2 * c + 1] = v.y;
   }
@@ -72,7 +101,7 @@ __device__ __forceinline__ void snap_load(const float* hf, int64_t t, float (&e)
   const float4* p = reinterpret_cast<const float4*>(hf) + (t / TILE) * (SNAP_NC32 * TILE) + (t % TILE);
 #pragma unroll
   for (int c = 0; c < SNAP_NC32; ++c) {
-    const float4 v = p[c * TILE];
+    const float4 v = ld_once(p + c * TILE);
     e[4 * c] = v.x;
     e[4 * c + 1] = v.y;
     e[4 * c + 2] = v.z;
@@ -87,7 +116,7 @@ __device__ __forceinline__ void geo_load(const double* geo, int64_t t, double (&
   const double2* p = reinterpret_cast<const double2*>(geo) + (t / TILE) * (GEO_NC * TILE) + (t % TILE);
 #pragma unroll
   for (int c = 0; c < GEO_NC; ++c) {
-    const double2 v = p[c * TILE];
+    const double2 v = ld_once(p + c * TILE);
     g[2 * c] = v.x;
     g[2 * c + 1] = v.y;
   }

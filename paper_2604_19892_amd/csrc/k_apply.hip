@@ -52,7 +52,7 @@ __device__ __forceinline__ double decode_entry(uint2 w, int e) {
 template <int P, bool STREAM>
 __device__ __forceinline__ double tile_entry(const uint2 (&u)[STREAM ? 1 : tile_ud(P)], const uint2* s2, int t,
                                              int e) {
-  if constexpr (STREAM) return decode_entry<P>(s2[tile_unit(P, t, e / tile_epu(P))], e);
+  if constexpr (STREAM) return decode_entry<P>(ld_once(s2 + tile_unit(P, t, e / tile_epu(P))), e);
   else return decode_entry<P>(u[e / tile_epu(P)], e);
 }
 
@@ -69,7 +69,7 @@ __device__ __forceinline__ double block_apply(const unsigned char* slot, const f
 #pragma unroll
     for (int k = 0; k < UD; ++k) {
       u[k] = make_uint2(0u, 0u);
-      if (k < UO || diag) u[k] = s2[tile_unit(P, t, k)];
+      if (k < UO || diag) u[k] = ld_once(s2 + tile_unit(P, t, k));
     }
   }
   float sg = 1.0f;

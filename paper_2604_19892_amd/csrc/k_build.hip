@@ -49,12 +49,12 @@ __global__ __launch_bounds__(64) void k_elem_hess(int64_t nent, int64_t nent_pad
       float vv[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) vv[k] = (4 * c + k < EH) ? float(e[4 * c + k]) : 0.0f;
-      p32[c * TILE] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+      st_once(p32 + c * TILE, make_float4(vv[0], vv[1], vv[2], vv[3]));
     }
   } else {
     double2* p64 = reinterpret_cast<double2*>(hr64) + (w / TILE) * (SNAP_NC64 * TILE) + (w % TILE);
 #pragma unroll
-    for (int c = 0; c < SNAP_NC64; ++c) p64[c * TILE] = make_double2(e[2 * c], e[2 * c + 1]);
+    for (int c = 0; c < SNAP_NC64; ++c) st_once(p64 + c * TILE, make_double2(e[2 * c], e[2 * c + 1]));
   }
 }
 
@@ -433,7 +433,7 @@ __device__ __forceinline__ void store_tile(unsigned char* slot, int ti, int tj, 
         u.x = h[0] | (h[1] << 16);
         u.y = h[2] | (h[3] << 16);
       }
-      s2[tile_unit(P, o, k)] = u;
+      st_once(s2 + tile_unit(P, o, k), u);
     }
   } else {
     const int m = ti / 2, h = ti & 1;
