@@ -88,20 +88,24 @@ __device__ __forceinline__ void st_once(double2* p, double2 v) {
 // of 64 tets, 16-byte chunk c of every tet of the tile lies contiguously
 // (chunk-major, then tet), so a wavefront reads one chunk of 64 tets as one
 // 1 KiB access.
+// NT = false: plain loads, for gathers of scattered entries whose cache
+// lines other threads of the workgroup may read next.
+template <bool NT = true>
 __device__ __forceinline__ void snap_load(const double* hf, int64_t t, double (&e)[EH]) {
   const double2* p = reinterpret_cast<const double2*>(hf) + (t / TILE) * (SNAP_NC64 * TILE) + (t % TILE);
 #pragma unroll
   for (int c = 0; c < SNAP_NC64; ++c) {
-    const double2 v = ld_once(p + c * TILE);
+    const double2 v = NT ? ld_once(p + c * TILE) : p[c * TILE];
     e[2 * c] = v.x;
     e[2 * c + 1] = v.y;
   }
 }
+template <bool NT = true>
 __device__ __forceinline__ void snap_load(const float* hf, int64_t t, float (&e)[4 * SNAP_NC32]) {
   const float4* p = reinterpret_cast<const float4*>(hf) + (t / TILE) * (SNAP_NC32 * TILE) + (t % TILE);
 #pragma unroll
   for (int c = 0; c < SNAP_NC32; ++c) {
-    const float4 v = ld_once(p + c * TILE);
+    const float4 v = NT ? ld_once(p + c * TILE) : p[c * TILE];
     e[4 * c] = v.x;
     e[4 * c + 1] = v.y;
     e[4 * c + 2] = v.z;

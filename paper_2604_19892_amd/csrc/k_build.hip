@@ -297,8 +297,8 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
     if (!(need[0] || need[1] || need[2] || need[3])) continue;
     constexpr int NH = sizeof(TH) == 8 ? EH : 4 * SNAP_NC32;
     TH H[NH];
-    if constexpr (sizeof(TH) == 8) snap_load(a.h64, a.t_home[t], H);
-    else snap_load(a.h32, a.t_home[t], H);
+    if constexpr (sizeof(TH) == 8) snap_load<false>(a.h64, a.t_home[t], H);
+    else snap_load<false>(a.h32, a.t_home[t], H);
     double coef[4][3];
     {
       double dm[9];
