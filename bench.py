@@ -197,6 +197,34 @@ def ccd_measure(ctx, solver, reps=10):
             "subdomains_with_step_below_1": float((alpha < 1.0).double().mean().item())}
 
 
+def contact_measure(ctx, solver, dhat, reps=10):
+    """Contact narrow phase (distance, n = grad d and closest-feature type)
+    of every point-triangle / edge-edge stencil of the pool at the current
+    positions, timed with the library's events.  Algorithmic bytes per
+    pair: the four vertex ids and the kind read, the distance, twelve
+    gradient entries and the type written, and four vertex positions
+    gathered (counted once per pair)."""
+    import torch
+    pool = solver.pool
+    m = int(pool.idx.shape[0])
+    dev = pool.idx.device
+    kind = ((pool.key >> 60) == 3).to(torch.uint8)          # key tag 3: edge-edge, 2: point-triangle
+    dist = torch.empty(m, dtype=torch.float64, device=dev)
+    grad = torch.empty(m, 12, dtype=torch.float64, device=dev)
+    ty = torch.empty(m, dtype=torch.uint8, device=dev)
+    ctx.contact_distances(solver.x, pool.idx, kind, dist, grad, ty)
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.contact_distances(solver.x, pool.idx, kind, dist, grad, ty)
+    ms, n = ctx.profile_read("contact")
+    ctx.profile(False)
+    us = 1e3 * ms / max(n, 1)
+    per_pair = 16 + 1 + 4 * 24 + 8 + 12 * 8 + 1
+    return {"pairs": m, "us_per_call": us, "pairs_per_s": m / (us * 1e-6),
+            "algorithmic_GB_per_s": per_pair * m / (us * 1e-6) / 1e9, "bytes_per_pair": per_pair,
+            "pairs_below_dhat": float((dist < dhat).double().mean().item())}
+
+
 def tolerance_solves(sc, precs, tol, max_iter, repeats):
     """PNCG solves per block storage precision from the same start to
     ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds of each
@@ -367,6 +395,7 @@ def main():
         print("[bench] library error: %s" % msg, file=sys.stderr)
         sys.exit(1)
     out["ccd"] = ccd_measure(ctx, solver)
+    out["contact_narrow_phase"] = contact_measure(ctx, solver, sc.dhat)
     out["hbm_probe"] = hbm_probe()
     if not args.no_solve:
         solver.ctx.close()

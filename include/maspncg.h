@@ -230,9 +230,33 @@ mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_
  * (device float64 m, nullable) receives the pair steps; alpha (device
  * float64 D_0, nullable) receives per level-0 subdomain the smallest step
  * of the pairs with a vertex in it, 1 where there is none (Algorithm 1's
- * per-subdomain alpha_d). */
+ * per-subdomain alpha_d).  A pair with a vertex id outside [0, N) gets
+ * step 0, takes no part in alpha, and the next mas_sync_status returns
+ * MAS_ERR_INVALID_ARG. */
 mas_status mas_ccd_steps(void* ctx, const double* x, const double* p, int64_t m, const int32_t* pairs,
                          const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
+
+/* Narrow phase of the contact set: per point-triangle or edge-edge pair the
+ * distance d_c that the barrier of Section 3.1 takes, and its gradient
+ * n = grad d_c of the projected contact Hessian (Section 4.1; the update
+ * columns u = sqrt(k) n of supplement Eq. (11)).  d_c is the unsigned
+ * Euclidean distance between the two primitives; grad d_c = w_j n_hat on
+ * the vertices of the first primitive and -w_j n_hat on those of the
+ * second, with w the weights of the closest points (1 for the point, barycentric on the triangle, 1 - s and s
+ * on an edge) and n_hat the unit vector from the second closest point to the
+ * first; it is zero where d_c = 0.  Parallel edges have many closest pairs:
+ * the one on the first edge's first vertex or on a segment end is taken.
+ * x: device 3N.  pairs, kind: as for mas_ccd_steps.  dist: device float64
+ * m.  grad (device float64 12m, vertex-major: 12 i + 3 j + axis; nullable)
+ * and dist together are the d and grad of a mas_contacts set over the same
+ * idx.  type (device uint8 m, nullable) receives the closest features:
+ * point-triangle 0-2 vertex T0, T1, T2, 3 edge T0T1, 4 edge T1T2, 5 edge
+ * T2T0, 6 face; edge-edge 3 a + b with a, b = 0 first vertex, 1 second
+ * vertex, 2 interior of the first and second edge.  A pair with a vertex id
+ * outside [0, N) gets dist = NaN, grad = 0, type = 255, and the next
+ * mas_sync_status returns MAS_ERR_INVALID_ARG. */
+mas_status mas_contact_distances(void* ctx, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
+                                 double* dist, double* grad, uint8_t* type);
 
 /* Synchronises the stream and returns the sticky device error (and clears
  * it); msg (nullable) receives a description. */
@@ -268,7 +292,8 @@ typedef enum {
   MAS_T_ENERGY = 7,       /* the whole mas_energy_grad call */
   MAS_T_SUBSPACE = 8,     /* the whole pncg_subspace_step call */
   MAS_T_CCD = 9,          /* the whole mas_ccd_steps call */
-  MAS_T_COUNT = 10
+  MAS_T_CONTACT = 10,     /* the whole mas_contact_distances call */
+  MAS_T_COUNT = 11
 } mas_timer;
 
 /* Enables (1) or disables (0) the kernel timers; enabling clears them. */

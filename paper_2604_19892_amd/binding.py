@@ -205,6 +205,13 @@ class MasContext:
         check("mas_ccd_steps", _abi.lib().mas_ccd_steps(self.h, _ptr(x), _ptr(p), m, _ptr(pairs), _ptr(kind),
                                                        _ptr(dist), _ptr(alpha_pair), _ptr(alpha)))
 
+    def contact_distances(self, x, pairs, kind, dist, grad=None, type=None):
+        """Distance, gradient and closest-feature type of each point-triangle
+        / edge-edge pair (device tensors; pairs in library ids)."""
+        m = int(pairs.shape[0])
+        check("mas_contact_distances", _abi.lib().mas_contact_distances(
+            self.h, _ptr(x), m, _ptr(pairs), _ptr(kind), _ptr(dist), _ptr(grad), _ptr(type)))
+
     def safe_step(self, x, p, cand, scale, x_out, alpha=None):
         c = cand.struct() if cand is not None else None
         check("mas_safe_step", _abi.lib().mas_safe_step(self.h, _ptr(x), _ptr(p), ctypes.byref(c) if c else None,

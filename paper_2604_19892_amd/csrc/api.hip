@@ -541,6 +541,13 @@ mas_status mas_ccd_steps(void* p, const double* x, const double* pv, int64_t m, 
   return launch_ccd(*as_ctx(p), x, pv, m, pairs, kind, dist, alpha_pair, alpha);
 }
 
+mas_status mas_contact_distances(void* p, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
+                                 double* dist, double* grad, uint8_t* type) {
+  if (!p || !x || m < 0) return MAS_ERR_INVALID_ARG;
+  if (m > 0 && (!pairs || !kind || !dist)) return MAS_ERR_INVALID_ARG;
+  return launch_contact_distances(*as_ctx(p), x, m, pairs, kind, dist, grad, type);
+}
+
 mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
   if (!p) return MAS_ERR_INVALID_ARG;
   Ctx& c = *as_ctx(p);
@@ -558,6 +565,7 @@ mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
     if (bits & ERRB_NOT_SPD) st = MAS_ERR_NOT_SPD;
     else if (bits & ERRB_NONFINITE) st = MAS_ERR_NONFINITE;
     else if (bits & ERRB_RANK) st = MAS_ERR_RANK;
+    else if (bits & ERRB_INDEX) st = MAS_ERR_INVALID_ARG;
   }
   if (msg && msg_len > 0) {
     static const char* src[] = {"?", "level-0 block", "coarse block", "capacitance"};

@@ -33,6 +33,7 @@ constexpr int SNAP_NC32 = (EH + 3) / 4; // 16-byte chunks per float32 snapshot (
 constexpr uint32_t ERRB_NOT_SPD = 1u;
 constexpr uint32_t ERRB_NONFINITE = 2u;
 constexpr uint32_t ERRB_RANK = 4u;
+constexpr uint32_t ERRB_INDEX = 8u;  // a pair named a vertex id outside [0, N)
 
 // packed lower-triangular index, i >= j
 __host__ __device__ inline int pk(int i, int j) { return i * (i + 1) / 2 + j; }

@@ -90,13 +90,23 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
     p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_ccd_pairs(int64_t m, const int32_t* pairs, const uint8_t* kind,
+__global__ __launch_bounds__(256) void k_ccd_pairs(int64_t N, int64_t m, const int32_t* pairs, const uint8_t* kind,
                                                    const double* dist, const double* x, const double* p,
-                                                   double* alpha_pair, double* alpha) {
+                                                   double* alpha_pair, double* alpha, uint32_t* err) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int v[4] = {-1, -1, -1, -1};
   double step = 1.0;
-  if (i < m) {
+  bool ok = i < m;
+  if (ok) {
+    const int4 iv = reinterpret_cast<const int4*>(pairs)[i];
+    ok = iv.x >= 0 && iv.x < N && iv.y >= 0 && iv.y < N && iv.z >= 0 && iv.z < N && iv.w >= 0 && iv.w < N;
+    if (!ok) {
+      // a vertex id outside [0, N): no step for this pair, reported by the error flag
+      if (alpha_pair) alpha_pair[i] = 0.0;
+      atomicOr(err, ERRB_INDEX);
+    }
+  }
+  if (ok) {
     const int4 iv = reinterpret_cast<const int4*>(pairs)[i];
     v[0] = iv.x;
     v[1] = iv.y;
@@ -163,7 +173,8 @@ mas_status launch_ccd(Ctx& c, const double* x, const double* p, int64_t m, const
   const int64_t D = c.lv[0].nsub;
   if (alpha) k_fill_f64<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(alpha, D, 1.0);
   if (m > 0)
-    k_ccd_pairs<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(m, pairs, kind, dist, x, p, alpha_pair, alpha);
+    k_ccd_pairs<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(c.N, m, pairs, kind, dist, x, p, alpha_pair,
+                                                                alpha, c.err);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

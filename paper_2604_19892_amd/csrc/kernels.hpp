@@ -51,5 +51,7 @@ mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_
 // k_ccd.hip ------------------------------------------------------------
 mas_status launch_ccd(Ctx& c, const double* x, const double* p, int64_t m, const int32_t* pairs,
                       const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
+mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
+                                    double* dist, double* grad, uint8_t* type);
 
 }  // namespace mas
