@@ -2,9 +2,9 @@
 
 Test infrastructure (see the package docstring).
 
-The barrier of Section 3.1 acts on the distance d_c of a contact pair and
-the projected contact Hessian of Section 4.1 (supplement Eq. (12)) uses
-n = grad d_c.  The paper gives no formula for d_c; it is read here as the
+The barrier of Section 3.1 acts on the distance d_c of a contact pair;
+the projected contact Hessian of Section 4.1 and the update columns
+u = sqrt(k) n of supplement Eq. (11) use n = grad d_c.  The paper gives no formula for d_c; it is read here as the
 unsigned Euclidean distance between the two primitives (a point and a
 triangle, or two segments), and its gradient as the envelope-theorem one:
 with closest points c_1 = sum_j w_j y_j on the first primitive and
