@@ -552,5 +552,21 @@ def puffer_scene(seed=2, n_balls_axis=2, core=(36, 36, 37), n_spikes=1182, spike
                  pool=pool, levels=levels, K=K)
 
 
+def surface(tets):
+    """Boundary of a tet mesh: (vertices, triangles (F, 3), edges (E, 2)),
+    the triangles being the tet faces that belong to one tet only, the
+    edges and vertices those of the triangles (edges with the smaller id
+    first, all sorted).  Topology only."""
+    t = np.asarray(tets, np.int64)
+    faces = np.concatenate([t[:, [0, 1, 2]], t[:, [0, 1, 3]], t[:, [0, 2, 3]], t[:, [1, 2, 3]]])
+    key = np.sort(faces, axis=1)
+    uniq, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    tris = uniq[cnt == 1]
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [0, 2]]])
+    edges = np.unique(np.sort(e, axis=1), axis=0)
+    verts = np.unique(tris)
+    return verts.astype(np.int32), tris.astype(np.int32), edges.astype(np.int32)
+
+
 def scene_by_name(name, **kw):
     return {"grid": grid_scene, "two_boxes": two_boxes_scene, "puffer": puffer_scene}[name](**kw)
