@@ -225,6 +225,39 @@ def contact_measure(ctx, solver, dhat, reps=10):
             "pairs_below_dhat": float((dist < dhat).double().mean().item())}
 
 
+def constraint_set_measure(ctx, sc, x, reps=5):
+    """ComputeConstraintSet (mas_constraint_set) over the scene's whole
+    boundary surface at the current positions: hashed-grid broad phase and
+    narrow phase, timed with the library's events around the whole call
+    (which includes its two host read-backs).  The first call, which sizes
+    the grid tables, is not timed."""
+    import numpy as np
+    import torch
+    from paper_2604_19892_amd import synth
+    verts, tris, edges = synth.surface(sc.tets)
+    dev = x.device
+    r = ctx.rank
+    vt = torch.as_tensor(r[verts].astype(np.int32), device=dev)
+    tt = torch.as_tensor(r[tris].astype(np.int32), device=dev)
+    et = torch.as_tensor(r[edges].astype(np.int32), device=dev)
+    cap = 1 << 22
+    pairs = torch.empty(cap, 4, dtype=torch.int32, device=dev)
+    kind = torch.empty(cap, dtype=torch.uint8, device=dev)
+    dist = torch.empty(cap, dtype=torch.float64, device=dev)
+    grad = torch.empty(cap, 12, dtype=torch.float64, device=dev)
+    n = ctx.constraint_set(x, vt, tt, et, sc.dhat, pairs, kind, dist, grad)
+    ctx.profile(True)
+    for _ in range(reps):
+        n = ctx.constraint_set(x, vt, tt, et, sc.dhat, pairs, kind, dist, grad)
+    ms, calls = ctx.profile_read("constraint_set")
+    ctx.profile(False)
+    k = min(n, cap)
+    n_pt = int((kind[:k] == 0).sum().item())
+    return {"surface_vertices": int(len(verts)), "surface_triangles": int(len(tris)),
+            "surface_edges": int(len(edges)), "dhat": sc.dhat, "pairs": int(n), "pt_pairs": n_pt,
+            "ee_pairs": int(k - n_pt), "ms_per_call": ms / max(calls, 1)}
+
+
 def tolerance_solves(sc, precs, tol, max_iter, repeats):
     """PNCG solves per block storage precision from the same start to
     ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds of each
@@ -396,6 +429,7 @@ def main():
         sys.exit(1)
     out["ccd"] = ccd_measure(ctx, solver)
     out["contact_narrow_phase"] = contact_measure(ctx, solver, sc.dhat)
+    out["constraint_set"] = constraint_set_measure(ctx, sc, solver.x)
     out["hbm_probe"] = hbm_probe()
     if not args.no_solve:
         solver.ctx.close()

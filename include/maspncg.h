@@ -258,6 +258,29 @@ mas_status mas_ccd_steps(void* ctx, const double* x, const double* p, int64_t m,
 mas_status mas_contact_distances(void* ctx, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
                                  double* dist, double* grad, uint8_t* type);
 
+/* ComputeConstraintSet of Algorithm 1: every point-triangle pair (a surface
+ * vertex and a surface triangle not containing it) and every edge-edge
+ * pair (two surface edges without a common vertex, once, the edge listed
+ * first in edges first) with distance d_c < dhat (d_c, n = grad d_c and
+ * the layouts as for mas_contact_distances).  Broad phase: a hashed
+ * uniform grid of cell side (largest axis extent of a triangle or edge) +
+ * 2 dhat; narrow phase as mas_contact_distances.
+ * x: device 3N.  verts (device int32 nv), tris (device int32 3nt), edges
+ * (device int32 2ne): library vertex ids.  Outputs, device, capacity cap:
+ * pairs int32 4cap (P, T0, T1, T2 or E1a, E1b, E2a, E2b), kind uint8 cap
+ * (0 point-triangle, 1 edge-edge), dist float64 cap, grad float64 12cap
+ * (nullable).  *count (host) receives the number of pairs found; only the
+ * first min(count, cap) are written, in no fixed order (call again with a
+ * larger cap when count > cap).  Synchronises the stream.  The library
+ * keeps the grid tables between calls and grows them as needed (device
+ * allocation).  Errors: MAS_ERR_INVALID_ARG for an id outside [0, N),
+ * dhat <= 0, or coordinates so large against the cell side that cell
+ * indices would exceed 1e15; MAS_ERR_NONFINITE for a non-finite
+ * coordinate of a listed vertex; both before any pair is written. */
+mas_status mas_constraint_set(void* ctx, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
+                              const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
+                              uint8_t* kind, double* dist, double* grad, int64_t* count);
+
 /* Synchronises the stream and returns the sticky device error (and clears
  * it); msg (nullable) receives a description. */
 mas_status mas_sync_status(void* ctx, char* msg, int32_t msg_len);
@@ -293,7 +316,8 @@ typedef enum {
   MAS_T_SUBSPACE = 8,     /* the whole pncg_subspace_step call */
   MAS_T_CCD = 9,          /* the whole mas_ccd_steps call */
   MAS_T_CONTACT = 10,     /* the whole mas_contact_distances call */
-  MAS_T_COUNT = 11
+  MAS_T_CSET = 11,        /* the whole mas_constraint_set call */
+  MAS_T_COUNT = 12
 } mas_timer;
 
 /* Enables (1) or disables (0) the kernel timers; enabling clears them. */

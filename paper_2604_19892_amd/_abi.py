@@ -73,7 +73,7 @@ class MasStepOut(ctypes.Structure):
 STEP_FIELDS = [f for f, _ in MasStepOut._fields_]
 
 TIMERS = {"apply_l0": 0, "apply": 1, "hv_tets": 2, "hess_vec": 3, "update": 4, "capacitance": 5,
-          "build": 6, "energy": 7, "subspace": 8, "ccd": 9, "contact": 10}
+          "build": 6, "energy": 7, "subspace": 8, "ccd": 9, "contact": 10, "constraint_set": 11}
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -95,6 +95,8 @@ SIGNATURES = {
     "mas_safe_step": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _D, _P, _P]),
     "mas_ccd_steps": (_I32, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "mas_contact_distances": (_I32, [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    "mas_constraint_set": (_I32, [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.c_int64,
+                                  _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "mas_sync_status": (_I32, [_P, ctypes.c_char_p, _I32]),
     "mas_query": (_I32, [_P, _P, _P, _P, _P]),
     "mas_get_block": (_I32, [_P, _I32, _I64, _P]),

@@ -212,6 +212,17 @@ class MasContext:
         check("mas_contact_distances", _abi.lib().mas_contact_distances(
             self.h, _ptr(x), m, _ptr(pairs), _ptr(kind), _ptr(dist), _ptr(grad), _ptr(type)))
 
+    def constraint_set(self, x, verts, tris, edges, dhat, pairs, kind, dist, grad=None):
+        """Active point-triangle / edge-edge pairs within dhat (device
+        tensors in library ids; outputs of capacity pairs.shape[0]).
+        Returns the number of pairs found (may exceed the capacity)."""
+        cnt = ctypes.c_int64(0)
+        check("mas_constraint_set", _abi.lib().mas_constraint_set(
+            self.h, _ptr(x), float(dhat), int(verts.shape[0]), _ptr(verts), int(tris.shape[0]), _ptr(tris),
+            int(edges.shape[0]), _ptr(edges), int(pairs.shape[0]), _ptr(pairs), _ptr(kind), _ptr(dist), _ptr(grad),
+            ctypes.byref(cnt)))
+        return int(cnt.value)
+
     def safe_step(self, x, p, cand, scale, x_out, alpha=None):
         c = cand.struct() if cand is not None else None
         check("mas_safe_step", _abi.lib().mas_safe_step(self.h, _ptr(x), _ptr(p), ctypes.byref(c) if c else None,

@@ -1,5 +1,6 @@
 // C ABI entry points: argument checks, context lifetime, call order.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <numeric>
 #include <new>
@@ -159,6 +160,12 @@ mas_status mas_destroy(void* p) {
                   c->alpha, c->amark, c->err, c->diag, c->cub_tmp};
   for (void* q : ptrs)
     if (q) hipFree(q);
+  for (auto& t : c->cs) {
+    void* tp[] = {t.cnt, t.off, t.key, t.id};
+    for (void* q : tp)
+      if (q) hipFree(q);
+  }
+  if (c->cs_misc) hipFree(c->cs_misc);
   for (int l = 0; l < MAXL; ++l) {
     Level& L = c->lv[l];
     void* lp[] = {L.blk, L.bprec, L.scale, L.acc, L.r, L.c};
@@ -546,6 +553,18 @@ mas_status mas_contact_distances(void* p, const double* x, int64_t m, const int3
   if (!p || !x || m < 0) return MAS_ERR_INVALID_ARG;
   if (m > 0 && (!pairs || !kind || !dist)) return MAS_ERR_INVALID_ARG;
   return launch_contact_distances(*as_ctx(p), x, m, pairs, kind, dist, grad, type);
+}
+
+mas_status mas_constraint_set(void* p, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
+                              const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
+                              uint8_t* kind, double* dist, double* grad, int64_t* count) {
+  if (!p || !x || !count || !(dhat > 0.0) || !std::isfinite(dhat) || nv < 0 || nt < 0 || ne < 0 || cap < 0)
+    return MAS_ERR_INVALID_ARG;
+  if ((nv > 0 && !verts) || (nt > 0 && !tris) || (ne > 0 && !edges)) return MAS_ERR_INVALID_ARG;
+  if (cap > 0 && (!pairs || !kind || !dist)) return MAS_ERR_INVALID_ARG;
+  if (nt > INT32_MAX || ne > INT32_MAX || cap > INT32_MAX) return MAS_ERR_INVALID_ARG;
+  return launch_constraint_set(*as_ctx(p), x, dhat, nv, verts, nt, tris, ne, edges, cap, pairs, kind, dist, grad,
+                               count);
 }
 
 mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {

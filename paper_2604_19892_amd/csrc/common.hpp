@@ -395,6 +395,17 @@ struct Ctx {
   DiagRec* diag = nullptr;         // first failure record
   void* cub_tmp = nullptr;
   size_t cub_bytes = 0;
+
+  // broad phase of the contact set: one spatial hash table per primitive
+  // kind (triangles, edges), grown on demand
+  struct CellTable {
+    int32_t* cnt = nullptr;  // H + 1 bucket counts, then fill cursors
+    int32_t* off = nullptr;  // H + 1 bucket offsets
+    uint64_t* key = nullptr; // entries: cell key
+    int32_t* id = nullptr;   // entries: primitive index
+    int64_t h_cap = 0, e_cap = 0;
+  } cs[2];
+  unsigned long long* cs_misc = nullptr;  // [0] largest primitive extent (bits), [1] pair count
 };
 
 // Scatter through an LDS window.  A workgroup handles a chunk of items

@@ -3,6 +3,8 @@
 // features and the gradient n = grad d_c that the projected contact Hessian
 // of Section 4.1 uses.  One thread per pair; the outputs are the d and grad
 // arrays of a contact stencil set.
+#include <cstring>
+
 #include "kernels.hpp"
 
 namespace mas {
@@ -130,6 +132,46 @@ __device__ int ee_closest(V3 a0, V3 a1, V3 b0, V3 b1, double& s, double& t) {
   return 3 * fs + ft;
 }
 
+// Distance of pair X (point-triangle or edge-edge), the closest-point
+// weights (second primitive negated) and the unit vector n from the second
+// closest point to the first (zero at d = 0); returns the type.
+__device__ int pair_geometry(const V3 (&X)[4], int kind, double& d, double (&wt)[4], V3& n) {
+  V3 c1, c2;
+  int ty;
+  if (kind == 0) {
+    double w[3];
+    ty = pt_closest(X[0], X[1], X[2], X[3], w);
+    wt[0] = 1.0, wt[1] = -w[0], wt[2] = -w[1], wt[3] = -w[2];
+    c1 = X[0];
+    c2 = {w[0] * X[1].x + w[1] * X[2].x + w[2] * X[3].x, w[0] * X[1].y + w[1] * X[2].y + w[2] * X[3].y,
+          w[0] * X[1].z + w[1] * X[2].z + w[2] * X[3].z};
+  } else {
+    double s, t;
+    ty = ee_closest(X[0], X[1], X[2], X[3], s, t);
+    wt[0] = 1.0 - s, wt[1] = s, wt[2] = -(1.0 - t), wt[3] = -t;
+    c1 = axpy(s, X[1] - X[0], X[0]);
+    c2 = axpy(t, X[3] - X[2], X[2]);
+  }
+  const V3 dv = c1 - c2;
+  d = sqrt(dot(dv, dv));
+  const double inv = d > 0.0 ? 1.0 / d : 0.0;
+  n = {dv.x * inv, dv.y * inv, dv.z * inv};
+  return ty;
+}
+
+__device__ __forceinline__ V3 load_v3(const double* x, int v) {
+  return {x[3 * int64_t(v)], x[3 * int64_t(v) + 1], x[3 * int64_t(v) + 2]};
+}
+
+__device__ __forceinline__ void store_grad(double* grad, int64_t i, const double (&wt)[4], V3 n) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    grad[12 * i + 3 * j] = wt[j] * n.x;
+    grad[12 * i + 3 * j + 1] = wt[j] * n.y;
+    grad[12 * i + 3 * j + 2] = wt[j] * n.z;
+  }
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_contact_dist(int64_t N, int64_t m, const int32_t* pairs,
@@ -149,38 +191,13 @@ __global__ __launch_bounds__(256) void k_contact_dist(int64_t N, int64_t m, cons
   }
   V3 X[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) X[j] = {x[3 * int64_t(v[j])], x[3 * int64_t(v[j]) + 1], x[3 * int64_t(v[j]) + 2]};
-  double wt[4];  // weights of the closest points, second primitive negated
-  V3 c1, c2;
-  int ty;
-  if (kind[i] == 0) {
-    double w[3];
-    ty = pt_closest(X[0], X[1], X[2], X[3], w);
-    wt[0] = 1.0, wt[1] = -w[0], wt[2] = -w[1], wt[3] = -w[2];
-    c1 = X[0];
-    c2 = {w[0] * X[1].x + w[1] * X[2].x + w[2] * X[3].x, w[0] * X[1].y + w[1] * X[2].y + w[2] * X[3].y,
-          w[0] * X[1].z + w[1] * X[2].z + w[2] * X[3].z};
-  } else {
-    double s, t;
-    ty = ee_closest(X[0], X[1], X[2], X[3], s, t);
-    wt[0] = 1.0 - s, wt[1] = s, wt[2] = -(1.0 - t), wt[3] = -t;
-    c1 = axpy(s, X[1] - X[0], X[0]);
-    c2 = axpy(t, X[3] - X[2], X[2]);
-  }
-  const V3 dv = c1 - c2;
-  const double d = sqrt(dot(dv, dv));
+  for (int j = 0; j < 4; ++j) X[j] = load_v3(x, v[j]);
+  double d, wt[4];
+  V3 n;
+  const int ty = pair_geometry(X, kind[i], d, wt, n);
   dist[i] = d;
   if (type) type[i] = uint8_t(ty);
-  if (grad) {
-    const double inv = d > 0.0 ? 1.0 / d : 0.0;
-    const V3 n = {dv.x * inv, dv.y * inv, dv.z * inv};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      grad[12 * i + 3 * j] = wt[j] * n.x;
-      grad[12 * i + 3 * j + 1] = wt[j] * n.y;
-      grad[12 * i + 3 * j + 2] = wt[j] * n.z;
-    }
-  }
+  if (grad) store_grad(grad, i, wt, n);
 }
 
 mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
@@ -190,6 +207,327 @@ mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const in
     k_contact_dist<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(c.N, m, pairs, kind, x, dist, grad, type,
                                                                   c.err);
   HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Broad phase of ComputeConstraintSet (Algorithm 1): a uniform grid of
+// cells of side h = (largest primitive extent) + 2 dhat, hashed into
+// buckets.  Every triangle and every edge is entered into each cell its
+// box, grown by dhat, overlaps (at most two cells per axis at this h).  A
+// point probes its own cell: a triangle within dhat of it has a grown box
+// containing it, so it is entered there, once.  An edge probes the cells
+// of its own box and keeps a partner edge only in the cell holding the
+// lower corner of (own box) x (partner's grown box), so each pair is found
+// once.  Candidates whose boxes are dhat or more apart are dropped, the
+// rest go through the narrow phase and are kept when d < dhat.  Results
+// are appended through one counter (their order is not fixed).
+namespace {
+
+constexpr int CELL_BITS = 21;  // per axis in the cell key (cells wrap every 2^21)
+
+__device__ __forceinline__ uint64_t cell_key(int64_t cx, int64_t cy, int64_t cz) {
+  const uint64_t m = (1ull << CELL_BITS) - 1;
+  return ((uint64_t(cx) & m) << (2 * CELL_BITS)) | ((uint64_t(cy) & m) << CELL_BITS) | (uint64_t(cz) & m);
+}
+
+__device__ __forceinline__ int64_t cell_of(double v, double h) { return int64_t(floor(v / h)); }
+
+struct Box {
+  double lo[3], hi[3];
+};
+
+template <int NV>
+__device__ __forceinline__ Box prim_box(const double* x, const int32_t* ids, int64_t p) {
+  Box b;
+  for (int a = 0; a < 3; ++a) b.lo[a] = b.hi[a] = x[3 * int64_t(ids[NV * p]) + a];
+#pragma unroll
+  for (int j = 1; j < NV; ++j)
+    for (int a = 0; a < 3; ++a) {
+      const double v = x[3 * int64_t(ids[NV * p + j]) + a];
+      b.lo[a] = fmin(b.lo[a], v);
+      b.hi[a] = fmax(b.hi[a], v);
+    }
+  return b;
+}
+
+// squared distance between boxes a and b
+__device__ __forceinline__ double box_dist2(const Box& a, const Box& b) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double g = fmax(0.0, fmax(a.lo[q] - b.hi[q], b.lo[q] - a.hi[q]));
+    s += g * g;
+  }
+  return s;
+}
+
+__device__ __forceinline__ void append_pair(unsigned long long* count, int64_t cap, const int (&v)[4], int kind,
+                                            double d, const double (&wt)[4], V3 n, int32_t* pairs, uint8_t* kinds,
+                                            double* dist, double* grad) {
+  const unsigned long long slot = atomicAdd(count, 1ull);
+  if (int64_t(slot) >= cap) return;
+  const int64_t i = int64_t(slot);
+  reinterpret_cast<int4*>(pairs)[i] = make_int4(v[0], v[1], v[2], v[3]);
+  kinds[i] = uint8_t(kind);
+  dist[i] = d;
+  if (grad) store_grad(grad, i, wt, n);
+}
+
+}  // namespace
+
+// Checks every id against N and every coordinate for finiteness (misc[2]:
+// bit 0 a bad id, bit 1 a non-finite coordinate) before anything else
+// reads them; misc[0] receives the largest axis extent of a triangle or
+// edge and misc[3] the largest |coordinate|, both as the bits of a
+// non-negative double (their order is the order of the values).
+__global__ __launch_bounds__(256) void k_cs_prep(int64_t N, int64_t nt, const int32_t* tris, int64_t ne,
+                                                 const int32_t* edges, int64_t nv, const int32_t* verts,
+                                                 const double* x, unsigned long long* misc) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int32_t* ids = nullptr;
+  int nid = 0;
+  if (i < nt) ids = tris + 3 * i, nid = 3;
+  else if (i < nt + ne) ids = edges + 2 * (i - nt), nid = 2;
+  else if (i < nt + ne + nv) ids = verts + (i - nt - ne), nid = 1;
+  double e = 0.0, amax = 0.0;
+  unsigned long long bad = 0;
+  if (nid > 0) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = 0; j < nid; ++j) {
+      const int v = ids[j];
+      if (!(v >= 0 && v < N)) {
+        bad |= 1ull;
+        continue;
+      }
+      for (int a = 0; a < 3; ++a) {
+        const double c = x[3 * int64_t(v) + a];
+        if (!isfinite(c)) bad |= 2ull;
+        lo[a] = fmin(lo[a], c);
+        hi[a] = fmax(hi[a], c);
+        amax = fmax(amax, fabs(c));
+      }
+    }
+    if (!bad && nid > 1) e = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
+    if (bad) e = amax = 0.0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    e = fmax(e, __shfl_xor(e, o));
+    amax = fmax(amax, __shfl_xor(amax, o));
+    bad |= __shfl_xor(bad, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (e > 0.0) atomicMax(&misc[0], (unsigned long long)__double_as_longlong(e));
+    if (bad) atomicOr(&misc[2], bad);
+    if (amax > 0.0) atomicMax(&misc[3], (unsigned long long)__double_as_longlong(amax));
+  }
+}
+
+// enters every primitive into the cells of its grown box: FILL = false
+// counts per bucket, FILL = true takes slots from the bucket cursors
+template <int NV, bool FILL>
+__global__ __launch_bounds__(256) void k_cs_insert(int64_t n, const int32_t* ids, const double* x, double h,
+                                                   double dhat, uint64_t hmask, int32_t* cnt, uint64_t* ekey,
+                                                   int32_t* eid, uint32_t* err) {
+  const int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (p >= n) return;
+  const Box b = prim_box<NV>(x, ids, p);
+  int64_t c0[3], c1[3];
+  for (int a = 0; a < 3; ++a) {
+    c0[a] = cell_of(b.lo[a] - dhat, h);
+    c1[a] = cell_of(b.hi[a] + dhat, h);
+    if (c1[a] - c0[a] > 2 || c1[a] < c0[a]) {  // cannot happen with h >= extent + 2 dhat; never loop long
+      atomicOr(err, ERRB_INDEX);
+      return;
+    }
+  }
+  for (int64_t cx = c0[0]; cx <= c1[0]; ++cx)
+    for (int64_t cy = c0[1]; cy <= c1[1]; ++cy)
+      for (int64_t cz = c0[2]; cz <= c1[2]; ++cz) {
+        const uint64_t k = cell_key(cx, cy, cz);
+        const uint64_t bkt = key_hash(k) & hmask;
+        if constexpr (!FILL) {
+          atomicAdd(&cnt[bkt], 1);
+        } else {
+          const int slot = atomicAdd(&cnt[bkt], 1);
+          ekey[slot] = k;
+          eid[slot] = int32_t(p);
+        }
+      }
+}
+
+__global__ __launch_bounds__(256) void k_cs_query_pt(int64_t nv, const int32_t* verts, const int32_t* tris,
+                                                     const double* x, double h, double dhat, uint64_t hmask,
+                                                     const int32_t* off, const uint64_t* ekey, const int32_t* eid,
+                                                     int64_t cap, int32_t* pairs, uint8_t* kinds, double* dist,
+                                                     double* grad, unsigned long long* count) {
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const int v = verts[i];
+  const V3 P = load_v3(x, v);
+  const Box pb = {{P.x, P.y, P.z}, {P.x, P.y, P.z}};
+  const uint64_t k = cell_key(cell_of(P.x, h), cell_of(P.y, h), cell_of(P.z, h));
+  const uint64_t bkt = key_hash(k) & hmask;
+  const double dh2 = dhat * dhat;
+  for (int e = off[bkt]; e < off[bkt + 1]; ++e) {
+    if (ekey[e] != k) continue;
+    const int t = eid[e];
+    const int tv[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    if (tv[0] == v || tv[1] == v || tv[2] == v) continue;
+    if (!(box_dist2(pb, prim_box<3>(x, tris, t)) < dh2)) continue;
+    const int q[4] = {v, tv[0], tv[1], tv[2]};
+    const V3 X[4] = {P, load_v3(x, tv[0]), load_v3(x, tv[1]), load_v3(x, tv[2])};
+    double d, wt[4];
+    V3 n;
+    pair_geometry(X, 0, d, wt, n);
+    if (d < dhat) append_pair(count, cap, q, 0, d, wt, n, pairs, kinds, dist, grad);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* edges, const double* x, double h,
+                                                     double dhat, uint64_t hmask, const int32_t* off,
+                                                     const uint64_t* ekey, const int32_t* eid, int64_t cap,
+                                                     int32_t* pairs, uint8_t* kinds, double* dist, double* grad,
+                                                     unsigned long long* count, uint32_t* err) {
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  const int a0 = edges[2 * i], a1 = edges[2 * i + 1];
+  const Box ab = prim_box<2>(x, edges, i);
+  int64_t c0[3], c1[3];
+  for (int a = 0; a < 3; ++a) {
+    c0[a] = cell_of(ab.lo[a], h);
+    c1[a] = cell_of(ab.hi[a], h);
+    if (c1[a] - c0[a] > 2 || c1[a] < c0[a]) {  // as in k_cs_insert
+      atomicOr(err, ERRB_INDEX);
+      return;
+    }
+  }
+  const double dh2 = dhat * dhat;
+  for (int64_t cx = c0[0]; cx <= c1[0]; ++cx)
+    for (int64_t cy = c0[1]; cy <= c1[1]; ++cy)
+      for (int64_t cz = c0[2]; cz <= c1[2]; ++cz) {
+        const uint64_t k = cell_key(cx, cy, cz);
+        const uint64_t bkt = key_hash(k) & hmask;
+        for (int e = off[bkt]; e < off[bkt + 1]; ++e) {
+          if (ekey[e] != k) continue;
+          const int j = eid[e];
+          if (j <= i) continue;
+          const int b0 = edges[2 * j], b1 = edges[2 * j + 1];
+          if (b0 == a0 || b0 == a1 || b1 == a0 || b1 == a1) continue;
+          const Box bb = prim_box<2>(x, edges, j);
+          if (!(box_dist2(ab, bb) < dh2)) continue;
+          // report from the cell of the lower corner of (own box) x (grown partner box)
+          const int64_t rx = cell_of(fmax(ab.lo[0], bb.lo[0] - dhat), h);
+          const int64_t ry = cell_of(fmax(ab.lo[1], bb.lo[1] - dhat), h);
+          const int64_t rz = cell_of(fmax(ab.lo[2], bb.lo[2] - dhat), h);
+          if (rx != cx || ry != cy || rz != cz) continue;
+          const int q[4] = {a0, a1, b0, b1};
+          const V3 X[4] = {load_v3(x, a0), load_v3(x, a1), load_v3(x, b0), load_v3(x, b1)};
+          double d, wt[4];
+          V3 n;
+          pair_geometry(X, 1, d, wt, n);
+          if (d < dhat) append_pair(count, cap, q, 1, d, wt, n, pairs, kinds, dist, grad);
+        }
+      }
+}
+
+static mas_status grow_table(Ctx::CellTable& t, int64_t H, int64_t E) {
+  if (H + 1 > t.h_cap) {
+    if (t.cnt) HIPCHK(hipFree(t.cnt));
+    if (t.off) HIPCHK(hipFree(t.off));
+    t.cnt = nullptr, t.off = nullptr, t.h_cap = 0;
+    if (hipMalloc(&t.cnt, sizeof(int32_t) * (H + 1)) != hipSuccess) return MAS_ERR_OOM;
+    if (hipMalloc(&t.off, sizeof(int32_t) * (H + 1)) != hipSuccess) return MAS_ERR_OOM;
+    t.h_cap = H + 1;
+  }
+  if (E > t.e_cap) {
+    if (t.key) HIPCHK(hipFree(t.key));
+    if (t.id) HIPCHK(hipFree(t.id));
+    t.key = nullptr, t.id = nullptr, t.e_cap = 0;
+    if (hipMalloc(&t.key, sizeof(uint64_t) * E) != hipSuccess) return MAS_ERR_OOM;
+    if (hipMalloc(&t.id, sizeof(int32_t) * E) != hipSuccess) return MAS_ERR_OOM;
+    t.e_cap = E;
+  }
+  return MAS_OK;
+}
+
+static int64_t pow2_at_least(int64_t n) {
+  int64_t H = 1024;
+  while (H < n) H <<= 1;
+  return H;
+}
+
+mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
+                                 const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
+                                 uint8_t* kind, double* dist, double* grad, int64_t* count) {
+  ProfScope ps(c, MAS_T_CSET);
+  *count = 0;
+  if (!c.cs_misc && hipMalloc(&c.cs_misc, 4 * sizeof(unsigned long long)) != hipSuccess) return MAS_ERR_OOM;
+  HIPCHK(hipMemsetAsync(c.cs_misc, 0, 4 * sizeof(unsigned long long), c.s));
+  if (nt + ne == 0) return MAS_OK;
+  k_cs_prep<<<dim3((nt + ne + nv + 255) / 256), dim3(256), 0, c.s>>>(c.N, nt, tris, ne, edges, nv, verts, x,
+                                                                     c.cs_misc);
+  unsigned long long misc[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(misc, c.cs_misc, sizeof(misc), hipMemcpyDeviceToHost, c.s));
+  HIPCHK(hipStreamSynchronize(c.s));
+  if (misc[2] & 1ull) return MAS_ERR_INVALID_ARG;
+  if (misc[2] & 2ull) return MAS_ERR_NONFINITE;
+  double ext, amax;
+  std::memcpy(&ext, &misc[0], sizeof(ext));
+  std::memcpy(&amax, &misc[3], sizeof(amax));
+  const double h = ext + 2.0 * dhat;
+  // cell indices |x| / h must stay far inside int64
+  if (!(h > 0.0) || !std::isfinite(h) || amax / h > 1e15) return MAS_ERR_INVALID_ARG;
+  const int64_t n[2] = {nt, ne};
+  const int32_t* ids[2] = {tris, edges};
+  int64_t H[2];
+  int32_t total[2] = {0, 0};
+  for (int k = 0; k < 2; ++k) {
+    H[k] = pow2_at_least(2 * n[k]);
+    mas_status st = grow_table(c.cs[k], H[k], 0);
+    if (st != MAS_OK) return st;
+    HIPCHK(hipMemsetAsync(c.cs[k].cnt, 0, sizeof(int32_t) * (H[k] + 1), c.s));
+    if (n[k] == 0) continue;
+    const dim3 g((n[k] + 255) / 256);
+    if (k == 0)
+      k_cs_insert<3, false><<<g, dim3(256), 0, c.s>>>(n[k], ids[k], x, h, dhat, uint64_t(H[k] - 1), c.cs[k].cnt,
+                                                       nullptr, nullptr, c.err);
+    else
+      k_cs_insert<2, false><<<g, dim3(256), 0, c.s>>>(n[k], ids[k], x, h, dhat, uint64_t(H[k] - 1), c.cs[k].cnt,
+                                                       nullptr, nullptr, c.err);
+    mas_status s2 = exclusive_scan_i32(c, c.cs[k].cnt, c.cs[k].off, H[k] + 1);
+    if (s2 != MAS_OK) return s2;
+    HIPCHK(hipMemcpyAsync(&total[k], c.cs[k].off + H[k], sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+  }
+  HIPCHK(hipStreamSynchronize(c.s));
+  for (int k = 0; k < 2; ++k) {
+    if (n[k] == 0) continue;
+    if (total[k] < 0) return MAS_ERR_INVALID_ARG;  // more than 2^31 cell entries
+    mas_status st = grow_table(c.cs[k], H[k], std::max<int64_t>(total[k], 1));
+    if (st != MAS_OK) return st;
+    HIPCHK(hipMemcpyAsync(c.cs[k].cnt, c.cs[k].off, sizeof(int32_t) * H[k], hipMemcpyDeviceToDevice, c.s));
+    const dim3 g((n[k] + 255) / 256);
+    if (k == 0)
+      k_cs_insert<3, true><<<g, dim3(256), 0, c.s>>>(n[k], ids[k], x, h, dhat, uint64_t(H[k] - 1), c.cs[k].cnt,
+                                                      c.cs[k].key, c.cs[k].id, c.err);
+    else
+      k_cs_insert<2, true><<<g, dim3(256), 0, c.s>>>(n[k], ids[k], x, h, dhat, uint64_t(H[k] - 1), c.cs[k].cnt,
+                                                      c.cs[k].key, c.cs[k].id, c.err);
+  }
+  unsigned long long* cnt = c.cs_misc + 1;
+  if (nv > 0 && nt > 0)
+    k_cs_query_pt<<<dim3((nv + 255) / 256), dim3(256), 0, c.s>>>(nv, verts, tris, x, h, dhat, uint64_t(H[0] - 1),
+                                                                  c.cs[0].off, c.cs[0].key, c.cs[0].id, cap, pairs,
+                                                                  kind, dist, grad, cnt);
+  if (ne > 1)
+    k_cs_query_ee<<<dim3((ne + 255) / 256), dim3(256), 0, c.s>>>(ne, edges, x, h, dhat, uint64_t(H[1] - 1),
+                                                                  c.cs[1].off, c.cs[1].key, c.cs[1].id, cap, pairs,
+                                                                  kind, dist, grad, cnt, c.err);
+  HIPCHK(hipGetLastError());
+  unsigned long long found = 0;
+  HIPCHK(hipMemcpyAsync(&found, cnt, sizeof(found), hipMemcpyDeviceToHost, c.s));
+  HIPCHK(hipStreamSynchronize(c.s));
+  *count = int64_t(found);
   return MAS_OK;
 }
 

@@ -93,6 +93,15 @@ mas_status ensure_cub(Ctx& c, size_t bytes) {
   return MAS_OK;
 }
 
+mas_status exclusive_scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n1) {
+  size_t bytes = 0;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, int(n1), c.s));
+  mas_status st = ensure_cub(c, bytes);
+  if (st != MAS_OK) return st;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(c.cub_tmp, bytes, in, out, int(n1), c.s));
+  return MAS_OK;
+}
+
 mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
                            const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
   HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (D + 1), c.s));

@@ -15,6 +15,8 @@ mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64
                            const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
 
 mas_status ensure_cub(Ctx& c, size_t bytes);
+// out[0..n] = exclusive prefix sums of in[0..n] (n + 1 entries)
+mas_status exclusive_scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n1);
 // one-thread store of a counter (graph-capturable, unlike a memset)
 __global__ void k_set_u32(uint32_t* p, uint32_t v);
 
@@ -53,5 +55,8 @@ mas_status launch_ccd(Ctx& c, const double* x, const double* p, int64_t m, const
                       const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
 mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
                                     double* dist, double* grad, uint8_t* type);
+mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
+                                 const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
+                                 uint8_t* kind, double* dist, double* grad, int64_t* count);
 
 }  // namespace mas

@@ -558,12 +558,21 @@ def surface(tets):
     edges and vertices those of the triangles (edges with the smaller id
     first, all sorted).  Topology only."""
     t = np.asarray(tets, np.int64)
-    faces = np.concatenate([t[:, [0, 1, 2]], t[:, [0, 1, 3]], t[:, [0, 2, 3]], t[:, [1, 2, 3]]])
-    key = np.sort(faces, axis=1)
-    uniq, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
-    tris = uniq[cnt == 1]
-    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [0, 2]]])
-    edges = np.unique(np.sort(e, axis=1), axis=0)
+    faces = np.sort(np.concatenate([t[:, [0, 1, 2]], t[:, [0, 1, 3]], t[:, [0, 2, 3]], t[:, [1, 2, 3]]]), axis=1)
+    if t.size and t.max() < (1 << 21):
+        # one 63-bit key per sorted face / edge: a 1-D unique
+        fk = (faces[:, 0] << 42) | (faces[:, 1] << 21) | faces[:, 2]
+        uk, cnt = np.unique(fk, return_counts=True)
+        k1 = uk[cnt == 1]
+        tris = np.stack([k1 >> 42, (k1 >> 21) & 0x1FFFFF, k1 & 0x1FFFFF], 1)
+        e = np.sort(np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [0, 2]]]), axis=1)
+        ek = np.unique((e[:, 0] << 21) | e[:, 1])
+        edges = np.stack([ek >> 21, ek & 0x1FFFFF], 1)
+    else:
+        uniq, cnt = np.unique(faces, axis=0, return_counts=True)
+        tris = uniq[cnt == 1]
+        e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [0, 2]]])
+        edges = np.unique(np.sort(e, axis=1), axis=0)
     verts = np.unique(tris)
     return verts.astype(np.int32), tris.astype(np.int32), edges.astype(np.int32)
 
