@@ -218,8 +218,8 @@ mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const in
 // point probes its own cell: a triangle within dhat of it has a grown box
 // containing it, so it is entered there, once.  An edge probes the cells
 // of its own box and keeps a partner edge only in the cell holding the
-// lower corner of (own box) x (partner's grown box), so each pair is found
-// once.  Candidates whose boxes are dhat or more apart are dropped, the
+// lower corner of the overlap of its own box and the partner's grown box,
+// so each pair is found once.  Candidates whose boxes are dhat or more apart are dropped, the
 // rest go through the narrow phase and are kept when d < dhat.  Results
 // are appended through one counter (their order is not fixed).
 namespace {
@@ -284,39 +284,51 @@ __device__ __forceinline__ void append_pair(unsigned long long* count, int64_t c
 __global__ __launch_bounds__(256) void k_cs_prep(int64_t N, int64_t nt, const int32_t* tris, int64_t ne,
                                                  const int32_t* edges, int64_t nv, const int32_t* verts,
                                                  const double* x, unsigned long long* misc) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  const int32_t* ids = nullptr;
-  int nid = 0;
-  if (i < nt) ids = tris + 3 * i, nid = 3;
-  else if (i < nt + ne) ids = edges + 2 * (i - nt), nid = 2;
-  else if (i < nt + ne + nv) ids = verts + (i - nt - ne), nid = 1;
+  __shared__ double se[4], sa[4];
+  __shared__ unsigned long long sb[4];
   double e = 0.0, amax = 0.0;
   unsigned long long bad = 0;
-  if (nid > 0) {
+  const int64_t total = nt + ne + nv;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t* ids;
+    int nid;
+    if (i < nt) ids = tris + 3 * i, nid = 3;
+    else if (i < nt + ne) ids = edges + 2 * (i - nt), nid = 2;
+    else ids = verts + (i - nt - ne), nid = 1;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool ok = true;
     for (int j = 0; j < nid; ++j) {
       const int v = ids[j];
       if (!(v >= 0 && v < N)) {
         bad |= 1ull;
+        ok = false;
         continue;
       }
       for (int a = 0; a < 3; ++a) {
         const double c = x[3 * int64_t(v) + a];
-        if (!isfinite(c)) bad |= 2ull;
+        if (!isfinite(c)) {
+          bad |= 2ull;
+          ok = false;
+        }
         lo[a] = fmin(lo[a], c);
         hi[a] = fmax(hi[a], c);
-        amax = fmax(amax, fabs(c));
       }
     }
-    if (!bad && nid > 1) e = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
-    if (bad) e = amax = 0.0;
+    if (ok) {
+      for (int a = 0; a < 3; ++a) amax = fmax(amax, fmax(fabs(lo[a]), fabs(hi[a])));
+      if (nid > 1) e = fmax(e, fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2])));
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     e = fmax(e, __shfl_xor(e, o));
     amax = fmax(amax, __shfl_xor(amax, o));
     bad |= __shfl_xor(bad, o);
   }
-  if ((threadIdx.x & 63) == 0) {
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) se[w] = e, sa[w] = amax, sb[w] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q) e = fmax(e, se[q]), amax = fmax(amax, sa[q]), bad |= sb[q];
     if (e > 0.0) atomicMax(&misc[0], (unsigned long long)__double_as_longlong(e));
     if (bad) atomicOr(&misc[2], bad);
     if (amax > 0.0) atomicMax(&misc[3], (unsigned long long)__double_as_longlong(amax));
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* 
           if (b0 == a0 || b0 == a1 || b1 == a0 || b1 == a1) continue;
           const Box bb = prim_box<2>(x, edges, j);
           if (!(box_dist2(ab, bb) < dh2)) continue;
-          // report from the cell of the lower corner of (own box) x (grown partner box)
+          // report from the cell of the lower corner of the overlap of the own box and the grown partner box
           const int64_t rx = cell_of(fmax(ab.lo[0], bb.lo[0] - dhat), h);
           const int64_t ry = cell_of(fmax(ab.lo[1], bb.lo[1] - dhat), h);
           const int64_t rz = cell_of(fmax(ab.lo[2], bb.lo[2] - dhat), h);
@@ -465,8 +477,8 @@ mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t n
   if (!c.cs_misc && hipMalloc(&c.cs_misc, 4 * sizeof(unsigned long long)) != hipSuccess) return MAS_ERR_OOM;
   HIPCHK(hipMemsetAsync(c.cs_misc, 0, 4 * sizeof(unsigned long long), c.s));
   if (nt + ne == 0) return MAS_OK;
-  k_cs_prep<<<dim3((nt + ne + nv + 255) / 256), dim3(256), 0, c.s>>>(c.N, nt, tris, ne, edges, nv, verts, x,
-                                                                     c.cs_misc);
+  const int64_t prep_grid = std::min<int64_t>((nt + ne + nv + 255) / 256, int64_t(c.n_cu) * 8);
+  k_cs_prep<<<dim3(prep_grid), dim3(256), 0, c.s>>>(c.N, nt, tris, ne, edges, nv, verts, x, c.cs_misc);
   unsigned long long misc[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(misc, c.cs_misc, sizeof(misc), hipMemcpyDeviceToHost, c.s));
   HIPCHK(hipStreamSynchronize(c.s));
