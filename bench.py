@@ -317,8 +317,8 @@ def main():
                               "two_boxes" if args.small else "puffer_balls")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (how it would shard is described "
+              "in the design notes).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
