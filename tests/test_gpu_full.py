@@ -183,3 +183,70 @@ def test_iterations_with_rebuilds_full():
         assert s.log[-1]["gnorm"] < 5e-2 * s.g0norm
     finally:
         s.ctx.close()
+
+
+def test_constraint_set_full(full):
+    """ComputeConstraintSet over the whole puffer boundary surface (816k
+    vertices, 1.63M triangles, 2.45M edges): sampled pairs found are
+    contacts with the oracle's distance, none twice, and for sampled
+    vertices and edges the pairs found are exactly the brute-force ones
+    (all triangles / edges, box-distance prune, oracle distance)."""
+    from oracle import constraint_set as CS
+    from oracle import contact as C
+    sc, ctx, torch = full["sc"], full["ctx"], full["torch"]
+    verts, tris, edges = synth.surface(sc.tets)
+    dev = "cuda"
+    r = ctx.rank
+    cap = 1 << 22
+    pairs = torch.empty(cap, 4, dtype=torch.int32, device=dev)
+    kind = torch.empty(cap, dtype=torch.uint8, device=dev)
+    dist = torch.empty(cap, dtype=torch.float64, device=dev)
+    n = ctx.constraint_set(full["x"], torch.as_tensor(r[verts].astype(np.int32), device=dev),
+                           torch.as_tensor(r[tris].astype(np.int32), device=dev),
+                           torch.as_tensor(r[edges].astype(np.int32), device=dev), sc.dhat, pairs, kind, dist)
+    code, msg = ctx.sync()
+    assert code == 0, msg
+    assert 0 < n <= cap
+    P = ctx.perm[pairs[:n].cpu().numpy()]
+    K = kind[:n].cpu().numpy()
+    D = dist[:n].cpu().numpy()
+    X = sc.x.reshape(-1, 3)
+    print("pairs %d (PT %d, EE %d)" % (n, int((K == 0).sum()), int((K == 1).sum())))
+
+    def key(p, k):
+        if k == 0:
+            return (0, int(p[0]), *sorted(map(int, p[1:])))
+        a, b = tuple(sorted(map(int, p[:2]))), tuple(sorted(map(int, p[2:])))
+        return (1, *min(a, b), *max(a, b))
+
+    keys = [key(p, k) for p, k in zip(P, K)]
+    assert len(set(keys)) == len(keys)
+    rng = np.random.default_rng(8)
+    for i in rng.choice(n, 2000, replace=False):
+        do = C.pair_distance(X[P[i]], K[i])[0]
+        assert do < sc.dhat and abs(D[i] - do) <= 1e-12 * np.linalg.norm(np.ptp(X[P[i]], axis=0))
+    kset = set(keys)
+    T, E = X[tris], X[edges]
+    tlo, thi, elo, ehi = T.min(1), T.max(1), E.min(1), E.max(1)
+    # completeness: vertices that take part in contacts and random ones
+    cand_v = np.unique(P[K == 0][:, 0])
+    sv = np.concatenate([rng.choice(cand_v, 40, replace=False), rng.choice(verts, 30, replace=False)])
+    for v in sv:
+        for t in np.nonzero(CS.box_distance(X[v], X[v], tlo, thi) < sc.dhat)[0]:
+            tv = tris[t]
+            if v in tv:
+                continue
+            ids = np.array([v, *tv])
+            if C.pair_distance(X[ids], C.PT)[0] < sc.dhat:
+                assert key(ids, 0) in kset, ids
+    se = edges[rng.choice(len(edges), 40, replace=False)]
+    ee_edges = P[K == 1]
+    se = np.concatenate([se, ee_edges[rng.choice(len(ee_edges), 30, replace=False), :2]])
+    for e in se:
+        for j in np.nonzero(CS.box_distance(X[e].min(0), X[e].max(0), elo, ehi) < sc.dhat)[0]:
+            f = edges[j]
+            if len({*e, *f}) < 4:
+                continue
+            ids = np.array([*e, *f])
+            if C.pair_distance(X[ids], C.EE)[0] < sc.dhat:
+                assert key(ids, 1) in kset, ids
