@@ -15,16 +15,29 @@ namespace mas {
 // applies every tet and every base stencil touching r, keeps only the rows of
 // its own vertices (LDS accumulation) and writes y for them together with
 // the mass term, so no output is ever written by two workgroups.  A tet
-// touching k ranges has k entries (about 1.4 on the test scenes), each with
-// its own copy of the snapshot, so a workgroup streams contiguous data.
-// Resident workgroups take ranges from a counter (dynamic balance); each
+// touching k ranges has k entries (about 1.3 on the test scenes), each with
+// its own copy of the snapshot, so a workgroup streams contiguous data.  The
+// range's own part of v is staged in LDS once and read from there by every
+// entry (only the vertices of other ranges are gathered from memory).  One
+// workgroup per compute unit (the two 48 KB LDS arrays);
+// resident workgroups take ranges from a counter (dynamic balance) and each
 // exits once the counter has passed the last range.
+// float64 snapshots take 512 threads, so that their larger per-thread state
+// stays in registers.
 template <typename TH>
-__global__ __launch_bounds__(256, 3) void k_hv_range(int64_t nrange, const int32_t* rbeg, const int32_t* rt_off,
-                                                     const int32_t* rl_tv, const TH* hr, const int32_t* bidx,
-                                                     const double* bu, const int32_t* rc_off, const int32_t* rc_list,
-                                                     const double* mass, const double* v, double* y, uint32_t* ctr) {
+constexpr int hv_threads() {
+  return sizeof(TH) == 8 ? 512 : 1024;
+}
+
+template <typename TH>
+__global__ __launch_bounds__(hv_threads<TH>()) void k_hv_range(int64_t nrange, const int32_t* rbeg,
+                                                                const int32_t* rt_off, const int32_t* rl_tv,
+                                                                const TH* hr, const int32_t* bidx, const double* bu,
+                                                                const int32_t* rc_off, const int32_t* rc_list,
+                                                                const double* mass, const double* v, double* y,
+                                                                uint32_t* ctr) {
   __shared__ double win[3 * RANGE_MAX];
+  __shared__ double vs[3 * RANGE_MAX];
   __shared__ int64_t cur;
   constexpr int NH = sizeof(TH) == 8 ? EH : 4 * SNAP_NC32;
   while (true) {
@@ -33,7 +46,10 @@ __global__ __launch_bounds__(256, 3) void k_hv_range(int64_t nrange, const int32
     const int64_t r = cur;
     if (r >= nrange) break;  // every workgroup ends here once the counter passes nrange
     const int v0 = rbeg[r], nv = rbeg[r + 1] - v0;
-    for (int e = threadIdx.x; e < 3 * nv; e += blockDim.x) win[e] = 0.0;
+    for (int e = threadIdx.x; e < 3 * nv; e += blockDim.x) {
+      win[e] = 0.0;
+      vs[e] = v[3 * int64_t(v0) + e];
+    }
     __syncthreads();
     const int t0 = rt_off[r], t1 = rt_off[r + 1];
     for (int w = t0 + threadIdx.x; w < t1; w += blockDim.x) {
@@ -43,9 +59,16 @@ __global__ __launch_bounds__(256, 3) void k_hv_range(int64_t nrange, const int32
       snap_load(hr, w, H);
       double ve[12];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
+        const int lv = vi[j] - v0;
+        if (lv >= 0 && lv < nv) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ve[3 * j + a] = v[3 * vi[j] + a];
+          for (int a = 0; a < 3; ++a) ve[3 * j + a] = vs[3 * lv + a];
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) ve[3 * j + a] = v[3 * vi[j] + a];
+        }
+      }
       double f[12];
       elem_hv<TH>(H, H + 45, ve, f);
 #pragma unroll
@@ -69,8 +92,10 @@ __global__ __launch_bounds__(256, 3) void k_hv_range(int64_t nrange, const int32
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (vi[j] < 0) continue;
+        const int lv = vi[j] - v0;
+        const bool own = lv >= 0 && lv < nv;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) s += uu[3 * j + a] * v[3 * vi[j] + a];
+        for (int a = 0; a < 3; ++a) s += uu[3 * j + a] * (own ? vs[3 * lv + a] : v[3 * vi[j] + a]);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -84,7 +109,7 @@ __global__ __launch_bounds__(256, 3) void k_hv_range(int64_t nrange, const int32
     __syncthreads();
     for (int e = threadIdx.x; e < 3 * nv; e += blockDim.x) {
       const int64_t q = 3 * int64_t(v0) + e;
-      y[q] = mass[q / 3] * v[q] + win[e];
+      y[q] = mass[q / 3] * vs[e] + win[e];
     }
     __syncthreads();
   }
@@ -141,13 +166,13 @@ mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update) {
   k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr, 0u);
   {
     ProfScope pt(c, MAS_T_HV_TETS);
-    const int64_t grid = std::min<int64_t>(c.nrange, int64_t(c.n_cu) * 4);
+    const int64_t grid = std::min<int64_t>(c.nrange, int64_t(c.n_cu));
     if (c.hr32)
-      k_hv_range<float><<<dim3(grid), dim3(256), 0, c.s>>>(c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr32, c.bidx, c.bu,
-                                                           c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
+      k_hv_range<float><<<dim3(grid), dim3(hv_threads<float>()), 0, c.s>>>(
+          c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr32, c.bidx, c.bu, c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
     else
-      k_hv_range<double><<<dim3(grid), dim3(256), 0, c.s>>>(c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr64, c.bidx,
-                                                            c.bu, c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
+      k_hv_range<double><<<dim3(grid), dim3(hv_threads<double>()), 0, c.s>>>(
+          c.nrange, c.rbeg, c.rt_off, c.rl_tv, c.hr64, c.bidx, c.bu, c.rc_off, c.rc_list, c.mass, v, y, c.ctr);
   }
   if (with_update && c.have_update && c.mc > 0)
     k_hv_cols<<<dim3((c.mc + SW_CHUNK - 1) / SW_CHUNK), dim3(256), 0, c.s>>>(c.N, c.mc, c.Uidx, c.U, c.dS, v, y);
