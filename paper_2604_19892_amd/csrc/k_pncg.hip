@@ -39,18 +39,22 @@ __device__ inline void block_reduce_store(double (&v)[NV], double* out, int nblk
 // own vertices in LDS and writes g for them (no atomics).  A tet's energy
 // h^2 V Psi(F) is counted by its home entry (the range of its smallest
 // vertex).  Energies are reduced per
-// range in a fixed order (part rows 0 and 1, one slot per range).
-__global__ __launch_bounds__(RB) void k_eg_range(int64_t nrange, const int32_t* rbeg, const int32_t* rl_t,
-                                                 const int32_t* rl_tv, const double* rl_geo, const int32_t* rt_off,
-                                                 const double* mass, const double* x, const double* xt, double h2,
-                                                 double* g, double* part, int nblk, uint32_t* ctr) {
+// range in a fixed order (part rows 0 and 1, one slot per range).  The
+// range's own part of x is staged in LDS and read from there by every
+// entry; one 1024-thread workgroup per compute unit (two 48 KB LDS arrays).
+constexpr int EGT = 1024;
+__global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t* rbeg, const int32_t* rl_t,
+                                                  const int32_t* rl_tv, const double* rl_geo, const int32_t* rt_off,
+                                                  const double* mass, const double* x, const double* xt, double h2,
+                                                  double* g, double* part, int nblk, uint32_t* ctr) {
   __shared__ double win[3 * RANGE_MAX];
-  __shared__ double red[2][RB / 64];
+  __shared__ double xs[3 * RANGE_MAX];
+  __shared__ double red[2][EGT / 64];
   __shared__ int64_t cur;
   const bool grad = g != nullptr;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // partial slots past the last range stay zero
-  for (int64_t q = nrange + blockIdx.x * int64_t(RB) + threadIdx.x; q < nblk; q += int64_t(gridDim.x) * RB) {
+  for (int64_t q = nrange + blockIdx.x * int64_t(EGT) + threadIdx.x; q < nblk; q += int64_t(gridDim.x) * EGT) {
     part[q] = 0.0;
     part[nblk + q] = 0.0;
   }
@@ -61,8 +65,11 @@ __global__ __launch_bounds__(RB) void k_eg_range(int64_t nrange, const int32_t* 
     if (r >= nrange) break;  // every workgroup ends here once the counter passes nrange
     double e[2] = {0.0, 0.0};
     const int v0 = rbeg[r], nv = rbeg[r + 1] - v0;
-    for (int q = threadIdx.x; q < 3 * nv; q += RB) win[q] = 0.0;
-    for (int lv = threadIdx.x; lv < nv; lv += RB) {
+    for (int q = threadIdx.x; q < 3 * nv; q += EGT) {
+      win[q] = 0.0;
+      xs[q] = x[3 * int64_t(v0) + q];
+    }
+    for (int lv = threadIdx.x; lv < nv; lv += EGT) {
       const double m = mass[v0 + lv];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -72,7 +79,7 @@ __global__ __launch_bounds__(RB) void k_eg_range(int64_t nrange, const int32_t* 
     }
     __syncthreads();
     const int t0 = rt_off[r], t1 = rt_off[r + 1];
-    for (int w = t0 + threadIdx.x; w < t1; w += RB) {
+    for (int w = t0 + threadIdx.x; w < t1; w += EGT) {
       const int4 tv = reinterpret_cast<const int4*>(rl_tv)[w];
       const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
       const bool own_e = rl_t[w] < 0;  // home entry of the tet
@@ -81,9 +88,16 @@ __global__ __launch_bounds__(RB) void k_eg_range(int64_t nrange, const int32_t* 
       for (int j = 0; j < 4; ++j) touch[j] = grad && vi[j] >= v0 && vi[j] < v0 + nv;
       double xe[12];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
+        const int lv = vi[j] - v0;
+        if (lv >= 0 && lv < nv) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
+          for (int a = 0; a < 3; ++a) xe[3 * j + a] = xs[3 * lv + a];
+        } else {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) xe[3 * j + a] = x[3 * vi[j] + a];
+        }
+      }
       double gm[12];
       geo_load(rl_geo, w, gm);
       double F[3][3];
@@ -120,13 +134,13 @@ __global__ __launch_bounds__(RB) void k_eg_range(int64_t nrange, const int32_t* 
     __syncthreads();
     if (threadIdx.x < 2) {
       double t = 0.0;
-      for (int i = 0; i < RB / 64; ++i) t += red[threadIdx.x][i];
+      for (int i = 0; i < EGT / 64; ++i) t += red[threadIdx.x][i];
       part[threadIdx.x * int64_t(nblk) + r] = t;
     }
     if (grad) {
-      for (int q = threadIdx.x; q < 3 * nv; q += RB) {
+      for (int q = threadIdx.x; q < 3 * nv; q += EGT) {
         const int64_t gq = 3 * int64_t(v0) + q;
-        g[gq] = mass[gq / 3] * (x[gq] - xt[gq]) + win[q];
+        g[gq] = mass[gq / 3] * (xs[q] - xt[gq]) + win[q];
       }
     }
     __syncthreads();
@@ -226,7 +240,7 @@ mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const m
   const int nb = c.n_partial_blocks;
   double* part = c.partials;  // [0]: inertia [1]: elastic [2]: barrier [3]: infeasible count
   k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr + 1, 0u);
-  k_eg_range<<<dim3(std::min<int64_t>(c.nrange, int64_t(c.n_cu) * 4)), dim3(RB), 0, c.s>>>(
+  k_eg_range<<<dim3(std::min<int64_t>(c.nrange, int64_t(c.n_cu))), dim3(EGT), 0, c.s>>>(
       c.nrange, c.rbeg, c.rl_t, c.rl_tv, c.rl_geo, c.rt_off, c.mass, x, xt, c.cfg.h * c.cfg.h, g, part, nb, c.ctr + 1);
   int64_t m = ct ? ct->m : 0;
   if (m > 0) {
