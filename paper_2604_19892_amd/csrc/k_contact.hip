@@ -221,7 +221,8 @@ mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const in
 // lower corner of the overlap of its own box and the partner's grown box,
 // so each pair is found once.  Candidates whose boxes are dhat or more apart are dropped, the
 // rest go through the narrow phase and are kept when d < dhat.  Results
-// are appended through one counter (their order is not fixed).
+// are appended through one counter, one atomic per wavefront for up to
+// four pairs per lane (their order is not fixed).
 namespace {
 
 constexpr int CELL_BITS = 21;  // per axis in the cell key (cells wrap every 2^21)
@@ -368,20 +369,70 @@ __global__ __launch_bounds__(256) void k_cs_insert(int64_t n, const int32_t* ids
       }
 }
 
+// Up to HITS pairs a lane has found are appended together with those of
+// the other lanes at the next point the whole wavefront reaches: one atomic
+// per wavefront instead of one per pair (pairs beyond HITS take their own).
+// The lane keeps only the partner's index and recomputes the geometry when
+// it writes.
+constexpr int HITS = 4;
+
+__device__ __forceinline__ void push_hit(int (&hb)[HITS], int j) {
+#pragma unroll
+  for (int q = HITS - 1; q > 0; --q) hb[q] = hb[q - 1];
+  hb[0] = j;
+}
+
+// First output slot of this lane's nb pairs; every lane of the wavefront calls.
+__device__ __forceinline__ int64_t wave_reserve(int nb, unsigned long long* count) {
+  const int lane = threadIdx.x & 63;
+  int incl = nb;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const int total = __shfl(incl, 63);
+  unsigned long long base = 0;
+  if (total > 0 && lane == 63) base = atomicAdd(count, (unsigned long long)total);
+  base = __shfl(base, 63);
+  return int64_t(base) + incl - nb;
+}
+
+__device__ __forceinline__ void write_pair(int64_t slot, int64_t cap, const int (&q)[4], int kind, const double* x,
+                                           int32_t* pairs, uint8_t* kinds, double* dist, double* grad) {
+  if (slot >= cap) return;
+  const V3 X[4] = {load_v3(x, q[0]), load_v3(x, q[1]), load_v3(x, q[2]), load_v3(x, q[3])};
+  double d, wt[4];
+  V3 n;
+  pair_geometry(X, kind, d, wt, n);
+  reinterpret_cast<int4*>(pairs)[slot] = make_int4(q[0], q[1], q[2], q[3]);
+  kinds[slot] = uint8_t(kind);
+  dist[slot] = d;
+  if (grad) store_grad(grad, slot, wt, n);
+}
+
 __global__ __launch_bounds__(256) void k_cs_query_pt(int64_t nv, const int32_t* verts, const int32_t* tris,
                                                      const double* x, double h, double dhat, uint64_t hmask,
                                                      const int32_t* off, const uint64_t* ekey, const int32_t* eid,
                                                      int64_t cap, int32_t* pairs, uint8_t* kinds, double* dist,
                                                      double* grad, unsigned long long* count) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= nv) return;
-  const int v = verts[i];
-  const V3 P = load_v3(x, v);
+  int v = 0, e0 = 0, e1 = 0;
+  V3 P{};
+  uint64_t k = 0;
+  if (i < nv) {
+    v = verts[i];
+    P = load_v3(x, v);
+    k = cell_key(cell_of(P.x, h), cell_of(P.y, h), cell_of(P.z, h));
+    const uint64_t bkt = key_hash(k) & hmask;
+    e0 = off[bkt];
+    e1 = off[bkt + 1];
+  }
   const Box pb = {{P.x, P.y, P.z}, {P.x, P.y, P.z}};
-  const uint64_t k = cell_key(cell_of(P.x, h), cell_of(P.y, h), cell_of(P.z, h));
-  const uint64_t bkt = key_hash(k) & hmask;
   const double dh2 = dhat * dhat;
-  for (int e = off[bkt]; e < off[bkt + 1]; ++e) {
+  int hb[HITS] = {0, 0, 0, 0};
+  int nb = 0;
+  for (int e = e0; e < e1; ++e) {
     if (ekey[e] != k) continue;
     const int t = eid[e];
     const int tv[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
@@ -392,7 +443,23 @@ __global__ __launch_bounds__(256) void k_cs_query_pt(int64_t nv, const int32_t* 
     double d, wt[4];
     V3 n;
     pair_geometry(X, 0, d, wt, n);
-    if (d < dhat) append_pair(count, cap, q, 0, d, wt, n, pairs, kinds, dist, grad);
+    if (d < dhat) {
+      if (nb < HITS) {
+        push_hit(hb, t);
+        ++nb;
+      } else {
+        append_pair(count, cap, q, 0, d, wt, n, pairs, kinds, dist, grad);
+      }
+    }
+  }
+  const int64_t s0 = wave_reserve(nb, count);
+#pragma unroll
+  for (int q = 0; q < HITS; ++q) {
+    if (q < nb) {
+      const int t = hb[q];
+      const int ids[4] = {v, tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+      write_pair(s0 + q, cap, ids, 0, x, pairs, kinds, dist, grad);
+    }
   }
 }
 
@@ -402,45 +469,74 @@ __global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* 
                                                      int32_t* pairs, uint8_t* kinds, double* dist, double* grad,
                                                      unsigned long long* count, uint32_t* err) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= ne) return;
-  const int a0 = edges[2 * i], a1 = edges[2 * i + 1];
-  const Box ab = prim_box<2>(x, edges, i);
-  int64_t c0[3], c1[3];
-  for (int a = 0; a < 3; ++a) {
-    c0[a] = cell_of(ab.lo[a], h);
-    c1[a] = cell_of(ab.hi[a], h);
-    if (c1[a] - c0[a] > 2 || c1[a] < c0[a]) {  // as in k_cs_insert
-      atomicOr(err, ERRB_INDEX);
-      return;
+  int a0 = 0, a1 = 0, ncell = 0;
+  int64_t c0[3] = {0, 0, 0}, span[3] = {1, 1, 1};
+  Box ab{};
+  if (i < ne) {
+    a0 = edges[2 * i];
+    a1 = edges[2 * i + 1];
+    ab = prim_box<2>(x, edges, i);
+    ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+      c0[a] = cell_of(ab.lo[a], h);
+      span[a] = cell_of(ab.hi[a], h) - c0[a] + 1;
+      if (span[a] > 3 || span[a] < 1) {  // as in k_cs_insert
+        atomicOr(err, ERRB_INDEX);
+        ncell = 0;
+        span[a] = 1;
+      }
     }
+    if (ncell) ncell = int(span[0] * span[1] * span[2]);
   }
   const double dh2 = dhat * dhat;
-  for (int64_t cx = c0[0]; cx <= c1[0]; ++cx)
-    for (int64_t cy = c0[1]; cy <= c1[1]; ++cy)
-      for (int64_t cz = c0[2]; cz <= c1[2]; ++cz) {
-        const uint64_t k = cell_key(cx, cy, cz);
-        const uint64_t bkt = key_hash(k) & hmask;
-        for (int e = off[bkt]; e < off[bkt + 1]; ++e) {
-          if (ekey[e] != k) continue;
-          const int j = eid[e];
-          if (j <= i) continue;
-          const int b0 = edges[2 * j], b1 = edges[2 * j + 1];
-          if (b0 == a0 || b0 == a1 || b1 == a0 || b1 == a1) continue;
-          const Box bb = prim_box<2>(x, edges, j);
-          if (!(box_dist2(ab, bb) < dh2)) continue;
-          // report from the cell of the lower corner of the overlap of the own box and the grown partner box
-          const int64_t rx = cell_of(fmax(ab.lo[0], bb.lo[0] - dhat), h);
-          const int64_t ry = cell_of(fmax(ab.lo[1], bb.lo[1] - dhat), h);
-          const int64_t rz = cell_of(fmax(ab.lo[2], bb.lo[2] - dhat), h);
-          if (rx != cx || ry != cy || rz != cz) continue;
-          const int q[4] = {a0, a1, b0, b1};
-          const V3 X[4] = {load_v3(x, a0), load_v3(x, a1), load_v3(x, b0), load_v3(x, b1)};
-          double d, wt[4];
-          V3 n;
-          pair_geometry(X, 1, d, wt, n);
-          if (d < dhat) append_pair(count, cap, q, 1, d, wt, n, pairs, kinds, dist, grad);
+  // one cell per step for every lane, so that the appends after each step
+  // are reached by the whole wavefront
+  for (int cell = 0; __ballot(cell < ncell) != 0ull; ++cell) {
+    int hb[HITS] = {0, 0, 0, 0};
+    int nb = 0;
+    if (cell < ncell) {
+      const int64_t cx = c0[0] + cell % span[0], cy = c0[1] + (cell / span[0]) % span[1],
+                    cz = c0[2] + cell / (span[0] * span[1]);
+      const uint64_t k = cell_key(cx, cy, cz);
+      const uint64_t bkt = key_hash(k) & hmask;
+      for (int e = off[bkt]; e < off[bkt + 1]; ++e) {
+        if (ekey[e] != k) continue;
+        const int j = eid[e];
+        if (j <= i) continue;
+        const int b0 = edges[2 * j], b1 = edges[2 * j + 1];
+        if (b0 == a0 || b0 == a1 || b1 == a0 || b1 == a1) continue;
+        const Box bb = prim_box<2>(x, edges, j);
+        if (!(box_dist2(ab, bb) < dh2)) continue;
+        // report from the cell of the lower corner of the overlap of the own box and the grown partner box
+        const int64_t rx = cell_of(fmax(ab.lo[0], bb.lo[0] - dhat), h);
+        const int64_t ry = cell_of(fmax(ab.lo[1], bb.lo[1] - dhat), h);
+        const int64_t rz = cell_of(fmax(ab.lo[2], bb.lo[2] - dhat), h);
+        if (rx != cx || ry != cy || rz != cz) continue;
+        const int q[4] = {a0, a1, b0, b1};
+        const V3 X[4] = {load_v3(x, a0), load_v3(x, a1), load_v3(x, b0), load_v3(x, b1)};
+        double d, wt[4];
+        V3 n;
+        pair_geometry(X, 1, d, wt, n);
+        if (d < dhat) {
+          if (nb < HITS) {
+            push_hit(hb, j);
+            ++nb;
+          } else {
+            append_pair(count, cap, q, 1, d, wt, n, pairs, kinds, dist, grad);
+          }
         }
       }
+    }
+    const int64_t s0 = wave_reserve(nb, count);
+#pragma unroll
+    for (int q = 0; q < HITS; ++q) {
+      if (q < nb) {
+        const int j = hb[q];
+        const int ids[4] = {a0, a1, edges[2 * j], edges[2 * j + 1]};
+        write_pair(s0 + q, cap, ids, 1, x, pairs, kinds, dist, grad);
+      }
+    }
+  }
 }
 
 static mas_status grow_table(Ctx::CellTable& t, int64_t H, int64_t E) {
