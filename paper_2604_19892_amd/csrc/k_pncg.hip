@@ -154,22 +154,26 @@ __global__ __launch_bounds__(RB) void k_eg_contacts(int64_t N, int64_t m, const 
                                                     const double* grad, double kappa, double dhat, double* g,
                                                     double* part, int nblk) {
   __shared__ double win[3 * SW_WIN];
+  __shared__ double win2[3 * SW_WIN];
   double e[2] = {0.0, 0.0};
   const bool gr = g != nullptr;
   for (int64_t chunk = blockIdx.x; chunk * SW_CHUNK < m; chunk += nblk) {
     const int64_t c0 = chunk * SW_CHUNK;
-    int vbase;
+    // two windows: from the smallest vertex of the chunk's first stencil,
+    // and around its largest one (a contact's two sides lie far apart in
+    // the vertex order); vertices in neither go to memory
+    int vbase, vbase2;
     {
       const int4 f4 = reinterpret_cast<const int4*>(idx)[c0];
-      int mn = INT32_MAX;
-      if (f4.x >= 0) mn = min(mn, f4.x);
-      if (f4.y >= 0) mn = min(mn, f4.y);
-      if (f4.z >= 0) mn = min(mn, f4.z);
-      if (f4.w >= 0) mn = min(mn, f4.w);
+      int mn = INT32_MAX, mx = -1;
+      const int fv[4] = {f4.x, f4.y, f4.z, f4.w};
+      for (int j = 0; j < 4; ++j)
+        if (fv[j] >= 0) mn = min(mn, fv[j]), mx = max(mx, fv[j]);
       vbase = (mn == INT32_MAX) ? 0 : mn;
+      vbase2 = max(vbase + SW_WIN, mx - SW_WIN / 4);
     }
     if (gr) {
-      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0;
+      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0, win2[q] = 0.0;
       __syncthreads();
     }
     for (int k = 0; k < SW_CHUNK; k += RB) {
@@ -192,13 +196,21 @@ __global__ __launch_bounds__(RB) void k_eg_contacts(int64_t N, int64_t m, const 
         for (int j = 0; j < 4; ++j) {
           if (vi[j] < 0) continue;
 #pragma unroll
-          for (int a = 0; a < 3; ++a) sw_add(win, g, vbase, vi[j], a, s * grad[12 * i + 3 * j + a]);
+          for (int a = 0; a < 3; ++a) {
+            const double val = s * grad[12 * i + 3 * j + a];
+            const int l2 = vi[j] - vbase2;
+            if (l2 >= 0 && l2 < SW_WIN)
+              __hip_atomic_fetch_add(&win2[3 * l2 + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+              sw_add(win, g, vbase, vi[j], a, val);
+          }
         }
       }
     }
     if (gr) {
       __syncthreads();
       sw_flush(win, g, vbase, N);
+      sw_flush(win2, g, vbase2, N);
       __syncthreads();
     }
   }
