@@ -21,7 +21,7 @@ Test infrastructure (see the package docstring).
   steps).  A common step keeps every d_c >= 0.1 d_c; where the subdomains of
   one stencil move with different steps and the combined motion would bring
   it below 0.05 d_c, the steps of those subdomains are halved, repeatedly
-  (at most 40 rounds), so that only the critical subdomains are damped.
+  (at most 16 rounds), so that only the critical subdomains are damped.
 """
 from __future__ import annotations
 
@@ -69,7 +69,7 @@ def restart_ratio(g_new, z_prev, z_new):
     return abs(float(g_new @ z_prev)) / float(g_new @ z_new)
 
 
-SAFE_ROUNDS = 40
+SAFE_ROUNDS = 16
 
 
 def safe_alpha(hier, idx, grad, d, p):
