@@ -100,8 +100,15 @@ typedef struct {
   int32_t block_prec;   /* requested mas_prec of level-0 blocks */
   int32_t coarse_prec;  /* requested mas_prec of levels >= 1 */
   int32_t hess_prec;    /* MAS_F64 or MAS_F32 element Hessian snapshot */
-  int32_t reserved;
+  int32_t deterministic; /* 1: every sum in a fixed order, so that repeated calls
+                            on the same inputs give bitwise equal results (the
+                            sums of the fast mode follow the order of atomics) */
   double prec_guard;    /* promotion threshold factor (default 0.5; 0: never promote) */
+  /* Capacities.  All device memory is allocated by mas_create; no later call
+   * allocates.  0 picks the default shown. */
+  int64_t max_contacts; /* largest base or current contact set (max(2 N, 65536)) */
+  int64_t max_tris;     /* largest triangle list of mas_constraint_set (2 N + 64) */
+  int64_t max_edges;    /* largest edge list of mas_constraint_set (3 N + 64) */
 } mas_config;
 
 /* Tetrahedral mesh, host pointers, original vertex numbering.  tets must
@@ -138,6 +145,23 @@ typedef struct {
   int32_t reserved;
 } mas_step_out;
 
+/* Counters of the last mas_woodbury_update and mas_safe_step (host copy,
+ * filled by mas_read_stats).  The classification follows Section 4.1.1:
+ * a current contact with k > 0 is new (no base entry with k > 0), rotated
+ * (its normal turned past the rotation threshold; dS = k), stiffened
+ * (dS = k - k_base > 0) or softened (dS = 0). */
+typedef struct {
+  int64_t contacts;        /* current contacts of the last mas_woodbury_update */
+  int64_t active;          /* of them with k > 0 (d < dhat) */
+  int64_t n_new, n_rotated, n_stiffened, n_softened;
+  int64_t rank_sum;        /* sum over level-0 subdomains of the kept rank r_d */
+  int32_t rank_max;        /* largest r_d */
+  int32_t safe_rounds;     /* damping rounds of the last mas_safe_step that damped a subdomain */
+  int64_t safe_left;       /* stencils still closing below 0.05 d after the last round */
+  int64_t alpha_hist[8];   /* level-0 subdomains by the last safe step alpha_d: [0] alpha = 1,
+                              [i] alpha in [2^-i, 2^(1-i)) for i = 1..6, [7] alpha < 2^-6 */
+} mas_iter_stats;
+
 /* Fills cfg with the paper's stated defaults (K = 8, 25 degrees, delta = 0.3,
  * eps_sing = 1e-12) and float64 storage. */
 void mas_default_config(mas_config* cfg);
@@ -145,7 +169,9 @@ void mas_default_config(mas_config* cfg);
 /* Creates a context: Morton order, element rest quantities (Dm^-1, volume,
  * Lame parameters from Young's modulus and Poisson's ratio, lumped masses),
  * subdomain tables.  perm_out (host, N) receives perm[new] = old.
- * Allocates all fixed-size device memory.  stream may be NULL (default). */
+ * Allocates all device memory the context will use, sized by the mesh and
+ * the capacities of cfg; no later call allocates.  stream may be NULL
+ * (default). */
 mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_stream,
                       void** ctx_out, int32_t* perm_out);
 
@@ -156,7 +182,8 @@ mas_status mas_destroy(void* ctx);
  * base contact set (copied; k = kappa b''(d), n = grad), level-0 blocks
  * S_d H_base S_d^T and Galerkin coarse blocks of every level, all inverted in
  * float64 and stored at the configured precision.  Clears the Woodbury
- * update.  A non-positive pivot sets MAS_ERR_NOT_SPD. */
+ * update.  A non-positive pivot sets MAS_ERR_NOT_SPD.  base->m must not
+ * exceed max_contacts (MAS_ERR_INVALID_ARG). */
 mas_status mas_build(void* ctx, const double* x_base, const mas_contacts* base);
 
 /* Sparse-Input Woodbury update (Section 4.1).  Classifies every current
@@ -165,19 +192,26 @@ mas_status mas_build(void* ctx, const double* x_base, const mas_contacts* base);
  * hess_vec and the subspace step, selects per level-0 subdomain the max_rank
  * candidates of largest dS (ties: smaller key first), and factors the
  * capacitance I + U_d^T B_d U_d in float64.  rank_hist (device, max_rank+1
- * int32, nullable) receives the histogram of per-subdomain ranks. */
+ * int32, nullable) receives the histogram of per-subdomain ranks.
+ * curr->m must not exceed max_contacts (MAS_ERR_INVALID_ARG).  A
+ * capacitance pivot that is not positive (rounding, in exact arithmetic the
+ * matrix is SPD) drops that column and the later ones, which rank lowest by
+ * dS: the subdomain keeps the factor of its leading columns, and the next
+ * mas_sync_status returns MAS_ERR_RANK naming the subdomain.  A non-finite
+ * distance sets MAS_ERR_NONFINITE. */
 mas_status mas_woodbury_update(void* ctx, const mas_contacts* curr, int32_t* rank_hist);
 /* (W_d = B_d U_d is kept in float64: its product with C_d^-1 cancels against
  * B_d along stiff contact directions.) */
 
 /* z = P g (device vectors, 3N, must not alias): level-0 blocks with the
  * Woodbury correction z_d = B_d g_d - W_d C_d^-1 U_d^T B_d g_d, plus
- * C_(l)^T M_(l)^-1 C_(l) g for every coarse level. */
+ * C_(l)^T M_(l)^-1 C_(l) g for every coarse level.  A non-finite entry of g
+ * sets MAS_ERR_NONFINITE. */
 mas_status mas_apply(void* ctx, const double* g, double* z);
 
 /* y = H_base v, plus U U^T v when with_update != 0 (device, 3N, no alias).
  * H_base = M + sum_e S_e^T H_e S_e + sum_{c in base} k_c n_c n_c^T frozen at
- * the last mas_build. */
+ * the last mas_build.  A non-finite entry of v sets MAS_ERR_NONFINITE. */
 mas_status hess_vec(void* ctx, const double* v, double* y, int32_t with_update);
 
 /* 2x2 subspace step (Section 4.2; supplement Section 2.4).  Inputs g, z,
@@ -190,7 +224,9 @@ mas_status pncg_subspace_step(void* ctx, const double* g, const double* z, const
                               mas_step_out* out);
 
 /* Incremental potential (Section 3.1) at x: E (device scalar) and, if g is
- * not NULL, its gradient (device, 3N).  Contacts with d <= 0 make E = +inf. */
+ * not NULL, its gradient (device, 3N).  Contacts with d <= 0 make E = +inf.
+ * In deterministic mode c->m must not exceed max_contacts when g is given
+ * (the contact terms are gathered per vertex in ascending contact order). */
 mas_status mas_energy_grad(void* ctx, const double* x, const double* x_tilde,
                            const mas_contacts* c, double* E, double* g);
 
@@ -205,12 +241,17 @@ mas_status mas_stencil_distance(void* ctx, const double* x, int64_t m, const int
  * supplement Section 3, relative displacement of the stencil's vertices):
  * a stencil closing at the rate s_c = -sum_j grad_cj . p_j > 0 allows
  * alpha_c = max(0, min(1, 0.9 d_c / s_c)); alpha_d = min(1, min over stencils
- * touching subdomain d).  Writes x_out = x + scale * alpha_{sub(v)} p_v
- * (device, 3N).  Vertices of one stencil in different subdomains may move
- * with different steps; the caller's energy check (E = +inf at d <= 0)
- * rejects trial points that close a stencil.  cand == NULL reuses the step
- * sizes of the previous call (line-search halving only changes scale).
- * alpha (device, D_0, nullable) receives the step sizes. */
+ * touching subdomain d).  Vertices of one stencil in different subdomains
+ * move with different steps: in up to 16 damping rounds, run on the device
+ * without host synchronisation (a round after one that found nothing does
+ * no work), every subdomain of a stencil whose distance would fall below
+ * 0.05 d_c under the mixed steps has its step halved.  Writes
+ * x_out = x + scale * alpha_{sub(v)} p_v (device, 3N).  A stencil still
+ * closing after the last round is left to the caller's energy check
+ * (E = +inf at d <= 0), and counted in mas_iter_stats.safe_left.
+ * cand == NULL reuses the step sizes of the previous call (line-search
+ * halving only changes scale).  alpha (device, D_0, nullable) receives the
+ * step sizes.  cand->m must not exceed max_contacts. */
 mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_contacts* cand,
                          double scale, double* alpha, double* x_out);
 
@@ -271,9 +312,12 @@ mas_status mas_contact_distances(void* ctx, const double* x, int64_t m, const in
  * (0 point-triangle, 1 edge-edge), dist float64 cap, grad float64 12cap
  * (nullable).  *count (host) receives the number of pairs found; only the
  * first min(count, cap) are written, in no fixed order (call again with a
- * larger cap when count > cap).  Synchronises the stream.  The library
- * keeps the grid tables between calls and grows them as needed (device
- * allocation).  Errors: MAS_ERR_INVALID_ARG for an id outside [0, N),
+ * larger cap when count > cap).  Synchronises the stream (it reads the
+ * largest primitive extent, which sets the cell side, and the table sizes
+ * back).  The grid tables are allocated by mas_create for max_tris and
+ * max_edges primitives with up to 8 cell entries each.  Errors:
+ * MAS_ERR_INVALID_ARG for nt > max_tris, ne > max_edges, more cell entries
+ * than the tables hold, an id outside [0, N),
  * dhat <= 0, or coordinates so large against the cell side that cell
  * indices would exceed 1e15; MAS_ERR_NONFINITE for a non-finite
  * coordinate of a listed vertex; both before any pair is written. */
@@ -284,6 +328,10 @@ mas_status mas_constraint_set(void* ctx, const double* x, double dhat, int64_t n
 /* Synchronises the stream and returns the sticky device error (and clears
  * it); msg (nullable) receives a description. */
 mas_status mas_sync_status(void* ctx, char* msg, int32_t msg_len);
+
+/* Synchronises the stream and fills *out (host) from the device counters
+ * of the last mas_woodbury_update and mas_safe_step. */
+mas_status mas_read_stats(void* ctx, mas_iter_stats* out);
 
 /* Sizes: N, T, number of levels, D_l for l < 6. */
 mas_status mas_query(void* ctx, int64_t* N, int64_t* T, int32_t* levels, int64_t* nsub /*6*/);

@@ -32,8 +32,11 @@ class MasConfig(ctypes.Structure):
         ("block_prec", ctypes.c_int32),
         ("coarse_prec", ctypes.c_int32),
         ("hess_prec", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("deterministic", ctypes.c_int32),
         ("prec_guard", ctypes.c_double),
+        ("max_contacts", ctypes.c_int64),
+        ("max_tris", ctypes.c_int64),
+        ("max_edges", ctypes.c_int64),
     ]
 
 
@@ -72,6 +75,16 @@ class MasStepOut(ctypes.Structure):
 
 STEP_FIELDS = [f for f, _ in MasStepOut._fields_]
 
+
+class MasIterStats(ctypes.Structure):
+    _fields_ = [
+        ("contacts", ctypes.c_int64), ("active", ctypes.c_int64),
+        ("n_new", ctypes.c_int64), ("n_rotated", ctypes.c_int64),
+        ("n_stiffened", ctypes.c_int64), ("n_softened", ctypes.c_int64),
+        ("rank_sum", ctypes.c_int64), ("rank_max", ctypes.c_int32), ("safe_rounds", ctypes.c_int32),
+        ("safe_left", ctypes.c_int64), ("alpha_hist", ctypes.c_int64 * 8),
+    ]
+
 TIMERS = {"apply_l0": 0, "apply": 1, "hv_tets": 2, "hess_vec": 3, "update": 4, "capacitance": 5,
           "build": 6, "energy": 7, "subspace": 8, "ccd": 9, "contact": 10, "constraint_set": 11}
 
@@ -98,6 +111,7 @@ SIGNATURES = {
     "mas_constraint_set": (_I32, [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.c_int64,
                                   _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "mas_sync_status": (_I32, [_P, ctypes.c_char_p, _I32]),
+    "mas_read_stats": (_I32, [_P, ctypes.POINTER(MasIterStats)]),
     "mas_query": (_I32, [_P, _P, _P, _P, _P]),
     "mas_get_block": (_I32, [_P, _I32, _I64, _P]),
     "mas_block_precisions": (_I32, [_P, _I32, _P]),

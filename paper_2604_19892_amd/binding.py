@@ -20,7 +20,8 @@ def _ptr(t):
 
 
 def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=None,
-                hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12, prec_guard=None):
+                hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12, prec_guard=None,
+                deterministic=False, max_contacts=0, max_tris=0, max_edges=0):
     cfg = MasConfig()
     _abi.lib().mas_default_config(ctypes.byref(cfg))
     if scene is not None:
@@ -47,6 +48,10 @@ def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=N
         cfg.cos_rot = float(cos_rot)
     if prec_guard is not None:
         cfg.prec_guard = float(prec_guard)
+    cfg.deterministic = int(bool(deterministic))
+    cfg.max_contacts = int(max_contacts)
+    cfg.max_tris = int(max_tris)
+    cfg.max_edges = int(max_edges)
     return cfg
 
 
@@ -227,6 +232,14 @@ class MasContext:
         c = cand.struct() if cand is not None else None
         check("mas_safe_step", _abi.lib().mas_safe_step(self.h, _ptr(x), _ptr(p), ctypes.byref(c) if c else None,
                                                        float(scale), _ptr(alpha), _ptr(x_out)))
+
+    def stats(self):
+        """Counters of the last Woodbury update and safe step (synchronises)."""
+        st = _abi.MasIterStats()
+        check("mas_read_stats", _abi.lib().mas_read_stats(self.h, ctypes.byref(st)))
+        out = {f: getattr(st, f) for f, _ in _abi.MasIterStats._fields_ if f != "alpha_hist"}
+        out["alpha_hist"] = list(st.alpha_hist)
+        return out
 
     def sync(self):
         buf = ctypes.create_string_buffer(256)

@@ -143,7 +143,7 @@ const char* mas_status_string(mas_status s) {
     case MAS_ERR_HIP: return "HIP runtime error";
     case MAS_ERR_NOT_SPD: return "non-positive pivot (matrix not SPD)";
     case MAS_ERR_NONFINITE: return "non-finite input";
-    case MAS_ERR_RANK: return "rank overflow";
+    case MAS_ERR_RANK: return "capacitance rank reduced (trailing update columns dropped)";
   }
   return "unknown status";
 }
@@ -157,7 +157,8 @@ mas_status mas_destroy(void* p) {
                   c->hkey, c->hval, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
-                  c->alpha, c->amark, c->err, c->diag, c->cub_tmp};
+                  c->alpha, c->alpha0, c->ahalf, c->around, c->err, c->diag, c->cls_part, c->scan_tmp,
+                  c->inc_cnt, c->inc_off, c->inc_list, c->coup};
   for (void* q : ptrs)
     if (q) hipFree(q);
   for (auto& t : c->cs) {
@@ -200,6 +201,10 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (!(cfg->prec_guard >= 0)) return MAS_ERR_INVALID_ARG;
   if (cfg->hess_prec != MAS_F64 && cfg->hess_prec != MAS_F32) return MAS_ERR_INVALID_ARG;
   if (!(cfg->dhat > 0) || !(cfg->h > 0) || !(cfg->kappa >= 0)) return MAS_ERR_INVALID_ARG;
+  if (cfg->deterministic != 0 && cfg->deterministic != 1) return MAS_ERR_INVALID_ARG;
+  if (cfg->max_contacts < 0 || cfg->max_tris < 0 || cfg->max_edges < 0) return MAS_ERR_INVALID_ARG;
+  if (cfg->max_contacts > INT32_MAX / 4 || cfg->max_tris > INT32_MAX / 8 || cfg->max_edges > INT32_MAX / 8)
+    return MAS_ERR_INVALID_ARG;
   for (int64_t t = 0; t < 4 * T; ++t)
     if (mesh->tets[t] < 0 || mesh->tets[t] >= N) return MAS_ERR_INVALID_ARG;
 
@@ -207,6 +212,9 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (!c) return MAS_ERR_OOM;
   c->s = reinterpret_cast<hipStream_t>(hip_stream);
   c->cfg = *cfg;
+  if (c->cfg.max_contacts == 0) c->cfg.max_contacts = std::max<int64_t>(2 * N, 65536);
+  if (c->cfg.max_tris == 0) c->cfg.max_tris = 2 * N + 64;
+  if (c->cfg.max_edges == 0) c->cfg.max_edges = 3 * N + 64;
   c->N = N;
   c->T = T;
   c->Tpad = (T + TILE - 1) / TILE * TILE;
@@ -403,14 +411,67 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->partials, 16 * c->n_partial_blocks));
   TRY(dalloc(&c->scal, 64));
   TRY(dalloc(&c->alpha, D0));
-  TRY(dalloc(&c->amark, D0));
+  TRY(dalloc(&c->alpha0, D0));
+  TRY(dalloc(&c->ahalf, D0));
+  TRY(dalloc(&c->around, SAFE_ROUNDS + 1));
   TRY(dalloc(&c->err, 1));
   TRY(dalloc(&c->diag, 1));
+  // contact sets: capacity max_contacts, key table twice that (power of two)
+  {
+    const int64_t cap = std::max<int64_t>(c->cfg.max_contacts, 1);
+    c->mb_cap = c->mc_cap = cap;
+    c->hcap = 1024;
+    while (c->hcap < 2 * cap) c->hcap *= 2;
+    TRY(dalloc(&c->bkey, cap));
+    TRY(dalloc(&c->hkey, c->hcap));
+    TRY(dalloc(&c->hval, c->hcap));
+    TRY(dalloc(&c->bk, cap));
+    TRY(dalloc(&c->bgrad, 12 * cap));
+    TRY(dalloc(&c->bidx, 4 * cap));
+    TRY(dalloc(&c->bu, 12 * cap));
+    TRY(dalloc(&c->bc_list, 4 * cap));
+    TRY(dalloc(&c->rc_list, 4 * cap));
+    TRY(dalloc(&c->U, 12 * cap));
+    TRY(dalloc(&c->Uidx, 4 * cap));
+    TRY(dalloc(&c->dS, cap));
+    TRY(dalloc(&c->ckey, cap));
+    TRY(dalloc(&c->cand_list, 4 * cap));
+    TRY(dalloc(&c->cls_part, 5 * ((cap + 255) / 256)));
+  }
+  // constraint-set grid tables: buckets a power of two of at least twice the
+  // primitives, up to 8 cell entries per primitive
+  {
+    const int64_t np[2] = {c->cfg.max_tris, c->cfg.max_edges};
+    for (int k = 0; k < 2; ++k) {
+      Ctx::CellTable& t = c->cs[k];
+      int64_t H = 1024;
+      while (H < 2 * np[k]) H <<= 1;
+      t.h_cap = H + 1;
+      t.e_cap = std::max<int64_t>(8 * np[k], 1);
+      TRY(dalloc(&t.cnt, t.h_cap));
+      TRY(dalloc(&t.off, t.h_cap));
+      TRY(dalloc(&t.key, t.e_cap));
+      TRY(dalloc(&t.id, t.e_cap));
+    }
+    TRY(dalloc(&c->cs_misc, 4));
+  }
+  // deterministic mode: vertex incidence lists and the per-subdomain
+  // deep-level coupling tables
+  if (c->cfg.deterministic) {
+    TRY(dalloc(&c->inc_cnt, N + 1));
+    TRY(dalloc(&c->inc_off, N + 1));
+    TRY(dalloc(&c->inc_list, 4 * std::max<int64_t>(c->cfg.max_contacts, 1)));
+    if (c->L > 2) TRY(dalloc(&c->coup, size_t(D0) * (c->L - 2) * SUB * 9));
+  }
+  // scratch of the exclusive scans: the longest scan is a bucket table (or
+  // the vertex counts of the incidence lists)
+  c->scan_cap = std::max<int64_t>({D0 + 1, c->nrange + 1, c->cs[0].h_cap, c->cs[1].h_cap, N + 1});
+  TRY(dalloc(&c->scan_tmp, scan_scratch_elems(c->scan_cap)));
   HIPCHK(hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->s));
   HIPCHK(hipMemsetAsync(c->diag, 0, sizeof(DiagRec), c->s));
   HIPCHK(hipMemsetAsync(c->rank, 0, sizeof(int32_t) * D0, c->s));
   HIPCHK(hipMemsetAsync(c->alpha, 0, sizeof(double) * D0, c->s));
-  HIPCHK(hipMemsetAsync(c->amark, 0, D0, c->s));
+  HIPCHK(hipMemsetAsync(c->around, 0, sizeof(uint32_t) * (SAFE_ROUNDS + 1), c->s));
 
   HIPCHK(hipMemcpyAsync(c->tets, tets.data(), 4 * T * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->tet_off, toff.data(), (D0 + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
@@ -454,7 +515,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     mas_destroy(c);
     return st;
   }
-  // scan temporaries for the subdomain buckets, sized once
+  // empty bucket lists until the first build
   TRY(bucket_by_subdomain(*c, 0, nullptr, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
   TRY(bucket_stencils(*c, 1, c->vrange, c->nrange, 0, nullptr, nullptr, nullptr, c->rc_cnt, c->rc_off, nullptr));
   HIPCHK(hipStreamSynchronize(c->s));
@@ -469,6 +530,7 @@ mas_status mas_build(void* p, const double* x_base, const mas_contacts* base) {
   mas_status st = valid_contacts(base);
   if (st != MAS_OK) return st;
   Ctx& c = *as_ctx(p);
+  if (base && base->m > c.mb_cap) return MAS_ERR_INVALID_ARG;
   ProfScope ps(c, MAS_T_BUILD);
   if ((st = launch_elem_hessians(c, x_base)) != MAS_OK) return st;
   if ((st = launch_base_contacts(c, base)) != MAS_OK) return st;
@@ -486,6 +548,7 @@ mas_status mas_woodbury_update(void* p, const mas_contacts* cur, int32_t* rank_h
   if (st != MAS_OK) return st;
   Ctx& c = *as_ctx(p);
   if (!c.built) return MAS_ERR_STATE;
+  if (cur && cur->m > c.mc_cap) return MAS_ERR_INVALID_ARG;
   if ((st = launch_woodbury(c, cur, rank_hist)) != MAS_OK) return st;
   c.have_update = true;
   return MAS_OK;
@@ -519,7 +582,10 @@ mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, cons
   if (!p || !x || !x_tilde || !E) return MAS_ERR_INVALID_ARG;
   mas_status st = valid_contacts(ct);
   if (st != MAS_OK) return st;
-  return launch_energy_grad(*as_ctx(p), x, x_tilde, ct, E, g);
+  Ctx& c = *as_ctx(p);
+  // the ordered gather of deterministic mode lists the contacts per vertex
+  if (c.cfg.deterministic && g && ct && ct->m > c.cfg.max_contacts) return MAS_ERR_INVALID_ARG;
+  return launch_energy_grad(c, x, x_tilde, ct, E, g);
 }
 
 mas_status mas_inertial_target(void* p, const double* x_t, const double* v_t, double* x_tilde) {
@@ -587,7 +653,7 @@ mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
     else if (bits & ERRB_INDEX) st = MAS_ERR_INVALID_ARG;
   }
   if (msg && msg_len > 0) {
-    static const char* src[] = {"?", "level-0 block", "coarse block", "capacitance"};
+    static const char* src[] = {"?", "level-0 block", "coarse block", "capacitance (columns from this step on dropped)"};
     if (st == MAS_ERR_HIP)
       std::snprintf(msg, msg_len, "%s: %s", mas_status_string(st), hipGetErrorString(e));
     else if (dg.flag)
@@ -598,6 +664,52 @@ mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
       std::snprintf(msg, msg_len, "%s", mas_status_string(st));
   }
   return st;
+}
+
+mas_status mas_read_stats(void* p, mas_iter_stats* out) {
+  if (!p || !out) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  std::memset(out, 0, sizeof(*out));
+  HIPCHK(hipStreamSynchronize(c.s));
+  const int64_t D0 = c.lv[0].nsub;
+  out->contacts = c.have_update ? c.mc : 0;
+  if (c.have_update && c.cls_blocks > 0) {
+    std::vector<int32_t> part(5 * c.cls_blocks);
+    HIPCHK(hipMemcpy(part.data(), c.cls_part, part.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t b = 0; b < c.cls_blocks; ++b) {
+      out->active += part[5 * b];
+      out->n_new += part[5 * b + 1];
+      out->n_rotated += part[5 * b + 2];
+      out->n_stiffened += part[5 * b + 3];
+      out->n_softened += part[5 * b + 4];
+    }
+  }
+  if (c.have_update && c.K > 0) {
+    std::vector<int32_t> rk(D0);
+    HIPCHK(hipMemcpy(rk.data(), c.rank, D0 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int32_t r : rk) {
+      out->rank_sum += r;
+      out->rank_max = std::max(out->rank_max, r);
+    }
+  }
+  uint32_t rounds[SAFE_ROUNDS + 1];
+  HIPCHK(hipMemcpy(rounds, c.around, sizeof(rounds), hipMemcpyDeviceToHost));
+  for (int r = 0; r < SAFE_ROUNDS; ++r) out->safe_rounds += rounds[r] > 0;
+  out->safe_left = rounds[SAFE_ROUNDS];
+  std::vector<double> al(D0);
+  HIPCHK(hipMemcpy(al.data(), c.alpha, D0 * sizeof(double), hipMemcpyDeviceToHost));
+  for (double a : al) {
+    int bin = 7;
+    if (a >= 1.0) bin = 0;
+    else
+      for (int i = 1; i <= 6; ++i)
+        if (a >= std::ldexp(1.0, -i)) {
+          bin = i;
+          break;
+        }
+    out->alpha_hist[bin]++;
+  }
+  return MAS_OK;
 }
 
 mas_status mas_query(void* p, int64_t* N, int64_t* T, int32_t* levels, int64_t* nsub) {

@@ -16,7 +16,7 @@ constexpr int BD = 96;                  // block dimension (3 DOFs x 32)
 constexpr int PK = BD * (BD + 1) / 2;   // packed lower-triangular entries (4656)
 constexpr int MAXL = 6;                 // maximum MAS levels
 constexpr int MAXK = 32;                // maximum Woodbury rank per subdomain
-constexpr int SAFE_ROUNDS = 40;         // safe-step repair rounds
+constexpr int SAFE_ROUNDS = 16;         // safe-step damping rounds (device side, no host sync)
 constexpr int EH = 54;                  // per-tet snapshot: 45 (9x9 packed) + 9 (Dm^-1)
 constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
 // Vertex ranges of the owner-computes products: range r owns the vertices
@@ -352,12 +352,13 @@ struct Ctx {
   int32_t* t_home = nullptr;   // T: range entry holding each tet's home copy (the block assembly reads it)
   bool built = false;
 
-  // base contact set
+  // base contact set (capacity cfg.max_contacts, allocated at create)
   int64_t mb = 0, mb_cap = 0;
   uint64_t* bkey = nullptr;        // mb, input order
   uint64_t* hkey = nullptr;        // hcap: open-addressing table of the base keys (HKEY_EMPTY: free)
   int32_t* hval = nullptr;         // hcap: base index of each stored key
-  int64_t hcap = 0;                // power of two, at least twice the base capacity
+  int64_t hcap = 0;                // allocated slots: a power of two, at least twice max_contacts
+  int64_t hsize = 1024;            // slots in use: a power of two, at least twice the base contacts
   double* bk = nullptr;            // mb stiffness
   double* bgrad = nullptr;         // 12 mb
   int32_t* bidx = nullptr;         // 4 mb
@@ -370,6 +371,7 @@ struct Ctx {
   int32_t* rc_list = nullptr;      // 4 mb
 
   // current update (untruncated U) and the localized Woodbury data
+  // (capacity cfg.max_contacts)
   int64_t mc = 0, mc_cap = 0;
   double* U = nullptr;             // 12 mc
   int32_t* Uidx = nullptr;         // 4 mc
@@ -389,15 +391,27 @@ struct Ctx {
   double* partials = nullptr;      // reductions
   int n_partial_blocks = 1024;
   double* scal = nullptr;          // small device scalars (mu, nu, ...)
-  double* alpha = nullptr;         // D0
-  uint8_t* amark = nullptr;        // D0, subdomains marked by the safe-step check
+  double* alpha = nullptr;         // D0, step sizes of the last safe step
+  double* alpha0 = nullptr;        // D0, step sizes before damping
+  uint64_t* ahalf = nullptr;       // D0, bit r: subdomain halved in damping round r
+  uint32_t* around = nullptr;      // SAFE_ROUNDS violation counts of the damping rounds
   uint32_t* err = nullptr;         // sticky error bits
   DiagRec* diag = nullptr;         // first failure record
-  void* cub_tmp = nullptr;
-  size_t cub_bytes = 0;
+  mas_iter_stats* stats = nullptr; // per-iteration counters (device)
+  // deterministic mode: vertex incidence lists of a stencil set (for
+  // each vertex its (stencil, slot) pairs 4 c + j in ascending order) and
+  // the deep-level coupling blocks of every level-0 subdomain
+  int32_t* inc_cnt = nullptr;      // N + 1 counts, then fill cursors
+  int32_t* inc_off = nullptr;      // N + 1
+  int32_t* inc_list = nullptr;     // 4 max_contacts
+  double* coup = nullptr;          // D0 x (L - 2) x 32 x 9 (levels >= 2), when L > 2
+  int32_t* cls_part = nullptr;     // branch counts of the classification, 5 per workgroup
+  int64_t cls_blocks = 0;          // workgroups of the last classification
+  int32_t* scan_tmp = nullptr;     // block sums of the exclusive scans
+  int64_t scan_cap = 0;            // longest scan the scratch serves
 
   // broad phase of the contact set: one spatial hash table per primitive
-  // kind (triangles, edges), grown on demand
+  // kind (triangles, edges), sized at create for cfg.max_tris / max_edges
   struct CellTable {
     int32_t* cnt = nullptr;  // H + 1 bucket counts, then fill cursors
     int32_t* off = nullptr;  // H + 1 bucket offsets
@@ -461,6 +475,60 @@ __device__ __forceinline__ void wave_min_pos(long long key, double* addr, double
     const double m = wave_min(mine ? val : INFINITY);
     if (lane == leader) atomic_min_pos(addr, m);
     if (mine) pending = false;
+  }
+}
+
+// ------------------------------------------------------ deterministic sums
+// Order-independent accumulation (deterministic mode).  A sum whose terms
+// arrive through atomics in no fixed order is taken in two passes over the
+// same terms.  Pass 0 records per destination entry the largest |term| (the
+// bits of a non-negative double order like its value) and the number of
+// terms; from these the entry's quantum 2^e is the power of two with
+// max * count < 2^(62 + e), so every partial sum fits an int64.  Pass 1 adds
+// each term rounded once to a multiple of 2^e, as an integer: integer
+// addition is associative, so the result is the same whatever order the
+// atomics take.  The error of an entry is at most count^2 * max * 2^-62, no
+// more than float64 accumulation's own worst case (count^2 * max * 2^-53
+// relative to the partial sums).  An entry that saw a non-finite term
+// reads back as NaN.
+constexpr int FX_NONFINITE = -100000;  // exponent marker of an entry with a non-finite term
+
+__device__ __forceinline__ void fx_note(double* slot, int* cnt, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(slot), (unsigned long long)__double_as_longlong(fabs(v)));
+  atomicAdd(cnt, 1);
+}
+// after pass 0: the entry's exponent (stored over its count); the slot is
+// cleared to an integer zero
+__device__ __forceinline__ void fx_mid(double* slot, int* cnt) {
+  const unsigned long long bits = *reinterpret_cast<unsigned long long*>(slot);
+  const double mx = __longlong_as_double((long long)bits);
+  int e = 0;
+  if (!isfinite(mx)) {
+    e = FX_NONFINITE;
+  } else if (mx > 0.0) {
+    frexp(mx * double(*cnt), &e);  // mx * cnt < 2^e
+    e -= 62;
+  }
+  *cnt = e;
+  *reinterpret_cast<long long*>(slot) = 0;
+}
+__device__ __forceinline__ void fx_add(double* slot, const int* ex, double v) {
+  if (*ex == FX_NONFINITE) return;
+  atomicAdd(reinterpret_cast<unsigned long long*>(slot), (unsigned long long)llrint(ldexp(v, -*ex)));
+}
+__device__ __forceinline__ double fx_get(const double* slot, const int* ex) {
+  if (*ex == FX_NONFINITE) return NAN;
+  return ldexp(double(*reinterpret_cast<const long long*>(slot)), *ex);
+}
+// one term into an LDS accumulator: plain float atomics (fast mode) or the
+// pass of the two-pass fixed-point sum (DET)
+template <bool DET>
+__device__ __forceinline__ void acc_term(double* win, int* aux, int e, double v, int pass) {
+  if constexpr (!DET) {
+    atomicAdd(&win[e], v);
+  } else {
+    if (pass == 0) fx_note(&win[e], &aux[e], v);
+    else fx_add(&win[e], &aux[e], v);
   }
 }
 

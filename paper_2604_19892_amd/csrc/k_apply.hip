@@ -189,6 +189,7 @@ struct FineArgs {
   const double* Lcap;
   int L;
   const double* c[MAXL];
+  uint32_t* err;
 };
 
 // One workgroup per level-0 subdomain d: z_d = B_d g_d, minus the Woodbury
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(NTILE, WIDE ? 4 : 5) void k_apply_l0(FineArgs fa) {
   double xv = 0.0, corr = 0.0;
   if (t < BD && v < fa.N) {
     xv = fa.g[BD * d + t];
+    if (!isfinite(xv)) atomicOr(fa.err, ERRB_NONFINITE);
 #pragma unroll
     for (int l = 1; l < MAXL; ++l)
       if (l < fa.L) corr += fa.c[l][3 * (v >> (5 * l)) + t % 3];
@@ -304,6 +306,7 @@ mas_status launch_apply(Ctx& c, const double* g, double* z) {
   fa.Lcap = c.Lcap;
   fa.L = c.L;
   for (int l = 1; l < c.L; ++l) fa.c[l] = c.lv[l].c;
+  fa.err = c.err;
   prof_begin(c, MAS_T_APPLY_L0);
   const int K = std::max(c.K, 1);
   const size_t wlds = sizeof(double) * size_t(K * (K + 1) / 2 + 2 * K + 1) + sizeof(SlotCol) * size_t(K);

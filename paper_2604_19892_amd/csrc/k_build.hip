@@ -130,37 +130,23 @@ __global__ void k_hash_insert(int64_t m, const uint64_t* key, const double* bk, 
   }
 }
 
-static mas_status grow_base(Ctx& c, int64_t m) {
-  if (m <= c.mb_cap) return MAS_OK;
-  int64_t cap = m + m / 4 + 1024;
-  hipFree(c.bkey); hipFree(c.hkey); hipFree(c.hval);
-  hipFree(c.bk); hipFree(c.bgrad); hipFree(c.bidx); hipFree(c.bu); hipFree(c.bc_list); hipFree(c.rc_list);
-  int64_t hcap = 1024;
-  while (hcap < 2 * cap) hcap *= 2;
-  bool ok = hipMalloc(&c.bkey, 8 * cap) == hipSuccess && hipMalloc(&c.hkey, 8 * hcap) == hipSuccess &&
-            hipMalloc(&c.hval, 4 * hcap) == hipSuccess &&
-            hipMalloc(&c.bk, 8 * cap) == hipSuccess && hipMalloc(&c.bgrad, 96 * cap) == hipSuccess &&
-            hipMalloc(&c.bidx, 16 * cap) == hipSuccess && hipMalloc(&c.bu, 96 * cap) == hipSuccess &&
-            hipMalloc(&c.bc_list, 16 * cap) == hipSuccess && hipMalloc(&c.rc_list, 16 * cap) == hipSuccess;
-  if (!ok) return MAS_ERR_OOM;
-  c.mb_cap = cap;
-  c.hcap = hcap;
-  return MAS_OK;
-}
-
 mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
   int64_t m = b ? b->m : 0;
-  mas_status st = grow_base(c, m > 0 ? m : 1);
-  if (st != MAS_OK) return st;
+  if (m > c.mb_cap) return MAS_ERR_INVALID_ARG;  // checked by mas_build before any launch
   c.mb = m;
+  // the part of the key table in use: a power of two of at least twice the
+  // base contacts (the table was allocated for max_contacts)
+  c.hsize = 1024;
+  while (c.hsize < 2 * m) c.hsize *= 2;
+  mas_status st = MAS_OK;
   if (m > 0) {
     int bs = 256;
     k_base_copy<<<dim3((m + bs - 1) / bs), dim3(bs), 0, c.s>>>(
         m, b->key, b->idx, b->d, b->grad, c.cfg.kappa, c.cfg.dhat, c.bkey, c.bk, c.bgrad,
         c.bidx, c.bu, c.err);
-    k_fill_u64<<<dim3(std::min<int64_t>(1024, (c.hcap + 255) / 256)), dim3(256), 0, c.s>>>(c.hkey, c.hcap,
-                                                                                            HKEY_EMPTY);
-    k_hash_insert<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(m, c.bkey, c.bk, c.hkey, c.hval, c.hcap - 1);
+    k_fill_u64<<<dim3(std::min<int64_t>(1024, (c.hsize + 255) / 256)), dim3(256), 0, c.s>>>(c.hkey, c.hsize,
+                                                                                             HKEY_EMPTY);
+    k_hash_insert<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(m, c.bkey, c.bk, c.hkey, c.hval, c.hsize - 1);
     HIPCHK(hipGetLastError());
   }
   st = bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
@@ -179,22 +165,24 @@ __device__ __forceinline__ double rcp_nr(double x) {
 }
 
 // place a 3x3 block (pair of local nodes li, lj) into the packed lower matrix
-__device__ inline void add_block_lds(double* A, int li, int lj, bool diag, const double b[3][3]) {
+template <bool DET>
+__device__ inline void add_block_lds(double* A, int* Acnt, int pass, int li, int lj, bool diag,
+                                     const double b[3][3]) {
   if (diag) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int q = 0; q <= a; ++q) atomicAdd(&A[pk(3 * li + a, 3 * li + q)], b[a][q]);
+      for (int q = 0; q <= a; ++q) acc_term<DET>(A, Acnt, pk(3 * li + a, 3 * li + q), b[a][q], pass);
   } else if (li > lj) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * li + a, 3 * lj + q)], b[a][q]);
+      for (int q = 0; q < 3; ++q) acc_term<DET>(A, Acnt, pk(3 * li + a, 3 * lj + q), b[a][q], pass);
   } else {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) atomicAdd(&A[pk(3 * lj + q, 3 * li + a)], b[a][q]);
+      for (int q = 0; q < 3; ++q) acc_term<DET>(A, Acnt, pk(3 * lj + q, 3 * li + a), b[a][q], pass);
   }
 }
 
@@ -229,6 +217,7 @@ struct L0Args {
   const int32_t* bc_off;
   const int32_t* bc_list;
   double* acc[MAXL];
+  double* coup;  // deterministic mode: deep-level coupling tables per subdomain
 };
 
 // Where the pair (vi, vj) of a stencil touching subdomain d goes: 0 = level 0
@@ -250,30 +239,46 @@ __device__ __forceinline__ int route_pair(int64_t d, int L, int vi, int vj, int*
   return -1;
 }
 
-__device__ __forceinline__ void add_coupling(double* T, int l, int nb, bool flip, const double (&b)[3][3]) {
-  double* e = T + ((l - 1) * SUB + nb) * 9;
+template <bool DET>
+__device__ __forceinline__ void add_coupling(double* T, int* Tcnt, int pass, int l, int nb, bool flip,
+                                             const double (&b)[3][3]) {
+  const int e = ((l - 1) * SUB + nb) * 9;
 #pragma unroll
   for (int x = 0; x < 3; ++x)
 #pragma unroll
-    for (int y = 0; y < 3; ++y) atomicAdd(&e[3 * x + y], flip ? b[y][x] : b[x][y]);
+    for (int y = 0; y < 3; ++y) acc_term<DET>(T, Tcnt, e + 3 * x + y, flip ? b[y][x] : b[x][y], pass);
 }
 
 constexpr int L0_THREADS = 128;
 
-template <typename TH>
+// DET: the sums of A and of the coupling tables are taken with the two-pass
+// fixed-point accumulation (so that they do not depend on the order of the
+// LDS atomics), and the deep-level tables go to a.coup, to be summed over
+// the subdomains in ascending order by k_coup_reduce.
+template <typename TH, bool DET>
 __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   __shared__ double A[PK];
-  extern __shared__ double T[];  // (L - 1) x 32 node blocks of 9
+  extern __shared__ double T[];  // (L - 1) x 32 node blocks of 9; DET: then the counts of A and T
   const int64_t d = xcd_block(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int nT = (a.L - 1) * SUB * 9;
+  int* Acnt = DET ? reinterpret_cast<int*>(T + nT) : nullptr;
+  int* Tcnt = DET ? Acnt + PK : nullptr;
   for (int e = tid; e < PK; e += blockDim.x) A[e] = 0.0;
   for (int e = tid; e < nT; e += blockDim.x) T[e] = 0.0;
+  if (DET) {
+    for (int e = tid; e < PK; e += blockDim.x) Acnt[e] = 0;
+    for (int e = tid; e < nT; e += blockDim.x) Tcnt[e] = 0;
+  }
   __syncthreads();
-  // the lumped mass goes in before any tet or stencil adds to the diagonal
+  for (int pass = DET ? 0 : 1; pass < 2; ++pass) {
+  // the lumped mass (identity on padded rows) goes in before any tet or
+  // stencil adds to the diagonal
   if (tid < BD) {
     int64_t v = SUB * d + tid / 3;
-    A[pk(tid, tid)] = (v < a.N) ? a.mass[v] : 1.0;
+    const double mv = (v < a.N) ? a.mass[v] : 1.0;
+    if (DET) acc_term<DET>(A, Acnt, pk(tid, tid), mv, pass);
+    else A[pk(tid, tid)] = mv;
   }
   __syncthreads();
   const int t0 = a.tet_off[d], t1 = a.tet_off[d + 1];
@@ -325,8 +330,8 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
 #pragma unroll
           for (int y = 0; y < 3; ++y)
             blk[x][y] = coef[i][0] * G[x][y] + coef[i][1] * G[3 + x][y] + coef[i][2] * G[6 + x][y];
-        if (dest[i][j] == 0) add_block_lds(A, v[i] & 31, v[j] & 31, i == j, blk);
-        else add_coupling(T, dest[i][j], nbr[i][j], flip[i][j], blk);
+        if (dest[i][j] == 0) add_block_lds<DET>(A, Acnt, pass, v[i] & 31, v[j] & 31, i == j, blk);
+        else add_coupling<DET>(T, Tcnt, pass, dest[i][j], nbr[i][j], flip[i][j], blk);
       }
     }
   }
@@ -353,14 +358,30 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
         for (int x = 0; x < 3; ++x)
 #pragma unroll
           for (int y = 0; y < 3; ++y) blk[x][y] = k * n[3 * i + x] * n[3 * j + y];
-        if (dest == 0) add_block_lds(A, v[i] & 31, v[j] & 31, i == j, blk);
-        else add_coupling(T, dest, nbr, flip, blk);
+        if (dest == 0) add_block_lds<DET>(A, Acnt, pass, v[i] & 31, v[j] & 31, i == j, blk);
+        else add_coupling<DET>(T, Tcnt, pass, dest, nbr, flip, blk);
       }
     }
   }
   __syncthreads();
+  if (DET) {
+    if (pass == 0) {
+      for (int e = tid; e < PK; e += blockDim.x) fx_mid(&A[e], &Acnt[e]);
+      for (int e = tid; e < nT; e += blockDim.x) fx_mid(&T[e], &Tcnt[e]);
+    } else {
+      for (int e = tid; e < PK; e += blockDim.x) A[e] = fx_get(&A[e], &Acnt[e]);
+      for (int e = tid; e < nT; e += blockDim.x) T[e] = fx_get(&T[e], &Tcnt[e]);
+    }
+    __syncthreads();
+  }
+  }  // passes
   double* out = a.acc[0] + d * PK;
   for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
+  if (DET && a.L > 2) {
+    // the deep-level tables of this subdomain, zeros included
+    double* cp = a.coup + d * int64_t(nT - SUB * 9);
+    for (int q = SUB * 9 + tid; q < nT; q += blockDim.x) cp[q - SUB * 9] = T[q];
+  }
   if (a.L > 1) {
     // level 1: the blocks (d, u), u < d, of row d of subdomain d >> 5
     const int ld = int(d & 31);
@@ -370,7 +391,7 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
       o1[pk(3 * ld + x, 3 * u + y)] = T[u * 9 + 3 * x + y];
     }
     // deeper levels: only the tables this subdomain touched
-    for (int q = SUB * 9 + tid; q < nT; q += blockDim.x) {
+    for (int q = SUB * 9 + tid; !DET && q < nT; q += blockDim.x) {
       const double val = T[q];
       if (val == 0.0) continue;
       const int l = q / (SUB * 9) + 1, u = (q / 9) % SUB, x = (q % 9) / 3, y = q % 3;
@@ -640,6 +661,27 @@ __global__ void k_zero(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
+// Deterministic mode: the coupling blocks of level l >= 2 summed over the
+// level-0 subdomains in ascending order.  Row node na of level-l subdomain
+// P is the level-(l-1) subdomain s = 32 P + na, whose level-0 subdomains
+// d in [s 32^(l-1), (s + 1) 32^(l-1)) each wrote their table for it; only
+// the blocks (na, u < na) of the lower triangle exist.
+__global__ void k_coup_reduce(int l, int L, int64_t D0, int64_t nsub_prev, const double* coup, double* acc_l) {
+  const int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t s = q / (SUB * 9);
+  if (s >= nsub_prev) return;
+  const int r = int(q % (SUB * 9));
+  const int u = r / 9, x = (r % 9) / 3, y = r % 3;
+  const int na = int(s & 31);
+  if (u >= na) return;
+  const int sh = 5 * (l - 1);
+  const int64_t d0 = s << sh, d1 = min<int64_t>(D0, (s + 1) << sh);
+  const int64_t stride = int64_t(L - 2) * SUB * 9;
+  double sum = 0.0;
+  for (int64_t dd = d0; dd < d1; ++dd) sum += coup[dd * stride + (l - 2) * SUB * 9 + r];
+  acc_l[(s >> 5) * PK + pk(3 * na + x, 3 * u + y)] = sum;
+}
+
 mas_status launch_level0_build(Ctx& c) {
   Level& L0 = c.lv[0];
   for (int l = 2; l < c.L; ++l) k_zero<<<dim3(256), dim3(256), 0, c.s>>>(c.lv[l].acc, c.lv[l].nsub * PK);
@@ -659,11 +701,26 @@ mas_status launch_level0_build(Ctx& c) {
   a.bc_off = c.bc_off;
   a.bc_list = c.bc_list;
   for (int l = 0; l < c.L; ++l) a.acc[l] = c.lv[l].acc;
-  const size_t lds = sizeof(double) * size_t(std::max(c.L - 1, 1)) * SUB * 9;
-  if (c.hr32)
-    k_assemble_l0<float><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
-  else
-    k_assemble_l0<double><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+  a.coup = c.coup;
+  const size_t nT = size_t(std::max(c.L - 1, 1)) * SUB * 9;
+  if (c.cfg.deterministic) {
+    const size_t lds = sizeof(double) * nT + sizeof(int) * (PK + nT);
+    if (c.hr32)
+      k_assemble_l0<float, true><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+    else
+      k_assemble_l0<double, true><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+    for (int l = 2; l < c.L; ++l) {
+      const int64_t n = c.lv[l - 1].nsub * int64_t(SUB * 9);
+      k_coup_reduce<<<dim3((n + 255) / 256), dim3(256), 0, c.s>>>(l, c.L, L0.nsub, c.lv[l - 1].nsub, c.coup,
+                                                                   c.lv[l].acc);
+    }
+  } else {
+    const size_t lds = sizeof(double) * nT;
+    if (c.hr32)
+      k_assemble_l0<float, false><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+    else
+      k_assemble_l0<double, false><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
+  }
   launch_invert(c, 0);
   HIPCHK(hipGetLastError());
   return MAS_OK;

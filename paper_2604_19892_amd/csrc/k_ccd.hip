@@ -85,11 +85,6 @@ __device__ __forceinline__ double dot3(const double* u, const double* v) {
 
 }  // namespace
 
-__global__ void k_fill_f64(double* p, int64_t n, double v) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = v;
-}
-
 __global__ __launch_bounds__(256) void k_ccd_pairs(int64_t N, int64_t m, const int32_t* pairs, const uint8_t* kind,
                                                    const double* dist, const double* x, const double* p,
                                                    double* alpha_pair, double* alpha, uint32_t* err) {
@@ -171,7 +166,7 @@ mas_status launch_ccd(Ctx& c, const double* x, const double* p, int64_t m, const
                       const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha) {
   ProfScope ps(c, MAS_T_CCD);
   const int64_t D = c.lv[0].nsub;
-  if (alpha) k_fill_f64<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(alpha, D, 1.0);
+  if (alpha) fill_f64(c, alpha, D, 1.0);
   if (m > 0)
     k_ccd_pairs<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(c.N, m, pairs, kind, dist, x, p, alpha_pair,
                                                                 alpha, c.err);

@@ -539,24 +539,10 @@ __global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* 
   }
 }
 
-static mas_status grow_table(Ctx::CellTable& t, int64_t H, int64_t E) {
-  if (H + 1 > t.h_cap) {
-    if (t.cnt) HIPCHK(hipFree(t.cnt));
-    if (t.off) HIPCHK(hipFree(t.off));
-    t.cnt = nullptr, t.off = nullptr, t.h_cap = 0;
-    if (hipMalloc(&t.cnt, sizeof(int32_t) * (H + 1)) != hipSuccess) return MAS_ERR_OOM;
-    if (hipMalloc(&t.off, sizeof(int32_t) * (H + 1)) != hipSuccess) return MAS_ERR_OOM;
-    t.h_cap = H + 1;
-  }
-  if (E > t.e_cap) {
-    if (t.key) HIPCHK(hipFree(t.key));
-    if (t.id) HIPCHK(hipFree(t.id));
-    t.key = nullptr, t.id = nullptr, t.e_cap = 0;
-    if (hipMalloc(&t.key, sizeof(uint64_t) * E) != hipSuccess) return MAS_ERR_OOM;
-    if (hipMalloc(&t.id, sizeof(int32_t) * E) != hipSuccess) return MAS_ERR_OOM;
-    t.e_cap = E;
-  }
-  return MAS_OK;
+// the tables were allocated by mas_create; a request beyond them is an
+// argument error
+static mas_status check_table(const Ctx::CellTable& t, int64_t H, int64_t E) {
+  return (H + 1 > t.h_cap || E > t.e_cap) ? MAS_ERR_INVALID_ARG : MAS_OK;
 }
 
 static int64_t pow2_at_least(int64_t n) {
@@ -570,7 +556,7 @@ mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t n
                                  uint8_t* kind, double* dist, double* grad, int64_t* count) {
   ProfScope ps(c, MAS_T_CSET);
   *count = 0;
-  if (!c.cs_misc && hipMalloc(&c.cs_misc, 4 * sizeof(unsigned long long)) != hipSuccess) return MAS_ERR_OOM;
+  if (nt > c.cfg.max_tris || ne > c.cfg.max_edges) return MAS_ERR_INVALID_ARG;
   HIPCHK(hipMemsetAsync(c.cs_misc, 0, 4 * sizeof(unsigned long long), c.s));
   if (nt + ne == 0) return MAS_OK;
   const int64_t prep_grid = std::min<int64_t>((nt + ne + nv + 255) / 256, int64_t(c.n_cu) * 8);
@@ -592,7 +578,7 @@ mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t n
   int32_t total[2] = {0, 0};
   for (int k = 0; k < 2; ++k) {
     H[k] = pow2_at_least(2 * n[k]);
-    mas_status st = grow_table(c.cs[k], H[k], 0);
+    mas_status st = check_table(c.cs[k], H[k], 0);
     if (st != MAS_OK) return st;
     HIPCHK(hipMemsetAsync(c.cs[k].cnt, 0, sizeof(int32_t) * (H[k] + 1), c.s));
     if (n[k] == 0) continue;
@@ -611,7 +597,7 @@ mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t n
   for (int k = 0; k < 2; ++k) {
     if (n[k] == 0) continue;
     if (total[k] < 0) return MAS_ERR_INVALID_ARG;  // more than 2^31 cell entries
-    mas_status st = grow_table(c.cs[k], H[k], std::max<int64_t>(total[k], 1));
+    mas_status st = check_table(c.cs[k], H[k], std::max<int64_t>(total[k], 1));
     if (st != MAS_OK) return st;
     HIPCHK(hipMemcpyAsync(c.cs[k].cnt, c.cs[k].off, sizeof(int32_t) * H[k], hipMemcpyDeviceToDevice, c.s));
     const dim3 g((n[k] + 255) / 256);

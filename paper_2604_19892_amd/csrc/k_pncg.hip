@@ -42,13 +42,17 @@ __device__ inline void block_reduce_store(double (&v)[NV], double* out, int nblk
 // range in a fixed order (part rows 0 and 1, one slot per range).  The
 // range's own part of x is staged in LDS and read from there by every
 // entry; one 1024-thread workgroup per compute unit (two 48 KB LDS arrays).
+// DET: the gradient rows are summed with the two-pass fixed-point
+// accumulation (the element stresses are evaluated twice).
 constexpr int EGT = 1024;
+template <bool DET>
 __global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t* rbeg, const int32_t* rl_t,
                                                   const int32_t* rl_tv, const double* rl_geo, const int32_t* rt_off,
                                                   const double* mass, const double* x, const double* xt, double h2,
                                                   double* g, double* part, int nblk, uint32_t* ctr) {
   __shared__ double win[3 * RANGE_MAX];
   __shared__ double xs[3 * RANGE_MAX];
+  __shared__ int aux[DET ? 3 * RANGE_MAX : 1];
   __shared__ double red[2][EGT / 64];
   __shared__ int64_t cur;
   const bool grad = g != nullptr;
@@ -67,6 +71,7 @@ __global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t*
     const int v0 = rbeg[r], nv = rbeg[r + 1] - v0;
     for (int q = threadIdx.x; q < 3 * nv; q += EGT) {
       win[q] = 0.0;
+      if (DET) aux[q] = 0;
       xs[q] = x[3 * int64_t(v0) + q];
     }
     for (int lv = threadIdx.x; lv < nv; lv += EGT) {
@@ -79,6 +84,7 @@ __global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t*
     }
     __syncthreads();
     const int t0 = rt_off[r], t1 = rt_off[r + 1];
+    for (int pass = (DET && grad) ? 0 : 1; pass < 2; ++pass) {
     for (int w = t0 + threadIdx.x; w < t1; w += EGT) {
       const int4 tv = reinterpret_cast<const int4*>(rl_tv)[w];
       const int vi[4] = {tv.x, tv.y, tv.z, tv.w};
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t*
       double F[3][3];
       def_grad(xe, gm, F);
       const double s = h2 * gm[9];
-      if (own_e) e[1] += s * snh_energy(F, gm[10], gm[11]);
+      if (own_e && pass == 1) e[1] += s * snh_energy(F, gm[10], gm[11]);
       if (touch[0] || touch[1] || touch[2] || touch[3]) {
         double P[3][3];
         snh_stress(F, gm[10], gm[11], P);
@@ -117,15 +123,24 @@ __global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t*
             for (int b = 0; b < 3; ++b) acc += P[a][b] * gm[3 * cc + b];
             acc *= s;
             f0[a] -= acc;
-            if (touch[cc + 1]) atomicAdd(&win[3 * (vi[cc + 1] - v0) + a], acc);
+            if (touch[cc + 1]) acc_term<DET>(win, aux, 3 * (vi[cc + 1] - v0) + a, acc, pass);
           }
         }
         if (touch[0]) {
 #pragma unroll
-          for (int a = 0; a < 3; ++a) atomicAdd(&win[3 * (vi[0] - v0) + a], f0[a]);
+          for (int a = 0; a < 3; ++a) acc_term<DET>(win, aux, 3 * (vi[0] - v0) + a, f0[a], pass);
         }
       }
     }
+    if (DET && grad) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < 3 * nv; q += EGT) {
+        if (pass == 0) fx_mid(&win[q], &aux[q]);
+        else win[q] = fx_get(&win[q], &aux[q]);
+      }
+      __syncthreads();
+    }
+    }  // passes
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const double t = wave_sum(e[q]);
@@ -246,21 +261,57 @@ __global__ __launch_bounds__(RB) void k_eg_finalize(const double* part, int nblk
   if (threadIdx.x == 0) *E = tot[3] > 0 ? INFINITY : (tot[0] + tot[1]) + tot[2];
 }
 
+// Deterministic mode: g[3 v + a] += kappa b'(d_c) grad_c[3 j + a] over the
+// incidences (c, j) of vertex v in ascending order (0 < d_c < dhat).
+__global__ __launch_bounds__(256) void k_eg_contacts_gather(int64_t N, const int32_t* off, const int32_t* list,
+                                                            const double* d, const double* grad, double kappa,
+                                                            double dhat, double* g) {
+  const int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (v >= N) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int q = off[v]; q < off[v + 1]; ++q) {
+    const int64_t slot = list[q];
+    const int64_t ci = slot >> 2;
+    const double di = d[ci];
+    if (!(di > 0.0) || di >= dhat) continue;
+    double b, b1, b2;
+    barrier3(di, dhat, &b, &b1, &b2);
+    const double s = kappa * b1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a] += s * grad[12 * ci + 3 * (slot & 3) + a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g[3 * v + a] += acc[a];
+}
+
 mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const mas_contacts* ct,
                               double* E, double* g) {
   ProfScope ps(c, MAS_T_ENERGY);
   const int nb = c.n_partial_blocks;
   double* part = c.partials;  // [0]: inertia [1]: elastic [2]: barrier [3]: infeasible count
+  const bool det = c.cfg.deterministic != 0;
   k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr + 1, 0u);
-  k_eg_range<<<dim3(std::min<int64_t>(c.nrange, int64_t(c.n_cu))), dim3(EGT), 0, c.s>>>(
-      c.nrange, c.rbeg, c.rl_t, c.rl_tv, c.rl_geo, c.rt_off, c.mass, x, xt, c.cfg.h * c.cfg.h, g, part, nb, c.ctr + 1);
+  const dim3 gr(std::min<int64_t>(c.nrange, int64_t(c.n_cu)));
+  if (det)
+    k_eg_range<true><<<gr, dim3(EGT), 0, c.s>>>(c.nrange, c.rbeg, c.rl_t, c.rl_tv, c.rl_geo, c.rt_off, c.mass, x, xt,
+                                                c.cfg.h * c.cfg.h, g, part, nb, c.ctr + 1);
+  else
+    k_eg_range<false><<<gr, dim3(EGT), 0, c.s>>>(c.nrange, c.rbeg, c.rl_t, c.rl_tv, c.rl_geo, c.rt_off, c.mass, x,
+                                                 xt, c.cfg.h * c.cfg.h, g, part, nb, c.ctr + 1);
   int64_t m = ct ? ct->m : 0;
   if (m > 0) {
-    // writes part[2*nb..] (energy) and part[3*nb..] (infeasible count)
+    // writes part[2*nb..] (energy) and part[3*nb..] (infeasible count); in
+    // deterministic mode the gradient terms come from the ordered gather
     k_eg_contacts<<<dim3(nb), dim3(RB), 0, c.s>>>(c.N, m, ct->idx, ct->d, ct->grad, c.cfg.kappa, c.cfg.dhat,
-                                                   g, part + 2 * nb, nb);
+                                                   det ? nullptr : g, part + 2 * nb, nb);
+    if (det && g) {
+      mas_status st = build_incidence(c, m, ct->idx, nullptr);
+      if (st != MAS_OK) return st;
+      k_eg_contacts_gather<<<dim3((c.N + 255) / 256), dim3(256), 0, c.s>>>(c.N, c.inc_off, c.inc_list, ct->d,
+                                                                            ct->grad, c.cfg.kappa, c.cfg.dhat, g);
+    }
   } else {
-    HIPCHK(hipMemsetAsync(part + 2 * nb, 0, sizeof(double) * 2 * nb, c.s));
+    fill_f64(c, part + 2 * nb, 2 * nb, 0.0);
   }
   k_eg_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(part, nb, E);
   HIPCHK(hipGetLastError());
@@ -399,9 +450,13 @@ mas_status launch_subspace(Ctx& c, const double* g, const double* z, const doubl
 }
 
 // ------------------------------------------------------------- safe step
-__global__ void k_alpha_init(int64_t D, double* alpha) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i < D) alpha[i] = 1.0;
+__global__ void k_alpha_init(int64_t D, double* a0, uint64_t* half, uint32_t* rounds) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < D) {
+    a0[i] = 1.0;
+    half[i] = 0ull;
+  }
+  if (i <= SAFE_ROUNDS) rounds[i] = 0u;
 }
 
 // alpha_c = min(1, 0.9 d / s) for a stencil closing at the rate
@@ -433,18 +488,25 @@ __global__ __launch_bounds__(256) void k_alpha_stencils(int64_t m, const int32_t
   }
 }
 
-__global__ void k_step(int64_t n3, const double* x, const double* p, const double* alpha, double scale,
-                       double* xo) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= n3) return;
-  xo[i] = x[i] + scale * alpha[(i / 3) >> 5] * p[i];
+// Step of subdomain s in damping round r: a0 halved once for every earlier
+// round that marked it (bit q of half[s] for q < r; bits of round r itself,
+// set concurrently, are masked off, so the value does not depend on the
+// order of the atomics).
+__device__ __forceinline__ double alpha_round(const double* a0, const uint64_t* half, int s, uint64_t mask) {
+  const uint64_t h = __hip_atomic_load(half + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & mask;
+  return ldexp(a0[s], -__popcll(h));
 }
 
-// A stencil whose vertices, each moved with its own subdomain's step, would
-// close to below 0.05 of its distance marks the subdomains it touches.
-__global__ __launch_bounds__(256) void k_alpha_check(int64_t m, const int32_t* idx, const double* grad,
-                                                     const double* d, const double* p, const double* alpha,
-                                                     uint8_t* mark, uint32_t* count) {
+// Damping round r < SAFE_ROUNDS: a stencil whose vertices, each moved with
+// its own subdomain's step, would close to below 0.05 of its distance marks
+// its subdomains for halving (bit r) and is counted in rounds[r].  A round
+// after one that found nothing returns at once.  Round SAFE_ROUNDS only
+// counts what is left.
+__global__ __launch_bounds__(256) void k_alpha_round(int r, int64_t m, const int32_t* idx, const double* grad,
+                                                     const double* d, const double* p, const double* a0,
+                                                     uint64_t* half, uint32_t* rounds) {
+  if (r > 0 && rounds[r - 1] == 0u) return;  // uniform: written by the previous launch
+  const uint64_t mask = (1ull << r) - 1ull;
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   bool viol = false;
   if (i < m) {
@@ -459,52 +521,59 @@ __global__ __launch_bounds__(256) void k_alpha_check(int64_t m, const int32_t* i
         double dot = 0.0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
-        dn += alpha[vi[j] >> 5] * dot;
+        dn += alpha_round(a0, half, vi[j] >> 5, mask) * dot;
       }
       if (dn < 0.05 * di) {
         viol = true;
+        if (r < SAFE_ROUNDS) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (vi[j] >= 0) mark[vi[j] >> 5] = 1;
+          for (int j = 0; j < 4; ++j)
+            if (vi[j] >= 0) atomicOr(reinterpret_cast<unsigned long long*>(half + (vi[j] >> 5)), 1ull << r);
+        }
       }
     }
   }
   const unsigned long long b = __ballot(viol);
-  if (b != 0 && (threadIdx.x & 63) == 0) atomicAdd(count, uint32_t(__popcll(b)));
+  if (b != 0 && (threadIdx.x & 63) == 0) atomicAdd(rounds + r, uint32_t(__popcll(b)));
 }
 
-__global__ void k_alpha_halve(int64_t D, double* alpha, uint8_t* mark) {
+__global__ void k_alpha_final(int64_t D, const double* a0, const uint64_t* half, double* alpha) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i < D && mark[i]) {
-    alpha[i] *= 0.5;
-    mark[i] = 0;
-  }
+  if (i < D) alpha[i] = ldexp(a0[i], -__popcll(half[i]));
+}
+
+__global__ void k_step(int64_t n3, const double* x, const double* p, const double* alpha, double scale,
+                       double* xo) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  xo[i] = x[i] + scale * alpha[(i / 3) >> 5] * p[i];
+}
+
+__global__ void k_copy_f64(const double* src, double* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
 }
 
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out) {
   const int64_t D = c.lv[0].nsub;
+  const dim3 gD((std::max<int64_t>(D, SAFE_ROUNDS + 1) + 255) / 256), b256(256);
   if (cand) {
-    k_alpha_init<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, c.alpha);
+    k_alpha_init<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.ahalf, c.around);
     if (cand->m > 0) {
-      const dim3 g((cand->m + 255) / 256), b(256);
-      k_alpha_stencils<<<g, b, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha);
+      const dim3 g((cand->m + 255) / 256);
+      k_alpha_stencils<<<g, b256, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0);
       // subdomains moving at different steps: halve the steps of the
       // subdomains of any stencil the combined motion would close
-      for (int round = 0; round < SAFE_ROUNDS; ++round) {
-        k_set_u32<<<dim3(1), dim3(1), 0, c.s>>>(c.ctr + 2, 0u);
-        k_alpha_check<<<g, b, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha, c.amark, c.ctr + 2);
-        uint32_t nv = 0;
-        HIPCHK(hipMemcpyAsync(&nv, c.ctr + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, c.s));
-        HIPCHK(hipStreamSynchronize(c.s));
-        if (nv == 0) break;
-        k_alpha_halve<<<dim3((D + 255) / 256), dim3(256), 0, c.s>>>(D, c.alpha, c.amark);
-      }
+      for (int r = 0; r <= SAFE_ROUNDS; ++r)
+        k_alpha_round<<<g, b256, 0, c.s>>>(r, cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0, c.ahalf,
+                                           c.around);
     }
+    k_alpha_final<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.ahalf, c.alpha);
   }
   int64_t n3 = 3 * c.N;
-  k_step<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);
-  if (alpha) HIPCHK(hipMemcpyAsync(alpha, c.alpha, sizeof(double) * D, hipMemcpyDeviceToDevice, c.s));
+  k_step<<<dim3((n3 + 255) / 256), b256, 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);
+  if (alpha) k_copy_f64<<<dim3(std::min<int64_t>((D + 255) / 256, 1024)), b256, 0, c.s>>>(c.alpha, alpha, D);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -1,5 +1,6 @@
-// Bucketing of contact stencils into per-subdomain and per-range lists.
-#include <hipcub/hipcub.hpp>
+// Bucketing of contact stencils into per-subdomain and per-range lists, and
+// the exclusive prefix sum they are built with.
+#include <algorithm>
 
 #include "kernels.hpp"
 
@@ -83,44 +84,174 @@ __global__ __launch_bounds__(256) void k_bucket_fill(int div, const int32_t* map
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
-mas_status ensure_cub(Ctx& c, size_t bytes) {
-  if (bytes <= c.cub_bytes) return MAS_OK;
-  if (c.cub_tmp) HIPCHK(hipFree(c.cub_tmp));
-  c.cub_tmp = nullptr;
-  c.cub_bytes = 0;
-  if (hipMalloc(&c.cub_tmp, bytes) != hipSuccess) return MAS_ERR_OOM;
-  c.cub_bytes = bytes;
-  return MAS_OK;
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_copy_i32(const int32_t* src, int32_t* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+void fill_f64(Ctx& c, double* p, int64_t n, double v) {
+  if (n <= 0) return;
+  k_fill_f64<<<dim3(std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, c.s>>>(p, n, v);
+}
+
+void fill_i32(Ctx& c, int32_t* p, int64_t n, int32_t v) {
+  if (n <= 0) return;
+  k_fill_i32<<<dim3(std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, c.s>>>(p, n, v);
+}
+
+// ------------------------------------------------------------ prefix sums
+// Exclusive scan of int32 counts in tiles of SCAN_N items: each tile is
+// scanned in one workgroup (SCAN_IPT consecutive items per thread, thread
+// totals scanned across the wavefront with shuffles, wavefront totals in
+// LDS) and writes its total; the totals are scanned the same way
+// (recursively) and added back.  Integer sums, so the result does not depend
+// on any order.
+constexpr int SCAN_T = 256, SCAN_IPT = 8, SCAN_N = SCAN_T * SCAN_IPT;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum) {
+  __shared__ int32_t s[SCAN_N];
+  __shared__ int32_t wsum[SCAN_T / 64];
+  const int64_t base = int64_t(blockIdx.x) * SCAN_N;
+  for (int q = threadIdx.x; q < SCAN_N; q += SCAN_T) {
+    const int64_t i = base + q;
+    s[q] = i < n ? in[i] : 0;
+  }
+  __syncthreads();
+  int32_t loc[SCAN_IPT];
+  int32_t tot = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_IPT; ++k) {
+    loc[k] = tot;
+    tot += s[threadIdx.x * SCAN_IPT + k];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t inc = tot;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t u = __shfl_up(inc, o);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int32_t ex = inc - tot;
+  for (int q = 0; q < w; ++q) ex += wsum[q];
+#pragma unroll
+  for (int k = 0; k < SCAN_IPT; ++k) s[threadIdx.x * SCAN_IPT + k] = ex + loc[k];
+  if (threadIdx.x == SCAN_T - 1) tsum[blockIdx.x] = ex + tot;
+  __syncthreads();
+  for (int q = threadIdx.x; q < SCAN_N; q += SCAN_T) {
+    const int64_t i = base + q;
+    if (i < n) out[i] = s[q];
+  }
+}
+
+__global__ void k_scan_add(int32_t* out, int64_t n, const int32_t* tsum) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) out[i] += tsum[i / SCAN_N];
+}
+
+int64_t scan_scratch_elems(int64_t n) {
+  int64_t tot = 0;
+  while (n > 1) {
+    n = (n + SCAN_N - 1) / SCAN_N;
+    tot += n + 64;
+  }
+  return tot + 64;
+}
+
+static void scan_rec(Ctx& c, const int32_t* in, int32_t* out, int64_t n, int32_t* tmp) {
+  const int64_t nb = (n + SCAN_N - 1) / SCAN_N;
+  k_scan_tile<<<dim3(nb), dim3(SCAN_T), 0, c.s>>>(in, out, n, tmp);
+  if (nb > 1) {
+    scan_rec(c, tmp, tmp, nb, tmp + nb + 64);
+    k_scan_add<<<dim3((n + 255) / 256), dim3(256), 0, c.s>>>(out, n, tmp);
+  }
 }
 
 mas_status exclusive_scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n1) {
-  size_t bytes = 0;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, int(n1), c.s));
-  mas_status st = ensure_cub(c, bytes);
-  if (st != MAS_OK) return st;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(c.cub_tmp, bytes, in, out, int(n1), c.s));
+  if (n1 <= 0) return MAS_OK;
+  if (n1 > c.scan_cap) return MAS_ERR_INVALID_ARG;
+  scan_rec(c, in, out, n1, c.scan_tmp);
+  HIPCHK(hipGetLastError());
   return MAS_OK;
 }
 
 mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
                            const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
-  HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (D + 1), c.s));
+  fill_i32(c, cnt, D + 1, 0);
   if (m > 0) {
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
     k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(div, map, m, idx, w, vec12, cnt);
   }
-  size_t bytes = 0;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, cnt, off, int(D + 1), c.s));
-  mas_status st = ensure_cub(c, bytes);
+  mas_status st = exclusive_scan_i32(c, cnt, off, D + 1);
   if (st != MAS_OK) return st;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(c.cub_tmp, bytes, cnt, off, int(D + 1), c.s));
   if (m > 0) {
     // reuse cnt as the fill cursor
-    HIPCHK(hipMemcpyAsync(cnt, off, sizeof(int32_t) * D, hipMemcpyDeviceToDevice, c.s));
+    k_copy_i32<<<dim3(std::min<int64_t>((D + 255) / 256, 4096)), dim3(256), 0, c.s>>>(off, cnt, D);
     int bs = 256;
     int64_t gs = (m + bs - 1) / bs;
     k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(div, map, m, idx, w, vec12, cnt, list);
+  }
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+// ------------------------------------------------- vertex incidence lists
+// Deterministic mode: for every vertex v the slots 4 c + j of the stencils
+// c (with w[c] > 0 when w is given) whose vertex j is v, in ascending order:
+// counted with integer atomics, placed by an exclusive scan and a fill in
+// atomic order, then each vertex's list sorted by its own thread (lists are
+// short: the contacts of one vertex).
+__global__ void k_inc_count(int64_t m, const int32_t* idx, const double* w, int32_t* cnt) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= 4 * m) return;
+  const int v = idx[i];
+  if (v >= 0 && (!w || w[i >> 2] > 0.0)) atomicAdd(&cnt[v], 1);
+}
+
+__global__ void k_inc_fill(int64_t m, const int32_t* idx, const double* w, int32_t* cursor, int32_t* list) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= 4 * m) return;
+  const int v = idx[i];
+  if (v >= 0 && (!w || w[i >> 2] > 0.0)) list[atomicAdd(&cursor[v], 1)] = int32_t(i);
+}
+
+__global__ void k_inc_sort(int64_t N, const int32_t* off, int32_t* list) {
+  const int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (v >= N) return;
+  const int b = off[v], e = off[v + 1];
+  for (int q = b + 1; q < e; ++q) {
+    const int32_t key = list[q];
+    int p = q - 1;
+    while (p >= b && list[p] > key) {
+      list[p + 1] = list[p];
+      --p;
+    }
+    list[p + 1] = key;
+  }
+}
+
+mas_status build_incidence(Ctx& c, int64_t m, const int32_t* idx, const double* w) {
+  if (m > c.cfg.max_contacts) return MAS_ERR_INVALID_ARG;
+  fill_i32(c, c.inc_cnt, c.N + 1, 0);
+  const dim3 g((4 * m + 255) / 256), b(256);
+  if (m > 0) k_inc_count<<<g, b, 0, c.s>>>(m, idx, w, c.inc_cnt);
+  mas_status st = exclusive_scan_i32(c, c.inc_cnt, c.inc_off, c.N + 1);
+  if (st != MAS_OK) return st;
+  if (m > 0) {
+    k_copy_i32<<<dim3(std::min<int64_t>((c.N + 255) / 256, 4096)), b, 0, c.s>>>(c.inc_off, c.inc_cnt, c.N);
+    k_inc_fill<<<g, b, 0, c.s>>>(m, idx, w, c.inc_cnt, c.inc_list);
+    k_inc_sort<<<dim3((c.N + 255) / 256), b, 0, c.s>>>(c.N, c.inc_off, c.inc_list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;

@@ -19,67 +19,92 @@ namespace mas {
 // test dS first).  The lookup first tries the same position in the base
 // set (contact sets that keep their order between build and update), then
 // the base-key hash table.
-__global__ void k_classify(int64_t m, const uint64_t* key, const int32_t* idx, const double* d,
-                           const double* grad, double kappa, double dhat, double cos_rot, int64_t mb,
-                           const uint64_t* bkey, const uint64_t* hkey, const int32_t* hval, int64_t hmask,
-                           const double* bk, const double* bgrad, double* U, int32_t* Uidx, double* dS,
-                           uint64_t* ckey, uint32_t* err) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= m) return;
-  double b, b1, b2;
-  double di = d[i];
-  if (!isfinite(di)) atomicOr(err, ERRB_NONFINITE);
-  barrier3(di, dhat, &b, &b1, &b2);
-  double k = kappa * b2;
-  uint64_t kk = key[i];
-  ckey[i] = kk;
-  reinterpret_cast<int4*>(Uidx)[i] = reinterpret_cast<const int4*>(idx)[i];
-  if (!(k > 0.0)) {
-    dS[i] = 0.0;  // the column is zero and is not stored: readers test dS first
-    return;
-  }
-  double n[12];
+// Per workgroup the counts of the branches taken (active, new, rotated,
+// stiffened, softened) go to part[5 * block + q]; they are summed only when
+// the counters are read.
+constexpr int CLS_T = 256;
+
+__global__ __launch_bounds__(CLS_T) void k_classify(int64_t m, const uint64_t* key, const int32_t* idx,
+                                                    const double* d, const double* grad, double kappa, double dhat,
+                                                    double cos_rot, int64_t mb, const uint64_t* bkey,
+                                                    const uint64_t* hkey, const int32_t* hval, int64_t hmask,
+                                                    const double* bk, const double* bgrad, double* U, int32_t* Uidx,
+                                                    double* dS, uint64_t* ckey, uint32_t* err, int32_t* part) {
+  __shared__ int cnt[5];
+  if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  int branch = -1;  // 1 new, 2 rotated, 3 stiffened, 4 softened
+  if (i < m) {
+    double b, b1, b2;
+    const double di = d[i];
+    if (!isfinite(di)) atomicOr(err, ERRB_NONFINITE);
+    barrier3(di, dhat, &b, &b1, &b2);
+    const double k = kappa * b2;
+    const uint64_t kk = key[i];
+    ckey[i] = kk;
+    reinterpret_cast<int4*>(Uidx)[i] = reinterpret_cast<const int4*>(idx)[i];
+    if (!(k > 0.0)) {
+      dS[i] = 0.0;  // the column is zero and is not stored: readers test dS first
+    } else {
+      double n[12];
 #pragma unroll
-  for (int q = 0; q < 12; ++q) n[q] = grad[12 * i + q];
-  double s = k;
-  int64_t bi = -1;
-  {
-    if (i < mb && bkey[i] == kk) {
-      bi = i;
-    } else if (mb > 0) {
-      // probe the base-key table until the key or a free slot
-      int64_t h = int64_t(key_hash(kk) & uint64_t(hmask));
-      while (true) {
-        const uint64_t hk = hkey[h];
-        if (hk == kk) {
-          bi = hval[h];
-          break;
+      for (int q = 0; q < 12; ++q) n[q] = grad[12 * i + q];
+      double s = k;
+      branch = 1;
+      int64_t bi = -1;
+      if (i < mb && bkey[i] == kk) {
+        bi = i;
+      } else if (mb > 0) {
+        // probe the base-key table until the key or a free slot
+        int64_t h = int64_t(key_hash(kk) & uint64_t(hmask));
+        while (true) {
+          const uint64_t hk = hkey[h];
+          if (hk == kk) {
+            bi = hval[h];
+            break;
+          }
+          if (hk == HKEY_EMPTY) break;
+          h = (h + 1) & hmask;
         }
-        if (hk == HKEY_EMPTY) break;
-        h = (h + 1) & hmask;
+      }
+      if (bi >= 0) {
+        double dot = 0, nn = 0, bb = 0;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+          const double nb = bgrad[12 * bi + q];
+          dot += n[q] * nb;
+          nn += n[q] * n[q];
+          bb += nb * nb;
+        }
+        const double cosang = dot / (sqrt(nn) * sqrt(bb));
+        if (cosang < cos_rot) {
+          s = k;
+          branch = 2;
+        } else if (k > bk[bi]) {
+          s = k - bk[bi];
+          branch = 3;
+        } else {
+          s = 0.0;
+          branch = 4;
+        }
+      }
+      if (!(s > 0.0)) s = 0.0;
+      dS[i] = s;
+      if (s > 0.0) {
+        const double sq = sqrt(s);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) U[12 * i + q] = sq * n[q];
       }
     }
   }
-  if (bi >= 0) {
-    double dot = 0, nn = 0, bb = 0;
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-      double nb = bgrad[12 * bi + q];
-      dot += n[q] * nb;
-      nn += n[q] * n[q];
-      bb += nb * nb;
+  if (part) {
+    if (branch > 0) {
+      atomicAdd(&cnt[0], 1);
+      atomicAdd(&cnt[branch], 1);
     }
-    double cosang = dot / (sqrt(nn) * sqrt(bb));
-    if (cosang < cos_rot) s = k;
-    else if (k > bk[bi]) s = k - bk[bi];
-    else s = 0.0;
-  }
-  if (!(s > 0.0)) s = 0.0;
-  dS[i] = s;
-  if (s > 0.0) {
-    const double sq = sqrt(s);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) U[12 * i + q] = sq * n[q];
+    __syncthreads();
+    if (threadIdx.x < 5) part[5 * int64_t(blockIdx.x) + threadIdx.x] = cnt[threadIdx.x];
   }
 }
 
@@ -244,7 +269,7 @@ __device__ __forceinline__ void gather_w(const unsigned char* As, const float* s
 constexpr size_t CAP_STAGE = blk_elems(MAS_F32) * 4;
 
 __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, const uint8_t* bprec,
-                                                     const float* scale, const int32_t* rank, const SlotCol* slots,
+                                                     const float* scale, int32_t* rank, const SlotCol* slots,
                                                      double* W, double* Lcap, uint32_t* err, DiagRec* dg) {
   __shared__ __align__(16) unsigned char As[CAP_STAGE];
   __shared__ float sig[BD];
@@ -291,18 +316,26 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
     Cm[j * r + k] = acc;
   }
   __syncthreads();
-  // C = L L^T in place (lower triangle), float64
+  // C = L L^T in place (lower triangle), float64.  Column j of L depends on
+  // the leading (j + 1) x (j + 1) part of C only, so a pivot that is not
+  // positive ends the factor there: the subdomain keeps its first j columns
+  // (the ones of largest dS) and the rank drops to j.
+  int rk = r;
   for (int j = 0; j < r; ++j) {
     if (tid == 0) {
-      double djj = Cm[j * r + j];
-      if (!(djj > 0.0)) {
-        if (!bad) diag_report(dg, 3, 0, d, j, djj);
+      const double djj = Cm[j * r + j];
+      if (!(djj > 0.0) || !isfinite(djj)) {
+        diag_report(dg, 3, 0, d, j, djj);
         bad = 1;
-        djj = 1.0;
+      } else {
+        Cm[j * r + j] = sqrt(djj);
       }
-      Cm[j * r + j] = sqrt(djj);
     }
     __syncthreads();
+    if (bad) {
+      rk = j;
+      break;
+    }
     const double ljj = Cm[j * r + j];
     for (int i = j + 1 + tid; i < r; i += blockDim.x) Cm[i * r + j] /= ljj;
     __syncthreads();
@@ -313,59 +346,55 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
     }
     __syncthreads();
   }
-  if (tid == 0 && bad) atomicOr(err, ERRB_NOT_SPD);
+  if (tid == 0 && bad) {
+    atomicOr(err, ERRB_RANK);
+    rank[d] = rk;
+  }
   double* L = Lcap + d * (K * (K + 1) / 2);
-  for (int q = tid; q < r * r; q += blockDim.x) {
-    const int i = q / r, j = q % r;
+  for (int q = tid; q < rk * rk; q += blockDim.x) {
+    const int i = q / rk, j = q % rk;
     if (j <= i) L[pk(i, j)] = Cm[i * r + j];
   }
-  for (int q = tid; q < r * BD; q += blockDim.x) {
+  for (int q = tid; q < rk * BD; q += blockDim.x) {
     int j = q / BD, i = q % BD;
     W[(d * K + j) * BD + i] = Ws[j][i];
   }
 }
 
-static mas_status grow_current(Ctx& c, int64_t m) {
-  if (m <= c.mc_cap) return MAS_OK;
-  int64_t cap = m + m / 4 + 1024;
-  hipFree(c.U); hipFree(c.Uidx); hipFree(c.dS); hipFree(c.ckey); hipFree(c.cand_list);
-  bool ok = hipMalloc(&c.U, 96 * cap) == hipSuccess && hipMalloc(&c.Uidx, 16 * cap) == hipSuccess &&
-            hipMalloc(&c.dS, 8 * cap) == hipSuccess && hipMalloc(&c.ckey, 8 * cap) == hipSuccess &&
-            hipMalloc(&c.cand_list, 16 * cap) == hipSuccess;
-  if (!ok) return MAS_ERR_OOM;
-  c.mc_cap = cap;
-  return MAS_OK;
-}
-
 mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) {
   ProfScope ps(c, MAS_T_UPDATE);
   int64_t m = cur ? cur->m : 0;
-  mas_status st = grow_current(c, m > 0 ? m : 1);
-  if (st != MAS_OK) return st;
+  if (m > c.mc_cap) return MAS_ERR_INVALID_ARG;  // checked by mas_woodbury_update
+  mas_status st = MAS_OK;
   c.mc = m;
+  c.cls_blocks = (m + CLS_T - 1) / CLS_T;
   if (m > 0) {
-    k_classify<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(
+    k_classify<<<dim3(c.cls_blocks), dim3(CLS_T), 0, c.s>>>(
         m, cur->key, cur->idx, cur->d, cur->grad, c.cfg.kappa, c.cfg.dhat, c.cfg.cos_rot, c.mb,
-        c.bkey, c.hkey, c.hval, c.hcap - 1, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err);
+        c.bkey, c.hkey, c.hval, c.hsize - 1, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err, c.cls_part);
     HIPCHK(hipGetLastError());
   }
   st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
   if (st != MAS_OK) return st;
   const int64_t D = c.lv[0].nsub;
-  if (rank_hist) HIPCHK(hipMemsetAsync(rank_hist, 0, sizeof(int32_t) * (c.K + 1), c.s));
+  if (rank_hist) fill_i32(c, rank_hist, c.K + 1, 0);
   if (c.K == 0) {
-    HIPCHK(hipMemsetAsync(c.rank, 0, sizeof(int32_t) * D, c.s));
+    fill_i32(c, c.rank, D, 0);
+    if (rank_hist) fill_i32(c, rank_hist, 1, int32_t(D));
     return MAS_OK;
   }
   k_topk<<<dim3(D), dim3(64), 0, c.s>>>(c.K, c.cand_off, c.cand_list, c.dS, c.ckey, c.Uidx, c.U, c.rank,
                                         c.sel, c.slots);
+  Level& L0 = c.lv[0];
+  {
+    ProfScope pc(c, MAS_T_CAPACITANCE);
+    const size_t cap_lds = sizeof(double) * (size_t(c.K) * BD + size_t(c.K) * c.K) + sizeof(SlotCol) * c.K;
+    k_capacitance<<<dim3(D), dim3(256), cap_lds, c.s>>>(c.K, L0.blk, L0.bprec, L0.scale, c.rank, c.slots, c.W,
+                                                        c.Lcap, c.err, c.diag);
+  }
+  // after the capacitance factors, which may lower a rank
   if (rank_hist)
     k_rank_hist<<<dim3(std::min<int64_t>(64, (D + 255) / 256)), dim3(256), 0, c.s>>>(D, c.K, c.rank, rank_hist);
-  Level& L0 = c.lv[0];
-  ProfScope pc(c, MAS_T_CAPACITANCE);
-  const size_t cap_lds = sizeof(double) * (size_t(c.K) * BD + size_t(c.K) * c.K) + sizeof(SlotCol) * c.K;
-  k_capacitance<<<dim3(D), dim3(256), cap_lds, c.s>>>(c.K, L0.blk, L0.bprec, L0.scale, c.rank, c.slots, c.W,
-                                                      c.Lcap, c.err, c.diag);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -14,11 +14,19 @@ mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const doub
 mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
                            const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
 
-mas_status ensure_cub(Ctx& c, size_t bytes);
-// out[0..n] = exclusive prefix sums of in[0..n] (n + 1 entries)
+// deterministic mode: per-vertex incidence lists (c.inc_off, c.inc_list) of
+// the stencils with w[c] > 0 (all when w is null), each list ascending
+mas_status build_incidence(Ctx& c, int64_t m, const int32_t* idx, const double* w);
+// out[0..n1) = exclusive prefix sums of in[0..n1) (in == out allowed);
+// n1 must not exceed c.scan_cap
 mas_status exclusive_scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n1);
+// scratch (int32 elements) that scans of up to n items need
+int64_t scan_scratch_elems(int64_t n);
 // one-thread store of a counter (graph-capturable, unlike a memset)
 __global__ void k_set_u32(uint32_t* p, uint32_t v);
+// p[0..n) = v with a fill kernel (graph-capturable, unlike a memset)
+void fill_i32(Ctx& c, int32_t* p, int64_t n, int32_t v);
+void fill_f64(Ctx& c, double* p, int64_t n, double v);
 
 // k_setup.hip ----------------------------------------------------------
 mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E,

@@ -23,9 +23,10 @@ from .binding import DeviceContacts, MasContext, make_config
 
 class PNCG:
     def __init__(self, scene, block_prec="f32", levels=None, K=None, delta=0.3, hess_prec=None,
-                 max_halvings=8, device="cuda"):
+                 max_halvings=8, device="cuda", deterministic=False, prec_guard=None, collect_stats=False):
         cfg = make_config(scene, levels=levels, K=K, block_prec=block_prec, hess_prec=hess_prec,
-                          delta=delta)
+                          delta=delta, deterministic=deterministic, prec_guard=prec_guard)
+        self.collect_stats = collect_stats
         self.ctx = ctx = MasContext(scene, cfg, device=device)
         self.scene = scene
         self.max_halvings = max_halvings
@@ -85,9 +86,15 @@ class PNCG:
         st = ctx.step_out()
         if self.g0norm is None:
             self.g0norm = np.sqrt(st["gnorm2"])
-        self.log.append(dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), znorm=float(np.sqrt(st["znorm2"])),
-                             mu=st["mu"], nu=st["nu"], r=st["r"], restart=bool(self.restart),
-                             fallback=bool(st["fallback"]), E=Et, scale=scale))
+        rec = dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), znorm=float(np.sqrt(st["znorm2"])),
+                   mu=st["mu"], nu=st["nu"], r=st["r"], restart=bool(self.restart),
+                   fallback=bool(st["fallback"]), E=Et, scale=scale, accepted=accepted)
+        if self.collect_stats:
+            # counters of this iteration's update (none on a restart) and
+            # safe step; reading them synchronises the stream
+            rec.update(ctx.stats())
+            rec["active_pool"] = int(((self.pool.d > 0) & (self.pool.d < self.scene.dhat)).sum().item())
+        self.log.append(rec)
         if accepted:
             self.x, self.x_trial = self.x_trial, self.x
             self.g, self.g_trial = self.g_trial, self.g

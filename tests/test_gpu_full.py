@@ -250,3 +250,58 @@ def test_constraint_set_full(full):
             ids = np.array([*e, *f])
             if C.pair_distance(X[ids], C.EE)[0] < sc.dhat:
                 assert key(ids, 1) in kset, ids
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16", 2e-2), ("f16", 2e-2)])
+def test_sampled_woodbury_apply_full(full, prec, tol):
+    """Level 0 alone (one level, no coarse correction) after a Woodbury
+    update, for each block storage: the apply on sampled subdomains against
+    the oracle's direct inverse of S_d (H_base + U_d U_d^T) S_d^T (Section
+    4.1.2), with the Top-K selection of the subdomain compared by key
+    (Section 4.1.1).  The subdomains of largest rank are among the samples."""
+    from oracle import woodbury
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    sc, prob, hier, torch = full["sc"], full["prob"], full["hier"], full["torch"]
+    print("\n[full-size case] puffer balls, one level, %s blocks, Woodbury update" % prec, flush=True)
+    ctx = MasContext(sc, make_config(sc, levels=1, block_prec=prec, hess_prec="f32"))
+    d0 = full["d0"]
+    pool = ctx.contacts(dict(key=sc.pool["key"], idx=sc.pool["idx"], grad=sc.pool["grad"], d=d0), sort=True)
+    ctx.build(ctx.to_lib(sc.x), pool)
+    rng = np.random.default_rng(23)
+    dc = d0.copy()
+    pick = rng.random(dc.size) < 0.2
+    dc[pick] *= rng.uniform(0.5, 1.0, pick.sum())
+    cur = ctx.contacts(dict(key=sc.pool["key"], idx=sc.pool["idx"], grad=sc.pool["grad"], d=dc), sort=True)
+    ctx.woodbury_update(cur)
+    code, msg = ctx.sync()
+    assert code == 0, msg
+    counts = ctx.block_precisions(0)
+    D = int(ctx.nsub[0])
+    print("stored block precisions", counts, "of", D)
+    assert sum(counts.values()) == D
+    rank, sel = ctx.get_selection()
+    keys_lib = cur.key.cpu().numpy().view(np.uint64)
+    top = [int(q) for q in np.argsort(-rank, kind="stable")[:3]]
+    worst = 0.0
+    for d in top + [0, 17000]:
+        verts, _, _, cmask, A = local_system(full, d)
+        sub = np.nonzero(cmask)[0]
+        base_sub = dict(key=sc.pool["key"][sub], idx=sc.pool["idx"][sub], grad=sc.pool["grad"][sub], d=d0[sub])
+        curr_sub = dict(base_sub, d=dc[sub])
+        dS, u, _ = woodbury.classify(prob, base_sub, curr_sub)
+        selo = woodbury.topk(hier, curr_sub, dS, u, ctx.cfg.max_rank).get(d, [])
+        assert [int(k) for k in keys_lib[sel[d, :rank[d]]]] == [int(k) for k in curr_sub["key"][selo]], d
+        Ud = woodbury.local_U(hier, curr_sub, u, d, selo)
+        Bt = np.linalg.inv(A + Ud @ Ud.T)
+        g = np.zeros(3 * sc.N)
+        dofs = hier.subdomain_dofs(d)
+        g[dofs] = rng.standard_normal(dofs.size)
+        z = ctx.from_lib(ctx.apply(ctx.to_lib(g)))
+        err = rel(z[dofs], Bt @ g[dofs])
+        worst = max(worst, err)
+        print("subdomain %d rank %d: rel err %.2e" % (d, rank[d], err))
+        assert err < tol, (d, err)
+        outside = np.delete(z, dofs)
+        assert np.all(outside == 0.0)
+    print("%s: worst sampled error %.2e" % (prec, worst))
+    ctx.close()

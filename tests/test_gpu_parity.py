@@ -215,6 +215,13 @@ def test_stencil_distance_and_safe_step(case):
     np.testing.assert_allclose(alpha.cpu().numpy(), ao, rtol=1e-12)
     xn = pncg.step_positions(case.hier, sc.x.reshape(-1), p, ao)
     assert rel(ctx.from_lib(xo), xn) < 1e-14
+    # the step-size histogram of the counters
+    st = ctx.stats()
+    hist = np.zeros(8, np.int64)
+    for a in ao:
+        hist[0 if a >= 1 else next((i for i in range(1, 7) if a >= 2.0 ** -i), 7)] += 1
+    assert st['alpha_hist'] == hist.tolist()
+    assert st['safe_left'] == 0
     # halved step reuses the step sizes
     ctx.safe_step(case.x, ctx.to_lib(p), None, 0.5, xo)
     assert rel(ctx.from_lib(xo), pncg.step_positions(case.hier, sc.x.reshape(-1), p, 0.5 * ao)) < 1e-14
@@ -234,26 +241,143 @@ def test_apply_after_rebuild_without_update(case):
     assert code == 0, msg
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16", 2e-2), ("f16", 2e-2)])
-def test_low_precision_blocks(prec, tol):
-    print("\n[parity case] grid %s" % prec, flush=True)
-    c = grid_case(prec)
-    counts = c.ctx.block_precisions(0)
+_ORACLE = {}
+
+
+def oracle_case(name):
+    """The oracle side of a parity case (no GPU context), cached per scene."""
+    if name not in _ORACLE:
+        if name == "grid":
+            sc = synth.grid_scene()
+            base, curr = synth.grid_update_sets(sc)
+            L = 2
+        else:
+            sc = synth.two_boxes_scene()
+            rng = np.random.default_rng(5)
+            d = synth.pool_distance(sc.pool, sc.x)
+            base = synth.contact_set(sc.pool['key'], sc.pool['idx'], sc.pool['grad'], d)
+            curr = synth.churn_set(rng, sc, base, 0.3)
+            L = 3
+        c = Case.__new__(Case)
+        c.scene, c.base, c.curr = sc, base, curr
+        c.prob = fem.Problem(sc)
+        c.hier = mas.Hierarchy(sc.X, L)
+        c.H = c.prob.assemble(sc.x, base)
+        c.M = mas.MAS(c.hier, c.H)
+        c.dS, c.u, c.case = woodbury.classify(c.prob, base, curr)
+        c.sel = woodbury.topk(c.hier, curr, c.dS, c.u, 8)
+        c.blocks = woodbury.updated_blocks(c.hier, c.H, curr, c.u, c.sel)
+        c.U = woodbury.global_U(c.prob, curr, c.u, c.dS)
+        _ORACLE[name] = (c, L)
+    return _ORACLE[name]
+
+
+# (scene, storage, guard, tolerance, least share of blocks stored as asked):
+# guard 0 never promotes, so every block is stored in the requested 16-bit
+# format; the default guard keeps most two-box blocks in 16 bits and
+# promotes the stiff grid blocks (the share is then only reported).
+LOW = [("grid", "f32", 0.5, 1e-5, 1.0), ("grid", "bf16", 0.0, 2e-2, 1.0), ("grid", "f16", 0.0, 2e-2, 1.0),
+       ("grid", "bf16", 0.5, 2e-2, 0.0), ("boxes", "bf16", 0.5, 2e-2, 0.8), ("boxes", "f16", 0.5, 2e-2, 0.95)]
+
+
+@pytest.mark.parametrize("name,prec,guard,tol,share", LOW)
+def test_low_precision_blocks(name, prec, guard, tol, share):
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    print("\n[parity case] %s %s guard %g" % (name, prec, guard), flush=True)
+    c, L = oracle_case(name)
+    ctx = MasContext(c.scene, make_config(c.scene, levels=L, K=8, block_prec=prec, prec_guard=guard))
+    ctx.build(ctx.to_lib(c.scene.x), ctx.contacts(c.base))
+    ctx.woodbury_update(ctx.contacts(c.curr))
+    code, msg = ctx.sync()
+    assert code == 0, msg
+    counts = ctx.block_precisions(0)
+    D = c.hier.num_subdomains(0)
     print("stored block precisions", counts)
-    assert sum(counts.values()) == c.hier.num_subdomains(0)
+    assert sum(counts.values()) == D
+    assert counts[prec] >= share * D, counts
+    if guard == 0.0:
+        assert counts[prec] == D
     rng = np.random.default_rng(8)
     g = rng.standard_normal(3 * c.scene.N)
     zo = c.M.apply(g, c.blocks)
-    zg = c.ctx.from_lib(c.ctx.apply(c.ctx.to_lib(g)))
+    zg = ctx.from_lib(ctx.apply(ctx.to_lib(g)))
     err = rel(zg, zo)
-    print("apply rel err %s: %.3e" % (prec, err))
+    print("apply rel err %s: %.3e (%d of %d blocks stored as %s)" % (prec, err, counts[prec], D, prec))
     assert err < tol
     # Hessian snapshot in float32 for the mixed forms
     v = rng.standard_normal(3 * c.scene.N)
     yo = c.H @ v + c.U @ (c.U.T @ v)
-    y = c.ctx.from_lib(c.ctx.hess_vec(c.ctx.to_lib(v), with_update=True))
+    y = ctx.from_lib(ctx.hess_vec(ctx.to_lib(v), with_update=True))
     assert rel(y, yo) < 1e-5
-    c.ctx.close()
+    ctx.close()
+
+
+def test_nonfinite_inputs_are_reported(case):
+    """A NaN in g (mas_apply) or an inf in v (hess_vec) sets
+    MAS_ERR_NONFINITE, which the read clears."""
+    ctx = case.ctx
+    n = 3 * case.scene.N
+    g = np.ones(n)
+    g[n // 3] = np.nan
+    ctx.apply(ctx.to_lib(g))
+    code, msg = ctx.sync()
+    assert code == 6, (code, msg)
+    assert ctx.sync()[0] == 0
+    v = np.ones(n)
+    v[-1] = np.inf
+    ctx.hess_vec(ctx.to_lib(v), with_update=False)
+    code, msg = ctx.sync()
+    assert code == 6, (code, msg)
+    assert ctx.sync()[0] == 0
+
+
+def test_capacity_limits():
+    """Contact sets beyond max_contacts are refused before any launch."""
+    from paper_2604_19892_amd._abi import MasError
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    print("\n[parity case] grid with max_contacts 100", flush=True)
+    sc = synth.grid_scene()
+    base, curr = synth.grid_update_sets(sc)
+    assert base['key'].size > 100 and curr['key'].size > 100
+    ctx = MasContext(sc, make_config(sc, levels=2, K=8, max_contacts=100))
+    with pytest.raises(MasError) as e:
+        ctx.build(ctx.to_lib(sc.x), ctx.contacts(base))
+    assert e.value.code == 1
+    small = synth.subset(base, slice(0, 100))
+    ctx.build(ctx.to_lib(sc.x), ctx.contacts(small))
+    with pytest.raises(MasError) as e:
+        ctx.woodbury_update(ctx.contacts(curr))
+    assert e.value.code == 1
+    ctx.woodbury_update(ctx.contacts(synth.subset(curr, slice(0, 100))))
+    code, msg = ctx.sync()
+    assert code == 0, msg
+    ctx.close()
+
+
+def test_iteration_stats(case):
+    """Branch counts of the classification and the kept ranks, against the
+    oracle's classification of the same sets."""
+    st = case.ctx.stats()
+    k = case.prob.contact_stiffness(case.curr['d'])
+    act = k > 0
+    # a base entry with k = 0 classifies like absence (dS = k either way);
+    # the library keeps only base contacts with k > 0 and counts these as new
+    kb = case.prob.contact_stiffness(case.base['d'])
+    where = {int(q): i for i, q in enumerate(case.base['key'])}
+    br = case.case.copy()
+    for c_ in np.nonzero(act)[0]:
+        b = where.get(int(case.curr['key'][c_]))
+        if b is None or kb[b] == 0:
+            br[c_] = woodbury.NEW
+    assert st['contacts'] == case.curr['key'].size
+    assert st['active'] == int(act.sum())
+    assert st['n_new'] == int(((br == woodbury.NEW) & act).sum())
+    assert st['n_rotated'] == int(((br == woodbury.ROTATED) & act).sum())
+    assert st['n_stiffened'] == int(((br == woodbury.STIFFEN) & act).sum())
+    assert st['n_softened'] == int(((br == woodbury.SOFTEN) & act).sum())
+    ranks = [len(v) for v in case.sel.values()]
+    assert st['rank_sum'] == sum(ranks)
+    assert st['rank_max'] == max(ranks)
 
 
 def stiff_case(prec, guard):
