@@ -137,7 +137,9 @@ class MasContext:
         return torch.as_tensor(np.ascontiguousarray(a), device=self.device)
 
     def from_lib(self, t):
-        a = t.detach().cpu().numpy().reshape(-1, 3)
+        """(3N,) device tensor or host array in library order -> (3N,) host
+        array in original order."""
+        a = (t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)).reshape(-1, 3)
         out = np.empty_like(a)
         out[self.perm] = a
         return out.reshape(-1)

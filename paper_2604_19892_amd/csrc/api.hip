@@ -306,8 +306,9 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   // vertex ranges: cut greedily in vertex order so that each range is
   // touched by about RANGE_TETS tets and spans at most RANGE_MAX vertices
   std::vector<int32_t> rbeg, vrange(N);
+  // vertex -> touching tets, ascending tet order (ranges; lumped masses)
+  std::vector<int32_t> voff(N + 1, 0), vt(std::max<int64_t>(4 * T, 1));
   {
-    std::vector<int32_t> voff(N + 1, 0), vt(4 * T);
     for (int64_t q = 0; q < 4 * T; ++q) voff[tets[q] + 1]++;
     for (int64_t v = 0; v < N; ++v) voff[v + 1] += voff[v];
     std::vector<int32_t> cur(voff.begin(), voff.end() - 1);
@@ -496,21 +497,30 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     HIPCHK(hipMemcpy(c->rl_tv, etv.data(), etv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->t_home, th.data(), th.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
-  double *dX = nullptr, *drho = nullptr, *dE = nullptr, *dnu = nullptr;
+  double *dX = nullptr, *drho = nullptr, *dE = nullptr, *dnu = nullptr, *dmq = nullptr;
+  int32_t *dvoff = nullptr, *dvt = nullptr;
   TRY(dalloc(&dX, 3 * N));
   TRY(dalloc(&drho, T));
   TRY(dalloc(&dE, T));
   TRY(dalloc(&dnu, T));
+  TRY(dalloc(&dmq, T));
+  TRY(dalloc(&dvoff, N + 1));
+  TRY(dalloc(&dvt, vt.size()));
   HIPCHK(hipMemcpyAsync(dX, Xl.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(drho, rho.data(), T * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(dE, E.data(), T * sizeof(double), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(dnu, nu.data(), T * sizeof(double), hipMemcpyHostToDevice, c->s));
-  st = launch_rest(*c, dX, drho, dE, dnu);
+  HIPCHK(hipMemcpyAsync(dvoff, voff.data(), (N + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(dvt, vt.data(), vt.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
+  st = launch_rest(*c, dX, drho, dE, dnu, dmq, dvoff, dvt);
   hipStreamSynchronize(c->s);
   hipFree(dX);
   hipFree(drho);
   hipFree(dE);
   hipFree(dnu);
+  hipFree(dmq);
+  hipFree(dvoff);
+  hipFree(dvt);
   if (st != MAS_OK) {
     mas_destroy(c);
     return st;

@@ -7,9 +7,9 @@ namespace mas {
 
 // Dm = [X1-X0, X2-X0, X3-X0]; Dm^-1 rows are the cross products of its
 // columns over det(Dm); V = det/6; mu, lam from Young's modulus and Poisson's
-// ratio; each vertex receives a quarter of rho V.
+// ratio; tmass[t] = rho V / 4, the share each of its vertices receives.
 __global__ void k_rest(int64_t T, const int32_t* tets, const double* X, const double* rho,
-                       const double* E, const double* nu, double* geo, double* mass) {
+                       const double* E, const double* nu, double* geo, double* tmass) {
   int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (t >= T) return;
   int v[4];
@@ -42,8 +42,19 @@ __global__ void k_rest(int64_t T, const int32_t* tets, const double* X, const do
   g[10] = Ev / (2.0 * (1.0 + nv));
   g[11] = Ev * nv / ((1.0 + nv) * (1.0 - 2.0 * nv));
   geo_store(geo, t, g);
-  double mq = rho[t] * vol * 0.25;
-  for (int j = 0; j < 4; ++j) atomicAdd(&mass[v[j]], mq);
+  tmass[t] = rho[t] * vol * 0.25;
+}
+
+// Lumped mass of each vertex: the shares of its tets summed in ascending tet
+// order (voff/vt: vertex -> touching tets), so the masses do not depend on
+// the order in which threads run.
+__global__ void k_lumped_mass(int64_t N, const int32_t* voff, const int32_t* vt, const double* tmass,
+                              double* mass) {
+  const int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (v >= N) return;
+  double m = 0.0;
+  for (int32_t q = voff[v]; q < voff[v + 1]; ++q) m += tmass[vt[q]];
+  mass[v] = m;
 }
 
 // rest data copied to the range-major entries (padding entries zero)
@@ -58,11 +69,11 @@ __global__ void k_geo_entries(int64_t nent, int64_t nent_pad, const int32_t* rl_
   geo_store(rl_geo, w, g);
 }
 
-mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E,
-                       const double* nu) {
-  HIPCHK(hipMemsetAsync(c.mass, 0, sizeof(double) * c.N, c.s));
+mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E, const double* nu,
+                       double* tmass, const int32_t* voff, const int32_t* vt) {
   int bs = 256;
-  k_rest<<<dim3((c.T + bs - 1) / bs), dim3(bs), 0, c.s>>>(c.T, c.tets, X, rho, E, nu, c.geo, c.mass);
+  k_rest<<<dim3((c.T + bs - 1) / bs), dim3(bs), 0, c.s>>>(c.T, c.tets, X, rho, E, nu, c.geo, tmass);
+  k_lumped_mass<<<dim3((c.N + bs - 1) / bs), dim3(bs), 0, c.s>>>(c.N, voff, vt, tmass, c.mass);
   k_geo_entries<<<dim3((c.nent_pad + bs - 1) / bs), dim3(bs), 0, c.s>>>(c.nent, c.nent_pad, c.rl_t, c.geo,
                                                                         c.rl_geo);
   HIPCHK(hipGetLastError());
