@@ -223,6 +223,23 @@ mas_status pncg_subspace_step(void* ctx, const double* g, const double* z, const
                               const double* v_z, double* p, double* v_p, int32_t restart,
                               mas_step_out* out);
 
+/* pncg_subspace_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but the reduction
+ * workspace (11 per-block partial sums for each of max(1024, vertex ranges)
+ * blocks, then mu and nu) lives in a fixed 768 KiB device array that the
+ * library's code object holds on each device (up to 98,304 doubles, enough
+ * for about 8,900 vertex ranges, on the order of 10M vertices); the call
+ * makes no allocation and no host synchronisation.  A context needing more
+ * gives MAS_ERR_INVALID_ARG; before mas_build MAS_ERR_STATE.  Every call on
+ * one device shares that array (it keeps the last call's contents, and every
+ * entry is written before it is read): calls that overlap in time on one
+ * device, from contexts on different streams, race and must be ordered by
+ * the caller. */
+mas_status pncg_subspace_step_noalloc(void* ctx, const double* g, const double* z, const double* z_prev,
+                                      const double* v_z, double* p, double* v_p, int32_t restart,
+                                      mas_step_out* out);
+
 /* Incremental potential (Section 3.1) at x: E (device scalar) and, if g is
  * not NULL, its gradient (device, 3N).  Contacts with d <= 0 make E = +inf.
  * In deterministic mode c->m must not exceed max_contacts when g is given

@@ -102,6 +102,7 @@ SIGNATURES = {
     "mas_apply": (_I32, [_P, _P, _P]),
     "hess_vec": (_I32, [_P, _P, _P, _I32]),
     "pncg_subspace_step": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I32, _P]),
+    "pncg_subspace_step_noalloc": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "mas_energy_grad": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _P, _P]),
     "mas_inertial_target": (_I32, [_P, _P, _P, _P]),
     "mas_stencil_distance": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),

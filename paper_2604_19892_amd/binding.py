@@ -185,8 +185,16 @@ class MasContext:
             _ptr(self.out)))
         return self.out
 
-    def step_out(self):
-        raw = self.out.cpu().numpy().view(np.uint8)
+    def subspace_step_noalloc(self, g, z, z_prev, vz, p, vp, restart, out=None):
+        """pncg_subspace_step_noalloc: the subspace step with the library's
+        fixed device workspace (no allocation)."""
+        out = self.out if out is None else out
+        check("pncg_subspace_step_noalloc", _abi.lib().pncg_subspace_step_noalloc(
+            self.h, _ptr(g), _ptr(z), _ptr(z_prev), _ptr(vz), _ptr(p), _ptr(vp), int(restart), _ptr(out)))
+        return out
+
+    def step_out(self, out=None):
+        raw = (self.out if out is None else out).cpu().numpy().view(np.uint8)
         s = MasStepOut.from_buffer_copy(raw.tobytes())
         return {f: getattr(s, f) for f in _abi.STEP_FIELDS}
 

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <numeric>
 #include <new>
 #include <vector>
@@ -48,6 +49,38 @@ void prof_end(Ctx& c, int t) {
 }  // namespace mas
 
 using namespace mas;
+
+// Fixed workspace of pncg_subspace_step_noalloc: the per-block partial sums
+// of the subspace step's reductions and its two scalars, in device memory
+// that the code object itself holds (each device that loads the library has
+// its own copy until the process ends), so that call allocates nothing.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// kernels only ever receive the address from hipGetSymbolAddress, looked up
+// once per device by mas_create with that device current.
+constexpr int64_t SCRATCH_DOUBLES = 98304;  // 768 KiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[MAX_DEVICES] = {};
+
+// this device's address of `scratch` (the current device)
+mas_status scratch_address(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return MAS_ERR_HIP;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MAS_ERR_HIP;
+    scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = scratch_dev[dev];
+  return MAS_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -221,6 +254,10 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (c->Tpad == 0) c->Tpad = TILE;
   c->L = cfg->num_levels;
   c->K = cfg->max_rank;
+  if (scratch_address(&c->fixed_ws) != MAS_OK) {
+    delete c;
+    return MAS_ERR_HIP;
+  }
   {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -585,6 +622,17 @@ mas_status pncg_subspace_step(void* p, const double* g, const double* z, const d
   Ctx& c = *as_ctx(p);
   if (!c.built) return MAS_ERR_STATE;
   return launch_subspace(c, g, z, z_prev, v_z, pk_, v_p, restart, out);
+}
+
+mas_status pncg_subspace_step_noalloc(void* p, const double* g, const double* z, const double* z_prev,
+                                      const double* v_z, double* pk_, double* v_p, int32_t restart,
+                                      mas_step_out* out) {
+  if (!p || !g || !z || !v_z || !pk_ || !v_p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.built || !c.fixed_ws) return MAS_ERR_STATE;
+  const int64_t need = subspace_workspace_elems(c);
+  if (need > SCRATCH_DOUBLES) return MAS_ERR_INVALID_ARG;
+  return launch_subspace_ws(c, g, z, z_prev, v_z, pk_, v_p, restart, out, c.fixed_ws, c.fixed_ws + need - 2);
 }
 
 mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, const mas_contacts* ct,

@@ -391,6 +391,7 @@ struct Ctx {
   double* partials = nullptr;      // reductions
   int n_partial_blocks = 1024;
   double* scal = nullptr;          // small device scalars (mu, nu, ...)
+  double* fixed_ws = nullptr;      // this device's address of the library's fixed workspace array
   double* alpha = nullptr;         // D0, step sizes of the last safe step
   double* alpha0 = nullptr;        // D0, step sizes before damping
   uint64_t* ahalf = nullptr;       // D0, bit r: subdomain halved in damping round r

@@ -434,19 +434,29 @@ __global__ void k_ss_update(int64_t n3, const double* z, const double* vz, doubl
   }
 }
 
-mas_status launch_subspace(Ctx& c, const double* g, const double* z, const double* zp,
-                           const double* vz, double* p, double* vp, int restart, mas_step_out* out) {
-  ProfScope ps(c, MAS_T_SUBSPACE);
+int64_t subspace_workspace_elems(const Ctx& c) { return int64_t(NS) * c.n_partial_blocks + 2; }
+
+// part: NS x n_partial_blocks per-block partial sums; scal: mu and nu.  Every
+// entry is written before it is read, so neither needs clearing.
+mas_status launch_subspace_ws(Ctx& c, const double* g, const double* z, const double* zp, const double* vz,
+                              double* p, double* vp, int restart, mas_step_out* out, double* part,
+                              double* scal) {
   const int nb = c.n_partial_blocks;
   int64_t n3 = 3 * c.N;
   int64_t m = (c.have_update) ? c.mc : 0;
   k_ss_reduce<<<dim3(nb), dim3(RB), 0, c.s>>>(n3, g, z, zp, p, vz, vp, restart ? 0 : 1, m, c.Uidx, c.U,
-                                              c.dS, c.partials, nb);
-  k_ss_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(c.partials, nb, restart, zp != nullptr, c.cfg.eps_sing,
-                                               c.cfg.eps_abs, c.cfg.restart_delta, out, c.scal);
-  k_ss_update<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, z, vz, p, vp, c.scal);
+                                              c.dS, part, nb);
+  k_ss_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(part, nb, restart, zp != nullptr, c.cfg.eps_sing,
+                                               c.cfg.eps_abs, c.cfg.restart_delta, out, scal);
+  k_ss_update<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, z, vz, p, vp, scal);
   HIPCHK(hipGetLastError());
   return MAS_OK;
+}
+
+mas_status launch_subspace(Ctx& c, const double* g, const double* z, const double* zp,
+                           const double* vz, double* p, double* vp, int restart, mas_step_out* out) {
+  ProfScope ps(c, MAS_T_SUBSPACE);
+  return launch_subspace_ws(c, g, z, zp, vz, p, vp, restart, out, c.partials, c.scal);
 }
 
 // ------------------------------------------------------------- safe step

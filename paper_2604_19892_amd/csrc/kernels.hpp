@@ -55,6 +55,12 @@ mas_status launch_energy_grad(Ctx& c, const double* x, const double* xt, const m
                               double* E, double* g);
 mas_status launch_subspace(Ctx& c, const double* g, const double* z, const double* zp,
                            const double* vz, double* p, double* vp, int restart, mas_step_out* out);
+// the subspace step with its reduction workspace given by the caller:
+// subspace_workspace_elems(c) doubles, partials first, then mu and nu
+int64_t subspace_workspace_elems(const Ctx& c);
+mas_status launch_subspace_ws(Ctx& c, const double* g, const double* z, const double* zp, const double* vz,
+                              double* p, double* vp, int restart, mas_step_out* out, double* part,
+                              double* scal);
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out);
 
