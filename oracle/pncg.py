@@ -80,7 +80,13 @@ def safe_alpha(hier, idx, grad, d, p):
     step is 0.9 of the time to contact, capped at 1 (and 0 for a stencil
     already at d <= 0).  Each subdomain takes the smallest step of the
     stencils touching it; subdomains whose different steps would together
-    close a stencil are then damped (halved) until none does."""
+    close a stencil are then damped (halved) until none does.  If
+    SAFE_ROUNDS rounds leave such a stencil, every subdomain takes instead
+    the bound that holds for any mix of per-vertex steps: a stencil whose
+    vertices close at the rates s_j = max(0, -grad_j . p_j) takes
+    min(1, 0.9 d / sum_j s_j), each subdomain the smallest over its
+    stencils, so that no stencil comes below 0.1 d whatever steps its
+    vertices take up to that bound."""
     P = np.asarray(p).reshape(-1, 3)
     D = hier.num_subdomains(0)
     alpha = np.ones(D)
@@ -102,7 +108,8 @@ def safe_alpha(hier, idx, grad, d, p):
     # steps: while the combined motion would bring a stencil below 0.05 of
     # its distance, halve the steps of every subdomain such a stencil touches.
     sub = np.where(idx >= 0, hier.rank[np.maximum(idx, 0)] // 32, -1)
-    for _ in range(SAFE_ROUNDS):
+
+    def violating(a):
         marked = np.zeros(D, bool)
         for c in range(idx.shape[0]):
             if not d[c] > 0.0:
@@ -111,13 +118,33 @@ def safe_alpha(hier, idx, grad, d, p):
             for j in range(4):
                 v = idx[c, j]
                 if v >= 0:
-                    dn += alpha[sub[c, j]] * float(grad[c, 3 * j:3 * j + 3] @ P[v])
+                    dn += a[sub[c, j]] * float(grad[c, 3 * j:3 * j + 3] @ P[v])
             if dn < 0.05 * d[c]:
                 marked[sub[c][sub[c] >= 0]] = True
+        return marked
+
+    for _ in range(SAFE_ROUNDS):
+        marked = violating(alpha)
         if not marked.any():
-            break
+            return alpha
         alpha[marked] *= 0.5
-    return alpha
+    if not violating(alpha).any():
+        return alpha
+    # the rounds did not separate every stencil: the bound for any mix
+    safe = np.ones(D)
+    for c in range(idx.shape[0]):
+        closing = 0.0
+        for j in range(4):
+            v = idx[c, j]
+            if v >= 0:
+                closing += max(0.0, -float(grad[c, 3 * j:3 * j + 3] @ P[v]))
+        if closing <= 0.0:
+            continue
+        a = max(0.0, min(1.0, 0.9 * d[c] / closing))
+        for j in range(4):
+            if idx[c, j] >= 0:
+                safe[sub[c, j]] = min(safe[sub[c, j]], a)
+    return safe
 
 
 def step_positions(hier, x, p, alpha):

@@ -202,3 +202,48 @@ def test_safe_step_single_contact_closed_form():
     d = hier.subdomain_of_vertex(3)
     assert alpha[d] == pytest.approx(0.9 * 1e-3 / 2e-3)
     assert np.all(np.delete(alpha, d) == 1.0)
+
+
+def test_safe_step_falls_back_when_damping_rounds_do_not_separate():
+    """A stencil across two subdomains whose vertices close fast on one side
+    and open as fast on the other has no net closing rate, so its own rule
+    leaves both steps at 1, while a second stencil holds one subdomain to a
+    small step: the mixed steps close the first stencil by about 1, which
+    halving both steps cures only after about 30 rounds (d = 1e-9).  The
+    fallback then gives every subdomain the bound for any mix of steps,
+    worked by hand here: 0.9 d / (sum of the closing rates)."""
+    X = np.random.default_rng(5).uniform(size=(64, 3))
+    hier = mas.Hierarchy(X, 1)
+    r = hier.rank
+    # one vertex of each of the two level-0 subdomains (library order)
+    va = int(np.flatnonzero(r // 32 == 0)[0])
+    vb = int(np.flatnonzero(r // 32 == 1)[0])
+    vb2 = int(np.flatnonzero(r // 32 == 1)[1])
+    idx = np.array([[va, vb, -1, -1], [vb2, -1, -1, -1]], np.int32)
+    grad = np.zeros((2, 12))
+    grad[0, 2] = 1.0           # grad at va: +z
+    grad[0, 5] = -1.0          # grad at vb: -z
+    grad[1, 2] = 1.0
+    p = np.zeros(3 * 64)
+    p[3 * va + 2] = -1.0       # va closes stencil 0 at rate 1
+    p[3 * vb + 2] = -1.0       # vb opens it at rate 1 (the net rate is 0)
+    p[3 * vb2 + 2] = -1.0      # stencil 1 closes at rate 1 from d = 1e-3
+    d = np.array([1e-9, 1e-3])
+    alpha = pncg.safe_alpha(hier, idx, grad, d, p)
+    assert alpha[0] == pytest.approx(0.9e-9, rel=1e-15)
+    assert alpha[1] == pytest.approx(0.9e-9, rel=1e-15)
+    # both stencils keep at least 0.1 of their distances
+    xn = pncg.step_positions(hier, X.reshape(-1), p, alpha)
+    d_new = np.array([(grad[c].reshape(4, 3)[:1 + (c == 0)] * (xn.reshape(-1, 3)[idx[c][idx[c] >= 0]]
+                                                          - X[idx[c][idx[c] >= 0]])).sum() for c in range(2)]) + d
+    assert np.all(d_new >= 0.1 * d)
+    # at d = 1e-3 the rounds suffice: stencil 1 sets 9e-4 on subdomain 1,
+    # and stencil 0 (1e-3 - a_0 + a_1 >= 5e-5) needs 11 halvings of both
+    alpha2 = pncg.safe_alpha(hier, idx, grad, np.array([1e-3, 1e-3]), p)
+    assert alpha2[0] == 2.0 ** -11
+    assert alpha2[1] == pytest.approx(9e-4 * 2.0 ** -11, rel=1e-15)
+    xn2 = pncg.step_positions(hier, X.reshape(-1), p, alpha2)
+    for c in range(2):
+        vs = idx[c][idx[c] >= 0]
+        dd = 1e-3 + (grad[c].reshape(4, 3)[:vs.size] * (xn2.reshape(-1, 3)[vs] - X[vs])).sum()
+        assert dd >= 0.05 * 1e-3
