@@ -10,9 +10,12 @@ Woodbury update, z = P g, H_base z, the subspace step, safe steps, trial
 energy/gradient with the descent check, restart test); restarts happen
 when the restart test asks for them, inside the timed region.
 
-Prints one JSON line.  The roofline object covers the level-0 kernel of
-mas_apply, timed with HIP events recorded by the library on its own stream
-during the timed steps.  After the timed steps, ``tol_solve`` solves from
+Prints one JSON line.  The timed steps run in blocks of ten iterations,
+each block from the scene's start (x^0, a restart), so that about 1M
+contacts are active through them.  The roofline object covers the level-0
+kernel of mas_apply, timed with HIP events recorded by the library on its
+own stream during the timed steps.  ``warm_frame`` times iterations of a
+later time step (the first two solved to tolerance first).  After the timed steps, ``tol_solve`` solves from
 the same start to ||grad E|| <= 1e-6 ||grad E_0|| five times per level-0
 block storage (f64 with float64 element Hessians; f32, bf16 and f16 with
 float32 element Hessians) and reports iterations and wall-clock times.
@@ -62,6 +65,67 @@ def hv_bytes(ctx, hess_prec, n_active):
     N = ctx.N
     return ctx.scene.T * (54 * sH + 16) + n_active * (12 * 8 + 16) + 8 * N + 2 * 8 * 3 * N
 
+
+def update_bytes(ctx, solver, rec, hist):
+    """Algorithmic bytes of one mas_woodbury_update call: every current
+    contact's key, indices, distance and gradient read and its dS and
+    indices written; for each active one its base entry looked up (key-table
+    slot, k, base gradient); for each contact with dS > 0 its u column
+    written and its candidate entry written and read; per updated subdomain
+    its stored block read once (the mean stored size), its float64 W, slot
+    columns and capacitance factor written; ranks written and read."""
+    size = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+    counts = solver.precision_counts
+    D0 = int(ctx.nsub[0])
+    m, act = rec["contacts"], rec["active"]
+    nu = rec["n_new"] + rec["n_rotated"] + rec["n_stiffened"]
+    b = m * (8 + 16 + 8 + 96) + m * (8 + 16)
+    b += act * (12 + 8 + 96)
+    b += nu * (96 + 2 * 4)
+    blk = sum(n * (PK * size[p] + (96 * 4 if size[p] == 2 else 0)) for p, n in counts.items()) / max(D0, 1)
+    for r, cnt in enumerate(hist):
+        if r:
+            b += cnt * (blk + 96 * r * 8 + r * 112 + 8 * r * (r + 1) // 2)
+    return b + 2 * 4 * D0
+
+
+def warm_frame(sc, prec, hess_prec, iters, tol=1e-6, max_iter=800):
+    """A later time step: the first two are solved to ||grad E|| <= tol
+    ||grad E_0|| (untimed; implicit Euler between them), then `iters`
+    iterations of the third are timed, started from the second's end, the
+    regime of a running simulation (contacts near their balance)."""
+    import numpy as np
+    import torch
+    from paper_2604_19892_amd.pncg import PNCG
+    s = PNCG(sc, block_prec=prec, hess_prec=hess_prec)
+    frames = []
+    for _ in range(2):
+        it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
+        frames.append({"iters": it, "seconds": sec, "rel_gnorm": rel, "converged": bool(rel <= tol)})
+        s.next_frame()
+    def active():
+        return int(((s.pool.d > 0) & (s.pool.d < sc.dhat)).sum().item())
+
+    a0 = active()
+    r0 = s.n_restarts
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(iters):
+        s.iterate()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    code, msg = s.ctx.sync()
+    out = {"iters_per_s": iters / dt, "ms_per_iter": 1e3 * dt / iters, "iters": iters,
+           "restart_fraction": (s.n_restarts - r0) / iters,
+           "active_contacts_first_last": [a0, active()],
+           "previous_frames": frames, "status": code}
+    s.ctx.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+BLOCK = 10
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = {"k_apply_l0": "k_apply.hip", "k_hv_range": "k_hessvec.hip"}
@@ -140,9 +204,9 @@ def cpu_baseline(full_N, iters=3):
     dt = time.perf_counter() - t
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     return {"value": iters / dt * sc.N / full_N, "unit": "iters/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "extrapolated": True,
             "sample": "%d oracle iterations (first one a restart) on an 8-ball puffer scene with %d vertices, "
-                      "%d tets, %d stencils; %.1f s; iters/s scaled by %d/%d vertices"
+                      "%d tets, %d stencils; %.1f s; iters/s extrapolated linearly in vertex count by %d/%d"
                       % (iters, sc.N, sc.T, sc.pool['key'].size, dt, sc.N, full_N)}
 
 
@@ -303,6 +367,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the solves to the gradient tolerance (f64 vs mixed storage)")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-frame regime")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=1500)
     ap.add_argument("--solve-repeats", type=int, default=5)
@@ -340,7 +405,11 @@ def main():
     solver = PNCG(sc, block_prec=args.prec, hess_prec=hess_prec)
     ctx = solver.ctx
     print("[bench] context ready (%.1fs)" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    # timed steps: blocks of BLOCK iterations, each from the scene's start
+    # (x^0, a restart), so that about 1M contacts stay active through them
     for i in range(args.warmup):
+        if i % BLOCK == 0:
+            solver.reset()
         solver.iterate()
     torch.cuda.synchronize()
     print("[bench] warmup done (%d iters)" % args.warmup, file=sys.stderr, flush=True)
@@ -348,34 +417,74 @@ def main():
     solver.track_precisions = True
     if solver.precision_counts is None:
         solver.precision_counts = ctx.block_precisions(0)
+    # counters of the same blocks, in an untimed pass (reading them
+    # synchronises the stream every iteration)
+    solver.collect_stats = True
+    recs, upd_bytes = [], []
+    done = 0
+    while done < args.steps:
+        solver.reset()
+        for i in range(min(BLOCK, args.steps - done)):
+            restart = solver.restart
+            solver.iterate()
+            recs.append(solver.log[-1])
+            if not restart:
+                upd_bytes.append(update_bytes(ctx, solver, solver.log[-1],
+                                              solver.rank_hist.cpu().numpy().tolist()))
+        done += BLOCK
+    solver.collect_stats = False
+    # the timed pass: the rank histograms are summed on the device (no host
+    # read); the algorithmic bytes are linear in them
     ctx.profile(True)
-    l0_bytes = []
-    hist_sum = None
+    hist_acc = torch.zeros_like(solver.rank_hist, dtype=torch.int64)
     r0 = solver.n_restarts
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in range(args.steps):
-        restart = solver.restart
-        solver.iterate()
-        hist = [0] if restart else solver.rank_hist.cpu().numpy().tolist()
-        if not restart:
-            hist_sum = hist if hist_sum is None else [a + b for a, b in zip(hist_sum, hist)]
-        l0_bytes.append(apply_l0_bytes(ctx, solver.precision_counts, hist))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
+    n_upd = 0
+    timer_names = ("apply_l0", "apply", "hv_tets", "hess_vec", "update", "capacitance", "build", "energy",
+                   "subspace")
+    timers = {k: [0.0, 0] for k in timer_names}
+    dt = 0.0
+    done = 0
+    while done < args.steps:
+        solver.reset()
+        ctx.profile_read("energy")           # the reset's own energy call is not a step
+        n = min(BLOCK, args.steps - done)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(n):
+            restart = solver.restart
+            solver.iterate()
+            if not restart:
+                hist_acc += solver.rank_hist
+                n_upd += 1
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t
+        done += n
+        for k in timer_names:
+            ms, cnt = ctx.profile_read(k)
+            timers[k][0] += ms
+            timers[k][1] += cnt
     restarts = solver.n_restarts - r0
-    timers = {k: ctx.profile_read(k) for k in ("apply_l0", "apply", "hv_tets", "hess_vec", "update",
-                                               "capacitance", "build", "energy", "subspace")}
     ctx.profile(False)
     print("[bench] timed %d iters in %.3fs" % (args.steps, dt), file=sys.stderr, flush=True)
+    hist_sum = hist_acc.cpu().numpy().tolist()
+    # per apply launch: the mean of the per-step bytes (linear in the
+    # histogram of the step; restarts carry no update)
+    zero = apply_l0_bytes(ctx, solver.precision_counts, [0])
+    with_upd = apply_l0_bytes(ctx, solver.precision_counts, hist_sum) - zero
+    l0_mean = zero + with_upd / args.steps
+    l0_bytes = [l0_mean] * args.steps
 
     ms_l0, n_l0 = timers["apply_l0"]
     bytes_l0 = l0_bytes
     achieved = sum(bytes_l0) / (ms_l0 * 1e-3) / 1e9 if n_l0 else 0.0
     ms_hv, n_hv = timers["hv_tets"]
-    n_active = int(((solver.pool.d > 0) & (solver.pool.d < sc.dhat)).sum().item())
+    actives = [r["active_pool"] for r in recs]
+    n_active = int(np.mean(actives))
     hv_b = hv_bytes(ctx, hess_prec, n_active)
     hv_achieved = n_hv * hv_b / (ms_hv * 1e-3) / 1e9 if n_hv else 0.0
+    ms_up, n_up = timers["update"]
+    up_mean = float(np.mean(upd_bytes)) if upd_bytes else 0.0
+    up_achieved = n_up * up_mean / (ms_up * 1e-3) / 1e9 if n_up else 0.0
     traffic = traffic_record("k_apply_l0", args.prec, workload)
     traffic_hv = traffic_record("k_hv_range", args.prec, workload)
     if args.copy_probe:
@@ -383,6 +492,7 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+    alpha_hist = [sum(r["alpha_hist"][q] for r in recs) for q in range(8)]
 
     out = {
         "metric": METRIC,
@@ -401,10 +511,22 @@ def main():
             "workload": workload,
             "vertices": int(sc.N), "tets": int(sc.T), "stencils": int(sc.pool['key'].size),
             "levels": int(ctx.levels), "K": int(ctx.cfg.max_rank),
+            "arithmetic": "f64 (vectors, barrier sums, capacitance, 2x2 solve; products with stored blocks "
+                          "accumulate in f64)",
             "block_storage": args.prec, "hessian_storage": hess_prec,
+            "timed_steps": "blocks of %d iterations, each from the scene's start (x^0, a restart)" % BLOCK,
             "restarts_in_timed_steps": int(restarts),
             "stored_block_precisions": solver.precision_counts,
         },
+        "active_contacts_per_step": {"mean": float(np.mean(actives)), "min": int(min(actives)),
+                                     "max": int(max(actives))},
+        "restart_fraction": restarts / args.steps,
+        "counters_pass": "active contacts, step sizes, fallbacks, update bytes: an untimed pass over the same "
+                         "blocks with per-iteration counters",
+        "alpha_hist_subdomains": {"bins": "[0] alpha = 1, [i] alpha in [2^-i, 2^(1-i)) for i = 1..6, [7] < 2^-6",
+                                  "counts": alpha_hist},
+        "safe_step_fallbacks": int(sum(1 for r in recs if r["safe_left"] > 0)),
+        "descent_halvings": int(sum(1 for r in recs if r["scale"] < 1.0)),
         "mas_apply_GBps": achieved,
         "roofline": {
             "kernel": "k_apply_l0 (level-0 blocks + Woodbury correction of mas_apply)",
@@ -419,6 +541,13 @@ def main():
             "traffic": traffic_hv, "bytes_per_launch": hv_b, "active_base_stencils": n_active,
             "launches": int(n_hv), "avg_us": 1e3 * ms_hv / max(n_hv, 1),
         },
+        "roofline_woodbury_update": {
+            "call": "mas_woodbury_update (classification, Top-K, capacitance; all its launches)",
+            "bound": "hbm", "achieved": up_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": up_achieved / HBM_PEAK_GBS,
+            "bytes_per_call": up_mean,
+            "calls": int(n_up), "avg_us": 1e3 * ms_up / max(n_up, 1),
+        },
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in timers.items()},
         "woodbury_rank_hist": hist_sum,
         "gnorm_rel": solver.log[-1]["gnorm"] / solver.g0norm if solver.g0norm else None,
@@ -431,10 +560,13 @@ def main():
     out["contact_narrow_phase"] = contact_measure(ctx, solver, sc.dhat)
     out["constraint_set"] = constraint_set_measure(ctx, sc, solver.x)
     out["hbm_probe"] = hbm_probe()
+    solver.ctx.close()
+    del solver, ctx
+    torch.cuda.empty_cache()
+    if not args.no_warm:
+        print("[bench] warm frame", file=sys.stderr, flush=True)
+        out["warm_frame"] = warm_frame(sc, args.prec, hess_prec, 60)
     if not args.no_solve:
-        solver.ctx.close()
-        del solver, ctx
-        torch.cuda.empty_cache()
         out["tol_solve"] = tolerance_solves(sc, ("f64", "f32", "bf16", "f16"), args.solve_tol,
                                             args.solve_max_iter, args.solve_repeats)
     if not args.no_cpu_baseline:

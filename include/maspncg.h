@@ -157,7 +157,8 @@ typedef struct {
   int64_t rank_sum;        /* sum over level-0 subdomains of the kept rank r_d */
   int32_t rank_max;        /* largest r_d */
   int32_t safe_rounds;     /* damping rounds of the last mas_safe_step that damped a subdomain */
-  int64_t safe_left;       /* stencils still closing below 0.05 d after the last round */
+  int64_t safe_left;       /* stencils still closing below 0.05 d after the last round
+                              (> 0: the any-mix fallback bound was taken) */
   int64_t alpha_hist[8];   /* level-0 subdomains by the last safe step alpha_d: [0] alpha = 1,
                               [i] alpha in [2^-i, 2^(1-i)) for i = 1..6, [7] alpha < 2^-6 */
 } mas_iter_stats;
@@ -250,6 +251,12 @@ mas_status mas_energy_grad(void* ctx, const double* x, const double* x_tilde,
 /* x~ = x^t + h v^t + h^2 gravity (device vectors). */
 mas_status mas_inertial_target(void* ctx, const double* x_t, const double* v_t, double* x_tilde);
 
+/* The next time step of implicit Euler (Algorithm 1's inputs x^t, v^t): after
+ * a step from x_old to x_new, v = (x_new - x_old) / h and
+ * x~ = x_new + h v + h^2 gravity.  Device vectors of 3N; v or x_tilde may be
+ * NULL; x_new and x_old may not alias the outputs. */
+mas_status mas_next_frame(void* ctx, const double* x_new, const double* x_old, double* v, double* x_tilde);
+
 /* Distances of affine stencils d = grad . x[idx] - off (device arrays). */
 mas_status mas_stencil_distance(void* ctx, const double* x, int64_t m, const int32_t* idx,
                                 const double* grad, const double* off, double* d_out);
@@ -263,9 +270,12 @@ mas_status mas_stencil_distance(void* ctx, const double* x, int64_t m, const int
  * without host synchronisation (a round after one that found nothing does
  * no work), every subdomain of a stencil whose distance would fall below
  * 0.05 d_c under the mixed steps has its step halved.  Writes
- * x_out = x + scale * alpha_{sub(v)} p_v (device, 3N).  A stencil still
- * closing after the last round is left to the caller's energy check
- * (E = +inf at d <= 0), and counted in mas_iter_stats.safe_left.
+ * x_out = x + scale * alpha_{sub(v)} p_v (device, 3N).  If a stencil is
+ * still closing below 0.05 d_c after the last round, every subdomain takes
+ * instead the bound that holds for any mix of steps: a stencil allows
+ * min(1, 0.9 d_c / sum_j max(0, -grad_cj . p_j)), alpha_d the smallest over
+ * the stencils touching d, so no stencil comes below 0.1 d_c; the number of
+ * such stencils is mas_iter_stats.safe_left.
  * cand == NULL reuses the step sizes of the previous call (line-search
  * halving only changes scale).  alpha (device, D_0, nullable) receives the
  * step sizes.  cand->m must not exceed max_contacts. */

@@ -105,6 +105,7 @@ SIGNATURES = {
     "pncg_subspace_step_noalloc": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "mas_energy_grad": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _P, _P]),
     "mas_inertial_target": (_I32, [_P, _P, _P, _P]),
+    "mas_next_frame": (_I32, [_P, _P, _P, _P, _P]),
     "mas_stencil_distance": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
     "mas_safe_step": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _D, _P, _P]),
     "mas_ccd_steps": (_I32, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),

@@ -203,6 +203,9 @@ class MasContext:
         check("mas_energy_grad", _abi.lib().mas_energy_grad(self.h, _ptr(x), _ptr(x_tilde),
                                                            ctypes.byref(c) if c else None, _ptr(E), _ptr(g)))
 
+    def next_frame(self, x_new, x_old, v=None, x_tilde=None):
+        check("mas_next_frame", _abi.lib().mas_next_frame(self.h, _ptr(x_new), _ptr(x_old), _ptr(v), _ptr(x_tilde)))
+
     def inertial_target(self, x_t, v_t, out=None):
         out = self.vec() if out is None else out
         check("mas_inertial_target", _abi.lib().mas_inertial_target(self.h, _ptr(x_t), _ptr(v_t), _ptr(out)))

@@ -190,7 +190,7 @@ mas_status mas_destroy(void* p) {
                   c->hkey, c->hval, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
-                  c->alpha, c->alpha0, c->ahalf, c->around, c->err, c->diag, c->cls_part, c->scan_tmp,
+                  c->alpha, c->alpha0, c->alpha_mix, c->ahalf, c->around, c->err, c->diag, c->cls_part, c->scan_tmp,
                   c->inc_cnt, c->inc_off, c->inc_list, c->coup};
   for (void* q : ptrs)
     if (q) hipFree(q);
@@ -450,6 +450,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->scal, 64));
   TRY(dalloc(&c->alpha, D0));
   TRY(dalloc(&c->alpha0, D0));
+  TRY(dalloc(&c->alpha_mix, D0));
   TRY(dalloc(&c->ahalf, D0));
   TRY(dalloc(&c->around, SAFE_ROUNDS + 1));
   TRY(dalloc(&c->err, 1));
@@ -644,6 +645,13 @@ mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, cons
   // the ordered gather of deterministic mode lists the contacts per vertex
   if (c.cfg.deterministic && g && ct && ct->m > c.cfg.max_contacts) return MAS_ERR_INVALID_ARG;
   return launch_energy_grad(c, x, x_tilde, ct, E, g);
+}
+
+mas_status mas_next_frame(void* p, const double* x_new, const double* x_old, double* v, double* x_tilde) {
+  if (!p || !x_new || !x_old || (!v && !x_tilde)) return MAS_ERR_INVALID_ARG;
+  if (v == x_new || v == x_old || x_tilde == x_new || x_tilde == x_old || (v && v == x_tilde))
+    return MAS_ERR_INVALID_ARG;
+  return launch_next_frame(*as_ctx(p), x_new, x_old, v, x_tilde);
 }
 
 mas_status mas_inertial_target(void* p, const double* x_t, const double* v_t, double* x_tilde) {

@@ -394,6 +394,7 @@ struct Ctx {
   double* fixed_ws = nullptr;      // this device's address of the library's fixed workspace array
   double* alpha = nullptr;         // D0, step sizes of the last safe step
   double* alpha0 = nullptr;        // D0, step sizes before damping
+  double* alpha_mix = nullptr;     // D0, step sizes safe for any mix of steps (fallback)
   uint64_t* ahalf = nullptr;       // D0, bit r: subdomain halved in damping round r
   uint32_t* around = nullptr;      // SAFE_ROUNDS violation counts of the damping rounds
   uint32_t* err = nullptr;         // sticky error bits

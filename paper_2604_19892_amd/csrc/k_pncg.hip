@@ -460,10 +460,11 @@ mas_status launch_subspace(Ctx& c, const double* g, const double* z, const doubl
 }
 
 // ------------------------------------------------------------- safe step
-__global__ void k_alpha_init(int64_t D, double* a0, uint64_t* half, uint32_t* rounds) {
+__global__ void k_alpha_init(int64_t D, double* a0, double* amix, uint64_t* half, uint32_t* rounds) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (i < D) {
     a0[i] = 1.0;
+    amix[i] = 1.0;
     half[i] = 0ull;
   }
   if (i <= SAFE_ROUNDS) rounds[i] = 0u;
@@ -471,30 +472,40 @@ __global__ void k_alpha_init(int64_t D, double* a0, uint64_t* half, uint32_t* ro
 
 // alpha_c = min(1, 0.9 d / s) for a stencil closing at the rate
 // s = -sum_j grad_j . p_j > 0, to every subdomain the stencil touches
+// (alpha); and the fallback bound min(1, 0.9 d / sum_j max(0, -grad_j . p_j)),
+// which holds for any mix of per-vertex steps up to it (amix)
 __global__ __launch_bounds__(256) void k_alpha_stencils(int64_t m, const int32_t* idx, const double* grad,
-                                                        const double* d, const double* p, double* alpha) {
+                                                        const double* d, const double* p, double* alpha,
+                                                        double* amix) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int vi[4] = {-1, -1, -1, -1};
-  double a = INFINITY;
+  double a = INFINITY, am = INFINITY;
   if (i < m) {
     const int4 iv = reinterpret_cast<const int4*>(idx)[i];
     vi[0] = iv.x; vi[1] = iv.y; vi[2] = iv.z; vi[3] = iv.w;
-    double s = 0;  // closing rate of the stencil along p
+    double s = 0;   // closing rate of the stencil along p
+    double sp = 0;  // sum of the vertices' own closing rates
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (vi[j] < 0) continue;
+      double dot = 0.0;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) s -= grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
+      for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
+      s -= dot;
+      sp += fmax(0.0, -dot);
     }
     if (s > 0.0) a = fmax(fmin(1.0, 0.9 * d[i] / s), 0.0);
+    if (sp > 0.0) am = fmax(fmin(1.0, 0.9 * d[i] / sp), 0.0);
   }
-  const bool has = a < 1.0;
-  if (__ballot(has) == 0) return;  // uniform
+  const bool has = a < 1.0, hasm = am < 1.0;
+  if (__ballot(has || hasm) == 0) return;  // uniform
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int sd = vi[j] >> 5;
     const long long key = (has && vi[j] >= 0) ? (long long)sd : -1ll;
     wave_min_pos(key, alpha + (key >= 0 ? sd : 0), a);
+    const long long keym = (hasm && vi[j] >= 0) ? (long long)sd : -1ll;
+    wave_min_pos(keym, amix + (keym >= 0 ? sd : 0), am);
   }
 }
 
@@ -547,9 +558,13 @@ __global__ __launch_bounds__(256) void k_alpha_round(int r, int64_t m, const int
   if (b != 0 && (threadIdx.x & 63) == 0) atomicAdd(rounds + r, uint32_t(__popcll(b)));
 }
 
-__global__ void k_alpha_final(int64_t D, const double* a0, const uint64_t* half, double* alpha) {
+// the damped steps, or, if the last round still found a stencil closing
+// below 0.05 d, the bound for any mix of steps for every subdomain
+__global__ void k_alpha_final(int64_t D, const double* a0, const double* amix, const uint64_t* half,
+                              const uint32_t* rounds, double* alpha) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i < D) alpha[i] = ldexp(a0[i], -__popcll(half[i]));
+  if (i >= D) return;
+  alpha[i] = rounds[SAFE_ROUNDS] != 0u ? amix[i] : ldexp(a0[i], -__popcll(half[i]));
 }
 
 __global__ void k_step(int64_t n3, const double* x, const double* p, const double* alpha, double scale,
@@ -569,17 +584,17 @@ mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_
   const int64_t D = c.lv[0].nsub;
   const dim3 gD((std::max<int64_t>(D, SAFE_ROUNDS + 1) + 255) / 256), b256(256);
   if (cand) {
-    k_alpha_init<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.ahalf, c.around);
+    k_alpha_init<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.alpha_mix, c.ahalf, c.around);
     if (cand->m > 0) {
       const dim3 g((cand->m + 255) / 256);
-      k_alpha_stencils<<<g, b256, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0);
+      k_alpha_stencils<<<g, b256, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0, c.alpha_mix);
       // subdomains moving at different steps: halve the steps of the
       // subdomains of any stencil the combined motion would close
       for (int r = 0; r <= SAFE_ROUNDS; ++r)
         k_alpha_round<<<g, b256, 0, c.s>>>(r, cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0, c.ahalf,
                                            c.around);
     }
-    k_alpha_final<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.ahalf, c.alpha);
+    k_alpha_final<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.alpha_mix, c.ahalf, c.around, c.alpha);
   }
   int64_t n3 = 3 * c.N;
   k_step<<<dim3((n3 + 255) / 256), b256, 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);

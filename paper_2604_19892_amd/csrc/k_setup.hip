@@ -98,6 +98,26 @@ mas_status launch_inertial(Ctx& c, const double* xt, const double* vt, double* x
   return MAS_OK;
 }
 
+// implicit Euler: v = (x_new - x_old) / h, x~ = x_new + h v + h^2 g
+__global__ void k_next_frame(int64_t n3, const double* xn, const double* xo, double h, double g0, double g1,
+                             double g2, double* v, double* xtil) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  const int a = int(i % 3);
+  const double g = a == 0 ? g0 : (a == 1 ? g1 : g2);
+  const double vi = (xn[i] - xo[i]) / h;
+  if (v) v[i] = vi;
+  if (xtil) xtil[i] = xn[i] + h * vi + h * h * g;
+}
+
+mas_status launch_next_frame(Ctx& c, const double* xn, const double* xo, double* v, double* xtil) {
+  const int64_t n3 = 3 * c.N;
+  k_next_frame<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, xn, xo, c.cfg.h, c.cfg.gravity[0],
+                                                             c.cfg.gravity[1], c.cfg.gravity[2], v, xtil);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
 __global__ void k_stencil_distance(int64_t m, const double* x, const int32_t* idx,
                                    const double* grad, const double* off, double* d) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;

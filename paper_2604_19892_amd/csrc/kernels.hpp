@@ -28,10 +28,16 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v);
 void fill_i32(Ctx& c, int32_t* p, int64_t n, int32_t v);
 void fill_f64(Ctx& c, double* p, int64_t n, double v);
 
+// k_invert.hip ---------------------------------------------------------
+// inverts the blocks of level l (FP64 MFMA) and stores them in their
+// chosen precision; completes the next level's diagonal node blocks
+void launch_invert_mfma(Ctx& c, int l);
+
 // k_setup.hip ----------------------------------------------------------
 mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E, const double* nu,
                        double* tmass, const int32_t* voff, const int32_t* vt);
 mas_status launch_inertial(Ctx& c, const double* xt, const double* vt, double* xtil);
+mas_status launch_next_frame(Ctx& c, const double* xn, const double* xo, double* v, double* xtil);
 mas_status launch_stencil_distance(Ctx& c, const double* x, int64_t m, const int32_t* idx,
                                    const double* grad, const double* off, double* d);
 

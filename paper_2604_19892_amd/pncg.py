@@ -36,7 +36,10 @@ class PNCG:
         self.pool_t.__dict__.update(self.pool.__dict__)
         self.pool_t.d = torch.zeros_like(self.pool.d)
         self.x = ctx.to_lib(scene.x)
-        self.xt = ctx.inertial_target(self.x, ctx.to_lib(scene.v))
+        self.x0 = self.x.clone()               # the scene's start
+        self.x_frame = self.x.clone()          # x^t of the current time step
+        self.v_frame = ctx.to_lib(scene.v)     # v^t
+        self.xt = ctx.inertial_target(self.x, self.v_frame)
         v = ctx.vec
         self.x_trial, self.g, self.g_trial = v(), v(), v()
         self.z, self.z_prev, self.vz, self.p, self.vp = v(), v(), v(), v(), v()
@@ -48,6 +51,8 @@ class PNCG:
         self.E_host = float(self.E.item())
         self.restart = True
         self.k = 0
+        self.fk = 0                            # iterations in the current time step
+        self.frames = 0
         self.n_restarts = 0
         self.n_halvings = 0
         self.n_rejected = 0
@@ -67,7 +72,7 @@ class PNCG:
             ctx.woodbury_update(self.pool, self.rank_hist)
         ctx.apply(self.g, self.z)
         ctx.hess_vec(self.z, with_update=False, y=self.vz)
-        ctx.subspace_step(self.g, self.z, self.z_prev if self.k > 0 else None, self.vz, self.p, self.vp,
+        ctx.subspace_step(self.g, self.z, self.z_prev if self.fk > 0 else None, self.vz, self.p, self.vp,
                           self.restart)
         ctx.safe_step(self.x, self.p, self.pool, 1.0, self.x_trial)
         scale = 1.0
@@ -109,7 +114,36 @@ class PNCG:
             self.n_rejected += 1
             self.restart = True
         self.k += 1
+        self.fk += 1
         return st
+
+    def reset(self):
+        """Back to the scene's start (x^0, v^0, its inertial target); the
+        next iteration restarts."""
+        ctx = self.ctx
+        self.x.copy_(self.x0)
+        self.x_frame.copy_(self.x0)
+        self.v_frame.copy_(ctx.to_lib(self.scene.v))
+        ctx.inertial_target(self.x, self.v_frame, self.xt)
+        ctx.stencil_distance(self.x, self.pool)
+        ctx.energy_grad(self.x, self.xt, self.pool, self.E, self.g)
+        self.E_host = float(self.E.item())
+        self.restart = True
+        self.fk = 0
+
+    def next_frame(self):
+        """Ends the time step at the current x (implicit Euler): x^{t+1} = x,
+        v^{t+1} = (x - x^t) / h, a new inertial target, and the next
+        iteration restarts (Algorithm 1 starts every time step with a
+        rebuild)."""
+        ctx = self.ctx
+        ctx.next_frame(self.x, self.x_frame, self.v_frame, self.xt)
+        self.x_frame.copy_(self.x)
+        ctx.energy_grad(self.x, self.xt, self.pool, self.E, self.g)
+        self.E_host = float(self.E.item())
+        self.restart = True
+        self.fk = 0
+        self.frames += 1
 
     def gnorm(self):
         return float(torch.linalg.vector_norm(self.g).item())

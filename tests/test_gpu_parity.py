@@ -227,6 +227,35 @@ def test_stencil_distance_and_safe_step(case):
     assert rel(ctx.from_lib(xo), pncg.step_positions(case.hier, sc.x.reshape(-1), p, 0.5 * ao)) < 1e-14
 
 
+def test_safe_step_fallback_when_rounds_do_not_separate(case):
+    """A stencil across two subdomains with no net closing rate but one
+    vertex closing fast, beside a stencil holding one subdomain to a small
+    step: 16 damping rounds cannot separate it at d = 1e-9, and every
+    subdomain takes the bound for any mix of steps (oracle: the same
+    rule)."""
+    sc, hier = case.scene, case.hier
+    r = hier.rank
+    va = int(np.flatnonzero(r // 32 == 0)[0])
+    vb, vb2 = (int(v) for v in np.flatnonzero(r // 32 == 1)[:2])
+    idx = np.array([[va, vb, -1, -1], [vb2, -1, -1, -1]], np.int32)
+    grad = np.zeros((2, 12))
+    grad[0, 2], grad[0, 5], grad[1, 2] = 1.0, -1.0, 1.0
+    d = np.array([1e-9, 1e-3])
+    p = np.zeros(3 * sc.N)
+    p[[3 * va + 2, 3 * vb + 2, 3 * vb2 + 2]] = -1.0
+    cset = synth.contact_set(np.array([1, 2], np.uint64), idx, grad, d)
+    ao = pncg.safe_alpha(hier, idx, grad, d, p)
+    assert ao[0] == pytest.approx(0.9e-9)
+    ctx = case.ctx
+    alpha = case.torch.zeros(hier.num_subdomains(0), dtype=case.torch.float64, device="cuda")
+    xo = ctx.vec()
+    ctx.safe_step(case.x, ctx.to_lib(p), ctx.contacts(cset), 1.0, xo, alpha)
+    np.testing.assert_allclose(alpha.cpu().numpy(), ao, rtol=1e-12)
+    assert ctx.stats()['safe_left'] > 0
+    code, msg = ctx.sync()
+    assert code == 0, msg
+
+
 def test_apply_after_rebuild_without_update(case):
     ctx = case.ctx
     ctx.build(case.x, case.dbase)

@@ -43,3 +43,31 @@ def test_pncg_reaches_tolerance(prec):
     assert rel <= 1e-6
     # the library's norm of the gradient the last iteration started from
     assert gpu.log[-1]["gnorm"] <= 1e-6 * gpu.g0norm * 1.0000001
+
+
+def test_next_frame_and_later_time_steps():
+    """mas_next_frame against implicit Euler written out (v = (x1 - x0)/h,
+    x~ = x1 + h v + h^2 g), and three time steps of the two-box scene in a
+    row, each solved to 1e-6 of its first gradient with finite energies."""
+    import torch
+    from oracle import fem
+    from paper_2604_19892_amd.pncg import PNCG
+    sc = synth.two_boxes_scene(active_frac=0.8)
+    s = PNCG(sc, block_prec="f32", hess_prec="f32")
+    x0 = s.ctx.from_lib(s.x)
+    for f in range(3):
+        it, secs, rel = s.solve(rel_tol=1e-6, max_iter=600)
+        print("two boxes, time step %d: %d iterations, %d restarts so far" % (f, it, s.n_restarts))
+        assert rel <= 1e-6, (f, rel)
+        assert np.isfinite(s.E_host)
+        x1 = s.ctx.from_lib(s.x)
+        s.next_frame()
+        v = (x1 - x0) / sc.h
+        xt = fem.inertial_target(x1.reshape(-1, 3), v.reshape(-1, 3), sc.h, sc.gravity).reshape(-1)
+        assert np.allclose(s.ctx.from_lib(s.v_frame), v, rtol=1e-13, atol=1e-13 * np.abs(v).max())
+        assert np.allclose(s.ctx.from_lib(s.xt), xt, rtol=1e-14, atol=1e-14 * np.abs(xt).max())
+        x0 = x1
+    code, msg = s.ctx.sync()
+    assert code == 0, msg
+    s.ctx.close()
+    torch.cuda.empty_cache()
