@@ -155,14 +155,6 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
 }
 
 // ---------------------------------------------------------------------------
-// 1/x: hardware reciprocal refined by two Newton steps (x positive, normal)
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
 
 // place a 3x3 block (pair of local nodes li, lj) into the packed lower matrix
 template <bool DET>
@@ -401,260 +393,8 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Block inversion.  One workgroup per block; thread t < 136 keeps the 6x6
-// tile (ti, tj), ti >= tj, of the 16x16 tile grid in registers from load to
-// store (t = ti (ti + 1) / 2 + tj).
-//
-// The inverse comes from the symmetric sweep operator (Goodnight 1979):
-// sweeping pivot k maps a_kk to -1/a_kk, a_ik and a_kj to a_ik/a_kk and
-// a_kj/a_kk, and every other a_ij to a_ij - a_ik a_kj / a_kk; after all
-// pivots the matrix is -A^-1.  The block is first scaled to unit diagonal
-// (sc_i = a_ii^-1/2).  The three updates of a step are one rank-1 product
-// R -= u w^T with u the pivot column, its pivot entry lowered by 1, and
-// w = u / a_kk: that leaves a_kk larger by exactly 2, an entry no later step
-// reads, so 2 is taken off at the end (the diagonal of the scaled inverse is
-// at least 1, so this costs no accuracy).  The pivot column passes through
-// LDS, double-buffered, one barrier per pivot.
-constexpr int INV_THREADS = 192;
-
-__device__ __forceinline__ void tri_tile(int t, int& ti, int& tj) {
-  ti = 0;
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  tj = t - ti * (ti + 1) / 2;
-}
-
-// Store the final tile F (values of A^-1, 16-bit: divided by sig_i sig_j) in
-// the tiled layout of the block products.  Off-diagonal tiles own whole
-// 8-byte units; diagonal tiles share units with their pair partner and store
-// entry by entry.
-template <int P>
-__device__ __forceinline__ void store_tile(unsigned char* slot, int ti, int tj, const double (&F)[6][6]) {
-  constexpr int EPU = tile_epu(P);
-  if (ti > tj) {
-    const int o = ti * (ti - 1) / 2 + tj;
-    uint2* s2 = reinterpret_cast<uint2*>(slot);
-#pragma unroll
-    for (int k = 0; k < tile_uo(P); ++k) {
-      uint2 u;
-      if constexpr (P == MAS_F64) {
-        const double v = F[k / 6][k % 6];
-        u.x = uint32_t(__double2loint(v));
-        u.y = uint32_t(__double2hiint(v));
-      } else if constexpr (P == MAS_F32) {
-        u.x = __float_as_uint(float(F[(2 * k) / 6][(2 * k) % 6]));
-        u.y = __float_as_uint(float(F[(2 * k + 1) / 6][(2 * k + 1) % 6]));
-      } else {
-        uint32_t h[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float f = float(F[(4 * k + q) / 6][(4 * k + q) % 6]);
-          h[q] = (P == MAS_BF16) ? f32_to_bf16(f) : f32_to_f16(f);
-        }
-        u.x = h[0] | (h[1] << 16);
-        u.y = h[2] | (h[3] << 16);
-      }
-      st_once(s2 + tile_unit(P, o, k), u);
-    }
-  } else {
-    const int m = ti / 2, h = ti & 1;
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int q = 0; q <= r; ++q) {
-        const int e = 21 * h + r * (r + 1) / 2 + q;
-        const int pos = tile_unit(P, 120 + m, e / EPU) * EPU + e % EPU;
-        if constexpr (P == MAS_F64) reinterpret_cast<double*>(slot)[pos] = F[r][q];
-        else if constexpr (P == MAS_F32) reinterpret_cast<float*>(slot)[pos] = float(F[r][q]);
-        else
-          reinterpret_cast<uint16_t*>(slot)[pos] =
-              (P == MAS_BF16) ? f32_to_bf16(float(F[r][q])) : f32_to_f16(float(F[r][q]));
-      }
-  }
-}
-
-// Inverts the packed float64 blocks of one level (rows and columns of nodes
-// beyond the node count are identity) and stores each in the requested
-// precision, or a wider one when kappa = max_i M_ii B_ii exceeds
-// guard / (20 eps): the spectral norm of the rounding error of a
-// unit-diagonal 96x96 matrix is about 20 eps, and 1/kappa bounds its smallest
-// eigenvalue from above.  With acc_next, the sum of all 3x3 blocks of the
-// block (before inversion) becomes the diagonal block of node d at the next
-// level (C_(l+1) sums the nodes of d).
-__global__ __launch_bounds__(INV_THREADS) void k_invert_blocks(int64_t nodes, const double* acc, void* blk,
-                                                               float* scale, uint8_t* bprec, int req, double guard,
-                                                               uint32_t* err, DiagRec* dg, int level,
-                                                               double* acc_next) {
-  __shared__ __align__(16) double col[2][BD];
-  __shared__ double pv[2], pinv[2];
-  __shared__ __align__(16) double sc[BD];
-  __shared__ float sig[BD];
-  __shared__ double red[9][4];
-  __shared__ int chosen;
-  const int64_t d = blockIdx.x;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  const bool act = t < 136;
-  int ti = 0, tj = 0;
-  if (act) tri_tile(t, ti, tj);
-  const bool dtile = act && ti == tj;
-  const double* src = acc + d * PK;
-  const int valid = int(min<int64_t>(SUB, nodes - SUB * d));
-  double R[6][6];
-#pragma unroll
-  for (int r = 0; r < 6; ++r)
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int i = 6 * ti + r, j = 6 * tj + q;
-      const bool pad = i / 3 >= valid || j / 3 >= valid;
-      R[r][q] = 0.0;
-      if (act) R[r][q] = pad ? (i == j ? 1.0 : 0.0) : src[i >= j ? pk(i, j) : pk(j, i)];
-    }
-  if (acc_next) {
-    double s9[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) s9[q] = 0.0;
-#pragma unroll
-    for (int nr = 0; nr < 2; ++nr)
-#pragma unroll
-      for (int nq = 0; nq < 2; ++nq) {
-        if (!act || 2 * ti + nr >= valid || 2 * tj + nq >= valid) continue;
-#pragma unroll
-        for (int x = 0; x < 3; ++x)
-#pragma unroll
-          for (int y = 0; y < 3; ++y) {
-            const double v = R[3 * nr + x][3 * nq + y];
-            s9[3 * x + y] += v;
-            if (!dtile) s9[3 * y + x] += v;
-          }
-      }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const double v = wave_sum(s9[q]);
-      if (lane == 0) red[q][wv] = v;
-    }
-  }
-  if (dtile) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r) sc[6 * ti + r] = 1.0 / sqrt(R[r][r]);
-  }
-  __syncthreads();
-  if (acc_next && t < 9 && (t / 3) >= (t % 3)) {
-    const int ln = int(d & 31);
-    acc_next[(d >> 5) * PK + pk(3 * ln + t / 3, 3 * ln + t % 3)] = red[t][0] + red[t][1] + red[t][2];
-  }
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int q = 0; q < 6; ++q) R[r][q] *= sc[6 * ti + r] * sc[6 * tj + q];
-  }
-  int bad_k = -1;
-  double bad_v = 0.0;
-  for (int kb = 0; kb < BD / 6; ++kb) {
-#pragma unroll
-    for (int kr = 0; kr < 6; ++kr) {
-      const int k = 6 * kb + kr;
-      double* cb = col[kr & 1];
-      if (act) {
-        if (tj == kb) {
-#pragma unroll
-          for (int r = 0; r < 6; ++r) cb[6 * ti + r] = (ti == kb && r == kr) ? R[r][kr] - 1.0 : R[r][kr];
-          if (ti == kb) {
-            pv[kr & 1] = R[kr][kr];
-            pinv[kr & 1] = rcp_nr(R[kr][kr]);  // once here instead of in every thread
-          }
-        } else if (ti == kb) {
-#pragma unroll
-          for (int q = 0; q < 6; ++q) cb[6 * tj + q] = R[kr][q];
-        }
-      }
-      __syncthreads();
-      const double p = pv[kr & 1];
-      if (bad_k < 0 && !(p > 0.0 && isfinite(p))) {
-        bad_k = k;
-        bad_v = p;
-      }
-      const double inv = pinv[kr & 1];
-      if (act) {
-        double ci[6], cj[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) ci[r] = cb[6 * ti + r];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) cj[q] = cb[6 * tj + q] * inv;
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int q = 0; q < 6; ++q) R[r][q] -= ci[r] * cj[q];
-      }
-    }
-  }
-  if (bad_k >= 0 && t == 0) {
-    atomicOr(err, ERRB_NOT_SPD);
-    diag_report(dg, level == 0 ? 1 : 2, level, d, bad_k, bad_v);
-  }
-  // kappa = max_i M_ii B_ii = max_i of the scaled inverse's diagonal
-  double kap = 0.0;
-  if (dtile) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r) kap = fmax(kap, 2.0 - R[r][r]);
-  }
-  for (int o = 32; o > 0; o >>= 1) kap = fmax(kap, __shfl_xor(kap, o));
-  if (lane == 0) red[0][wv] = kap;
-  // final values of A^-1 in R
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int q = 0; q < 6; ++q)
-        R[r][q] = (dtile && r == q ? 2.0 - R[r][q] : -R[r][q]) * sc[6 * ti + r] * sc[6 * tj + q];
-  }
-  __syncthreads();
-  if (t == 0) {
-    const double k1 = fmax(fmax(red[0][0], red[0][1]), red[0][2]);
-    int pr = req;
-    while (guard > 0.0 && pr != MAS_F64 && !(k1 <= guard / (20.0 * prec_eps(pr))))
-      pr = (pr == MAS_F32) ? MAS_F64 : MAS_F32;
-    chosen = pr;
-    bprec[d] = uint8_t(pr);
-  }
-  __syncthreads();
-  const int P = chosen;
-  unsigned char* slot = reinterpret_cast<unsigned char*>(blk) + d * BLK_STRIDE;
-  if (P == MAS_BF16 || P == MAS_F16) {
-    // 16-bit storage keeps B_ij / (sig_i sig_j), sig_i = sqrt(B_ii)
-    if (dtile) {
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        const float sgv = float(sqrt(R[r][r]));
-        sig[6 * ti + r] = sgv;
-        scale[d * BD + 6 * ti + r] = sgv;
-      }
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 6; ++r)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) R[r][q] /= double(sig[6 * ti + r]) * double(sig[6 * tj + q]);
-    }
-  }
-  if (!act) return;
-  switch (P) {
-    case MAS_F64: store_tile<MAS_F64>(slot, ti, tj, R); break;
-    case MAS_F32: store_tile<MAS_F32>(slot, ti, tj, R); break;
-    case MAS_BF16: store_tile<MAS_BF16>(slot, ti, tj, R); break;
-    default: store_tile<MAS_F16>(slot, ti, tj, R);
-  }
-}
-
-static void launch_invert(Ctx& c, int l) {
-  Level& Lv = c.lv[l];
-  k_invert_blocks<<<dim3(Lv.nsub), dim3(INV_THREADS), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, Lv.bprec,
-                                                                 Lv.prec,
-                                                         c.cfg.prec_guard, c.err, c.diag, l,
-                                                         l + 1 < c.L ? c.lv[l + 1].acc : nullptr);
-}
+// Block inversion: k_invert.hip (FP64 MFMA, one wavefront per block).
+static void launch_invert(Ctx& c, int l) { launch_invert_mfma(c, l); }
 
 __global__ void k_zero(double* p, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
