@@ -7,7 +7,8 @@ Test infrastructure (see the package docstring).
   step.  The standard bound (Eq. (23)) adds the largest displacement on each
   side; the frame-invariant bound takes the largest relative displacement
   of a vertex pair across the primitives (Eq. (29) point-triangle,
-  Eq. (31) edge-edge), which is never larger.  alpha_l = dist / l.
+  Eq. (31) edge-edge), which is never larger.  alpha_l = d_min / l with
+  d_min = 0.9 dist (see ``pair_step``).
 * Coplanarity cubic (supplement Section 3.4): f(t) is the signed volume of
   the tetrahedron spanned by the four vertices at x + t p.  Its coefficients
   are obtained here by evaluating the determinant at t = 0, 1, 2, 3 and
@@ -124,10 +125,19 @@ def cubic_safe(coef, alpha_l):
     return 1.0
 
 
+D_MIN_FRACTION = 0.9
+
+
 def pair_step(x4, p4, kind, dist):
-    """Safe step of one pair: alpha_l = dist / l_tight, then CubicSafe."""
+    """Safe step of one pair: alpha_l = d_min / l_tight, then CubicSafe.
+    The supplement leaves d_min open; the reading here is d_min = 0.9 dist
+    (the conservative fraction of additive CCD), so that a coplanarity root
+    before alpha_l is always a crossing of the plane away from the other
+    primitive (the pair is still at least 0.1 dist apart there) and a pair
+    that meets exactly at dist / l_tight (a pure approach along the
+    contact normal) is found by CubicSafe instead of being skipped."""
     l = l_tight(p4, kind)
-    alpha_l = dist / l if l > 0.0 else np.inf
+    alpha_l = D_MIN_FRACTION * dist / l if l > 0.0 else np.inf
     return cubic_safe(cubic_coefficients(x4, p4), alpha_l)
 
 

@@ -151,3 +151,52 @@ def step_positions(hier, x, p, alpha):
     """x + S_d^T alpha_d S_d p for every subdomain (Algorithm 1)."""
     a = alpha[hier.rank // 32]
     return (np.asarray(x).reshape(-1, 3) + a[:, None] * np.asarray(p).reshape(-1, 3)).reshape(-1)
+
+
+def ccd_safe_alpha(hier, x, p, radius, pairs, kinds, dist):
+    """Per-subdomain steps on point-triangle / edge-edge pairs (Algorithm 1's
+    ConservativeCCD and per-subdomain alpha_d; Section 4.4; supplement
+    Section 3).  Each subdomain starts at the smallest CCD step along p
+    (``oracle.ccd.pair_step``) of the candidate pairs with a vertex in it,
+    capped at radius / (2 max_v |p_v|) (candidates are every pair closer
+    than radius; no two vertices approach each other by more than the cap
+    allows, so the others cannot meet).  A pair whose vertices lie in
+    subdomains with different steps is checked by the CCD along its
+    vertices' actual displacements; while one finds a root before 1, the
+    steps of its subdomains are halved (at most SAFE_ROUNDS rounds).  If a
+    pair is left after that, every subdomain takes the smallest step (one
+    common step along p, which the CCD covers)."""
+    from . import ccd
+    X = np.asarray(x, np.float64).reshape(-1, 3)
+    P = np.asarray(p, np.float64).reshape(-1, 3)
+    D = hier.num_subdomains(0)
+    alpha = np.ones(D)
+    sub = hier.rank[np.asarray(pairs, np.int64)] // 32 if len(pairs) else np.zeros((0, 4), np.int64)
+    for i in range(len(pairs)):
+        a = ccd.pair_step(X[pairs[i]], P[pairs[i]], kinds[i], dist[i])
+        for s in sub[i]:
+            alpha[s] = min(alpha[s], a)
+    pmax = float(np.max(np.linalg.norm(P, axis=1))) if P.size else 0.0
+    if pmax > 0.0:
+        alpha = np.minimum(alpha, min(1.0, radius / (2.0 * pmax)))
+    common = alpha.min()   # one step along p for every subdomain
+
+    def violating(a):
+        marked = np.zeros(D, bool)
+        for i in range(len(pairs)):
+            s = a[sub[i]]
+            if np.all(s == s[0]):
+                continue
+            step = ccd.pair_step(X[pairs[i]], s[:, None] * P[pairs[i]], kinds[i], dist[i])
+            if step < 1.0:
+                marked[sub[i]] = True
+        return marked
+
+    for _ in range(SAFE_ROUNDS):
+        marked = violating(alpha)
+        if not marked.any():
+            return alpha
+        alpha = np.where(marked, 0.5 * alpha, alpha)
+    if not violating(alpha).any():
+        return alpha
+    return np.full(D, common)

@@ -1,4 +1,6 @@
-"""The PNCG loop of Algorithm 1 on the affine contact pool (FP64).
+"""The PNCG loop of Algorithm 1 (FP64): on the affine contact pool
+(``OraclePNCG``) and on geometric point-triangle / edge-edge contacts of a
+boundary surface (``OracleGeoPNCG``).
 
 Test infrastructure (see the package docstring).  Every iteration follows
 Algorithm 1 with full-rebuild semantics for the preconditioner blocks:
@@ -18,7 +20,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fem, mas, woodbury, pncg
+from . import constraint_set as CS
+from . import contact, fem, mas, woodbury, pncg
 
 
 def pool_distance(pool, x):
@@ -90,6 +93,112 @@ class OraclePNCG:
                              mu=mu, nu=nu, r=r, restart=self.restart, fallback=fb, E=E0,
                              m=int(C['key'].size), accepted=accepted))
         # without a decrease the point is kept and the next iteration restarts
+        self.restart = (r > self.delta) or not accepted
+        self.z_prev = z
+        self.p = p
+        if accepted:
+            self.x = xn
+        return g, z, p
+
+
+def pair_keys(pairs, kinds, verts, tris, edges):
+    """Contact identities of geometric pairs (the reading of Section 4.1.1's
+    contact identity): the kind (tag 2 point-triangle, 3 edge-edge, bits
+    60-63) and the two primitives' indices in the surface lists, 30 bits
+    each (vertex index in verts and triangle index in tris; the two edge
+    indices, smaller first)."""
+    vpos = {int(v): i for i, v in enumerate(verts)}
+    tpos = {tuple(int(a) for a in t): i for i, t in enumerate(np.asarray(tris).reshape(-1, 3))}
+    epos = {tuple(int(a) for a in e): i for i, e in enumerate(np.asarray(edges).reshape(-1, 2))}
+    keys = np.zeros(len(pairs), np.uint64)
+    for n, (p, k) in enumerate(zip(pairs, kinds)):
+        if k == contact.PT:
+            a, b = vpos[int(p[0])], tpos[tuple(int(q) for q in p[1:])]
+        else:
+            a, b = epos[(int(p[0]), int(p[1]))], epos[(int(p[2]), int(p[3]))]
+            a, b = min(a, b), max(a, b)
+        keys[n] = (np.uint64(2 + int(k)) << np.uint64(60)) | (np.uint64(a) << np.uint64(30)) | np.uint64(b)
+    return keys
+
+
+class OracleGeoPNCG:
+    """Algorithm 1 on the geometric contacts of a boundary surface (verts,
+    tris, edges): ComputeConstraintSet at the head of each iteration
+    (brute force, ``oracle.constraint_set``) with distances and gradients
+    from ``oracle.contact``; RebuildMAS or the Woodbury update against it;
+    the subspace step; ConservativeCCD over the pairs within ``radius`` for
+    the per-subdomain steps (``pncg.ccd_safe_alpha``); the descent check
+    with the contact set of the trial point; the restart test."""
+
+    def __init__(self, scene, surface, radius, levels=None, K=None, delta=0.3,
+                 cos_rot=np.cos(np.deg2rad(25.0)), max_halvings=8):
+        self.scene = scene
+        self.verts, self.tris, self.edges = surface
+        self.radius = float(radius)
+        self.prob = fem.Problem(scene)
+        self.hier = mas.Hierarchy(scene.X, levels or scene.levels)
+        self.K = K or scene.K
+        self.delta = delta
+        self.cos_rot = cos_rot
+        self.max_halvings = max_halvings
+        self.x_tilde = fem.inertial_target(scene.x, scene.v, scene.h, scene.gravity).reshape(-1)
+        self.x = np.asarray(scene.x, np.float64).reshape(-1).copy()
+        self.restart = True
+        self.p = np.zeros_like(self.x)
+        self.z_prev = None
+        self.log = []
+
+    def pairs_within(self, x, dist):
+        pairs, kinds, d = CS.constraint_set(x, self.verts, self.tris, self.edges, dist)
+        return np.asarray(pairs, np.int64).reshape(-1, 4), np.asarray(kinds, np.int64), np.asarray(d)
+
+    def constraint_set(self, x):
+        pairs, kinds, _ = self.pairs_within(x, self.prob.dhat)
+        d, grad, _ = contact.contact_distances(x, pairs, kinds)
+        return {'key': pair_keys(pairs, kinds, self.verts, self.tris, self.edges), 'idx': pairs,
+                'grad': grad, 'd': d, 'kind': kinds}
+
+    def iterate(self):
+        prob, hier = self.prob, self.hier
+        x = self.x
+        C = self.constraint_set(x)
+        if self.restart:
+            self.H_base = prob.assemble(x, C)
+            self.mas = mas.MAS(hier, self.H_base)
+            self.base = C
+            blocks = self.mas.fine
+            U = None
+        else:
+            dS, u, _ = woodbury.classify(prob, self.base, C, self.cos_rot)
+            sel = woodbury.topk(hier, C, dS, u, self.K)
+            blocks = woodbury.updated_blocks(hier, self.H_base, C, u, sel)
+            U = woodbury.global_U(prob, C, u, dS)
+        g = prob.gradient(x, self.x_tilde, C)
+        z = self.mas.apply(g, blocks)
+
+        def Hmul(v):
+            y = self.H_base @ v
+            if U is not None:
+                y = y + U @ (U.T @ v)
+            return y
+
+        mu, nu, p, fb, *_ = pncg.subspace_step(g, z, self.p, Hmul, self.restart)
+        cp, ck, cd = self.pairs_within(x, self.radius)
+        alpha = pncg.ccd_safe_alpha(hier, x, p, self.radius, cp, ck, cd)
+        E0 = prob.energy(x, self.x_tilde, C)
+        accepted = False
+        scale = 1.0
+        for _ in range(self.max_halvings + 1):
+            xn = pncg.step_positions(hier, x, p, scale * alpha)
+            if prob.energy(xn, self.x_tilde, self.constraint_set(xn)) <= E0:
+                accepted = True
+                break
+            scale *= 0.5
+        r = pncg.restart_ratio(g, self.z_prev, z) if self.z_prev is not None else 0.0
+        self.log.append(dict(gnorm=float(np.linalg.norm(g)), znorm=float(np.linalg.norm(z)),
+                             mu=mu, nu=nu, r=r, restart=self.restart, fallback=fb, E=E0,
+                             m=int(C['key'].size), accepted=accepted, alpha=alpha, scale=scale,
+                             candidates=int(len(cp))))
         self.restart = (r > self.delta) or not accepted
         self.z_prev = z
         self.p = p

@@ -132,3 +132,23 @@ def test_pair_step_frame_invariant_and_safe(kind):
         coef = ccd.cubic_coefficients(x, p)
         r = _first_root(coef, 0.0)
         assert (r is None and a1 == 1.0) or a1 <= r + 1e-12
+
+
+def test_tight_lower_bound_normal_approach():
+    """A point falling straight onto a triangle, the triangle moving away
+    more slowly: the time of contact t_c is exactly dist / l_tight, where
+    rounding can leave f past its root.  The step comes before the contact
+    (the point stays above the plane), no earlier than the lower bound
+    0.9 t_c, and within the bisection's 2^-16 of t_c when that is finer."""
+    for gap, vt in ((1e-9, 0.3), (1e-3, 0.0), (0.25, 0.5), (3e-7, 0.9)):
+        x4 = np.array([[0.1, 0.2, gap], [-1.0, -1.0, 0.0], [1.0, -1.0, 0.0], [0.0, 1.0, 0.0]])
+        p4 = np.array([[0.0, 0.0, -1.0]] + [[0.0, 0.0, -vt]] * 3)
+        t_c = gap / (1.0 - vt)
+        step = ccd.pair_step(x4, p4, ccd.PT, gap)
+        if t_c >= 1.0:
+            assert step == 1.0
+            continue
+        assert 0.9 * t_c * (1.0 - 1e-12) <= step < t_c
+        assert t_c - step <= max(0.1 * t_c, 2.0 ** -16) * (1.0 + 1e-9)
+        z = x4[0, 2] + step * p4[0, 2] - step * p4[1, 2]
+        assert z > 0.0

@@ -9,7 +9,8 @@ property of the affine step bound.
 import numpy as np
 import pytest
 
-from oracle import mas, pncg
+from oracle import ccd, mas, pncg
+from oracle import contact as C
 from paper_2604_19892_amd import synth
 
 
@@ -247,3 +248,102 @@ def test_safe_step_falls_back_when_damping_rounds_do_not_separate():
         vs = idx[c][idx[c] >= 0]
         dd = 1e-3 + (grad[c].reshape(4, 3)[:vs.size] * (xn2.reshape(-1, 3)[vs] - X[vs])).sum()
         assert dd >= 0.05 * 1e-3
+
+
+def _two_subdomain_pt_case(gap):
+    """A point in subdomain 0 above a triangle in subdomain 1, both moving
+    down together (no relative motion along p), and a second point in
+    subdomain 1 falling onto a fixed triangle of subdomain 1 from 0.3."""
+    X = np.random.default_rng(7).uniform(size=(64, 3))
+    hier = mas.Hierarchy(X, 1)
+    r = hier.rank
+    s0 = [int(v) for v in np.flatnonzero(r // 32 == 0)[:1]]
+    s1 = [int(v) for v in np.flatnonzero(r // 32 == 1)[:7]]
+    P, T = s0[0], s1[:3]
+    Q, R = s1[3], s1[4:7]
+    x = X.copy()
+    x[P] = [0.0, 0.0, gap]
+    x[T] = [[-1.0, -1.0, 0.0], [1.0, -1.0, 0.0], [0.0, 1.0, 0.0]]
+    x[Q] = [10.0, 0.0, 0.3]
+    x[R] = [[9.0, -1.0, 0.0], [11.0, -1.0, 0.0], [10.0, 1.0, 0.0]]
+    p = np.zeros_like(x)
+    p[[P] + T] = [0.0, 0.0, -1.0]
+    p[Q] = [0.0, 0.0, -1.0]
+    pairs = np.array([[P] + T, [Q] + R])
+    kinds = np.array([ccd.PT, ccd.PT])
+    dist = np.array([gap, 0.3])
+    return hier, x, p, pairs, kinds, dist
+
+
+def test_ccd_safe_step_falls_back_to_a_common_step():
+    """At a gap of 1e-9 the mixed steps (1 for the moving point, about 0.3 for
+    the triangle held by the other pair) close it by about 0.7, which halving
+    both steps cures only after about 30 rounds: every subdomain takes the
+    smallest step, the CCD step of the falling point, and both pairs stay
+    open along the whole motion."""
+    hier, x, p, pairs, kinds, dist = _two_subdomain_pt_case(1e-9)
+    a2 = ccd.pair_step(x[pairs[1]], p[pairs[1]], ccd.PT, 0.3)
+    assert 0.29 < a2 <= 0.3
+    alpha = pncg.ccd_safe_alpha(hier, x, p, 1.0, pairs, kinds, dist)
+    assert np.all(alpha == a2)
+    for t in np.linspace(0.0, 1.0, 201):
+        xt = pncg.step_positions(hier, x.reshape(-1), p.reshape(-1), t * alpha).reshape(-1, 3)
+        for q, k in zip(pairs, kinds):
+            assert C.pair_distance(xt[q], k)[0] > 0.0
+
+
+def test_ccd_safe_step_damping_rounds_suffice():
+    """At a gap of 0.05 halving both steps separates the pair.  The moving
+    point's subdomain starts at the radius cap 1 / (2 max |p|) = 0.5, the
+    triangle's at the falling point's CCD step a2; k halvings of both leave
+    the relative approach 2^-k (0.5 - a2) no larger than the gap, and k - 1
+    would not.  The result keeps every pair open along the mixed motion."""
+    hier, x, p, pairs, kinds, dist = _two_subdomain_pt_case(0.05)
+    a2 = ccd.pair_step(x[pairs[1]], p[pairs[1]], ccd.PT, 0.3)
+    alpha = pncg.ccd_safe_alpha(hier, x, p, 1.0, pairs, kinds, dist)
+    k = -np.log2(alpha[0] / 0.5)
+    assert k == int(k) and 1 <= k <= 16
+    assert alpha[1] == pytest.approx(a2 * 2.0 ** -k, rel=1e-15)
+    assert alpha[0] - alpha[1] <= 0.05
+    assert 2.0 * (alpha[0] - alpha[1]) >= 0.05 * (1.0 - 1e-12)
+    for t in np.linspace(0.0, 1.0, 201):
+        xt = pncg.step_positions(hier, x.reshape(-1), p.reshape(-1), t * alpha).reshape(-1, 3)
+        for q, kk in zip(pairs, kinds):
+            assert C.pair_distance(xt[q], kk)[0] > 0.0
+
+
+def test_ccd_safe_step_radius_cap():
+    """No pair within the radius: every step is radius / (2 max |p|)."""
+    X = np.random.default_rng(3).uniform(size=(40, 3))
+    hier = mas.Hierarchy(X, 1)
+    p = np.zeros_like(X)
+    p[5] = [0.0, 2.0, 0.0]
+    alpha = pncg.ccd_safe_alpha(hier, X, p, 0.5, np.zeros((0, 4), np.int64), np.zeros(0, np.int64),
+                                np.zeros(0))
+    assert np.all(alpha == 0.125)
+
+
+def test_ccd_safe_step_keeps_all_surface_pairs_apart():
+    """Two boxes a small gap apart, a random direction with a downward push
+    on the upper box: with the candidates of the radius 2 max |p|, every
+    pair of the surface within 1.5 times that radius (brute force, a
+    superset of the candidates and of every pair the motion could close)
+    stays at a positive distance along the mixed per-subdomain motion."""
+    from oracle import constraint_set as CS
+    sc = synth.two_boxes_scene(nxy=4, nz=3, n_contacts=8)
+    verts, tris, edges = synth.surface(sc.tets)
+    hier = mas.Hierarchy(sc.X, 1)
+    x = sc.x.reshape(-1, 3)
+    rng = np.random.default_rng(11)
+    p = 0.02 * rng.standard_normal(x.shape)
+    p[x[:, 2] > x[:, 2].mean(), 2] -= 0.05
+    radius = 2.0 * np.linalg.norm(p, axis=1).max()
+    cp, ck, cd = CS.constraint_set(x, verts, tris, edges, radius)
+    alpha = pncg.ccd_safe_alpha(hier, x, p, radius, np.asarray(cp), np.asarray(ck), np.asarray(cd))
+    assert np.any(alpha < 1.0)
+    allp, allk, _ = CS.constraint_set(x, verts, tris, edges, 1.5 * radius)
+    assert len(allp) > len(cp)
+    for t in np.linspace(0.0, 1.0, 11):
+        xt = pncg.step_positions(hier, x.reshape(-1), p.reshape(-1), t * alpha).reshape(-1, 3)
+        d, _, _ = C.contact_distances(xt, np.asarray(allp), np.asarray(allk))
+        assert d.min() > 0.0
