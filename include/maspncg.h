@@ -284,7 +284,10 @@ mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_
 
 /* Conservative CCD of point-triangle and edge-edge pairs (supplement
  * Section 3.4, Algorithms 1 and 2).  Per pair: the lower bound
- * alpha_l = dist / l with l the largest relative displacement along p of a
+ * alpha_l = d_min / l, d_min = 0.9 dist (the supplement leaves d_min open;
+ * the margin makes a root before alpha_l a crossing of the plane away from
+ * the other primitive, and finds a pair that meets exactly at dist / l),
+ * with l the largest relative displacement along p of a
  * vertex of one primitive and a vertex of the other (supplement Eqs. (29),
  * (31)); then the coplanarity cubic f(t), the signed volume of the four
  * vertices at x + t p, is cut at its critical points into monotonic pieces
@@ -303,6 +306,28 @@ mas_status mas_safe_step(void* ctx, const double* x, const double* p, const mas_
  * MAS_ERR_INVALID_ARG. */
 mas_status mas_ccd_steps(void* ctx, const double* x, const double* p, int64_t m, const int32_t* pairs,
                          const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
+
+/* Per-subdomain safe steps on point-triangle and edge-edge pairs (Algorithm
+ * 1: ConservativeCCD giving {alpha_d}, x + sum_d S_d^T alpha_d S_d p;
+ * Section 4.4).  alpha_d starts as the smallest mas_ccd_steps step along p
+ * of the candidate pairs with a vertex in subdomain d, capped at
+ * radius / (2 max_v |p_v|): candidates must include every pair closer than
+ * radius, and the cap keeps pairs farther apart from meeting under any
+ * steps.  Vertices of one pair in subdomains with different steps move by
+ * different fractions of p: in up to 16 damping rounds on the device, a
+ * pair whose CCD along its vertices' actual displacements finds a root
+ * before 1 halves the steps of its subdomains; if one is left after the last
+ * round, every subdomain takes the smallest alpha_d (one common step along
+ * p, which the CCD covers), counted in mas_iter_stats.safe_left.  Writes
+ * x_out = x + scale alpha_{sub(v)} p_v (device 3N, 0 <= scale <= 1); alpha
+ * (device D_0, nullable) receives the steps; mas_safe_step with cand = NULL
+ * reuses them with another scale.  pairs, kind, dist (device, m >= 0) as
+ * for mas_ccd_steps (dist: current distances, a lower bound is safe).
+ * MAS_ERR_INVALID_ARG for radius <= 0, scale outside [0, 1] or null
+ * arrays. */
+mas_status mas_ccd_safe_step(void* ctx, const double* x, const double* p, double radius, int64_t m,
+                             const int32_t* pairs, const uint8_t* kind, const double* dist, double scale,
+                             double* alpha, double* x_out);
 
 /* Narrow phase of the contact set: per point-triangle or edge-edge pair the
  * distance d_c that the barrier of Section 3.1 takes, and its gradient
@@ -337,7 +362,13 @@ mas_status mas_contact_distances(void* ctx, const double* x, int64_t m, const in
  * (device int32 2ne): library vertex ids.  Outputs, device, capacity cap:
  * pairs int32 4cap (P, T0, T1, T2 or E1a, E1b, E2a, E2b), kind uint8 cap
  * (0 point-triangle, 1 edge-edge), dist float64 cap, grad float64 12cap
- * (nullable).  *count (host) receives the number of pairs found; only the
+ * (nullable), key uint64 cap (nullable): the contact's identity for the
+ * classification of Section 4.1.1, tag 2 (point-triangle) or 3 (edge-edge)
+ * in bits 60-63, then 30 bits each for the two primitives' indices in the
+ * lists given (the vertex's index in verts and the triangle's in tris, or
+ * the two edges' indices in edges, the smaller first), so a pair keeps its
+ * key across calls over the same lists (nv, nt, ne < 2^30).  *count (host)
+ * receives the number of pairs found; only the
  * first min(count, cap) are written, in no fixed order (call again with a
  * larger cap when count > cap).  Synchronises the stream (it reads the
  * largest primitive extent, which sets the cell side, and the table sizes
@@ -350,7 +381,7 @@ mas_status mas_contact_distances(void* ctx, const double* x, int64_t m, const in
  * coordinate of a listed vertex; both before any pair is written. */
 mas_status mas_constraint_set(void* ctx, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
                               const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
-                              uint8_t* kind, double* dist, double* grad, int64_t* count);
+                              uint8_t* kind, double* dist, double* grad, uint64_t* key, int64_t* count);
 
 /* Synchronises the stream and returns the sticky device error (and clears
  * it); msg (nullable) receives a description. */

@@ -109,9 +109,10 @@ SIGNATURES = {
     "mas_stencil_distance": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
     "mas_safe_step": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _D, _P, _P]),
     "mas_ccd_steps": (_I32, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    "mas_ccd_safe_step": (_I32, [_P, _P, _P, _D, _I64, _P, _P, _P, _D, _P, _P]),
     "mas_contact_distances": (_I32, [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "mas_constraint_set": (_I32, [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.c_int64,
-                                  _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+                                  _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P]),
     "mas_sync_status": (_I32, [_P, ctypes.c_char_p, _I32]),
     "mas_read_stats": (_I32, [_P, ctypes.POINTER(MasIterStats)]),
     "mas_query": (_I32, [_P, _P, _P, _P, _P]),

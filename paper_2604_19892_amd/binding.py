@@ -230,7 +230,7 @@ class MasContext:
         check("mas_contact_distances", _abi.lib().mas_contact_distances(
             self.h, _ptr(x), m, _ptr(pairs), _ptr(kind), _ptr(dist), _ptr(grad), _ptr(type)))
 
-    def constraint_set(self, x, verts, tris, edges, dhat, pairs, kind, dist, grad=None):
+    def constraint_set(self, x, verts, tris, edges, dhat, pairs, kind, dist, grad=None, key=None):
         """Active point-triangle / edge-edge pairs within dhat (device
         tensors in library ids; outputs of capacity pairs.shape[0]).
         Returns the number of pairs found (may exceed the capacity)."""
@@ -238,13 +238,20 @@ class MasContext:
         check("mas_constraint_set", _abi.lib().mas_constraint_set(
             self.h, _ptr(x), float(dhat), int(verts.shape[0]), _ptr(verts), int(tris.shape[0]), _ptr(tris),
             int(edges.shape[0]), _ptr(edges), int(pairs.shape[0]), _ptr(pairs), _ptr(kind), _ptr(dist), _ptr(grad),
-            ctypes.byref(cnt)))
+            _ptr(key), ctypes.byref(cnt)))
         return int(cnt.value)
 
     def safe_step(self, x, p, cand, scale, x_out, alpha=None):
         c = cand.struct() if cand is not None else None
         check("mas_safe_step", _abi.lib().mas_safe_step(self.h, _ptr(x), _ptr(p), ctypes.byref(c) if c else None,
                                                        float(scale), _ptr(alpha), _ptr(x_out)))
+
+    def ccd_safe_step(self, x, p, radius, pairs, kind, dist, m, scale, x_out, alpha=None):
+        """Per-subdomain CCD steps over m candidate pairs within radius, the
+        mixed-step damping rounds, and x_out = x + scale alpha p."""
+        check("mas_ccd_safe_step", _abi.lib().mas_ccd_safe_step(
+            self.h, _ptr(x), _ptr(p), float(radius), int(m), _ptr(pairs), _ptr(kind), _ptr(dist), float(scale),
+            _ptr(alpha), _ptr(x_out)))
 
     def stats(self):
         """Counters of the last Woodbury update and safe step (synchronises)."""

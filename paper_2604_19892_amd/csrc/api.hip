@@ -647,6 +647,15 @@ mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, cons
   return launch_energy_grad(c, x, x_tilde, ct, E, g);
 }
 
+mas_status mas_ccd_safe_step(void* p, const double* x, const double* pdir, double radius, int64_t m,
+                             const int32_t* pairs, const uint8_t* kind, const double* dist, double scale,
+                             double* alpha, double* x_out) {
+  if (!p || !x || !pdir || !x_out || m < 0 || !(radius > 0.0) || !std::isfinite(radius)) return MAS_ERR_INVALID_ARG;
+  if (m > 0 && (!pairs || !kind || !dist)) return MAS_ERR_INVALID_ARG;
+  if (!(scale >= 0.0) || !(scale <= 1.0)) return MAS_ERR_INVALID_ARG;
+  return launch_ccd_safe_step(*as_ctx(p), x, pdir, radius, m, pairs, kind, dist, scale, alpha, x_out);
+}
+
 mas_status mas_next_frame(void* p, const double* x_new, const double* x_old, double* v, double* x_tilde) {
   if (!p || !x_new || !x_old || (!v && !x_tilde)) return MAS_ERR_INVALID_ARG;
   if (v == x_new || v == x_old || x_tilde == x_new || x_tilde == x_old || (v && v == x_tilde))
@@ -689,14 +698,14 @@ mas_status mas_contact_distances(void* p, const double* x, int64_t m, const int3
 
 mas_status mas_constraint_set(void* p, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
                               const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
-                              uint8_t* kind, double* dist, double* grad, int64_t* count) {
+                              uint8_t* kind, double* dist, double* grad, uint64_t* key, int64_t* count) {
   if (!p || !x || !count || !(dhat > 0.0) || !std::isfinite(dhat) || nv < 0 || nt < 0 || ne < 0 || cap < 0)
     return MAS_ERR_INVALID_ARG;
   if ((nv > 0 && !verts) || (nt > 0 && !tris) || (ne > 0 && !edges)) return MAS_ERR_INVALID_ARG;
   if (cap > 0 && (!pairs || !kind || !dist)) return MAS_ERR_INVALID_ARG;
   if (nt > INT32_MAX || ne > INT32_MAX || cap > INT32_MAX) return MAS_ERR_INVALID_ARG;
   return launch_constraint_set(*as_ctx(p), x, dhat, nv, verts, nt, tris, ne, edges, cap, pairs, kind, dist, grad,
-                               count);
+                               key, count);
 }
 
 mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {

@@ -263,9 +263,19 @@ __device__ __forceinline__ double box_dist2(const Box& a, const Box& b) {
   return s;
 }
 
+// Identity of a pair found by the constraint set: the kind (tag 2
+// point-triangle, 3 edge-edge, in bits 60-63) and the indices of its two
+// primitives in the caller's lists (the vertex's index in verts and the
+// triangle's in tris, or the two edges' indices in edges, the smaller
+// first), 30 bits each.  The lists are fixed across calls, so a pair keeps
+// its key from one contact set to the next.
+__device__ __forceinline__ uint64_t pair_key(int kind, int64_t a, int64_t b) {
+  return (uint64_t(2 + kind) << 60) | (uint64_t(a) << 30) | uint64_t(b);
+}
+
 __device__ __forceinline__ void append_pair(unsigned long long* count, int64_t cap, const int (&v)[4], int kind,
                                             double d, const double (&wt)[4], V3 n, int32_t* pairs, uint8_t* kinds,
-                                            double* dist, double* grad) {
+                                            double* dist, double* grad, uint64_t* keys, uint64_t key) {
   const unsigned long long slot = atomicAdd(count, 1ull);
   if (int64_t(slot) >= cap) return;
   const int64_t i = int64_t(slot);
@@ -273,6 +283,7 @@ __device__ __forceinline__ void append_pair(unsigned long long* count, int64_t c
   kinds[i] = uint8_t(kind);
   dist[i] = d;
   if (grad) store_grad(grad, i, wt, n);
+  if (keys) keys[i] = key;
 }
 
 }  // namespace
@@ -399,8 +410,10 @@ __device__ __forceinline__ int64_t wave_reserve(int nb, unsigned long long* coun
 }
 
 __device__ __forceinline__ void write_pair(int64_t slot, int64_t cap, const int (&q)[4], int kind, const double* x,
-                                           int32_t* pairs, uint8_t* kinds, double* dist, double* grad) {
+                                           int32_t* pairs, uint8_t* kinds, double* dist, double* grad,
+                                           uint64_t* keys, uint64_t key) {
   if (slot >= cap) return;
+  if (keys) keys[slot] = key;
   const V3 X[4] = {load_v3(x, q[0]), load_v3(x, q[1]), load_v3(x, q[2]), load_v3(x, q[3])};
   double d, wt[4];
   V3 n;
@@ -415,7 +428,7 @@ __global__ __launch_bounds__(256) void k_cs_query_pt(int64_t nv, const int32_t* 
                                                      const double* x, double h, double dhat, uint64_t hmask,
                                                      const int32_t* off, const uint64_t* ekey, const int32_t* eid,
                                                      int64_t cap, int32_t* pairs, uint8_t* kinds, double* dist,
-                                                     double* grad, unsigned long long* count) {
+                                                     double* grad, uint64_t* keys, unsigned long long* count) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int v = 0, e0 = 0, e1 = 0;
   V3 P{};
@@ -448,7 +461,7 @@ __global__ __launch_bounds__(256) void k_cs_query_pt(int64_t nv, const int32_t* 
         push_hit(hb, t);
         ++nb;
       } else {
-        append_pair(count, cap, q, 0, d, wt, n, pairs, kinds, dist, grad);
+        append_pair(count, cap, q, 0, d, wt, n, pairs, kinds, dist, grad, keys, pair_key(0, i, t));
       }
     }
   }
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(256) void k_cs_query_pt(int64_t nv, const int32_t* 
     if (q < nb) {
       const int t = hb[q];
       const int ids[4] = {v, tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
-      write_pair(s0 + q, cap, ids, 0, x, pairs, kinds, dist, grad);
+      write_pair(s0 + q, cap, ids, 0, x, pairs, kinds, dist, grad, keys, pair_key(0, i, t));
     }
   }
 }
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* 
                                                      double dhat, uint64_t hmask, const int32_t* off,
                                                      const uint64_t* ekey, const int32_t* eid, int64_t cap,
                                                      int32_t* pairs, uint8_t* kinds, double* dist, double* grad,
-                                                     unsigned long long* count, uint32_t* err) {
+                                                     uint64_t* keys, unsigned long long* count, uint32_t* err) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int a0 = 0, a1 = 0, ncell = 0;
   int64_t c0[3] = {0, 0, 0}, span[3] = {1, 1, 1};
@@ -522,7 +535,7 @@ __global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* 
             push_hit(hb, j);
             ++nb;
           } else {
-            append_pair(count, cap, q, 1, d, wt, n, pairs, kinds, dist, grad);
+            append_pair(count, cap, q, 1, d, wt, n, pairs, kinds, dist, grad, keys, pair_key(1, i, j));
           }
         }
       }
@@ -533,7 +546,7 @@ __global__ __launch_bounds__(256) void k_cs_query_ee(int64_t ne, const int32_t* 
       if (q < nb) {
         const int j = hb[q];
         const int ids[4] = {a0, a1, edges[2 * j], edges[2 * j + 1]};
-        write_pair(s0 + q, cap, ids, 1, x, pairs, kinds, dist, grad);
+        write_pair(s0 + q, cap, ids, 1, x, pairs, kinds, dist, grad, keys, pair_key(1, i, j));
       }
     }
   }
@@ -553,7 +566,7 @@ static int64_t pow2_at_least(int64_t n) {
 
 mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
                                  const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
-                                 uint8_t* kind, double* dist, double* grad, int64_t* count) {
+                                 uint8_t* kind, double* dist, double* grad, uint64_t* key, int64_t* count) {
   ProfScope ps(c, MAS_T_CSET);
   *count = 0;
   if (nt > c.cfg.max_tris || ne > c.cfg.max_edges) return MAS_ERR_INVALID_ARG;
@@ -612,11 +625,11 @@ mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t n
   if (nv > 0 && nt > 0)
     k_cs_query_pt<<<dim3((nv + 255) / 256), dim3(256), 0, c.s>>>(nv, verts, tris, x, h, dhat, uint64_t(H[0] - 1),
                                                                   c.cs[0].off, c.cs[0].key, c.cs[0].id, cap, pairs,
-                                                                  kind, dist, grad, cnt);
+                                                                  kind, dist, grad, key, cnt);
   if (ne > 1)
     k_cs_query_ee<<<dim3((ne + 255) / 256), dim3(256), 0, c.s>>>(ne, edges, x, h, dhat, uint64_t(H[1] - 1),
                                                                   c.cs[1].off, c.cs[1].key, c.cs[1].id, cap, pairs,
-                                                                  kind, dist, grad, cnt, c.err);
+                                                                  kind, dist, grad, key, cnt, c.err);
   HIPCHK(hipGetLastError());
   unsigned long long found = 0;
   HIPCHK(hipMemcpyAsync(&found, cnt, sizeof(found), hipMemcpyDeviceToHost, c.s));

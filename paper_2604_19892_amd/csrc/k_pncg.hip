@@ -579,6 +579,19 @@ __global__ void k_copy_f64(const double* src, double* dst, int64_t n) {
     dst[i] = src[i];
 }
 
+// x_out = x + scale alpha_{sub(v)} p_v with the step sizes in c.alpha (and a
+// copy of them to alpha when given)
+mas_status launch_step_with(Ctx& c, const double* x, const double* p, double scale, double* alpha,
+                            double* x_out) {
+  const int64_t D = c.lv[0].nsub;
+  const int64_t n3 = 3 * c.N;
+  k_step<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);
+  if (alpha)
+    k_copy_f64<<<dim3(std::min<int64_t>((D + 255) / 256, 1024)), dim3(256), 0, c.s>>>(c.alpha, alpha, D);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out) {
   const int64_t D = c.lv[0].nsub;

@@ -69,14 +69,19 @@ mas_status launch_subspace_ws(Ctx& c, const double* g, const double* z, const do
                               double* scal);
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out);
+mas_status launch_step_with(Ctx& c, const double* x, const double* p, double scale, double* alpha,
+                            double* x_out);
 
 // k_ccd.hip ------------------------------------------------------------
+mas_status launch_ccd_safe_step(Ctx& c, const double* x, const double* p, double radius, int64_t m,
+                                const int32_t* pairs, const uint8_t* kind, const double* dist, double scale,
+                                double* alpha, double* x_out);
 mas_status launch_ccd(Ctx& c, const double* x, const double* p, int64_t m, const int32_t* pairs,
                       const uint8_t* kind, const double* dist, double* alpha_pair, double* alpha);
 mas_status launch_contact_distances(Ctx& c, const double* x, int64_t m, const int32_t* pairs, const uint8_t* kind,
                                     double* dist, double* grad, uint8_t* type);
 mas_status launch_constraint_set(Ctx& c, const double* x, double dhat, int64_t nv, const int32_t* verts, int64_t nt,
                                  const int32_t* tris, int64_t ne, const int32_t* edges, int64_t cap, int32_t* pairs,
-                                 uint8_t* kind, double* dist, double* grad, int64_t* count);
+                                 uint8_t* kind, double* dist, double* grad, uint64_t* key, int64_t* count);
 
 }  // namespace mas

@@ -30,7 +30,7 @@ def test_header_declares_the_hot_path_calls():
     names = declared_functions()
     for n in ("mas_build", "mas_woodbury_update", "mas_apply", "hess_vec", "pncg_subspace_step"):
         assert n in names
-    assert len(names) == 26
+    assert len(names) == 27
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -83,5 +83,6 @@ def test_argument_errors_return_without_gpu(L):
     assert L.mas_build(None, None, None) == 1
     assert L.mas_ccd_steps(None, None, None, 0, None, None, None, None, None) == 1
     assert L.mas_contact_distances(None, None, 0, None, None, None, None, None) == 1
-    assert L.mas_constraint_set(None, None, 1e-3, 0, None, 0, None, 0, None, 0, None, None, None, None, None) == 1
+    assert L.mas_constraint_set(None, None, 1e-3, 0, None, 0, None, 0, None, 0, None, None, None, None, None,
+                                None) == 1
     assert L.mas_status_string(5) == b"non-positive pivot (matrix not SPD)"

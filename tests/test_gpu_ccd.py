@@ -63,7 +63,7 @@ def test_ccd_steps_match_oracle(scale):
         X = sc.x.reshape(-1, 3)
         for i in np.nonzero(ag < 1.0)[0][:2000]:
             lt = ccd.l_tight(p[pairs[i]], kinds[i])
-            x0 = max(0.0, dist[i] / lt) if lt > 0 else np.inf
+            x0 = max(0.0, 0.9 * dist[i] / lt) if lt > 0 else np.inf
             coef = ccd.cubic_coefficients(X[pairs[i]], p[pairs[i]])
             d, c, b, a = coef
             r = np.roots([a, b, c, d])

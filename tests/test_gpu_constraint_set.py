@@ -28,13 +28,33 @@ def gpu_set(ctx, x, verts, tris, edges, dhat, cap=None):
     kind = torch.zeros(cap, dtype=torch.uint8, device=dev)
     dist = torch.zeros(cap, dtype=torch.float64, device=dev)
     grad = torch.zeros(cap, 12, dtype=torch.float64, device=dev)
-    n = ctx.constraint_set(ctx.to_lib(x), vt, tt, et, dhat, pairs, kind, dist, grad)
+    key = torch.zeros(cap, dtype=torch.int64, device=dev)
+    n = ctx.constraint_set(ctx.to_lib(x), vt, tt, et, dhat, pairs, kind, dist, grad, key)
     code, msg = ctx.sync()
     assert code == 0, msg
     k = min(n, cap)
     inv = np.argsort(r)  # library id -> original id
     P = inv[pairs[:k].cpu().numpy()]
+    check_keys(key[:k].cpu().numpy().view(np.uint64), P, kind[:k].cpu().numpy(), verts, tris, edges)
     return n, P, kind[:k].cpu().numpy(), dist[:k].cpu().numpy(), grad[:k].cpu().numpy()
+
+
+def check_keys(keys, P, K, verts, tris, edges):
+    """Each pair's key names its two primitives in the lists given: tag 2
+    point-triangle (vertex index, triangle index), tag 3 edge-edge (the
+    two edge indices, smaller first); no key twice."""
+    assert len(np.unique(keys)) == len(keys)
+    tag = keys >> np.uint64(60)
+    a = ((keys >> np.uint64(30)) & np.uint64((1 << 30) - 1)).astype(np.int64)
+    b = (keys & np.uint64((1 << 30) - 1)).astype(np.int64)
+    tris = np.asarray(tris).reshape(-1, 3)
+    edges = np.asarray(edges).reshape(-1, 2)
+    for t, i, j, p, k in zip(tag, a, b, P, K):
+        assert int(t) == 2 + int(k)
+        if k == C.PT:
+            assert verts[i] == p[0] and list(tris[j]) == list(p[1:])
+        else:
+            assert i < j and list(edges[i]) == list(p[:2]) and list(edges[j]) == list(p[2:])
 
 
 def as_rows(P, K):
