@@ -68,6 +68,13 @@ class DeviceContacts:
         self.off = (torch.as_tensor(np.ascontiguousarray(off, np.float64), device=device)
                     if off is not None else None)
 
+    @classmethod
+    def from_tensors(cls, key, idx, grad, d):
+        """A view of device tensors (no copies)."""
+        c = cls.__new__(cls)
+        c.key, c.idx, c.grad, c.d, c.off = key, idx, grad, d, None
+        return c
+
     @property
     def m(self):
         return int(self.key.shape[0])

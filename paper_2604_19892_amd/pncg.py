@@ -18,6 +18,7 @@ import time
 import numpy as np
 import torch
 
+from . import synth
 from .binding import DeviceContacts, MasContext, make_config
 
 
@@ -169,3 +170,121 @@ class PNCG:
                 break
         torch.cuda.synchronize()
         return it, time.perf_counter() - t, rel
+
+
+class _PairBuffers:
+    """Device outputs of one mas_constraint_set call (capacity cap)."""
+
+    def __init__(self, cap, device, with_contacts=True):
+        self.cap = cap
+        self.pairs = torch.full((cap, 4), -1, dtype=torch.int32, device=device)
+        self.kind = torch.zeros(cap, dtype=torch.uint8, device=device)
+        self.dist = torch.zeros(cap, dtype=torch.float64, device=device)
+        self.grad = torch.zeros(cap, 12, dtype=torch.float64, device=device) if with_contacts else None
+        self.key = torch.zeros(cap, dtype=torch.int64, device=device) if with_contacts else None
+        self.m = 0
+
+    def contacts(self):
+        m = self.m
+        return DeviceContacts.from_tensors(self.key[:m], self.pairs[:m], self.grad[:m], self.dist[:m])
+
+
+class GeoPNCG:
+    """Algorithm 1 on the geometric point-triangle / edge-edge contacts of the
+    scene's boundary surface, through the C ABI: ComputeConstraintSet at the
+    head of each iteration (mas_constraint_set: distances, n = grad d and
+    contact keys), RebuildMAS or the Woodbury update against it, z = P g,
+    H_base z, the subspace step, ConservativeCCD for the per-subdomain steps
+    (mas_ccd_safe_step over the pairs within ``radius``), and the descent
+    check with the trial point's contact set (the energy's barrier is taken
+    on the geometric distances).  The host reads per iteration the pair
+    counts, the trial energy and the step scalars."""
+
+    def __init__(self, scene, radius, block_prec="f64", levels=None, K=None, delta=0.3, hess_prec=None,
+                 max_halvings=8, cap=None, device="cuda", deterministic=False):
+        cfg = make_config(scene, levels=levels, K=K, block_prec=block_prec, hess_prec=hess_prec, delta=delta,
+                          deterministic=deterministic)
+        self.ctx = ctx = MasContext(scene, cfg, device=device)
+        self.scene = scene
+        self.radius = float(radius)
+        self.max_halvings = max_halvings
+        verts, tris, edges = synth.surface(scene.tets)
+        r = ctx.rank
+        self.vt = torch.as_tensor(r[verts].astype(np.int32), device=device)
+        self.tt = torch.as_tensor(r[tris].astype(np.int32).reshape(-1, 3), device=device)
+        self.et = torch.as_tensor(r[edges].astype(np.int32).reshape(-1, 2), device=device)
+        max_contacts = cfg.max_contacts or max(2 * scene.X.shape[0], 65536)   # mas_create's default
+        cap = cap or int(min(max_contacts, 8 * (len(verts) + len(edges)) + 4096))
+        self.C = _PairBuffers(cap, device)          # contact set at x
+        self.Ct = _PairBuffers(cap, device)         # contact set at the trial point
+        self.cand = _PairBuffers(cap, device, with_contacts=False)
+        v = ctx.vec
+        self.x = ctx.to_lib(scene.x)
+        self.xt = ctx.inertial_target(self.x, ctx.to_lib(scene.v))
+        self.x_trial, self.g, self.g_trial = v(), v(), v()
+        self.z, self.z_prev, self.vz, self.p, self.vp = v(), v(), v(), v(), v()
+        self.E = torch.zeros(1, dtype=torch.float64, device=device)
+        self.E_trial = torch.zeros(1, dtype=torch.float64, device=device)
+        self.rank_hist = torch.zeros(max(cfg.max_rank, 0) + 1, dtype=torch.int32, device=device)
+        self._set(self.x, self.C, self.scene.dhat)
+        ctx.energy_grad(self.x, self.xt, self.C.contacts(), self.E, self.g)
+        self.E_host = float(self.E.item())
+        self.restart = True
+        self.k = 0
+        self.n_restarts = 0
+        self.n_rejected = 0
+        self.log = []
+
+    def _set(self, x, buf, dist):
+        with_c = buf.grad is not None
+        n = self.ctx.constraint_set(x, self.vt, self.tt, self.et, dist, buf.pairs, buf.kind, buf.dist,
+                                    buf.grad if with_c else None, buf.key if with_c else None)
+        if n > buf.cap:
+            raise RuntimeError("constraint set of %d pairs exceeds the capacity %d" % (n, buf.cap))
+        buf.m = n
+        return n
+
+    def iterate(self):
+        ctx = self.ctx
+        C = self.C.contacts()
+        if self.restart:
+            ctx.build(self.x, C)
+            self.n_restarts += 1
+        else:
+            ctx.woodbury_update(C, self.rank_hist)
+        ctx.apply(self.g, self.z)
+        ctx.hess_vec(self.z, with_update=False, y=self.vz)
+        ctx.subspace_step(self.g, self.z, self.z_prev if self.k > 0 else None, self.vz, self.p, self.vp,
+                          self.restart)
+        mc = self._set(self.x, self.cand, self.radius)
+        ctx.ccd_safe_step(self.x, self.p, self.radius, self.cand.pairs, self.cand.kind, self.cand.dist, mc, 1.0,
+                          self.x_trial)
+        scale = 1.0
+        accepted = False
+        Et = float("inf")
+        for h in range(self.max_halvings + 1):
+            self._set(self.x_trial, self.Ct, self.scene.dhat)
+            ctx.energy_grad(self.x_trial, self.xt, self.Ct.contacts(), self.E_trial, self.g_trial)
+            Et = float(self.E_trial.item())
+            if Et <= self.E_host:
+                accepted = True
+                break
+            if h < self.max_halvings:
+                scale *= 0.5
+                ctx.safe_step(self.x, self.p, None, scale, self.x_trial)
+        st = ctx.step_out()
+        self.log.append(dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), mu=st["mu"], nu=st["nu"], r=st["r"],
+                             restart=bool(self.restart), fallback=bool(st["fallback"]), E=self.E_host,
+                             m=self.C.m, candidates=mc, scale=scale, accepted=accepted))
+        if accepted:
+            self.x, self.x_trial = self.x_trial, self.x
+            self.g, self.g_trial = self.g_trial, self.g
+            self.C, self.Ct = self.Ct, self.C
+            self.E_host = Et
+            self.restart = bool(st["restart_next"])
+        else:
+            self.n_rejected += 1
+            self.restart = True
+        self.z, self.z_prev = self.z_prev, self.z
+        self.k += 1
+        return st

@@ -18,6 +18,8 @@ the Woodbury update (Section 4.1) relies on.
 Scenes (sizes follow the paper's workloads, Table 1):
   * ``grid_scene``       8x8x8 lattice, point-plane contacts (small case)
   * ``two_boxes_scene``  two stacked 40x40x20 boxes, PT/EE stencils
+  * ``stacked_boxes_scene`` two boxes a fraction of dhat apart, one falling
+                         onto the other (geometric contacts of the surface)
   * ``puffer_scene``     eight spiky balls, ~1.14M vertices / ~2.72M tets,
                          ~1M active contacts (the Puffer Balls shape)
 """
@@ -377,6 +379,30 @@ def two_boxes_scene(seed=1, n_contacts=20000, dhat=1e-3, h=0.01, E=1e5, nu=0.4, 
                  np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
                  kappa=rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]),
                  pool=pool, levels=levels, K=K)
+
+
+def stacked_boxes_scene(seed=4, nxy=10, nz=5, dhat=1e-3, h=0.01, E=1e5, nu=0.4, rho=1000.0, levels=2, K=8,
+                        gap=0.5, speed=0.5):
+    """Two boxes for geometric contacts: the upper one (offset by half an
+    edge in x and y) rests gap * dhat above the lower one and moves down at
+    ``speed`` (its inertial target lies far inside the lower box, so the
+    barrier has to hold it); vertex noise of 0.05 gap * dhat keeps the start
+    free of intersections.  No contact pool: the contacts are the boundary
+    surface's point-triangle and edge-edge pairs within dhat."""
+    rng = np.random.default_rng(seed)
+    edge = 1.0 / (nxy - 1)
+    Xl, tl = lattice_from_cubes(box_cubes(nxy, nxy, nz), edge, (0, 0, 0))
+    z0 = (nz - 1) * edge + gap * dhat
+    Xu, tu = lattice_from_cubes(box_cubes(nxy, nxy, nz), edge, (0.5 * edge, 0.5 * edge, z0))
+    X = np.concatenate([Xl, Xu])
+    tets = np.concatenate([tl, tu + Xl.shape[0]]).astype(np.int32)
+    x = _perturb(rng, X, tets, 0.05 * gap * dhat)
+    v = np.zeros_like(X)
+    v[Xl.shape[0]:, 2] = -speed
+    T = tets.shape[0]
+    empty = stencil_pool(np.zeros(0, np.uint64), np.zeros((0, 4), np.int32), np.zeros((0, 12)), x, np.zeros(0))
+    return Scene("stacked_boxes", X, x, v, tets, np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
+                 kappa=rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]), pool=empty, levels=levels, K=K)
 
 
 def churn_set(rng, scene, base, frac=0.3):
