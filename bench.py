@@ -125,6 +125,49 @@ def warm_frame(sc, prec, hess_prec, iters, tol=1e-6, max_iter=800):
     return out
 
 
+def geometric_measure(iters=20, warmup=3):
+    """Algorithm 1 on geometric contacts (GeoPNCG): the stacked-boxes scene
+    at 2 x 40x40x20 vertices, the upper box falling onto the lower; per
+    iteration ComputeConstraintSet at x (contacts) and within the candidate
+    radius (CCD), the trial point's set for the descent check, the CCD safe
+    step.  Iterations per second over ``iters`` timed iterations and the
+    library's stage times."""
+    import numpy as np
+    import torch
+    from paper_2604_19892_amd import synth
+    from paper_2604_19892_amd.pncg import GeoPNCG
+    sc = synth.stacked_boxes_scene(nxy=40, nz=20, levels=3)
+    edge = 1.0 / 39
+    g = GeoPNCG(sc, 0.25 * edge, block_prec="f32", hess_prec="f32")
+    for _ in range(warmup):
+        g.iterate()
+    ctx = g.ctx
+    ctx.profile(True)
+    r0, k0 = g.n_restarts, len(g.log)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(iters):
+        g.iterate()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    stages = {k: ctx.profile_read(k)[0] / iters for k in ("build", "update", "apply", "hess_vec", "energy",
+                                                          "subspace", "ccd", "constraint_set")}
+    ctx.profile(False)
+    code, msg = ctx.sync()
+    recs = g.log[k0:]
+    out = {"workload": "stacked boxes 2 x 40x40x20 (%d verts, %d tets), upper box falling at 0.5 m/s" % (sc.N, sc.T),
+           "iters_per_s": iters / dt, "ms_per_iter": 1e3 * dt / iters, "iters": iters,
+           "restart_fraction": (g.n_restarts - r0) / iters,
+           "contacts_mean": float(np.mean([r["m"] for r in recs])),
+           "ccd_candidates_mean": float(np.mean([r["candidates"] for r in recs])),
+           "descent_halvings": int(sum(1 for r in recs if r["scale"] < 1.0)),
+           "stage_ms_per_iter": stages, "status": code}
+    ctx.close()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 BLOCK = 10
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
@@ -322,40 +365,104 @@ def constraint_set_measure(ctx, sc, x, reps=5):
             "ee_pairs": int(k - n_pt), "ms_per_call": ms / max(calls, 1)}
 
 
-def tolerance_solves(sc, precs, tol, max_iter, repeats):
-    """PNCG solves per block storage precision from the same start to
-    ||grad E|| <= tol ||grad E_0||: iterations and wall-clock seconds of each
-    (each context is created before its clock starts).  Trajectories differ
-    between runs (the order of atomic float64 sums differs, and a restart
-    decision near the threshold can flip), so each form is solved
-    ``repeats`` times, interleaved, and the means are compared."""
+# block storage forms of the tolerance solves: (requested level-0 storage,
+# element Hessian storage, precision guard; None = the library's default)
+SOLVE_FORMS = {"f64": ("f64", "f64", None), "f32": ("f32", "f32", None), "bf16": ("bf16", "f32", None),
+               "f16": ("f16", "f32", None), "bf16_all": ("bf16", "f32", 0.0), "f16_all": ("f16", "f32", 0.0)}
+
+
+def tolerance_solves(sc, forms, tol, max_iter, repeats):
+    """PNCG solves per storage form from the same start to ||grad E|| <=
+    tol ||grad E_0||: iterations and wall-clock seconds of each, and the
+    level-0 blocks actually stored in each precision (the guard promotes
+    blocks whose conditioning the requested format cannot hold; the *_all
+    forms switch it off).  One context per form, reset to the start before
+    each of ``repeats`` solves (its blocks are rebuilt at the first
+    iteration).  Trajectories differ between runs (float64 sums taken
+    through atomics in no fixed order, restart decisions near the
+    threshold), so the spread is reported beside the means."""
+    import numpy as np
     import torch
     from paper_2604_19892_amd.pncg import PNCG
-    runs = {p: [] for p in precs}
-    for _ in range(repeats):
-        for prec in precs:
-            s = PNCG(sc, block_prec=prec, hess_prec="f64" if prec == "f64" else "f32")
-            it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
+    runs = {f: [] for f in forms}
+    stored = {}
+    for f in forms:
+        bp, hp, guard = SOLVE_FORMS[f]
+        s = PNCG(sc, block_prec=bp, hess_prec=hp, prec_guard=guard)
+        # with the guard off the stiff blocks lose definiteness in 16 bits
+        # (capacitance pivots <= 0) and the solve does not converge: one
+        # short run shows it
+        reps, cap = (1, min(max_iter, 300)) if guard == 0.0 else (repeats, max_iter)
+        for _ in range(reps):
+            s.reset()
+            it, sec, rel = s.solve(rel_tol=tol, max_iter=cap)
             code, msg = s.ctx.sync()
-            runs[prec].append({"iters": it, "seconds": sec, "rel_gnorm": rel, "converged": bool(rel <= tol),
-                               "restarts": s.n_restarts, "rejected_steps": s.n_rejected, "status": code})
-            print("[bench] solve %s: %d iters %.2fs rel %.2e" % (prec, it, sec, rel), file=sys.stderr, flush=True)
-            s.ctx.close()
-            del s
-            torch.cuda.empty_cache()
-    out = {"tol": tol, "max_iter": max_iter, "repeats": repeats, "runs": runs, "mean_seconds": {},
-           "mean_iters": {}, "mean_ms_per_iter": {}}
-    for p, rs in runs.items():
-        ok = [r for r in rs if r["converged"]]
-        if len(ok) == len(rs):
-            out["mean_seconds"][p] = sum(r["seconds"] for r in rs) / len(rs)
-            out["mean_iters"][p] = sum(r["iters"] for r in rs) / len(rs)
-            out["mean_ms_per_iter"][p] = 1e3 * out["mean_seconds"][p] / out["mean_iters"][p]
-    if "f64" in out["mean_seconds"]:
-        out["f64_seconds_over"] = {p: out["mean_seconds"]["f64"] / t for p, t in out["mean_seconds"].items()
-                                   if p != "f64"}
-    out["element_hessian_storage"] = {p: "f64" if p == "f64" else "f32" for p in precs}
+            runs[f].append({"iters": it, "seconds": sec, "rel_gnorm": rel, "converged": bool(rel <= tol),
+                            "status": code})
+            print("[bench] solve %s: %d iters %.2fs rel %.2e" % (f, it, sec, rel), file=sys.stderr, flush=True)
+        stored[f] = s.ctx.block_precisions(0)   # the last rebuild's storage
+        s.ctx.close()
+        del s
+        torch.cuda.empty_cache()
+    out = {"tol": tol, "max_iter": max_iter, "repeats": repeats, "runs": runs, "stored_level0_blocks": stored,
+           "forms": {f: {"block_storage": SOLVE_FORMS[f][0], "hessian_storage": SOLVE_FORMS[f][1],
+                         "guard": "off" if SOLVE_FORMS[f][2] == 0.0 else "default"} for f in forms},
+           "seconds": {}, "iters": {}, "mean_ms_per_iter": {}}
+    for f, rs in runs.items():
+        if all(r["converged"] for r in rs):
+            t = np.array([r["seconds"] for r in rs])
+            n = np.array([r["iters"] for r in rs])
+            out["seconds"][f] = {"mean": float(t.mean()), "min": float(t.min()), "max": float(t.max()),
+                                 "median": float(np.median(t))}
+            out["iters"][f] = {"mean": float(n.mean()), "min": int(n.min()), "max": int(n.max())}
+            out["mean_ms_per_iter"][f] = 1e3 * float(t.sum() / n.sum())
+    if "f64" in out["seconds"]:
+        f64 = out["seconds"]["f64"]
+        out["f64_seconds_over"] = {f: {"mean": f64["mean"] / v["mean"], "median": f64["median"] / v["median"]}
+                                   for f, v in out["seconds"].items() if f != "f64"}
+        ms64 = out["mean_ms_per_iter"]["f64"]
+        out["f64_ms_per_iter_over"] = {f: ms64 / v for f, v in out["mean_ms_per_iter"].items() if f != "f64"}
     return out
+
+
+def precision_errors(sc, seed=12):
+    """Error of each output of the mixed-precision forms against the float64
+    form on the same inputs at the full scene: mas_apply after a rebuild at
+    the start and a Woodbury update with the contacts a quarter of the way
+    to the inertial target, and hess_vec with the update, for random g and v
+    (relative 2-norm errors).  The float64 form itself matches the oracle to
+    1e-10 (parity tests); the stored blocks of each form are listed."""
+    import numpy as np
+    import torch
+    from paper_2604_19892_amd.pncg import PNCG
+    rng = np.random.default_rng(seed)
+    g0 = rng.standard_normal(3 * sc.N)
+    v0 = rng.standard_normal(3 * sc.N)
+    outs, stored = {}, {}
+    for f in ("f64", "f32", "bf16", "f16", "bf16_all", "f16_all"):
+        bp, hp, guard = SOLVE_FORMS[f]
+        s = PNCG(sc, block_prec=bp, hess_prec=hp, prec_guard=guard)
+        ctx = s.ctx
+        ctx.build(s.x, s.pool)
+        stored[f] = ctx.block_precisions(0)
+        x1 = s.x + 0.25 * (s.xt - s.x)
+        ctx.stencil_distance(x1, s.pool_t)
+        ctx.woodbury_update(s.pool_t)
+        z = ctx.apply(ctx.to_lib(g0))
+        y = ctx.hess_vec(ctx.to_lib(v0), with_update=True)
+        code, msg = ctx.sync()
+        outs[f] = (z.cpu().numpy(), y.cpu().numpy(), code)
+        ctx.close()
+        del s, ctx
+        torch.cuda.empty_cache()
+    zr, yr, _ = outs["f64"]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"inputs": "rebuild at the start, update with the contacts at x0 + (x~ - x0) / 4, random g and v",
+            "stored_level0_blocks": stored,
+            "mas_apply_rel_err": {f: rel(o[0], zr) for f, o in outs.items() if f != "f64"},
+            "hess_vec_rel_err": {f: rel(o[1], yr) for f, o in outs.items() if f != "f64"},
+            "status": {f: o[2] for f, o in outs.items()},
+            "tolerances": {"f32": 1e-5, "bf16": 2e-2, "f16": 2e-2}}
 
 
 def main():
@@ -368,6 +475,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the solves to the gradient tolerance (f64 vs mixed storage)")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-frame regime")
+    ap.add_argument("--no-geo", action="store_true", help="skip the geometric-contacts measurement")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=1500)
     ap.add_argument("--solve-repeats", type=int, default=5)
@@ -566,8 +674,13 @@ def main():
     if not args.no_warm:
         print("[bench] warm frame", file=sys.stderr, flush=True)
         out["warm_frame"] = warm_frame(sc, args.prec, hess_prec, 60)
+    if not args.no_geo:
+        print("[bench] geometric contacts", file=sys.stderr, flush=True)
+        out["geometric_contacts"] = geometric_measure()
     if not args.no_solve:
-        out["tol_solve"] = tolerance_solves(sc, ("f64", "f32", "bf16", "f16"), args.solve_tol,
+        print("[bench] precision errors", file=sys.stderr, flush=True)
+        out["precision_errors"] = precision_errors(sc)
+        out["tol_solve"] = tolerance_solves(sc, tuple(SOLVE_FORMS), args.solve_tol,
                                             args.solve_max_iter, args.solve_repeats)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
