@@ -65,6 +65,68 @@ def subspace_step(g, z, p, Hmul, restart, eps_sing=1e-12, eps_abs=1e-300):
     return float(mu), float(nu), -mu * z + nu * p, False, A11, A12, A22
 
 
+# Comparison direction rules (Section 5, search-direction study): classic
+# nonlinear CG with a preconditioner, p = alpha d, d = -z + beta d_prev.
+BETA_FR, BETA_CD, BETA_DK = 1, 2, 3
+
+
+def beta_coefficient(rule, g, g_prev, z, z_prev, d_prev):
+    """beta of the comparison rules, preconditioned (z = P g), or None when
+    its denominator is not positive.  The paper names the rules without
+    formulas; these are the published ones with g^T g replaced by g^T z:
+
+    * Fletcher-Reeves (1964): g^T z / (g_prev^T z_prev);
+    * conjugate descent (Fletcher 1987): g^T z / (-d_prev^T g_prev);
+    * Dai-Kou (2013), the member tau = s^T y / s^T s of their family:
+      y^T z / (d^T y) - (y^T P y / d^T y) (d^T g) / (d^T y), y = g - g_prev,
+      with P y = z - z_prev.
+    """
+    g, g_prev, z, z_prev, d_prev = (np.asarray(a, np.float64) for a in (g, g_prev, z, z_prev, d_prev))
+    if rule == BETA_FR:
+        num, den = float(g @ z), float(g_prev @ z_prev)
+        return num / den if den > 0 else None
+    if rule == BETA_CD:
+        num, den = float(g @ z), -float(d_prev @ g_prev)
+        return num / den if den > 0 else None
+    if rule == BETA_DK:
+        y = g - g_prev
+        dy = float(d_prev @ y)
+        if not dy > 0:
+            return None
+        return float(y @ z) / dy - (float(y @ (z - z_prev)) / dy) * (float(d_prev @ g) / dy)
+    raise ValueError("unknown rule %r" % (rule,))
+
+
+def beta_step(rule, g, g_prev, z, z_prev, d_prev, Hmul, restart):
+    """One direction of a comparison rule: d = -z + beta d_prev (beta = 0 on
+    a restart), alpha minimising g^T (alpha d) + 1/2 alpha^2 d^T H~ d, and
+    the step p = alpha d that the safe step then scales per subdomain.
+    Safeguards (the reading used where the rules need them): a denominator
+    that is not positive, or a d that is not a descent direction
+    (g^T d >= 0), gives d = -z; d^T H~ d <= 0 gives alpha = 1.  Either sets
+    the fallback flag.  Returns (alpha, beta, d, p, fallback)."""
+    fb = False
+    beta = 0.0
+    if not restart:
+        b = beta_coefficient(rule, g, g_prev, z, z_prev, d_prev)
+        if b is None:
+            fb = True
+        else:
+            beta = b
+    d = -z + beta * d_prev if beta != 0.0 else -np.asarray(z, np.float64)
+    gd = float(g @ d)
+    if not restart and not gd < 0:
+        beta, fb = 0.0, True
+        d = -np.asarray(z, np.float64)
+        gd = float(g @ d)
+    dHd = float(d @ Hmul(d))
+    if dHd > 0:
+        alpha = -gd / dHd
+    else:
+        alpha, fb = 1.0, True
+    return alpha, beta, d, alpha * d, fb
+
+
 def restart_ratio(g_new, z_prev, z_new):
     return abs(float(g_new @ z_prev)) / float(g_new @ z_new)
 

@@ -29,13 +29,30 @@ def pool_distance(pool, x):
     return (pool['grad'] * fem.stencil_gather(pool['idx'], x)).sum(1) - pool['off']
 
 
+RULES = {"fr": pncg.BETA_FR, "cd": pncg.BETA_CD, "dk": pncg.BETA_DK}
+
+
 class OraclePNCG:
+    """``update`` picks the preconditioner strategy of the ablation study
+    (Section 5, preconditioner update strategy): "woodbury" (the method),
+    "freeze" (the restart's MAS kept until the next restart: no Top-K
+    columns, while H~ keeps the untruncated U) or "rebuild" (RebuildMAS at
+    every iteration, the CG restart form still decided by the ratio test).
+    ``rule`` picks the direction: "subspace" (the method's 2x2 step) or a
+    comparison rule "fr", "cd", "dk" (``pncg.beta_step``)."""
+
     def __init__(self, scene, levels=None, K=None, delta=0.3,
-                 cos_rot=np.cos(np.deg2rad(25.0)), max_halvings=8):
+                 cos_rot=np.cos(np.deg2rad(25.0)), max_halvings=8, update="woodbury", rule="subspace"):
+        if update not in ("woodbury", "freeze", "rebuild") or (rule != "subspace" and rule not in RULES):
+            raise ValueError("unknown update strategy or direction rule")
+        self.update = update
+        self.rule = rule
         self.scene = scene
         self.prob = fem.Problem(scene)
         self.hier = mas.Hierarchy(scene.X, levels or scene.levels)
-        self.K = K or scene.K
+        self.K = 0 if update == "freeze" else (K or scene.K)
+        self.g_prev = None
+        self.d = None
         self.delta = delta
         self.cos_rot = cos_rot
         self.max_halvings = max_halvings
@@ -57,7 +74,7 @@ class OraclePNCG:
         prob, hier = self.prob, self.hier
         x = self.x
         C = self.constraint_set(x)
-        if self.restart:
+        if self.restart or self.update == "rebuild":
             self.H_base = prob.assemble(x, C)
             self.mas = mas.MAS(hier, self.H_base)
             self.base = C
@@ -77,7 +94,13 @@ class OraclePNCG:
                 y = y + U @ (U.T @ v)
             return y
 
-        mu, nu, p, fb, *_ = pncg.subspace_step(g, z, self.p, Hmul, self.restart)
+        if self.rule == "subspace":
+            mu, nu, p, fb, *_ = pncg.subspace_step(g, z, self.p, Hmul, self.restart)
+            d = p
+        else:
+            # mu, nu of the log hold alpha and beta
+            mu, nu, d, p, fb = pncg.beta_step(RULES[self.rule], g, self.g_prev, z, self.z_prev, self.d, Hmul,
+                                              self.restart)
         dpool = pool_distance(self.pool, x)
         alpha = pncg.safe_alpha(hier, self.pool['idx'], self.pool['grad'], dpool, p)
         E0 = prob.energy(x, self.x_tilde, C)
@@ -95,7 +118,9 @@ class OraclePNCG:
         # without a decrease the point is kept and the next iteration restarts
         self.restart = (r > self.delta) or not accepted
         self.z_prev = z
+        self.g_prev = g
         self.p = p
+        self.d = d
         if accepted:
             self.x = xn
         return g, z, p
