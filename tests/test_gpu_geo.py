@@ -30,6 +30,7 @@ def test_geometric_iterations_match_oracle():
     radius = 0.25 * EDGE
     ora = OracleGeoPNCG(sc, surf, radius)
     gpu = GeoPNCG(sc, radius, block_prec="f64", hess_prec="f64")
+    dx_prev = 0.0  # ||x_gpu - x_oracle|| at the point the iteration starts from
     for k in range(6):
         ora.iterate()
         gpu.iterate()
@@ -42,9 +43,14 @@ def test_geometric_iterations_match_oracle():
         assert lg["mu"] == pytest.approx(lo["mu"], rel=1e-7), k
         assert lg["nu"] == pytest.approx(lo["nu"], rel=1e-6, abs=1e-9), k
         assert lg["scale"] == lo["scale"] and lg["accepted"] == lo["accepted"], k
-        assert lg["E"] == pytest.approx(lo["E"], rel=1e-9), k
+        # E at the start point: to first order its difference is bounded by
+        # ||grad E|| times the distance between the two start points (the
+        # fast mode's float atomics make the trajectories drift apart at
+        # rounding level); twice that, plus rounding of E itself
+        assert abs(lg["E"] - lo["E"]) <= 2.0 * lo["gnorm"] * dx_prev + 1e-12 * abs(lo["E"]), k
         xg = gpu.ctx.from_lib(gpu.x)
-        err = np.linalg.norm(xg - ora.x) / np.linalg.norm(ora.x - sc.x.reshape(-1))
+        dx_prev = float(np.linalg.norm(xg - ora.x))
+        err = dx_prev / np.linalg.norm(ora.x - sc.x.reshape(-1))
         assert err < 1e-6, (k, err)
     code, msg = gpu.ctx.sync()
     assert code == 0, msg
