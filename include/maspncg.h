@@ -109,7 +109,20 @@ typedef struct {
   int64_t max_contacts; /* largest base or current contact set (max(2 N, 65536)) */
   int64_t max_tris;     /* largest triangle list of mas_constraint_set (2 N + 64) */
   int64_t max_edges;    /* largest edge list of mas_constraint_set (3 N + 64) */
+  int32_t precond;      /* MAS_PRECOND_MAS (the method) or MAS_PRECOND_BJ3 */
 } mas_config;
+
+/* Preconditioner of a context.  MAS_PRECOND_BJ3 is the comparison
+ * preconditioner of the ablation study (Section 5, preconditioner
+ * efficacy): the 3x3 block-Jacobi inverse of H~ (each vertex's diagonal
+ * block of H_base, plus that of U U^T after mas_woodbury_update), inverted
+ * by Cholesky in float64.  In that mode mas_build assembles the level-0
+ * blocks but inverts no MAS level, mas_woodbury_update classifies (for H~)
+ * and rebuilds the vertex blocks instead of Top-K and capacitance, and
+ * mas_apply returns z_i = B_i^-1 g_i; mas_get_block and the MAS queries
+ * have nothing to report.  Not combinable with deterministic mode. */
+#define MAS_PRECOND_MAS 0
+#define MAS_PRECOND_BJ3 1
 
 /* Tetrahedral mesh, host pointers, original vertex numbering.  tets must
  * have positive orientation at rest. */
@@ -240,6 +253,30 @@ mas_status pncg_subspace_step(void* ctx, const double* g, const double* z, const
 mas_status pncg_subspace_step_noalloc(void* ctx, const double* g, const double* z, const double* z_prev,
                                       const double* v_z, double* p, double* v_p, int32_t restart,
                                       mas_step_out* out);
+
+/* Direction rules of the search-direction comparison (Section 5): classic
+ * preconditioned nonlinear CG, d = -z + beta d_prev, beta by
+ *   MAS_BETA_FR  Fletcher-Reeves    g^T z / (g_prev^T z_prev)
+ *   MAS_BETA_CD  conjugate descent  g^T z / (-d_prev^T g_prev)
+ *   MAS_BETA_DK  Dai-Kou            y^T z / (d^T y) - (y^T (z - z_prev) /
+ *                d^T y) (d^T g) / (d^T y), y = g - g_prev
+ * (the published formulas with g^T g replaced by g^T z; the paper names the
+ * rules without printing them), then p = alpha d with alpha = -g^T d /
+ * d^T H~ d.  Inputs g, z, v_z = H_base z, z_prev (may be NULL on a restart:
+ * r = 0) and, unless restart != 0, g_prev (device, 3N; g_prev is not read on
+ * a restart); in/out d (d_prev -> d) and v_d (H_base d, updated by
+ * linearity); out p (3N, the step for the safe step).  restart != 0 takes
+ * beta = 0 (the same step as pncg_subspace_step's restart form).  A
+ * non-positive denominator or a d that is not a descent direction gives
+ * d = -z; d^T H~ d <= 0 gives alpha = 1; either sets out->fallback.  out
+ * (device) holds alpha in mu and beta in nu; r and restart_next as for the
+ * subspace step.  Bad rule or missing g_prev / z_prev: MAS_ERR_INVALID_ARG. */
+#define MAS_BETA_FR 1
+#define MAS_BETA_CD 2
+#define MAS_BETA_DK 3
+mas_status pncg_beta_step(void* ctx, int32_t rule, const double* g, const double* g_prev, const double* z,
+                          const double* z_prev, const double* v_z, double* d, double* v_d, int32_t restart,
+                          double* p, mas_step_out* out);
 
 /* Incremental potential (Section 3.1) at x: E (device scalar) and, if g is
  * not NULL, its gradient (device, 3N).  Contacts with d <= 0 make E = +inf.

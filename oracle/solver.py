@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import constraint_set as CS
-from . import contact, fem, mas, woodbury, pncg
+from . import contact, fem, jacobi, mas, woodbury, pncg
 
 
 def pool_distance(pool, x):
@@ -39,14 +39,19 @@ class OraclePNCG:
     columns, while H~ keeps the untruncated U) or "rebuild" (RebuildMAS at
     every iteration, the CG restart form still decided by the ratio test).
     ``rule`` picks the direction: "subspace" (the method's 2x2 step) or a
-    comparison rule "fr", "cd", "dk" (``pncg.beta_step``)."""
+    comparison rule "fr", "cd", "dk" (``pncg.beta_step``).  ``precond``
+    "bj3" replaces MAS by the 3x3 block-Jacobi inverse of H~ (the
+    comparison preconditioner, ``oracle.jacobi``)."""
 
     def __init__(self, scene, levels=None, K=None, delta=0.3,
-                 cos_rot=np.cos(np.deg2rad(25.0)), max_halvings=8, update="woodbury", rule="subspace"):
-        if update not in ("woodbury", "freeze", "rebuild") or (rule != "subspace" and rule not in RULES):
-            raise ValueError("unknown update strategy or direction rule")
+                 cos_rot=np.cos(np.deg2rad(25.0)), max_halvings=8, update="woodbury", rule="subspace",
+                 precond="mas"):
+        if update not in ("woodbury", "freeze", "rebuild") or (rule != "subspace" and rule not in RULES) \
+                or precond not in ("mas", "bj3"):
+            raise ValueError("unknown update strategy, direction rule or preconditioner")
         self.update = update
         self.rule = rule
+        self.precond = precond
         self.scene = scene
         self.prob = fem.Problem(scene)
         self.hier = mas.Hierarchy(scene.X, levels or scene.levels)
@@ -74,19 +79,26 @@ class OraclePNCG:
         prob, hier = self.prob, self.hier
         x = self.x
         C = self.constraint_set(x)
+        bj = self.precond == "bj3"
         if self.restart or self.update == "rebuild":
             self.H_base = prob.assemble(x, C)
-            self.mas = mas.MAS(hier, self.H_base)
+            if not bj:
+                self.mas = mas.MAS(hier, self.H_base)
+                blocks = self.mas.fine
             self.base = C
-            blocks = self.mas.fine
             U = None
         else:
             dS, u, _ = woodbury.classify(prob, self.base, C, self.cos_rot)
-            sel = woodbury.topk(hier, C, dS, u, self.K)
-            blocks = woodbury.updated_blocks(hier, self.H_base, C, u, sel)
+            if not bj:
+                sel = woodbury.topk(hier, C, dS, u, self.K)
+                blocks = woodbury.updated_blocks(hier, self.H_base, C, u, sel)
             U = woodbury.global_U(prob, C, u, dS)
         g = prob.gradient(x, self.x_tilde, C)
-        z = self.mas.apply(g, blocks)
+        if bj:
+            Ht = self.H_base if U is None else self.H_base + U @ U.T
+            z = jacobi.apply(jacobi.inverse_blocks(Ht), g)
+        else:
+            z = self.mas.apply(g, blocks)
 
         def Hmul(v):
             y = self.H_base @ v

@@ -12,6 +12,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmaspncg.
 
 MAS_F64, MAS_F32, MAS_BF16, MAS_F16 = 0, 1, 2, 3
 PREC = {"f64": MAS_F64, "f32": MAS_F32, "bf16": MAS_BF16, "f16": MAS_F16}
+BETA = {"fr": 1, "cd": 2, "dk": 3}
+PRECOND = {"mas": 0, "bj3": 1}
 
 STATUS = {0: "MAS_OK", 1: "MAS_ERR_INVALID_ARG", 2: "MAS_ERR_STATE", 3: "MAS_ERR_OOM",
           4: "MAS_ERR_HIP", 5: "MAS_ERR_NOT_SPD", 6: "MAS_ERR_NONFINITE", 7: "MAS_ERR_RANK"}
@@ -37,6 +39,7 @@ class MasConfig(ctypes.Structure):
         ("max_contacts", ctypes.c_int64),
         ("max_tris", ctypes.c_int64),
         ("max_edges", ctypes.c_int64),
+        ("precond", ctypes.c_int32),
     ]
 
 
@@ -103,6 +106,7 @@ SIGNATURES = {
     "hess_vec": (_I32, [_P, _P, _P, _I32]),
     "pncg_subspace_step": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "pncg_subspace_step_noalloc": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I32, _P]),
+    "pncg_beta_step": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _P, _P]),
     "mas_energy_grad": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _P, _P]),
     "mas_inertial_target": (_I32, [_P, _P, _P, _P]),
     "mas_next_frame": (_I32, [_P, _P, _P, _P, _P]),

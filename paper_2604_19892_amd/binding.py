@@ -21,7 +21,7 @@ def _ptr(t):
 
 def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=None,
                 hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12, prec_guard=None,
-                deterministic=False, max_contacts=0, max_tris=0, max_edges=0):
+                deterministic=False, max_contacts=0, max_tris=0, max_edges=0, precond="mas"):
     cfg = MasConfig()
     _abi.lib().mas_default_config(ctypes.byref(cfg))
     if scene is not None:
@@ -52,6 +52,7 @@ def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=N
     cfg.max_contacts = int(max_contacts)
     cfg.max_tris = int(max_tris)
     cfg.max_edges = int(max_edges)
+    cfg.precond = _abi.PRECOND[precond]
     return cfg
 
 
@@ -199,6 +200,15 @@ class MasContext:
         check("pncg_subspace_step_noalloc", _abi.lib().pncg_subspace_step_noalloc(
             self.h, _ptr(g), _ptr(z), _ptr(z_prev), _ptr(vz), _ptr(p), _ptr(vp), int(restart), _ptr(out)))
         return out
+
+    def beta_step(self, rule, g, g_prev, z, z_prev, vz, d, vd, restart, p):
+        """pncg_beta_step: a comparison direction rule ("fr", "cd", "dk");
+        d, vd in/out, p the step; the step scalars land in self.out (alpha
+        in mu, beta in nu)."""
+        check("pncg_beta_step", _abi.lib().pncg_beta_step(
+            self.h, _abi.BETA[rule], _ptr(g), _ptr(g_prev), _ptr(z), _ptr(z_prev), _ptr(vz), _ptr(d), _ptr(vd),
+            int(restart), _ptr(p), _ptr(self.out)))
+        return self.out
 
     def step_out(self, out=None):
         raw = (self.out if out is None else out).cpu().numpy().view(np.uint8)

@@ -191,7 +191,7 @@ mas_status mas_destroy(void* p) {
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
                   c->alpha, c->alpha0, c->alpha_mix, c->ahalf, c->around, c->err, c->diag, c->cls_part, c->scan_tmp,
-                  c->inc_cnt, c->inc_off, c->inc_list, c->coup};
+                  c->inc_cnt, c->inc_off, c->inc_list, c->coup, c->bj, c->bjinv};
   for (void* q : ptrs)
     if (q) hipFree(q);
   for (auto& t : c->cs) {
@@ -235,6 +235,8 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (cfg->hess_prec != MAS_F64 && cfg->hess_prec != MAS_F32) return MAS_ERR_INVALID_ARG;
   if (!(cfg->dhat > 0) || !(cfg->h > 0) || !(cfg->kappa >= 0)) return MAS_ERR_INVALID_ARG;
   if (cfg->deterministic != 0 && cfg->deterministic != 1) return MAS_ERR_INVALID_ARG;
+  if (cfg->precond != MAS_PRECOND_MAS && cfg->precond != MAS_PRECOND_BJ3) return MAS_ERR_INVALID_ARG;
+  if (cfg->precond == MAS_PRECOND_BJ3 && cfg->deterministic) return MAS_ERR_INVALID_ARG;
   if (cfg->max_contacts < 0 || cfg->max_tris < 0 || cfg->max_edges < 0) return MAS_ERR_INVALID_ARG;
   if (cfg->max_contacts > INT32_MAX / 4 || cfg->max_tris > INT32_MAX / 8 || cfg->max_edges > INT32_MAX / 8)
     return MAS_ERR_INVALID_ARG;
@@ -451,6 +453,10 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->alpha, D0));
   TRY(dalloc(&c->alpha0, D0));
   TRY(dalloc(&c->alpha_mix, D0));
+  if (cfg->precond == MAS_PRECOND_BJ3) {
+    TRY(dalloc(&c->bj, 6 * N));
+    TRY(dalloc(&c->bjinv, 6 * N));
+  }
   TRY(dalloc(&c->ahalf, D0));
   TRY(dalloc(&c->around, SAFE_ROUNDS + 1));
   TRY(dalloc(&c->err, 1));
@@ -636,6 +642,17 @@ mas_status pncg_subspace_step_noalloc(void* p, const double* g, const double* z,
   return launch_subspace_ws(c, g, z, z_prev, v_z, pk_, v_p, restart, out, c.fixed_ws, c.fixed_ws + need - 2);
 }
 
+mas_status pncg_beta_step(void* p, int32_t rule, const double* g, const double* g_prev, const double* z,
+                          const double* z_prev, const double* v_z, double* d, double* v_d, int32_t restart,
+                          double* step, mas_step_out* out) {
+  if (!p || !g || !z || !v_z || !d || !v_d || !step) return MAS_ERR_INVALID_ARG;
+  if (rule != MAS_BETA_FR && rule != MAS_BETA_CD && rule != MAS_BETA_DK) return MAS_ERR_INVALID_ARG;
+  if (!restart && (!g_prev || !z_prev)) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.built) return MAS_ERR_STATE;
+  return launch_beta(c, rule, g, restart ? nullptr : g_prev, z, z_prev, v_z, d, v_d, restart, step, out);
+}
+
 mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, const mas_contacts* ct,
                            double* E, double* g) {
   if (!p || !x || !x_tilde || !E) return MAS_ERR_INVALID_ARG;
@@ -802,7 +819,7 @@ mas_status mas_get_block(void* p, int32_t level, int64_t d, double* out) {
   if (!p || !out) return MAS_ERR_INVALID_ARG;
   Ctx& c = *as_ctx(p);
   if (level < 0 || level >= c.L || d < 0 || d >= c.lv[level].nsub) return MAS_ERR_INVALID_ARG;
-  if (!c.built) return MAS_ERR_STATE;
+  if (!c.built || c.cfg.precond != MAS_PRECOND_MAS) return MAS_ERR_STATE;
   Level& L = c.lv[level];
   uint8_t p8 = 0;
   HIPCHK(hipStreamSynchronize(c.s));
@@ -834,7 +851,7 @@ mas_status mas_block_precisions(void* p, int32_t level, int64_t* counts) {
   if (!p || !counts) return MAS_ERR_INVALID_ARG;
   Ctx& c = *as_ctx(p);
   if (level < 0 || level >= c.L) return MAS_ERR_INVALID_ARG;
-  if (!c.built) return MAS_ERR_STATE;
+  if (!c.built || c.cfg.precond != MAS_PRECOND_MAS) return MAS_ERR_STATE;
   Level& L = c.lv[level];
   std::vector<uint8_t> pr(L.nsub);
   HIPCHK(hipStreamSynchronize(c.s));
@@ -889,7 +906,7 @@ mas_status mas_get_selection(void* p, int32_t* rank_host, int32_t* sel_host) {
   Ctx& c = *as_ctx(p);
   const int64_t D0 = c.lv[0].nsub;
   HIPCHK(hipStreamSynchronize(c.s));
-  if (!c.have_update || c.K == 0) {
+  if (!c.have_update || c.K == 0 || c.cfg.precond != MAS_PRECOND_MAS) {
     if (rank_host) std::memset(rank_host, 0, D0 * sizeof(int32_t));
     if (sel_host) std::fill(sel_host, sel_host + D0 * c.K, -1);
     return MAS_OK;

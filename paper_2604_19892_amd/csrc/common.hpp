@@ -387,6 +387,11 @@ struct Ctx {
   double* Lcap = nullptr;          // D0*K*(K+1)/2
   bool have_update = false;
 
+  // 3x3 block-Jacobi comparison preconditioner (precond = MAS_PRECOND_BJ3):
+  // per vertex the packed lower 3x3 block of H~ (6 doubles) and its inverse
+  double* bj = nullptr;            // 6N
+  double* bjinv = nullptr;         // 6N
+
   // scratch
   double* partials = nullptr;      // reductions
   int n_partial_blocks = 1024;

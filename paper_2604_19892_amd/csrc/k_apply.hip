@@ -270,6 +270,7 @@ __global__ __launch_bounds__(NTILE, WIDE ? 4 : 5) void k_apply_l0(FineArgs fa) {
 }
 
 mas_status launch_apply(Ctx& c, const double* g, double* z) {
+  if (c.cfg.precond == MAS_PRECOND_BJ3) return launch_bj_apply(c, g, z);
   ProfScope ps(c, MAS_T_APPLY);
   if (c.L > 1) {
     for (int l = 1; l < c.L; ++l) {

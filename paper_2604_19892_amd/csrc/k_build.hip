@@ -461,6 +461,7 @@ mas_status launch_level0_build(Ctx& c) {
     else
       k_assemble_l0<double, false><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
   }
+  if (c.cfg.precond == MAS_PRECOND_BJ3) return launch_bj_build(c);  // no MAS level is inverted
   launch_invert(c, 0);
   HIPCHK(hipGetLastError());
   return MAS_OK;
@@ -469,6 +470,7 @@ mas_status launch_level0_build(Ctx& c) {
 // the coarse levels, in order: inverting level l completes the diagonal node
 // blocks of level l + 1
 mas_status launch_coarse_build(Ctx& c) {
+  if (c.cfg.precond == MAS_PRECOND_BJ3) return MAS_OK;
   for (int l = 1; l < c.L; ++l) launch_invert(c, l);
   HIPCHK(hipGetLastError());
   return MAS_OK;

@@ -459,6 +459,130 @@ mas_status launch_subspace(Ctx& c, const double* g, const double* z, const doubl
   return launch_subspace_ws(c, g, z, zp, vz, p, vp, restart, out, c.partials, c.scal);
 }
 
+// ------------------------------------------------- comparison direction rules
+// Classic preconditioned nonlinear CG directions of the search-direction
+// study (Section 5): d = -z + beta d_prev with the Fletcher-Reeves,
+// conjugate-descent or Dai-Kou beta, and the step p = alpha d with alpha
+// minimising the quadratic model g^T p + 1/2 p^T H~ p along d.  The
+// subspace step's reduction supplies g.z, g.d_prev, g.z_prev and the H~
+// products of z and d_prev; three more sums bring in g_prev.
+
+// per block: g_prev.z, g_prev.z_prev, g_prev.d_prev
+__global__ __launch_bounds__(RB) void k_beta_reduce(int64_t n3, const double* gq, const double* z,
+                                                    const double* zq, const double* d, double* part, int nblk) {
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * int64_t(RB) + threadIdx.x; i < n3; i += int64_t(nblk) * RB) {
+    const double a = gq[i];
+    s[0] += a * z[i];
+    s[1] += a * zq[i];
+    s[2] += a * d[i];
+  }
+  block_reduce_store<3>(s, part, nblk);
+}
+
+__global__ __launch_bounds__(RB) void k_beta_finalize(const double* part, const double* part3, int nblk, int rule,
+                                                      int restart, int has_zp, double delta, mas_step_out* out,
+                                                      double* scal) {
+  __shared__ double s[NS];
+  __shared__ double t[3];
+  sum_partials<NS>(part, nblk, s);
+  if (!restart) sum_partials<3>(part3, nblk, t);  // restart is uniform over the block
+  if (threadIdx.x != 0) return;
+  const double gz = s[0], gd = s[1], gzp = s[2];
+  const double A11 = s[3] + s[8], A12 = s[4] + s[9], A22 = s[5] + s[10];
+  double beta = 0.0;
+  int fb = 0;
+  if (!restart) {
+    const double qz = t[0], qzp = t[1], qd = t[2];  // g_prev . (z, z_prev, d_prev)
+    double den = 0.0, b = 0.0;
+    if (rule == MAS_BETA_FR) {
+      den = qzp;
+      b = gz / den;
+    } else if (rule == MAS_BETA_CD) {
+      den = -qd;
+      b = gz / den;
+    } else {  // Dai-Kou: y = g - g_prev, P y = z - z_prev
+      den = gd - qd;                       // d_prev . y
+      const double yz = gz - qz;           // y . z
+      const double yPy = gz - gzp - qz + qzp;
+      b = yz / den - (yPy / den) * (gd / den);
+    }
+    if (den > 0.0) beta = b;
+    else fb = 1;
+  }
+  double gdn = -gz + beta * gd;  // g . d
+  if (!restart && !(gdn < 0.0)) {
+    beta = 0.0;
+    fb = 1;
+    gdn = -gz;
+  }
+  const double dHd = beta == 0.0 ? A11 : A11 - 2.0 * beta * A12 + beta * beta * A22;
+  double alpha;
+  if (dHd > 0.0) {
+    alpha = -gdn / dHd;
+  } else {
+    alpha = 1.0;
+    fb = 1;
+  }
+  const double r = has_zp ? fabs(gzp) / gz : 0.0;
+  mas_step_out o;
+  o.mu = alpha;
+  o.nu = beta;
+  o.r = r;
+  o.gz = gz;
+  o.gp = gd;
+  o.gzp = gzp;
+  o.A11 = A11;
+  o.A12 = A12;
+  o.A22 = A22;
+  o.gnorm2 = s[6];
+  o.znorm2 = s[7];
+  o.fallback = fb;
+  o.restart_next = (r > delta) ? 1 : 0;
+  o.restart_used = restart ? 1 : 0;
+  o.reserved = 0;
+  if (out) *out = o;
+  scal[0] = alpha;
+  scal[1] = beta;
+}
+
+// d <- -z + beta d;  v_d <- -v_z + beta v_d;  p = alpha d
+__global__ void k_beta_update(int64_t n3, const double* z, const double* vz, double* d, double* vd, double* p,
+                              const double* scal) {
+  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  const double alpha = scal[0], beta = scal[1];
+  double dn, vn;
+  if (beta == 0.0) {
+    dn = -z[i];
+    vn = -vz[i];
+  } else {
+    dn = -z[i] + beta * d[i];
+    vn = -vz[i] + beta * vd[i];
+  }
+  d[i] = dn;
+  vd[i] = vn;
+  p[i] = alpha * dn;
+}
+
+mas_status launch_beta(Ctx& c, int rule, const double* g, const double* gq, const double* z, const double* zq,
+                       const double* vz, double* d, double* vd, int restart, double* p, mas_step_out* out) {
+  ProfScope ps(c, MAS_T_SUBSPACE);
+  const int nb = c.n_partial_blocks;
+  const int64_t n3 = 3 * c.N;
+  const int64_t m = (c.have_update) ? c.mc : 0;
+  double* part = c.partials;
+  double* part3 = c.partials + int64_t(NS) * nb;  // rows NS..NS+2 of the 16-row workspace
+  k_ss_reduce<<<dim3(nb), dim3(RB), 0, c.s>>>(n3, g, z, zq, d, vz, vd, restart ? 0 : 1, m, c.Uidx, c.U, c.dS,
+                                              part, nb);
+  if (!restart) k_beta_reduce<<<dim3(nb), dim3(RB), 0, c.s>>>(n3, gq, z, zq, d, part3, nb);
+  k_beta_finalize<<<dim3(1), dim3(RB), 0, c.s>>>(part, part3, nb, rule, restart, zq != nullptr,
+                                                 c.cfg.restart_delta, out, c.scal);
+  k_beta_update<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, z, vz, d, vd, p, c.scal);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
 // ------------------------------------------------------------- safe step
 __global__ void k_alpha_init(int64_t D, double* a0, double* amix, uint64_t* half, uint32_t* rounds) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;

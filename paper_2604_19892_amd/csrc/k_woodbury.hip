@@ -374,9 +374,17 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
         c.bkey, c.hkey, c.hval, c.hsize - 1, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err, c.cls_part);
     HIPCHK(hipGetLastError());
   }
+  const int64_t D = c.lv[0].nsub;
+  if (c.cfg.precond == MAS_PRECOND_BJ3) {
+    // the vertex blocks of H~ instead of Top-K and capacitance
+    if (rank_hist) {
+      fill_i32(c, rank_hist, c.K + 1, 0);
+      fill_i32(c, rank_hist, 1, int32_t(D));
+    }
+    return launch_bj_update(c, m);
+  }
   st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
   if (st != MAS_OK) return st;
-  const int64_t D = c.lv[0].nsub;
   if (rank_hist) fill_i32(c, rank_hist, c.K + 1, 0);
   if (c.K == 0) {
     fill_i32(c, c.rank, D, 0);

@@ -53,6 +53,12 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist);
 // k_apply.hip ----------------------------------------------------------
 mas_status launch_apply(Ctx& c, const double* g, double* z);
 
+// k_jacobi.hip ---------------------------------------------------------
+// 3x3 block-Jacobi comparison preconditioner (precond = MAS_PRECOND_BJ3)
+mas_status launch_bj_build(Ctx& c);
+mas_status launch_bj_update(Ctx& c, int64_t m);
+mas_status launch_bj_apply(Ctx& c, const double* g, double* z);
+
 // k_hessvec.hip --------------------------------------------------------
 mas_status launch_hessvec(Ctx& c, const double* v, double* y, int with_update);
 
@@ -67,6 +73,10 @@ int64_t subspace_workspace_elems(const Ctx& c);
 mas_status launch_subspace_ws(Ctx& c, const double* g, const double* z, const double* zp, const double* vz,
                               double* p, double* vp, int restart, mas_step_out* out, double* part,
                               double* scal);
+// comparison direction rules (rule: MAS_BETA_FR, MAS_BETA_CD, MAS_BETA_DK)
+mas_status launch_beta(Ctx& c, int rule, const double* g, const double* g_prev, const double* z,
+                       const double* z_prev, const double* vz, double* d, double* vd, int restart, double* p,
+                       mas_step_out* out);
 mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_contacts* cand,
                             double scale, double* alpha, double* x_out);
 mas_status launch_step_with(Ctx& c, const double* x, const double* p, double scale, double* alpha,

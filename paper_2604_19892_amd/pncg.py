@@ -22,11 +22,32 @@ from . import synth
 from .binding import DeviceContacts, MasContext, make_config
 
 
+UPDATES = ("woodbury", "freeze", "rebuild")
+RULES = ("subspace", "fr", "cd", "dk")
+
+
 class PNCG:
+    """``update`` and ``rule`` select the variants of the ablation study
+    (Section 5): "woodbury" (the method), "freeze" (the restart's MAS kept
+    until the next restart: max_rank 0, so the preconditioner takes no
+    Top-K columns while H~ keeps the untruncated U) or "rebuild" (mas_build
+    at every iteration; H_base p is then recomputed by one more hess_vec);
+    "subspace" (the method's 2x2 step) or a comparison rule "fr", "cd",
+    "dk" (pncg_beta_step); ``precond`` "bj3" swaps MAS for the 3x3
+    block-Jacobi comparison preconditioner."""
+
     def __init__(self, scene, block_prec="f32", levels=None, K=None, delta=0.3, hess_prec=None,
-                 max_halvings=8, device="cuda", deterministic=False, prec_guard=None, collect_stats=False):
+                 max_halvings=8, device="cuda", deterministic=False, prec_guard=None, collect_stats=False,
+                 update="woodbury", rule="subspace", precond="mas"):
+        if update not in UPDATES or rule not in RULES:
+            raise ValueError("unknown update strategy or direction rule")
+        self.update = update
+        self.rule = rule
+        if update == "freeze":
+            K = 0
         cfg = make_config(scene, levels=levels, K=K, block_prec=block_prec, hess_prec=hess_prec,
-                          delta=delta, deterministic=deterministic, prec_guard=prec_guard)
+                          delta=delta, deterministic=deterministic, prec_guard=prec_guard, precond=precond)
+        self.precond = precond
         self.collect_stats = collect_stats
         self.ctx = ctx = MasContext(scene, cfg, device=device)
         self.scene = scene
@@ -44,6 +65,7 @@ class PNCG:
         v = ctx.vec
         self.x_trial, self.g, self.g_trial = v(), v(), v()
         self.z, self.z_prev, self.vz, self.p, self.vp = v(), v(), v(), v(), v()
+        self.step = v() if rule != "subspace" else None
         self.E = torch.zeros(1, dtype=torch.float64, device=device)
         self.E_trial = torch.zeros(1, dtype=torch.float64, device=device)
         self.rank_hist = torch.zeros(max(cfg.max_rank, 0) + 1, dtype=torch.int32, device=device)
@@ -64,18 +86,31 @@ class PNCG:
 
     def iterate(self):
         ctx = self.ctx
+        # p and vp hold the previous step (subspace) or direction (rules) and
+        # its H_base product
         if self.restart:
             ctx.build(self.x, self.pool)
             self.n_restarts += 1
             if self.track_precisions:
                 self.precision_counts = ctx.block_precisions(0)
+        elif self.update == "rebuild":
+            ctx.build(self.x, self.pool)
+            ctx.hess_vec(self.p, with_update=False, y=self.vp)
         else:
             ctx.woodbury_update(self.pool, self.rank_hist)
         ctx.apply(self.g, self.z)
         ctx.hess_vec(self.z, with_update=False, y=self.vz)
-        ctx.subspace_step(self.g, self.z, self.z_prev if self.fk > 0 else None, self.vz, self.p, self.vp,
-                          self.restart)
-        ctx.safe_step(self.x, self.p, self.pool, 1.0, self.x_trial)
+        z_prev = self.z_prev if self.fk > 0 else None
+        if self.rule == "subspace":
+            ctx.subspace_step(self.g, self.z, z_prev, self.vz, self.p, self.vp, self.restart)
+            step = self.p
+        else:
+            # g_trial holds the previous iterate's gradient after an accepted
+            # step; a rejected one makes this iteration a restart
+            ctx.beta_step(self.rule, self.g, self.g_trial, self.z, z_prev, self.vz, self.p, self.vp,
+                          self.restart, self.step)
+            step = self.step
+        ctx.safe_step(self.x, step, self.pool, 1.0, self.x_trial)
         scale = 1.0
         accepted = False
         for h in range(self.max_halvings + 1):
@@ -88,7 +123,7 @@ class PNCG:
             if h < self.max_halvings:
                 scale *= 0.5
                 self.n_halvings += 1
-                ctx.safe_step(self.x, self.p, None, scale, self.x_trial)
+                ctx.safe_step(self.x, step, None, scale, self.x_trial)
         st = ctx.step_out()
         if self.g0norm is None:
             self.g0norm = np.sqrt(st["gnorm2"])

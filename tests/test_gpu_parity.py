@@ -179,6 +179,92 @@ def test_subspace_step(case):
     assert rel(ctx.from_lib(dp), pn0) < 1e-10
 
 
+@pytest.mark.parametrize("rule", ["fr", "cd", "dk"])
+def test_beta_step(case, rule):
+    """pncg_beta_step against the oracle's comparison rules: beta, alpha,
+    the new direction and its H_base product, the step, and the restart
+    form."""
+    from oracle.solver import RULES
+    rng = np.random.default_rng(7)
+    n = 3 * case.scene.N
+    xt = fem.inertial_target(case.scene.x, case.scene.v, case.scene.h, case.scene.gravity).reshape(-1)
+    g = case.prob.gradient(case.scene.x, xt, case.curr)
+    z = case.M.apply(g, case.blocks)
+    sc_z = np.abs(z).max()
+    g_prev = g + 0.5 * rng.standard_normal(n) * np.abs(g).max()
+    z_prev = case.M.apply(g_prev, case.blocks)
+    d_prev = -0.8 * z_prev + 0.05 * rng.standard_normal(n) * sc_z
+
+    def Ht(v):
+        return case.H @ v + case.U @ (case.U.T @ v)
+
+    a, b, dn, pn, fb = pncg.beta_step(RULES[rule], g, g_prev, z, z_prev, d_prev, Ht, restart=False)
+    assert not fb and b != 0.0
+    r = pncg.restart_ratio(g, z_prev, z)
+    ctx = case.ctx
+    dd, dvd, dp = ctx.to_lib(d_prev), ctx.to_lib(case.H @ d_prev), ctx.vec()
+    ctx.beta_step(rule, ctx.to_lib(g), ctx.to_lib(g_prev), ctx.to_lib(z), ctx.to_lib(z_prev),
+                  ctx.to_lib(case.H @ z), dd, dvd, False, dp)
+    s = ctx.step_out()
+    assert s['fallback'] == 0 and s['restart_used'] == 0
+    assert s['nu'] == pytest.approx(b, rel=1e-10)
+    assert s['mu'] == pytest.approx(a, rel=1e-10)
+    assert s['r'] == pytest.approx(r, rel=1e-10)
+    assert rel(ctx.from_lib(dd), dn) < 1e-10
+    assert rel(ctx.from_lib(dvd), case.H @ dn) < 1e-10
+    assert rel(ctx.from_lib(dp), pn) < 1e-10
+    # restart form (g_prev not read): the subspace step's restart step
+    a0, b0, dn0, pn0, fb0 = pncg.beta_step(RULES[rule], g, None, z, None, None, Ht, restart=True)
+    dd, dvd = ctx.to_lib(d_prev), ctx.to_lib(case.H @ d_prev)
+    ctx.beta_step(rule, ctx.to_lib(g), None, ctx.to_lib(z), None, ctx.to_lib(case.H @ z), dd, dvd, True, dp)
+    s = ctx.step_out()
+    assert s['mu'] == pytest.approx(a0, rel=1e-10) and s['nu'] == 0.0 and s['restart_used'] == 1
+    assert rel(ctx.from_lib(dp), pn0) < 1e-10
+    assert rel(ctx.from_lib(dd), -z) < 1e-15
+    # a previous direction pointing uphill: fallback to d = -z
+    up = ctx.to_lib(z_prev)
+    ctx.beta_step("cd", ctx.to_lib(g), ctx.to_lib(g_prev), ctx.to_lib(z), ctx.to_lib(z_prev),
+                  ctx.to_lib(case.H @ z), up, ctx.to_lib(case.H @ z_prev), False, dp)
+    s = ctx.step_out()
+    a1, b1, dn1, pn1, fb1 = pncg.beta_step(pncg.BETA_CD, g, g_prev, z, z_prev, z_prev, Ht, restart=False)
+    assert fb1 and s['fallback'] == 1 and s['nu'] == 0.0
+    assert rel(ctx.from_lib(dp), pn1) < 1e-10
+    with pytest.raises(Exception):
+        ctx.beta_step("fr", ctx.to_lib(g), None, ctx.to_lib(z), None, ctx.to_lib(case.H @ z), dd, dvd, False, dp)
+
+
+def test_block_jacobi_preconditioner(case):
+    """precond = MAS_PRECOND_BJ3: z = blockdiag(H~_ii)^-1 g after mas_build
+    (H~ = H_base) and after mas_woodbury_update (H~ = H_base + U U^T),
+    against the oracle's dense 3x3 inverses; the MAS block queries refuse."""
+    from oracle import jacobi
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    sc = case.scene
+    ctx = MasContext(sc, make_config(sc, levels=case.hier.L, K=8, precond="bj3"))
+    try:
+        rng = np.random.default_rng(9)
+        g = rng.standard_normal(3 * sc.N)
+        ctx.build(ctx.to_lib(sc.x), ctx.contacts(case.base))
+        z = ctx.from_lib(ctx.apply(ctx.to_lib(g)))
+        assert rel(z, jacobi.apply(jacobi.inverse_blocks(case.H), g)) < 1e-12
+        hist = case.torch.zeros(9, dtype=case.torch.int32, device="cuda")
+        ctx.woodbury_update(ctx.contacts(case.curr), hist)
+        z = ctx.from_lib(ctx.apply(ctx.to_lib(g)))
+        Ht = case.H + case.U @ case.U.T
+        assert rel(z, jacobi.apply(jacobi.inverse_blocks(Ht), g)) < 1e-12
+        # hess_vec and the update columns are those of the MAS mode
+        v = rng.standard_normal(3 * sc.N)
+        y = ctx.from_lib(ctx.hess_vec(ctx.to_lib(v), with_update=True))
+        assert rel(y, Ht @ v) < 1e-10
+        assert int(hist[0].item()) == int(case.ctx.nsub[0]) and int(hist[1:].sum().item()) == 0
+        code, msg = ctx.sync()
+        assert code == 0, msg
+        with pytest.raises(Exception):
+            ctx.get_block(0, 0)
+    finally:
+        ctx.close()
+
+
 def test_energy_gradient(case):
     sc = case.scene
     xt = fem.inertial_target(sc.x, sc.v, sc.h, sc.gravity).reshape(-1)

@@ -32,6 +32,35 @@ def test_pncg_trajectory_matches_oracle():
     assert code == 0, msg
 
 
+@pytest.mark.parametrize("update,rule,precond", [("freeze", "subspace", "mas"), ("rebuild", "subspace", "mas"),
+                                                 ("woodbury", "fr", "mas"), ("woodbury", "cd", "mas"),
+                                                 ("woodbury", "dk", "mas"), ("rebuild", "dk", "mas"),
+                                                 ("woodbury", "subspace", "bj3"), ("woodbury", "fr", "bj3")])
+def test_ablation_variants_match_oracle(update, rule, precond):
+    """The update strategies and direction rules of the ablation study
+    against the oracle's loop with the same variant (ratio test off, so that
+    every iteration after the first uses the variant's update and rule)."""
+    from paper_2604_19892_amd.pncg import PNCG
+    print("\n[ablation case] grid, update %s, rule %s, preconditioner %s" % (update, rule, precond), flush=True)
+    sc = synth.grid_scene()
+    ora = OraclePNCG(sc, update=update, rule=rule, precond=precond, delta=1e3)
+    gpu = PNCG(sc, block_prec="f64", update=update, rule=rule, precond=precond, delta=1e3)
+    for k in range(4):
+        ora.iterate()
+        gpu.iterate()
+        lo, lg = ora.log[-1], gpu.log[-1]
+        assert lo["restart"] == lg["restart"], k
+        assert lo["fallback"] == lg["fallback"], k
+        assert lg["mu"] == pytest.approx(lo["mu"], rel=1e-7), k
+        assert lg["nu"] == pytest.approx(lo["nu"], rel=1e-6, abs=1e-9), k
+        xg = gpu.ctx.from_lib(gpu.x)
+        err = np.linalg.norm(xg - ora.x) / np.linalg.norm(ora.x - sc.x.reshape(-1))
+        assert err < 1e-6, (k, err)
+    assert sum(not r["restart"] for r in gpu.log) == 3
+    code, msg = gpu.ctx.sync()
+    assert code == 0, msg
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_pncg_reaches_tolerance(prec):
     from paper_2604_19892_amd.pncg import PNCG

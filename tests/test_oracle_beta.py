@@ -183,3 +183,17 @@ def test_variants_never_raise_the_energy(grid, update, rule):
     E = [r['E'] for r in s.log] + [s.prob.energy(s.x, s.x_tilde, s.constraint_set(s.x))]
     assert all(b <= a for a, b in zip(E, E[1:]))
     assert E[-1] < E[0]
+
+
+def test_block_jacobi_loop(grid):
+    from oracle import fem, jacobi, solver
+    s = solver.OraclePNCG(grid, precond="bj3")
+    x0 = s.x.copy()
+    C = s.constraint_set(x0)
+    g, z, p = s.iterate()
+    H = fem.Problem(grid).assemble(x0, C)
+    np.testing.assert_allclose(z, jacobi.apply(jacobi.inverse_blocks(H), g), rtol=1e-13, atol=0)
+    for _ in range(3):
+        s.iterate()
+    E = [r['E'] for r in s.log]
+    assert all(b <= a for a, b in zip(E, E[1:])) and E[-1] < E[0]
