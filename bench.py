@@ -425,6 +425,66 @@ def tolerance_solves(sc, forms, tol, max_iter, repeats):
     return out
 
 
+ABLATION_VARIANTS = (("woodbury", "subspace", "mas"), ("freeze", "subspace", "mas"),
+                     ("rebuild", "subspace", "mas"), ("woodbury", "fr", "mas"), ("woodbury", "cd", "mas"),
+                     ("woodbury", "dk", "mas"), ("woodbury", "subspace", "bj3"))
+
+
+def _variant_solve(sc, update, rule, precond, tol, max_iter, prec="f32"):
+    import torch
+    from paper_2604_19892_amd.pncg import PNCG
+    s = PNCG(sc, block_prec=prec, hess_prec="f32", update=update, rule=rule, precond=precond)
+    it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
+    code, msg = s.ctx.sync()
+    rec = {"update": update, "rule": rule, "preconditioner": precond, "iters": it, "seconds": sec,
+           "ms_per_iter": 1e3 * sec / max(it, 1), "rel_gnorm": rel, "converged": bool(rel <= tol),
+           "restarts": s.n_restarts, "status": code}
+    s.ctx.close()
+    del s
+    torch.cuda.empty_cache()
+    return rec
+
+
+def ablation_solves(sc, tol, max_iter):
+    """The ablation study's variants on one scene (Section 5): update
+    strategy (Woodbury, Freeze, Full Rebuild), direction rule (2x2 subspace
+    step, FR, CD, DK) and preconditioner (MAS, 3x3 block-Jacobi); one solve
+    each from the scene's start to ||grad E|| <= tol ||grad E_0|| (at most
+    max_iter iterations)."""
+    runs = []
+    for update, rule, precond in ABLATION_VARIANTS:
+        rec = _variant_solve(sc, update, rule, precond, tol, max_iter)
+        print("[bench] ablation %s/%s/%s: %d iters %.2fs rel %.2e" % (
+            update, rule, precond, rec["iters"], rec["seconds"], rec["rel_gnorm"]), file=sys.stderr, flush=True)
+        runs.append(rec)
+    return {"workload": sc.name, "tol": tol, "max_iter": max_iter, "block_storage": "f32",
+            "hessian_storage": "f32", "runs": runs}
+
+
+def stiffness_sweep(tol, max_iter, moduli=(2.15e4, 1e5, 1e6, 1e7)):
+    """MAS-PNCG against 3x3 block-Jacobi PNCG as the material stiffens
+    (Section 5, stiffness robustness): the two-box scene with one Young's
+    modulus per run, and with the modulus graded geometrically over the
+    height from 2.15e4 to 1e7 (a 500-fold span).  Barrier stiffness 1e3 rho
+    edge^3, as for the puffer balls: with rho edge^3 the stiff materials
+    press the stencils to distances where the blocks lose definiteness in
+    float64."""
+    from paper_2604_19892_amd import synth
+    base = synth.two_boxes_scene(active_frac=0.8, kappa_scale=1e3)
+    scenes = [(float(E), synth.with_youngs(base, E)) for E in moduli]
+    scenes.append(("graded 2.15e4..1e7", synth.graded_stiffness(base)))
+    runs = []
+    for label, sc in scenes:
+        for precond in ("mas", "bj3"):
+            rec = _variant_solve(sc, "woodbury", "subspace", precond, tol, max_iter)
+            rec["youngs"] = label
+            print("[bench] stiffness %s %s: %d iters %.2fs rel %.2e" % (
+                label, precond, rec["iters"], rec["seconds"], rec["rel_gnorm"]), file=sys.stderr, flush=True)
+            runs.append(rec)
+    return {"workload": "two_boxes (64000 verts, 288990 tets, 20000 stencils)", "tol": tol, "max_iter": max_iter,
+            "runs": runs}
+
+
 def precision_errors(sc, seed=12):
     """Error of each output of the mixed-precision forms against the float64
     form on the same inputs at the full scene: mas_apply after a rebuild at
@@ -476,6 +536,8 @@ def main():
                     help="skip the solves to the gradient tolerance (f64 vs mixed storage)")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-frame regime")
     ap.add_argument("--no-geo", action="store_true", help="skip the geometric-contacts measurement")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the ablation variants and the stiffness sweep")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=1500)
     ap.add_argument("--solve-repeats", type=int, default=5)
@@ -682,6 +744,10 @@ def main():
         out["precision_errors"] = precision_errors(sc)
         out["tol_solve"] = tolerance_solves(sc, tuple(SOLVE_FORMS), args.solve_tol,
                                             args.solve_max_iter, args.solve_repeats)
+    if not args.no_ablation:
+        print("[bench] ablations", file=sys.stderr, flush=True)
+        out["ablations"] = ablation_solves(sc, args.solve_tol, args.solve_max_iter)
+        out["stiffness_sweep"] = stiffness_sweep(args.solve_tol, args.solve_max_iter)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc.N)

@@ -291,6 +291,12 @@ class GeoPNCG:
         ctx.hess_vec(self.z, with_update=False, y=self.vz)
         ctx.subspace_step(self.g, self.z, self.z_prev if self.k > 0 else None, self.vz, self.p, self.vp,
                           self.restart)
+        st = ctx.step_out()
+        if not (np.isfinite(st["mu"]) and np.isfinite(st["nu"])):
+            # a block or capacitance factor failed: report the library's first error
+            code, msg = ctx.sync()
+            raise RuntimeError("GeoPNCG iteration %d: non-finite step scalars; library status %d (%s)"
+                               % (self.k, code, msg))
         mc = self._set(self.x, self.cand, self.radius)
         ctx.ccd_safe_step(self.x, self.p, self.radius, self.cand.pairs, self.cand.kind, self.cand.dist, mc, 1.0,
                           self.x_trial)
@@ -307,7 +313,6 @@ class GeoPNCG:
             if h < self.max_halvings:
                 scale *= 0.5
                 ctx.safe_step(self.x, self.p, None, scale, self.x_trial)
-        st = ctx.step_out()
         self.log.append(dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), mu=st["mu"], nu=st["nu"], r=st["r"],
                              restart=bool(self.restart), fallback=bool(st["fallback"]), E=self.E_host,
                              m=self.C.m, candidates=mc, scale=scale, accepted=accepted))

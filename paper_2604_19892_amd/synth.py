@@ -326,11 +326,12 @@ def _loguniform(rng, lo, hi, n):
 # ---------------------------------------------------------- two boxes
 
 def two_boxes_scene(seed=1, n_contacts=20000, dhat=1e-3, h=0.01, E=1e5, nu=0.4, rho=1000.0,
-                    levels=3, K=8, nxy=40, nz=20, active_frac=1.0):
+                    levels=3, K=8, nxy=40, nz=20, active_frac=1.0, kappa_scale=1.0):
     """Two 40x40x20-vertex boxes (edge 1/39) stacked with the upper box
     offset by half an edge in x and y; PT and EE stencils between the
     facing layers with distances log-uniform in (1e-6, dhat) and normals
-    within 10 degrees of the vertical."""
+    within 10 degrees of the vertical.  Barrier stiffness kappa_scale * rho
+    * edge^3."""
     rng = np.random.default_rng(seed)
     edge = 1.0 / (nxy - 1)
     Xl, tl = lattice_from_cubes(box_cubes(nxy, nxy, nz), edge, (0, 0, 0))
@@ -377,18 +378,23 @@ def two_boxes_scene(seed=1, n_contacts=20000, dhat=1e-3, h=0.01, E=1e5, nu=0.4, 
     T = tets.shape[0]
     return Scene("two_boxes", X, x, np.zeros_like(X), tets,
                  np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
-                 kappa=rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]),
+                 kappa=kappa_scale * rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]),
                  pool=pool, levels=levels, K=K)
 
 
 def stacked_boxes_scene(seed=4, nxy=10, nz=5, dhat=1e-3, h=0.01, E=1e5, nu=0.4, rho=1000.0, levels=2, K=8,
-                        gap=0.5, speed=0.5):
+                        gap=0.5, speed=0.5, kappa_scale=1e3):
     """Two boxes for geometric contacts: the upper one (offset by half an
     edge in x and y) rests gap * dhat above the lower one and moves down at
     ``speed`` (its inertial target lies far inside the lower box, so the
     barrier has to hold it); vertex noise of 0.05 gap * dhat keeps the start
     free of intersections.  No contact pool: the contacts are the boundary
-    surface's point-triangle and edge-edge pairs within dhat."""
+    surface's point-triangle and edge-edge pairs within dhat.
+
+    The barrier stiffness is kappa_scale * rho * edge^3, as for the puffer
+    balls: at kappa_scale = 1 the CCD-limited steps let surface pairs close
+    to 1e-12 and below (the safe step only keeps them apart), where the
+    barrier's curvature puts the blocks beyond float64 Cholesky."""
     rng = np.random.default_rng(seed)
     edge = 1.0 / (nxy - 1)
     Xl, tl = lattice_from_cubes(box_cubes(nxy, nxy, nz), edge, (0, 0, 0))
@@ -402,7 +408,8 @@ def stacked_boxes_scene(seed=4, nxy=10, nz=5, dhat=1e-3, h=0.01, E=1e5, nu=0.4, 
     T = tets.shape[0]
     empty = stencil_pool(np.zeros(0, np.uint64), np.zeros((0, 4), np.int32), np.zeros((0, 12)), x, np.zeros(0))
     return Scene("stacked_boxes", X, x, v, tets, np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
-                 kappa=rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]), pool=empty, levels=levels, K=K)
+                 kappa=kappa_scale * rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]), pool=empty,
+                 levels=levels, K=K)
 
 
 def churn_set(rng, scene, base, frac=0.3):
@@ -576,6 +583,23 @@ def puffer_scene(seed=2, n_balls_axis=2, core=(36, 36, 37), n_spikes=1182, spike
                  np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
                  kappa=kappa_scale * rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]),
                  pool=pool, levels=levels, K=K)
+
+
+def graded_stiffness(scene, lo=2.15e4, hi=1e7):
+    """A copy of the scene whose Young's modulus grows geometrically with
+    the height of each tet's centroid, from lo at the lowest to hi at the
+    highest (the 500-fold span of the paper's stiffness-robustness scene,
+    Section 5)."""
+    import dataclasses
+    zc = scene.X[scene.tets].mean(axis=1)[:, 2]
+    t = (zc - zc.min()) / max(float(zc.max() - zc.min()), 1e-300)
+    return dataclasses.replace(scene, name=scene.name + "_graded", youngs=lo * (hi / lo) ** t)
+
+
+def with_youngs(scene, E):
+    """A copy of the scene with one Young's modulus E for every tet."""
+    import dataclasses
+    return dataclasses.replace(scene, name="%s_E%.3g" % (scene.name, E), youngs=np.full(scene.T, float(E)))
 
 
 def surface(tets):
