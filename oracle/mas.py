@@ -22,6 +22,31 @@ it names in supplement Section 1.2):
 * a level-l subdomain is a run of 32 consecutive level-l nodes (96x96
   blocks); the last one may be smaller.
 
+The connectivity-aware grouping (supplement Section 1.2: an adjacency
+graph of nodes that share an element, grouped by greedy aggregation) is
+the alternative order ``connectivity_perm``; the paper gives no procedure,
+and the reading taken here is:
+* level-0 graph: vertices adjacent when they share a tet; its nodes are
+  numbered component by component (components in the order of their
+  smallest Morton rank), by Morton rank inside a component;
+* a cluster starts at the smallest unassigned node and repeatedly takes the
+  smallest unassigned node adjacent to any of its members, or, when there
+  is none, the smallest unassigned node, until it holds 32 nodes;
+  clusters are numbered in the order they are started;
+* the graph of level l + 1 has the clusters of level l as nodes, adjacent
+  when some of their members are, and is aggregated the same way;
+* a node holding fewer than 32^l vertices (only the last one can) is kept
+  out of the growth and appended to the last cluster (or starts one of its
+  own when that cluster is full), so every level-l node but the last holds
+  exactly 32^l vertices;
+* the vertex order lists the clusters of the top level in their order and,
+  inside each cluster, its members in the order they were added, down to
+  the vertices; runs of 32^l consecutive vertices are then the level-l
+  nodes, as for the Morton order.
+The paper's dynamic reconnection (contact edges added to the graph as
+contacts form) would change the order, and with it the data layout,
+between rebuilds; it is not part of this reading.
+
 Every block is cut out of the assembled matrix with explicit S_d / C_(l)
 and inverted with numpy.linalg.inv; nothing is blocked or fused.
 """
@@ -54,13 +79,141 @@ def morton_perm(X):
     return np.argsort(morton_codes(X), kind='stable').astype(np.int64)
 
 
-class Hierarchy:
-    """Subdomain and coarsening structure for N vertices and L levels."""
+def vertex_adjacency(tets, n):
+    """Adjacency sets of the graph whose nodes 0..n-1 are adjacent when they
+    share a tet (tets given in those node ids)."""
+    adj = [set() for _ in range(n)]
+    for t in np.asarray(tets, np.int64).reshape(-1, 4):
+        for a in range(4):
+            for b in range(4):
+                if t[a] != t[b]:
+                    adj[int(t[a])].add(int(t[b]))
+    return adj
 
-    def __init__(self, X, levels):
+
+def aggregate(adj, n, sub=SUB, partial_last=False):
+    """Greedy aggregation of the nodes 0..n-1 of a graph into clusters of
+    ``sub`` nodes (the reading in the module docstring).  With
+    ``partial_last`` the node n-1 is left out of the growth and appended to
+    the last cluster (or starts its own).  Returns the clusters, each the
+    list of its nodes in the order they were added."""
+    limit = n - 1 if partial_last else n
+    assigned = np.zeros(n, bool)
+    clusters = []
+    for seed in range(limit):
+        if assigned[seed]:
+            continue
+        members = []
+        cand = set()
+        u = seed
+        while True:
+            members.append(u)
+            assigned[u] = True
+            cand.discard(u)
+            cand.update(w for w in adj[u] if w < limit and not assigned[w])
+            if len(members) == sub:
+                break
+            if cand:
+                u = min(cand)
+            else:
+                rest = np.flatnonzero(~assigned[:limit])
+                if rest.size == 0:
+                    break
+                u = int(rest[0])
+        clusters.append(members)
+    if partial_last:
+        if clusters and len(clusters[-1]) < sub:
+            clusters[-1].append(n - 1)
+        else:
+            clusters.append([n - 1])
+    return clusters
+
+
+def cluster_adjacency(adj, clusters):
+    """Adjacency of the clusters: two are adjacent when some of their
+    members are."""
+    cid = np.empty(len(adj), np.int64)
+    for c, mem in enumerate(clusters):
+        cid[mem] = c
+    cadj = [set() for _ in clusters]
+    for u, nb in enumerate(adj):
+        for w in nb:
+            if cid[u] != cid[w]:
+                cadj[cid[u]].add(int(cid[w]))
+    return cadj
+
+
+def component_major_perm(X, tets):
+    """perm[id] = vertex of level-0 node id: vertices grouped by connected
+    component of the tet graph (components in the order of their smallest
+    Morton rank), by Morton rank inside a component."""
+    from scipy.sparse.csgraph import connected_components
+    N = X.shape[0]
+    mperm = morton_perm(X)
+    t = np.asarray(tets, np.int64)
+    rows = np.repeat(t, 4, axis=1).ravel()
+    cols = np.tile(t, (1, 4)).ravel()
+    A = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(N, N)).tocsr()
+    _, lab = connected_components(A, directed=False)
+    comp = lab[mperm]                      # component of each Morton rank
+    first = np.full(comp.max() + 1 if N else 0, N, np.int64)
+    np.minimum.at(first, comp, np.arange(N))
+    order = np.lexsort((np.arange(N), first[comp]))
+    return mperm[order]
+
+
+def connectivity_clusters(X, tets, levels, sub=SUB):
+    """The clusters of every level (level l: clusters of level-l nodes) and
+    the vertex of each level-0 node."""
+    N = X.shape[0]
+    mperm = component_major_perm(X, tets)
+    mrank = np.empty(N, np.int64)
+    mrank[mperm] = np.arange(N)
+    adj = vertex_adjacency(mrank[np.asarray(tets, np.int64)], N)
+    size = np.ones(N, np.int64)
+    out = []
+    for l in range(levels):
+        n = len(adj)
+        partial = n > 0 and size[-1] < sub ** l
+        cl = aggregate(adj, n, sub, partial_last=partial)
+        out.append(cl)
+        size = np.array([size[m].sum() for m in cl], np.int64)
+        adj = cluster_adjacency(adj, cl)
+    return mperm, out
+
+
+def connectivity_perm(X, tets, levels, sub=SUB):
+    """perm[new] = old vertex id of the connectivity-aware order."""
+    mperm, cls = connectivity_clusters(X, tets, levels, sub)
+
+    def expand(l, c):
+        if l < 0:
+            return [c]
+        out = []
+        for m in cls[l][c]:
+            out.extend(expand(l - 1, m))
+        return out
+
+    order = []
+    for c in range(len(cls[-1])):
+        order.extend(expand(len(cls) - 1, c))
+    return mperm[np.asarray(order, np.int64)]
+
+
+class Hierarchy:
+    """Subdomain and coarsening structure for N vertices and L levels, in
+    the Morton order or (``tets`` given, ``order="connectivity"``) the
+    connectivity-aware one."""
+
+    def __init__(self, X, levels, tets=None, order="morton"):
         self.N = X.shape[0]
         self.L = levels
-        self.perm = morton_perm(X)
+        if order == "connectivity":
+            self.perm = connectivity_perm(X, tets, levels)
+        elif order == "morton":
+            self.perm = morton_perm(X)
+        else:
+            raise ValueError(order)
         self.rank = np.empty(self.N, np.int64)
         self.rank[self.perm] = np.arange(self.N)
 

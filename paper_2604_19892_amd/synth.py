@@ -412,6 +412,64 @@ def stacked_boxes_scene(seed=4, nxy=10, nz=5, dhat=1e-3, h=0.01, E=1e5, nu=0.4, 
                  levels=levels, K=K)
 
 
+def combs_scene(seed=3, teeth=8, width=2, tooth_len=12, base=2, depth=4, dhat=1e-3, h=0.01, E=1e5, nu=0.4,
+                rho=1000.0, levels=2, K=8, kappa_scale=1e3):
+    """Two combs whose teeth interleave one lattice edge apart (edge 1/32):
+    parts that are close in space but not connected, the case where a
+    Morton grouping puts vertices of both combs into one subdomain.  Teeth
+    ``width`` cubes wide, ``tooth_len`` long and ``depth`` deep hang from
+    slabs ``base`` cubes thick.  Affine point-point stencils join facing
+    vertices of neighbouring teeth (d = x_B - x_A along the x axis minus an
+    offset), with distances log-uniform in (1e-6, dhat)."""
+    rng = np.random.default_rng(seed)
+    edge = 1.0 / 32
+    pitch = width + 1
+    nxc = 2 * teeth * pitch
+    ca, cb = [], []
+    for i in range(nxc):
+        for k in range(depth):
+            for j in range(base):
+                ca.append((i, j, k))
+                cb.append((i, base + 1 + tooth_len + j, k))
+    for t in range(teeth):
+        for i in range(width):
+            for j in range(tooth_len):
+                for k in range(depth):
+                    ca.append((2 * t * pitch + i, base + j, k))
+                    cb.append(((2 * t + 1) * pitch + i, base + 1 + j, k))
+    XA, tA = lattice_from_cubes(np.array(ca), edge, (0.0, 0.0, 0.0))
+    XB, tB = lattice_from_cubes(np.array(cb), edge, (0.0, 0.0, 0.0))
+    X = np.concatenate([XA, XB])
+    tets = np.concatenate([tA, tB + XA.shape[0]]).astype(np.int32)
+    x = _perturb(rng, X, tets, 0.01 * edge)
+    # facing tooth faces: A tooth t's right face and B tooth t's left face
+    lut = {tuple(np.round(p / edge).astype(np.int64)): i for i, p in enumerate(XB)}
+    pairs = []
+    for t in range(teeth):
+        xa = 2 * t * pitch + width
+        for ia in np.nonzero(np.round(XA[:, 0] / edge).astype(np.int64) == xa)[0]:
+            q = np.round(XA[ia] / edge).astype(np.int64)
+            if q[1] < base + 1:
+                continue
+            jb = lut.get((xa + 1, int(q[1]), int(q[2])))
+            if jb is not None:
+                pairs.append((ia, jb + XA.shape[0]))
+    pairs = np.array(pairs, np.int64)
+    m = pairs.shape[0]
+    idx = -np.ones((m, 4), np.int32)
+    idx[:, :2] = pairs
+    grad = np.zeros((m, 12))
+    grad[:, 0] = -1.0
+    grad[:, 3] = 1.0
+    d = _loguniform(rng, 1e-6, dhat, m)
+    key = _make_key(KEY_PT, pairs)
+    pool = stencil_pool(key, idx, grad, x, d)
+    T = tets.shape[0]
+    return Scene("combs", X, x, np.zeros_like(X), tets, np.full(T, rho), np.full(T, E), np.full(T, nu), h, dhat,
+                 kappa=kappa_scale * rho * edge ** 3, gravity=np.array([0.0, 0.0, -9.81]), pool=pool,
+                 levels=levels, K=K)
+
+
 def churn_set(rng, scene, base, frac=0.3):
     """Scripted contact churn of a fraction ``frac`` of a contact set:
     40% replaced by fresh stencils (new keys), 30% stiffen (distance x
