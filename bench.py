@@ -430,14 +430,14 @@ ABLATION_VARIANTS = (("woodbury", "subspace", "mas"), ("freeze", "subspace", "ma
                      ("woodbury", "dk", "mas"), ("woodbury", "subspace", "bj3"))
 
 
-def _variant_solve(sc, update, rule, precond, tol, max_iter, prec="f32"):
+def _variant_solve(sc, update, rule, precond, tol, max_iter, prec="f32", hierarchy="morton"):
     import torch
     from paper_2604_19892_amd.pncg import PNCG
-    s = PNCG(sc, block_prec=prec, hess_prec="f32", update=update, rule=rule, precond=precond)
+    s = PNCG(sc, block_prec=prec, hess_prec="f32", update=update, rule=rule, precond=precond, hierarchy=hierarchy)
     it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
     code, msg = s.ctx.sync()
-    rec = {"update": update, "rule": rule, "preconditioner": precond, "iters": it, "seconds": sec,
-           "ms_per_iter": 1e3 * sec / max(it, 1), "rel_gnorm": rel, "converged": bool(rel <= tol),
+    rec = {"update": update, "rule": rule, "preconditioner": precond, "hierarchy": hierarchy, "iters": it,
+           "seconds": sec, "ms_per_iter": 1e3 * sec / max(it, 1), "rel_gnorm": rel, "converged": bool(rel <= tol),
            "restarts": s.n_restarts, "status": code}
     s.ctx.close()
     del s
@@ -459,6 +459,41 @@ def ablation_solves(sc, tol, max_iter):
         runs.append(rec)
     return {"workload": sc.name, "tol": tol, "max_iter": max_iter, "block_storage": "f32",
             "hessian_storage": "f32", "runs": runs}
+
+
+def hierarchy_solves(sc, tol, max_iter, repeats=2):
+    """MAS on the Morton order against the connectivity-aware hierarchy
+    (supplement Section 1.2, with the stencils active at the start as
+    reconnection links) on the same scene: solves from the start to tol
+    ||grad E_0||, and how many level-0 subdomains hold vertices of more than
+    one body in each order."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    from paper_2604_19892_amd import synth
+    from paper_2604_19892_amd.binding import vertex_order
+    t = np.asarray(sc.tets, np.int64)
+    A = sp.coo_matrix((np.ones(t.size * 4), (np.repeat(t, 4, axis=1).ravel(), np.tile(t, (1, 4)).ravel())),
+                      shape=(sc.N, sc.N)).tocsr()
+    _, lab = connected_components(A, directed=False)
+    runs = {}
+    for h in ("morton", "connectivity"):
+        t0 = time.perf_counter()
+        links = synth.contact_links(sc.pool, sc.x, sc.dhat) if h == "connectivity" else None
+        perm = vertex_order(sc.X, sc.tets, sc.levels, h, links)
+        order_s = time.perf_counter() - t0
+        n32 = (sc.N // 32) * 32
+        b = lab[perm[:n32]].reshape(-1, 32)
+        recs = []
+        for _ in range(repeats):
+            rec = _variant_solve(sc, "woodbury", "subspace", "mas", tol, max_iter, hierarchy=h)
+            print("[bench] hierarchy %s: %d iters %.2fs rel %.2e" % (h, rec["iters"], rec["seconds"],
+                                                                    rec["rel_gnorm"]), file=sys.stderr, flush=True)
+            recs.append(rec)
+        runs[h] = {"solves": recs, "order_seconds_host": order_s,
+                   "level0_subdomains_mixing_bodies": int((b.min(1) != b.max(1)).sum()),
+                   "level0_subdomains": int(-(-sc.N // 32))}
+    return {"workload": sc.name, "tol": tol, "max_iter": max_iter, "block_storage": "f32", "runs": runs}
 
 
 def stiffness_sweep(tol, max_iter, moduli=(2.15e4, 1e5, 1e6, 1e7)):
@@ -748,6 +783,7 @@ def main():
         print("[bench] ablations", file=sys.stderr, flush=True)
         out["ablations"] = ablation_solves(sc, args.solve_tol, args.solve_max_iter)
         out["stiffness_sweep"] = stiffness_sweep(args.solve_tol, args.solve_max_iter)
+        out["hierarchy"] = hierarchy_solves(sc, args.solve_tol, args.solve_max_iter)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc.N)

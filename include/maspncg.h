@@ -110,7 +110,25 @@ typedef struct {
   int64_t max_tris;     /* largest triangle list of mas_constraint_set (2 N + 64) */
   int64_t max_edges;    /* largest edge list of mas_constraint_set (3 N + 64) */
   int32_t precond;      /* MAS_PRECOND_MAS (the method) or MAS_PRECOND_BJ3 */
+  int32_t hierarchy;    /* MAS_HIER_MORTON or MAS_HIER_CONNECTIVITY */
 } mas_config;
+
+/* Vertex order that defines the hierarchy (a level-l node is a run of 32^l
+ * consecutive vertices, a subdomain a run of 32 nodes).  MAS_HIER_MORTON:
+ * Morton order of the rest positions.  MAS_HIER_CONNECTIVITY: the
+ * connectivity-aware hierarchy of supplement Section 1.2 (greedy
+ * aggregation over the graph of vertices that share a tet): vertices
+ * numbered component by component (Morton order inside); each cluster of
+ * 32 nodes grows from the smallest unassigned node by the smallest
+ * unassigned node adjacent to its members (else the smallest unassigned
+ * node); the clusters of level l are the nodes of level l + 1, aggregated
+ * the same way; a partial node closes the last cluster.  The mesh's
+ * contact links are edges of the graph too (the reconnection of supplement
+ * Section 1.2, taken once: the order is computed by mas_create on the host
+ * and fixes the data layout, so contacts that form later do not regroup
+ * it). */
+#define MAS_HIER_MORTON 0
+#define MAS_HIER_CONNECTIVITY 1
 
 /* Preconditioner of a context.  MAS_PRECOND_BJ3 is the comparison
  * preconditioner of the ablation study (Section 5, preconditioner
@@ -134,6 +152,13 @@ typedef struct {
   const double* density;  /* T */
   const double* youngs;   /* T */
   const double* poisson;  /* T */
+  /* Contact links for the connectivity-aware hierarchy (supplement Section
+   * 1.2, reconnection: primitives in close proximity join the adjacency
+   * graph): num_links pairs of original vertex ids (2 * num_links int32,
+   * host), read by mas_create and mas_vertex_order only when the hierarchy
+   * is MAS_HIER_CONNECTIVITY; may be 0 / NULL. */
+  int64_t num_links;
+  const int32_t* links;
 } mas_mesh;
 
 /* Contact stencils, device pointers, library vertex numbering. */
@@ -430,6 +455,14 @@ mas_status mas_read_stats(void* ctx, mas_iter_stats* out);
 
 /* Sizes: N, T, number of levels, D_l for l < 6. */
 mas_status mas_query(void* ctx, int64_t* N, int64_t* T, int32_t* levels, int64_t* nsub /*6*/);
+
+/* The vertex order mas_create would use for this mesh (host only, no
+ * device call, no context): perm_out (host, N) receives perm[new] = old
+ * vertex id for the hierarchy kind (MAS_HIER_MORTON or
+ * MAS_HIER_CONNECTIVITY, supplement Section 1.2) and num_levels (1..6).
+ * Only num_vertices, num_tets, rest_x, tets and the links of the mesh are
+ * read. */
+mas_status mas_vertex_order(const mas_mesh* mesh, int32_t num_levels, int32_t hierarchy, int32_t* perm_out);
 
 /* Number of blocks of level l stored in each precision by the last
  * mas_build (counts[4] indexed by mas_prec, host). */

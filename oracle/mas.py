@@ -26,9 +26,12 @@ The connectivity-aware grouping (supplement Section 1.2: an adjacency
 graph of nodes that share an element, grouped by greedy aggregation) is
 the alternative order ``connectivity_perm``; the paper gives no procedure,
 and the reading taken here is:
-* level-0 graph: vertices adjacent when they share a tet; its nodes are
-  numbered component by component (components in the order of their
-  smallest Morton rank), by Morton rank inside a component;
+* level-0 graph: vertices adjacent when they share a tet or are joined by
+  a contact link (the paper's reconnection: primitives in close proximity
+  join the graph; taken once, from the contacts when the hierarchy is
+  built); its nodes are numbered component by component (components in
+  the order of their smallest Morton rank), by Morton rank inside a
+  component;
 * a cluster starts at the smallest unassigned node and repeatedly takes the
   smallest unassigned node adjacent to any of its members, or, when there
   is none, the smallest unassigned node, until it holds 32 nodes;
@@ -43,9 +46,8 @@ and the reading taken here is:
   inside each cluster, its members in the order they were added, down to
   the vertices; runs of 32^l consecutive vertices are then the level-l
   nodes, as for the Morton order.
-The paper's dynamic reconnection (contact edges added to the graph as
-contacts form) would change the order, and with it the data layout,
-between rebuilds; it is not part of this reading.
+Reconnecting again as contacts form later would change the order, and
+with it the data layout, between rebuilds; it is not part of this reading.
 
 Every block is cut out of the assembled matrix with explicit S_d / C_(l)
 and inverted with numpy.linalg.inv; nothing is blocked or fused.
@@ -79,15 +81,20 @@ def morton_perm(X):
     return np.argsort(morton_codes(X), kind='stable').astype(np.int64)
 
 
-def vertex_adjacency(tets, n):
+def vertex_adjacency(tets, n, links=None):
     """Adjacency sets of the graph whose nodes 0..n-1 are adjacent when they
-    share a tet (tets given in those node ids)."""
+    share a tet or form a link (both given in those node ids)."""
     adj = [set() for _ in range(n)]
     for t in np.asarray(tets, np.int64).reshape(-1, 4):
         for a in range(4):
             for b in range(4):
                 if t[a] != t[b]:
                     adj[int(t[a])].add(int(t[b]))
+    if links is not None:
+        for a, b in np.asarray(links, np.int64).reshape(-1, 2):
+            if a != b:
+                adj[int(a)].add(int(b))
+                adj[int(b)].add(int(a))
     return adj
 
 
@@ -143,16 +150,20 @@ def cluster_adjacency(adj, clusters):
     return cadj
 
 
-def component_major_perm(X, tets):
+def component_major_perm(X, tets, links=None):
     """perm[id] = vertex of level-0 node id: vertices grouped by connected
-    component of the tet graph (components in the order of their smallest
-    Morton rank), by Morton rank inside a component."""
+    component of the graph of tets and links (components in the order of
+    their smallest Morton rank), by Morton rank inside a component."""
     from scipy.sparse.csgraph import connected_components
     N = X.shape[0]
     mperm = morton_perm(X)
     t = np.asarray(tets, np.int64)
     rows = np.repeat(t, 4, axis=1).ravel()
     cols = np.tile(t, (1, 4)).ravel()
+    if links is not None:
+        lk = np.asarray(links, np.int64).reshape(-1, 2)
+        rows = np.concatenate([rows, lk[:, 0]])
+        cols = np.concatenate([cols, lk[:, 1]])
     A = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(N, N)).tocsr()
     _, lab = connected_components(A, directed=False)
     comp = lab[mperm]                      # component of each Morton rank
@@ -162,14 +173,15 @@ def component_major_perm(X, tets):
     return mperm[order]
 
 
-def connectivity_clusters(X, tets, levels, sub=SUB):
+def connectivity_clusters(X, tets, levels, sub=SUB, links=None):
     """The clusters of every level (level l: clusters of level-l nodes) and
     the vertex of each level-0 node."""
     N = X.shape[0]
-    mperm = component_major_perm(X, tets)
+    mperm = component_major_perm(X, tets, links)
     mrank = np.empty(N, np.int64)
     mrank[mperm] = np.arange(N)
-    adj = vertex_adjacency(mrank[np.asarray(tets, np.int64)], N)
+    adj = vertex_adjacency(mrank[np.asarray(tets, np.int64)], N,
+                           None if links is None else mrank[np.asarray(links, np.int64)])
     size = np.ones(N, np.int64)
     out = []
     for l in range(levels):
@@ -182,9 +194,9 @@ def connectivity_clusters(X, tets, levels, sub=SUB):
     return mperm, out
 
 
-def connectivity_perm(X, tets, levels, sub=SUB):
+def connectivity_perm(X, tets, levels, sub=SUB, links=None):
     """perm[new] = old vertex id of the connectivity-aware order."""
-    mperm, cls = connectivity_clusters(X, tets, levels, sub)
+    mperm, cls = connectivity_clusters(X, tets, levels, sub, links)
 
     def expand(l, c):
         if l < 0:
@@ -205,11 +217,11 @@ class Hierarchy:
     the Morton order or (``tets`` given, ``order="connectivity"``) the
     connectivity-aware one."""
 
-    def __init__(self, X, levels, tets=None, order="morton"):
+    def __init__(self, X, levels, tets=None, order="morton", links=None):
         self.N = X.shape[0]
         self.L = levels
         if order == "connectivity":
-            self.perm = connectivity_perm(X, tets, levels)
+            self.perm = connectivity_perm(X, tets, levels, links=links)
         elif order == "morton":
             self.perm = morton_perm(X)
         else:

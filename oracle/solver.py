@@ -41,11 +41,13 @@ class OraclePNCG:
     ``rule`` picks the direction: "subspace" (the method's 2x2 step) or a
     comparison rule "fr", "cd", "dk" (``pncg.beta_step``).  ``precond``
     "bj3" replaces MAS by the 3x3 block-Jacobi inverse of H~ (the
-    comparison preconditioner, ``oracle.jacobi``)."""
+    comparison preconditioner, ``oracle.jacobi``); ``hierarchy``
+    "connectivity" groups the MAS levels by the connectivity-aware order
+    (``mas.connectivity_perm``) instead of the Morton order."""
 
     def __init__(self, scene, levels=None, K=None, delta=0.3,
                  cos_rot=np.cos(np.deg2rad(25.0)), max_halvings=8, update="woodbury", rule="subspace",
-                 precond="mas"):
+                 precond="mas", hierarchy="morton"):
         if update not in ("woodbury", "freeze", "rebuild") or (rule != "subspace" and rule not in RULES) \
                 or precond not in ("mas", "bj3"):
             raise ValueError("unknown update strategy, direction rule or preconditioner")
@@ -54,7 +56,15 @@ class OraclePNCG:
         self.precond = precond
         self.scene = scene
         self.prob = fem.Problem(scene)
-        self.hier = mas.Hierarchy(scene.X, levels or scene.levels)
+        links = None
+        if hierarchy == "connectivity":
+            # every vertex pair of the pool stencils active at the start
+            d = pool_distance(scene.pool, np.asarray(scene.x, np.float64).reshape(-1))
+            idx = scene.pool['idx'][(d > 0) & (d < scene.dhat)]
+            links = [(int(s[a]), int(s[b])) for s in idx for a in range(4) for b in range(a + 1, 4)
+                     if s[a] >= 0 and s[b] >= 0]
+            links = np.array(links, np.int64).reshape(-1, 2)
+        self.hier = mas.Hierarchy(scene.X, levels or scene.levels, tets=scene.tets, order=hierarchy, links=links)
         self.K = 0 if update == "freeze" else (K or scene.K)
         self.g_prev = None
         self.d = None

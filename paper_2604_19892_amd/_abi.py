@@ -14,6 +14,7 @@ MAS_F64, MAS_F32, MAS_BF16, MAS_F16 = 0, 1, 2, 3
 PREC = {"f64": MAS_F64, "f32": MAS_F32, "bf16": MAS_BF16, "f16": MAS_F16}
 BETA = {"fr": 1, "cd": 2, "dk": 3}
 PRECOND = {"mas": 0, "bj3": 1}
+HIERARCHY = {"morton": 0, "connectivity": 1}
 
 STATUS = {0: "MAS_OK", 1: "MAS_ERR_INVALID_ARG", 2: "MAS_ERR_STATE", 3: "MAS_ERR_OOM",
           4: "MAS_ERR_HIP", 5: "MAS_ERR_NOT_SPD", 6: "MAS_ERR_NONFINITE", 7: "MAS_ERR_RANK"}
@@ -40,6 +41,7 @@ class MasConfig(ctypes.Structure):
         ("max_tris", ctypes.c_int64),
         ("max_edges", ctypes.c_int64),
         ("precond", ctypes.c_int32),
+        ("hierarchy", ctypes.c_int32),
     ]
 
 
@@ -52,6 +54,8 @@ class MasMesh(ctypes.Structure):
         ("density", ctypes.c_void_p),
         ("youngs", ctypes.c_void_p),
         ("poisson", ctypes.c_void_p),
+        ("num_links", ctypes.c_int64),
+        ("links", ctypes.c_void_p),
     ]
 
 
@@ -120,6 +124,7 @@ SIGNATURES = {
     "mas_sync_status": (_I32, [_P, ctypes.c_char_p, _I32]),
     "mas_read_stats": (_I32, [_P, ctypes.POINTER(MasIterStats)]),
     "mas_query": (_I32, [_P, _P, _P, _P, _P]),
+    "mas_vertex_order": (_I32, [ctypes.POINTER(MasMesh), _I32, _I32, _P]),
     "mas_get_block": (_I32, [_P, _I32, _I64, _P]),
     "mas_block_precisions": (_I32, [_P, _I32, _P]),
     "mas_get_selection": (_I32, [_P, _P, _P]),

@@ -21,7 +21,7 @@ def _ptr(t):
 
 def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=None,
                 hess_prec=None, delta=0.3, cos_rot=None, eps_sing=1e-12, prec_guard=None,
-                deterministic=False, max_contacts=0, max_tris=0, max_edges=0, precond="mas"):
+                deterministic=False, max_contacts=0, max_tris=0, max_edges=0, precond="mas", hierarchy="morton"):
     cfg = MasConfig()
     _abi.lib().mas_default_config(ctypes.byref(cfg))
     if scene is not None:
@@ -53,6 +53,7 @@ def make_config(scene=None, levels=None, K=None, block_prec="f64", coarse_prec=N
     cfg.max_tris = int(max_tris)
     cfg.max_edges = int(max_edges)
     cfg.precond = _abi.PRECOND[precond]
+    cfg.hierarchy = _abi.HIERARCHY[hierarchy]
     return cfg
 
 
@@ -90,18 +91,38 @@ class DeviceContacts:
         return c
 
 
+def vertex_order(X, tets, levels, hierarchy="morton", links=None):
+    """mas_vertex_order: perm[new] = old vertex id of the hierarchy's order
+    (host only); ``links`` (k, 2) vertex pairs joined by contacts."""
+    X = np.ascontiguousarray(X, np.float64)
+    tets = np.ascontiguousarray(tets, np.int32)
+    lk = np.ascontiguousarray(np.zeros((0, 2)) if links is None else links, np.int32)
+    mesh = MasMesh()
+    mesh.num_vertices = X.shape[0]
+    mesh.num_tets = tets.shape[0]
+    mesh.rest_x = X.ctypes.data
+    mesh.tets = tets.ctypes.data
+    mesh.num_links = lk.shape[0]
+    mesh.links = lk.ctypes.data if lk.shape[0] else None
+    perm = np.zeros(X.shape[0], np.int32)
+    check("mas_vertex_order", _abi.lib().mas_vertex_order(ctypes.byref(mesh), int(levels),
+                                                          _abi.HIERARCHY[hierarchy], perm.ctypes.data))
+    return perm
+
+
 class MasContext:
     """One library context for one mesh (``mas_create`` .. ``mas_destroy``)."""
 
-    def __init__(self, scene, cfg, device="cuda"):
+    def __init__(self, scene, cfg, device="cuda", links=None):
         L = _abi.lib()
         self.device = device
         self.scene = scene
         X = np.ascontiguousarray(scene.X, np.float64)
         tets = np.ascontiguousarray(scene.tets, np.int32)
+        lk = np.ascontiguousarray(np.zeros((0, 2)) if links is None else links, np.int32)
         self._host = [X, tets, np.ascontiguousarray(scene.density, np.float64),
                       np.ascontiguousarray(scene.youngs, np.float64),
-                      np.ascontiguousarray(scene.poisson, np.float64)]
+                      np.ascontiguousarray(scene.poisson, np.float64), lk]
         mesh = MasMesh()
         mesh.num_vertices = X.shape[0]
         mesh.num_tets = tets.shape[0]
@@ -110,6 +131,8 @@ class MasContext:
         mesh.density = self._host[2].ctypes.data
         mesh.youngs = self._host[3].ctypes.data
         mesh.poisson = self._host[4].ctypes.data
+        mesh.num_links = lk.shape[0]
+        mesh.links = lk.ctypes.data if lk.shape[0] else None
         self.N = X.shape[0]
         self.perm = np.zeros(self.N, np.int32)
         h = ctypes.c_void_p()

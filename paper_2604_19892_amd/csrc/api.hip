@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <mutex>
 #include <numeric>
+#include <queue>
 #include <new>
 #include <vector>
 
@@ -136,6 +137,186 @@ void morton_order(const double* X, int64_t N, std::vector<int32_t>& perm) {
   std::stable_sort(perm.begin(), perm.end(), [&](int32_t p, int32_t q) { return code[p] < code[q]; });
 }
 
+// Connectivity-aware order (supplement Section 1.2: greedy aggregation over
+// the graph of nodes that share an element).  Level-0 nodes are the
+// vertices, numbered component by component of the tet graph (components
+// in the order of their smallest Morton rank, Morton order inside); a
+// cluster grows from the smallest unassigned node by the smallest
+// unassigned node adjacent to its members (else the smallest unassigned
+// node) to SUB nodes; the clusters of level l are the nodes of level l+1,
+// adjacent when some of their members are.  A node with fewer than SUB^l
+// vertices (only the last can be) stays out of the growth and closes the
+// last cluster, so every level-l node but the last holds SUB^l vertices.
+// The vertex order expands the top-level clusters in order, members in the
+// order they were added.
+struct Graph {
+  std::vector<int64_t> off;  // n + 1
+  std::vector<int32_t> adj;  // sorted, unique neighbour lists
+};
+
+static void graph_from_pairs(int64_t n, std::vector<uint64_t>& pairs, Graph& g) {
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  g.off.assign(n + 1, 0);
+  g.adj.resize(pairs.size());
+  for (uint64_t e : pairs) ++g.off[(e >> 32) + 1];
+  for (int64_t i = 0; i < n; ++i) g.off[i + 1] += g.off[i];
+  for (size_t k = 0; k < pairs.size(); ++k) g.adj[k] = int32_t(pairs[k] & 0xffffffffu);
+}
+
+// clusters of nodes 0..n-1: members in the order added; cl_off has one
+// entry per cluster plus one
+static void aggregate_graph(const Graph& g, int64_t n, bool partial_last, std::vector<int64_t>& cl_off,
+                            std::vector<int32_t>& members) {
+  const int64_t limit = partial_last ? n - 1 : n;
+  std::vector<uint8_t> assigned(n, 0);
+  cl_off.assign(1, 0);
+  members.clear();
+  members.reserve(n);
+  int64_t nxt = 0;
+  std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> cand;
+  for (int64_t seed = 0; seed < limit; ++seed) {
+    if (assigned[seed]) continue;
+    while (!cand.empty()) cand.pop();
+    int64_t u = seed;
+    int count = 0;
+    while (true) {
+      members.push_back(int32_t(u));
+      assigned[u] = 1;
+      ++count;
+      for (int64_t k = g.off[u]; k < g.off[u + 1]; ++k) {
+        const int32_t w = g.adj[k];
+        if (w < limit && !assigned[w]) cand.push(w);
+      }
+      if (count == SUB) break;
+      int64_t next = -1;
+      while (!cand.empty()) {
+        const int32_t w = cand.top();
+        cand.pop();
+        if (!assigned[w]) {
+          next = w;
+          break;
+        }
+      }
+      if (next < 0) {
+        while (nxt < limit && assigned[nxt]) ++nxt;
+        if (nxt >= limit) break;
+        next = nxt;
+      }
+      u = next;
+    }
+    cl_off.push_back(int64_t(members.size()));
+  }
+  if (partial_last) {
+    const int64_t nc = int64_t(cl_off.size()) - 1;
+    if (nc > 0 && cl_off[nc] - cl_off[nc - 1] < SUB) {
+      members.push_back(int32_t(n - 1));
+      cl_off[nc] += 1;
+    } else {
+      members.push_back(int32_t(n - 1));
+      cl_off.push_back(int64_t(members.size()));
+    }
+  }
+}
+
+void connectivity_order(const double* X, int64_t N, const int32_t* tets, int64_t T, const int32_t* links,
+                        int64_t nlinks, int L, std::vector<int32_t>& perm) {
+  std::vector<int32_t> mperm;
+  morton_order(X, N, mperm);
+  std::vector<int64_t> mrank(N);
+  for (int64_t i = 0; i < N; ++i) mrank[mperm[i]] = i;
+  // components of the tet graph (union-find)
+  std::vector<int64_t> par(N);
+  std::iota(par.begin(), par.end(), 0);
+  auto find = [&](int64_t a) {
+    while (par[a] != a) {
+      par[a] = par[par[a]];
+      a = par[a];
+    }
+    return a;
+  };
+  auto unite = [&](int64_t a, int64_t b) {
+    a = find(a);
+    b = find(b);
+    if (a != b) par[std::max(a, b)] = std::min(a, b);
+  };
+  for (int64_t t = 0; t < T; ++t)
+    for (int j = 1; j < 4; ++j) unite(tets[4 * t], tets[4 * t + j]);
+  for (int64_t k = 0; k < nlinks; ++k) unite(links[2 * k], links[2 * k + 1]);
+  std::vector<int64_t> first(N, N);  // smallest Morton rank of each component (at its root)
+  for (int64_t v = 0; v < N; ++v) {
+    const int64_t r = find(v);
+    first[r] = std::min(first[r], mrank[v]);
+  }
+  // level-0 node ids: (component's smallest rank, rank)
+  std::vector<int32_t> node_vertex(mperm);
+  std::stable_sort(node_vertex.begin(), node_vertex.end(),
+                   [&](int32_t a, int32_t b) { return first[find(a)] < first[find(b)]; });
+  std::vector<int32_t> vertex_node(N);
+  for (int64_t i = 0; i < N; ++i) vertex_node[node_vertex[i]] = int32_t(i);
+  Graph g;
+  {
+    std::vector<uint64_t> pairs;
+    pairs.reserve(size_t(12) * T);
+    for (int64_t t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          const uint64_t u = uint64_t(vertex_node[tets[4 * t + a]]), w = uint64_t(vertex_node[tets[4 * t + b]]);
+          if (u != w) pairs.push_back((u << 32) | w);
+        }
+    for (int64_t k = 0; k < nlinks; ++k) {
+      const uint64_t u = uint64_t(vertex_node[links[2 * k]]), w = uint64_t(vertex_node[links[2 * k + 1]]);
+      if (u != w) {
+        pairs.push_back((u << 32) | w);
+        pairs.push_back((w << 32) | u);
+      }
+    }
+    graph_from_pairs(N, pairs, g);
+  }
+  std::vector<std::vector<int64_t>> offs(L);
+  std::vector<std::vector<int32_t>> mems(L);
+  std::vector<int64_t> size(N, 1);
+  int64_t n = N, full = 1;
+  for (int l = 0; l < L; ++l) {
+    const bool partial = n > 0 && size[n - 1] < full;
+    aggregate_graph(g, n, partial, offs[l], mems[l]);
+    const int64_t nc = int64_t(offs[l].size()) - 1;
+    std::vector<int64_t> csize(nc, 0);
+    std::vector<int32_t> cid(n);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int64_t k = offs[l][c]; k < offs[l][c + 1]; ++k) {
+        cid[mems[l][k]] = int32_t(c);
+        csize[c] += size[mems[l][k]];
+      }
+    if (l + 1 < L) {
+      std::vector<uint64_t> pairs;
+      for (int64_t u = 0; u < n; ++u)
+        for (int64_t k = g.off[u]; k < g.off[u + 1]; ++k) {
+          const int32_t a = cid[u], b = cid[g.adj[k]];
+          if (a != b) pairs.push_back((uint64_t(a) << 32) | uint64_t(b));
+        }
+      Graph h;
+      graph_from_pairs(nc, pairs, h);
+      g = std::move(h);
+    }
+    size = std::move(csize);
+    n = nc;
+    full *= SUB;
+  }
+  // expand the top-level clusters down to level-0 nodes
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  for (int l = L - 1; l >= 0; --l) {
+    std::vector<int32_t> next;
+    next.reserve(mems[l].size());
+    for (int32_t c : order)
+      for (int64_t k = offs[l][c]; k < offs[l][c + 1]; ++k) next.push_back(mems[l][k]);
+    order = std::move(next);
+  }
+  perm.resize(N);
+  for (int64_t i = 0; i < N; ++i) perm[i] = node_vertex[order[i]];
+}
+
 mas_status valid_contacts(const mas_contacts* c) {
   if (!c) return MAS_OK;
   if (c->m < 0) return MAS_ERR_INVALID_ARG;
@@ -237,11 +418,15 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (cfg->deterministic != 0 && cfg->deterministic != 1) return MAS_ERR_INVALID_ARG;
   if (cfg->precond != MAS_PRECOND_MAS && cfg->precond != MAS_PRECOND_BJ3) return MAS_ERR_INVALID_ARG;
   if (cfg->precond == MAS_PRECOND_BJ3 && cfg->deterministic) return MAS_ERR_INVALID_ARG;
+  if (cfg->hierarchy != MAS_HIER_MORTON && cfg->hierarchy != MAS_HIER_CONNECTIVITY) return MAS_ERR_INVALID_ARG;
   if (cfg->max_contacts < 0 || cfg->max_tris < 0 || cfg->max_edges < 0) return MAS_ERR_INVALID_ARG;
   if (cfg->max_contacts > INT32_MAX / 4 || cfg->max_tris > INT32_MAX / 8 || cfg->max_edges > INT32_MAX / 8)
     return MAS_ERR_INVALID_ARG;
   for (int64_t t = 0; t < 4 * T; ++t)
     if (mesh->tets[t] < 0 || mesh->tets[t] >= N) return MAS_ERR_INVALID_ARG;
+  if (mesh->num_links < 0 || (mesh->num_links > 0 && !mesh->links)) return MAS_ERR_INVALID_ARG;
+  for (int64_t k = 0; k < 2 * mesh->num_links; ++k)
+    if (mesh->links[k] < 0 || mesh->links[k] >= N) return MAS_ERR_INVALID_ARG;
 
   Ctx* c = new (std::nothrow) Ctx();
   if (!c) return MAS_ERR_OOM;
@@ -279,7 +464,10 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
 
   // Morton order and renumbered, locality-sorted tets
   std::vector<int32_t> perm;
-  morton_order(mesh->rest_x, N, perm);
+  if (cfg->hierarchy == MAS_HIER_CONNECTIVITY)
+    connectivity_order(mesh->rest_x, N, mesh->tets, T, mesh->links, mesh->num_links, cfg->num_levels, perm);
+  else
+    morton_order(mesh->rest_x, N, perm);
   std::vector<int32_t> rank(N);
   for (int64_t i = 0; i < N; ++i) rank[perm[i]] = int32_t(i);
   std::vector<int32_t> torder(T);
@@ -801,6 +989,26 @@ mas_status mas_read_stats(void* p, mas_iter_stats* out) {
         }
     out->alpha_hist[bin]++;
   }
+  return MAS_OK;
+}
+
+mas_status mas_vertex_order(const mas_mesh* mesh, int32_t num_levels, int32_t hierarchy, int32_t* perm_out) {
+  if (!mesh || !perm_out || !mesh->rest_x) return MAS_ERR_INVALID_ARG;
+  const int64_t N = mesh->num_vertices, T = mesh->num_tets;
+  if (N <= 0 || T < 0 || N > (int64_t(1) << 30) || (T > 0 && !mesh->tets)) return MAS_ERR_INVALID_ARG;
+  if (num_levels < 1 || num_levels > MAXL) return MAS_ERR_INVALID_ARG;
+  if (hierarchy != MAS_HIER_MORTON && hierarchy != MAS_HIER_CONNECTIVITY) return MAS_ERR_INVALID_ARG;
+  for (int64_t t = 0; t < 4 * T; ++t)
+    if (mesh->tets[t] < 0 || mesh->tets[t] >= N) return MAS_ERR_INVALID_ARG;
+  std::vector<int32_t> perm;
+  if (mesh->num_links < 0 || (mesh->num_links > 0 && !mesh->links)) return MAS_ERR_INVALID_ARG;
+  for (int64_t k = 0; k < 2 * mesh->num_links; ++k)
+    if (mesh->links[k] < 0 || mesh->links[k] >= N) return MAS_ERR_INVALID_ARG;
+  if (hierarchy == MAS_HIER_CONNECTIVITY)
+    connectivity_order(mesh->rest_x, N, mesh->tets, T, mesh->links, mesh->num_links, num_levels, perm);
+  else
+    morton_order(mesh->rest_x, N, perm);
+  std::copy(perm.begin(), perm.end(), perm_out);
   return MAS_OK;
 }
 

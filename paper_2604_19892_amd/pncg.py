@@ -34,11 +34,12 @@ class PNCG:
     at every iteration; H_base p is then recomputed by one more hess_vec);
     "subspace" (the method's 2x2 step) or a comparison rule "fr", "cd",
     "dk" (pncg_beta_step); ``precond`` "bj3" swaps MAS for the 3x3
-    block-Jacobi comparison preconditioner."""
+    block-Jacobi comparison preconditioner; ``hierarchy`` "connectivity"
+    builds the MAS levels on the connectivity-aware order."""
 
     def __init__(self, scene, block_prec="f32", levels=None, K=None, delta=0.3, hess_prec=None,
                  max_halvings=8, device="cuda", deterministic=False, prec_guard=None, collect_stats=False,
-                 update="woodbury", rule="subspace", precond="mas"):
+                 update="woodbury", rule="subspace", precond="mas", hierarchy="morton"):
         if update not in UPDATES or rule not in RULES:
             raise ValueError("unknown update strategy or direction rule")
         self.update = update
@@ -46,10 +47,15 @@ class PNCG:
         if update == "freeze":
             K = 0
         cfg = make_config(scene, levels=levels, K=K, block_prec=block_prec, hess_prec=hess_prec,
-                          delta=delta, deterministic=deterministic, prec_guard=prec_guard, precond=precond)
+                          delta=delta, deterministic=deterministic, prec_guard=prec_guard, precond=precond,
+                          hierarchy=hierarchy)
         self.precond = precond
+        self.hierarchy = hierarchy
         self.collect_stats = collect_stats
-        self.ctx = ctx = MasContext(scene, cfg, device=device)
+        # the connectivity-aware hierarchy links the vertices of the
+        # stencils active at the start (its reconnection edges)
+        links = synth.contact_links(scene.pool, scene.x, scene.dhat) if hierarchy == "connectivity" else None
+        self.ctx = ctx = MasContext(scene, cfg, device=device, links=links)
         self.scene = scene
         self.max_halvings = max_halvings
         self.pool = ctx.contacts(scene.pool, sort=True)

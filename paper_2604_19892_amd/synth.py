@@ -413,14 +413,16 @@ def stacked_boxes_scene(seed=4, nxy=10, nz=5, dhat=1e-3, h=0.01, E=1e5, nu=0.4, 
 
 
 def combs_scene(seed=3, teeth=8, width=2, tooth_len=12, base=2, depth=4, dhat=1e-3, h=0.01, E=1e5, nu=0.4,
-                rho=1000.0, levels=2, K=8, kappa_scale=1e3):
+                rho=1000.0, levels=2, K=8, kappa_scale=1.0):
     """Two combs whose teeth interleave one lattice edge apart (edge 1/32):
     parts that are close in space but not connected, the case where a
     Morton grouping puts vertices of both combs into one subdomain.  Teeth
     ``width`` cubes wide, ``tooth_len`` long and ``depth`` deep hang from
     slabs ``base`` cubes thick.  Affine point-point stencils join facing
     vertices of neighbouring teeth (d = x_B - x_A along the x axis minus an
-    offset), with distances log-uniform in (1e-6, dhat)."""
+    offset), with distances log-uniform in (1e-6, dhat).  Barrier stiffness
+    kappa_scale * rho * edge^3 (the blocks' condition numbers stay near 1e6
+    at the default, as on the grid and two-box scenes)."""
     rng = np.random.default_rng(seed)
     edge = 1.0 / 32
     pitch = width + 1
@@ -658,6 +660,19 @@ def with_youngs(scene, E):
     """A copy of the scene with one Young's modulus E for every tet."""
     import dataclasses
     return dataclasses.replace(scene, name="%s_E%.3g" % (scene.name, E), youngs=np.full(scene.T, float(E)))
+
+
+def contact_links(pool, x, dhat):
+    """Vertex pairs joined by the pool's stencils that are active at x
+    (0 < d < dhat): every pair of distinct vertices of such a stencil."""
+    d = pool_distance(pool, x)
+    idx = pool['idx'][(d > 0) & (d < dhat)]
+    out = []
+    for a in range(4):
+        for b in range(a + 1, 4):
+            sel = (idx[:, a] >= 0) & (idx[:, b] >= 0)
+            out.append(idx[sel][:, [a, b]])
+    return np.concatenate(out).astype(np.int32) if out else np.zeros((0, 2), np.int32)
 
 
 def surface(tets):

@@ -30,7 +30,7 @@ def test_header_declares_the_hot_path_calls():
     names = declared_functions()
     for n in ("mas_build", "mas_woodbury_update", "mas_apply", "hess_vec", "pncg_subspace_step"):
         assert n in names
-    assert len(names) == 28
+    assert len(names) == 29
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -43,9 +43,9 @@ def test_every_declared_symbol_is_exported(L):
 def test_struct_layouts_match_header(L):
     from paper_2604_19892_amd import _abi
     # field order / sizes as in the header (8-byte aligned members)
-    assert ctypes.sizeof(_abi.MasConfig) == 4 + 4 + 7 * 8 + 3 * 8 + 4 * 4 + 8 + 3 * 8 + 4 + 4  # precond, tail padding
+    assert ctypes.sizeof(_abi.MasConfig) == 4 + 4 + 7 * 8 + 3 * 8 + 4 * 4 + 8 + 3 * 8 + 4 + 4  # precond, hierarchy
     assert ctypes.sizeof(_abi.MasIterStats) == 7 * 8 + 2 * 4 + 8 + 8 * 8
-    assert ctypes.sizeof(_abi.MasMesh) == 2 * 8 + 5 * 8
+    assert ctypes.sizeof(_abi.MasMesh) == 2 * 8 + 5 * 8 + 2 * 8
     assert ctypes.sizeof(_abi.MasContacts) == 5 * 8
     assert ctypes.sizeof(_abi.MasStepOut) == 11 * 8 + 4 * 4
 
@@ -86,3 +86,31 @@ def test_argument_errors_return_without_gpu(L):
     assert L.mas_constraint_set(None, None, 1e-3, 0, None, 0, None, 0, None, 0, None, None, None, None, None,
                                 None) == 1
     assert L.mas_status_string(5) == b"non-positive pivot (matrix not SPD)"
+
+
+@pytest.mark.parametrize("scene,levels", [("grid", 2), ("combs", 2), ("combs", 3), ("two_boxes", 3)])
+def test_vertex_order_matches_oracle(L, scene, levels):
+    """mas_vertex_order (host logic) against the oracle's orders, bit for
+    bit: Morton and the connectivity-aware hierarchy."""
+    from oracle import mas
+    from paper_2604_19892_amd import synth
+    from paper_2604_19892_amd.binding import vertex_order
+    sc = {"grid": synth.grid_scene, "combs": synth.combs_scene, "two_boxes": synth.two_boxes_scene}[scene]()
+    np.testing.assert_array_equal(vertex_order(sc.X, sc.tets, levels, "morton"), mas.morton_perm(sc.X))
+    np.testing.assert_array_equal(vertex_order(sc.X, sc.tets, levels, "connectivity"),
+                                  mas.connectivity_perm(sc.X, sc.tets, levels))
+    links = synth.contact_links(sc.pool, sc.x, sc.dhat)
+    np.testing.assert_array_equal(vertex_order(sc.X, sc.tets, levels, "connectivity", links),
+                                  mas.connectivity_perm(sc.X, sc.tets, levels, links=links))
+
+
+def test_vertex_order_rejects_bad_input(L):
+    from paper_2604_19892_amd import _abi
+    from paper_2604_19892_amd.binding import vertex_order
+    X = np.zeros((4, 3))
+    with pytest.raises(_abi.MasError):
+        vertex_order(X, np.array([[0, 1, 2, 4]]), 1, "connectivity")
+    with pytest.raises(_abi.MasError):
+        vertex_order(X, np.array([[0, 1, 2, 3]]), 7, "connectivity")
+    with pytest.raises(_abi.MasError):
+        vertex_order(X, np.array([[0, 1, 2, 3]]), 1, "connectivity", links=np.array([[0, 4]]))

@@ -62,6 +62,19 @@ def test_interleaved_chains_are_not_mixed():
     assert np.all(mort.min(1) != mort.max(1))           # Morton runs mix both
 
 
+def test_contact_links_join_the_graph():
+    # links between every pair of neighbouring positions make the two
+    # chains one path: the clusters are runs of consecutive positions
+    X, tets = _interleaved_chains(128)
+    links = np.array([[r, r + 1] for r in range(127)])
+    perm = mas.connectivity_perm(X, tets, 1, links=links)
+    np.testing.assert_array_equal(perm, np.arange(128))
+    # a single link merges the components: component-major numbering then
+    # keeps the chain of the smallest rank first only up to the link
+    perm1 = mas.connectivity_perm(X, tets, 1, links=np.array([[0, 1]]))
+    assert perm1[0] == 0 and perm1[1] == 1
+
+
 def _components(X, tets):
     t = np.asarray(tets, np.int64)
     rows = np.repeat(t, 4, axis=1).ravel()
