@@ -499,6 +499,12 @@ typedef enum {
 /* Enables (1) or disables (0) the kernel timers; enabling clears them. */
 mas_status mas_profile_enable(void* ctx, int32_t enable);
 
+/* Restricts the timers recorded while enabled to those whose bit (1 << t)
+ * is set in mask (default: all).  Each timed launch adds an event pair to
+ * the stream, so a timed region that must not be slowed down records only
+ * the timers it reports. */
+mas_status mas_profile_select(void* ctx, uint32_t mask);
+
 /* Synchronises the stream and returns the summed duration (ms) and number of
  * timed launches of one timer since the last read, then clears it. */
 mas_status mas_profile_read(void* ctx, int32_t timer, double* total_ms, int64_t* count);

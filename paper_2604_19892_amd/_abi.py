@@ -131,6 +131,7 @@ SIGNATURES = {
     "mas_status_string": (ctypes.c_char_p, [_I32]),
     "mas_profile_enable": (_I32, [_P, _I32]),
     "mas_profile_read": (_I32, [_P, _I32, _P, _P]),
+    "mas_profile_select": (_I32, [_P, ctypes.c_uint32]),
 }
 
 _lib = None

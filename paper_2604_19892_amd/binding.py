@@ -311,7 +311,10 @@ class MasContext:
         check("mas_get_block", _abi.lib().mas_get_block(self.h, int(level), int(d), out.ctypes.data))
         return out
 
-    def profile(self, enable=True):
+    def profile(self, enable=True, timers=None):
+        """Enables the kernel timers (all, or only the named ones)."""
+        mask = 0xffffffff if timers is None else sum(1 << _abi.TIMERS[t] for t in timers)
+        check("mas_profile_select", _abi.lib().mas_profile_select(self.h, mask))
         check("mas_profile_enable", _abi.lib().mas_profile_enable(self.h, int(enable)))
 
     def profile_read(self, timer):

@@ -14,6 +14,7 @@ namespace mas {
 
 struct Prof {
   bool on = false;
+  uint32_t mask = 0xffffffffu;  // timers recorded while on (bit t: timer t)
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> done[MAS_T_COUNT];
   hipEvent_t open[MAS_T_COUNT] = {};
@@ -31,7 +32,7 @@ static hipEvent_t prof_take(Prof& p) {
 }
 
 void prof_begin(Ctx& c, int t) {
-  if (!c.prof || !c.prof->on || t < 0 || t >= MAS_T_COUNT) return;
+  if (!c.prof || !c.prof->on || t < 0 || t >= MAS_T_COUNT || !((c.prof->mask >> t) & 1u)) return;
   hipEvent_t e = prof_take(*c.prof);
   if (!e) return;
   hipEventRecord(e, c.s);
@@ -1084,6 +1085,15 @@ mas_status mas_profile_enable(void* p, int32_t enable) {
     c.prof->open[t] = nullptr;
   }
   c.prof->on = enable != 0;
+  return MAS_OK;
+}
+
+mas_status mas_profile_select(void* p, uint32_t mask) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.prof) c.prof = new (std::nothrow) Prof();
+  if (!c.prof) return MAS_ERR_OOM;
+  c.prof->mask = mask;
   return MAS_OK;
 }
 

@@ -13,6 +13,7 @@ search.
 """
 from __future__ import annotations
 
+import contextlib
 import time
 
 import numpy as np
@@ -39,9 +40,25 @@ class PNCG:
 
     def __init__(self, scene, block_prec="f32", levels=None, K=None, delta=0.3, hess_prec=None,
                  max_halvings=8, device="cuda", deterministic=False, prec_guard=None, collect_stats=False,
-                 update="woodbury", rule="subspace", precond="mas", hierarchy="morton"):
+                 update="woodbury", rule="subspace", precond="mas", hierarchy="morton", graph=False):
         if update not in UPDATES or rule not in RULES:
             raise ValueError("unknown update strategy or direction rule")
+        # graph mode: the device part of each iteration (build or update up
+        # to the trial point's energy) is captured once per form and buffer
+        # assignment in a HIP graph and replayed; everything runs on a
+        # stream of the solver's own
+        self.graph = bool(graph)
+        self.stream = torch.cuda.Stream() if self.graph else None
+        self._graphs = {}
+        with self._on_stream():
+            self._init(scene, block_prec, levels, K, delta, hess_prec, max_halvings, device, deterministic,
+                       prec_guard, collect_stats, update, rule, precond, hierarchy)
+
+    def _on_stream(self):
+        return torch.cuda.stream(self.stream) if self.stream is not None else contextlib.nullcontext()
+
+    def _init(self, scene, block_prec, levels, K, delta, hess_prec, max_halvings, device, deterministic,
+              prec_guard, collect_stats, update, rule, precond, hierarchy):
         self.update = update
         self.rule = rule
         if update == "freeze":
@@ -90,15 +107,14 @@ class PNCG:
         self.track_precisions = False
         self.precision_counts = None
 
-    def iterate(self):
+    def _device_part(self, restart, z_prev):
+        """The launches of one iteration up to the trial point's energy: no
+        host read, no allocation (capturable).  Returns the step vector."""
         ctx = self.ctx
         # p and vp hold the previous step (subspace) or direction (rules) and
         # its H_base product
-        if self.restart:
+        if restart:
             ctx.build(self.x, self.pool)
-            self.n_restarts += 1
-            if self.track_precisions:
-                self.precision_counts = ctx.block_precisions(0)
         elif self.update == "rebuild":
             ctx.build(self.x, self.pool)
             ctx.hess_vec(self.p, with_update=False, y=self.vp)
@@ -106,22 +122,52 @@ class PNCG:
             ctx.woodbury_update(self.pool, self.rank_hist)
         ctx.apply(self.g, self.z)
         ctx.hess_vec(self.z, with_update=False, y=self.vz)
-        z_prev = self.z_prev if self.fk > 0 else None
         if self.rule == "subspace":
-            ctx.subspace_step(self.g, self.z, z_prev, self.vz, self.p, self.vp, self.restart)
+            ctx.subspace_step(self.g, self.z, z_prev, self.vz, self.p, self.vp, restart)
             step = self.p
         else:
             # g_trial holds the previous iterate's gradient after an accepted
             # step; a rejected one makes this iteration a restart
             ctx.beta_step(self.rule, self.g, self.g_trial, self.z, z_prev, self.vz, self.p, self.vp,
-                          self.restart, self.step)
+                          restart, self.step)
             step = self.step
         ctx.safe_step(self.x, step, self.pool, 1.0, self.x_trial)
+        ctx.stencil_distance(self.x_trial, self.pool_t)
+        ctx.energy_grad(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
+        return step
+
+    def iterate(self):
+        with self._on_stream():
+            return self._iterate()
+
+    def _iterate(self):
+        ctx = self.ctx
+        z_prev = self.z_prev if self.fk > 0 else None
+        if self.graph:
+            # one graph per form (restart or not, with or without z_prev) and
+            # buffer assignment (the swaps below alternate it)
+            key = (self.restart, z_prev is None, self.x.data_ptr(), self.z.data_ptr(), self.g.data_ptr(),
+                   self.pool.d.data_ptr())
+            gr = self._graphs.get(key)
+            if gr is None:
+                gr = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gr, stream=self.stream):
+                    self._device_part(self.restart, z_prev)
+                self._graphs[key] = gr
+            gr.replay()
+            step = self.p if self.rule == "subspace" else self.step
+        else:
+            step = self._device_part(self.restart, z_prev)
+        if self.restart:
+            self.n_restarts += 1
+            if self.track_precisions:
+                self.precision_counts = ctx.block_precisions(0)
         scale = 1.0
         accepted = False
         for h in range(self.max_halvings + 1):
-            ctx.stencil_distance(self.x_trial, self.pool_t)
-            ctx.energy_grad(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
+            if h > 0:
+                ctx.stencil_distance(self.x_trial, self.pool_t)
+                ctx.energy_grad(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
             Et = float(self.E_trial.item())
             if Et <= self.E_host:
                 accepted = True
@@ -162,6 +208,10 @@ class PNCG:
     def reset(self):
         """Back to the scene's start (x^0, v^0, its inertial target); the
         next iteration restarts."""
+        with self._on_stream():
+            self._reset()
+
+    def _reset(self):
         ctx = self.ctx
         self.x.copy_(self.x0)
         self.x_frame.copy_(self.x0)
@@ -178,6 +228,10 @@ class PNCG:
         v^{t+1} = (x - x^t) / h, a new inertial target, and the next
         iteration restarts (Algorithm 1 starts every time step with a
         rebuild)."""
+        with self._on_stream():
+            self._next_frame()
+
+    def _next_frame(self):
         ctx = self.ctx
         ctx.next_frame(self.x, self.x_frame, self.v_frame, self.xt)
         self.x_frame.copy_(self.x)
@@ -188,7 +242,8 @@ class PNCG:
         self.frames += 1
 
     def gnorm(self):
-        return float(torch.linalg.vector_norm(self.g).item())
+        with self._on_stream():
+            return float(torch.linalg.vector_norm(self.g).item())
 
     def solve(self, rel_tol=1e-6, max_iter=1000):
         """Iterates until the gradient an iteration starts from satisfies

@@ -98,3 +98,35 @@ def test_captured_iteration_replays_bitwise():
         del graph
         S.ctx.close()
     torch.cuda.synchronize()
+
+
+def test_graph_driver_follows_the_eager_trajectory():
+    """PNCG(graph=True) replays captured iterations (restart and update
+    forms, both buffer assignments); in deterministic mode it follows the
+    eager driver's trajectory bit for bit, rejected steps and halvings
+    (eager, after the replay) included."""
+    import torch
+    from paper_2604_19892_amd.pncg import PNCG
+    print("\n[graph case] two boxes, deterministic, 30 iterations eager and replayed", flush=True)
+    sc = synth.two_boxes_scene(active_frac=0.8)
+    runs = []
+    for graph in (False, True):
+        s = PNCG(sc, block_prec="f32", hess_prec="f32", deterministic=True, graph=graph)
+        for k in range(30):
+            if k == 15:
+                s.reset()
+            s.iterate()
+        torch.cuda.synchronize()
+        code, msg = s.ctx.sync()
+        assert code == 0, msg
+        runs.append(([(r["mu"], r["nu"], r["r"], r["E"], r["restart"], r["scale"]) for r in s.log],
+                     s.x.cpu().numpy().copy(), len(s._graphs)))
+        s._graphs.clear()
+        s.ctx.close()
+        del s
+        torch.cuda.empty_cache()
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert sum(r[4] for r in runs[0][0]) >= 2 and sum(not r[4] for r in runs[0][0]) >= 2
+    print("graphs captured: %d" % runs[1][2], flush=True)
+    assert runs[1][2] >= 2
