@@ -500,6 +500,80 @@ def hierarchy_solves(sc, tol, max_iter, repeats=2):
     return {"workload": sc.name, "tol": tol, "max_iter": max_iter, "block_storage": "f32", "runs": runs}
 
 
+def batched_measure(steps=30, tol=1e-6, max_iter=600):
+    """Many independent scenes in one context (the batched configuration):
+    64 stacked-box scenes of 5k..120k vertices and 1k..40k stencils, K = 24,
+    three levels; every stage is one launch over all scenes and the
+    iterations replay captured HIP graphs.  The scenes share the PNCG step
+    scalars (one 2x2 system over their union; per-scene scalars are not
+    built).  Iterations per second over blocks of ten from the start, the
+    Woodbury rank histogram, then a solve to tol on the union and each
+    scene's own gradient reduction."""
+    import numpy as np
+    import torch
+    from paper_2604_19892_amd import synth
+    from paper_2604_19892_amd.pncg import PNCG
+    t0 = time.perf_counter()
+    sc, offs = synth.batch_scene()
+    gen_s = time.perf_counter() - t0
+    s = PNCG(sc, block_prec="f32", hess_prec="f32", graph=True)
+    ctx = s.ctx
+    for i in range(BLOCK):                       # captures every form
+        if i == 0:
+            s.reset()
+        s.iterate()
+    torch.cuda.synchronize()
+    hist = torch.zeros(sc.K + 1, dtype=torch.int64, device="cuda")
+    with s._on_stream():
+        hist += s.rank_hist
+        hist.zero_()
+    torch.cuda.synchronize()
+    dt, done, r0, n_upd = 0.0, 0, s.n_restarts, 0
+    while done < steps:
+        s.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(min(BLOCK, steps - done)):
+            rs = s.restart
+            s.iterate()
+            if not rs:
+                with s._on_stream():
+                    hist += s.rank_hist
+                n_upd += 1
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t
+        done += BLOCK
+    restarts = s.n_restarts - r0
+    # per-scene gradient reduction after a solve of the union
+    s.reset()
+    torch.cuda.synchronize()
+
+    def scene_norms():
+        torch.cuda.synchronize()
+        g = ctx.from_lib(s.g).reshape(-1, 3)
+        return np.array([np.linalg.norm(g[offs[i]:offs[i + 1]]) for i in range(len(offs) - 1)])
+
+    g0 = scene_norms()
+    it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
+    ratio = scene_norms() / np.maximum(g0, 1e-300)
+    code, msg = ctx.sync()
+    sizes = np.diff(offs)
+    out = {"workload": "%d stacked-box scenes, %d..%d verts each (%d verts, %d tets, %d stencils in all)"
+                       % (len(sizes), sizes.min(), sizes.max(), sc.N, sc.T, sc.pool['key'].size),
+           "levels": int(ctx.levels), "K": int(sc.K), "generation_s": gen_s,
+           "iters_per_s": steps / dt, "ms_per_iter": 1e3 * dt / steps, "restart_fraction": restarts / steps,
+           "graphs": len(s._graphs), "woodbury_rank_hist": hist.cpu().numpy().tolist(),
+           "solve": {"iters": it, "seconds": sec, "rel_gnorm_union": rel, "tol": tol,
+                     "scene_rel_gnorm": {"min": float(ratio.min()), "median": float(np.median(ratio)),
+                                         "max": float(ratio.max())}},
+           "shared_step_scalars": True, "status": code}
+    s._graphs.clear()
+    ctx.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def stiffness_sweep(tol, max_iter, moduli=(2.15e4, 1e5, 1e6, 1e7)):
     """MAS-PNCG against 3x3 block-Jacobi PNCG as the material stiffens
     (Section 5, stiffness robustness): the two-box scene with one Young's
@@ -577,6 +651,7 @@ def main():
     ap.add_argument("--no-geo", action="store_true", help="skip the geometric-contacts measurement")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the ablation variants and the stiffness sweep")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-scenes measurement")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--solve-max-iter", type=int, default=1500)
     ap.add_argument("--solve-repeats", type=int, default=5)
@@ -796,6 +871,9 @@ def main():
         out["precision_errors"] = precision_errors(sc)
         out["tol_solve"] = tolerance_solves(sc, tuple(SOLVE_FORMS), args.solve_tol,
                                             args.solve_max_iter, args.solve_repeats)
+    if not args.no_batch:
+        print("[bench] batched scenes", file=sys.stderr, flush=True)
+        out["batched"] = batched_measure()
     if not args.no_ablation:
         print("[bench] ablations", file=sys.stderr, flush=True)
         out["ablations"] = ablation_solves(sc, args.solve_tol, args.solve_max_iter)

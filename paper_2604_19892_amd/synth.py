@@ -472,6 +472,48 @@ def combs_scene(seed=3, teeth=8, width=2, tooth_len=12, base=2, depth=4, dhat=1e
                  levels=levels, K=K)
 
 
+def batch_scene(n_scenes=64, seed=11, size_range=(5e3, 1.2e5), contact_range=(1e3, 4e4), levels=3, K=24,
+                dhat=1e-3, h=0.01, rho=1000.0, kappa=1e3 * 1000.0 / 39 ** 3, speed=0.5, spacing=2.0):
+    """Independent scenes in one mesh: each a pair of stacked boxes (two_boxes
+    layout) with a vertex count log-uniform in ``size_range`` and a stencil
+    count log-uniform in ``contact_range`` (capped by what its facing layers
+    hold), the upper box moving down at ``speed``; scenes sit ``spacing``
+    apart on a 4-wide grid, so they share no tet and no stencil.  Returns
+    the combined scene and the vertex offset of each scene (n_scenes + 1)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1]), n_scenes))
+    counts = np.exp(rng.uniform(np.log(contact_range[0]), np.log(contact_range[1]), n_scenes))
+    Xs, xs, vs, ts, pools, offs = [], [], [], [], [], [0]
+    for i in range(n_scenes):
+        nxy = max(8, int(round(sizes[i] ** (1.0 / 3.0))))
+        nz = max(4, nxy // 2)
+        cap = 8 * nxy * nxy
+        sc = two_boxes_scene(seed=seed * 1000 + i, n_contacts=int(min(counts[i], cap)), dhat=dhat, h=h, rho=rho,
+                             levels=levels, K=K, nxy=nxy, nz=nz, active_frac=0.8)
+        shift = spacing * np.array([i % 4, (i // 4) % 4, i // 16], np.float64)
+        o = offs[-1]
+        Xs.append(sc.X + shift)
+        xs.append(sc.x + shift)
+        v = np.zeros_like(sc.X)
+        v[sc.N // 2:, 2] = -speed
+        vs.append(v)
+        ts.append(sc.tets + o)
+        idx = np.where(sc.pool['idx'] >= 0, sc.pool['idx'] + o, -1).astype(np.int32)
+        tag = sc.pool['key'] >> np.uint64(60)
+        key = (tag << np.uint64(60)) | (np.uint64(i) << np.uint64(52)) | (sc.pool['key'] & np.uint64((1 << 52) - 1))
+        pools.append(dict(key=key, idx=idx, grad=sc.pool['grad'], off=sc.pool['off'] + (sc.pool['grad'].reshape(
+            -1, 4, 3) * np.where(sc.pool['idx'][..., None] >= 0, shift, 0.0)).sum((1, 2))))
+        offs.append(o + sc.N)
+    X = np.concatenate(Xs)
+    tets = np.concatenate(ts).astype(np.int32)
+    pool = {k: np.concatenate([p[k] for p in pools]) for k in ("key", "idx", "grad", "off")}
+    T = tets.shape[0]
+    out = Scene("batch%d" % n_scenes, X, np.concatenate(xs), np.concatenate(vs), tets, np.full(T, rho),
+                np.full(T, 1e5), np.full(T, 0.4), h, dhat, kappa=kappa, gravity=np.array([0.0, 0.0, -9.81]),
+                pool=pool, levels=levels, K=K)
+    return out, np.array(offs, np.int64)
+
+
 def churn_set(rng, scene, base, frac=0.3):
     """Scripted contact churn of a fraction ``frac`` of a contact set:
     40% replaced by fresh stencils (new keys), 30% stiffen (distance x
