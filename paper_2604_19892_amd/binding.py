@@ -234,6 +234,8 @@ class MasContext:
         return self.out
 
     def step_out(self, out=None):
+        """The step scalars (from self.out, or from a copy of it, device or
+        host)."""
         raw = (self.out if out is None else out).cpu().numpy().view(np.uint8)
         s = MasStepOut.from_buffer_copy(raw.tobytes())
         return {f: getattr(s, f) for f in _abi.STEP_FIELDS}

@@ -652,34 +652,37 @@ __global__ __launch_bounds__(256) void k_alpha_round(int r, int64_t m, const int
                                                      uint64_t* half, uint32_t* rounds) {
   if (r > 0 && rounds[r - 1] == 0u) return;  // uniform: written by the previous launch
   const uint64_t mask = (1ull << r) - 1ull;
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  bool viol = false;
-  if (i < m) {
+  // a bounded grid (most rounds find nothing and return at once, so their
+  // cost is the dispatch); each workgroup walks a contiguous run of
+  // stencils, runs placed by xcd_block
+  const int64_t per = (m + int64_t(gridDim.x) * 256 - 1) / (int64_t(gridDim.x) * 256) * 256;
+  const int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * per;
+  uint32_t nviol = 0;
+  for (int64_t i = b0 + threadIdx.x; i < min(m, b0 + per); i += blockDim.x) {
     const double di = d[i];
-    if (di > 0.0) {
-      const int4 iv = reinterpret_cast<const int4*>(idx)[i];
-      const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
-      double dn = di;
+    if (!(di > 0.0)) continue;
+    const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+    const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+    double dn = di;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (vi[j] < 0) continue;
-        double dot = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      if (vi[j] < 0) continue;
+      double dot = 0.0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
-        dn += alpha_round(a0, half, vi[j] >> 5, mask) * dot;
-      }
-      if (dn < 0.05 * di) {
-        viol = true;
-        if (r < SAFE_ROUNDS) {
+      for (int q = 0; q < 3; ++q) dot += grad[12 * i + 3 * j + q] * p[3 * vi[j] + q];
+      dn += alpha_round(a0, half, vi[j] >> 5, mask) * dot;
+    }
+    if (dn < 0.05 * di) {
+      ++nviol;
+      if (r < SAFE_ROUNDS) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (vi[j] >= 0) atomicOr(reinterpret_cast<unsigned long long*>(half + (vi[j] >> 5)), 1ull << r);
-        }
+        for (int j = 0; j < 4; ++j)
+          if (vi[j] >= 0) atomicOr(reinterpret_cast<unsigned long long*>(half + (vi[j] >> 5)), 1ull << r);
       }
     }
   }
-  const unsigned long long b = __ballot(viol);
-  if (b != 0 && (threadIdx.x & 63) == 0) atomicAdd(rounds + r, uint32_t(__popcll(b)));
+  for (int o = 32; o > 0; o >>= 1) nviol += __shfl_xor(nviol, o);
+  if (nviol != 0 && (threadIdx.x & 63) == 0) atomicAdd(rounds + r, nviol);
 }
 
 // the damped steps, or, if the last round still found a stencil closing
@@ -727,9 +730,10 @@ mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_
       k_alpha_stencils<<<g, b256, 0, c.s>>>(cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0, c.alpha_mix);
       // subdomains moving at different steps: halve the steps of the
       // subdomains of any stencil the combined motion would close
+      const dim3 gr(unsigned(std::min<int64_t>(g.x, 4 * int64_t(c.n_cu))));
       for (int r = 0; r <= SAFE_ROUNDS; ++r)
-        k_alpha_round<<<g, b256, 0, c.s>>>(r, cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0, c.ahalf,
-                                           c.around);
+        k_alpha_round<<<gr, b256, 0, c.s>>>(r, cand->m, cand->idx, cand->grad, cand->d, p, c.alpha0, c.ahalf,
+                                            c.around);
     }
     k_alpha_final<<<gD, b256, 0, c.s>>>(D, c.alpha0, c.alpha_mix, c.ahalf, c.around, c.alpha);
   }

@@ -90,7 +90,10 @@ class PNCG:
         self.z, self.z_prev, self.vz, self.p, self.vp = v(), v(), v(), v(), v()
         self.step = v() if rule != "subspace" else None
         self.E = torch.zeros(1, dtype=torch.float64, device=device)
-        self.E_trial = torch.zeros(1, dtype=torch.float64, device=device)
+        # the trial energy and a copy of the step scalars side by side, so
+        # that one read brings both to the host
+        self._readback = torch.zeros(1 + ctx.out.numel(), dtype=torch.float64, device=device)
+        self.E_trial = self._readback[:1]
         self.rank_hist = torch.zeros(max(cfg.max_rank, 0) + 1, dtype=torch.int32, device=device)
         ctx.stencil_distance(self.x, self.pool)
         ctx.energy_grad(self.x, self.xt, self.pool, self.E, self.g)
@@ -164,11 +167,16 @@ class PNCG:
                 self.precision_counts = ctx.block_precisions(0)
         scale = 1.0
         accepted = False
+        self._readback[1:].copy_(ctx.out)
+        rb = self._readback.cpu()
+        st = ctx.step_out(rb[1:])
         for h in range(self.max_halvings + 1):
             if h > 0:
                 ctx.stencil_distance(self.x_trial, self.pool_t)
                 ctx.energy_grad(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
-            Et = float(self.E_trial.item())
+                Et = float(self.E_trial.item())
+            else:
+                Et = float(rb[0])
             if Et <= self.E_host:
                 accepted = True
                 break
@@ -176,7 +184,6 @@ class PNCG:
                 scale *= 0.5
                 self.n_halvings += 1
                 ctx.safe_step(self.x, step, None, scale, self.x_trial)
-        st = ctx.step_out()
         if self.g0norm is None:
             self.g0norm = np.sqrt(st["gnorm2"])
         rec = dict(k=self.k, gnorm=float(np.sqrt(st["gnorm2"])), znorm=float(np.sqrt(st["znorm2"])),
