@@ -503,71 +503,62 @@ def hierarchy_solves(sc, tol, max_iter, repeats=2):
 def batched_measure(steps=30, tol=1e-6, max_iter=600):
     """Many independent scenes in one context (the batched configuration):
     64 stacked-box scenes of 5k..120k vertices and 1k..40k stencils, K = 24,
-    three levels; every stage is one launch over all scenes and the
-    iterations replay captured HIP graphs.  The scenes share the PNCG step
-    scalars (one 2x2 system over their union; per-scene scalars are not
-    built).  Iterations per second over blocks of ten from the start, the
-    Woodbury rank histogram, then a solve to tol on the union and each
-    scene's own gradient reduction."""
+    three levels; every stage is one launch over all scenes, and each scene
+    keeps its own 2x2 step scalars, restart decision and descent check
+    (ScenePNCG).  Iterations per second over blocks of ten from the start,
+    the Woodbury rank histogram, then a solve until every scene's gradient
+    is below tol of its own first one, with the iteration at which each got
+    there."""
     import numpy as np
     import torch
     from paper_2604_19892_amd import synth
-    from paper_2604_19892_amd.pncg import PNCG
+    from paper_2604_19892_amd.pncg import ScenePNCG
     t0 = time.perf_counter()
     sc, offs = synth.batch_scene()
     gen_s = time.perf_counter() - t0
-    s = PNCG(sc, block_prec="f32", hess_prec="f32", graph=True)
+    s = ScenePNCG(sc, offs, block_prec="f32", hess_prec="f32")
     ctx = s.ctx
-    for i in range(BLOCK):                       # captures every form
-        if i == 0:
-            s.reset()
+    for _ in range(BLOCK):                       # warm-up block
         s.iterate()
-    torch.cuda.synchronize()
     hist = torch.zeros(sc.K + 1, dtype=torch.int64, device="cuda")
-    with s._on_stream():
-        hist += s.rank_hist
-        hist.zero_()
+    hist += s.rank_hist
+    hist.zero_()
     torch.cuda.synchronize()
-    dt, done, r0, n_upd = 0.0, 0, s.n_restarts, 0
+    dt, done, n_upd, builds0, restarts = 0.0, 0, 0, s.n_builds, 0
     while done < steps:
         s.reset()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(min(BLOCK, steps - done)):
-            rs = s.restart
+            any_restart = bool(s.restart.any())
+            restarts += int(s.restart.sum())
             s.iterate()
-            if not rs:
-                with s._on_stream():
-                    hist += s.rank_hist
+            if not any_restart:
+                hist += s.rank_hist
                 n_upd += 1
         torch.cuda.synchronize()
         dt += time.perf_counter() - t
         done += BLOCK
-    restarts = s.n_restarts - r0
-    # per-scene gradient reduction after a solve of the union
+    builds = s.n_builds - builds0
     s.reset()
-    torch.cuda.synchronize()
-
-    def scene_norms():
-        torch.cuda.synchronize()
-        g = ctx.from_lib(s.g).reshape(-1, 3)
-        return np.array([np.linalg.norm(g[offs[i]:offs[i + 1]]) for i in range(len(offs) - 1)])
-
-    g0 = scene_norms()
-    it, sec, rel = s.solve(rel_tol=tol, max_iter=max_iter)
-    ratio = scene_norms() / np.maximum(g0, 1e-300)
+    first, it, sec, rel_end = s.solve(rel_tol=tol, max_iter=max_iter)
     code, msg = ctx.sync()
     sizes = np.diff(offs)
+    reached = first[first >= 0]
     out = {"workload": "%d stacked-box scenes, %d..%d verts each (%d verts, %d tets, %d stencils in all)"
                        % (len(sizes), sizes.min(), sizes.max(), sc.N, sc.T, sc.pool['key'].size),
            "levels": int(ctx.levels), "K": int(sc.K), "generation_s": gen_s,
-           "iters_per_s": steps / dt, "ms_per_iter": 1e3 * dt / steps, "restart_fraction": restarts / steps,
-           "graphs": len(s._graphs), "woodbury_rank_hist": hist.cpu().numpy().tolist(),
-           "solve": {"iters": it, "seconds": sec, "rel_gnorm_union": rel, "tol": tol,
-                     "scene_rel_gnorm": {"min": float(ratio.min()), "median": float(np.median(ratio)),
-                                         "max": float(ratio.max())}},
-           "shared_step_scalars": True, "status": code}
-    s._graphs.clear()
+           "iters_per_s": steps / dt, "ms_per_iter": 1e3 * dt / steps,
+           "scene_restart_fraction": restarts / (steps * len(sizes)), "iterations_with_a_rebuild": builds / steps,
+           "woodbury_rank_hist": hist.cpu().numpy().tolist(),
+           "solve": {"iters": it, "seconds": sec, "tol": tol, "scenes_converged": int(reached.size),
+                     "scene_iters_to_tol": {"min": int(reached.min()) if reached.size else None,
+                                            "median": float(np.median(reached)) if reached.size else None,
+                                            "max": int(reached.max()) if reached.size else None},
+                     "not_converged": [{"scene": int(q), "verts": int(sizes[q]), "rel_gnorm_end": float(rel_end[q]),
+                                        "restarts_last_10": int(sum(r["restart"][q] for r in s.log[-10:]))}
+                                       for q in np.nonzero(first < 0)[0]]},
+           "per_scene_step_scalars": True, "status": code}
     ctx.close()
     del s
     torch.cuda.empty_cache()

@@ -159,6 +159,17 @@ typedef struct {
    * is MAS_HIER_CONNECTIVITY; may be 0 / NULL. */
   int64_t num_links;
   const int32_t* links;
+  /* Independent scenes in one mesh (the batched form): scene s owns the
+   * original vertices [scene_offsets[s], scene_offsets[s + 1]) (host,
+   * num_scenes + 1 entries, 0 first, num_vertices last, increasing); no tet
+   * or link may join two scenes.  num_scenes 0 or 1 (and NULL offsets):
+   * one scene.  The library then orders vertices scene by scene (Morton
+   * order inside each; MAS_HIER_MORTON only), cuts its vertex ranges at
+   * scene starts, and the *_scenes calls below take per-scene scalars.
+   * Coarse MAS nodes are runs of 32^l library vertices and may span the end
+   * of one scene and the start of the next (P stays SPD on the union). */
+  int32_t num_scenes;
+  const int64_t* scene_offsets;
 } mas_mesh;
 
 /* Contact stencils, device pointers, library vertex numbering. */
@@ -302,6 +313,28 @@ mas_status pncg_subspace_step_noalloc(void* ctx, const double* g, const double* 
 mas_status pncg_beta_step(void* ctx, int32_t rule, const double* g, const double* g_prev, const double* z,
                           const double* z_prev, const double* v_z, double* d, double* v_d, int32_t restart,
                           double* p, mas_step_out* out);
+
+/* Per-scene forms of the iteration for a mesh of several scenes (the same
+ * calls serve one scene).  Each scene takes its own 2x2 step (Section 4.2;
+ * supplement Section 2.4) from sums over its own vertices and update
+ * columns:
+ *   pncg_subspace_step_scenes: as pncg_subspace_step, with restart (device
+ *     int32, num_scenes) and out (device, num_scenes) per scene; z_prev may be
+ *     NULL (r = 0);
+ *   mas_energy_grad_scenes: E (device, num_scenes) per scene and the gradient
+ *     g (device, 3N, nullable) as mas_energy_grad;
+ *   mas_step_scenes: x_out = x + scale_s alpha_d p with the per-subdomain steps
+ *     of the last mas_safe_step and a scale per scene (device, num_scenes);
+ *   mas_scenes: the scene count and, if voff is not NULL, the library vertex
+ *     offset of each scene (host int64, num_scenes + 1).
+ * Not available in deterministic mode (MAS_ERR_STATE). */
+mas_status pncg_subspace_step_scenes(void* ctx, const double* g, const double* z, const double* z_prev,
+                                     const double* v_z, double* p, double* v_p, const int32_t* restart,
+                                     mas_step_out* out);
+mas_status mas_energy_grad_scenes(void* ctx, const double* x, const double* x_tilde, const mas_contacts* c,
+                                  double* E, double* g);
+mas_status mas_step_scenes(void* ctx, const double* x, const double* p, const double* scale, double* x_out);
+mas_status mas_scenes(void* ctx, int32_t* num_scenes, int64_t* voff);
 
 /* Incremental potential (Section 3.1) at x: E (device scalar) and, if g is
  * not NULL, its gradient (device, 3N).  Contacts with d <= 0 make E = +inf.

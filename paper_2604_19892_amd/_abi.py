@@ -56,6 +56,8 @@ class MasMesh(ctypes.Structure):
         ("poisson", ctypes.c_void_p),
         ("num_links", ctypes.c_int64),
         ("links", ctypes.c_void_p),
+        ("num_scenes", ctypes.c_int32),
+        ("scene_offsets", ctypes.c_void_p),
     ]
 
 
@@ -112,6 +114,10 @@ SIGNATURES = {
     "pncg_subspace_step_noalloc": (_I32, [_P, _P, _P, _P, _P, _P, _P, _I32, _P]),
     "pncg_beta_step": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _P, _P]),
     "mas_energy_grad": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _P, _P]),
+    "pncg_subspace_step_scenes": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "mas_energy_grad_scenes": (_I32, [_P, _P, _P, ctypes.POINTER(MasContacts), _P, _P]),
+    "mas_step_scenes": (_I32, [_P, _P, _P, _P, _P]),
+    "mas_scenes": (_I32, [_P, _P, _P]),
     "mas_inertial_target": (_I32, [_P, _P, _P, _P]),
     "mas_next_frame": (_I32, [_P, _P, _P, _P, _P]),
     "mas_stencil_distance": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),

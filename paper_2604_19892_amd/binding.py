@@ -113,16 +113,17 @@ def vertex_order(X, tets, levels, hierarchy="morton", links=None):
 class MasContext:
     """One library context for one mesh (``mas_create`` .. ``mas_destroy``)."""
 
-    def __init__(self, scene, cfg, device="cuda", links=None):
+    def __init__(self, scene, cfg, device="cuda", links=None, scene_offsets=None):
         L = _abi.lib()
         self.device = device
         self.scene = scene
         X = np.ascontiguousarray(scene.X, np.float64)
         tets = np.ascontiguousarray(scene.tets, np.int32)
         lk = np.ascontiguousarray(np.zeros((0, 2)) if links is None else links, np.int32)
+        so = np.ascontiguousarray(np.array([0, X.shape[0]]) if scene_offsets is None else scene_offsets, np.int64)
         self._host = [X, tets, np.ascontiguousarray(scene.density, np.float64),
                       np.ascontiguousarray(scene.youngs, np.float64),
-                      np.ascontiguousarray(scene.poisson, np.float64), lk]
+                      np.ascontiguousarray(scene.poisson, np.float64), lk, so]
         mesh = MasMesh()
         mesh.num_vertices = X.shape[0]
         mesh.num_tets = tets.shape[0]
@@ -133,6 +134,8 @@ class MasContext:
         mesh.poisson = self._host[4].ctypes.data
         mesh.num_links = lk.shape[0]
         mesh.links = lk.ctypes.data if lk.shape[0] else None
+        mesh.num_scenes = so.shape[0] - 1
+        mesh.scene_offsets = so.ctypes.data
         self.N = X.shape[0]
         self.perm = np.zeros(self.N, np.int32)
         h = ctypes.c_void_p()
@@ -233,10 +236,34 @@ class MasContext:
             int(restart), _ptr(p), _ptr(self.out)))
         return self.out
 
+    def scenes(self):
+        """(number of scenes, library vertex offset of each scene)."""
+        S = ctypes.c_int32()
+        check("mas_scenes", _abi.lib().mas_scenes(self.h, ctypes.byref(S), None))
+        voff = np.zeros(S.value + 1, np.int64)
+        check("mas_scenes", _abi.lib().mas_scenes(self.h, None, voff.ctypes.data))
+        return S.value, voff
+
+    def subspace_step_scenes(self, g, z, z_prev, vz, p, vp, restart, out):
+        """pncg_subspace_step_scenes: restart (device int32, one per scene),
+        out (device float64, one MasStepOut per scene)."""
+        check("pncg_subspace_step_scenes", _abi.lib().pncg_subspace_step_scenes(
+            self.h, _ptr(g), _ptr(z), _ptr(z_prev), _ptr(vz), _ptr(p), _ptr(vp), _ptr(restart), _ptr(out)))
+
+    def energy_grad_scenes(self, x, x_tilde, contacts, E, g=None):
+        c = contacts.struct() if contacts is not None else None
+        check("mas_energy_grad_scenes", _abi.lib().mas_energy_grad_scenes(
+            self.h, _ptr(x), _ptr(x_tilde), ctypes.byref(c) if c else None, _ptr(E), _ptr(g)))
+
+    def step_scenes(self, x, p, scale, x_out):
+        check("mas_step_scenes", _abi.lib().mas_step_scenes(self.h, _ptr(x), _ptr(p), _ptr(scale), _ptr(x_out)))
+
     def step_out(self, out=None):
         """The step scalars (from self.out, or from a copy of it, device or
         host)."""
-        raw = (self.out if out is None else out).cpu().numpy().view(np.uint8)
+        src = self.out if out is None else out
+        arr = src if isinstance(src, np.ndarray) else src.cpu().numpy()
+        raw = np.ascontiguousarray(arr, np.float64).view(np.uint8)
         s = MasStepOut.from_buffer_copy(raw.tobytes())
         return {f: getattr(s, f) for f in _abi.STEP_FIELDS}
 

@@ -373,7 +373,7 @@ mas_status mas_destroy(void* p) {
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
                   c->alpha, c->alpha0, c->alpha_mix, c->ahalf, c->around, c->err, c->diag, c->cls_part, c->scan_tmp,
-                  c->inc_cnt, c->inc_off, c->inc_list, c->coup, c->bj, c->bjinv};
+                  c->inc_cnt, c->inc_off, c->inc_list, c->coup, c->bj, c->bjinv, c->seg, c->scene_r, c->sc_acc};
   for (void* q : ptrs)
     if (q) hipFree(q);
   for (auto& t : c->cs) {
@@ -428,6 +428,23 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   if (mesh->num_links < 0 || (mesh->num_links > 0 && !mesh->links)) return MAS_ERR_INVALID_ARG;
   for (int64_t k = 0; k < 2 * mesh->num_links; ++k)
     if (mesh->links[k] < 0 || mesh->links[k] >= N) return MAS_ERR_INVALID_ARG;
+  // scenes: contiguous original vertex ranges that no tet or link joins
+  const int S = mesh->num_scenes > 1 ? mesh->num_scenes : 1;
+  std::vector<int32_t> vscene(N, 0);
+  if (S > 1) {
+    const int64_t* so = mesh->scene_offsets;
+    if (!so || S > MAX_SCENES || cfg->hierarchy != MAS_HIER_MORTON || so[0] != 0 || so[S] != N)
+      return MAS_ERR_INVALID_ARG;
+    for (int q = 0; q < S; ++q) {
+      if (so[q + 1] <= so[q]) return MAS_ERR_INVALID_ARG;
+      for (int64_t v = so[q]; v < so[q + 1]; ++v) vscene[v] = q;
+    }
+    for (int64_t t = 0; t < T; ++t)
+      for (int j = 1; j < 4; ++j)
+        if (vscene[mesh->tets[4 * t + j]] != vscene[mesh->tets[4 * t]]) return MAS_ERR_INVALID_ARG;
+    for (int64_t k = 0; k < mesh->num_links; ++k)
+      if (vscene[mesh->links[2 * k]] != vscene[mesh->links[2 * k + 1]]) return MAS_ERR_INVALID_ARG;
+  }
 
   Ctx* c = new (std::nothrow) Ctx();
   if (!c) return MAS_ERR_OOM;
@@ -469,6 +486,15 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     connectivity_order(mesh->rest_x, N, mesh->tets, T, mesh->links, mesh->num_links, cfg->num_levels, perm);
   else
     morton_order(mesh->rest_x, N, perm);
+  c->S = S;
+  c->scene_v.assign(S + 1, 0);
+  if (S > 1) {
+    // scene by scene, Morton order inside each
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return vscene[a] < vscene[b]; });
+    for (int q = 0; q <= S; ++q) c->scene_v[q] = mesh->scene_offsets[q];
+  } else {
+    c->scene_v[1] = N;
+  }
   std::vector<int32_t> rank(N);
   for (int64_t i = 0; i < N; ++i) rank[perm[i]] = int32_t(i);
   std::vector<int32_t> torder(T);
@@ -550,7 +576,8 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     for (int64_t v = 0; v < N; ++v) {
       int64_t add = 0;
       for (int32_t q = voff[v]; q < voff[v + 1]; ++q) add += mark[vt[q]] != r;
-      if (v > start && (cnt + add > target || v - start >= RANGE_MAX)) {
+      const bool scene_start = std::binary_search(c->scene_v.begin(), c->scene_v.end(), int64_t(v));
+      if (v > start && (cnt + add > target || v - start >= RANGE_MAX || scene_start)) {
         ++r;
         start = int32_t(v);
         rbeg.push_back(start);
@@ -601,6 +628,20 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->tet_list, tlist.size()));
   TRY(dalloc(&c->rt_off, c->nrange + 1));
   TRY(dalloc(&c->rbeg, c->nrange + 1));
+  {
+    // scenes: library vertex -> scene, first range of each scene
+    std::vector<int32_t> segh(N);
+    for (int q = 0; q < S; ++q)
+      for (int64_t v = c->scene_v[q]; v < c->scene_v[q + 1]; ++v) segh[v] = q;
+    std::vector<int64_t> sr(S + 1);
+    for (int q = 0; q < S; ++q) sr[q] = vrange[c->scene_v[q]];
+    sr[S] = c->nrange;
+    TRY(dalloc(&c->seg, N));
+    TRY(dalloc(&c->scene_r, S + 1));
+    TRY(dalloc(&c->sc_acc, 8 * S));
+    HIPCHK(hipMemcpy(c->seg, segh.data(), N * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->scene_r, sr.data(), (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
   TRY(dalloc(&c->vrange, N));
   TRY(dalloc(&c->ctr, 4));
   HIPCHK(hipMemcpy(c->rbeg, rbeg.data(), rbeg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -842,6 +883,40 @@ mas_status pncg_beta_step(void* p, int32_t rule, const double* g, const double* 
   return launch_beta(c, rule, g, restart ? nullptr : g_prev, z, z_prev, v_z, d, v_d, restart, step, out);
 }
 
+mas_status pncg_subspace_step_scenes(void* p, const double* g, const double* z, const double* z_prev,
+                                     const double* v_z, double* pk_, double* v_p, const int32_t* restart,
+                                     mas_step_out* out) {
+  if (!p || !g || !z || !v_z || !pk_ || !v_p || !restart) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (!c.built || c.cfg.deterministic) return MAS_ERR_STATE;
+  return launch_subspace_scenes(c, g, z, z_prev, v_z, pk_, v_p, restart, out);
+}
+
+mas_status mas_energy_grad_scenes(void* p, const double* x, const double* x_tilde, const mas_contacts* ct,
+                                  double* E, double* g) {
+  if (!p || !x || !x_tilde || !E) return MAS_ERR_INVALID_ARG;
+  mas_status st = valid_contacts(ct);
+  if (st != MAS_OK) return st;
+  Ctx& c = *as_ctx(p);
+  if (c.cfg.deterministic) return MAS_ERR_STATE;
+  return launch_energy_grad_scenes(c, x, x_tilde, ct, E, g);
+}
+
+mas_status mas_step_scenes(void* p, const double* x, const double* pk_, const double* scale, double* x_out) {
+  if (!p || !x || !pk_ || !scale || !x_out || x == x_out) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (c.cfg.deterministic) return MAS_ERR_STATE;
+  return launch_step_scenes(c, x, pk_, scale, x_out);
+}
+
+mas_status mas_scenes(void* p, int32_t* num_scenes, int64_t* voff) {
+  if (!p) return MAS_ERR_INVALID_ARG;
+  Ctx& c = *as_ctx(p);
+  if (num_scenes) *num_scenes = c.S;
+  if (voff) std::copy(c.scene_v.begin(), c.scene_v.end(), voff);
+  return MAS_OK;
+}
+
 mas_status mas_energy_grad(void* p, const double* x, const double* x_tilde, const mas_contacts* ct,
                            double* E, double* g) {
   if (!p || !x || !x_tilde || !E) return MAS_ERR_INVALID_ARG;
@@ -1009,6 +1084,19 @@ mas_status mas_vertex_order(const mas_mesh* mesh, int32_t num_levels, int32_t hi
     connectivity_order(mesh->rest_x, N, mesh->tets, T, mesh->links, mesh->num_links, num_levels, perm);
   else
     morton_order(mesh->rest_x, N, perm);
+  if (mesh->num_scenes > 1) {
+    // scene by scene, as mas_create orders them
+    const int S = mesh->num_scenes;
+    const int64_t* so = mesh->scene_offsets;
+    if (!so || S > MAX_SCENES || hierarchy != MAS_HIER_MORTON || so[0] != 0 || so[S] != N)
+      return MAS_ERR_INVALID_ARG;
+    std::vector<int32_t> vscene(N, 0);
+    for (int q = 0; q < S; ++q) {
+      if (so[q + 1] <= so[q]) return MAS_ERR_INVALID_ARG;
+      for (int64_t v = so[q]; v < so[q + 1]; ++v) vscene[v] = q;
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return vscene[a] < vscene[b]; });
+  }
   std::copy(perm.begin(), perm.end(), perm_out);
   return MAS_OK;
 }

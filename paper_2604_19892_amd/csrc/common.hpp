@@ -7,6 +7,8 @@
 #include <cstring>
 #include <cmath>
 
+#include <vector>
+
 #include "maspncg.h"
 
 namespace mas {
@@ -16,6 +18,7 @@ constexpr int BD = 96;                  // block dimension (3 DOFs x 32)
 constexpr int PK = BD * (BD + 1) / 2;   // packed lower-triangular entries (4656)
 constexpr int MAXL = 6;                 // maximum MAS levels
 constexpr int MAXK = 32;                // maximum Woodbury rank per subdomain
+constexpr int MAX_SCENES = 1024;        // scenes of one context (batched form)
 constexpr int SAFE_ROUNDS = 16;         // safe-step damping rounds (device side, no host sync)
 constexpr int EH = 54;                  // per-tet snapshot: 45 (9x9 packed) + 9 (Dm^-1)
 constexpr int TILE = 64;                // tets per AoSoA tile (one wavefront)
@@ -386,6 +389,14 @@ struct Ctx {
   double* W = nullptr;             // D0*K*96, float64
   double* Lcap = nullptr;          // D0*K*(K+1)/2
   bool have_update = false;
+
+  // scenes of the batched form: library vertex -> scene, the first vertex
+  // range of each scene (ranges are cut at scene starts), per-scene scratch
+  int S = 1;
+  std::vector<int64_t> scene_v;  // host, S + 1 library vertex offsets
+  int32_t* seg = nullptr;        // N
+  int64_t* scene_r = nullptr;    // S + 1
+  double* sc_acc = nullptr;      // 8 S
 
   // 3x3 block-Jacobi comparison preconditioner (precond = MAS_PRECOND_BJ3):
   // per vertex the packed lower 3x3 block of H~ (6 doubles) and its inverse

@@ -367,12 +367,22 @@ __global__ __launch_bounds__(RB) void k_ss_reduce(int64_t n3, const double* g, c
   block_reduce_store<NS>(s, part, nblk);
 }
 
+// the 2x2 solve from the sums s[NS] (thread-local); writes out (nullable)
+// and returns mu, nu in scal[0], scal[1]
+__device__ void ss_solve(const double* s, int restart, int has_zp, double eps_sing, double eps_abs, double delta,
+                         mas_step_out* out, double* scal);
+
 __global__ __launch_bounds__(RB) void k_ss_finalize(const double* part, int nblk, int restart, int has_zp,
                                                     double eps_sing, double eps_abs, double delta,
                                                     mas_step_out* out, double* scal) {
   __shared__ double s[NS];
   sum_partials<NS>(part, nblk, s);
   if (threadIdx.x != 0) return;
+  ss_solve(s, restart, has_zp, eps_sing, eps_abs, delta, out, scal);
+}
+
+__device__ void ss_solve(const double* s, int restart, int has_zp, double eps_sing, double eps_abs, double delta,
+                         mas_step_out* out, double* scal) {
   double gz = s[0], gp = s[1], gzp = s[2];
   double A11 = s[3] + s[8], A12 = s[4] + s[9], A22 = s[5] + s[10];
   double mu, nu;
@@ -740,6 +750,227 @@ mas_status launch_safe_step(Ctx& c, const double* x, const double* p, const mas_
   int64_t n3 = 3 * c.N;
   k_step<<<dim3((n3 + 255) / 256), b256, 0, c.s>>>(n3, x, p, c.alpha, scale, x_out);
   if (alpha) k_copy_f64<<<dim3(std::min<int64_t>((D + 255) / 256, 1024)), b256, 0, c.s>>>(c.alpha, alpha, D);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+
+// ------------------------------------------------------------------ scenes
+// Batched form: independent scenes in one context.  Library vertices are
+// ordered scene by scene and no vertex range crosses a scene, so per-range
+// partial sums add up to per-scene sums in a fixed order; the terms of the
+// update columns and of the contacts go to their scene through LDS and one
+// atomic per scene and workgroup.  Scratch: sc_acc[0, 3S) the xi sums,
+// [3S, 5S) the per-scene mu and nu, [5S, 7S) the contact energies.
+
+// per range: the vector sums 0..7 of the 2x2 system over the range's DOFs
+__global__ __launch_bounds__(RB) void k_ss_reduce_rng(const int32_t* rbeg, const int32_t* seg, const double* g,
+                                                      const double* z, const double* zp, const double* p,
+                                                      const double* vz, const double* vp, const int32_t* restart,
+                                                      double* part, int nrange) {
+  const int r = blockIdx.x;
+  const int64_t i0 = 3 * int64_t(rbeg[r]), i1 = 3 * int64_t(rbeg[r + 1]);
+  const bool use_p = restart[seg[rbeg[r]]] == 0;
+  double s[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s[q] = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RB) {
+    const double gi = g[i], zi = z[i], vzi = vz[i];
+    s[0] += gi * zi;
+    if (zp) s[2] += gi * zp[i];
+    s[3] += zi * vzi;
+    s[6] += gi * gi;
+    s[7] += zi * zi;
+    if (use_p) {
+      const double pi = p[i], vpi = vp[i];
+      s[1] += gi * pi;
+      s[4] += zi * vpi;
+      s[5] += pi * vpi;
+    }
+  }
+  block_reduce_store<8>(s, part, nrange);
+}
+
+// (u.z)^2, (u.z)(u.p), (u.p)^2 of the update columns, per scene
+__global__ __launch_bounds__(RB) void k_ss_xi_scenes(int64_t m, const int32_t* Uidx, const double* U,
+                                                     const double* dS, const double* z, const double* p,
+                                                     const int32_t* seg, const int32_t* restart, int S,
+                                                     double* acc) {
+  extern __shared__ double la[];
+  for (int q = threadIdx.x; q < 3 * S; q += RB) la[q] = 0.0;
+  __syncthreads();
+  for (int64_t c = blockIdx.x * int64_t(RB) + threadIdx.x; c < m; c += int64_t(gridDim.x) * RB) {
+    if (!(dS[c] > 0.0)) continue;
+    const int4 iv = reinterpret_cast<const int4*>(Uidx)[c];
+    const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+    int sc = -1;
+#pragma unroll
+    for (int j = 3; j >= 0; --j)
+      if (vi[j] >= 0) sc = seg[vi[j]];
+    if (sc < 0) continue;
+    const bool use_p = restart[sc] == 0;
+    double xz = 0.0, xp = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (vi[j] < 0) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double u = U[12 * c + 3 * j + a];
+        xz += u * z[3 * vi[j] + a];
+        if (use_p) xp += u * p[3 * vi[j] + a];
+      }
+    }
+    __hip_atomic_fetch_add(&la[3 * sc], xz * xz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&la[3 * sc + 1], xz * xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&la[3 * sc + 2], xp * xp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 3 * S; q += RB)
+    if (la[q] != 0.0) atomicAdd(&acc[q], la[q]);
+}
+
+// per scene (one workgroup each): its ranges' sums in a fixed order, the
+// xi sums, and the 2x2 solve
+__global__ __launch_bounds__(RB) void k_ss_final_scenes(const int64_t* scene_r, const double* part, int nrange,
+                                                        const double* acc, const int32_t* restart, int has_zp,
+                                                        double eps_sing, double eps_abs, double delta,
+                                                        mas_step_out* out, double* scal) {
+  __shared__ double red[8][RB];
+  const int sc = blockIdx.x;
+  const int64_t r0 = scene_r[sc], r1 = scene_r[sc + 1];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double t = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += RB) t += part[q * int64_t(nrange) + r];
+    red[q][threadIdx.x] = t;
+  }
+  __syncthreads();
+  for (int w = RB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double s[NS];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s[q] = red[q][0];
+  s[8] = acc[3 * sc];
+  s[9] = acc[3 * sc + 1];
+  s[10] = acc[3 * sc + 2];
+  ss_solve(s, restart[sc], has_zp, eps_sing, eps_abs, delta, out ? out + sc : nullptr, scal + 2 * sc);
+}
+
+__global__ void k_ss_update_scenes(int64_t n3, const int32_t* seg, const double* z, const double* vz, double* p,
+                                   double* vp, const double* scal) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  const int sc = seg[i / 3];
+  const double mu = scal[2 * sc], nu = scal[2 * sc + 1];
+  if (nu == 0.0) {
+    p[i] = -mu * z[i];
+    vp[i] = -mu * vz[i];
+  } else {
+    p[i] = -mu * z[i] + nu * p[i];
+    vp[i] = -mu * vz[i] + nu * vp[i];
+  }
+}
+
+mas_status launch_subspace_scenes(Ctx& c, const double* g, const double* z, const double* zp, const double* vz,
+                                  double* p, double* vp, const int32_t* restart, mas_step_out* out) {
+  ProfScope ps(c, MAS_T_SUBSPACE);
+  const int S = c.S, nr = int(c.nrange);
+  const int64_t n3 = 3 * c.N;
+  double* xi = c.sc_acc;
+  double* scal = c.sc_acc + 3 * S;
+  fill_f64(c, xi, 3 * S, 0.0);
+  k_ss_reduce_rng<<<dim3(nr), dim3(RB), 0, c.s>>>(c.rbeg, c.seg, g, z, zp, p, vz, vp, restart, c.partials, nr);
+  const int64_t m = c.have_update ? c.mc : 0;
+  if (m > 0)
+    k_ss_xi_scenes<<<dim3(unsigned(std::min<int64_t>((m + RB - 1) / RB, 1024))), dim3(RB),
+                     sizeof(double) * 3 * S, c.s>>>(m, c.Uidx, c.U, c.dS, z, p, c.seg, restart, S, xi);
+  k_ss_final_scenes<<<dim3(S), dim3(RB), 0, c.s>>>(c.scene_r, c.partials, nr, xi, restart, zp != nullptr,
+                                                   c.cfg.eps_sing, c.cfg.eps_abs, c.cfg.restart_delta, out, scal);
+  k_ss_update_scenes<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, c.seg, z, vz, p, vp, scal);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+// barrier energy and infeasible count of the contacts, per scene
+__global__ __launch_bounds__(RB) void k_eg_contacts_scenes(int64_t m, const int32_t* idx, const double* d,
+                                                           double kappa, double dhat, const int32_t* seg, int S,
+                                                           double* acc) {
+  extern __shared__ double la[];
+  for (int q = threadIdx.x; q < 2 * S; q += RB) la[q] = 0.0;
+  __syncthreads();
+  for (int64_t c = blockIdx.x * int64_t(RB) + threadIdx.x; c < m; c += int64_t(gridDim.x) * RB) {
+    const int4 iv = reinterpret_cast<const int4*>(idx)[c];
+    const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
+    int sc = -1;
+#pragma unroll
+    for (int j = 3; j >= 0; --j)
+      if (vi[j] >= 0) sc = seg[vi[j]];
+    if (sc < 0) continue;
+    const double di = d[c];
+    if (!(di > 0.0)) {
+      __hip_atomic_fetch_add(&la[2 * sc + 1], 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else if (di < dhat) {
+      double b, b1, b2;
+      barrier3(di, dhat, &b, &b1, &b2);
+      __hip_atomic_fetch_add(&la[2 * sc], kappa * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 2 * S; q += RB)
+    if (la[q] != 0.0) atomicAdd(&acc[q], la[q]);
+}
+
+// per scene: inertia and elasticity of its ranges (fixed order) plus its
+// contacts; +inf if one of its contacts is not at a positive distance
+__global__ __launch_bounds__(RB) void k_eg_final_scenes(const int64_t* scene_r, const double* part, int nblk,
+                                                        const double* acc, double* E) {
+  __shared__ double red[RB];
+  const int sc = blockIdx.x;
+  double t = 0.0;
+  for (int64_t r = scene_r[sc] + threadIdx.x; r < scene_r[sc + 1]; r += RB) t += part[r] + part[nblk + r];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = RB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E[sc] = acc[2 * sc + 1] > 0.0 ? INFINITY : red[0] + acc[2 * sc];
+}
+
+mas_status launch_energy_grad_scenes(Ctx& c, const double* x, const double* xt, const mas_contacts* ct,
+                                     double* E, double* g) {
+  const int S = c.S;
+  mas_status st = launch_energy_grad(c, x, xt, ct, c.scal + 32, g);
+  if (st != MAS_OK) return st;
+  double* eacc = c.sc_acc + 5 * S;
+  fill_f64(c, eacc, 2 * S, 0.0);
+  const int64_t m = ct ? ct->m : 0;
+  if (m > 0)
+    k_eg_contacts_scenes<<<dim3(unsigned(std::min<int64_t>((m + RB - 1) / RB, 1024))), dim3(RB),
+                           sizeof(double) * 2 * S, c.s>>>(m, ct->idx, ct->d, c.cfg.kappa, c.cfg.dhat, c.seg, S,
+                                                          eacc);
+  k_eg_final_scenes<<<dim3(S), dim3(RB), 0, c.s>>>(c.scene_r, c.partials, c.n_partial_blocks, eacc, E);
+  HIPCHK(hipGetLastError());
+  return MAS_OK;
+}
+
+__global__ void k_step_scenes(int64_t n3, const int32_t* seg, const double* x, const double* p, const double* alpha,
+                              const double* scale, double* xo) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n3) return;
+  const int64_t v = i / 3;
+  xo[i] = x[i] + scale[seg[v]] * alpha[v >> 5] * p[i];
+}
+
+mas_status launch_step_scenes(Ctx& c, const double* x, const double* p, const double* scale, double* x_out) {
+  const int64_t n3 = 3 * c.N;
+  k_step_scenes<<<dim3((n3 + 255) / 256), dim3(256), 0, c.s>>>(n3, c.seg, x, p, c.alpha, scale, x_out);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

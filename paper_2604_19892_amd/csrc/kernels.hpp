@@ -73,6 +73,12 @@ int64_t subspace_workspace_elems(const Ctx& c);
 mas_status launch_subspace_ws(Ctx& c, const double* g, const double* z, const double* zp, const double* vz,
                               double* p, double* vp, int restart, mas_step_out* out, double* part,
                               double* scal);
+// batched form: per-scene step scalars, energies and step scales
+mas_status launch_subspace_scenes(Ctx& c, const double* g, const double* z, const double* zp, const double* vz,
+                                  double* p, double* vp, const int32_t* restart, mas_step_out* out);
+mas_status launch_energy_grad_scenes(Ctx& c, const double* x, const double* xt, const mas_contacts* ct,
+                                     double* E, double* g);
+mas_status launch_step_scenes(Ctx& c, const double* x, const double* p, const double* scale, double* x_out);
 // comparison direction rules (rule: MAS_BETA_FR, MAS_BETA_CD, MAS_BETA_DK)
 mas_status launch_beta(Ctx& c, int rule, const double* g, const double* g_prev, const double* z,
                        const double* z_prev, const double* vz, double* d, double* vd, int restart, double* p,

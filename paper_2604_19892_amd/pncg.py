@@ -275,6 +275,141 @@ class PNCG:
         return it, time.perf_counter() - t, rel
 
 
+class ScenePNCG:
+    """Algorithm 1 on several independent scenes in one context (the batched
+    form): every stage is one launch over all scenes, and each scene keeps
+    its own 2x2 step scalars, restart decision, descent check and step
+    halving (pncg_subspace_step_scenes, mas_energy_grad_scenes,
+    mas_step_scenes).  When any scene restarts, every scene's preconditioner
+    is rebuilt (mas_build covers the whole context); the scenes that do not
+    restart keep their directions, whose H_base product is then recomputed.
+    The host reads the per-scene trial energies and step scalars once per
+    iteration (and once per halving round)."""
+
+    def __init__(self, scene, offsets, block_prec="f32", hess_prec=None, levels=None, K=None, delta=0.3,
+                 max_halvings=8, device="cuda"):
+        cfg = make_config(scene, levels=levels, K=K, block_prec=block_prec, hess_prec=hess_prec, delta=delta)
+        self.ctx = ctx = MasContext(scene, cfg, device=device, scene_offsets=offsets)
+        self.S, voff = ctx.scenes()
+        S = self.S
+        self.scene = scene
+        self.max_halvings = max_halvings
+        self.pool = ctx.contacts(scene.pool, sort=True)
+        self.pool_t = DeviceContacts.__new__(DeviceContacts)
+        self.pool_t.__dict__.update(self.pool.__dict__)
+        self.pool_t.d = torch.zeros_like(self.pool.d)
+        self.x = ctx.to_lib(scene.x)
+        self.x0 = self.x.clone()
+        self.xt = ctx.inertial_target(self.x, ctx.to_lib(scene.v))
+        v = ctx.vec
+        self.x_trial, self.g, self.g_trial = v(), v(), v()
+        self.z, self.z_prev, self.vz, self.p, self.vp = v(), v(), v(), v(), v()
+        self.nout = ctx.out.numel()
+        self.E = torch.zeros(S, dtype=torch.float64, device=device)
+        # per-scene trial energies and step scalars side by side (one read)
+        self._readback = torch.zeros(S + S * self.nout, dtype=torch.float64, device=device)
+        self.E_trial = self._readback[:S]
+        self.out = self._readback[S:]
+        self.restart_dev = torch.ones(S, dtype=torch.int32, device=device)
+        self.scale_dev = torch.ones(S, dtype=torch.float64, device=device)
+        self.rank_hist = torch.zeros(max(cfg.max_rank, 0) + 1, dtype=torch.int32, device=device)
+        self.seg_dof = torch.as_tensor(np.repeat(np.repeat(np.arange(S), np.diff(voff)), 3), device=device)
+        ctx.stencil_distance(self.x, self.pool)
+        ctx.energy_grad_scenes(self.x, self.xt, self.pool, self.E, self.g)
+        self.E_host = self.E.cpu().numpy().copy()
+        self.restart = np.ones(S, bool)
+        self.k = 0
+        self.n_builds = 0
+        self.log = []
+
+    def reset(self):
+        """Back to the scenes' start; the next iteration restarts every scene."""
+        self.x = self.x0.clone()
+        self.ctx.stencil_distance(self.x, self.pool)
+        self.ctx.energy_grad_scenes(self.x, self.xt, self.pool, self.E, self.g)
+        self.E_host = self.E.cpu().numpy().copy()
+        self.restart = np.ones(self.S, bool)
+        self.k = 0
+
+    def solve(self, rel_tol=1e-6, max_iter=1000):
+        """Iterates until every scene's gradient satisfies ||g_s|| <= rel_tol
+        ||g_s0|| (norms from the step kernel).  Returns the iteration at which
+        each scene first did (-1 if not), the iterations, the seconds and
+        each scene's final ||g_s|| / ||g_s0||."""
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        first = -np.ones(self.S, np.int64)
+        g0 = None
+        it = 0
+        gn = None
+        while it < max_iter:
+            outs = self.iterate()
+            it += 1
+            gn = np.sqrt([o["gnorm2"] for o in outs])
+            if g0 is None:
+                g0 = np.maximum(gn, 1e-300)
+            done = gn <= rel_tol * g0
+            first = np.where((first < 0) & done, it, first)
+            if np.all(first >= 0):
+                break
+        torch.cuda.synchronize()
+        return first, it, time.perf_counter() - t, (gn / g0 if gn is not None else None)
+
+    def _outs(self, flat):
+        return [self.ctx.step_out(flat[s * self.nout:(s + 1) * self.nout]) for s in range(self.S)]
+
+    def iterate(self):
+        ctx = self.ctx
+        S = self.S
+        if self.restart.any():
+            ctx.build(self.x, self.pool)
+            self.n_builds += 1
+            if not self.restart.all():
+                ctx.hess_vec(self.p, with_update=False, y=self.vp)
+        else:
+            ctx.woodbury_update(self.pool, self.rank_hist)
+        ctx.apply(self.g, self.z)
+        ctx.hess_vec(self.z, with_update=False, y=self.vz)
+        self.restart_dev.copy_(torch.as_tensor(self.restart.astype(np.int32)))
+        ctx.subspace_step_scenes(self.g, self.z, self.z_prev if self.k > 0 else None, self.vz, self.p, self.vp,
+                                 self.restart_dev, self.out)
+        ctx.safe_step(self.x, self.p, self.pool, 1.0, self.x_trial)
+        ctx.stencil_distance(self.x_trial, self.pool_t)
+        ctx.energy_grad_scenes(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
+        rb = self._readback.cpu().numpy()
+        Et = rb[:S].copy()
+        outs = self._outs(rb[S:])
+        accepted = Et <= self.E_host
+        scale = np.ones(S)
+        for _ in range(self.max_halvings):
+            if accepted.all():
+                break
+            scale[~accepted] *= 0.5
+            self.scale_dev.copy_(torch.as_tensor(scale))
+            ctx.step_scenes(self.x, self.p, self.scale_dev, self.x_trial)
+            ctx.stencil_distance(self.x_trial, self.pool_t)
+            ctx.energy_grad_scenes(self.x_trial, self.xt, self.pool_t, self.E_trial, self.g_trial)
+            E2 = self.E_trial.cpu().numpy()
+            Et = np.where(accepted, Et, E2)
+            accepted = accepted | (E2 <= self.E_host)
+        # every round recomputed the trial point of all scenes, the accepted
+        # ones at their accepted scale, so x_trial and g_trial hold them
+        keep = torch.as_tensor(accepted, device=self.x.device)[self.seg_dof]
+        self.x = torch.where(keep, self.x_trial, self.x)
+        self.g = torch.where(keep, self.g_trial, self.g)
+        ctx.stencil_distance(self.x, self.pool)
+        restart_next = np.array([o["restart_next"] for o in outs], bool)
+        self.log.append(dict(k=self.k, restart=self.restart.copy(), accepted=accepted.copy(), scale=scale.copy(),
+                             E=np.where(accepted, Et, self.E_host),
+                             gnorm=np.sqrt([o["gnorm2"] for o in outs]),
+                             mu=np.array([o["mu"] for o in outs]), nu=np.array([o["nu"] for o in outs])))
+        self.E_host = np.where(accepted, Et, self.E_host)
+        self.restart = (~accepted) | restart_next
+        self.z, self.z_prev = self.z_prev, self.z
+        self.k += 1
+        return outs
+
+
 class _PairBuffers:
     """Device outputs of one mas_constraint_set call (capacity cap)."""
 

@@ -30,7 +30,7 @@ def test_header_declares_the_hot_path_calls():
     names = declared_functions()
     for n in ("mas_build", "mas_woodbury_update", "mas_apply", "hess_vec", "pncg_subspace_step"):
         assert n in names
-    assert len(names) == 30
+    assert len(names) == 34
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -45,7 +45,7 @@ def test_struct_layouts_match_header(L):
     # field order / sizes as in the header (8-byte aligned members)
     assert ctypes.sizeof(_abi.MasConfig) == 4 + 4 + 7 * 8 + 3 * 8 + 4 * 4 + 8 + 3 * 8 + 4 + 4  # precond, hierarchy
     assert ctypes.sizeof(_abi.MasIterStats) == 7 * 8 + 2 * 4 + 8 + 8 * 8
-    assert ctypes.sizeof(_abi.MasMesh) == 2 * 8 + 5 * 8 + 2 * 8
+    assert ctypes.sizeof(_abi.MasMesh) == 2 * 8 + 5 * 8 + 2 * 8 + 8 + 8
     assert ctypes.sizeof(_abi.MasContacts) == 5 * 8
     assert ctypes.sizeof(_abi.MasStepOut) == 11 * 8 + 4 * 4
 
