@@ -326,14 +326,14 @@ def _loguniform(rng, lo, hi, n):
 # ---------------------------------------------------------- two boxes
 
 def two_boxes_scene(seed=1, n_contacts=20000, dhat=1e-3, h=0.01, E=1e5, nu=0.4, rho=1000.0,
-                    levels=3, K=8, nxy=40, nz=20, active_frac=1.0, kappa_scale=1.0):
-    """Two 40x40x20-vertex boxes (edge 1/39) stacked with the upper box
-    offset by half an edge in x and y; PT and EE stencils between the
-    facing layers with distances log-uniform in (1e-6, dhat) and normals
-    within 10 degrees of the vertical.  Barrier stiffness kappa_scale * rho
-    * edge^3."""
+                    levels=3, K=8, nxy=40, nz=20, active_frac=1.0, kappa_scale=1.0, edge=None):
+    """Two 40x40x20-vertex boxes (edge 1/39: unit boxes, unless ``edge`` is
+    given) stacked with the upper box offset by half an edge in x and y; PT
+    and EE stencils between the facing layers with distances log-uniform in
+    (1e-6, dhat) and normals within 10 degrees of the vertical.  Barrier
+    stiffness kappa_scale * rho * edge^3."""
     rng = np.random.default_rng(seed)
-    edge = 1.0 / (nxy - 1)
+    edge = 1.0 / (nxy - 1) if edge is None else float(edge)
     Xl, tl = lattice_from_cubes(box_cubes(nxy, nxy, nz), edge, (0, 0, 0))
     z0 = (nz - 1) * edge + 0.5 * dhat
     Xu, tu = lattice_from_cubes(box_cubes(nxy, nxy, nz), edge, (0.5 * edge, 0.5 * edge, z0))
@@ -475,11 +475,13 @@ def combs_scene(seed=3, teeth=8, width=2, tooth_len=12, base=2, depth=4, dhat=1e
 def batch_scene(n_scenes=64, seed=11, size_range=(5e3, 1.2e5), contact_range=(1e3, 4e4), levels=3, K=24,
                 dhat=1e-3, h=0.01, rho=1000.0, kappa=1e3 * 1000.0 / 39 ** 3, speed=0.5, spacing=2.0):
     """Independent scenes in one mesh: each a pair of stacked boxes (two_boxes
-    layout) with a vertex count log-uniform in ``size_range`` and a stencil
-    count log-uniform in ``contact_range`` (capped by what its facing layers
-    hold), the upper box moving down at ``speed``; scenes sit ``spacing``
-    apart on a 4-wide grid, so they share no tet and no stencil.  Returns
-    the combined scene and the vertex offset of each scene (n_scenes + 1)."""
+    layout, lattice edge 1/39 in every scene, so the boxes grow with the
+    vertex count and one kappa suits all) with a vertex count log-uniform in
+    ``size_range`` and a stencil count log-uniform in ``contact_range``
+    (capped by what its facing layers hold), the upper box moving down at
+    ``speed``; scenes sit ``spacing`` apart on a 4-wide grid, so they share
+    no tet and no stencil.  Returns the combined scene and the vertex offset
+    of each scene (n_scenes + 1)."""
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1]), n_scenes))
     counts = np.exp(rng.uniform(np.log(contact_range[0]), np.log(contact_range[1]), n_scenes))
@@ -489,7 +491,7 @@ def batch_scene(n_scenes=64, seed=11, size_range=(5e3, 1.2e5), contact_range=(1e
         nz = max(4, nxy // 2)
         cap = 8 * nxy * nxy
         sc = two_boxes_scene(seed=seed * 1000 + i, n_contacts=int(min(counts[i], cap)), dhat=dhat, h=h, rho=rho,
-                             levels=levels, K=K, nxy=nxy, nz=nz, active_frac=0.8)
+                             levels=levels, K=K, nxy=nxy, nz=nz, active_frac=0.8, edge=1.0 / 39)
         shift = spacing * np.array([i % 4, (i // 4) % 4, i // 16], np.float64)
         o = offs[-1]
         Xs.append(sc.X + shift)
