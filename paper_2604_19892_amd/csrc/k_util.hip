@@ -26,56 +26,67 @@ __device__ inline int stencil_buckets(int div, const int32_t* map, int64_t i, co
   return n;
 }
 
-// Counting and filling aggregate over the wavefront: lanes with the same
-// bucket share one atomic (stencils arrive sorted by their smallest vertex,
-// so neighbouring lanes mostly share buckets, which at coarse levels are
-// few).  Every lane runs the loops, including those past the end.
-__global__ __launch_bounds__(256) void k_bucket_count(int div, const int32_t* map, int64_t m, const int32_t* idx, const double* w,
-                                                      const double* vec12, int32_t* cnt) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  int b[4];
-  const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int key = q < n ? b[q] : -1;
-    while (true) {
-      const unsigned long long act = __ballot(key >= 0);
-      if (act == 0) break;
-      const int leader = __ffsll(act) - 1;
-      const int lk = __shfl(key, leader);
-      const unsigned long long match = __ballot(key == lk);
-      if (lane == leader) atomicAdd(&cnt[lk], __popcll(match));
-      if (key == lk) key = -1;
-    }
+// Counting and filling aggregate over the workgroup: each of its (up to
+// 4 x 256) bucket keys goes into an LDS hash table by linear probing, which
+// gives the key's slot and the item's rank among the workgroup's items of
+// that bucket; one global atomic per distinct key then adds the slot's
+// count (count pass) or reserves its run of list positions (fill pass).
+// Stencils arrive sorted by their smallest vertex, so the keys of a
+// stencil's other vertices are scattered; a per-key loop over the
+// wavefront would serialise on them.
+constexpr int BK_T = 256;
+constexpr int BK_HASH = 2048;  // > 4 keys x 256 items: at most half full
+
+__device__ inline int bk_slot(int* hkey, int key) {
+  int h = int((uint32_t(key) * 2654435761u) >> 21) & (BK_HASH - 1);
+  while (true) {
+    const int old = atomicCAS(&hkey[h], -1, key);
+    if (old == -1 || old == key) return h;
+    h = (h + 1) & (BK_HASH - 1);
   }
 }
 
-__global__ __launch_bounds__(256) void k_bucket_fill(int div, const int32_t* map, int64_t m, const int32_t* idx, const double* w,
-                                                     const double* vec12, int32_t* cursor, int32_t* list) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+__global__ __launch_bounds__(BK_T) void k_bucket_count(int div, const int32_t* map, int64_t m, const int32_t* idx,
+                                                       const double* w, const double* vec12, int32_t* cnt) {
+  __shared__ int hkey[BK_HASH];
+  __shared__ int hcnt[BK_HASH];
+  for (int q = threadIdx.x; q < BK_HASH; q += BK_T) {
+    hkey[q] = -1;
+    hcnt[q] = 0;
+  }
+  __syncthreads();
+  const int64_t i = blockIdx.x * int64_t(BK_T) + threadIdx.x;
   int b[4];
   const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
-  const int lane = threadIdx.x & 63;
-  const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int key = q < n ? b[q] : -1;
-    while (true) {
-      const unsigned long long act = __ballot(key >= 0);
-      if (act == 0) break;
-      const int leader = __ffsll(act) - 1;
-      const int lk = __shfl(key, leader);
-      const unsigned long long match = __ballot(key == lk);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&cursor[lk], __popcll(match));
-      base = __shfl(base, leader);
-      if (key == lk) {
-        list[base + __popcll(match & below)] = int32_t(i);
-        key = -1;
-      }
-    }
+  for (int q = 0; q < n; ++q) atomicAdd(&hcnt[bk_slot(hkey, b[q])], 1);
+  __syncthreads();
+  for (int q = threadIdx.x; q < BK_HASH; q += BK_T)
+    if (hkey[q] >= 0) atomicAdd(&cnt[hkey[q]], hcnt[q]);
+}
+
+__global__ __launch_bounds__(BK_T) void k_bucket_fill(int div, const int32_t* map, int64_t m, const int32_t* idx,
+                                                      const double* w, const double* vec12, int32_t* cursor,
+                                                      int32_t* list) {
+  __shared__ int hkey[BK_HASH];
+  __shared__ int hcnt[BK_HASH];
+  for (int q = threadIdx.x; q < BK_HASH; q += BK_T) {
+    hkey[q] = -1;
+    hcnt[q] = 0;
   }
+  __syncthreads();
+  const int64_t i = blockIdx.x * int64_t(BK_T) + threadIdx.x;
+  int b[4], slot[4], rank[4];
+  const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
+  for (int q = 0; q < n; ++q) {
+    slot[q] = bk_slot(hkey, b[q]);
+    rank[q] = atomicAdd(&hcnt[slot[q]], 1);
+  }
+  __syncthreads();
+  // the run of each distinct key (hcnt now holds its first list position)
+  for (int q = threadIdx.x; q < BK_HASH; q += BK_T)
+    if (hkey[q] >= 0) hcnt[q] = atomicAdd(&cursor[hkey[q]], hcnt[q]);
+  __syncthreads();
+  for (int q = 0; q < n; ++q) list[hcnt[slot[q]] + rank[q]] = int32_t(i);
 }
 
 // The order of items inside a bucket follows the atomics of the fill pass;
@@ -188,19 +199,13 @@ mas_status exclusive_scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n
 mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
                            const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
   fill_i32(c, cnt, D + 1, 0);
-  if (m > 0) {
-    int bs = 256;
-    int64_t gs = (m + bs - 1) / bs;
-    k_bucket_count<<<dim3(gs), dim3(bs), 0, c.s>>>(div, map, m, idx, w, vec12, cnt);
-  }
+  if (m > 0) k_bucket_count<<<dim3((m + BK_T - 1) / BK_T), dim3(BK_T), 0, c.s>>>(div, map, m, idx, w, vec12, cnt);
   mas_status st = exclusive_scan_i32(c, cnt, off, D + 1);
   if (st != MAS_OK) return st;
   if (m > 0) {
     // reuse cnt as the fill cursor
     k_copy_i32<<<dim3(std::min<int64_t>((D + 255) / 256, 4096)), dim3(256), 0, c.s>>>(off, cnt, D);
-    int bs = 256;
-    int64_t gs = (m + bs - 1) / bs;
-    k_bucket_fill<<<dim3(gs), dim3(bs), 0, c.s>>>(div, map, m, idx, w, vec12, cnt, list);
+    k_bucket_fill<<<dim3((m + BK_T - 1) / BK_T), dim3(BK_T), 0, c.s>>>(div, map, m, idx, w, vec12, cnt, list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;
