@@ -367,8 +367,8 @@ mas_status mas_destroy(void* p) {
   if (!p) return MAS_ERR_INVALID_ARG;
   Ctx* c = as_ctx(p);
   hipStreamSynchronize(c->s);
-  void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->tet_list, c->rt_off, c->rbeg, c->vrange, c->ctr, c->rl_t, c->rl_tv,
-                  c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->t_home, c->bkey,
+  void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->l0_tv, c->l0_home, c->rt_off, c->rbeg, c->vrange, c->ctr, c->rl_t, c->rl_tv,
+                  c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->bkey,
                   c->hkey, c->hval, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
                   c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
@@ -625,7 +625,8 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->geo, 12 * c->Tpad));
   TRY(dalloc(&c->mass, N));
   TRY(dalloc(&c->tet_off, D0 + 1));
-  TRY(dalloc(&c->tet_list, tlist.size()));
+  TRY(dalloc(&c->l0_tv, 4 * tlist.size()));
+  TRY(dalloc(&c->l0_home, tlist.size()));
   TRY(dalloc(&c->rt_off, c->nrange + 1));
   TRY(dalloc(&c->rbeg, c->nrange + 1));
   {
@@ -653,7 +654,6 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->rl_geo, 12 * c->nent_pad));
   TRY(dalloc(&c->rc_cnt, c->nrange + 1));
   TRY(dalloc(&c->rc_off, c->nrange + 1));
-  TRY(dalloc(&c->t_home, c->Tpad));
   if (cfg->hess_prec == MAS_F32) TRY(dalloc(&c->hr32, 4 * SNAP_NC32 * c->nent_pad));
   else TRY(dalloc(&c->hr64, EH * c->nent_pad));
   for (int l = 0; l < c->L; ++l) {
@@ -750,7 +750,6 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
 
   HIPCHK(hipMemcpyAsync(c->tets, tets.data(), 4 * T * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->tet_off, toff.data(), (D0 + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
-  HIPCHK(hipMemcpyAsync(c->tet_list, tlist.data(), tlist.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   HIPCHK(hipMemcpyAsync(c->rt_off, roff.data(), roff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->s));
   {
     // entries: tet id (home flag in bit 31) and its vertices
@@ -769,7 +768,16 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
       }
     HIPCHK(hipMemcpy(c->rl_t, et.data(), et.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->rl_tv, etv.data(), etv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->t_home, th.data(), th.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // level-0 records: the tet's vertices and its home entry side by side, so
+    // that the block assembly reads them without a chain of gathers
+    std::vector<int32_t> rtv(4 * tlist.size()), rh(tlist.size());
+    for (size_t w = 0; w < tlist.size(); ++w) {
+      const int64_t t = tlist[w];
+      for (int j = 0; j < 4; ++j) rtv[4 * w + j] = tets[4 * t + j];
+      rh[w] = th[t];
+    }
+    HIPCHK(hipMemcpy(c->l0_tv, rtv.data(), rtv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->l0_home, rh.data(), rh.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   double *dX = nullptr, *drho = nullptr, *dE = nullptr, *dnu = nullptr, *dmq = nullptr;
   int32_t *dvoff = nullptr, *dvt = nullptr;

@@ -336,8 +336,9 @@ struct Ctx {
   int32_t* tets = nullptr;     // 4T
   double* geo = nullptr;       // 12T: Dm^-1 (9, row-major), vol, mu, lam
   double* mass = nullptr;      // N
-  int32_t* tet_off = nullptr;  // D0+1, level-0 subdomain -> touching tets
-  int32_t* tet_list = nullptr;
+  int32_t* tet_off = nullptr;  // D0+1, level-0 subdomain d -> its tet records [tet_off[d], tet_off[d+1])
+  int32_t* l0_tv = nullptr;    // 4 per record: the vertices of a tet touching the subdomain
+  int32_t* l0_home = nullptr;  // per record: the range entry holding that tet's home snapshot copy
   int rmax = 0;                // largest range (vertices)
   int64_t nrange = 0;          // vertex ranges
   int32_t* rbeg = nullptr;     // nrange+1 range starts
@@ -351,8 +352,6 @@ struct Ctx {
   double* hr64 = nullptr;      // element snapshot per entry, float64 Hessian storage
   float* hr32 = nullptr;       // element snapshot per entry, float32 Hessian storage
 
-  // Hessian snapshot (AoSoA tiles of 64 tets: [Tpad/64][54][64])
-  int32_t* t_home = nullptr;   // T: range entry holding each tet's home copy (the block assembly reads it)
   bool built = false;
 
   // base contact set (capacity cfg.max_contacts, allocated at create)

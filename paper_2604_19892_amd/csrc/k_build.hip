@@ -196,13 +196,12 @@ __device__ inline void add_block_lds(double* A, int* Acnt, int pass, int li, int
 struct L0Args {
   int64_t N;
   int L;
-  const int32_t* tets;
   const double* mass;
-  const int32_t* t_home;  // tet -> its home range entry
   const float* h32;       // entry snapshots (one of the two is set)
   const double* h64;
-  const int32_t* tet_off;
-  const int32_t* tet_list;
+  const int32_t* tet_off;  // subdomain -> its tet records
+  const int32_t* l0_tv;    // per record: the tet's four vertices
+  const int32_t* l0_home;  // per record: the entry holding the tet's home snapshot
   const double* bk;
   const double* bgrad;
   const int32_t* bidx;
@@ -275,8 +274,7 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   __syncthreads();
   const int t0 = a.tet_off[d], t1 = a.tet_off[d + 1];
   for (int w = t0 + tid; w < t1; w += blockDim.x) {
-    const int64_t t = a.tet_list[w];
-    const int4 tv = reinterpret_cast<const int4*>(a.tets)[t];
+    const int4 tv = reinterpret_cast<const int4*>(a.l0_tv)[w];
     const int v[4] = {tv.x, tv.y, tv.z, tv.w};
     int dest[4][4], nbr[4][4];
     bool flip[4][4], need[4];
@@ -294,8 +292,8 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
     if (!(need[0] || need[1] || need[2] || need[3])) continue;
     constexpr int NH = sizeof(TH) == 8 ? EH : 4 * SNAP_NC32;
     TH H[NH];
-    if constexpr (sizeof(TH) == 8) snap_load<false>(a.h64, a.t_home[t], H);
-    else snap_load<false>(a.h32, a.t_home[t], H);
+    if constexpr (sizeof(TH) == 8) snap_load<false>(a.h64, a.l0_home[w], H);
+    else snap_load<false>(a.h32, a.l0_home[w], H);
     double coef[4][3];
     {
       double dm[9];
@@ -428,13 +426,12 @@ mas_status launch_level0_build(Ctx& c) {
   L0Args a{};
   a.N = c.N;
   a.L = c.L;
-  a.tets = c.tets;
   a.mass = c.mass;
-  a.t_home = c.t_home;
   a.h32 = c.hr32;
   a.h64 = c.hr64;
   a.tet_off = c.tet_off;
-  a.tet_list = c.tet_list;
+  a.l0_tv = c.l0_tv;
+  a.l0_home = c.l0_home;
   a.bk = c.bk;
   a.bgrad = c.bgrad;
   a.bidx = c.bidx;
