@@ -464,6 +464,15 @@ __device__ __forceinline__ void sw_flush(const double* win, double* y, int vbase
   }
 }
 
+// Orders the LDS accesses of one wavefront's lanes at this point: a
+// wavefront's LDS operations execute in program order, so it is enough that
+// the compiler moves no memory access across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wavefront aggregation of atomics: lanes whose key matches the lowest
 // pending lane's key combine their values (one shuffle reduction per
 // distinct key) and only that lane issues the atomic.  Every lane of the

@@ -263,7 +263,7 @@ __device__ __forceinline__ void gather_w(const unsigned char* As, const float* s
 
 // One workgroup per subdomain with rank r > 0: W = B_d U_d (96 x r), the
 // capacitance C = I + U_d^T W and its float64 Cholesky factor (right-looking,
-// the rank-one updates of each column spread over the workgroup).  Blocks
+// on the first wavefront).  Blocks
 // stored in 32 or 16 bits are staged in LDS, float64 blocks are read in
 // place; W, C and the slot columns live in dynamic LDS sized by K.
 constexpr size_t CAP_STAGE = blk_elems(MAS_F32) * 4;
@@ -273,7 +273,6 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
                                                      double* W, double* Lcap, uint32_t* err, DiagRec* dg) {
   __shared__ __align__(16) unsigned char As[CAP_STAGE];
   __shared__ float sig[BD];
-  __shared__ int bad;
   extern __shared__ __align__(16) double cdyn[];
   double(*Ws)[BD] = reinterpret_cast<double(*)[BD]>(cdyn);
   double* Cm = cdyn + K * BD;
@@ -294,7 +293,6 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
     if (tid < BD) sig[tid] = scale[d * BD + tid];
   }
   for (int q = tid; q < r; q += blockDim.x) sl[q] = slots[d * K + q];
-  if (tid == 0) bad = 0;
   __syncthreads();
   switch (P) {
     case MAS_F64: gather_w<MAS_F64>(src, sig, sl, r, Ws); break;
@@ -316,48 +314,48 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
     Cm[j * r + k] = acc;
   }
   __syncthreads();
-  // C = L L^T in place (lower triangle), float64.  Column j of L depends on
-  // the leading (j + 1) x (j + 1) part of C only, so a pivot that is not
-  // positive ends the factor there: the subdomain keeps its first j columns
-  // (the ones of largest dS) and the rank drops to j.
-  int rk = r;
-  for (int j = 0; j < r; ++j) {
-    if (tid == 0) {
-      const double djj = Cm[j * r + j];
+  // C = L L^T in place (lower triangle), float64, by the first wavefront
+  // alone (r <= K is small: the steps order themselves within the
+  // wavefront, no workgroup barrier) while the others write W.  Column j of
+  // L depends on the leading (j + 1) x (j + 1) part of C only, so a pivot
+  // that is not positive ends the factor there: the subdomain keeps its
+  // first j columns (the ones of largest dS) and the rank drops to j.
+  if (tid < 64) {
+    int rk = r;
+    for (int j = 0; j < r; ++j) {
+      const double djj = Cm[j * r + j];  // the same value in every lane
       if (!(djj > 0.0) || !isfinite(djj)) {
-        diag_report(dg, 3, 0, d, j, djj);
-        bad = 1;
-      } else {
-        Cm[j * r + j] = sqrt(djj);
+        if (tid == 0) diag_report(dg, 3, 0, d, j, djj);
+        rk = j;
+        break;
       }
+      const double ljj = sqrt(djj);
+      wave_sync();
+      for (int i = j + 1 + tid; i < r; i += 64) Cm[i * r + j] /= ljj;
+      if (tid == 0) Cm[j * r + j] = ljj;
+      wave_sync();
+      const int nr = r - j - 1;
+      for (int q = tid; q < nr * nr; q += 64) {
+        const int i = j + 1 + q / nr, k = j + 1 + q % nr;
+        if (k <= i) Cm[i * r + k] -= Cm[i * r + j] * Cm[k * r + j];
+      }
+      wave_sync();
     }
-    __syncthreads();
-    if (bad) {
-      rk = j;
-      break;
+    if (tid == 0 && rk < r) {
+      atomicOr(err, ERRB_RANK);
+      rank[d] = rk;
     }
-    const double ljj = Cm[j * r + j];
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) Cm[i * r + j] /= ljj;
-    __syncthreads();
-    const int nr = r - j - 1;
-    for (int q = tid; q < nr * nr; q += blockDim.x) {
-      const int i = j + 1 + q / nr, k = j + 1 + q % nr;
-      if (k <= i) Cm[i * r + k] -= Cm[i * r + j] * Cm[k * r + j];
+    double* L = Lcap + d * (K * (K + 1) / 2);
+    for (int q = tid; q < rk * rk; q += 64) {
+      const int i = q / rk, j = q % rk;
+      if (j <= i) L[pk(i, j)] = Cm[i * r + j];
     }
-    __syncthreads();
-  }
-  if (tid == 0 && bad) {
-    atomicOr(err, ERRB_RANK);
-    rank[d] = rk;
-  }
-  double* L = Lcap + d * (K * (K + 1) / 2);
-  for (int q = tid; q < rk * rk; q += blockDim.x) {
-    const int i = q / rk, j = q % rk;
-    if (j <= i) L[pk(i, j)] = Cm[i * r + j];
-  }
-  for (int q = tid; q < rk * BD; q += blockDim.x) {
-    int j = q / BD, i = q % BD;
-    W[(d * K + j) * BD + i] = Ws[j][i];
+  } else {
+    // all r columns (the apply reads only the first rank[d] of them)
+    for (int q = tid - 64; q < r * BD; q += blockDim.x - 64) {
+      const int j = q / BD, i = q % BD;
+      W[(d * K + j) * BD + i] = Ws[j][i];
+    }
   }
 }
 
