@@ -690,7 +690,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   TRY(dalloc(&c->ahalf, D0));
   TRY(dalloc(&c->around, SAFE_ROUNDS + 1));
   TRY(dalloc(&c->err, 1));
-  TRY(dalloc(&c->diag, 1));
+  TRY(dalloc(&c->diag, DIAG_SLOTS));
   // contact sets: capacity max_contacts, key table twice that (power of two)
   {
     const int64_t cap = std::max<int64_t>(c->cfg.max_contacts, 1);
@@ -743,7 +743,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
   c->scan_cap = std::max<int64_t>({D0 + 1, c->nrange + 1, c->cs[0].h_cap, c->cs[1].h_cap, N + 1});
   TRY(dalloc(&c->scan_tmp, scan_scratch_elems(c->scan_cap)));
   HIPCHK(hipMemsetAsync(c->err, 0, sizeof(uint32_t), c->s));
-  HIPCHK(hipMemsetAsync(c->diag, 0, sizeof(DiagRec), c->s));
+  HIPCHK(hipMemsetAsync(c->diag, 0, sizeof(DiagRec) * DIAG_SLOTS, c->s));
   HIPCHK(hipMemsetAsync(c->rank, 0, sizeof(int32_t) * D0, c->s));
   HIPCHK(hipMemsetAsync(c->alpha, 0, sizeof(double) * D0, c->s));
   HIPCHK(hipMemsetAsync(c->around, 0, sizeof(uint32_t) * (SAFE_ROUNDS + 1), c->s));
@@ -827,7 +827,6 @@ mas_status mas_build(void* p, const double* x_base, const mas_contacts* base) {
   if ((st = launch_elem_hessians(c, x_base)) != MAS_OK) return st;
   if ((st = launch_base_contacts(c, base)) != MAS_OK) return st;
   if ((st = launch_level0_build(c)) != MAS_OK) return st;
-  if ((st = launch_coarse_build(c)) != MAS_OK) return st;
   c.built = true;
   c.have_update = false;
   c.mc = 0;
@@ -1007,10 +1006,14 @@ mas_status mas_sync_status(void* p, char* msg, int32_t msg_len) {
     st = MAS_ERR_HIP;
   } else {
     uint32_t bits = 0;
+    DiagRec slots[DIAG_SLOTS];
     if (hipMemcpy(&bits, c.err, sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess) st = MAS_ERR_HIP;
-    if (hipMemcpy(&dg, c.diag, sizeof(dg), hipMemcpyDeviceToHost) != hipSuccess) st = MAS_ERR_HIP;
+    if (hipMemcpy(slots, c.diag, sizeof(slots), hipMemcpyDeviceToHost) != hipSuccess) st = MAS_ERR_HIP;
     hipMemset(c.err, 0, sizeof(uint32_t));
-    hipMemset(c.diag, 0, sizeof(DiagRec));
+    hipMemset(c.diag, 0, sizeof(slots));
+    // the lowest level that failed (its failures cause the ones above)
+    for (int q = 0; q < DIAG_SLOTS && !dg.flag; ++q)
+      if (slots[q].flag) dg = slots[q];
     if (bits & ERRB_NOT_SPD) st = MAS_ERR_NOT_SPD;
     else if (bits & ERRB_NONFINITE) st = MAS_ERR_NONFINITE;
     else if (bits & ERRB_RANK) st = MAS_ERR_RANK;

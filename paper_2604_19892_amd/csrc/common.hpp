@@ -258,8 +258,11 @@ __device__ inline void atomic_min_pos(double* a, double v) {
   atomicMin(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
 }
 
-// first device-side failure, written once (source: 1 level-0 build,
-// 2 coarse build, 3 capacitance)
+// first device-side failure of one source, written once (source: 1 level-0
+// build, 2 coarse build, 3 capacitance).  The context holds DIAG_SLOTS of
+// them: slot l for the blocks of level l, slot MAXL for the capacitance, so
+// that a failure of a level-0 block is reported before the coarse failures
+// it causes, whichever block reached its record first.
 struct DiagRec {
   uint32_t flag;
   int32_t source;
@@ -268,6 +271,8 @@ struct DiagRec {
   int64_t index;
   double value;
 };
+
+constexpr int DIAG_SLOTS = MAXL + 1;
 
 __device__ inline void diag_report(DiagRec* dg, int source, int level, int64_t index, int step,
                                    double value) {
@@ -413,7 +418,7 @@ struct Ctx {
   uint64_t* ahalf = nullptr;       // D0, bit r: subdomain halved in damping round r
   uint32_t* around = nullptr;      // SAFE_ROUNDS violation counts of the damping rounds
   uint32_t* err = nullptr;         // sticky error bits
-  DiagRec* diag = nullptr;         // first failure record
+  DiagRec* diag = nullptr;         // DIAG_SLOTS first-failure records
   mas_iter_stats* stats = nullptr; // per-iteration counters (device)
   // deterministic mode: vertex incidence lists of a stencil set (for
   // each vertex its (stencil, slot) pairs 4 c + j in ascending order) and

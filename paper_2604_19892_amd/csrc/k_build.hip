@@ -189,8 +189,8 @@ __device__ inline void add_block_lds(double* A, int* Acnt, int pass, int li, int
 // workgroup of the larger node takes it (the lower block).  Level 1's node is
 // d itself, so its row of blocks is complete here and written directly;
 // deeper levels are summed per workgroup in LDS and added with atomics.  The
-// diagonal node blocks come later, from the block sums taken while the level
-// below is inverted.  One thread per tet (or contact): it forms
+// diagonal node blocks come later: level 1's from the block sums taken while
+// level 0 is inverted, deeper ones from k_node_sums.  One thread per tet (or contact): it forms
 // G_j = Hf (c_j x I) once per vertex j and the 3x3 blocks c_i^T G_j of the
 // pairs it has to deliver.
 struct L0Args {
@@ -248,7 +248,7 @@ constexpr int L0_THREADS = 128;
 // the subdomains in ascending order by k_coup_reduce.
 template <typename TH, bool DET>
 __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
-  __shared__ double A[PK];
+  __shared__ __align__(16) double A[PK];
   extern __shared__ double T[];  // (L - 1) x 32 node blocks of 9; DET: then the counts of A and T
   const int64_t d = xcd_block(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
@@ -365,8 +365,13 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
     __syncthreads();
   }
   }  // passes
-  double* out = a.acc[0] + d * PK;
-  for (int e = tid; e < PK; e += blockDim.x) out[e] = A[e];
+  {
+    // 16-byte stores (PK is even, every block starts on 16 bytes), not
+    // kept in the caches: the inversion reads each block once
+    const double2* src2 = reinterpret_cast<const double2*>(A);
+    double2* out2 = reinterpret_cast<double2*>(a.acc[0] + d * PK);
+    for (int e = tid; e < PK / 2; e += blockDim.x) st_once(out2 + e, src2[e]);
+  }
   if (DET && a.L > 2) {
     // the deep-level tables of this subdomain, zeros included
     double* cp = a.coup + d * int64_t(nT - SUB * 9);
@@ -391,8 +396,57 @@ __global__ __launch_bounds__(L0_THREADS) void k_assemble_l0(L0Args a) {
   }
 }
 
-// Block inversion: k_invert.hip (FP64 MFMA, one wavefront per block).
-static void launch_invert(Ctx& c, int l) { launch_invert_mfma(c, l); }
+// Level l >= 2: the diagonal node block of node s (subdomain s of level
+// l - 1) is the sum of all 3x3 node blocks of that subdomain's block, both
+// triangles, rows of real nodes only (C_(l) sums the nodes of s).  One
+// workgroup per subdomain reads the packed block (entry e = tid + 256 k is
+// (i, j), tracked from one to the next) and keeps the sum
+// as W + W^T: entry (i, j < i) adds to W[3 (i mod 3) + j mod 3], a diagonal
+// entry half of itself.
+constexpr int NS_T = 256;
+__global__ __launch_bounds__(NS_T) void k_node_sums(int64_t nodes_prev, const double* acc_prev, double* acc_l) {
+  __shared__ double red[NS_T / 64][9];
+  const int64_t s = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nv = 3 * int(min<int64_t>(SUB, nodes_prev - SUB * s));
+  const double* A = acc_prev + s * PK;
+  double W[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) W[t] = 0.0;
+  // every load first (they are independent), then the bins
+  constexpr int NE = (PK + NS_T - 1) / NS_T;
+  double vals[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) vals[k] = tid + NS_T * k < PK ? A[tid + NS_T * k] : 0.0;
+  int i = 0, j = tid;
+  while (j > i) j -= ++i;
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    if (i < nv) {
+      const double val = vals[k];
+      const int k9 = 3 * (i % 3) + j % 3;
+      const double wv = j == i ? 0.5 * val : val;
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        if (k9 == t) W[t] += wv;
+    }
+    j += NS_T;
+    while (j > i && i < BD) j -= ++i;
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const double v = wave_sum(W[t]);
+    if ((tid & 63) == 0) red[tid >> 6][t] = v;
+  }
+  __syncthreads();
+  if (tid < 9 && tid / 3 >= tid % 3) {
+    const int x = tid / 3, y = tid % 3;
+    double sum = 0.0;
+    for (int w = 0; w < NS_T / 64; ++w) sum += red[w][3 * x + y] + red[w][3 * y + x];
+    const int ln = int(s & 31);
+    acc_l[(s >> 5) * PK + pk(3 * ln + x, 3 * ln + y)] = sum;
+  }
+}
 
 __global__ void k_zero(double* p, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -459,16 +513,13 @@ mas_status launch_level0_build(Ctx& c) {
       k_assemble_l0<double, false><<<dim3(L0.nsub), dim3(L0_THREADS), lds, c.s>>>(a);
   }
   if (c.cfg.precond == MAS_PRECOND_BJ3) return launch_bj_build(c);  // no MAS level is inverted
-  launch_invert(c, 0);
-  HIPCHK(hipGetLastError());
-  return MAS_OK;
-}
-
-// the coarse levels, in order: inverting level l completes the diagonal node
-// blocks of level l + 1
-mas_status launch_coarse_build(Ctx& c) {
-  if (c.cfg.precond == MAS_PRECOND_BJ3) return MAS_OK;
-  for (int l = 1; l < c.L; ++l) launch_invert(c, l);
+  // level 0, whose inversion completes level 1's diagonal node blocks; the
+  // deeper diagonal node blocks are sums over the level below; then every
+  // coarse level in one launch (their blocks are few, each a long chain)
+  launch_invert_mfma(c, 0, 1, c.L > 1 ? c.lv[1].acc : nullptr);
+  for (int l = 2; l < c.L; ++l)
+    k_node_sums<<<dim3(c.lv[l - 1].nsub), dim3(NS_T), 0, c.s>>>(c.lv[l - 1].nodes, c.lv[l - 1].acc, c.lv[l].acc);
+  if (c.L > 1) launch_invert_mfma(c, 1, c.L, nullptr);
   HIPCHK(hipGetLastError());
   return MAS_OK;
 }

@@ -275,29 +275,43 @@ __device__ __forceinline__ void factor_all(Factor& f, int c, int q) {
 
 // One wavefront per block, two wavefronts per SIMD (the 21 tiles need about
 // 170 of a wave's 256 registers; the compiler keeps the rest of the working
-// set within the limit with a few hundred bytes of spills, which stay in the
-// caches: 1.44 ms instead of 1.92 ms at one wave per SIMD for the 35,625
-// level-0 blocks of the puffer scene, the second wave issuing while the
-// first waits on its lane exchanges).  acc: the packed lower float64 blocks of the
-// level (rows and columns of nodes beyond the node count are identity).
-// Stored in the requested precision, or a wider one when
+// set within the limit with a few hundred bytes of spills outside the sweep,
+// which stay in the caches: 1.44 ms instead of 1.92 ms at one wave per SIMD
+// for the 35,625 level-0 blocks of the puffer scene, the second wave issuing
+// while the first waits on its lane exchanges).  One launch covers the
+// levels [lo, hi), the highest first.  acc: the packed lower float64 blocks
+// of each level (rows and columns of nodes beyond the node count are
+// identity).  Stored in the requested precision, or a wider one when
 // kappa = max_i M_ii B_ii exceeds guard / (20 eps) (the spectral norm of the
 // rounding error of a unit-diagonal 96x96 matrix is about 20 eps, and
 // 1/kappa bounds its smallest eigenvalue from above).  With acc_next, the
 // sum of all 3x3 node blocks of the block (before inversion) becomes the
 // diagonal block of node d at the next level (C_(l+1) sums the nodes of d).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_invert_mfma(int64_t nodes, const double* acc, void* blk, float* scale,
-                                                    uint8_t* bprec, int req, double guard, uint32_t* err,
-                                                    DiagRec* dg, int level, double* acc_next) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_invert_mfma(InvLevels iv, double guard,
+                                                                                             uint32_t* err, DiagRec* dg) {
   // transposes during the steps; the stored image of a 32- or 16-bit block
   // at the end
   __shared__ __align__(16) double lds[IMG_DOUBLES];
   double(*tb)[16 * TPAD] = reinterpret_cast<double(*)[16 * TPAD]>(lds);
   __shared__ double sc[BD];
   __shared__ float sig[BD];
-  const int64_t d = blockIdx.x;
+  // block -> (level, subdomain): levels hi - 1, ..., lo
+  int level = iv.lo;
+  int64_t d = blockIdx.x;
+  for (int q = iv.hi - 1; q > iv.lo; --q) {
+    if (d < iv.nsub[q]) {
+      level = q;
+      break;
+    }
+    d -= iv.nsub[q];
+  }
+  const int64_t nodes = iv.nodes[level];
+  const int req = iv.prec[level];
+  uint8_t* bprec = iv.bprec[level];
+  float* scale = iv.scale[level];
+  double* acc_next = iv.acc_next;
   const int l = threadIdx.x, c = l & 15, q = l >> 4;
-  const double* src = acc + d * PK;
+  const double* src = iv.acc[level] + d * PK;
   const int nv = 3 * int(min<int64_t>(SUB, nodes - SUB * d));  // rows of real nodes
   d4 T[6][6];
   // node-bin sums of the raw block: row bin (a + v + q) mod 3, column bin
@@ -376,7 +390,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   sweep_step<5>(T, G, tb, c, q, &bad, &badv);
   if (bad >= 0 && l == 0) {
     atomicOr(err, ERRB_NOT_SPD);
-    diag_report(dg, level == 0 ? 1 : 2, level, d, bad, badv);
+    diag_report(dg + level, level == 0 ? 1 : 2, level, d, bad, badv);
   }
   // T = S^-1 of the scaled block S; kappa = max_i of its diagonal
   double kap = 0.0;
@@ -390,7 +404,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   while (guard > 0.0 && P != MAS_F64 && !(kap <= guard / (20.0 * prec_eps(P))))
     P = (P == MAS_F32) ? MAS_F64 : MAS_F32;
   if (l == 0) bprec[d] = uint8_t(P);
-  unsigned char* slot = reinterpret_cast<unsigned char*>(blk) + d * BLK_STRIDE;
+  unsigned char* slot = reinterpret_cast<unsigned char*>(iv.blk[level]) + d * BLK_STRIDE;
   if (P == MAS_BF16 || P == MAS_F16) {
     // sig_i = sqrt(B_ii), B_ii = T_ii sc_i^2
 #pragma unroll
@@ -424,11 +438,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   for (int k = l; k < n16; k += 64) st_once(dst4 + k, src4[k]);
 }
 
-void launch_invert_mfma(Ctx& c, int l) {
-  Level& Lv = c.lv[l];
-  k_invert_mfma<<<dim3(Lv.nsub), dim3(64), 0, c.s>>>(Lv.nodes, Lv.acc, Lv.blk, Lv.scale, Lv.bprec, Lv.prec,
-                                                    c.cfg.prec_guard, c.err, c.diag, l,
-                                                    l + 1 < c.L ? c.lv[l + 1].acc : nullptr);
+void launch_invert_mfma(Ctx& c, int lo, int hi, double* acc_next) {
+  InvLevels iv{};
+  iv.lo = lo;
+  iv.hi = hi;
+  iv.acc_next = acc_next;
+  int64_t nb = 0;
+  for (int l = lo; l < hi; ++l) {
+    const Level& Lv = c.lv[l];
+    iv.nsub[l] = Lv.nsub;
+    iv.nodes[l] = Lv.nodes;
+    iv.acc[l] = Lv.acc;
+    iv.blk[l] = Lv.blk;
+    iv.scale[l] = Lv.scale;
+    iv.bprec[l] = Lv.bprec;
+    iv.prec[l] = Lv.prec;
+    nb += Lv.nsub;
+  }
+  if (nb > 0) k_invert_mfma<<<dim3(nb), dim3(64), 0, c.s>>>(iv, c.cfg.prec_guard, c.err, c.diag);
 }
 
 }  // namespace mas

@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_capacitance(int K, const void* blk, con
     for (int j = 0; j < r; ++j) {
       const double djj = Cm[j * r + j];  // the same value in every lane
       if (!(djj > 0.0) || !isfinite(djj)) {
-        if (tid == 0) diag_report(dg, 3, 0, d, j, djj);
+        if (tid == 0) diag_report(dg + MAXL, 3, 0, d, j, djj);
         rk = j;
         break;
       }

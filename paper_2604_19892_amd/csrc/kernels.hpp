@@ -29,9 +29,21 @@ void fill_i32(Ctx& c, int32_t* p, int64_t n, int32_t v);
 void fill_f64(Ctx& c, double* p, int64_t n, double v);
 
 // k_invert.hip ---------------------------------------------------------
-// inverts the blocks of level l (FP64 MFMA) and stores them in their
-// chosen precision; completes the next level's diagonal node blocks
-void launch_invert_mfma(Ctx& c, int l);
+// the blocks of the levels [lo, hi), for one inversion launch
+struct InvLevels {
+  int lo, hi;
+  int64_t nsub[MAXL], nodes[MAXL];
+  const double* acc[MAXL];
+  void* blk[MAXL];
+  float* scale[MAXL];
+  uint8_t* bprec[MAXL];
+  int prec[MAXL];
+  double* acc_next;  // when set, the node-block sums of each block go there
+};
+// inverts the assembled blocks of the levels [lo, hi) (FP64 MFMA) in one
+// launch and stores them in their chosen precision; with acc_next (a launch
+// of one level l), completes the diagonal node blocks of level l + 1
+void launch_invert_mfma(Ctx& c, int lo, int hi, double* acc_next);
 
 // k_setup.hip ----------------------------------------------------------
 mas_status launch_rest(Ctx& c, const double* X, const double* rho, const double* E, const double* nu,
@@ -44,8 +56,8 @@ mas_status launch_stencil_distance(Ctx& c, const double* x, int64_t m, const int
 // k_build.hip ----------------------------------------------------------
 mas_status launch_elem_hessians(Ctx& c, const double* x_base);
 mas_status launch_base_contacts(Ctx& c, const mas_contacts* b);
+// the blocks of every level: assembly, coarse diagonal node blocks, inversion
 mas_status launch_level0_build(Ctx& c);
-mas_status launch_coarse_build(Ctx& c);
 
 // k_woodbury.hip -------------------------------------------------------
 mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist);
