@@ -369,8 +369,8 @@ mas_status mas_destroy(void* p) {
   hipStreamSynchronize(c->s);
   void* ptrs[] = {c->tets, c->geo, c->mass, c->tet_off, c->l0_tv, c->l0_home, c->rt_off, c->rbeg, c->vrange, c->ctr, c->rl_t, c->rl_tv,
                   c->rl_geo, c->hr64, c->hr32, c->rc_cnt, c->rc_off, c->rc_list, c->bkey,
-                  c->hkey, c->hval, c->bk, c->bgrad, c->bidx, c->bu, c->bc_cnt,
-                  c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->ckey, c->cand_cnt, c->cand_off,
+                  c->hkey, c->hval, c->bk, c->bpm, c->bgrad, c->bidx, c->bu, c->bc_cnt,
+                  c->bc_off, c->bc_list, c->U, c->Uidx, c->dS, c->upm, c->ckey, c->cand_cnt, c->cand_off,
                   c->cand_list, c->rank, c->sel, c->slots, c->W, c->Lcap, c->partials, c->scal,
                   c->alpha, c->alpha0, c->alpha_mix, c->ahalf, c->around, c->err, c->diag, c->cls_part, c->scan_tmp,
                   c->inc_cnt, c->inc_off, c->inc_list, c->coup, c->bj, c->bjinv, c->seg, c->scene_r, c->sc_acc};
@@ -701,6 +701,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     TRY(dalloc(&c->hkey, c->hcap));
     TRY(dalloc(&c->hval, c->hcap));
     TRY(dalloc(&c->bk, cap));
+    TRY(dalloc(&c->bpm, cap));
     TRY(dalloc(&c->bgrad, 12 * cap));
     TRY(dalloc(&c->bidx, 4 * cap));
     TRY(dalloc(&c->bu, 12 * cap));
@@ -709,6 +710,7 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     TRY(dalloc(&c->U, 12 * cap));
     TRY(dalloc(&c->Uidx, 4 * cap));
     TRY(dalloc(&c->dS, cap));
+    TRY(dalloc(&c->upm, cap));
     TRY(dalloc(&c->ckey, cap));
     TRY(dalloc(&c->cand_list, 4 * cap));
     TRY(dalloc(&c->cls_part, 5 * ((cap + 255) / 256)));
@@ -808,8 +810,8 @@ mas_status mas_create(const mas_config* cfg, const mas_mesh* mesh, void* hip_str
     return st;
   }
   // empty bucket lists until the first build
-  TRY(bucket_by_subdomain(*c, 0, nullptr, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
-  TRY(bucket_stencils(*c, 1, c->vrange, c->nrange, 0, nullptr, nullptr, nullptr, c->rc_cnt, c->rc_off, nullptr));
+  TRY(bucket_by_subdomain(*c, 0, nullptr, nullptr, c->bc_cnt, c->bc_off, nullptr));
+  TRY(bucket_stencils(*c, 1, c->vrange, c->nrange, 0, nullptr, nullptr, c->rc_cnt, c->rc_off, nullptr));
   HIPCHK(hipStreamSynchronize(c->s));
   if (perm_out) std::memcpy(perm_out, perm.data(), N * sizeof(int32_t));
   *ctx_out = c;

@@ -258,6 +258,16 @@ __device__ inline void atomic_min_pos(double* a, double v) {
   atomicMin(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v));
 }
 
+// Bit j set when vertex j of a stencil carries a nonzero part of its
+// 12-vector u (the bucket passes then read one byte instead of u).
+__device__ inline uint8_t part_mask(const double (&u)[12]) {
+  uint8_t pm = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (u[3 * j] != 0.0 || u[3 * j + 1] != 0.0 || u[3 * j + 2] != 0.0) pm |= uint8_t(1u << j);
+  return pm;
+}
+
 // first device-side failure of one source, written once (source: 1 level-0
 // build, 2 coarse build, 3 capacitance).  The context holds DIAG_SLOTS of
 // them: slot l for the blocks of level l, slot MAXL for the capacitance, so
@@ -367,6 +377,7 @@ struct Ctx {
   int64_t hcap = 0;                // allocated slots: a power of two, at least twice max_contacts
   int64_t hsize = 1024;            // slots in use: a power of two, at least twice the base contacts
   double* bk = nullptr;            // mb stiffness
+  uint8_t* bpm = nullptr;          // mb: bit j set when vertex j carries a nonzero part of bgrad and k > 0
   double* bgrad = nullptr;         // 12 mb
   int32_t* bidx = nullptr;         // 4 mb
   double* bu = nullptr;            // 12 mb, sqrt(k) n
@@ -383,6 +394,7 @@ struct Ctx {
   double* U = nullptr;             // 12 mc
   int32_t* Uidx = nullptr;         // 4 mc
   double* dS = nullptr;            // mc
+  uint8_t* upm = nullptr;          // mc: bit j set when vertex j carries a nonzero part of U (dS > 0)
   uint64_t* ckey = nullptr;        // mc
   int32_t* cand_cnt = nullptr;     // D0
   int32_t* cand_off = nullptr;     // D0+1

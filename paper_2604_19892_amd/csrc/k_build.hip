@@ -71,7 +71,7 @@ mas_status launch_elem_hessians(Ctx& c, const double* x_base) {
 // wavefront in 64-element strides so that every store is contiguous.
 __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* key, const int32_t* idx,
                                                    const double* d, const double* grad, double kappa, double dhat,
-                                                   uint64_t* bkey, double* bk, double* bgrad,
+                                                   uint64_t* bkey, double* bk, uint8_t* bpm, double* bgrad,
                                                    int32_t* bidx, double* bu, uint32_t* err) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -88,6 +88,14 @@ __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* ke
     sk = sqrt(k);
 #pragma unroll
     for (int q = 0; q < 4; ++q) bidx[4 * i + q] = idx[4 * i + q];
+    uint8_t pm = 0;
+    if (k > 0.0) {
+      double u[12];  // the wavefront's rows, read again below through the cache
+#pragma unroll
+      for (int q = 0; q < 12; ++q) u[q] = grad[12 * i + q];
+      pm = part_mask(u);
+    }
+    bpm[i] = pm;
   }
   const int64_t n12 = 12 * (min<int64_t>(m, w0 + 64) - w0);
 #pragma unroll
@@ -142,16 +150,16 @@ mas_status launch_base_contacts(Ctx& c, const mas_contacts* b) {
   if (m > 0) {
     int bs = 256;
     k_base_copy<<<dim3((m + bs - 1) / bs), dim3(bs), 0, c.s>>>(
-        m, b->key, b->idx, b->d, b->grad, c.cfg.kappa, c.cfg.dhat, c.bkey, c.bk, c.bgrad,
+        m, b->key, b->idx, b->d, b->grad, c.cfg.kappa, c.cfg.dhat, c.bkey, c.bk, c.bpm, c.bgrad,
         c.bidx, c.bu, c.err);
     k_fill_u64<<<dim3(std::min<int64_t>(1024, (c.hsize + 255) / 256)), dim3(256), 0, c.s>>>(c.hkey, c.hsize,
                                                                                              HKEY_EMPTY);
     k_hash_insert<<<dim3((m + 255) / 256), dim3(256), 0, c.s>>>(m, c.bkey, c.bk, c.hkey, c.hval, c.hsize - 1);
     HIPCHK(hipGetLastError());
   }
-  st = bucket_by_subdomain(c, m, c.bidx, c.bk, c.bgrad, c.bc_cnt, c.bc_off, c.bc_list);
+  st = bucket_by_subdomain(c, m, c.bidx, c.bpm, c.bc_cnt, c.bc_off, c.bc_list);
   if (st != MAS_OK) return st;
-  return bucket_stencils(c, 1, c.vrange, c.nrange, m, c.bidx, c.bk, c.bgrad, c.rc_cnt, c.rc_off, c.rc_list);
+  return bucket_stencils(c, 1, c.vrange, c.nrange, m, c.bidx, c.bpm, c.rc_cnt, c.rc_off, c.rc_list);
 }
 
 // ---------------------------------------------------------------------------

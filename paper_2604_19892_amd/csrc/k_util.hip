@@ -6,18 +6,19 @@
 
 namespace mas {
 
-// buckets (map ? map[v] : v / div) of the vertices of stencil i (w[i] > 0)
-// whose part of vec12 is nonzero; returns the count and writes them to out[4]
-__device__ inline int stencil_buckets(int div, const int32_t* map, int64_t i, const int32_t* idx, const double* w,
-                                      const double* vec12, int out[4]) {
+// buckets (map ? map[v] : v / div) of the vertices j of stencil i with bit j
+// of pm[i] set; returns the count and writes them to out[4]
+__device__ inline int stencil_buckets(int div, const int32_t* map, int64_t i, const int32_t* idx, const uint8_t* pm,
+                                      int out[4]) {
   int n = 0;
-  if (!(w[i] > 0.0)) return 0;
+  const unsigned mask = pm[i];
+  if (mask == 0u) return 0;
+  const int4 iv = reinterpret_cast<const int4*>(idx)[i];
+  const int vi[4] = {iv.x, iv.y, iv.z, iv.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int v = idx[4 * i + j];
-    if (v < 0) continue;
-    const double* u = vec12 + 12 * i + 3 * j;
-    if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0) continue;
+    const int v = vi[j];
+    if (v < 0 || !((mask >> j) & 1u)) continue;
     const int d = map ? map[v] : v / div;
     bool dup = false;
     for (int q = 0; q < n; ++q) dup |= (out[q] == d);
@@ -47,7 +48,7 @@ __device__ inline int bk_slot(int* hkey, int key) {
 }
 
 __global__ __launch_bounds__(BK_T) void k_bucket_count(int div, const int32_t* map, int64_t m, const int32_t* idx,
-                                                       const double* w, const double* vec12, int32_t* cnt) {
+                                                       const uint8_t* pm, int32_t* cnt) {
   __shared__ int hkey[BK_HASH];
   __shared__ int hcnt[BK_HASH];
   for (int q = threadIdx.x; q < BK_HASH; q += BK_T) {
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(int div, const int32_t* m
   __syncthreads();
   const int64_t i = blockIdx.x * int64_t(BK_T) + threadIdx.x;
   int b[4];
-  const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
+  const int n = (i < m) ? stencil_buckets(div, map, i, idx, pm, b) : 0;
   for (int q = 0; q < n; ++q) atomicAdd(&hcnt[bk_slot(hkey, b[q])], 1);
   __syncthreads();
   for (int q = threadIdx.x; q < BK_HASH; q += BK_T)
@@ -65,8 +66,7 @@ __global__ __launch_bounds__(BK_T) void k_bucket_count(int div, const int32_t* m
 }
 
 __global__ __launch_bounds__(BK_T) void k_bucket_fill(int div, const int32_t* map, int64_t m, const int32_t* idx,
-                                                      const double* w, const double* vec12, int32_t* cursor,
-                                                      int32_t* list) {
+                                                      const uint8_t* pm, int32_t* cursor, int32_t* list) {
   __shared__ int hkey[BK_HASH];
   __shared__ int hcnt[BK_HASH];
   for (int q = threadIdx.x; q < BK_HASH; q += BK_T) {
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(BK_T) void k_bucket_fill(int div, const int32_t* ma
   __syncthreads();
   const int64_t i = blockIdx.x * int64_t(BK_T) + threadIdx.x;
   int b[4], slot[4], rank[4];
-  const int n = (i < m) ? stencil_buckets(div, map, i, idx, w, vec12, b) : 0;
+  const int n = (i < m) ? stencil_buckets(div, map, i, idx, pm, b) : 0;
   for (int q = 0; q < n; ++q) {
     slot[q] = bk_slot(hkey, b[q]);
     rank[q] = atomicAdd(&hcnt[slot[q]], 1);
@@ -196,16 +196,16 @@ mas_status exclusive_scan_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n
   return MAS_OK;
 }
 
-mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
-                           const double* vec12, int32_t* cnt, int32_t* off, int32_t* list) {
+mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx,
+                           const uint8_t* pm, int32_t* cnt, int32_t* off, int32_t* list) {
   fill_i32(c, cnt, D + 1, 0);
-  if (m > 0) k_bucket_count<<<dim3((m + BK_T - 1) / BK_T), dim3(BK_T), 0, c.s>>>(div, map, m, idx, w, vec12, cnt);
+  if (m > 0) k_bucket_count<<<dim3((m + BK_T - 1) / BK_T), dim3(BK_T), 0, c.s>>>(div, map, m, idx, pm, cnt);
   mas_status st = exclusive_scan_i32(c, cnt, off, D + 1);
   if (st != MAS_OK) return st;
   if (m > 0) {
     // reuse cnt as the fill cursor
     k_copy_i32<<<dim3(std::min<int64_t>((D + 255) / 256, 4096)), dim3(256), 0, c.s>>>(off, cnt, D);
-    k_bucket_fill<<<dim3((m + BK_T - 1) / BK_T), dim3(BK_T), 0, c.s>>>(div, map, m, idx, w, vec12, cnt, list);
+    k_bucket_fill<<<dim3((m + BK_T - 1) / BK_T), dim3(BK_T), 0, c.s>>>(div, map, m, idx, pm, cnt, list);
   }
   HIPCHK(hipGetLastError());
   return MAS_OK;
@@ -262,9 +262,9 @@ mas_status build_incidence(Ctx& c, int64_t m, const int32_t* idx, const double* 
   return MAS_OK;
 }
 
-mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
-                               int32_t* cnt, int32_t* off, int32_t* list) {
-  return bucket_stencils(c, SUB, nullptr, c.lv[0].nsub, m, idx, w, vec12, cnt, off, list);
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const uint8_t* pm, int32_t* cnt,
+                               int32_t* off, int32_t* list) {
+  return bucket_stencils(c, SUB, nullptr, c.lv[0].nsub, m, idx, pm, cnt, off, list);
 }
 
 }  // namespace mas

@@ -29,7 +29,8 @@ __global__ __launch_bounds__(CLS_T) void k_classify(int64_t m, const uint64_t* k
                                                     double cos_rot, int64_t mb, const uint64_t* bkey,
                                                     const uint64_t* hkey, const int32_t* hval, int64_t hmask,
                                                     const double* bk, const double* bgrad, double* U, int32_t* Uidx,
-                                                    double* dS, uint64_t* ckey, uint32_t* err, int32_t* part) {
+                                                    double* dS, uint8_t* upm, uint64_t* ckey, uint32_t* err,
+                                                    int32_t* part) {
   __shared__ int cnt[5];
   if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(CLS_T) void k_classify(int64_t m, const uint64_t* k
     reinterpret_cast<int4*>(Uidx)[i] = reinterpret_cast<const int4*>(idx)[i];
     if (!(k > 0.0)) {
       dS[i] = 0.0;  // the column is zero and is not stored: readers test dS first
+      upm[i] = 0;
     } else {
       double n[12];
 #pragma unroll
@@ -91,11 +93,18 @@ __global__ __launch_bounds__(CLS_T) void k_classify(int64_t m, const uint64_t* k
       }
       if (!(s > 0.0)) s = 0.0;
       dS[i] = s;
+      uint8_t pm = 0;
       if (s > 0.0) {
         const double sq = sqrt(s);
+        double u[12];
 #pragma unroll
-        for (int q = 0; q < 12; ++q) U[12 * i + q] = sq * n[q];
+        for (int q = 0; q < 12; ++q) {
+          u[q] = sq * n[q];
+          U[12 * i + q] = u[q];
+        }
+        pm = part_mask(u);
       }
+      upm[i] = pm;
     }
   }
   if (part) {
@@ -369,7 +378,7 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
   if (m > 0) {
     k_classify<<<dim3(c.cls_blocks), dim3(CLS_T), 0, c.s>>>(
         m, cur->key, cur->idx, cur->d, cur->grad, c.cfg.kappa, c.cfg.dhat, c.cfg.cos_rot, c.mb,
-        c.bkey, c.hkey, c.hval, c.hsize - 1, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.ckey, c.err, c.cls_part);
+        c.bkey, c.hkey, c.hval, c.hsize - 1, c.bk, c.bgrad, c.U, c.Uidx, c.dS, c.upm, c.ckey, c.err, c.cls_part);
     HIPCHK(hipGetLastError());
   }
   const int64_t D = c.lv[0].nsub;
@@ -381,7 +390,7 @@ mas_status launch_woodbury(Ctx& c, const mas_contacts* cur, int32_t* rank_hist) 
     }
     return launch_bj_update(c, m);
   }
-  st = bucket_by_subdomain(c, m, c.Uidx, c.dS, c.U, c.cand_cnt, c.cand_off, c.cand_list);
+  st = bucket_by_subdomain(c, m, c.Uidx, c.upm, c.cand_cnt, c.cand_off, c.cand_list);
   if (st != MAS_OK) return st;
   if (rank_hist) fill_i32(c, rank_hist, c.K + 1, 0);
   if (c.K == 0) {

@@ -6,13 +6,14 @@
 namespace mas {
 
 // k_util.hip -----------------------------------------------------------
-// Buckets stencils (w[i] > 0) into per-level-0-subdomain lists: the distinct
-// subdomains (v >> 5) of its vertices whose part of vec12 is nonzero.
-mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const double* w, const double* vec12,
-                               int32_t* cnt, int32_t* off, int32_t* list);
+// Buckets stencils into per-level-0-subdomain lists: the distinct
+// subdomains (v >> 5) of the vertices j with bit j of pm[i] set (part_mask
+// of the stencil's 12-vector, zero for a stencil left out).
+mas_status bucket_by_subdomain(Ctx& c, int64_t m, const int32_t* idx, const uint8_t* pm, int32_t* cnt,
+                               int32_t* off, int32_t* list);
 // the same into D buckets map[v] (map non-null) or v / div
-mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx, const double* w,
-                           const double* vec12, int32_t* cnt, int32_t* off, int32_t* list);
+mas_status bucket_stencils(Ctx& c, int div, const int32_t* map, int64_t D, int64_t m, const int32_t* idx,
+                           const uint8_t* pm, int32_t* cnt, int32_t* off, int32_t* list);
 
 // deterministic mode: per-vertex incidence lists (c.inc_off, c.inc_list) of
 // the stencils with w[c] > 0 (all when w is null), each list ascending
