@@ -162,33 +162,51 @@ __global__ __launch_bounds__(EGT) void k_eg_range(int64_t nrange, const int32_t*
   }
 }
 
+// LDS hash of the far side of a chunk's contacts: slot of vertex v (linear
+// probing, at most FAR_PROBES probes), or -1 when the table is too full
+constexpr int FAR_SLOTS = 1024;
+constexpr int FAR_PROBES = 16;
+__device__ inline int far_slot(int* hk, int v) {
+  int h = int((uint32_t(v) * 2654435761u) >> 22) & (FAR_SLOTS - 1);
+  for (int p = 0; p < FAR_PROBES; ++p) {
+    const int old = atomicCAS(&hk[h], -1, v);
+    if (old == -1 || old == v) return h;
+    h = (h + 1) & (FAR_SLOTS - 1);
+  }
+  return -1;
+}
+
 // kappa b(d) and kappa b'(d) grad d; a non-positive distance flags +inf.
 // Chunks of SW_CHUNK stencils scatter through an LDS window (stencils sorted
-// by smallest vertex stay local).
+// by smallest vertex stay local) and, for the vertices outside it (a
+// contact's other side lies far away in the vertex order), an LDS hash
+// table that is added to g once per distinct vertex.
 __global__ __launch_bounds__(RB) void k_eg_contacts(int64_t N, int64_t m, const int32_t* idx, const double* d,
                                                     const double* grad, double kappa, double dhat, double* g,
                                                     double* part, int nblk) {
   __shared__ double win[3 * SW_WIN];
-  __shared__ double win2[3 * SW_WIN];
+  __shared__ int hk[FAR_SLOTS];
+  __shared__ double hv[3 * FAR_SLOTS];
   double e[2] = {0.0, 0.0};
   const bool gr = g != nullptr;
   for (int64_t chunk = blockIdx.x; chunk * SW_CHUNK < m; chunk += nblk) {
     const int64_t c0 = chunk * SW_CHUNK;
-    // two windows: from the smallest vertex of the chunk's first stencil,
-    // and around its largest one (a contact's two sides lie far apart in
-    // the vertex order); vertices in neither go to memory
-    int vbase, vbase2;
+    // the window starts at the smallest vertex of the chunk's first stencil
+    int vbase;
     {
       const int4 f4 = reinterpret_cast<const int4*>(idx)[c0];
-      int mn = INT32_MAX, mx = -1;
+      int mn = INT32_MAX;
       const int fv[4] = {f4.x, f4.y, f4.z, f4.w};
       for (int j = 0; j < 4; ++j)
-        if (fv[j] >= 0) mn = min(mn, fv[j]), mx = max(mx, fv[j]);
+        if (fv[j] >= 0) mn = min(mn, fv[j]);
       vbase = (mn == INT32_MAX) ? 0 : mn;
-      vbase2 = max(vbase + SW_WIN, mx - SW_WIN / 4);
     }
     if (gr) {
-      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0, win2[q] = 0.0;
+      for (int q = threadIdx.x; q < 3 * SW_WIN; q += RB) win[q] = 0.0;
+      for (int q = threadIdx.x; q < FAR_SLOTS; q += RB) {
+        hk[q] = -1;
+        hv[3 * q] = hv[3 * q + 1] = hv[3 * q + 2] = 0.0;
+      }
       __syncthreads();
     }
     for (int k = 0; k < SW_CHUNK; k += RB) {
@@ -210,14 +228,18 @@ __global__ __launch_bounds__(RB) void k_eg_contacts(int64_t N, int64_t m, const 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (vi[j] < 0) continue;
+          const int lv = vi[j] - vbase;
+          const bool near = lv >= 0 && lv < SW_WIN;
+          const int fs = near ? -1 : far_slot(hk, vi[j]);
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const double val = s * grad[12 * i + 3 * j + a];
-            const int l2 = vi[j] - vbase2;
-            if (l2 >= 0 && l2 < SW_WIN)
-              __hip_atomic_fetch_add(&win2[3 * l2 + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (near)
+              __hip_atomic_fetch_add(&win[3 * lv + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else if (fs >= 0)
+              __hip_atomic_fetch_add(&hv[3 * fs + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             else
-              sw_add(win, g, vbase, vi[j], a, val);
+              __hip_atomic_fetch_add(&g[3 * int64_t(vi[j]) + a], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       }
@@ -225,7 +247,13 @@ __global__ __launch_bounds__(RB) void k_eg_contacts(int64_t N, int64_t m, const 
     if (gr) {
       __syncthreads();
       sw_flush(win, g, vbase, N);
-      sw_flush(win2, g, vbase2, N);
+      for (int q = threadIdx.x; q < FAR_SLOTS; q += RB) {
+        const int v = hk[q];
+        if (v < 0) continue;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if (hv[3 * q + a] != 0.0) atomicAdd(&g[3 * int64_t(v) + a], hv[3 * q + a]);
+      }
       __syncthreads();
     }
   }
