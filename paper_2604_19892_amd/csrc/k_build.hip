@@ -88,15 +88,13 @@ __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* ke
     sk = sqrt(k);
 #pragma unroll
     for (int q = 0; q < 4; ++q) bidx[4 * i + q] = idx[4 * i + q];
-    uint8_t pm = 0;
-    if (k > 0.0) {
-      double u[12];  // the wavefront's rows, read again below through the cache
-#pragma unroll
-      for (int q = 0; q < 12; ++q) u[q] = grad[12 * i + q];
-      pm = part_mask(u);
-    }
-    bpm[i] = pm;
   }
+  // part masks (part_mask) of the wavefront's stencils, gathered from the
+  // copy below: entry e is vertex (e mod 12) / 3 of stencil e / 12
+  __shared__ uint32_t pmw[256];
+  uint32_t* pw = pmw + (threadIdx.x & ~63);
+  pw[lane] = 0u;
+  wave_sync();
   const int64_t n12 = 12 * (min<int64_t>(m, w0 + 64) - w0);
 #pragma unroll
   for (int q = 0; q < 12; ++q) {
@@ -106,8 +104,11 @@ __global__ __launch_bounds__(256) void k_base_copy(int64_t m, const uint64_t* ke
       const double n = grad[12 * w0 + e];
       bgrad[12 * w0 + e] = n;
       bu[12 * w0 + e] = s * n;
+      if (n != 0.0) atomicOr(&pw[e / 12], 1u << ((e % 12) / 3));
     }
   }
+  wave_sync();
+  if (i < m) bpm[i] = sk > 0.0 ? uint8_t(pw[lane]) : uint8_t(0);
 }
 
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
