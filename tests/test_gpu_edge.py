@@ -1,8 +1,9 @@
 """GPU edge cases against the FP64 oracle: ragged sizes (vertex and node
 counts that are not multiples of 32), empty contact sets, a subdomain with
 more Top-K candidates than the register-resident selection holds (the
-rescanning path), and the largest Woodbury rank (K = 32).  Tolerance:
-relative 1e-10 (float64 storage); selections compared exactly."""
+rescanning path), the largest Woodbury rank (K = 32), and contact stencils
+scattered over the whole scene (the energy gradient's far-side table full).
+Tolerance: relative 1e-10 (float64 storage); selections compared exactly."""
 import numpy as np
 import pytest
 
@@ -115,3 +116,49 @@ def test_largest_rank_K32():
         assert rank.max() == 32
     finally:
         c.ctx.close()
+
+
+def test_energy_gradient_with_scattered_stencils():
+    """Stencils whose vertices are spread over the whole scene: after the
+    sort by smallest vertex, a chunk's far-side vertices outnumber the LDS
+    hash table, so the gradient takes the table, its bounded probing and the
+    global fallback.  Energy and gradient against the oracle (1e-10) and
+    against the deterministic mode's ordered gather (1e-12)."""
+    import torch
+    from paper_2604_19892_amd.binding import MasContext, make_config
+    print("\n[edge case] two boxes, 20000 stencils on random vertex quadruples", flush=True)
+    sc = synth.two_boxes_scene()
+    rng = np.random.default_rng(21)
+    m = 20000
+    idx = rng.integers(0, sc.N, (m, 4)).astype(np.int32)
+    while True:
+        s = np.sort(idx, axis=1)
+        dup = np.any(s[:, 1:] == s[:, :-1], axis=1)
+        if not dup.any():
+            break
+        idx[dup] = rng.integers(0, sc.N, (int(dup.sum()), 4))
+    grad = rng.standard_normal((m, 12))
+    key = (np.uint64(synth.KEY_PLANE) << np.uint64(60)) | (np.uint64(1 << 20) + np.arange(m, dtype=np.uint64))
+    cset = synth.contact_set(key, idx, grad, rng.uniform(1e-5, sc.dhat, m))
+    prob = fem.Problem(sc)
+    xt = fem.inertial_target(sc.x, sc.v, sc.h, sc.gravity).reshape(-1)
+    Eo = prob.energy(sc.x, xt, cset)
+    go = prob.gradient(sc.x, xt, cset)
+    out = {}
+    for det in (False, True):
+        ctx = MasContext(sc, make_config(sc, levels=2, K=8, deterministic=det, max_contacts=m))
+        try:
+            x = ctx.to_lib(sc.x)
+            dxt = ctx.inertial_target(x, ctx.to_lib(sc.v))
+            E = torch.zeros(1, dtype=torch.float64, device="cuda")
+            g = ctx.vec()
+            ctx.energy_grad(x, dxt, ctx.contacts(cset, sort=True), E, g)
+            code, msg = ctx.sync()
+            assert code == 0, msg
+            out[det] = (float(E.item()), ctx.from_lib(g))
+        finally:
+            ctx.close()
+    for det, (E, g) in out.items():
+        assert E == pytest.approx(Eo, rel=1e-10), det
+        assert rel(g, go) < 1e-10, (det, rel(g, go))
+    assert rel(out[False][1], out[True][1]) < 1e-12
