@@ -1,8 +1,9 @@
 """GPU edge cases against the FP64 oracle: ragged sizes (vertex and node
 counts that are not multiples of 32), empty contact sets, a subdomain with
 more Top-K candidates than the register-resident selection holds (the
-rescanning path), the largest Woodbury rank (K = 32), and contact stencils
-scattered over the whole scene (the energy gradient's far-side table full).
+rescanning path), the largest Woodbury rank (K = 32), contact stencils
+scattered over the whole scene (the energy gradient's far-side table full)
+and stencils with a zero gradient part (left out of that vertex's buckets).
 Tolerance: relative 1e-10 (float64 storage); selections compared exactly."""
 import numpy as np
 import pytest
@@ -162,3 +163,36 @@ def test_energy_gradient_with_scattered_stencils():
         assert E == pytest.approx(Eo, rel=1e-10), det
         assert rel(g, go) < 1e-10, (det, rel(g, go))
     assert rel(out[False][1], out[True][1]) < 1e-12
+
+
+def test_zero_gradient_parts_leave_their_subdomains_out():
+    """Stencils of the two-box pool with one vertex's part of the gradient
+    exactly zero (every even key, base and current sets alike): a subdomain
+    that only that vertex touches is no Top-K candidate for the stencil
+    (S_d u = 0), and the assembly and hess_vec lists drop it too.  Blocks,
+    selections, apply and hess_vec against the oracle."""
+    sc = synth.two_boxes_scene()
+    rng = np.random.default_rng(5)
+    d = synth.pool_distance(sc.pool, sc.x)
+    base = synth.contact_set(sc.pool['key'], sc.pool['idx'], sc.pool['grad'], d)
+    curr = synth.churn_set(rng, sc, base, 0.3)
+
+    def zero_part(cs):
+        cs = dict(cs)
+        g = cs['grad'].copy()
+        sel = (cs['key'] % np.uint64(2) == 0) & (cs['idx'][:, 3] >= 0)
+        g[sel, 9:12] = 0.0
+        cs['grad'] = g
+        return cs
+
+    base, curr = zero_part(base), zero_part(curr)
+    hier = mas.Hierarchy(sc.X, 3)
+    sub = np.where(curr['idx'] >= 0, hier.rank[np.maximum(curr['idx'], 0)] // 32, -1)
+    zeroed = (curr['key'] % np.uint64(2) == 0) & (curr['idx'][:, 3] >= 0)
+    assert np.sum(zeroed & np.all(sub[:, :3] != sub[:, 3:4], axis=1)) > 100
+    print("\n[edge case] two boxes, zero gradient parts on every even key", flush=True)
+    c = Case(sc, base, curr, levels=3, K=8)
+    try:
+        check_case(c, blocks=True)
+    finally:
+        c.ctx.close()
